@@ -1,0 +1,543 @@
+/*
+ * FP64 CPU oracle for the POTR removal-effect rasterizer -- TEST INFRASTRUCTURE ONLY.
+ * Loaded only by tests, the smoke check and the benchmark's CPU-baseline leg;
+ * the HIP path never calls it and shares no code with it.
+ *
+ * Readings adopted where the paper is silent (each is also a field of orc_config):
+ *  - pinhole u = fx*x/z + cx, pixel (i, j) samples (i + 0.5, j + 0.5);
+ *  - the affine approximation is the Jacobian of the pinhole map at the centre,
+ *    with x/z, y/z clamped to +-jclamp times the half field of view, plus an
+ *    eps2d low-pass on the 2D covariance diagonal;
+ *  - covariance Sigma = R(q) diag(s^2) R(q)^T with q = (w, x, y, z) normalised;
+ *  - colour = max(0, sum_i L_i Y_i(d) + 1/2), d = unit vector from the camera
+ *    centre to the splat centre, real SH with the Condon-Shortley phase;
+ *  - a splat is blended at a pixel iff q <= q_max and o*exp(-q/2) >= alpha_min,
+ *    with alpha = min(alpha_max, o*exp(-q/2)); the walk stops before the splat
+ *    that would drive T below t_min (t_min = 0: no early stop);
+ *  - background colour bg enters as T_final * bg.
+ */
+#define _GNU_SOURCE
+#include "potr_oracle.h"
+
+#include <math.h>
+#include <pthread.h>
+#include <stdlib.h>
+#include <string.h>
+
+int32_t orc_version(void) { return 1; }
+
+/* ------------------------------------------------------------------------- */
+/* Real spherical harmonics (Sec. 3): Y_{l,m} from the associated Legendre     */
+/* functions P_l^m (Condon-Shortley phase included) and                        */
+/* K_l^m = sqrt((2l+1)/(4 pi) (l-|m|)!/(l+|m|)!):                              */
+/*   m > 0: sqrt(2) K cos(m phi) P_l^m(cos theta)                              */
+/*   m = 0: K P_l^0(cos theta)                                                 */
+/*   m < 0: sqrt(2) K sin(|m| phi) P_l^|m|(cos theta)                          */
+/* ------------------------------------------------------------------------- */
+static double factorial(int n) { double f = 1.0; for (int i = 2; i <= n; ++i) f *= i; return f; }
+
+static double legendre_p(int l, int m, double x) /* m >= 0, with (-1)^m phase */
+{
+    double s = sqrt(fmax(0.0, 1.0 - x * x));
+    double pmm = 1.0;                      /* P_m^m = (-1)^m (2m-1)!! s^m */
+    for (int i = 1; i <= m; ++i) pmm *= -(2.0 * i - 1.0) * s;
+    if (l == m) return pmm;
+    double pm1 = x * (2.0 * m + 1.0) * pmm; /* P_{m+1}^m */
+    if (l == m + 1) return pm1;
+    double pl = 0.0;
+    for (int ll = m + 2; ll <= l; ++ll) {
+        pl = ((2.0 * ll - 1.0) * x * pm1 - (ll + m - 1.0) * pmm) / (ll - m);
+        pmm = pm1;
+        pm1 = pl;
+    }
+    return pl;
+}
+
+void orc_sh_basis(int32_t lmax, const double d[3], double* out)
+{
+    double ct = d[2];
+    double phi = atan2(d[1], d[0]);
+    for (int l = 0; l <= lmax; ++l) {
+        for (int m = -l; m <= l; ++m) {
+            int am = m < 0 ? -m : m;
+            double K = sqrt((2.0 * l + 1.0) / (4.0 * M_PI) * factorial(l - am) / factorial(l + am));
+            double P = legendre_p(l, am, ct);
+            double y;
+            if (m > 0) y = sqrt(2.0) * K * cos(m * phi) * P;
+            else if (m == 0) y = K * P;
+            else y = sqrt(2.0) * K * sin(am * phi) * P;
+            out[l * (l + 1) + m] = y;
+        }
+    }
+}
+
+/* ------------------------------------------------------------------------- */
+/* Projection (Sec. 3: affine approximation of the projective transform).      */
+/* ------------------------------------------------------------------------- */
+static void quat_rotation(const double qn[4], double M[9])
+{
+    double w = qn[0], x = qn[1], y = qn[2], z = qn[3];
+    M[0] = 1 - 2 * (y * y + z * z); M[1] = 2 * (x * y - w * z);     M[2] = 2 * (x * z + w * y);
+    M[3] = 2 * (x * y + w * z);     M[4] = 1 - 2 * (x * x + z * z); M[5] = 2 * (y * z - w * x);
+    M[6] = 2 * (x * z - w * y);     M[7] = 2 * (y * z + w * x);     M[8] = 1 - 2 * (x * x + y * y);
+}
+
+/* Camera-space depth in FP32 by the fixed chain t_z + R20 x + R21 y + R22 z,
+ * each step one fused multiply-add; its bits are the depth sort key. */
+static float depth_f32(const orc_camera* cam, const float* m)
+{
+    float acc = cam->t[2];
+    acc = fmaf(cam->R[6], m[0], acc);
+    acc = fmaf(cam->R[7], m[1], acc);
+    acc = fmaf(cam->R[8], m[2], acc);
+    return acc;
+}
+
+static void camera_eye(const orc_camera* cam, double eye[3])
+{
+    for (int i = 0; i < 3; ++i)
+        eye[i] = -((double)cam->R[0 + i] * cam->t[0] + (double)cam->R[3 + i] * cam->t[1] +
+                   (double)cam->R[6 + i] * cam->t[2]);
+}
+
+void orc_project(int64_t N, const orc_camera* cam, const orc_config* cfg,
+                 const float* means, const float* scales, const float* quats,
+                 const float* opac, const float* sh,
+                 double* mean2d, double* cov2d, double* conic, double* rgb,
+                 uint32_t* depth_key, int32_t* rect, int32_t* tiles_touched)
+{
+    const int W = cam->width, H = cam->height, tw = cfg->tile_w, th = cfg->tile_h;
+    double eye[3];
+    camera_eye(cam, eye);
+    const int nsh = (cfg->sh_degree + 1) * (cfg->sh_degree + 1);
+    for (int64_t i = 0; i < N; ++i) {
+        const float* m = means + 3 * i;
+        float z32 = depth_f32(cam, m);
+        uint32_t key;
+        memcpy(&key, &z32, 4);
+        depth_key[i] = key;
+        tiles_touched[i] = 0;
+        for (int k = 0; k < 4; ++k) rect[4 * i + k] = 0;
+        for (int k = 0; k < 2; ++k) mean2d[2 * i + k] = 0;
+        for (int k = 0; k < 3; ++k) { cov2d[3 * i + k] = 0; conic[3 * i + k] = 0; rgb[3 * i + k] = 0; }
+
+        /* camera-space centre */
+        double p[3];
+        for (int r = 0; r < 3; ++r)
+            p[r] = (double)cam->R[3 * r] * m[0] + (double)cam->R[3 * r + 1] * m[1] +
+                   (double)cam->R[3 * r + 2] * m[2] + (double)cam->t[r];
+        if (!(z32 > cfg->near_z)) continue;
+        double o = opac[i];
+        if (!(o >= (double)cfg->alpha_min)) continue;
+
+        /* 3D covariance from scale and rotation */
+        const float* q = quats + 4 * i;
+        double qn2 = (double)q[0] * q[0] + (double)q[1] * q[1] + (double)q[2] * q[2] + (double)q[3] * q[3];
+        if (!(qn2 > 0.0)) continue;
+        double qinv = 1.0 / sqrt(qn2), qn[4];
+        for (int k = 0; k < 4; ++k) qn[k] = q[k] * qinv;
+        double Rq[9];
+        quat_rotation(qn, Rq);
+        double s2[3];
+        for (int k = 0; k < 3; ++k) s2[k] = (double)scales[3 * i + k] * scales[3 * i + k];
+        double Sig[9];
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) {
+                double acc = 0;
+                for (int k = 0; k < 3; ++k) acc += Rq[3 * a + k] * s2[k] * Rq[3 * b + k];
+                Sig[3 * a + b] = acc;
+            }
+        /* Jacobian of the pinhole map at the centre, camera rotation folded in */
+        double z = p[2];
+        double limx = (double)cfg->jclamp * 0.5 * W / cam->fx;
+        double limy = (double)cfg->jclamp * 0.5 * H / cam->fy;
+        double tx = fmin(limx, fmax(-limx, p[0] / z));
+        double ty = fmin(limy, fmax(-limy, p[1] / z));
+        double J[6] = { cam->fx / z, 0.0, -cam->fx * tx / z,
+                        0.0, cam->fy / z, -cam->fy * ty / z };
+        double T[6]; /* T = J * Rcam */
+        for (int a = 0; a < 2; ++a)
+            for (int b = 0; b < 3; ++b) {
+                double acc = 0;
+                for (int k = 0; k < 3; ++k) acc += J[3 * a + k] * (double)cam->R[3 * k + b];
+                T[3 * a + b] = acc;
+            }
+        double C2[4];
+        for (int a = 0; a < 2; ++a)
+            for (int b = 0; b < 2; ++b) {
+                double acc = 0;
+                for (int k = 0; k < 3; ++k)
+                    for (int l = 0; l < 3; ++l) acc += T[3 * a + k] * Sig[3 * k + l] * T[3 * b + l];
+                C2[2 * a + b] = acc;
+            }
+        double cxx = C2[0] + cfg->eps2d, cxy = 0.5 * (C2[1] + C2[2]), cyy = C2[3] + cfg->eps2d;
+        double det = cxx * cyy - cxy * cxy;
+        if (!(det > 0.0)) continue;
+        double u = cam->fx * p[0] / z + cam->cx;
+        double v = cam->fy * p[1] / z + cam->cy;
+
+        /* conservative pixel rectangle: AABB of the ellipse q <= t_cut */
+        double t_cut = fmin((double)cfg->q_max, 2.0 * log(o / (double)cfg->alpha_min));
+        double rx = sqrt(t_cut * cxx) * (1.0 + 1.0 / 1024.0) + 1.0 / 64.0;
+        double ry = sqrt(t_cut * cyy) * (1.0 + 1.0 / 1024.0) + 1.0 / 64.0;
+        double ilo = fmax(ceil(u - rx - 0.5), 0.0), ihi = fmin(floor(u + rx - 0.5), W - 1.0);
+        double jlo = fmax(ceil(v - ry - 0.5), 0.0), jhi = fmin(floor(v + ry - 0.5), H - 1.0);
+
+        mean2d[2 * i] = u;
+        mean2d[2 * i + 1] = v;
+        cov2d[3 * i] = cxx; cov2d[3 * i + 1] = cxy; cov2d[3 * i + 2] = cyy;
+        conic[3 * i] = cyy / det; conic[3 * i + 1] = -cxy / det; conic[3 * i + 2] = cxx / det;
+
+        /* colour from SH along the camera -> centre direction */
+        double d[3] = { m[0] - eye[0], m[1] - eye[1], m[2] - eye[2] };
+        double dn = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+        for (int k = 0; k < 3; ++k) d[k] /= dn;
+        double Y[16];
+        orc_sh_basis(cfg->sh_degree, d, Y);
+        for (int c = 0; c < 3; ++c) {
+            double acc = 0.0;
+            for (int k = 0; k < nsh; ++k) acc += (double)sh[48 * i + 3 * k + c] * Y[k];
+            rgb[3 * i + c] = fmax(0.0, acc + 0.5);
+        }
+        if (!(ilo <= ihi) || !(jlo <= jhi)) continue;
+        int x0 = (int)ilo / tw, x1 = (int)ihi / tw + 1, y0 = (int)jlo / th, y1 = (int)jhi / th + 1;
+        rect[4 * i] = x0; rect[4 * i + 1] = y0; rect[4 * i + 2] = x1; rect[4 * i + 3] = y1;
+        tiles_touched[i] = (x1 - x0) * (y1 - y0);
+    }
+}
+
+/* ------------------------------------------------------------------------- */
+/* Tile lists ordered by (tile, depth key, splat id).                          */
+/* ------------------------------------------------------------------------- */
+typedef struct { uint32_t tile, key, id; } orc_pair;
+
+static int pair_cmp(const void* a, const void* b)
+{
+    const orc_pair* x = (const orc_pair*)a;
+    const orc_pair* y = (const orc_pair*)b;
+    if (x->tile != y->tile) return x->tile < y->tile ? -1 : 1;
+    if (x->key != y->key) return x->key < y->key ? -1 : 1;
+    if (x->id != y->id) return x->id < y->id ? -1 : 1;
+    return 0;
+}
+
+int64_t orc_bin_sort(int64_t N, int32_t tiles_x, int32_t tiles_y, const int32_t* rect,
+                     const uint32_t* depth_key, int32_t* out_tile, int32_t* out_id,
+                     int32_t* tile_ranges)
+{
+    int64_t n = 0;
+    for (int64_t i = 0; i < N; ++i) {
+        const int32_t* r = rect + 4 * i;
+        if (r[2] > r[0] && r[3] > r[1]) n += (int64_t)(r[2] - r[0]) * (r[3] - r[1]);
+    }
+    if (!out_id) return n;
+    orc_pair* pairs = (orc_pair*)malloc((size_t)(n > 0 ? n : 1) * sizeof(orc_pair));
+    int64_t k = 0;
+    for (int64_t i = 0; i < N; ++i) {
+        const int32_t* r = rect + 4 * i;
+        for (int ty = r[1]; ty < r[3]; ++ty)
+            for (int tx = r[0]; tx < r[2]; ++tx) {
+                pairs[k].tile = (uint32_t)(ty * tiles_x + tx);
+                pairs[k].key = depth_key[i];
+                pairs[k].id = (uint32_t)i;
+                ++k;
+            }
+    }
+    qsort(pairs, (size_t)n, sizeof(orc_pair), pair_cmp);
+    int64_t T = (int64_t)tiles_x * tiles_y;
+    for (int64_t t = 0; t < 2 * T; ++t) tile_ranges[t] = 0;
+    for (int64_t j = 0; j < n; ++j) {
+        if (out_tile) out_tile[j] = (int32_t)pairs[j].tile;
+        out_id[j] = (int32_t)pairs[j].id;
+        uint32_t t = pairs[j].tile;
+        if (j == 0 || pairs[j - 1].tile != t) tile_ranges[2 * t] = (int32_t)j;
+        if (j == n - 1 || pairs[j + 1].tile != t) tile_ranges[2 * t + 1] = (int32_t)(j + 1);
+    }
+    free(pairs);
+    return n;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Work splitting over image rows (pthreads).                                  */
+/* ------------------------------------------------------------------------- */
+typedef struct {
+    void (*fn)(void* ctx, int row);
+    void* ctx;
+    int rows;
+    int next;
+    pthread_mutex_t mu;
+} row_pool;
+
+static void* row_worker(void* arg)
+{
+    row_pool* p = (row_pool*)arg;
+    for (;;) {
+        pthread_mutex_lock(&p->mu);
+        int r = p->next++;
+        pthread_mutex_unlock(&p->mu);
+        if (r >= p->rows) break;
+        p->fn(p->ctx, r);
+    }
+    return NULL;
+}
+
+static void parallel_rows(int rows, int n_threads, void (*fn)(void*, int), void* ctx)
+{
+    row_pool p;
+    p.fn = fn; p.ctx = ctx; p.rows = rows; p.next = 0;
+    pthread_mutex_init(&p.mu, NULL);
+    if (n_threads < 1) n_threads = 1;
+    if (n_threads > 256) n_threads = 256;
+    pthread_t th[256];
+    for (int t = 1; t < n_threads; ++t) pthread_create(&th[t], NULL, row_worker, &p);
+    row_worker(&p);
+    for (int t = 1; t < n_threads; ++t) pthread_join(th[t], NULL);
+    pthread_mutex_destroy(&p.mu);
+}
+
+static void atomic_add_f64(double* addr, double v)
+{
+    double old;
+    __atomic_load(addr, &old, __ATOMIC_RELAXED);
+    for (;;) {
+        double nw = old + v;
+        if (__atomic_compare_exchange(addr, &old, &nw, 1, __ATOMIC_RELAXED, __ATOMIC_RELAXED)) return;
+    }
+}
+
+/* ------------------------------------------------------------------------- */
+/* Compositing (Sec. 3) and the removal effect (Sec. 4.2).                     */
+/* ------------------------------------------------------------------------- */
+typedef struct {
+    int64_t N;
+    const orc_camera* cam;
+    const orc_config* cfg;
+    const double *mean2d, *conic, *rgb;
+    const float* opac;
+    const int32_t *tile_ranges, *sorted_id;
+    const float* target;
+    int removal_method;
+    double *image, *p_final, *t_final;
+    int32_t *n_walk, *n_blend;
+    double *score_l1, *score_se, *importance, *magnitude, *flag_mass;
+    uint8_t* pixel_flag;
+    int64_t skip_id;            /* orc_render_without: the deleted splat, else -1 */
+    int max_list;
+    int64_t n_flagged;
+    pthread_mutex_t mu;
+} render_ctx;
+
+/* One evaluation of splat s at pixel centre (px, py): q and o*G. */
+static void eval_splat(const render_ctx* c, int64_t s, double px, double py,
+                       double* q_out, double* dq_err, double* a0_out)
+{
+    double dx = px - c->mean2d[2 * s], dy = py - c->mean2d[2 * s + 1];
+    double A = c->conic[3 * s], B = c->conic[3 * s + 1], C = c->conic[3 * s + 2];
+    double q = A * dx * dx + 2.0 * B * dx * dy + C * dy * dy;
+    *q_out = q;
+    *a0_out = (double)c->opac[s] * exp(-0.5 * q);
+    /* Error bound of an FP32 evaluation of q from FP32-rounded inputs (used only
+     * to flag decisions that FP32 arithmetic could take the other way): rounding
+     * of the pixel offsets, of the conic and of the quadratic form itself. */
+    const double u = ldexp(1.0, -24);
+    double edx = (fabs(c->mean2d[2 * s]) + fabs(dx) + fabs(px)) * u;
+    double edy = (fabs(c->mean2d[2 * s + 1]) + fabs(dy) + fabs(py)) * u;
+    double qabs = fabs(A) * dx * dx + 2.0 * fabs(B * dx * dy) + fabs(C) * dy * dy;
+    *dq_err = 2.0 * fabs(A * dx + B * dy) * edx + 2.0 * fabs(B * dx + C * dy) * edy + 12.0 * u * qabs;
+}
+
+static void render_row(void* vctx, int py_i)
+{
+    render_ctx* c = (render_ctx*)vctx;
+    const orc_camera* cam = c->cam;
+    const orc_config* cfg = c->cfg;
+    const int W = cam->width, tw = cfg->tile_w, th = cfg->tile_h;
+    const int tiles_x = (W + tw - 1) / tw;
+    const double qmax = cfg->q_max, amin = cfg->alpha_min, amax = cfg->alpha_max, tmin = cfg->t_min;
+    const double bg[3] = { cfg->bg[0], cfg->bg[1], cfg->bg[2] };
+    const double u = ldexp(1.0, -24);
+    const int M = c->max_list + 1;
+    double* al = (double*)malloc(sizeof(double) * M);
+    double* Tk = (double*)malloc(sizeof(double) * M);
+    double* Pk = (double*)malloc(sizeof(double) * 3 * (M + 1)); /* P_i, i = 0..K */
+    int64_t* ids = (int64_t*)malloc(sizeof(int64_t) * M);
+    int64_t* near_ids = (int64_t*)malloc(sizeof(int64_t) * M);
+    double* near_T = (double*)malloc(sizeof(double) * M);
+    double* near_a = (double*)malloc(sizeof(double) * M);
+    int64_t row_flagged = 0;
+
+    for (int px_i = 0; px_i < W; ++px_i) {
+        const double px = px_i + 0.5, py = py_i + 0.5;
+        const int tile = (py_i / th) * tiles_x + px_i / tw;
+        const int beg = c->tile_ranges[2 * tile], end = c->tile_ranges[2 * tile + 1];
+        double T = 1.0, elnT = 0.0;
+        int K = 0, stop = end, flagged = 0, n_near = 0;
+        Pk[0] = Pk[1] = Pk[2] = 0.0;
+        int pos;
+        for (pos = beg; pos < end; ++pos) {
+            int64_t s = c->sorted_id[pos];
+            if (s == c->skip_id) continue;
+            double q, eq, a0;
+            eval_splat(c, s, px, py, &q, &eq, &a0);
+            /* decisions that an FP32 evaluation could flip */
+            double elna = 0.5 * eq + 0.5 * q * 4.0 * u + 8.0 * u;
+            const int vis_q = q <= qmax, vis_a = a0 >= amin;
+            const int nq = fabs(q - qmax) <= 4.0 * eq;
+            const int na = a0 > 0.0 && fabs(log(a0) - log(amin)) <= 4.0 * elna;
+            const int may_flip = (nq && (vis_a || na)) || (na && (vis_q || nq));
+            if (!vis_q || !vis_a) {
+                if (may_flip) {
+                    flagged = 1;
+                    near_ids[n_near] = s; near_T[n_near] = T; near_a[n_near] = fmin(amax, a0); ++n_near;
+                }
+                continue;
+            }
+            if (may_flip) flagged = 1;
+            double a = fmin(amax, a0);
+            double ea = a0 < amax ? elna : 0.0;
+            double Tn = T * (1.0 - a);
+            if (tmin > 0.0) {
+                double e = elnT + a / (1.0 - a) * ea + 4.0 * u;
+                if (fabs(log(Tn) - log(tmin)) <= 4.0 * e) {
+                    flagged = 1;
+                    /* splats an FP32 walk could still blend past this point */
+                    double Tv = T;
+                    for (int pv = pos; pv < end && n_near < M; ++pv) {
+                        int64_t sv = c->sorted_id[pv];
+                        if (sv == c->skip_id) continue;
+                        double qv, eqv, av;
+                        eval_splat(c, sv, px, py, &qv, &eqv, &av);
+                        if (!(qv <= qmax * (1.0 + 1e-3)) || !(av >= amin * (1.0 - 1e-3))) continue;
+                        av = fmin(amax, av);
+                        if (Tv * (1.0 - av) < tmin * exp(-8.0 * e)) break;
+                        near_ids[n_near] = sv; near_T[n_near] = Tv; near_a[n_near] = av; ++n_near;
+                        Tv *= (1.0 - av);
+                    }
+                }
+                if (Tn < tmin) { stop = pos; break; }
+            }
+            elnT += a / (1.0 - a) * ea + 4.0 * u;
+            al[K] = a; Tk[K] = T; ids[K] = s;
+            const double* col = c->rgb + 3 * s;
+            for (int ch = 0; ch < 3; ++ch) Pk[3 * (K + 1) + ch] = Pk[3 * K + ch] + T * a * col[ch];
+            T = Tn;
+            ++K;
+        }
+        if (pos >= end) stop = end;
+        const int64_t pix = (int64_t)py_i * W + px_i;
+        const double* PK = Pk + 3 * K;
+        double img[3];
+        for (int ch = 0; ch < 3; ++ch) img[ch] = PK[ch] + T * bg[ch];
+        if (c->image) for (int ch = 0; ch < 3; ++ch) c->image[3 * pix + ch] = img[ch];
+        if (c->p_final) for (int ch = 0; ch < 3; ++ch) c->p_final[3 * pix + ch] = PK[ch];
+        if (c->t_final) c->t_final[pix] = T;
+        if (c->n_walk) c->n_walk[pix] = stop;
+        if (c->n_blend) c->n_blend[pix] = K;
+        if (c->pixel_flag) c->pixel_flag[pix] = (uint8_t)flagged;
+        row_flagged += flagged;
+
+        double sumabsP = fabs(PK[0]) + fabs(PK[1]) + fabs(PK[2]);
+        double sumabsB = T * (fabs(bg[0]) + fabs(bg[1]) + fabs(bg[2]));
+        for (int k = 0; k < K; ++k) {
+            const double a = al[k];
+            const double* col = c->rgb + 3 * ids[k];
+            double PD[3];
+            if (c->removal_method == 0) {
+                /* Sec. 4.2: PD_k = P_{i_k} - P_{i_k+1}/(1-a) + a/(1-a) P_K, plus the
+                 * background term a/(1-a) T_K bg for a non-black background. */
+                for (int ch = 0; ch < 3; ++ch)
+                    PD[ch] = Pk[3 * k + ch] - Pk[3 * (k + 1) + ch] / (1.0 - a) + a / (1.0 - a) * PK[ch] +
+                             a / (1.0 - a) * T * bg[ch];
+            } else {
+                /* definition: composite the blended list again without entry k */
+                double Tw = 1.0, Cw[3] = { 0, 0, 0 };
+                for (int j = 0; j < K; ++j) {
+                    if (j == k) continue;
+                    const double* cj = c->rgb + 3 * ids[j];
+                    for (int ch = 0; ch < 3; ++ch) Cw[ch] += Tw * al[j] * cj[ch];
+                    Tw *= (1.0 - al[j]);
+                }
+                for (int ch = 0; ch < 3; ++ch) PD[ch] = Cw[ch] + Tw * bg[ch] - img[ch];
+            }
+            int64_t s = ids[k];
+            if (c->score_l1) atomic_add_f64(&c->score_l1[s], fabs(PD[0]) + fabs(PD[1]) + fabs(PD[2]));
+            if (c->score_se && c->target) {
+                double se = 0.0;
+                for (int ch = 0; ch < 3; ++ch)
+                    se += PD[ch] * PD[ch] + 2.0 * PD[ch] * (img[ch] - (double)c->target[3 * pix + ch]);
+                atomic_add_f64(&c->score_se[s], se);
+            }
+            if (c->importance) atomic_add_f64(&c->importance[s], Tk[k] * a);
+            double mag = Tk[k] * a * (fabs(col[0]) + fabs(col[1]) + fabs(col[2])) +
+                         a / (1.0 - a) * (sumabsP + sumabsB);
+            if (c->magnitude) atomic_add_f64(&c->magnitude[s], mag);
+            if (flagged && c->flag_mass) atomic_add_f64(&c->flag_mass[s], 2.0 * mag);
+        }
+        if (flagged && c->flag_mass) {
+            for (int k = 0; k < n_near; ++k) {
+                const double a = near_a[k];
+                const double* col = c->rgb + 3 * near_ids[k];
+                double mag = near_T[k] * a * (fabs(col[0]) + fabs(col[1]) + fabs(col[2])) +
+                             a / (1.0 - a) * (sumabsP + sumabsB + near_T[k] * a * 3.0);
+                atomic_add_f64(&c->flag_mass[near_ids[k]], 2.0 * mag);
+            }
+        }
+    }
+    free(al); free(Tk); free(Pk); free(ids); free(near_ids); free(near_T); free(near_a);
+    pthread_mutex_lock(&c->mu);
+    c->n_flagged += row_flagged;
+    pthread_mutex_unlock(&c->mu);
+}
+
+static int max_list_len(const orc_camera* cam, const orc_config* cfg, const int32_t* tile_ranges)
+{
+    int tiles = ((cam->width + cfg->tile_w - 1) / cfg->tile_w) * ((cam->height + cfg->tile_h - 1) / cfg->tile_h);
+    int m = 0;
+    for (int t = 0; t < tiles; ++t) {
+        int l = tile_ranges[2 * t + 1] - tile_ranges[2 * t];
+        if (l > m) m = l;
+    }
+    return m;
+}
+
+int64_t orc_render(int64_t N, const orc_camera* cam, const orc_config* cfg,
+                   const double* mean2d, const double* conic, const double* rgb,
+                   const float* opac, const int32_t* tile_ranges, const int32_t* sorted_id,
+                   const float* target, int32_t removal_method, int32_t n_threads,
+                   double* image, double* p_final, double* t_final, int32_t* n_walk,
+                   int32_t* n_blend, double* score_l1, double* score_se, double* importance,
+                   double* magnitude, double* flag_mass, uint8_t* pixel_flag)
+{
+    render_ctx c;
+    memset(&c, 0, sizeof(c));
+    c.N = N; c.cam = cam; c.cfg = cfg; c.mean2d = mean2d; c.conic = conic; c.rgb = rgb; c.opac = opac;
+    c.tile_ranges = tile_ranges; c.sorted_id = sorted_id; c.target = target;
+    c.removal_method = removal_method;
+    c.image = image; c.p_final = p_final; c.t_final = t_final; c.n_walk = n_walk; c.n_blend = n_blend;
+    c.score_l1 = score_l1; c.score_se = score_se; c.importance = importance; c.magnitude = magnitude;
+    c.flag_mass = flag_mass; c.pixel_flag = pixel_flag;
+    c.skip_id = -1;
+    c.max_list = max_list_len(cam, cfg, tile_ranges);
+    pthread_mutex_init(&c.mu, NULL);
+    parallel_rows(cam->height, n_threads, render_row, &c);
+    pthread_mutex_destroy(&c.mu);
+    return c.n_flagged;
+}
+
+void orc_render_without(int64_t N, const orc_camera* cam, const orc_config* cfg,
+                        const double* mean2d, const double* conic, const double* rgb,
+                        const float* opac, const int32_t* tile_ranges, const int32_t* sorted_id,
+                        int64_t k, double* image)
+{
+    render_ctx c;
+    memset(&c, 0, sizeof(c));
+    c.N = N; c.cam = cam; c.cfg = cfg; c.mean2d = mean2d; c.conic = conic; c.rgb = rgb; c.opac = opac;
+    c.tile_ranges = tile_ranges; c.sorted_id = sorted_id;
+    c.removal_method = 0;
+    c.image = image;
+    c.skip_id = k;
+    c.max_list = max_list_len(cam, cfg, tile_ranges);
+    pthread_mutex_init(&c.mu, NULL);
+    parallel_rows(cam->height, 1, render_row, &c);
+    pthread_mutex_destroy(&c.mu);
+}

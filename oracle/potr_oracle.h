@@ -1,0 +1,120 @@
+/*
+ * FP64 CPU oracle for the POTR removal-effect rasterizer -- TEST INFRASTRUCTURE ONLY.
+ *
+ * Only tests, the smoke check and the benchmark's CPU-baseline leg may load this
+ * library. It shares no code, header or constant table with the HIP path under
+ * paper_2601_14821_amd/csrc, and the HIP path never calls it.
+ *
+ * What it computes (paper references are to "POTR: Post-Training 3DGS Compression"):
+ *   - projection of 3D Gaussians to 2D (Sec. 3: affine approximation of the
+ *     projective map) and the colour of each splat from real SH, l <= 3
+ *     (Sec. 3, the SH colour equation, index (l,m) -> l(l+1)+m+1);
+ *   - the depth-ordered tile lists;
+ *   - alpha compositing (Sec. 3, eq. alpha_blending; T_k = prod_{j<k}(1-alpha_j));
+ *   - the pruning difference PD_k(x) = c~_k(x) - c(x) (Sec. 4.2), both as the
+ *     paper's closed form in partial colours P_i and as its plain definition
+ *     (re-composite the pixel without splat k);
+ *   - per-splat reductions: sum |PD_k|_1 (the removal score used here), the
+ *     squared-error change dSE_k (Sec. 4.2) and the importance I_k (Sec. 4.1);
+ *   - the analytic gradient of an L1 image loss (the standard backward render
+ *     pass that the paper's fine-tuning relies on, Sec. 4.6).
+ * All floating point is FP64 except the depth key, which both sides compute in
+ * FP32 by one fixed fused-multiply-add chain so that the depth order (an
+ * integer result) is decided in the same precision on both sides.
+ */
+#ifndef POTR_ORACLE_H
+#define POTR_ORACLE_H
+#include <stdint.h>
+
+typedef struct {
+    float R[9];          /* world -> camera rotation, row-major, OpenCV axes */
+    float t[3];
+    float fx, fy, cx, cy;
+    int32_t width, height;
+} orc_camera;
+
+typedef struct {
+    int32_t tile_w, tile_h;
+    float eps2d;         /* low-pass added to the 2D covariance diagonal, px^2 */
+    float near_z;        /* cull if camera z <= near_z */
+    float jclamp;        /* clamp of x/z, y/z in the Jacobian, in units of the half field of view */
+    float alpha_min;     /* a splat is skipped at a pixel if o*G < alpha_min */
+    float alpha_max;     /* alpha = min(alpha_max, o*G) */
+    float q_max;         /* a splat is skipped at a pixel if its Mahalanobis q exceeds q_max */
+    float t_min;         /* stop before the splat that drives T below t_min; 0 = exact mode */
+    float bg[3];
+    int32_t sh_degree;   /* 0..3 */
+} orc_config;
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+int32_t orc_version(void);
+
+/* Real spherical harmonics with the Condon-Shortley phase, from the associated
+ * Legendre recurrences; out[l*(l+1)+m] for l <= lmax, unit direction d. */
+void orc_sh_basis(int32_t lmax, const double d[3], double* out);
+
+/* Projection of N splats for one camera. Outputs (per splat):
+ *   mean2d[2], cov2d[3] (xx, xy, yy incl. low-pass), conic[3], rgb[3],
+ *   depth_key (FP32 bits of camera z from the pinned FMA chain),
+ *   rect[4] = tile x0, y0, x1, y1 (half-open), tiles_touched.
+ * A culled splat has tiles_touched = 0 and rect = 0. */
+void orc_project(int64_t N, const orc_camera* cam, const orc_config* cfg,
+                 const float* means, const float* scales, const float* quats,
+                 const float* opac, const float* sh,
+                 double* mean2d, double* cov2d, double* conic, double* rgb,
+                 uint32_t* depth_key, int32_t* rect, int32_t* tiles_touched);
+
+/* Tile lists: every (tile, splat) pair of each splat's rect, ordered by
+ * (tile, depth_key, splat id). Returns the pair count; with out_id == NULL only
+ * counts. tile_ranges[2*t] .. [2*t+1] is the half-open range of tile t. */
+int64_t orc_bin_sort(int64_t N, int32_t tiles_x, int32_t tiles_y, const int32_t* rect,
+                     const uint32_t* depth_key, int32_t* out_tile, int32_t* out_id,
+                     int32_t* tile_ranges);
+
+/* Composite one view and evaluate the removal effect of every blended splat.
+ * removal_method: 0 = the paper's partial-colour closed form, 1 = definition
+ * (composite again without splat k). Optional outputs may be NULL.
+ *   image/p_final [H*W*3], t_final [H*W], n_walk [H*W] (list position of the
+ *   stop, or the list length), n_blend [H*W];
+ *   score_l1 [N] += sum over pixels and channels of |PD_k|;
+ *   score_se [N] += sum over pixels and channels of dSE_k (needs target);
+ *   importance [N] += sum over pixels of T_k alpha_k;
+ *   magnitude [N] += per-splat term magnitude (tolerance floor);
+ *   flag_mass [N] += allowance for pixels whose decisions sit within FP32 reach
+ *   of a threshold; pixel_flag [H*W] = 1 for such pixels.
+ * Returns the number of flagged pixels. */
+int64_t orc_render(int64_t N, const orc_camera* cam, const orc_config* cfg,
+                   const double* mean2d, const double* conic, const double* rgb,
+                   const float* opac, const int32_t* tile_ranges, const int32_t* sorted_id,
+                   const float* target, int32_t removal_method, int32_t n_threads,
+                   double* image, double* p_final, double* t_final, int32_t* n_walk,
+                   int32_t* n_blend, double* score_l1, double* score_se, double* importance,
+                   double* magnitude, double* flag_mass, uint8_t* pixel_flag);
+
+/* Literal removal of one splat: composite every pixel with splat `k` deleted
+ * (visibility tests and early stop rerun) and return the new image [H*W*3]. */
+void orc_render_without(int64_t N, const orc_camera* cam, const orc_config* cfg,
+                        const double* mean2d, const double* conic, const double* rgb,
+                        const float* opac, const int32_t* tile_ranges, const int32_t* sorted_id,
+                        int64_t k, double* image);
+
+/* Gradient of a loss L through the compositing of one view and the projection.
+ * dL_dimage [H*W*3]. Gradients (+=) with the input shapes: d_means [N*3],
+ * d_scales [N*3], d_quats [N*4] (w.r.t. the unnormalised quaternion), d_opac [N],
+ * d_sh [N*16*3]. Also (+=) d_mean2d [N*2], d_conic [N*3], d_rgb [N*3] when not NULL. */
+void orc_backward(int64_t N, const orc_camera* cam, const orc_config* cfg,
+                  const float* means, const float* scales, const float* quats,
+                  const float* opac, const float* sh,
+                  const double* mean2d, const double* conic, const double* rgb,
+                  const int32_t* tile_ranges, const int32_t* sorted_id,
+                  const double* dL_dimage, int32_t n_threads,
+                  double* d_means, double* d_scales, double* d_quats, double* d_opac,
+                  double* d_sh, double* d_mean2d, double* d_conic, double* d_rgb);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
