@@ -1,0 +1,184 @@
+/*
+ * potr.h -- C ABI of libpotr.so, the MI355X (gfx950) removal-effect rasterizer.
+ *
+ * The library computes, for every splat of a 3D Gaussian splatting scene and every
+ * view, the change of every pixel's colour if that splat alone were deleted
+ * (POTR, "Post-Training 3DGS Compression", Sec. 4.2: the pruning difference
+ * PD_k(x) = c~_k(x) - c(x)), and reduces it per splat. Its stages follow the
+ * forward rendering of Sec. 3: projection of each 3D Gaussian to a 2D Gaussian by
+ * an affine approximation, colour from real spherical harmonics, ordering of the
+ * splats by approximate depth, front-to-back alpha compositing
+ * (T_k = prod_{j<k} (1 - alpha_j), c = sum_k T_k alpha_k c_k + T_K bg).
+ *
+ * Conventions shared by all calls
+ *  - Every pointer is a DEVICE pointer unless marked (host). The caller owns all
+ *    memory; the library never allocates or frees caller buffers.
+ *  - `stream` is a hipStream_t (NULL = the null stream). Calls only enqueue work
+ *    on it and return; results are ready when the stream is synchronised.
+ *  - Splat parameters (FP32, row per splat, 236 bytes per splat):
+ *      means [N,3], scales [N,3] (activated, > 0), quats [N,4] (w,x,y,z; any norm,
+ *      zero norm culls), opac [N] (activated, in (0,1)), sh [N,16,3] (real SH
+ *      coefficients, coefficient-major, index l(l+1)+m).
+ *  - Images are [V,H,W,3] FP32, pixel (i,j) sampled at (i+0.5, j+0.5).
+ *  - Every view of one call has the same width and height.
+ *  - Errors: a negative potr_status; potr_last_error() returns a message for the
+ *    calling thread. Validation errors (POTR_EINVAL) are raised before any launch.
+ *    POTR_EHIP carries the HIP runtime's message.
+ *  - Calls on distinct streams may run concurrently; calls sharing a workspace on
+ *    one stream must not overlap.
+ */
+#ifndef POTR_H
+#define POTR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define POTR_ABI_VERSION 1
+
+#define POTR_API __attribute__((visibility("default")))
+
+typedef int32_t potr_status;
+#define POTR_OK 0
+#define POTR_EINVAL (-1)        /* bad argument; nothing was launched */
+#define POTR_ECAPACITY (-2)     /* a caller buffer is too small (see potr_bin) */
+#define POTR_EHIP (-3)          /* HIP runtime error */
+#define POTR_EUNSUPPORTED (-4)  /* valid request this build does not handle */
+
+/* Pinhole camera, OpenCV axes (x right, y down, z forward). R (row-major) and t
+ * map world points to camera coordinates: p_cam = R p + t. */
+typedef struct potr_camera {
+    float R[9];
+    float t[3];
+    float fx, fy, cx, cy;
+    int32_t width, height;
+} potr_camera;
+
+/* Rasterizer settings. Where the paper leaves a detail open, the setting names it.
+ *  tile_w x tile_h : screen tile, one of 16x16, 8x8, 32x8
+ *  lds_batch       : splat records staged in LDS per batch, 64..512, multiple of 64
+ *  eps2d           : low-pass added to the 2D covariance diagonal (px^2), e.g. 0.3
+ *  near_z          : splats with camera z <= near_z are culled
+ *  jclamp          : x/z and y/z in the Jacobian are clamped to +-jclamp half fields of view
+ *  alpha_min       : a splat counts at a pixel only if o*exp(-q/2) >= alpha_min (e.g. 1/255)
+ *  alpha_max       : alpha = min(alpha_max, o*exp(-q/2)) (e.g. 0.99)
+ *  q_max           : a splat counts at a pixel only if its Mahalanobis q <= q_max (e.g. 9)
+ *  t_min           : compositing stops before the splat that would drive the
+ *                    transmittance below t_min (e.g. 1e-4); 0 = exact mode, no stop
+ *  bg              : background colour, entering as T_final * bg
+ *  sh_degree       : 0..3 */
+typedef struct potr_config {
+    int32_t tile_w, tile_h;
+    int32_t lds_batch;
+    float eps2d, near_z, jclamp;
+    float alpha_min, alpha_max, q_max, t_min;
+    float bg[3];
+    int32_t sh_degree;
+} potr_config;
+
+/* Projected splat for one view (48 bytes). Culled splats have opacity 0 and an
+ * empty rect.
+ *  mean2d : centre in pixels
+ *  conic  : inverse 2D covariance (a, b, c): q = a dx^2 + 2 b dx dy + c dy^2
+ *  opacity: base opacity o
+ *  rgb    : colour, max(0, sum_i L_i Y_i(d) + 1/2), d from the camera centre to the splat
+ *  depth  : camera z by the fixed FP32 chain fma(R22,z,fma(R21,y,fma(R20,x,t_z)));
+ *           its bit pattern orders the splats of a view
+ *  rect   : tiles x0, y0, x1, y1 (half-open) that can hold a pixel where the splat
+ *           counts; a conservative bound, so images do not depend on the tile shape */
+typedef struct potr_proj {
+    float mean2d[2];
+    float conic[3];
+    float opacity;
+    float rgb[3];
+    float depth;
+    int16_t rect[4];
+} potr_proj;
+
+POTR_API int32_t potr_abi_version(void);
+POTR_API const char* potr_last_error(void);
+
+/* ---------------------------------------------------------------------------
+ * potr_project -- Sec. 3: affine (Jacobian) projection of each 3D Gaussian,
+ * Sigma' = J W Sigma W^T J^T + eps2d I with Sigma = R(q) diag(s^2) R(q)^T, its
+ * inverse (the conic), the SH colour along the camera-to-centre direction, the
+ * depth key and the tile rectangle, for N splats x V views.
+ *   cams  (host) [V]
+ *   proj  [V*N] potr_proj, view-major (proj[v*N + i])
+ *   tiles_touched [V*N] int32: number of tiles in rect (0 if culled)
+ * Arithmetic: the projection runs in FP64 and stores FP32.
+ * ------------------------------------------------------------------------- */
+POTR_API potr_status potr_project(int64_t N, int32_t V, const potr_camera* cams, const potr_config* cfg,
+                         const float* means, const float* scales, const float* quats,
+                         const float* opac, const float* sh,
+                         potr_proj* proj, int32_t* tiles_touched, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * potr_bin -- Sec. 3 ("layers ordered by approximate depth"): order each view's
+ * splats by depth key (ties by splat id) and emit one (tile, depth rank) pair per
+ * tile of every splat's rect, in depth order.
+ *   order  [V*N] uint32 out: order[v*N + r] = id of the splat with depth rank r in view v
+ *   pairs  [capacity] uint64 out: ((v*tiles + tile) << 32) | rank
+ *   n_pairs (device) int64 out: total number of pairs. If it exceeds `capacity`,
+ *          no pair is written; the caller grows `pairs` and calls again (the
+ *          Python wrapper does this). Later stages treat such a count as empty.
+ *   ws     workspace of potr_bin_workspace_size bytes.
+ * ------------------------------------------------------------------------- */
+POTR_API potr_status potr_bin_workspace_size(int64_t N, int32_t V, size_t* bytes);
+POTR_API potr_status potr_bin(int64_t N, int32_t V, const potr_camera* cams, const potr_config* cfg,
+                     const potr_proj* proj, const int32_t* tiles_touched, void* ws, size_t ws_bytes,
+                     uint32_t* order, uint64_t* pairs, int64_t capacity, int64_t* n_pairs, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * potr_sort -- stable radix sort of the pairs by (view, tile); since pairs are
+ * emitted in depth-rank order this yields the order (view, tile, depth key,
+ * splat id). Writes the splat id of every sorted pair and each tile's range.
+ *   n_pairs  (device) from potr_bin; n_max (host) >= the count, bounds the launch
+ *            (pass the count itself when known, else the capacity)
+ *   pairs    [capacity] in: from potr_bin; clobbered
+ *   sorted_ids [capacity] uint32 out: splat id (0..N-1) per sorted pair
+ *   tile_ranges [V*tiles*2] int32 out: half-open [start, end) into sorted_ids
+ *   ws       workspace of potr_sort_workspace_size bytes
+ * ------------------------------------------------------------------------- */
+POTR_API potr_status potr_sort_workspace_size(int64_t capacity, int32_t V, int32_t tiles_per_view, size_t* bytes);
+POTR_API potr_status potr_sort(int64_t N, int32_t V, const potr_camera* cams, const potr_config* cfg,
+                      const int64_t* n_pairs, int64_t n_max, uint64_t* pairs, const uint32_t* order,
+                      void* ws, size_t ws_bytes, uint32_t* sorted_ids, int32_t* tile_ranges, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * potr_blend -- Sec. 3, eq. (alpha_blending): front-to-back compositing per pixel
+ * over its tile's sorted list.
+ *   image   [V,H,W,3] out: P_K + T_final * bg
+ *   p_final [V,H,W,3] out: P_K = sum_k T_k alpha_k c_k (paper's partial colour after K splats)
+ *   t_final [V,H,W]   out: T after the last blended splat
+ *   n_walk  [V,H,W]   out int32: list entries visited before the stop (or the list length)
+ * ------------------------------------------------------------------------- */
+POTR_API potr_status potr_blend(int64_t N, int32_t V, const potr_camera* cams, const potr_config* cfg,
+                       const potr_proj* proj, const uint32_t* sorted_ids, const int32_t* tile_ranges,
+                       float* image, float* p_final, float* t_final, int32_t* n_walk, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * potr_score -- Sec. 4.2: the pruning difference of every blended splat k at every
+ * pixel, PD_k = -c_k alpha_k T_k + alpha_k/(1-alpha_k) (S_k + T_final bg) with
+ * S_k = P_K - P_{k+1} (equal to the paper's partial-colour form), reduced per splat
+ * over pixels and views. Outputs are ACCUMULATED (+=); zero them first.
+ *   scores     [N] += sum over pixels and channels of |PD_k|         (may be NULL)
+ *   scores_se  [N] += sum over pixels and channels of dSE_k
+ *                     = |PD_k|^2 + 2 PD_k.(c - target)  (Sec. 4.2; needs target)
+ *   importance [N] += sum over pixels of T_k alpha_k  (Sec. 4.1, before the 1/P)
+ *   target     [V,H,W,3] or NULL
+ * Inputs p_final, t_final, n_walk come from potr_blend with the same lists.
+ * ------------------------------------------------------------------------- */
+POTR_API potr_status potr_score(int64_t N, int32_t V, const potr_camera* cams, const potr_config* cfg,
+                       const potr_proj* proj, const uint32_t* sorted_ids, const int32_t* tile_ranges,
+                       const float* p_final, const float* t_final, const int32_t* n_walk,
+                       const float* target, float* scores, float* scores_se, float* importance,
+                       void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* POTR_H */

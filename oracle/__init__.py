@@ -129,6 +129,7 @@ def default_threads() -> int:
 
 
 def render(scene, cam, s, proj=None, bins=None, target=None, method: int = 0, threads: int | None = None,
+           record_f32: bool = False,
            want=("image", "p_final", "t_final", "n_walk", "n_blend", "score_l1", "importance",
                  "magnitude", "flag_mass", "pixel_flag")) -> dict:
     """Composite one view and reduce the removal effect per splat (see potr_oracle.h)."""
@@ -154,7 +155,7 @@ def render(scene, cam, s, proj=None, bins=None, target=None, method: int = 0, th
     nflag = lib().orc_render(
         C.c_int64(n), C.byref(cm), C.byref(cf), _p(proj["mean2d"], C.c_double), _p(proj["conic"], C.c_double),
         _p(proj["rgb"], C.c_double), _p(_f32(scene.opacities), C.c_float), _p(ranges, C.c_int32),
-        _p(ids, C.c_int32), _p(tgt, C.c_float), C.c_int32(method),
+        _p(ids, C.c_int32), _p(tgt, C.c_float), C.c_int32(method), C.c_int32(int(record_f32)),
         C.c_int32(threads or default_threads()),
         g("image", C.c_double), g("p_final", C.c_double), g("t_final", C.c_double), g("n_walk", C.c_int32),
         g("n_blend", C.c_int32), g("score_l1", C.c_double), g("score_se", C.c_double),
@@ -166,7 +167,7 @@ def render(scene, cam, s, proj=None, bins=None, target=None, method: int = 0, th
     return out
 
 
-def render_without(scene, cam, s, k: int, proj=None, bins=None) -> np.ndarray:
+def render_without(scene, cam, s, k: int, proj=None, bins=None, record_f32: bool = False) -> np.ndarray:
     """Image [H, W, 3] composited with splat k deleted (the plain definition of removal)."""
     if proj is None:
         proj = project(scene, cam, s)
@@ -179,18 +180,20 @@ def render_without(scene, cam, s, k: int, proj=None, bins=None) -> np.ndarray:
                              _p(proj["mean2d"], C.c_double), _p(proj["conic"], C.c_double),
                              _p(proj["rgb"], C.c_double), _p(_f32(scene.opacities), C.c_float),
                              _p(np.ascontiguousarray(ranges, np.int32), C.c_int32),
-                             _p(np.ascontiguousarray(ids, np.int32), C.c_int32), C.c_int64(k), _p(img, C.c_double))
+                             _p(np.ascontiguousarray(ids, np.int32), C.c_int32), C.c_int64(k),
+                             C.c_int32(int(record_f32)), _p(img, C.c_double))
     return img
 
 
 def score_views(scene, cams, s, method: int = 0, threads: int | None = None, target_images=None,
+                record_f32: bool = False,
                 want=("image", "score_l1", "importance", "magnitude", "flag_mass", "pixel_flag")):
     """Accumulate per-splat outputs over several views; returns (totals, per_view list)."""
     tot = {}
     views = []
     for v, cam in enumerate(cams):
         tgt = None if target_images is None else target_images[v]
-        r = render(scene, cam, s, target=tgt, method=method, threads=threads, want=want)
+        r = render(scene, cam, s, target=tgt, method=method, threads=threads, record_f32=record_f32, want=want)
         views.append(r)
         for k in ("score_l1", "score_se", "importance", "magnitude", "flag_mass"):
             if k in r:

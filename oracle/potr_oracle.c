@@ -180,6 +180,7 @@ void orc_project(int64_t N, const orc_camera* cam, const orc_config* cfg,
         double t_cut = fmin((double)cfg->q_max, 2.0 * log(o / (double)cfg->alpha_min));
         double rx = sqrt(t_cut * cxx) * (1.0 + 1.0 / 1024.0) + 1.0 / 64.0;
         double ry = sqrt(t_cut * cyy) * (1.0 + 1.0 / 1024.0) + 1.0 / 64.0;
+        if (!isfinite(u) || !isfinite(v) || !isfinite(rx) || !isfinite(ry)) continue;
         double ilo = fmax(ceil(u - rx - 0.5), 0.0), ihi = fmin(floor(u + rx - 0.5), W - 1.0);
         double jlo = fmax(ceil(v - ry - 0.5), 0.0), jhi = fmin(floor(v + ry - 0.5), H - 1.0);
 
@@ -317,6 +318,7 @@ typedef struct {
     const int32_t *tile_ranges, *sorted_id;
     const float* target;
     int removal_method;
+    int rec32;                  /* evaluate records rounded to FP32 (the stored record precision) */
     double *image, *p_final, *t_final;
     int32_t *n_walk, *n_blend;
     double *score_l1, *score_se, *importance, *magnitude, *flag_mass;
@@ -327,12 +329,15 @@ typedef struct {
     pthread_mutex_t mu;
 } render_ctx;
 
+static inline double rec(const render_ctx* c, double x) { return c->rec32 ? (double)(float)x : x; }
+
 /* One evaluation of splat s at pixel centre (px, py): q and o*G. */
 static void eval_splat(const render_ctx* c, int64_t s, double px, double py,
                        double* q_out, double* dq_err, double* a0_out)
 {
-    double dx = px - c->mean2d[2 * s], dy = py - c->mean2d[2 * s + 1];
-    double A = c->conic[3 * s], B = c->conic[3 * s + 1], C = c->conic[3 * s + 2];
+    const double mx = rec(c, c->mean2d[2 * s]), my = rec(c, c->mean2d[2 * s + 1]);
+    double dx = px - mx, dy = py - my;
+    double A = rec(c, c->conic[3 * s]), B = rec(c, c->conic[3 * s + 1]), C = rec(c, c->conic[3 * s + 2]);
     double q = A * dx * dx + 2.0 * B * dx * dy + C * dy * dy;
     *q_out = q;
     *a0_out = (double)c->opac[s] * exp(-0.5 * q);
@@ -340,11 +345,18 @@ static void eval_splat(const render_ctx* c, int64_t s, double px, double py,
      * to flag decisions that FP32 arithmetic could take the other way): rounding
      * of the pixel offsets, of the conic and of the quadratic form itself. */
     const double u = ldexp(1.0, -24);
-    double edx = (fabs(c->mean2d[2 * s]) + fabs(dx) + fabs(px)) * u;
-    double edy = (fabs(c->mean2d[2 * s + 1]) + fabs(dy) + fabs(py)) * u;
+    double edx = c->rec32 ? fabs(dx) * u : (fabs(mx) + fabs(dx) + fabs(px)) * u;
+    double edy = c->rec32 ? fabs(dy) * u : (fabs(my) + fabs(dy) + fabs(py)) * u;
     double qabs = fabs(A) * dx * dx + 2.0 * fabs(B * dx * dy) + fabs(C) * dy * dy;
     *dq_err = 2.0 * fabs(A * dx + B * dy) * edx + 2.0 * fabs(B * dx + C * dy) * edy + 12.0 * u * qabs;
 }
+
+/* A decision an FP32 evaluation could take the other way, and what it moves:
+ * kind 0: splat at blended position `pos` is near a visibility threshold;
+ * kind 1: a splat the oracle skips is near visible (it would sit before `pos`);
+ * kind 2: the early stop is near its threshold; `dS` is what the splats an FP32
+ *         walk might still blend add to the colour. */
+typedef struct { int kind, pos; double alpha, T, dS; } flip_event;
 
 static void render_row(void* vctx, int py_i)
 {
@@ -361,9 +373,11 @@ static void render_row(void* vctx, int py_i)
     double* Tk = (double*)malloc(sizeof(double) * M);
     double* Pk = (double*)malloc(sizeof(double) * 3 * (M + 1)); /* P_i, i = 0..K */
     int64_t* ids = (int64_t*)malloc(sizeof(int64_t) * M);
-    int64_t* near_ids = (int64_t*)malloc(sizeof(int64_t) * M);
-    double* near_T = (double*)malloc(sizeof(double) * M);
-    double* near_a = (double*)malloc(sizeof(double) * M);
+    flip_event* ev = (flip_event*)malloc(sizeof(flip_event) * (M + 1));
+    int64_t* extra_id = (int64_t*)malloc(sizeof(int64_t) * M);   /* splats blended only by a flip */
+    double* extra_m = (double*)malloc(sizeof(double) * M);       /* ... their own term T a |c|_1 */
+    double* extra_r = (double*)malloc(sizeof(double) * M);       /* ... a / (1 - a) */
+    double* extra_b = (double*)malloc(sizeof(double) * M);       /* ... colour behind them (<0: P_K) */
     int64_t row_flagged = 0;
 
     for (int px_i = 0; px_i < W; ++px_i) {
@@ -371,7 +385,7 @@ static void render_row(void* vctx, int py_i)
         const int tile = (py_i / th) * tiles_x + px_i / tw;
         const int beg = c->tile_ranges[2 * tile], end = c->tile_ranges[2 * tile + 1];
         double T = 1.0, elnT = 0.0;
-        int K = 0, stop = end, flagged = 0, n_near = 0;
+        int K = 0, stop = end, n_ev = 0, n_extra = 0;
         Pk[0] = Pk[1] = Pk[2] = 0.0;
         int pos;
         for (pos = beg; pos < end; ++pos) {
@@ -379,6 +393,9 @@ static void render_row(void* vctx, int py_i)
             if (s == c->skip_id) continue;
             double q, eq, a0;
             eval_splat(c, s, px, py, &q, &eq, &a0);
+            double col[3];
+            for (int ch = 0; ch < 3; ++ch) col[ch] = rec(c, c->rgb[3 * s + ch]);
+            const double c1 = fabs(col[0]) + fabs(col[1]) + fabs(col[2]);
             /* decisions that an FP32 evaluation could flip */
             double elna = 0.5 * eq + 0.5 * q * 4.0 * u + 8.0 * u;
             const int vis_q = q <= qmax, vis_a = a0 >= amin;
@@ -387,22 +404,29 @@ static void render_row(void* vctx, int py_i)
             const int may_flip = (nq && (vis_a || na)) || (na && (vis_q || nq));
             if (!vis_q || !vis_a) {
                 if (may_flip) {
-                    flagged = 1;
-                    near_ids[n_near] = s; near_T[n_near] = T; near_a[n_near] = fmin(amax, a0); ++n_near;
+                    const double a = fmin(amax, a0);
+                    flip_event e = { 1, K, a, T, T * a * c1 };
+                    ev[n_ev++] = e;
+                    extra_id[n_extra] = s; extra_m[n_extra] = T * a * c1;
+                    extra_r[n_extra] = a / (1.0 - a); extra_b[n_extra++] = -1.0;
                 }
                 continue;
             }
-            if (may_flip) flagged = 1;
             double a = fmin(amax, a0);
             double ea = a0 < amax ? elna : 0.0;
             double Tn = T * (1.0 - a);
+            if (may_flip) {
+                flip_event e = { 0, K, a, T, T * a * c1 };
+                ev[n_ev++] = e;
+            }
             if (tmin > 0.0) {
                 double e = elnT + a / (1.0 - a) * ea + 4.0 * u;
-                if (fabs(log(Tn) - log(tmin)) <= 4.0 * e) {
-                    flagged = 1;
-                    /* splats an FP32 walk could still blend past this point */
-                    double Tv = T;
-                    for (int pv = pos; pv < end && n_near < M; ++pv) {
+                int near_stop = fabs(log(Tn) - log(tmin)) <= 4.0 * e;
+                if (near_stop) {
+                    /* splats an FP32 walk could still blend from here on */
+                    double Tv = T, dS = 0.0;
+                    const int first_extra = n_extra;
+                    for (int pv = pos; pv < end && n_extra < M; ++pv) {
                         int64_t sv = c->sorted_id[pv];
                         if (sv == c->skip_id) continue;
                         double qv, eqv, av;
@@ -410,20 +434,30 @@ static void render_row(void* vctx, int py_i)
                         if (!(qv <= qmax * (1.0 + 1e-3)) || !(av >= amin * (1.0 - 1e-3))) continue;
                         av = fmin(amax, av);
                         if (Tv * (1.0 - av) < tmin * exp(-8.0 * e)) break;
-                        near_ids[n_near] = sv; near_T[n_near] = Tv; near_a[n_near] = av; ++n_near;
+                        double cv[3];
+                        for (int ch = 0; ch < 3; ++ch) cv[ch] = rec(c, c->rgb[3 * sv + ch]);
+                        double m = Tv * av * (fabs(cv[0]) + fabs(cv[1]) + fabs(cv[2]));
+                        dS += m;
+                        if (Tn < tmin || pv > pos) {
+                            extra_id[n_extra] = sv; extra_m[n_extra] = m;
+                            extra_r[n_extra] = av / (1.0 - av); extra_b[n_extra++] = 0.0;
+                        }
                         Tv *= (1.0 - av);
                     }
+                    for (int k = first_extra; k < n_extra; ++k) extra_b[k] = dS;
+                    flip_event ee = { 2, K, a, T, dS };
+                    ev[n_ev++] = ee;
                 }
                 if (Tn < tmin) { stop = pos; break; }
             }
             elnT += a / (1.0 - a) * ea + 4.0 * u;
             al[K] = a; Tk[K] = T; ids[K] = s;
-            const double* col = c->rgb + 3 * s;
             for (int ch = 0; ch < 3; ++ch) Pk[3 * (K + 1) + ch] = Pk[3 * K + ch] + T * a * col[ch];
             T = Tn;
             ++K;
         }
         if (pos >= end) stop = end;
+        const int flagged = n_ev > 0;
         const int64_t pix = (int64_t)py_i * W + px_i;
         const double* PK = Pk + 3 * K;
         double img[3];
@@ -436,11 +470,12 @@ static void render_row(void* vctx, int py_i)
         if (c->pixel_flag) c->pixel_flag[pix] = (uint8_t)flagged;
         row_flagged += flagged;
 
-        double sumabsP = fabs(PK[0]) + fabs(PK[1]) + fabs(PK[2]);
-        double sumabsB = T * (fabs(bg[0]) + fabs(bg[1]) + fabs(bg[2]));
+        const double sumabsP = fabs(PK[0]) + fabs(PK[1]) + fabs(PK[2]);
+        const double sumabsB = T * (fabs(bg[0]) + fabs(bg[1]) + fabs(bg[2]));
         for (int k = 0; k < K; ++k) {
             const double a = al[k];
-            const double* col = c->rgb + 3 * ids[k];
+            double col[3];
+            for (int ch = 0; ch < 3; ++ch) col[ch] = rec(c, c->rgb[3 * ids[k] + ch]);
             double PD[3];
             if (c->removal_method == 0) {
                 /* Sec. 4.2: PD_k = P_{i_k} - P_{i_k+1}/(1-a) + a/(1-a) P_K, plus the
@@ -453,8 +488,7 @@ static void render_row(void* vctx, int py_i)
                 double Tw = 1.0, Cw[3] = { 0, 0, 0 };
                 for (int j = 0; j < K; ++j) {
                     if (j == k) continue;
-                    const double* cj = c->rgb + 3 * ids[j];
-                    for (int ch = 0; ch < 3; ++ch) Cw[ch] += Tw * al[j] * cj[ch];
+                    for (int ch = 0; ch < 3; ++ch) Cw[ch] += Tw * al[j] * rec(c, c->rgb[3 * ids[j] + ch]);
                     Tw *= (1.0 - al[j]);
                 }
                 for (int ch = 0; ch < 3; ++ch) PD[ch] = Cw[ch] + Tw * bg[ch] - img[ch];
@@ -468,22 +502,37 @@ static void render_row(void* vctx, int py_i)
                 atomic_add_f64(&c->score_se[s], se);
             }
             if (c->importance) atomic_add_f64(&c->importance[s], Tk[k] * a);
-            double mag = Tk[k] * a * (fabs(col[0]) + fabs(col[1]) + fabs(col[2])) +
-                         a / (1.0 - a) * (sumabsP + sumabsB);
+            const double ratio = a / (1.0 - a);
+            const double mag = Tk[k] * a * (fabs(col[0]) + fabs(col[1]) + fabs(col[2])) + ratio * (sumabsP + sumabsB);
             if (c->magnitude) atomic_add_f64(&c->magnitude[s], mag);
-            if (flagged && c->flag_mass) atomic_add_f64(&c->flag_mass[s], 2.0 * mag);
+            if (flagged && c->flag_mass) {
+                /* first-order change of this splat's |PD| if an event flips */
+                double F = 0.0;
+                for (int e = 0; e < n_ev; ++e) {
+                    const flip_event* f = &ev[e];
+                    const double re = f->alpha / (1.0 - f->alpha);
+                    if (f->kind == 2) {            /* early stop: k may vanish or S_k may grow */
+                        if (k >= f->pos) F += mag;
+                        else F += ratio * (f->dS + sumabsB);
+                    } else if (f->kind == 0 && f->pos == k) {
+                        F += mag;                  /* its own visibility */
+                    } else if (f->pos > k) {       /* behind k: S_k and T_final move */
+                        F += ratio * (f->dS + re * (sumabsP + sumabsB));
+                    } else {                       /* in front of k: T_k scales by 1/(1-a) */
+                        F += 2.0 * re * mag;
+                    }
+                }
+                atomic_add_f64(&c->flag_mass[s], 2.0 * F);
+            }
         }
         if (flagged && c->flag_mass) {
-            for (int k = 0; k < n_near; ++k) {
-                const double a = near_a[k];
-                const double* col = c->rgb + 3 * near_ids[k];
-                double mag = near_T[k] * a * (fabs(col[0]) + fabs(col[1]) + fabs(col[2])) +
-                             a / (1.0 - a) * (sumabsP + sumabsB + near_T[k] * a * 3.0);
-                atomic_add_f64(&c->flag_mass[near_ids[k]], 2.0 * mag);
+            for (int k = 0; k < n_extra; ++k) {
+                const double behind = extra_b[k] < 0.0 ? sumabsP : extra_b[k];
+                atomic_add_f64(&c->flag_mass[extra_id[k]], 2.0 * (extra_m[k] + extra_r[k] * (behind + sumabsB)));
             }
         }
     }
-    free(al); free(Tk); free(Pk); free(ids); free(near_ids); free(near_T); free(near_a);
+    free(al); free(Tk); free(Pk); free(ids); free(ev); free(extra_id); free(extra_m); free(extra_r); free(extra_b);
     pthread_mutex_lock(&c->mu);
     c->n_flagged += row_flagged;
     pthread_mutex_unlock(&c->mu);
@@ -503,7 +552,7 @@ static int max_list_len(const orc_camera* cam, const orc_config* cfg, const int3
 int64_t orc_render(int64_t N, const orc_camera* cam, const orc_config* cfg,
                    const double* mean2d, const double* conic, const double* rgb,
                    const float* opac, const int32_t* tile_ranges, const int32_t* sorted_id,
-                   const float* target, int32_t removal_method, int32_t n_threads,
+                   const float* target, int32_t removal_method, int32_t record_f32, int32_t n_threads,
                    double* image, double* p_final, double* t_final, int32_t* n_walk,
                    int32_t* n_blend, double* score_l1, double* score_se, double* importance,
                    double* magnitude, double* flag_mass, uint8_t* pixel_flag)
@@ -513,6 +562,7 @@ int64_t orc_render(int64_t N, const orc_camera* cam, const orc_config* cfg,
     c.N = N; c.cam = cam; c.cfg = cfg; c.mean2d = mean2d; c.conic = conic; c.rgb = rgb; c.opac = opac;
     c.tile_ranges = tile_ranges; c.sorted_id = sorted_id; c.target = target;
     c.removal_method = removal_method;
+    c.rec32 = record_f32;
     c.image = image; c.p_final = p_final; c.t_final = t_final; c.n_walk = n_walk; c.n_blend = n_blend;
     c.score_l1 = score_l1; c.score_se = score_se; c.importance = importance; c.magnitude = magnitude;
     c.flag_mass = flag_mass; c.pixel_flag = pixel_flag;
@@ -527,13 +577,14 @@ int64_t orc_render(int64_t N, const orc_camera* cam, const orc_config* cfg,
 void orc_render_without(int64_t N, const orc_camera* cam, const orc_config* cfg,
                         const double* mean2d, const double* conic, const double* rgb,
                         const float* opac, const int32_t* tile_ranges, const int32_t* sorted_id,
-                        int64_t k, double* image)
+                        int64_t k, int32_t record_f32, double* image)
 {
     render_ctx c;
     memset(&c, 0, sizeof(c));
     c.N = N; c.cam = cam; c.cfg = cfg; c.mean2d = mean2d; c.conic = conic; c.rgb = rgb; c.opac = opac;
     c.tile_ranges = tile_ranges; c.sorted_id = sorted_id;
     c.removal_method = 0;
+    c.rec32 = record_f32;
     c.image = image;
     c.skip_id = k;
     c.max_list = max_list_len(cam, cfg, tile_ranges);

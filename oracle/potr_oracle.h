@@ -76,7 +76,9 @@ int64_t orc_bin_sort(int64_t N, int32_t tiles_x, int32_t tiles_y, const int32_t*
 
 /* Composite one view and evaluate the removal effect of every blended splat.
  * removal_method: 0 = the paper's partial-colour closed form, 1 = definition
- * (composite again without splat k). Optional outputs may be NULL.
+ * (composite again without splat k). record_f32 != 0 evaluates the projected
+ * centre, conic and colour rounded to FP32 (the precision the rasterizer stores
+ * them in); compositing stays FP64. Optional outputs may be NULL.
  *   image/p_final [H*W*3], t_final [H*W], n_walk [H*W] (list position of the
  *   stop, or the list length), n_blend [H*W];
  *   score_l1 [N] += sum over pixels and channels of |PD_k|;
@@ -89,7 +91,7 @@ int64_t orc_bin_sort(int64_t N, int32_t tiles_x, int32_t tiles_y, const int32_t*
 int64_t orc_render(int64_t N, const orc_camera* cam, const orc_config* cfg,
                    const double* mean2d, const double* conic, const double* rgb,
                    const float* opac, const int32_t* tile_ranges, const int32_t* sorted_id,
-                   const float* target, int32_t removal_method, int32_t n_threads,
+                   const float* target, int32_t removal_method, int32_t record_f32, int32_t n_threads,
                    double* image, double* p_final, double* t_final, int32_t* n_walk,
                    int32_t* n_blend, double* score_l1, double* score_se, double* importance,
                    double* magnitude, double* flag_mass, uint8_t* pixel_flag);
@@ -99,7 +101,7 @@ int64_t orc_render(int64_t N, const orc_camera* cam, const orc_config* cfg,
 void orc_render_without(int64_t N, const orc_camera* cam, const orc_config* cfg,
                         const double* mean2d, const double* conic, const double* rgb,
                         const float* opac, const int32_t* tile_ranges, const int32_t* sorted_id,
-                        int64_t k, double* image);
+                        int64_t k, int32_t record_f32, double* image);
 
 /* Gradient of a loss L through the compositing of one view and the projection.
  * dL_dimage [H*W*3]. Gradients (+=) with the input shapes: d_means [N*3],

@@ -1,0 +1,124 @@
+"""ctypes binding of libpotr.so (include/potr.h). Argument marshalling only.
+
+Names mirror the C entry points. Buffers are torch tensors on the GPU; their
+device pointers are passed as-is. Loading fails loudly if libpotr.so is
+missing: there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpotr.so")
+
+POTR_OK, POTR_EINVAL, POTR_ECAPACITY, POTR_EHIP, POTR_EUNSUPPORTED = 0, -1, -2, -3, -4
+PROJ_BYTES = 48
+# potr_proj as a numpy record (for inspecting device results on the host)
+PROJ_DTYPE = np.dtype([("mean2d", "<f4", (2,)), ("conic", "<f4", (3,)), ("opacity", "<f4"), ("rgb", "<f4", (3,)),
+                       ("depth", "<f4"), ("rect", "<i2", (4,))])
+assert PROJ_DTYPE.itemsize == PROJ_BYTES
+
+# every function the header declares, with its argument and return types
+_vp, _i32, _i64, _sz = C.c_void_p, C.c_int32, C.c_int64, C.c_size_t
+
+
+class potr_camera(C.Structure):
+    _fields_ = [("R", C.c_float * 9), ("t", C.c_float * 3), ("fx", C.c_float), ("fy", C.c_float),
+                ("cx", C.c_float), ("cy", C.c_float), ("width", C.c_int32), ("height", C.c_int32)]
+
+
+class potr_config(C.Structure):
+    _fields_ = [("tile_w", C.c_int32), ("tile_h", C.c_int32), ("lds_batch", C.c_int32),
+                ("eps2d", C.c_float), ("near_z", C.c_float), ("jclamp", C.c_float),
+                ("alpha_min", C.c_float), ("alpha_max", C.c_float), ("q_max", C.c_float),
+                ("t_min", C.c_float), ("bg", C.c_float * 3), ("sh_degree", C.c_int32)]
+
+
+_CAM_P, _CFG_P = C.POINTER(potr_camera), C.POINTER(potr_config)
+
+SIGNATURES = {
+    "potr_abi_version": (_i32, []),
+    "potr_last_error": (C.c_char_p, []),
+    "potr_project": (_i32, [_i64, _i32, _CAM_P, _CFG_P, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
+    "potr_bin_workspace_size": (_i32, [_i64, _i32, C.POINTER(_sz)]),
+    "potr_bin": (_i32, [_i64, _i32, _CAM_P, _CFG_P, _vp, _vp, _vp, _sz, _vp, _vp, _i64, _vp, _vp]),
+    "potr_sort_workspace_size": (_i32, [_i64, _i32, _i32, C.POINTER(_sz)]),
+    "potr_sort": (_i32, [_i64, _i32, _CAM_P, _CFG_P, _vp, _i64, _vp, _vp, _vp, _sz, _vp, _vp, _vp]),
+    "potr_blend": (_i32, [_i64, _i32, _CAM_P, _CFG_P, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
+    "potr_score": (_i32, [_i64, _i32, _CAM_P, _CFG_P, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
+}
+
+_lib = None
+
+
+class PotrError(RuntimeError):
+    def __init__(self, fn: str, status: int, msg: str):
+        super().__init__(f"{fn} failed ({status}): {msg}")
+        self.status = status
+
+
+def lib():
+    """Load libpotr.so (no fallback: a missing library is an error)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing; build it with `python -m paper_2601_14821_amd.build`")
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def call(name: str, *args) -> None:
+    st = getattr(lib(), name)(*args)
+    if st != POTR_OK:
+        raise PotrError(name, st, lib().potr_last_error().decode())
+
+
+def ptr(t) -> int | None:
+    """Device pointer of a torch tensor (None for None)."""
+    return None if t is None else t.data_ptr()
+
+
+def stream_handle(stream=None) -> int:
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return s.cuda_stream
+
+
+def make_cameras(cams):
+    arr = (potr_camera * len(cams))()
+    for k, c in enumerate(cams):
+        arr[k].R[:] = [float(x) for x in np.asarray(c.R, np.float32).reshape(-1)]
+        arr[k].t[:] = [float(x) for x in np.asarray(c.t, np.float32).reshape(-1)]
+        arr[k].fx, arr[k].fy, arr[k].cx, arr[k].cy = c.fx, c.fy, c.cx, c.cy
+        arr[k].width, arr[k].height = c.width, c.height
+    return arr
+
+
+def make_config(s) -> potr_config:
+    c = potr_config()
+    c.tile_w, c.tile_h, c.lds_batch = s.tile_w, s.tile_h, s.lds_batch
+    c.eps2d, c.near_z, c.jclamp = s.eps2d, s.near, s.jclamp
+    c.alpha_min, c.alpha_max, c.q_max, c.t_min = s.alpha_min, s.alpha_max, s.q_max, s.t_min
+    c.bg[:] = [float(x) for x in s.bg]
+    c.sh_degree = s.sh_degree
+    return c
+
+
+def bin_workspace_size(N: int, V: int) -> int:
+    b = C.c_size_t(0)
+    call("potr_bin_workspace_size", N, V, C.byref(b))
+    return b.value
+
+
+def sort_workspace_size(capacity: int, V: int, tiles_per_view: int) -> int:
+    b = C.c_size_t(0)
+    call("potr_sort_workspace_size", capacity, V, tiles_per_view, C.byref(b))
+    return b.value

@@ -1,0 +1,164 @@
+// C ABI of libpotr.so: argument validation, workspace sizing, error reporting.
+// Every entry point validates on the host, then enqueues kernels on the
+// caller's stream; none of them allocates device memory.
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+
+#include "common.h"
+
+namespace potr {
+
+static thread_local char g_err[512] = "";
+
+potr_status fail(potr_status st, const char* fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+    return st;
+}
+
+potr_status check_launch(const char* what) {
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(POTR_EHIP, "%s: %s", what, hipGetErrorString(e));
+    return POTR_OK;
+}
+
+}  // namespace potr
+
+using namespace potr;
+
+namespace {
+
+potr_status check_cfg(const potr_config* cfg) {
+    if (!cfg) return fail(POTR_EINVAL, "config is NULL");
+    const bool shape_ok = (cfg->tile_w == 16 && cfg->tile_h == 16) || (cfg->tile_w == 8 && cfg->tile_h == 8) ||
+                          (cfg->tile_w == 32 && cfg->tile_h == 8);
+    if (!shape_ok) return fail(POTR_EINVAL, "tile %dx%d: expected 16x16, 8x8 or 32x8", cfg->tile_w, cfg->tile_h);
+    if (cfg->lds_batch < 64 || cfg->lds_batch > 512 || cfg->lds_batch % 64)
+        return fail(POTR_EINVAL, "lds_batch %d: expected 64..512, multiple of 64", cfg->lds_batch);
+    if (cfg->sh_degree < 0 || cfg->sh_degree > 3) return fail(POTR_EINVAL, "sh_degree %d not in 0..3", cfg->sh_degree);
+    if (!(cfg->alpha_min > 0.f) || !(cfg->alpha_max < 1.f) || !(cfg->alpha_min <= cfg->alpha_max))
+        return fail(POTR_EINVAL, "need 0 < alpha_min <= alpha_max < 1");
+    if (!(cfg->q_max > 0.f) || !(cfg->t_min >= 0.f) || !(cfg->t_min < 1.f) || !(cfg->eps2d >= 0.f))
+        return fail(POTR_EINVAL, "need q_max > 0, 0 <= t_min < 1, eps2d >= 0");
+    return POTR_OK;
+}
+
+potr_status check_cams(int32_t V, const potr_camera* cams, const potr_config* cfg) {
+    if (V < 1) return fail(POTR_EINVAL, "V = %d, need >= 1", V);
+    if (!cams) return fail(POTR_EINVAL, "cams is NULL");
+    for (int32_t v = 0; v < V; ++v) {
+        const potr_camera& c = cams[v];
+        if (c.width < 1 || c.height < 1 || c.width > 16384 || c.height > 16384)
+            return fail(POTR_EINVAL, "view %d: size %dx%d out of range", v, c.width, c.height);
+        if (c.width != cams[0].width || c.height != cams[0].height)
+            return fail(POTR_EINVAL, "view %d: all views of one call need the same size", v);
+        if (!(c.fx > 0.f) || !(c.fy > 0.f)) return fail(POTR_EINVAL, "view %d: focal lengths must be > 0", v);
+    }
+    const int64_t tiles = (int64_t)tiles_x(cams[0], *cfg) * tiles_y(cams[0], *cfg);
+    if (tiles * V >= (int64_t(1) << 31)) return fail(POTR_EINVAL, "too many tiles x views");
+    return POTR_OK;
+}
+
+bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
+
+}  // namespace
+
+extern "C" {
+
+int32_t potr_abi_version(void) { return POTR_ABI_VERSION; }
+
+const char* potr_last_error(void) { return g_err; }
+
+potr_status potr_project(int64_t N, int32_t V, const potr_camera* cams, const potr_config* cfg, const float* means,
+                         const float* scales, const float* quats, const float* opac, const float* sh,
+                         potr_proj* proj, int32_t* tiles_touched, void* stream) {
+    potr_status st = check_cfg(cfg);
+    if (st == POTR_OK) st = check_cams(V, cams, cfg);
+    if (st != POTR_OK) return st;
+    if (N < 0 || N >= (int64_t(1) << 31)) return fail(POTR_EINVAL, "N = %lld out of range", (long long)N);
+    if (N > 0 && (!means || !scales || !quats || !opac || !sh || !proj || !tiles_touched))
+        return fail(POTR_EINVAL, "NULL buffer");
+    if (!aligned16(proj)) return fail(POTR_EINVAL, "proj must be 16-byte aligned");
+    return launch_project(N, V, cams, *cfg, means, scales, quats, opac, sh, proj, tiles_touched,
+                          (hipStream_t)stream);
+}
+
+potr_status potr_bin_workspace_size(int64_t N, int32_t V, size_t* bytes) {
+    if (!bytes || N < 0 || V < 1) return fail(POTR_EINVAL, "bad arguments");
+    *bytes = bin_workspace_bytes(N, V);
+    return POTR_OK;
+}
+
+potr_status potr_bin(int64_t N, int32_t V, const potr_camera* cams, const potr_config* cfg, const potr_proj* proj,
+                     const int32_t* tiles_touched, void* ws, size_t ws_bytes, uint32_t* order, uint64_t* pairs,
+                     int64_t capacity, int64_t* n_pairs, void* stream) {
+    potr_status st = check_cfg(cfg);
+    if (st == POTR_OK) st = check_cams(V, cams, cfg);
+    if (st != POTR_OK) return st;
+    if (N < 0 || N * (int64_t)V >= (int64_t(1) << 31)) return fail(POTR_EINVAL, "N x V out of range");
+    if (capacity < 0 || capacity >= (int64_t(1) << 31)) return fail(POTR_EINVAL, "capacity out of range");
+    if (!n_pairs || (N > 0 && (!proj || !tiles_touched || !ws || !order)) || (capacity > 0 && !pairs))
+        return fail(POTR_EINVAL, "NULL buffer");
+    if (ws_bytes < bin_workspace_bytes(N, V))
+        return fail(POTR_ECAPACITY, "bin workspace %zu < %zu bytes", ws_bytes, bin_workspace_bytes(N, V));
+    return launch_bin(N, V, cams[0], *cfg, proj, tiles_touched, ws, order, pairs, capacity, n_pairs,
+                      (hipStream_t)stream);
+}
+
+potr_status potr_sort_workspace_size(int64_t capacity, int32_t V, int32_t tiles_per_view, size_t* bytes) {
+    if (!bytes || capacity < 0 || V < 1 || tiles_per_view < 1) return fail(POTR_EINVAL, "bad arguments");
+    *bytes = sort_workspace_bytes(capacity, V, tiles_per_view);
+    return POTR_OK;
+}
+
+potr_status potr_sort(int64_t N, int32_t V, const potr_camera* cams, const potr_config* cfg,
+                      const int64_t* n_pairs, int64_t n_max, uint64_t* pairs, const uint32_t* order, void* ws,
+                      size_t ws_bytes, uint32_t* sorted_ids, int32_t* tile_ranges, void* stream) {
+    potr_status st = check_cfg(cfg);
+    if (st == POTR_OK) st = check_cams(V, cams, cfg);
+    if (st != POTR_OK) return st;
+    if (n_max < 0 || n_max >= (int64_t(1) << 31)) return fail(POTR_EINVAL, "n_max out of range");
+    if (!n_pairs || !tile_ranges || (n_max > 0 && (!pairs || !order || !ws || !sorted_ids)))
+        return fail(POTR_EINVAL, "NULL buffer");
+    const int32_t tpv = tiles_x(cams[0], *cfg) * tiles_y(cams[0], *cfg);
+    if (ws_bytes < sort_workspace_bytes(n_max, V, tpv))
+        return fail(POTR_ECAPACITY, "sort workspace %zu < %zu bytes", ws_bytes, sort_workspace_bytes(n_max, V, tpv));
+    return launch_sort(N, V, tpv, n_pairs, n_max, pairs, order, ws, sorted_ids, tile_ranges, (hipStream_t)stream);
+}
+
+potr_status potr_blend(int64_t N, int32_t V, const potr_camera* cams, const potr_config* cfg,
+                       const potr_proj* proj, const uint32_t* sorted_ids, const int32_t* tile_ranges, float* image,
+                       float* p_final, float* t_final, int32_t* n_walk, void* stream) {
+    potr_status st = check_cfg(cfg);
+    if (st == POTR_OK) st = check_cams(V, cams, cfg);
+    if (st != POTR_OK) return st;
+    if (!tile_ranges || !image || (N > 0 && (!proj || !sorted_ids))) return fail(POTR_EINVAL, "NULL buffer");
+    if (!aligned16(proj)) return fail(POTR_EINVAL, "proj must be 16-byte aligned");
+    return launch_blend(N, V, cams[0], *cfg, proj, sorted_ids, tile_ranges, image, p_final, t_final, n_walk,
+                        (hipStream_t)stream);
+}
+
+potr_status potr_score(int64_t N, int32_t V, const potr_camera* cams, const potr_config* cfg,
+                       const potr_proj* proj, const uint32_t* sorted_ids, const int32_t* tile_ranges,
+                       const float* p_final, const float* t_final, const int32_t* n_walk, const float* target,
+                       float* scores, float* scores_se, float* importance, void* stream) {
+    potr_status st = check_cfg(cfg);
+    if (st == POTR_OK) st = check_cams(V, cams, cfg);
+    if (st != POTR_OK) return st;
+    if (N < 0) return fail(POTR_EINVAL, "N = %lld", (long long)N);
+    if (N == 0) return POTR_OK;   /* no splat: nothing to accumulate */
+    if (!tile_ranges || !p_final || !t_final || !n_walk || !proj || !sorted_ids)
+        return fail(POTR_EINVAL, "NULL buffer");
+    if (scores_se && !target) return fail(POTR_EINVAL, "scores_se needs a target image");
+    if (!scores && !scores_se && !importance) return fail(POTR_EINVAL, "no output requested");
+    if (!aligned16(proj)) return fail(POTR_EINVAL, "proj must be 16-byte aligned");
+    return launch_score(N, V, cams[0], *cfg, proj, sorted_ids, tile_ranges, p_final, t_final, n_walk, target,
+                        scores, scores_se, importance, (hipStream_t)stream);
+}
+
+}  // extern "C"

@@ -1,0 +1,293 @@
+// Front-to-back alpha compositing (paper Sec. 3) and the removal pass (Sec. 4.2).
+//
+// One workgroup per (tile, view), one thread per pixel: 16x16 and 32x8 tiles are
+// four wave64s, 8x8 is one. The tile's depth-sorted records are staged through
+// LDS in batches of cfg.lds_batch; every lane of a wave then reads the same LDS
+// record (a broadcast, no bank conflicts) and evaluates it for its own pixel.
+//
+// potr_score walks each pixel's visited prefix again, front to back, and forms
+//   PD_k = -c_k w_k + alpha_k/(1-alpha_k) (S_k + T_final bg),
+//   w_k = T_k alpha_k,  S_k = P_K - P_{k+1},
+// which equals the paper's P_{i_k} - P_{i_k+1}/(1-alpha) + alpha/(1-alpha) P_K
+// (with the background term added) since P_{k+1} = P_k + w_k c_k. Per splat the
+// pixel values are summed across the wave with cross-lane shuffles, across the
+// waves of the tile through LDS, and then added to the per-splat output with one
+// device atomic per (tile, splat) that has a nonzero sum.
+#include "common.h"
+
+namespace potr {
+namespace {
+
+constexpr int kMaxBatch = 512;
+
+template <int NT>
+__device__ inline void stage_batch(const potr_proj* __restrict__ pv, const uint32_t* __restrict__ ids, int base,
+                                   int cnt, float4* s_a, float4* s_b, float* s_c, uint32_t* s_id) {
+    for (int j = threadIdx.x; j < cnt; j += NT) {
+        const uint32_t id = ids[base + j];
+        const float4* src = reinterpret_cast<const float4*>(pv + id);
+        const float4 r0 = src[0];   // mean2d.x, mean2d.y, conic.a, conic.b
+        const float4 r1 = src[1];   // conic.c, opacity, r, g
+        const float4 r2 = src[2];   // b, depth, rect
+        s_a[j] = make_float4(r0.x, r0.y, r1.y, r0.w);
+        s_b[j] = make_float4(r0.z, r1.x, r1.z, r1.w);
+        s_c[j] = r2.x;
+        if (s_id) s_id[j] = id;
+    }
+}
+
+// alpha of a staged record at pixel centre (fx, fy), or 0 where the splat does
+// not count (q > q_max or o*exp(-q/2) < alpha_min). Blend and score both call
+// this, so they take the same decisions on the same FP32 values.
+__device__ inline float eval_alpha(const float4& a, const float4& b, float fx, float fy, float qmax, float amin,
+                                   float amax) {
+    const float dx = a.x - fx, dy = a.y - fy;
+    const float q = b.x * dx * dx + 2.f * a.w * dx * dy + b.y * dy * dy;
+    const float al0 = a.z * __expf(-0.5f * q);
+    return (q <= qmax && al0 >= amin) ? fminf(amax, al0) : 0.f;
+}
+
+__device__ inline float wave_sum(float x) {
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) x += __shfl_xor(x, m, 64);
+    return x;
+}
+
+template <int TW, int TH>
+__global__ __launch_bounds__(TW * TH) void k_blend(int64_t N, int32_t W, int32_t H, int32_t tiles_x,
+                                                   int32_t tiles_per_view, potr_config cfg,
+                                                   const potr_proj* __restrict__ proj,
+                                                   const uint32_t* __restrict__ ids,
+                                                   const int32_t* __restrict__ ranges, float* __restrict__ image,
+                                                   float* __restrict__ p_final, float* __restrict__ t_final,
+                                                   int32_t* __restrict__ n_walk) {
+    constexpr int NT = TW * TH;
+    __shared__ float4 s_a[kMaxBatch];
+    __shared__ float4 s_b[kMaxBatch];
+    __shared__ float s_c[kMaxBatch];
+    const int tile = blockIdx.x, v = blockIdx.y;
+    const int px = (tile % tiles_x) * TW + (int)(threadIdx.x % TW);
+    const int py = (tile / tiles_x) * TH + (int)(threadIdx.x / TW);
+    const bool inside = px < W && py < H;
+    const float fx = (float)px + 0.5f, fy = (float)py + 0.5f;
+    const int64_t tg = (int64_t)v * tiles_per_view + tile;
+    const int beg = ranges[2 * tg], end = ranges[2 * tg + 1];
+    const potr_proj* pv = proj + (int64_t)v * N;
+    const int B = cfg.lds_batch;
+    const float qmax = cfg.q_max, amin = cfg.alpha_min, amax = cfg.alpha_max, tmin = cfg.t_min;
+
+    float T = 1.f, cr = 0.f, cg = 0.f, cb = 0.f;
+    bool done = !inside;
+    int walk = 0;
+    for (int base = beg; base < end; base += B) {
+        if (__syncthreads_count(!done) == 0) break;
+        const int cnt = min(B, end - base);
+        stage_batch<NT>(pv, ids, base, cnt, s_a, s_b, s_c, nullptr);
+        __syncthreads();
+        if (!done) {
+            for (int j = 0; j < cnt; ++j) {
+                const float4 a = s_a[j];
+                const float4 b = s_b[j];
+                const float al = eval_alpha(a, b, fx, fy, qmax, amin, amax);
+                if (al == 0.f) continue;
+                const float Tn = T * (1.f - al);
+                if (Tn < tmin) {
+                    done = true;
+                    walk = base - beg + j;
+                    break;
+                }
+                const float w = T * al;
+                cr += w * b.z;
+                cg += w * b.w;
+                cb += w * s_c[j];
+                T = Tn;
+            }
+        }
+    }
+    if (!inside) return;
+    if (!done) walk = end - beg;
+    const int64_t pix = ((int64_t)v * H + py) * W + px;
+    image[3 * pix] = cr + T * cfg.bg[0];
+    image[3 * pix + 1] = cg + T * cfg.bg[1];
+    image[3 * pix + 2] = cb + T * cfg.bg[2];
+    if (p_final) {
+        p_final[3 * pix] = cr;
+        p_final[3 * pix + 1] = cg;
+        p_final[3 * pix + 2] = cb;
+    }
+    if (t_final) t_final[pix] = T;
+    if (n_walk) n_walk[pix] = walk;
+}
+
+template <int TW, int TH>
+__global__ __launch_bounds__(TW * TH) void k_score(int64_t N, int32_t W, int32_t H, int32_t tiles_x,
+                                                   int32_t tiles_per_view, potr_config cfg,
+                                                   const potr_proj* __restrict__ proj,
+                                                   const uint32_t* __restrict__ ids,
+                                                   const int32_t* __restrict__ ranges,
+                                                   const float* __restrict__ p_final,
+                                                   const float* __restrict__ t_final,
+                                                   const int32_t* __restrict__ n_walk,
+                                                   const float* __restrict__ target, float* __restrict__ scores,
+                                                   float* __restrict__ scores_se, float* __restrict__ importance) {
+    constexpr int NT = TW * TH;
+    constexpr int NW = (NT + 63) / 64;
+    __shared__ float4 s_a[kMaxBatch];
+    __shared__ float4 s_b[kMaxBatch];
+    __shared__ float s_c[kMaxBatch];
+    __shared__ uint32_t s_id[kMaxBatch];
+    __shared__ float s_part[3][NW][kMaxBatch];
+    __shared__ int s_wmax;
+    const int tile = blockIdx.x, v = blockIdx.y;
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const int px = (tile % tiles_x) * TW + (int)(threadIdx.x % TW);
+    const int py = (tile / tiles_x) * TH + (int)(threadIdx.x / TW);
+    const bool inside = px < W && py < H;
+    const float fx = (float)px + 0.5f, fy = (float)py + 0.5f;
+    const int64_t tg = (int64_t)v * tiles_per_view + tile;
+    const int beg = ranges[2 * tg];
+    const potr_proj* pv = proj + (int64_t)v * N;
+    const int B = cfg.lds_batch;
+    const float qmax = cfg.q_max, amin = cfg.alpha_min, amax = cfg.alpha_max;
+    const bool want_l1 = scores != nullptr, want_se = scores_se != nullptr, want_im = importance != nullptr;
+
+    int walk = 0;
+    float PKr = 0.f, PKg = 0.f, PKb = 0.f, TF = 0.f, er = 0.f, eg = 0.f, eb = 0.f;
+    const int64_t pix = ((int64_t)v * H + py) * W + px;
+    if (inside) {
+        walk = n_walk[pix];
+        PKr = p_final[3 * pix];
+        PKg = p_final[3 * pix + 1];
+        PKb = p_final[3 * pix + 2];
+        TF = t_final[pix];
+        if (want_se) {   // c - c_t
+            er = PKr + TF * cfg.bg[0] - target[3 * pix];
+            eg = PKg + TF * cfg.bg[1] - target[3 * pix + 1];
+            eb = PKb + TF * cfg.bg[2] - target[3 * pix + 2];
+        }
+    }
+    const float Br = TF * cfg.bg[0], Bg = TF * cfg.bg[1], Bb = TF * cfg.bg[2];
+    if (threadIdx.x == 0) s_wmax = 0;
+    __syncthreads();
+    atomicMax(&s_wmax, walk);
+    __syncthreads();
+    const int wmax = s_wmax;
+
+    float T = 1.f, Pr = 0.f, Pg = 0.f, Pb = 0.f;
+    for (int base = 0; base < wmax; base += B) {
+        const int cnt = min(B, wmax - base);
+        stage_batch<NT>(pv, ids, beg + base, cnt, s_a, s_b, s_c, s_id);
+        __syncthreads();
+        for (int j = 0; j < cnt; ++j) {
+            float l1 = 0.f, se = 0.f, im = 0.f;
+            if (base + j < walk) {
+                const float4 a = s_a[j];
+                const float4 b = s_b[j];
+                const float al = eval_alpha(a, b, fx, fy, qmax, amin, amax);
+                if (al != 0.f) {
+                    const float w = T * al;
+                    const float cr = b.z, cg = b.w, cbl = s_c[j];
+                    Pr += w * cr;
+                    Pg += w * cg;
+                    Pb += w * cbl;
+                    const float k = al / (1.f - al);
+                    const float dr = -w * cr + k * (PKr - Pr + Br);
+                    const float dg = -w * cg + k * (PKg - Pg + Bg);
+                    const float db = -w * cbl + k * (PKb - Pb + Bb);
+                    l1 = fabsf(dr) + fabsf(dg) + fabsf(db);
+                    se = dr * dr + dg * dg + db * db + 2.f * (dr * er + dg * eg + db * eb);
+                    im = w;
+                    T *= (1.f - al);
+                }
+            }
+            if (want_l1) {
+                const float s = __ballot(l1 != 0.f) ? wave_sum(l1) : 0.f;
+                if (lane == 0) s_part[0][wid][j] = s;
+            }
+            if (want_se) {
+                const float s = __ballot(se != 0.f) ? wave_sum(se) : 0.f;
+                if (lane == 0) s_part[1][wid][j] = s;
+            }
+            if (want_im) {
+                const float s = __ballot(im != 0.f) ? wave_sum(im) : 0.f;
+                if (lane == 0) s_part[2][wid][j] = s;
+            }
+        }
+        __syncthreads();
+        for (int j = threadIdx.x; j < cnt; j += NT) {
+            const uint32_t id = s_id[j];
+            if (want_l1) {
+                float t = 0.f;
+#pragma unroll
+                for (int w = 0; w < NW; ++w) t += s_part[0][w][j];
+                if (t != 0.f) unsafeAtomicAdd(scores + id, t);
+            }
+            if (want_se) {
+                float t = 0.f;
+#pragma unroll
+                for (int w = 0; w < NW; ++w) t += s_part[1][w][j];
+                if (t != 0.f) unsafeAtomicAdd(scores_se + id, t);
+            }
+            if (want_im) {
+                float t = 0.f;
+#pragma unroll
+                for (int w = 0; w < NW; ++w) t += s_part[2][w][j];
+                if (t != 0.f) unsafeAtomicAdd(importance + id, t);
+            }
+        }
+        __syncthreads();
+    }
+}
+
+template <int TW, int TH>
+potr_status blend_shape(int64_t N, int32_t V, const potr_camera& c, const potr_config& cfg, const potr_proj* proj,
+                        const uint32_t* ids, const int32_t* ranges, float* image, float* p_final, float* t_final,
+                        int32_t* n_walk, hipStream_t s) {
+    const int txs = tiles_x(c, cfg), tpv = txs * tiles_y(c, cfg);
+    hipLaunchKernelGGL((k_blend<TW, TH>), dim3(tpv, V), dim3(TW * TH), 0, s, N, c.width, c.height, txs, tpv, cfg,
+                       proj, ids, ranges, image, p_final, t_final, n_walk);
+    return check_launch("k_blend");
+}
+
+template <int TW, int TH>
+potr_status score_shape(int64_t N, int32_t V, const potr_camera& c, const potr_config& cfg, const potr_proj* proj,
+                        const uint32_t* ids, const int32_t* ranges, const float* p_final, const float* t_final,
+                        const int32_t* n_walk, const float* target, float* scores, float* scores_se,
+                        float* importance, hipStream_t s) {
+    const int txs = tiles_x(c, cfg), tpv = txs * tiles_y(c, cfg);
+    hipLaunchKernelGGL((k_score<TW, TH>), dim3(tpv, V), dim3(TW * TH), 0, s, N, c.width, c.height, txs, tpv, cfg,
+                       proj, ids, ranges, p_final, t_final, n_walk, target, scores, scores_se, importance);
+    return check_launch("k_score");
+}
+
+}  // namespace
+
+potr_status launch_blend(int64_t N, int32_t V, const potr_camera& c, const potr_config& cfg, const potr_proj* proj,
+                         const uint32_t* ids, const int32_t* ranges, float* image, float* p_final, float* t_final,
+                         int32_t* n_walk, hipStream_t s) {
+    if (cfg.tile_w == 16 && cfg.tile_h == 16)
+        return blend_shape<16, 16>(N, V, c, cfg, proj, ids, ranges, image, p_final, t_final, n_walk, s);
+    if (cfg.tile_w == 8 && cfg.tile_h == 8)
+        return blend_shape<8, 8>(N, V, c, cfg, proj, ids, ranges, image, p_final, t_final, n_walk, s);
+    if (cfg.tile_w == 32 && cfg.tile_h == 8)
+        return blend_shape<32, 8>(N, V, c, cfg, proj, ids, ranges, image, p_final, t_final, n_walk, s);
+    return fail(POTR_EUNSUPPORTED, "tile %dx%d not built", cfg.tile_w, cfg.tile_h);
+}
+
+potr_status launch_score(int64_t N, int32_t V, const potr_camera& c, const potr_config& cfg, const potr_proj* proj,
+                         const uint32_t* ids, const int32_t* ranges, const float* p_final, const float* t_final,
+                         const int32_t* n_walk, const float* target, float* scores, float* scores_se,
+                         float* importance, hipStream_t s) {
+    if (cfg.tile_w == 16 && cfg.tile_h == 16)
+        return score_shape<16, 16>(N, V, c, cfg, proj, ids, ranges, p_final, t_final, n_walk, target, scores,
+                                   scores_se, importance, s);
+    if (cfg.tile_w == 8 && cfg.tile_h == 8)
+        return score_shape<8, 8>(N, V, c, cfg, proj, ids, ranges, p_final, t_final, n_walk, target, scores,
+                                 scores_se, importance, s);
+    if (cfg.tile_w == 32 && cfg.tile_h == 8)
+        return score_shape<32, 8>(N, V, c, cfg, proj, ids, ranges, p_final, t_final, n_walk, target, scores,
+                                  scores_se, importance, s);
+    return fail(POTR_EUNSUPPORTED, "tile %dx%d not built", cfg.tile_w, cfg.tile_h);
+}
+
+}  // namespace potr

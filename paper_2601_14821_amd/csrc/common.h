@@ -1,0 +1,74 @@
+// Internal declarations shared by the HIP translation units of libpotr.so.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "potr.h"
+
+namespace potr {
+
+// Views whose cameras travel by value in one launch's kernel arguments.
+constexpr int kViewsPerLaunch = 32;
+
+struct CamBatch {
+    potr_camera c[kViewsPerLaunch];
+};
+
+// Radix sort geometry: 256 threads x 16 items per block.
+constexpr int kRadixThreads = 256;
+constexpr int kRadixItems = 16;
+constexpr int kRadixTile = kRadixThreads * kRadixItems;
+
+// Device-wide scan geometry.
+constexpr int kScanThreads = 256;
+constexpr int kScanItems = 16;
+constexpr int kScanTile = kScanThreads * kScanItems;
+
+inline int tiles_x(const potr_camera& c, const potr_config& g) { return (c.width + g.tile_w - 1) / g.tile_w; }
+inline int tiles_y(const potr_camera& c, const potr_config& g) { return (c.height + g.tile_h - 1) / g.tile_h; }
+
+inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+inline size_t align_up(size_t x, size_t a = 256) { return (x + a - 1) / a * a; }
+
+// Thread-local error text behind potr_last_error().
+potr_status fail(potr_status st, const char* fmt, ...);
+// Turns the last launch error on this thread into POTR_EHIP.
+potr_status check_launch(const char* what);
+
+// ---- launchers (defined in the .hip files) ----
+potr_status launch_project(int64_t N, int32_t V, const potr_camera* cams, const potr_config& cfg,
+                           const float* means, const float* scales, const float* quats, const float* opac,
+                           const float* sh, potr_proj* proj, int32_t* tiles_touched, hipStream_t s);
+
+size_t bin_workspace_bytes(int64_t N, int32_t V);
+potr_status launch_bin(int64_t N, int32_t V, const potr_camera& cam0, const potr_config& cfg,
+                       const potr_proj* proj, const int32_t* tiles_touched, void* ws, uint32_t* order,
+                       uint64_t* pairs, int64_t capacity, int64_t* n_pairs, hipStream_t s);
+
+size_t sort_workspace_bytes(int64_t capacity, int32_t V, int32_t tiles_per_view);
+potr_status launch_sort(int64_t N, int32_t V, int32_t tiles_per_view, const int64_t* n_pairs, int64_t n_max,
+                        uint64_t* pairs, const uint32_t* order, void* ws, uint32_t* sorted_ids,
+                        int32_t* tile_ranges, hipStream_t s);
+
+potr_status launch_blend(int64_t N, int32_t V, const potr_camera& cam0, const potr_config& cfg,
+                         const potr_proj* proj, const uint32_t* sorted_ids, const int32_t* tile_ranges,
+                         float* image, float* p_final, float* t_final, int32_t* n_walk, hipStream_t s);
+
+potr_status launch_score(int64_t N, int32_t V, const potr_camera& cam0, const potr_config& cfg,
+                         const potr_proj* proj, const uint32_t* sorted_ids, const int32_t* tile_ranges,
+                         const float* p_final, const float* t_final, const int32_t* n_walk,
+                         const float* target, float* scores, float* scores_se, float* importance,
+                         hipStream_t s);
+
+// ---- device-wide helpers (scan.hip) ----
+// Exclusive scan of n int32 counts into int64 offsets; `total` (device, may be
+// null) receives the sum. `tmp` needs scan_tmp_bytes(n).
+size_t scan_tmp_bytes(int64_t n);
+potr_status scan_i32_to_i64(const int32_t* in, int64_t* out, int64_t n, int64_t* total, void* tmp,
+                            hipStream_t s);
+// Exclusive scan of n uint32 counts in place-capable form (out may alias in).
+potr_status scan_u32(const uint32_t* in, uint32_t* out, int64_t n, void* tmp, hipStream_t s);
+
+}  // namespace potr

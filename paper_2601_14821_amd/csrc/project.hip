@@ -1,0 +1,194 @@
+// Projection of 3D Gaussians to screen-space records (paper Sec. 3).
+//
+// One thread per splat; the thread reads the splat's 236 bytes once and loops
+// over the views of the launch, so a batch of views costs one parameter read.
+// All arithmetic is FP64: CDNA's FP64 vector rate is half its FP32 rate and this
+// kernel is bound by HBM (236 B in, 52 B out per splat-view for ~300 flops), so
+// FP64 is free here and keeps every stored FP32 value correctly rounded from a
+// near-exact result. The depth key is the one exception: a fixed FP32 FMA chain.
+#include "common.h"
+
+namespace potr {
+namespace {
+
+// Real spherical harmonics with the Condon-Shortley phase in Cartesian form,
+// Y_{l,m}(x, y, z) for a unit vector, stored at index l(l+1)+m. The constants are
+// K_l^m times the Legendre polynomial coefficients:
+//   l=0: 1/(2 sqrt(pi))
+//   l=1: sqrt(3/(4 pi))
+//   l=2: sqrt(15/pi)/2, sqrt(5/pi)/4, sqrt(15/pi)/4
+//   l=3: sqrt(35/(2 pi))/4, sqrt(105/pi)/2, sqrt(21/(2 pi))/4, sqrt(7/pi)/4, sqrt(105/pi)/4
+__device__ inline void sh_basis_d3(double x, double y, double z, int degree, double* Y) {
+    Y[0] = 0.28209479177387814;
+    if (degree < 1) return;
+    const double c1 = 0.4886025119029199;
+    Y[1] = -c1 * y;
+    Y[2] = c1 * z;
+    Y[3] = -c1 * x;
+    if (degree < 2) return;
+    const double xx = x * x, yy = y * y, zz = z * z;
+    Y[4] = 1.0925484305920792 * x * y;
+    Y[5] = -1.0925484305920792 * y * z;
+    Y[6] = 0.31539156525252005 * (2.0 * zz - xx - yy);
+    Y[7] = -1.0925484305920792 * x * z;
+    Y[8] = 0.5462742152960396 * (xx - yy);
+    if (degree < 3) return;
+    Y[9] = -0.5900435899266435 * y * (3.0 * xx - yy);
+    Y[10] = 2.890611442640554 * x * y * z;
+    Y[11] = -0.4570457994644658 * y * (4.0 * zz - xx - yy);
+    Y[12] = 0.3731763325901154 * z * (2.0 * zz - 3.0 * xx - 3.0 * yy);
+    Y[13] = -0.4570457994644658 * x * (4.0 * zz - xx - yy);
+    Y[14] = 1.445305721320277 * z * (xx - yy);
+    Y[15] = -0.5900435899266435 * x * (xx - 3.0 * yy);
+}
+
+__global__ __launch_bounds__(256) void k_project(int64_t N, int32_t v0, int32_t nv, CamBatch cams,
+                                                 potr_config cfg, const float* __restrict__ means,
+                                                 const float* __restrict__ scales, const float* __restrict__ quats,
+                                                 const float* __restrict__ opac, const float* __restrict__ sh,
+                                                 potr_proj* __restrict__ proj, int32_t* __restrict__ tiles_touched) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+
+    const float mx = means[3 * i], my = means[3 * i + 1], mz = means[3 * i + 2];
+    const double o = opac[i];
+    const float q0 = quats[4 * i], q1 = quats[4 * i + 1], q2 = quats[4 * i + 2], q3 = quats[4 * i + 3];
+    const double qn2 = (double)q0 * q0 + (double)q1 * q1 + (double)q2 * q2 + (double)q3 * q3;
+    const bool valid = (o >= (double)cfg.alpha_min) && (qn2 > 0.0);
+
+    // 3D covariance Sigma = R(q) diag(s^2) R(q)^T (view independent)
+    double S00 = 0, S01 = 0, S02 = 0, S11 = 0, S12 = 0, S22 = 0;
+    if (valid) {
+        const double inv = 1.0 / sqrt(qn2);
+        const double w = q0 * inv, x = q1 * inv, y = q2 * inv, z = q3 * inv;
+        const double M[9] = {1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y),
+                             2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x),
+                             2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)};
+        const double s0 = (double)scales[3 * i] * scales[3 * i];
+        const double s1 = (double)scales[3 * i + 1] * scales[3 * i + 1];
+        const double s2 = (double)scales[3 * i + 2] * scales[3 * i + 2];
+        S00 = M[0] * M[0] * s0 + M[1] * M[1] * s1 + M[2] * M[2] * s2;
+        S01 = M[0] * M[3] * s0 + M[1] * M[4] * s1 + M[2] * M[5] * s2;
+        S02 = M[0] * M[6] * s0 + M[1] * M[7] * s1 + M[2] * M[8] * s2;
+        S11 = M[3] * M[3] * s0 + M[4] * M[4] * s1 + M[5] * M[5] * s2;
+        S12 = M[3] * M[6] * s0 + M[4] * M[7] * s1 + M[5] * M[8] * s2;
+        S22 = M[6] * M[6] * s0 + M[7] * M[7] * s1 + M[8] * M[8] * s2;
+    }
+    const int nsh = (cfg.sh_degree + 1) * (cfg.sh_degree + 1);
+    const float* shp = sh + 48 * i;
+
+    for (int vv = 0; vv < nv; ++vv) {
+        const potr_camera& c = cams.c[vv];
+        const int64_t out = (int64_t)(v0 + vv) * N + i;
+        potr_proj rec;
+        rec.mean2d[0] = rec.mean2d[1] = 0.f;
+        rec.conic[0] = rec.conic[1] = rec.conic[2] = 0.f;
+        rec.opacity = 0.f;
+        rec.rgb[0] = rec.rgb[1] = rec.rgb[2] = 0.f;
+        rec.rect[0] = rec.rect[1] = rec.rect[2] = rec.rect[3] = 0;
+        int32_t ntiles = 0;
+
+        // depth key: t_z + R20 x + R21 y + R22 z, one rounding per fused step
+        float z32 = c.t[2];
+        z32 = __builtin_fmaf(c.R[6], mx, z32);
+        z32 = __builtin_fmaf(c.R[7], my, z32);
+        z32 = __builtin_fmaf(c.R[8], mz, z32);
+        rec.depth = z32;
+
+        bool ok = valid && (z32 > cfg.near_z);
+        if (ok) {
+            const double R0 = c.R[0], R1 = c.R[1], R2 = c.R[2], R3 = c.R[3], R4 = c.R[4], R5 = c.R[5],
+                         R6 = c.R[6], R7 = c.R[7], R8 = c.R[8];
+            const double px = R0 * mx + R1 * my + R2 * mz + (double)c.t[0];
+            const double py = R3 * mx + R4 * my + R5 * mz + (double)c.t[1];
+            const double pz = R6 * mx + R7 * my + R8 * mz + (double)c.t[2];
+            const double fx = c.fx, fy = c.fy;
+            const double limx = (double)cfg.jclamp * 0.5 * c.width / fx;
+            const double limy = (double)cfg.jclamp * 0.5 * c.height / fy;
+            const double tx = fmin(limx, fmax(-limx, px / pz));
+            const double ty = fmin(limy, fmax(-limy, py / pz));
+            // T = J W (2x3); J = [[fx/z, 0, -fx tx/z], [0, fy/z, -fy ty/z]]
+            const double j00 = fx / pz, j02 = -fx * tx / pz, j11 = fy / pz, j12 = -fy * ty / pz;
+            const double T00 = j00 * R0 + j02 * R6, T01 = j00 * R1 + j02 * R7, T02 = j00 * R2 + j02 * R8;
+            const double T10 = j11 * R3 + j12 * R6, T11 = j11 * R4 + j12 * R7, T12 = j11 * R5 + j12 * R8;
+            // cov2d = T Sigma T^T
+            const double a0 = T00 * S00 + T01 * S01 + T02 * S02;
+            const double a1 = T00 * S01 + T01 * S11 + T02 * S12;
+            const double a2 = T00 * S02 + T01 * S12 + T02 * S22;
+            const double b0 = T10 * S00 + T11 * S01 + T12 * S02;
+            const double b1 = T10 * S01 + T11 * S11 + T12 * S12;
+            const double b2 = T10 * S02 + T11 * S12 + T12 * S22;
+            const double cxx = a0 * T00 + a1 * T01 + a2 * T02 + (double)cfg.eps2d;
+            const double cxy = a0 * T10 + a1 * T11 + a2 * T12;
+            const double cyy = b0 * T10 + b1 * T11 + b2 * T12 + (double)cfg.eps2d;
+            const double det = cxx * cyy - cxy * cxy;
+            const double u = fx * px / pz + (double)c.cx;
+            const double v = fy * py / pz + (double)c.cy;
+            const double t_cut = fmin((double)cfg.q_max, 2.0 * log(o / (double)cfg.alpha_min));
+            const double rx = sqrt(t_cut * cxx) * (1.0 + 1.0 / 1024.0) + 1.0 / 64.0;
+            const double ry = sqrt(t_cut * cyy) * (1.0 + 1.0 / 1024.0) + 1.0 / 64.0;
+            ok = (det > 0.0) && isfinite(u) && isfinite(v) && isfinite(rx) && isfinite(ry);
+            if (ok) {
+                rec.mean2d[0] = (float)u;
+                rec.mean2d[1] = (float)v;
+                rec.conic[0] = (float)(cyy / det);
+                rec.conic[1] = (float)(-cxy / det);
+                rec.conic[2] = (float)(cxx / det);
+                rec.opacity = (float)o;
+
+                // colour along the camera -> centre direction
+                const double ex = -(R0 * c.t[0] + R3 * c.t[1] + R6 * c.t[2]);
+                const double ey = -(R1 * c.t[0] + R4 * c.t[1] + R7 * c.t[2]);
+                const double ez = -(R2 * c.t[0] + R5 * c.t[1] + R8 * c.t[2]);
+                double dx = mx - ex, dy = my - ey, dz = mz - ez;
+                const double dn = 1.0 / sqrt(dx * dx + dy * dy + dz * dz);
+                dx *= dn; dy *= dn; dz *= dn;
+                double Y[16];
+                sh_basis_d3(dx, dy, dz, cfg.sh_degree, Y);
+                double cr = 0.5, cg = 0.5, cb = 0.5;
+                for (int k = 0; k < nsh; ++k) {
+                    cr += (double)shp[3 * k] * Y[k];
+                    cg += (double)shp[3 * k + 1] * Y[k];
+                    cb += (double)shp[3 * k + 2] * Y[k];
+                }
+                rec.rgb[0] = (float)fmax(0.0, cr);
+                rec.rgb[1] = (float)fmax(0.0, cg);
+                rec.rgb[2] = (float)fmax(0.0, cb);
+
+                const double ilo = fmax(ceil(u - rx - 0.5), 0.0), ihi = fmin(floor(u + rx - 0.5), c.width - 1.0);
+                const double jlo = fmax(ceil(v - ry - 0.5), 0.0), jhi = fmin(floor(v + ry - 0.5), c.height - 1.0);
+                if (ilo <= ihi && jlo <= jhi) {
+                    const int x0 = (int)ilo / cfg.tile_w, x1 = (int)ihi / cfg.tile_w + 1;
+                    const int y0 = (int)jlo / cfg.tile_h, y1 = (int)jhi / cfg.tile_h + 1;
+                    rec.rect[0] = (int16_t)x0; rec.rect[1] = (int16_t)y0;
+                    rec.rect[2] = (int16_t)x1; rec.rect[3] = (int16_t)y1;
+                    ntiles = (x1 - x0) * (y1 - y0);
+                }
+            }
+        }
+        proj[out] = rec;
+        tiles_touched[out] = ntiles;
+    }
+}
+
+}  // namespace
+
+potr_status launch_project(int64_t N, int32_t V, const potr_camera* cams, const potr_config& cfg,
+                           const float* means, const float* scales, const float* quats, const float* opac,
+                           const float* sh, potr_proj* proj, int32_t* tiles_touched, hipStream_t s) {
+    if (N == 0) return POTR_OK;
+    const dim3 grid((unsigned)ceil_div(N, 256));
+    for (int32_t v0 = 0; v0 < V; v0 += kViewsPerLaunch) {
+        const int32_t nv = V - v0 < kViewsPerLaunch ? V - v0 : kViewsPerLaunch;
+        CamBatch cb;
+        for (int k = 0; k < nv; ++k) cb.c[k] = cams[v0 + k];
+        for (int k = nv; k < kViewsPerLaunch; ++k) cb.c[k] = cams[v0];
+        hipLaunchKernelGGL(k_project, grid, dim3(256), 0, s, N, v0, nv, cb, cfg, means, scales, quats, opac, sh,
+                           proj, tiles_touched);
+        potr_status st = check_launch("k_project");
+        if (st != POTR_OK) return st;
+    }
+    return POTR_OK;
+}
+
+}  // namespace potr

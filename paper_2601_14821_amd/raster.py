@@ -1,0 +1,163 @@
+"""Plain per-view pipeline over libpotr.so: project -> bin -> sort -> blend -> score.
+
+PyTorch supplies device memory and the stream; every step of the pipeline runs
+in the library's HIP kernels. The only host synchronisation is the read-back of
+the pair count after binning (to size the sort); a caller that reuses the
+Rasterizer keeps its buffers, so repeated calls allocate nothing new.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import dataclasses
+
+import torch
+
+from . import _lib as L
+
+
+@dataclasses.dataclass
+class DeviceScene:
+    means: torch.Tensor
+    scales: torch.Tensor
+    quats: torch.Tensor
+    opacities: torch.Tensor
+    sh: torch.Tensor
+
+    @property
+    def n(self) -> int:
+        return int(self.means.shape[0])
+
+
+def to_device(scene, device="cuda") -> DeviceScene:
+    f = lambda a: torch.as_tensor(a, dtype=torch.float32).contiguous().to(device)
+    return DeviceScene(f(scene.means), f(scene.scales), f(scene.quats), f(scene.opacities), f(scene.sh))
+
+
+@dataclasses.dataclass
+class ViewBatch:
+    """Device results for one batch of views (all views share one size)."""
+    V: int
+    N: int
+    proj: torch.Tensor            # uint8 [V*N*48]
+    tiles_touched: torch.Tensor   # int32 [V*N]
+    order: torch.Tensor | None = None
+    n_pairs: int = 0
+    sorted_ids: torch.Tensor | None = None
+    tile_ranges: torch.Tensor | None = None
+    image: torch.Tensor | None = None
+    p_final: torch.Tensor | None = None
+    t_final: torch.Tensor | None = None
+    n_walk: torch.Tensor | None = None
+
+
+class Rasterizer:
+    def __init__(self, settings, device="cuda"):
+        self.s = settings
+        self.cfg = L.make_config(settings)
+        self.device = torch.device(device)
+        self._bufs: dict[str, torch.Tensor] = {}
+        self.capacity = 0
+        L.lib()
+
+    # -------------------------------------------------------------- buffers
+    def _buf(self, name: str, nbytes: int) -> torch.Tensor:
+        b = self._bufs.get(name)
+        nbytes = max(int(nbytes), 256)
+        if b is None or b.numel() < nbytes:
+            b = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+            self._bufs[name] = b
+        return b
+
+    def _i32(self, name: str, n: int) -> torch.Tensor:
+        return self._buf(name, 4 * n)[: 4 * max(n, 1)].view(torch.int32)
+
+    def _f32(self, name: str, n: int) -> torch.Tensor:
+        return self._buf(name, 4 * n)[: 4 * max(n, 1)].view(torch.float32)
+
+    def tiles(self, cam):
+        return self.s.tiles(cam)
+
+    # -------------------------------------------------------------- stages
+    def project(self, ds: DeviceScene, cams, tag: str = "") -> ViewBatch:
+        N, V = ds.n, len(cams)
+        proj = self._buf("proj" + tag, L.PROJ_BYTES * V * N)[: L.PROJ_BYTES * max(V * N, 1)]
+        tt = self._i32("tt" + tag, V * N)
+        L.call("potr_project", N, V, L.make_cameras(cams), C.byref(self.cfg), L.ptr(ds.means), L.ptr(ds.scales),
+               L.ptr(ds.quats), L.ptr(ds.opacities), L.ptr(ds.sh), L.ptr(proj), L.ptr(tt), L.stream_handle())
+        return ViewBatch(V=V, N=N, proj=proj, tiles_touched=tt)
+
+    def bin(self, vb: ViewBatch, cams) -> ViewBatch:
+        N, V = vb.N, vb.V
+        order = self._i32("order", V * N)
+        n_pairs = self._buf("n_pairs", 8)[:8].view(torch.int64)
+        ws_bytes = L.bin_workspace_size(N, V)
+        ws = self._buf("bin_ws", ws_bytes)
+        cam_arr = L.make_cameras(cams)
+        for _ in range(2):
+            pairs = self._buf("pairs", 8 * max(self.capacity, 1))
+            L.call("potr_bin", N, V, cam_arr, C.byref(self.cfg), L.ptr(vb.proj), L.ptr(vb.tiles_touched),
+                   L.ptr(ws), ws.numel(), L.ptr(order), L.ptr(pairs), self.capacity, L.ptr(n_pairs),
+                   L.stream_handle())
+            n = int(n_pairs.item())
+            if n <= self.capacity:
+                break
+            self.capacity = int(n * 1.25) + 4096
+        vb.order, vb.n_pairs = order, n
+        vb._pairs = pairs
+        vb._n_pairs_dev = n_pairs
+        return vb
+
+    def sort(self, vb: ViewBatch, cams) -> ViewBatch:
+        tx, ty = self.tiles(cams[0])
+        n = vb.n_pairs
+        ws_bytes = L.sort_workspace_size(n, vb.V, tx * ty)
+        ws = self._buf("sort_ws", ws_bytes)
+        ids = self._i32("sorted_ids", n)
+        ranges = self._i32("ranges", 2 * vb.V * tx * ty)[: 2 * vb.V * tx * ty]
+        L.call("potr_sort", vb.N, vb.V, L.make_cameras(cams), C.byref(self.cfg), L.ptr(vb._n_pairs_dev), n,
+               L.ptr(vb._pairs), L.ptr(vb.order), L.ptr(ws), ws.numel(), L.ptr(ids), L.ptr(ranges),
+               L.stream_handle())
+        vb.sorted_ids, vb.tile_ranges = ids, ranges
+        return vb
+
+    def blend(self, vb: ViewBatch, cams, keep: bool = True) -> ViewBatch:
+        V, H, W = vb.V, cams[0].height, cams[0].width
+        P = V * H * W
+        image = self._f32("image", 3 * P)[: 3 * P].view(V, H, W, 3)
+        pf = self._f32("p_final", 3 * P)[: 3 * P].view(V, H, W, 3)
+        tf = self._f32("t_final", P)[:P].view(V, H, W)
+        nw = self._i32("n_walk", P)[:P].view(V, H, W)
+        L.call("potr_blend", vb.N, V, L.make_cameras(cams), C.byref(self.cfg), L.ptr(vb.proj), L.ptr(vb.sorted_ids),
+               L.ptr(vb.tile_ranges), L.ptr(image), L.ptr(pf), L.ptr(tf), L.ptr(nw), L.stream_handle())
+        vb.image, vb.p_final, vb.t_final, vb.n_walk = image, pf, tf, nw
+        return vb
+
+    def score(self, vb: ViewBatch, cams, scores=None, scores_se=None, importance=None, target=None) -> None:
+        L.call("potr_score", vb.N, vb.V, L.make_cameras(cams), C.byref(self.cfg), L.ptr(vb.proj),
+               L.ptr(vb.sorted_ids), L.ptr(vb.tile_ranges), L.ptr(vb.p_final), L.ptr(vb.t_final),
+               L.ptr(vb.n_walk), L.ptr(target), L.ptr(scores), L.ptr(scores_se), L.ptr(importance),
+               L.stream_handle())
+
+    # -------------------------------------------------------------- whole path
+    def render_views(self, ds: DeviceScene, cams) -> ViewBatch:
+        vb = self.project(ds, cams)
+        self.bin(vb, cams)
+        self.sort(vb, cams)
+        self.blend(vb, cams)
+        return vb
+
+    def score_views(self, ds: DeviceScene, cams, views_per_batch: int = 8, scores=None, importance=None,
+                    scores_se=None, targets=None, keep_images: bool = False):
+        """Removal scores accumulated over all views. Returns (scores, importance, images?)."""
+        N = ds.n
+        if scores is None:
+            scores = torch.zeros(N, dtype=torch.float32, device=self.device)
+        images = []
+        for v0 in range(0, len(cams), views_per_batch):
+            cb = cams[v0:v0 + views_per_batch]
+            vb = self.render_views(ds, cb)
+            tgt = None if targets is None else targets[v0:v0 + len(cb)].contiguous()
+            self.score(vb, cb, scores=scores, scores_se=scores_se, importance=importance, target=tgt)
+            if keep_images:
+                images.append(vb.image.clone())
+        return scores, importance, (torch.cat(images) if keep_images else None)

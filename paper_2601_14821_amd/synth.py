@@ -230,3 +230,20 @@ class RenderSettings:
 
     def tiles(self, cam: Camera):
         return (cam.width + self.tile_w - 1) // self.tile_w, (cam.height + self.tile_h - 1) // self.tile_h
+
+
+def random_tile_records(n: int, tiles_x: int, tiles_y: int, seed: int, n_depths: int = 64,
+                        max_w: int = 5, max_h: int = 4, empty_frac: float = 0.1):
+    """Seeded stand-ins for projected splats, for testing tile binning on its own:
+    tile rectangles (x0, y0, x1, y1, half-open; a share of them empty) and
+    positive FP32 depths drawn from `n_depths` values so that equal keys occur."""
+    rng = np.random.default_rng(seed)
+    x0 = rng.integers(0, tiles_x, n)
+    y0 = rng.integers(0, tiles_y, n)
+    x1 = np.minimum(tiles_x, x0 + rng.integers(1, max_w + 1, n))
+    y1 = np.minimum(tiles_y, y0 + rng.integers(1, max_h + 1, n))
+    empty = rng.uniform(size=n) < empty_frac
+    x1 = np.where(empty, x0, x1)
+    rect = np.stack([x0, y0, x1, y1], 1).astype(np.int16)
+    depths = np.float32(rng.uniform(0.5, 8.0, n_depths))[rng.integers(0, n_depths, n)]
+    return rect, depths

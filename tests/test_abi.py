@@ -1,0 +1,110 @@
+"""Host-side checks of libpotr.so: it loads, exports every entry point that
+include/potr.h declares, and rejects bad arguments before launching anything."""
+import ctypes as C
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+from paper_2601_14821_amd import _lib as L
+from paper_2601_14821_amd import synth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "potr.h")
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(potr_[a-z_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(L.LIB_PATH):
+        from paper_2601_14821_amd import build
+        build.build()
+    return L.lib()
+
+
+def test_exports_every_declared_symbol(lib):
+    names = _declared()
+    assert len(names) >= 9
+    out = subprocess.run(["nm", "-D", "--defined-only", L.LIB_PATH], capture_output=True, text=True).stdout
+    exported = {ln.split()[-1] for ln in out.splitlines() if ln.strip()}
+    missing = [n for n in names if n not in exported]
+    assert not missing, missing
+    for n in names:
+        assert n in L.SIGNATURES, f"{n} has no ctypes signature"
+    # nothing but the C ABI is exported from the library's own code
+    own = [s for s in exported if s.startswith("_ZN4potr")]
+    assert not own, own[:5]
+
+
+def test_abi_version(lib):
+    assert lib.potr_abi_version() == 1
+
+
+def test_struct_layouts():
+    assert C.sizeof(L.potr_camera) == 72
+    assert C.sizeof(L.potr_config) == 56
+    assert L.PROJ_DTYPE.itemsize == 48
+
+
+def _cfg(**kw):
+    return L.make_config(synth.RenderSettings(**kw))
+
+
+def _cams(n=1, w=64, h=48):
+    return L.make_cameras(synth.ring_cameras(n, w, h))
+
+
+def _status(name, *args):
+    return getattr(L.lib(), name)(*args)
+
+
+@pytest.mark.parametrize("kw, msg", [
+    (dict(tile_w=12, tile_h=12), "tile"),
+    (dict(lds_batch=100), "lds_batch"),
+    (dict(lds_batch=1024), "lds_batch"),
+    (dict(sh_degree=4), "sh_degree"),
+    (dict(alpha_max=1.0), "alpha"),
+    (dict(t_min=-1.0), "t_min"),
+])
+def test_project_rejects_bad_config(lib, kw, msg):
+    st = _status("potr_project", 10, 1, _cams(), C.byref(_cfg(**kw)), 16, 16, 16, 16, 16, 16, 16, None)
+    assert st == L.POTR_EINVAL
+    assert msg in lib.potr_last_error().decode()
+
+
+def test_rejects_bad_views_and_buffers(lib):
+    cfg = _cfg()
+    assert _status("potr_project", 10, 0, _cams(), C.byref(cfg), 16, 16, 16, 16, 16, 16, 16, None) == L.POTR_EINVAL
+    cams = _cams(2)
+    cams[1].width = 80
+    assert _status("potr_project", 10, 2, cams, C.byref(cfg), 16, 16, 16, 16, 16, 16, 16, None) == L.POTR_EINVAL
+    assert "same size" in lib.potr_last_error().decode()
+    assert _status("potr_project", 10, 1, _cams(), C.byref(cfg), None, 16, 16, 16, 16, 16, 16, None) == L.POTR_EINVAL
+    # misaligned record buffer
+    assert _status("potr_project", 10, 1, _cams(), C.byref(cfg), 16, 16, 16, 16, 16, 20, 16, None) == L.POTR_EINVAL
+    assert _status("potr_score", 10, 1, _cams(), C.byref(cfg), 16, 16, 16, 16, 16, 16, None, None, None, None,
+                   None) == L.POTR_EINVAL
+
+
+def test_workspace_too_small_is_capacity_error(lib):
+    cfg = _cfg()
+    need = L.bin_workspace_size(1000, 2)
+    assert need > 0
+    st = _status("potr_bin", 1000, 2, _cams(2), C.byref(cfg), 16, 16, 16, need - 1, 16, 16, 100, 16, None)
+    assert st == L.POTR_ECAPACITY
+    tx, ty = synth.RenderSettings().tiles(synth.ring_cameras(1, 64, 48)[0])
+    need = L.sort_workspace_size(5000, 2, tx * ty)
+    st = _status("potr_sort", 1000, 2, _cams(2), C.byref(cfg), 16, 5000, 16, 16, 16, need - 1, 16, 16, None)
+    assert st == L.POTR_ECAPACITY
+
+
+def test_workspace_sizes_grow(lib):
+    assert L.bin_workspace_size(10_000, 1) < L.bin_workspace_size(100_000, 1) < L.bin_workspace_size(100_000, 4)
+    assert L.sort_workspace_size(1000, 1, 100) < L.sort_workspace_size(10_000_000, 1, 100)
