@@ -155,10 +155,12 @@ POTR_API potr_status potr_sort(int64_t N, int32_t V, const potr_camera* cams, co
  *   p_final [V,H,W,3] out: P_K = sum_k T_k alpha_k c_k (paper's partial colour after K splats)
  *   t_final [V,H,W]   out: T after the last blended splat
  *   n_walk  [V,H,W]   out int32: list entries visited before the stop (or the list length)
+ *   n_blend [V,H,W]   out int32 or NULL: splats blended (K)
  * ------------------------------------------------------------------------- */
 POTR_API potr_status potr_blend(int64_t N, int32_t V, const potr_camera* cams, const potr_config* cfg,
                        const potr_proj* proj, const uint32_t* sorted_ids, const int32_t* tile_ranges,
-                       float* image, float* p_final, float* t_final, int32_t* n_walk, void* stream);
+                       float* image, float* p_final, float* t_final, int32_t* n_walk, int32_t* n_blend,
+                       void* stream);
 
 /* ---------------------------------------------------------------------------
  * potr_score -- Sec. 4.2: the pruning difference of every blended splat k at every

@@ -133,14 +133,14 @@ potr_status potr_sort(int64_t N, int32_t V, const potr_camera* cams, const potr_
 
 potr_status potr_blend(int64_t N, int32_t V, const potr_camera* cams, const potr_config* cfg,
                        const potr_proj* proj, const uint32_t* sorted_ids, const int32_t* tile_ranges, float* image,
-                       float* p_final, float* t_final, int32_t* n_walk, void* stream) {
+                       float* p_final, float* t_final, int32_t* n_walk, int32_t* n_blend, void* stream) {
     potr_status st = check_cfg(cfg);
     if (st == POTR_OK) st = check_cams(V, cams, cfg);
     if (st != POTR_OK) return st;
     if (!tile_ranges || !image || (N > 0 && (!proj || !sorted_ids))) return fail(POTR_EINVAL, "NULL buffer");
     if (!aligned16(proj)) return fail(POTR_EINVAL, "proj must be 16-byte aligned");
     return launch_blend(N, V, cams[0], *cfg, proj, sorted_ids, tile_ranges, image, p_final, t_final, n_walk,
-                        (hipStream_t)stream);
+                        n_blend, (hipStream_t)stream);
 }
 
 potr_status potr_score(int64_t N, int32_t V, const potr_camera* cams, const potr_config* cfg,

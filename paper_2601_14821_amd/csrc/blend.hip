@@ -60,7 +60,7 @@ __global__ __launch_bounds__(TW * TH) void k_blend(int64_t N, int32_t W, int32_t
                                                    const uint32_t* __restrict__ ids,
                                                    const int32_t* __restrict__ ranges, float* __restrict__ image,
                                                    float* __restrict__ p_final, float* __restrict__ t_final,
-                                                   int32_t* __restrict__ n_walk) {
+                                                   int32_t* __restrict__ n_walk, int32_t* __restrict__ n_blend) {
     constexpr int NT = TW * TH;
     __shared__ float4 s_a[kMaxBatch];
     __shared__ float4 s_b[kMaxBatch];
@@ -78,7 +78,7 @@ __global__ __launch_bounds__(TW * TH) void k_blend(int64_t N, int32_t W, int32_t
 
     float T = 1.f, cr = 0.f, cg = 0.f, cb = 0.f;
     bool done = !inside;
-    int walk = 0;
+    int walk = 0, blended = 0;
     for (int base = beg; base < end; base += B) {
         if (__syncthreads_count(!done) == 0) break;
         const int cnt = min(B, end - base);
@@ -101,6 +101,7 @@ __global__ __launch_bounds__(TW * TH) void k_blend(int64_t N, int32_t W, int32_t
                 cg += w * b.w;
                 cb += w * s_c[j];
                 T = Tn;
+                ++blended;
             }
         }
     }
@@ -117,6 +118,7 @@ __global__ __launch_bounds__(TW * TH) void k_blend(int64_t N, int32_t W, int32_t
     }
     if (t_final) t_final[pix] = T;
     if (n_walk) n_walk[pix] = walk;
+    if (n_blend) n_blend[pix] = blended;
 }
 
 template <int TW, int TH>
@@ -242,10 +244,10 @@ __global__ __launch_bounds__(TW * TH) void k_score(int64_t N, int32_t W, int32_t
 template <int TW, int TH>
 potr_status blend_shape(int64_t N, int32_t V, const potr_camera& c, const potr_config& cfg, const potr_proj* proj,
                         const uint32_t* ids, const int32_t* ranges, float* image, float* p_final, float* t_final,
-                        int32_t* n_walk, hipStream_t s) {
+                        int32_t* n_walk, int32_t* n_blend, hipStream_t s) {
     const int txs = tiles_x(c, cfg), tpv = txs * tiles_y(c, cfg);
     hipLaunchKernelGGL((k_blend<TW, TH>), dim3(tpv, V), dim3(TW * TH), 0, s, N, c.width, c.height, txs, tpv, cfg,
-                       proj, ids, ranges, image, p_final, t_final, n_walk);
+                       proj, ids, ranges, image, p_final, t_final, n_walk, n_blend);
     return check_launch("k_blend");
 }
 
@@ -264,13 +266,13 @@ potr_status score_shape(int64_t N, int32_t V, const potr_camera& c, const potr_c
 
 potr_status launch_blend(int64_t N, int32_t V, const potr_camera& c, const potr_config& cfg, const potr_proj* proj,
                          const uint32_t* ids, const int32_t* ranges, float* image, float* p_final, float* t_final,
-                         int32_t* n_walk, hipStream_t s) {
+                         int32_t* n_walk, int32_t* n_blend, hipStream_t s) {
     if (cfg.tile_w == 16 && cfg.tile_h == 16)
-        return blend_shape<16, 16>(N, V, c, cfg, proj, ids, ranges, image, p_final, t_final, n_walk, s);
+        return blend_shape<16, 16>(N, V, c, cfg, proj, ids, ranges, image, p_final, t_final, n_walk, n_blend, s);
     if (cfg.tile_w == 8 && cfg.tile_h == 8)
-        return blend_shape<8, 8>(N, V, c, cfg, proj, ids, ranges, image, p_final, t_final, n_walk, s);
+        return blend_shape<8, 8>(N, V, c, cfg, proj, ids, ranges, image, p_final, t_final, n_walk, n_blend, s);
     if (cfg.tile_w == 32 && cfg.tile_h == 8)
-        return blend_shape<32, 8>(N, V, c, cfg, proj, ids, ranges, image, p_final, t_final, n_walk, s);
+        return blend_shape<32, 8>(N, V, c, cfg, proj, ids, ranges, image, p_final, t_final, n_walk, n_blend, s);
     return fail(POTR_EUNSUPPORTED, "tile %dx%d not built", cfg.tile_w, cfg.tile_h);
 }
 

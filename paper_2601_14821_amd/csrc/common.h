@@ -54,7 +54,8 @@ potr_status launch_sort(int64_t N, int32_t V, int32_t tiles_per_view, const int6
 
 potr_status launch_blend(int64_t N, int32_t V, const potr_camera& cam0, const potr_config& cfg,
                          const potr_proj* proj, const uint32_t* sorted_ids, const int32_t* tile_ranges,
-                         float* image, float* p_final, float* t_final, int32_t* n_walk, hipStream_t s);
+                         float* image, float* p_final, float* t_final, int32_t* n_walk, int32_t* n_blend,
+                         hipStream_t s);
 
 potr_status launch_score(int64_t N, int32_t V, const potr_camera& cam0, const potr_config& cfg,
                          const potr_proj* proj, const uint32_t* sorted_ids, const int32_t* tile_ranges,

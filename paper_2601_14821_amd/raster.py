@@ -48,6 +48,7 @@ class ViewBatch:
     p_final: torch.Tensor | None = None
     t_final: torch.Tensor | None = None
     n_walk: torch.Tensor | None = None
+    n_blend: torch.Tensor | None = None
 
 
 class Rasterizer:
@@ -120,16 +121,17 @@ class Rasterizer:
         vb.sorted_ids, vb.tile_ranges = ids, ranges
         return vb
 
-    def blend(self, vb: ViewBatch, cams, keep: bool = True) -> ViewBatch:
+    def blend(self, vb: ViewBatch, cams, count_blended: bool = False) -> ViewBatch:
         V, H, W = vb.V, cams[0].height, cams[0].width
         P = V * H * W
         image = self._f32("image", 3 * P)[: 3 * P].view(V, H, W, 3)
         pf = self._f32("p_final", 3 * P)[: 3 * P].view(V, H, W, 3)
         tf = self._f32("t_final", P)[:P].view(V, H, W)
         nw = self._i32("n_walk", P)[:P].view(V, H, W)
+        nb = self._i32("n_blend", P)[:P].view(V, H, W) if count_blended else None
         L.call("potr_blend", vb.N, V, L.make_cameras(cams), C.byref(self.cfg), L.ptr(vb.proj), L.ptr(vb.sorted_ids),
-               L.ptr(vb.tile_ranges), L.ptr(image), L.ptr(pf), L.ptr(tf), L.ptr(nw), L.stream_handle())
-        vb.image, vb.p_final, vb.t_final, vb.n_walk = image, pf, tf, nw
+               L.ptr(vb.tile_ranges), L.ptr(image), L.ptr(pf), L.ptr(tf), L.ptr(nw), L.ptr(nb), L.stream_handle())
+        vb.image, vb.p_final, vb.t_final, vb.n_walk, vb.n_blend = image, pf, tf, nw, nb
         return vb
 
     def score(self, vb: ViewBatch, cams, scores=None, scores_se=None, importance=None, target=None) -> None:
