@@ -180,6 +180,44 @@ POTR_API potr_status potr_score(int64_t N, int32_t V, const potr_camera* cams, c
                        const float* target, float* scores, float* scores_se, float* importance,
                        void* stream);
 
+/* ---------------------------------------------------------------------------
+ * Backward of the forward render for a loss L given dL/dimage [V,H,W,3]: the
+ * standard training pass that the paper's fine-tuning stage runs (Sec. 4.6).
+ * With S_k = P_K - P_{k+1} per pixel,
+ *   dC/dc_k = T_k alpha_k,  dC/dalpha_k = T_k c_k - (S_k + T_final bg)/(1 - alpha_k),
+ * alpha_k = min(alpha_max, o G), G = exp(-q/2) (no gradient through the clamp,
+ * the colour clamp at 0 or the Jacobian clamp). The removal effect of Sec. 4.2
+ * is PD_k = -alpha_k dC/dalpha_k.
+ *
+ * potr_blend_backward: grad2d [V*N*9] += per (view, splat):
+ *   d mean2d.x, d mean2d.y, d conic.a, d conic.b, d conic.c, d opacity, d r, d g, d b
+ *   (conic.b is the stored off-diagonal entry, entering q as 2b dx dy).
+ * potr_project_backward: chains grad2d through the projection (FP64) into
+ *   d_means [N,3], d_scales [N,3], d_quats [N,4] (w.r.t. the unnormalised
+ *   quaternion), d_opac [N], d_sh [N,16,3]; all ACCUMULATED (+=), summed over views.
+ * potr_backward: both, with grad2d in a workspace of potr_backward_workspace_size
+ *   bytes that it clears itself.
+ * Inputs proj, sorted_ids, tile_ranges, p_final, t_final, n_walk are those of
+ * the forward (potr_project ... potr_blend) of the same views.
+ * ------------------------------------------------------------------------- */
+POTR_API potr_status potr_blend_backward(int64_t N, int32_t V, const potr_camera* cams, const potr_config* cfg,
+                                         const potr_proj* proj, const uint32_t* sorted_ids,
+                                         const int32_t* tile_ranges, const float* p_final, const float* t_final,
+                                         const int32_t* n_walk, const float* dL_dimage, float* grad2d, void* stream);
+POTR_API potr_status potr_project_backward(int64_t N, int32_t V, const potr_camera* cams, const potr_config* cfg,
+                                           const float* means, const float* scales, const float* quats,
+                                           const float* opac, const float* sh, const float* grad2d,
+                                           float* d_means, float* d_scales, float* d_quats, float* d_opac,
+                                           float* d_sh, void* stream);
+POTR_API potr_status potr_backward_workspace_size(int64_t N, int32_t V, size_t* bytes);
+POTR_API potr_status potr_backward(int64_t N, int32_t V, const potr_camera* cams, const potr_config* cfg,
+                                   const float* means, const float* scales, const float* quats, const float* opac,
+                                   const float* sh, const potr_proj* proj, const uint32_t* sorted_ids,
+                                   const int32_t* tile_ranges, const float* p_final, const float* t_final,
+                                   const int32_t* n_walk, const float* dL_dimage, void* ws, size_t ws_bytes,
+                                   float* d_means, float* d_scales, float* d_quats, float* d_opac, float* d_sh,
+                                   void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -82,6 +82,10 @@ def _f32(a):
     return np.ascontiguousarray(a, dtype=np.float32)
 
 
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
 def sh_basis(lmax: int, d) -> np.ndarray:
     d = np.ascontiguousarray(d, np.float64)
     out = np.zeros((lmax + 1) ** 2)
@@ -94,10 +98,10 @@ def project(scene, cam, s) -> dict:
     out = dict(mean2d=np.zeros((n, 2)), cov2d=np.zeros((n, 3)), conic=np.zeros((n, 3)),
                rgb=np.zeros((n, 3)), depth_key=np.zeros(n, np.uint32), rect=np.zeros((n, 4), np.int32),
                tiles_touched=np.zeros(n, np.int32))
-    m, sc, q, o, sh = (_f32(a) for a in (scene.means, scene.scales, scene.quats, scene.opacities, scene.sh))
+    m, sc, q, o, sh = (_f64(a) for a in (scene.means, scene.scales, scene.quats, scene.opacities, scene.sh))
     cm, cf = _cam(cam), _cfg(s)
-    lib().orc_project(C.c_int64(n), C.byref(cm), C.byref(cf), _p(m, C.c_float), _p(sc, C.c_float),
-                      _p(q, C.c_float), _p(o, C.c_float), _p(sh, C.c_float),
+    lib().orc_project(C.c_int64(n), C.byref(cm), C.byref(cf), _p(m, C.c_double), _p(sc, C.c_double),
+                      _p(q, C.c_double), _p(o, C.c_double), _p(sh, C.c_double),
                       _p(out["mean2d"], C.c_double), _p(out["cov2d"], C.c_double),
                       _p(out["conic"], C.c_double), _p(out["rgb"], C.c_double),
                       _p(out["depth_key"], C.c_uint32), _p(out["rect"], C.c_int32),
@@ -154,7 +158,7 @@ def render(scene, cam, s, proj=None, bins=None, target=None, method: int = 0, th
     g = lambda k, ct: _p(out.get(k), ct)
     nflag = lib().orc_render(
         C.c_int64(n), C.byref(cm), C.byref(cf), _p(proj["mean2d"], C.c_double), _p(proj["conic"], C.c_double),
-        _p(proj["rgb"], C.c_double), _p(_f32(scene.opacities), C.c_float), _p(ranges, C.c_int32),
+        _p(proj["rgb"], C.c_double), _p(_f64(scene.opacities), C.c_double), _p(ranges, C.c_int32),
         _p(ids, C.c_int32), _p(tgt, C.c_float), C.c_int32(method), C.c_int32(int(record_f32)),
         C.c_int32(threads or default_threads()),
         g("image", C.c_double), g("p_final", C.c_double), g("t_final", C.c_double), g("n_walk", C.c_int32),
@@ -178,7 +182,7 @@ def render_without(scene, cam, s, k: int, proj=None, bins=None, record_f32: bool
     img = np.zeros((cam.height, cam.width, 3))
     lib().orc_render_without(C.c_int64(scene.n), C.byref(_cam(cam)), C.byref(_cfg(s)),
                              _p(proj["mean2d"], C.c_double), _p(proj["conic"], C.c_double),
-                             _p(proj["rgb"], C.c_double), _p(_f32(scene.opacities), C.c_float),
+                             _p(proj["rgb"], C.c_double), _p(_f64(scene.opacities), C.c_double),
                              _p(np.ascontiguousarray(ranges, np.int32), C.c_int32),
                              _p(np.ascontiguousarray(ids, np.int32), C.c_int32), C.c_int64(k),
                              C.c_int32(int(record_f32)), _p(img, C.c_double))
@@ -200,3 +204,31 @@ def score_views(scene, cams, s, method: int = 0, threads: int | None = None, tar
                 tot[k] = tot.get(k, 0.0) + r[k]
         tot["n_flagged"] = tot.get("n_flagged", 0) + r["n_flagged"]
     return tot, views
+
+
+def backward(scene, cam, s, dL_dimage, proj=None, bins=None, threads: int | None = None) -> dict:
+    """Analytic FP64 gradient of a loss through one view given dL/dimage [H, W, 3]."""
+    if proj is None:
+        proj = project(scene, cam, s)
+    tx, ty = s.tiles(cam)
+    if bins is None:
+        bins = bin_sort(proj["rect"], proj["depth_key"], tx, ty)
+    _, ids, ranges = bins
+    n = scene.n
+    out = dict(d_means=np.zeros((n, 3)), d_scales=np.zeros((n, 3)), d_quats=np.zeros((n, 4)),
+               d_opac=np.zeros(n), d_sh=np.zeros((n, 16, 3)), d_mean2d=np.zeros((n, 2)),
+               d_conic=np.zeros((n, 3)), d_rgb=np.zeros((n, 3)))
+    m, sc, q, o, sh = (_f64(a) for a in (scene.means, scene.scales, scene.quats, scene.opacities, scene.sh))
+    g = _f64(dL_dimage)
+    assert g.shape == (cam.height, cam.width, 3)
+    d = lambda k: _p(out[k], C.c_double)
+    lib().orc_backward(C.c_int64(n), C.byref(_cam(cam)), C.byref(_cfg(s)), _p(m, C.c_double),
+                       _p(sc, C.c_double), _p(q, C.c_double), _p(o, C.c_double), _p(sh, C.c_double),
+                       _p(proj["mean2d"], C.c_double), _p(proj["conic"], C.c_double), _p(proj["rgb"], C.c_double),
+                       _p(np.ascontiguousarray(ranges, np.int32), C.c_int32),
+                       _p(np.ascontiguousarray(ids, np.int32), C.c_int32), _p(g, C.c_double),
+                       C.c_int32(threads or default_threads()), d("d_means"), d("d_scales"), d("d_quats"),
+                       d("d_opac"), d("d_sh"), d("d_mean2d"), d("d_conic"), d("d_rgb"))
+    out["proj"] = proj
+    out["bins"] = bins
+    return out

@@ -84,12 +84,12 @@ static void quat_rotation(const double qn[4], double M[9])
 
 /* Camera-space depth in FP32 by the fixed chain t_z + R20 x + R21 y + R22 z,
  * each step one fused multiply-add; its bits are the depth sort key. */
-static float depth_f32(const orc_camera* cam, const float* m)
+static float depth_f32(const orc_camera* cam, const double* m)
 {
     float acc = cam->t[2];
-    acc = fmaf(cam->R[6], m[0], acc);
-    acc = fmaf(cam->R[7], m[1], acc);
-    acc = fmaf(cam->R[8], m[2], acc);
+    acc = fmaf(cam->R[6], (float)m[0], acc);
+    acc = fmaf(cam->R[7], (float)m[1], acc);
+    acc = fmaf(cam->R[8], (float)m[2], acc);
     return acc;
 }
 
@@ -101,8 +101,8 @@ static void camera_eye(const orc_camera* cam, double eye[3])
 }
 
 void orc_project(int64_t N, const orc_camera* cam, const orc_config* cfg,
-                 const float* means, const float* scales, const float* quats,
-                 const float* opac, const float* sh,
+                 const double* means, const double* scales, const double* quats,
+                 const double* opac, const double* sh,
                  double* mean2d, double* cov2d, double* conic, double* rgb,
                  uint32_t* depth_key, int32_t* rect, int32_t* tiles_touched)
 {
@@ -111,7 +111,7 @@ void orc_project(int64_t N, const orc_camera* cam, const orc_config* cfg,
     camera_eye(cam, eye);
     const int nsh = (cfg->sh_degree + 1) * (cfg->sh_degree + 1);
     for (int64_t i = 0; i < N; ++i) {
-        const float* m = means + 3 * i;
+        const double* m = means + 3 * i;
         float z32 = depth_f32(cam, m);
         uint32_t key;
         memcpy(&key, &z32, 4);
@@ -131,15 +131,15 @@ void orc_project(int64_t N, const orc_camera* cam, const orc_config* cfg,
         if (!(o >= (double)cfg->alpha_min)) continue;
 
         /* 3D covariance from scale and rotation */
-        const float* q = quats + 4 * i;
-        double qn2 = (double)q[0] * q[0] + (double)q[1] * q[1] + (double)q[2] * q[2] + (double)q[3] * q[3];
+        const double* q = quats + 4 * i;
+        double qn2 = q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3];
         if (!(qn2 > 0.0)) continue;
         double qinv = 1.0 / sqrt(qn2), qn[4];
         for (int k = 0; k < 4; ++k) qn[k] = q[k] * qinv;
         double Rq[9];
         quat_rotation(qn, Rq);
         double s2[3];
-        for (int k = 0; k < 3; ++k) s2[k] = (double)scales[3 * i + k] * scales[3 * i + k];
+        for (int k = 0; k < 3; ++k) s2[k] = scales[3 * i + k] * scales[3 * i + k];
         double Sig[9];
         for (int a = 0; a < 3; ++a)
             for (int b = 0; b < 3; ++b) {
@@ -197,7 +197,7 @@ void orc_project(int64_t N, const orc_camera* cam, const orc_config* cfg,
         orc_sh_basis(cfg->sh_degree, d, Y);
         for (int c = 0; c < 3; ++c) {
             double acc = 0.0;
-            for (int k = 0; k < nsh; ++k) acc += (double)sh[48 * i + 3 * k + c] * Y[k];
+            for (int k = 0; k < nsh; ++k) acc += sh[48 * i + 3 * k + c] * Y[k];
             rgb[3 * i + c] = fmax(0.0, acc + 0.5);
         }
         if (!(ilo <= ihi) || !(jlo <= jhi)) continue;
@@ -314,7 +314,7 @@ typedef struct {
     const orc_camera* cam;
     const orc_config* cfg;
     const double *mean2d, *conic, *rgb;
-    const float* opac;
+    const double* opac;
     const int32_t *tile_ranges, *sorted_id;
     const float* target;
     int removal_method;
@@ -340,7 +340,7 @@ static void eval_splat(const render_ctx* c, int64_t s, double px, double py,
     double A = rec(c, c->conic[3 * s]), B = rec(c, c->conic[3 * s + 1]), C = rec(c, c->conic[3 * s + 2]);
     double q = A * dx * dx + 2.0 * B * dx * dy + C * dy * dy;
     *q_out = q;
-    *a0_out = (double)c->opac[s] * exp(-0.5 * q);
+    *a0_out = c->opac[s] * exp(-0.5 * q);
     /* Error bound of an FP32 evaluation of q from FP32-rounded inputs (used only
      * to flag decisions that FP32 arithmetic could take the other way): rounding
      * of the pixel offsets, of the conic and of the quadratic form itself. */
@@ -551,7 +551,7 @@ static int max_list_len(const orc_camera* cam, const orc_config* cfg, const int3
 
 int64_t orc_render(int64_t N, const orc_camera* cam, const orc_config* cfg,
                    const double* mean2d, const double* conic, const double* rgb,
-                   const float* opac, const int32_t* tile_ranges, const int32_t* sorted_id,
+                   const double* opac, const int32_t* tile_ranges, const int32_t* sorted_id,
                    const float* target, int32_t removal_method, int32_t record_f32, int32_t n_threads,
                    double* image, double* p_final, double* t_final, int32_t* n_walk,
                    int32_t* n_blend, double* score_l1, double* score_se, double* importance,
@@ -576,7 +576,7 @@ int64_t orc_render(int64_t N, const orc_camera* cam, const orc_config* cfg,
 
 void orc_render_without(int64_t N, const orc_camera* cam, const orc_config* cfg,
                         const double* mean2d, const double* conic, const double* rgb,
-                        const float* opac, const int32_t* tile_ranges, const int32_t* sorted_id,
+                        const double* opac, const int32_t* tile_ranges, const int32_t* sorted_id,
                         int64_t k, int32_t record_f32, double* image)
 {
     render_ctx c;
@@ -591,4 +591,307 @@ void orc_render_without(int64_t N, const orc_camera* cam, const orc_config* cfg,
     pthread_mutex_init(&c.mu, NULL);
     parallel_rows(cam->height, 1, render_row, &c);
     pthread_mutex_destroy(&c.mu);
+}
+
+/* ------------------------------------------------------------------------- */
+/* Backward: gradient of a loss L given dL/dC per pixel, through compositing   */
+/* (Sec. 3) and the projection. Per pixel, C = P_k + T_k a_k c_k              */
+/* + (S_k + T_K bg) / (1 - a_k) * (1 - a_k), so with S_k = P_K - P_{k+1}:       */
+/*   dC/dc_k = T_k a_k,   dC/da_k = T_k c_k - (S_k + T_K bg) / (1 - a_k).       */
+/* a_k = min(a_max, o G), G = exp(-q/2): zero gradient on the clamp.           */
+/* ------------------------------------------------------------------------- */
+typedef struct {
+    const orc_camera* cam;
+    const orc_config* cfg;
+    const double *mean2d, *conic, *rgb, *opac;
+    const int32_t *tile_ranges, *sorted_id;
+    const double* dL_dC;
+    double *g_mean2d, *g_conic, *g_opac, *g_rgb;
+    int max_list;
+} bwd_ctx;
+
+static void backward_row(void* vctx, int py_i)
+{
+    bwd_ctx* c = (bwd_ctx*)vctx;
+    const orc_camera* cam = c->cam;
+    const orc_config* cfg = c->cfg;
+    const int W = cam->width, tw = cfg->tile_w, th = cfg->tile_h;
+    const int tiles_x = (W + tw - 1) / tw;
+    const double qmax = cfg->q_max, amin = cfg->alpha_min, amax = cfg->alpha_max, tmin = cfg->t_min;
+    const double bg[3] = { cfg->bg[0], cfg->bg[1], cfg->bg[2] };
+    const int M = c->max_list + 1;
+    double* al = (double*)malloc(sizeof(double) * M);
+    double* a0s = (double*)malloc(sizeof(double) * M);
+    double* Tk = (double*)malloc(sizeof(double) * M);
+    double* dxs = (double*)malloc(sizeof(double) * 2 * M);
+    double* Pk = (double*)malloc(sizeof(double) * 3 * (M + 1));
+    int64_t* ids = (int64_t*)malloc(sizeof(int64_t) * M);
+    for (int px_i = 0; px_i < W; ++px_i) {
+        const double px = px_i + 0.5, py = py_i + 0.5;
+        const int tile = (py_i / th) * tiles_x + px_i / tw;
+        const int beg = c->tile_ranges[2 * tile], end = c->tile_ranges[2 * tile + 1];
+        const int64_t pix = (int64_t)py_i * W + px_i;
+        const double* g = c->dL_dC + 3 * pix;
+        double T = 1.0;
+        int K = 0;
+        Pk[0] = Pk[1] = Pk[2] = 0.0;
+        for (int pos = beg; pos < end; ++pos) {
+            const int64_t s = c->sorted_id[pos];
+            const double dx = px - c->mean2d[2 * s], dy = py - c->mean2d[2 * s + 1];
+            const double A = c->conic[3 * s], B = c->conic[3 * s + 1], Cc = c->conic[3 * s + 2];
+            const double q = A * dx * dx + 2.0 * B * dx * dy + Cc * dy * dy;
+            const double a0 = c->opac[s] * exp(-0.5 * q);
+            if (!(q <= qmax) || !(a0 >= amin)) continue;
+            const double a = fmin(amax, a0);
+            const double Tn = T * (1.0 - a);
+            if (tmin > 0.0 && Tn < tmin) break;
+            al[K] = a; a0s[K] = a0; Tk[K] = T; ids[K] = s; dxs[2 * K] = dx; dxs[2 * K + 1] = dy;
+            for (int ch = 0; ch < 3; ++ch) Pk[3 * (K + 1) + ch] = Pk[3 * K + ch] + T * a * c->rgb[3 * s + ch];
+            T = Tn;
+            ++K;
+        }
+        const double* PK = Pk + 3 * K;
+        for (int k = 0; k < K; ++k) {
+            const int64_t s = ids[k];
+            const double a = al[k];
+            double dLda = 0.0;
+            for (int ch = 0; ch < 3; ++ch) {
+                const double S = PK[ch] - Pk[3 * (k + 1) + ch];
+                dLda += g[ch] * (Tk[k] * c->rgb[3 * s + ch] - (S + T * bg[ch]) / (1.0 - a));
+                atomic_add_f64(&c->g_rgb[3 * s + ch], g[ch] * Tk[k] * a);
+            }
+            if (a0s[k] >= amax) continue;           /* clamped: alpha does not move */
+            const double o = c->opac[s];
+            atomic_add_f64(&c->g_opac[s], dLda * a0s[k] / o);
+            const double dLdq = -0.5 * a0s[k] * dLda;
+            const double dx = dxs[2 * k], dy = dxs[2 * k + 1];
+            const double A = c->conic[3 * s], B = c->conic[3 * s + 1], Cc = c->conic[3 * s + 2];
+            /* dx = px - mean_x, so dq/dmean_x = -2 (A dx + B dy) */
+            atomic_add_f64(&c->g_mean2d[2 * s], dLdq * -2.0 * (A * dx + B * dy));
+            atomic_add_f64(&c->g_mean2d[2 * s + 1], dLdq * -2.0 * (B * dx + Cc * dy));
+            atomic_add_f64(&c->g_conic[3 * s], dLdq * dx * dx);
+            atomic_add_f64(&c->g_conic[3 * s + 1], dLdq * 2.0 * dx * dy);
+            atomic_add_f64(&c->g_conic[3 * s + 2], dLdq * dy * dy);
+        }
+    }
+    free(al); free(a0s); free(Tk); free(dxs); free(Pk); free(ids);
+}
+
+/* Derivative of d -> Y(d / |d|) at a unit direction, by a fourth-order central
+ * difference of the recurrence-based basis: D[k*3 + j] = dY_k / du_j. */
+static void sh_direction_jacobian(int lmax, const double d[3], double* D)
+{
+    const int nk = (lmax + 1) * (lmax + 1);
+    const double h = 1e-3;
+    const double w[4] = { 1.0, -8.0, 8.0, -1.0 }, off[4] = { -2.0, -1.0, 1.0, 2.0 };
+    double Y[16];
+    for (int k = 0; k < 3 * nk; ++k) D[k] = 0.0;
+    for (int j = 0; j < 3; ++j) {
+        for (int t = 0; t < 4; ++t) {
+            double u[3] = { d[0], d[1], d[2] };
+            u[j] += off[t] * h;
+            const double n = sqrt(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+            for (int i = 0; i < 3; ++i) u[i] /= n;
+            orc_sh_basis(lmax, u, Y);
+            for (int k = 0; k < nk; ++k) D[3 * k + j] += w[t] * Y[k] / (12.0 * h);
+        }
+    }
+}
+
+static void project_backward(int64_t i, const orc_camera* cam, const orc_config* cfg,
+                             const double* means, const double* scales, const double* quats,
+                             const double* opac, const double* sh,
+                             const double* g_mean2d, const double* g_conic, const double* g_opac,
+                             const double* g_rgb,
+                             double* d_means, double* d_scales, double* d_quats, double* d_opac, double* d_sh)
+{
+    const double* m = means + 3 * i;
+    const int W = cam->width, H = cam->height;
+    double Rc[9], t[3];
+    for (int k = 0; k < 9; ++k) Rc[k] = cam->R[k];
+    for (int k = 0; k < 3; ++k) t[k] = cam->t[k];
+    double p[3];
+    for (int r = 0; r < 3; ++r) p[r] = Rc[3 * r] * m[0] + Rc[3 * r + 1] * m[1] + Rc[3 * r + 2] * m[2] + t[r];
+    const double x = p[0], y = p[1], z = p[2], fx = cam->fx, fy = cam->fy;
+    /* forward intermediates */
+    const double* q = quats + 4 * i;
+    const double qn = sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+    const double qh[4] = { q[0] / qn, q[1] / qn, q[2] / qn, q[3] / qn };
+    double Rq[9];
+    quat_rotation(qh, Rq);
+    const double s[3] = { scales[3 * i], scales[3 * i + 1], scales[3 * i + 2] };
+    double Mm[9], Sig[9];
+    for (int r = 0; r < 3; ++r)
+        for (int k = 0; k < 3; ++k) Mm[3 * r + k] = Rq[3 * r + k] * s[k];
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) {
+            double acc = 0;
+            for (int k = 0; k < 3; ++k) acc += Mm[3 * a + k] * Mm[3 * b + k];
+            Sig[3 * a + b] = acc;
+        }
+    const double limx = (double)cfg->jclamp * 0.5 * W / fx, limy = (double)cfg->jclamp * 0.5 * H / fy;
+    const double rx = x / z, ry = y / z;
+    const int freex = rx > -limx && rx < limx, freey = ry > -limy && ry < limy;
+    const double tx = fmin(limx, fmax(-limx, rx)), ty = fmin(limy, fmax(-limy, ry));
+    const double J[6] = { fx / z, 0.0, -fx * tx / z, 0.0, fy / z, -fy * ty / z };
+    double T[6];
+    for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 3; ++b) {
+            double acc = 0;
+            for (int k = 0; k < 3; ++k) acc += J[3 * a + k] * Rc[3 * k + b];
+            T[3 * a + b] = acc;
+        }
+    double C2[4];
+    for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b) {
+            double acc = 0;
+            for (int k = 0; k < 3; ++k)
+                for (int l = 0; l < 3; ++l) acc += T[3 * a + k] * Sig[3 * k + l] * T[3 * b + l];
+            C2[2 * a + b] = acc;
+        }
+    C2[0] += cfg->eps2d;
+    C2[3] += cfg->eps2d;
+    C2[1] = C2[2] = 0.5 * (C2[1] + C2[2]);
+    const double det = C2[0] * C2[3] - C2[1] * C2[2];
+    const double Q[4] = { C2[3] / det, -C2[1] / det, -C2[2] / det, C2[0] / det };
+
+    /* conic -> 2D covariance: dL/dSigma' = -Q G_Q Q, G_Q symmetric with the
+     * off-diagonal gradient split over both entries */
+    const double GQ[4] = { g_conic[3 * i], 0.5 * g_conic[3 * i + 1], 0.5 * g_conic[3 * i + 1], g_conic[3 * i + 2] };
+    double tmp[4], GS[4];
+    for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b) tmp[2 * a + b] = GQ[2 * a] * Q[b] + GQ[2 * a + 1] * Q[2 + b];
+    for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b) GS[2 * a + b] = -(Q[2 * a] * tmp[b] + Q[2 * a + 1] * tmp[2 + b]);
+    /* Sigma' = T Sigma T^T: dL/dSigma = T^T GS T, dL/dT = 2 GS T Sigma */
+    double GSig[9], GT[6], TS[6];
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) {
+            double acc = 0;
+            for (int k = 0; k < 2; ++k)
+                for (int l = 0; l < 2; ++l) acc += T[3 * k + a] * GS[2 * k + l] * T[3 * l + b];
+            GSig[3 * a + b] = acc;
+        }
+    for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 3; ++b) {
+            double acc = 0;
+            for (int k = 0; k < 3; ++k) acc += T[3 * a + k] * Sig[3 * k + b];
+            TS[3 * a + b] = acc;
+        }
+    for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 3; ++b) GT[3 * a + b] = 2.0 * (GS[2 * a] * TS[b] + GS[2 * a + 1] * TS[3 + b]);
+    /* T = J R: dL/dJ = GT R^T */
+    double GJ[6];
+    for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 3; ++b) {
+            double acc = 0;
+            for (int k = 0; k < 3; ++k) acc += GT[3 * a + k] * Rc[3 * b + k];
+            GJ[3 * a + b] = acc;
+        }
+    /* J and the pixel centre as functions of the camera-space point */
+    double gp[3] = { 0, 0, 0 };
+    gp[2] += GJ[0] * (-fx / (z * z)) + GJ[4] * (-fy / (z * z));
+    gp[0] += GJ[2] * (freex ? -fx / (z * z) : 0.0);
+    gp[2] += GJ[2] * fx * tx / (z * z) * (freex ? 2.0 : 1.0);
+    gp[1] += GJ[5] * (freey ? -fy / (z * z) : 0.0);
+    gp[2] += GJ[5] * fy * ty / (z * z) * (freey ? 2.0 : 1.0);
+    const double gu = g_mean2d[2 * i], gv = g_mean2d[2 * i + 1];
+    gp[0] += gu * fx / z;
+    gp[1] += gv * fy / z;
+    gp[2] += -gu * fx * x / (z * z) - gv * fy * y / (z * z);
+    for (int j = 0; j < 3; ++j) d_means[3 * i + j] += Rc[j] * gp[0] + Rc[3 + j] * gp[1] + Rc[6 + j] * gp[2];
+
+    /* Sigma = M M^T, M = R(q) diag(s) */
+    double GM[9];
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) {
+            double acc = 0;
+            for (int k = 0; k < 3; ++k) acc += (GSig[3 * a + k] + GSig[3 * k + a]) * Mm[3 * k + b];
+            GM[3 * a + b] = acc;
+        }
+    double GR[9];
+    for (int r = 0; r < 3; ++r)
+        for (int k = 0; k < 3; ++k) {
+            d_scales[3 * i + k] += GM[3 * r + k] * Rq[3 * r + k];
+            GR[3 * r + k] = GM[3 * r + k] * s[k];
+        }
+    const double w = qh[0], X = qh[1], Y = qh[2], Z = qh[3];
+    /* partial derivatives of the rotation entries w.r.t. (w, x, y, z) */
+    const double dRw[9] = { 0, -2 * Z, 2 * Y, 2 * Z, 0, -2 * X, -2 * Y, 2 * X, 0 };
+    const double dRx[9] = { 0, 2 * Y, 2 * Z, 2 * Y, -4 * X, -2 * w, 2 * Z, 2 * w, -4 * X };
+    const double dRy[9] = { -4 * Y, 2 * X, 2 * w, 2 * X, 0, 2 * Z, -2 * w, 2 * Z, -4 * Y };
+    const double dRz[9] = { -4 * Z, -2 * w, 2 * X, 2 * w, -4 * Z, 2 * Y, 2 * X, 2 * Y, 0 };
+    double gqh[4] = { 0, 0, 0, 0 };
+    for (int k = 0; k < 9; ++k) {
+        gqh[0] += GR[k] * dRw[k];
+        gqh[1] += GR[k] * dRx[k];
+        gqh[2] += GR[k] * dRy[k];
+        gqh[3] += GR[k] * dRz[k];
+    }
+    const double dotq = gqh[0] * qh[0] + gqh[1] * qh[1] + gqh[2] * qh[2] + gqh[3] * qh[3];
+    for (int k = 0; k < 4; ++k) d_quats[4 * i + k] += (gqh[k] - qh[k] * dotq) / qn;
+
+    d_opac[i] += g_opac[i];
+
+    /* colour: max(0, sum_k L_k Y_k(d) + 1/2), d = (mu - eye) / |mu - eye| */
+    double eye[3];
+    camera_eye(cam, eye);
+    double u[3] = { m[0] - eye[0], m[1] - eye[1], m[2] - eye[2] };
+    const double un = sqrt(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+    double d[3] = { u[0] / un, u[1] / un, u[2] / un };
+    const int nk = (cfg->sh_degree + 1) * (cfg->sh_degree + 1);
+    double Yb[16], D[48];
+    orc_sh_basis(cfg->sh_degree, d, Yb);
+    sh_direction_jacobian(cfg->sh_degree, d, D);
+    double gY[16];
+    for (int k = 0; k < nk; ++k) gY[k] = 0.0;
+    for (int ch = 0; ch < 3; ++ch) {
+        double pre = 0.5;
+        for (int k = 0; k < nk; ++k) pre += sh[48 * i + 3 * k + ch] * Yb[k];
+        if (!(pre > 0.0)) continue;
+        const double gc = g_rgb[3 * i + ch];
+        for (int k = 0; k < nk; ++k) {
+            d_sh[48 * i + 3 * k + ch] += gc * Yb[k];
+            gY[k] += gc * sh[48 * i + 3 * k + ch];
+        }
+    }
+    for (int j = 0; j < 3; ++j) {
+        double acc = 0.0;
+        for (int k = 0; k < nk; ++k) acc += gY[k] * D[3 * k + j];
+        d_means[3 * i + j] += acc / un;
+    }
+}
+
+void orc_backward(int64_t N, const orc_camera* cam, const orc_config* cfg,
+                  const double* means, const double* scales, const double* quats,
+                  const double* opac, const double* sh,
+                  const double* mean2d, const double* conic, const double* rgb,
+                  const int32_t* tile_ranges, const int32_t* sorted_id,
+                  const double* dL_dimage, int32_t n_threads,
+                  double* d_means, double* d_scales, double* d_quats, double* d_opac,
+                  double* d_sh, double* d_mean2d, double* d_conic, double* d_rgb)
+{
+    double* g_mean2d = (double*)calloc((size_t)(2 * N + 1), sizeof(double));
+    double* g_conic = (double*)calloc((size_t)(3 * N + 1), sizeof(double));
+    double* g_opac = (double*)calloc((size_t)(N + 1), sizeof(double));
+    double* g_rgb = (double*)calloc((size_t)(3 * N + 1), sizeof(double));
+    bwd_ctx c;
+    memset(&c, 0, sizeof(c));
+    c.cam = cam; c.cfg = cfg; c.mean2d = mean2d; c.conic = conic; c.rgb = rgb; c.opac = opac;
+    c.tile_ranges = tile_ranges; c.sorted_id = sorted_id; c.dL_dC = dL_dimage;
+    c.g_mean2d = g_mean2d; c.g_conic = g_conic; c.g_opac = g_opac; c.g_rgb = g_rgb;
+    c.max_list = max_list_len(cam, cfg, tile_ranges);
+    parallel_rows(cam->height, n_threads, backward_row, &c);
+    for (int64_t i = 0; i < N; ++i) {
+        if (d_mean2d) { d_mean2d[2 * i] += g_mean2d[2 * i]; d_mean2d[2 * i + 1] += g_mean2d[2 * i + 1]; }
+        if (d_conic) for (int k = 0; k < 3; ++k) d_conic[3 * i + k] += g_conic[3 * i + k];
+        if (d_rgb) for (int k = 0; k < 3; ++k) d_rgb[3 * i + k] += g_rgb[3 * i + k];
+        const int touched = g_mean2d[2 * i] != 0.0 || g_mean2d[2 * i + 1] != 0.0 || g_opac[i] != 0.0 ||
+                            g_rgb[3 * i] != 0.0 || g_rgb[3 * i + 1] != 0.0 || g_rgb[3 * i + 2] != 0.0 ||
+                            g_conic[3 * i] != 0.0 || g_conic[3 * i + 1] != 0.0 || g_conic[3 * i + 2] != 0.0;
+        if (!touched) continue;
+        project_backward(i, cam, cfg, means, scales, quats, opac, sh, g_mean2d, g_conic, g_opac, g_rgb,
+                         d_means, d_scales, d_quats, d_opac, d_sh);
+    }
+    free(g_mean2d); free(g_conic); free(g_opac); free(g_rgb);
 }

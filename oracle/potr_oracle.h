@@ -20,7 +20,9 @@
  *     pass that the paper's fine-tuning relies on, Sec. 4.6).
  * All floating point is FP64 except the depth key, which both sides compute in
  * FP32 by one fixed fused-multiply-add chain so that the depth order (an
- * integer result) is decided in the same precision on both sides.
+ * integer result) is decided in the same precision on both sides. Splat
+ * parameters are taken as FP64 arrays (FP32 scenes convert exactly), so that
+ * finite differences can perturb them below FP32 resolution.
  */
 #ifndef POTR_ORACLE_H
 #define POTR_ORACLE_H
@@ -62,8 +64,8 @@ void orc_sh_basis(int32_t lmax, const double d[3], double* out);
  *   rect[4] = tile x0, y0, x1, y1 (half-open), tiles_touched.
  * A culled splat has tiles_touched = 0 and rect = 0. */
 void orc_project(int64_t N, const orc_camera* cam, const orc_config* cfg,
-                 const float* means, const float* scales, const float* quats,
-                 const float* opac, const float* sh,
+                 const double* means, const double* scales, const double* quats,
+                 const double* opac, const double* sh,
                  double* mean2d, double* cov2d, double* conic, double* rgb,
                  uint32_t* depth_key, int32_t* rect, int32_t* tiles_touched);
 
@@ -90,7 +92,7 @@ int64_t orc_bin_sort(int64_t N, int32_t tiles_x, int32_t tiles_y, const int32_t*
  * Returns the number of flagged pixels. */
 int64_t orc_render(int64_t N, const orc_camera* cam, const orc_config* cfg,
                    const double* mean2d, const double* conic, const double* rgb,
-                   const float* opac, const int32_t* tile_ranges, const int32_t* sorted_id,
+                   const double* opac, const int32_t* tile_ranges, const int32_t* sorted_id,
                    const float* target, int32_t removal_method, int32_t record_f32, int32_t n_threads,
                    double* image, double* p_final, double* t_final, int32_t* n_walk,
                    int32_t* n_blend, double* score_l1, double* score_se, double* importance,
@@ -100,16 +102,18 @@ int64_t orc_render(int64_t N, const orc_camera* cam, const orc_config* cfg,
  * (visibility tests and early stop rerun) and return the new image [H*W*3]. */
 void orc_render_without(int64_t N, const orc_camera* cam, const orc_config* cfg,
                         const double* mean2d, const double* conic, const double* rgb,
-                        const float* opac, const int32_t* tile_ranges, const int32_t* sorted_id,
+                        const double* opac, const int32_t* tile_ranges, const int32_t* sorted_id,
                         int64_t k, int32_t record_f32, double* image);
 
-/* Gradient of a loss L through the compositing of one view and the projection.
- * dL_dimage [H*W*3]. Gradients (+=) with the input shapes: d_means [N*3],
- * d_scales [N*3], d_quats [N*4] (w.r.t. the unnormalised quaternion), d_opac [N],
- * d_sh [N*16*3]. Also (+=) d_mean2d [N*2], d_conic [N*3], d_rgb [N*3] when not NULL. */
+/* Gradient of a loss L through the compositing of one view and the projection,
+ * given dL_dimage [H*W*3] (FP64). Gradients are ADDED (+=) with the input
+ * shapes: d_means [N*3], d_scales [N*3], d_quats [N*4] (w.r.t. the unnormalised
+ * quaternion), d_opac [N], d_sh [N*16*3]; and, when not NULL, the per-splat
+ * screen-space gradients d_mean2d [N*2], d_conic [N*3] (a, b, c; b is the
+ * off-diagonal entry), d_rgb [N*3]. Uses the same decisions as orc_render. */
 void orc_backward(int64_t N, const orc_camera* cam, const orc_config* cfg,
-                  const float* means, const float* scales, const float* quats,
-                  const float* opac, const float* sh,
+                  const double* means, const double* scales, const double* quats,
+                  const double* opac, const double* sh,
                   const double* mean2d, const double* conic, const double* rgb,
                   const int32_t* tile_ranges, const int32_t* sorted_id,
                   const double* dL_dimage, int32_t n_threads,

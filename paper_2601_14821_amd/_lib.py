@@ -49,6 +49,10 @@ SIGNATURES = {
     "potr_sort": (_i32, [_i64, _i32, _CAM_P, _CFG_P, _vp, _i64, _vp, _vp, _vp, _sz, _vp, _vp, _vp]),
     "potr_blend": (_i32, [_i64, _i32, _CAM_P, _CFG_P, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "potr_score": (_i32, [_i64, _i32, _CAM_P, _CFG_P, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
+    "potr_blend_backward": (_i32, [_i64, _i32, _CAM_P, _CFG_P, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
+    "potr_project_backward": (_i32, [_i64, _i32, _CAM_P, _CFG_P] + [_vp] * 12),
+    "potr_backward_workspace_size": (_i32, [_i64, _i32, C.POINTER(_sz)]),
+    "potr_backward": (_i32, [_i64, _i32, _CAM_P, _CFG_P] + [_vp] * 13 + [_sz] + [_vp] * 6),
 }
 
 _lib = None

@@ -161,4 +161,68 @@ potr_status potr_score(int64_t N, int32_t V, const potr_camera* cams, const potr
                         scores, scores_se, importance, (hipStream_t)stream);
 }
 
+potr_status potr_blend_backward(int64_t N, int32_t V, const potr_camera* cams, const potr_config* cfg,
+                                const potr_proj* proj, const uint32_t* sorted_ids, const int32_t* tile_ranges,
+                                const float* p_final, const float* t_final, const int32_t* n_walk,
+                                const float* dL_dimage, float* grad2d, void* stream) {
+    potr_status st = check_cfg(cfg);
+    if (st == POTR_OK) st = check_cams(V, cams, cfg);
+    if (st != POTR_OK) return st;
+    if (N < 0) return fail(POTR_EINVAL, "N = %lld", (long long)N);
+    if (N == 0) return POTR_OK;
+    if (!proj || !sorted_ids || !tile_ranges || !p_final || !t_final || !n_walk || !dL_dimage || !grad2d)
+        return fail(POTR_EINVAL, "NULL buffer");
+    if (!aligned16(proj)) return fail(POTR_EINVAL, "proj must be 16-byte aligned");
+    return launch_blend_backward(N, V, cams[0], *cfg, proj, sorted_ids, tile_ranges, p_final, t_final, n_walk,
+                                 dL_dimage, grad2d, (hipStream_t)stream);
+}
+
+potr_status potr_project_backward(int64_t N, int32_t V, const potr_camera* cams, const potr_config* cfg,
+                                  const float* means, const float* scales, const float* quats, const float* opac,
+                                  const float* sh, const float* grad2d, float* d_means, float* d_scales,
+                                  float* d_quats, float* d_opac, float* d_sh, void* stream) {
+    potr_status st = check_cfg(cfg);
+    if (st == POTR_OK) st = check_cams(V, cams, cfg);
+    if (st != POTR_OK) return st;
+    if (N < 0 || N >= (int64_t(1) << 31)) return fail(POTR_EINVAL, "N = %lld out of range", (long long)N);
+    if (N == 0) return POTR_OK;
+    if (!means || !scales || !quats || !opac || !sh || !grad2d || !d_means || !d_scales || !d_quats || !d_opac ||
+        !d_sh)
+        return fail(POTR_EINVAL, "NULL buffer");
+    return launch_project_backward(N, V, cams, *cfg, means, scales, quats, opac, sh, grad2d, d_means, d_scales,
+                                   d_quats, d_opac, d_sh, (hipStream_t)stream);
+}
+
+potr_status potr_backward_workspace_size(int64_t N, int32_t V, size_t* bytes) {
+    if (!bytes || N < 0 || V < 1) return fail(POTR_EINVAL, "bad arguments");
+    *bytes = (size_t)N * V * 9 * sizeof(float);
+    return POTR_OK;
+}
+
+potr_status potr_backward(int64_t N, int32_t V, const potr_camera* cams, const potr_config* cfg,
+                          const float* means, const float* scales, const float* quats, const float* opac,
+                          const float* sh, const potr_proj* proj, const uint32_t* sorted_ids,
+                          const int32_t* tile_ranges, const float* p_final, const float* t_final,
+                          const int32_t* n_walk, const float* dL_dimage, void* ws, size_t ws_bytes,
+                          float* d_means, float* d_scales, float* d_quats, float* d_opac, float* d_sh,
+                          void* stream) {
+    potr_status st = check_cfg(cfg);
+    if (st == POTR_OK) st = check_cams(V, cams, cfg);
+    if (st != POTR_OK) return st;
+    if (N < 0 || N * (int64_t)V >= (int64_t(1) << 31)) return fail(POTR_EINVAL, "N x V out of range");
+    if (N == 0) return POTR_OK;
+    if (!ws) return fail(POTR_EINVAL, "NULL workspace");
+    if (ws_bytes < (size_t)N * V * 9 * sizeof(float))
+        return fail(POTR_ECAPACITY, "backward workspace %zu < %zu bytes", ws_bytes, (size_t)N * V * 9 * sizeof(float));
+    float* g2 = (float*)ws;
+    st = launch_zero(g2, N * V * 9, (hipStream_t)stream);
+    if (st == POTR_OK)
+        st = potr_blend_backward(N, V, cams, cfg, proj, sorted_ids, tile_ranges, p_final, t_final, n_walk, dL_dimage,
+                                 g2, stream);
+    if (st == POTR_OK)
+        st = potr_project_backward(N, V, cams, cfg, means, scales, quats, opac, sh, g2, d_means, d_scales, d_quats,
+                                   d_opac, d_sh, stream);
+    return st;
+}
+
 }  // extern "C"

@@ -1,0 +1,403 @@
+// Backward of the forward render (the standard 3DGS training pass the paper's
+// fine-tuning relies on, Sec. 4.6), for a loss given as dL/dimage.
+//
+// k_blend_bwd walks every pixel's visited prefix front to back, like the score
+// pass, with
+//   dC/dc_k     = T_k alpha_k
+//   dC/dalpha_k = T_k c_k - (S_k + T_final bg) / (1 - alpha_k),  S_k = P_K - P_{k+1}
+// (so the removal effect PD_k = -alpha_k dC/dalpha_k), alpha_k = min(alpha_max,
+// o G), G = exp(-q/2), and accumulates per (view, splat) the gradients of the
+// 2D record: mean2d (2), conic (3), opacity, rgb (3). Front-to-back recovery of
+// T_k avoids dividing by (1 - alpha) as a back-to-front walk would.
+//
+// k_project_bwd chains those to the splat parameters in FP64, one thread per
+// splat, looping over the views of the call.
+#include "common.h"
+#include "dpp.h"
+#include "raster_eval.h"
+
+namespace potr {
+namespace {
+
+constexpr int kBwdChunk = 128;   // entries staged per round
+constexpr int kG = 9;            // gradient components per (view, splat)
+
+template <int TW, int TH>
+__global__ __launch_bounds__(TW * TH) void k_blend_bwd(int64_t N, int32_t W, int32_t H, int32_t tiles_x,
+                                                       int32_t tiles_per_view, potr_config cfg,
+                                                       const potr_proj* __restrict__ proj,
+                                                       const uint32_t* __restrict__ ids,
+                                                       const int32_t* __restrict__ ranges,
+                                                       const float* __restrict__ p_final,
+                                                       const float* __restrict__ t_final,
+                                                       const int32_t* __restrict__ n_walk,
+                                                       const float* __restrict__ dL_dimage,
+                                                       float* __restrict__ grad2d) {
+    constexpr int NT = TW * TH;
+    constexpr int NW = (NT + 63) / 64;
+    __shared__ float4 s_a[kBwdChunk];   // mean2d.x, mean2d.y, opacity, conic.b
+    __shared__ float4 s_b[kBwdChunk];   // conic.a, conic.c, r, g
+    __shared__ float s_c[kBwdChunk];    // b
+    __shared__ uint32_t s_id[kBwdChunk];
+    __shared__ float s_part[kG][NW][kBwdChunk];
+    __shared__ int s_wmax;
+    const int tile = blockIdx.x, v = blockIdx.y;
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const int px = (tile % tiles_x) * TW + (int)(threadIdx.x % TW);
+    const int py = (tile / tiles_x) * TH + (int)(threadIdx.x / TW);
+    const bool inside = px < W && py < H;
+    const float fx = (float)px + 0.5f, fy = (float)py + 0.5f;
+    const int64_t tg = (int64_t)v * tiles_per_view + tile;
+    const int beg = ranges[2 * tg];
+    const potr_proj* pv = proj + (int64_t)v * N;
+    const float qmax = cfg.q_max, amin = cfg.alpha_min, amax = cfg.alpha_max;
+
+    int walk = 0;
+    float PKr = 0.f, PKg = 0.f, PKb = 0.f, TF = 0.f, gr = 0.f, gg = 0.f, gb = 0.f;
+    if (inside) {
+        const int64_t pix = ((int64_t)v * H + py) * W + px;
+        walk = n_walk[pix];
+        PKr = p_final[3 * pix];
+        PKg = p_final[3 * pix + 1];
+        PKb = p_final[3 * pix + 2];
+        TF = t_final[pix];
+        gr = dL_dimage[3 * pix];
+        gg = dL_dimage[3 * pix + 1];
+        gb = dL_dimage[3 * pix + 2];
+    }
+    const float Br = TF * cfg.bg[0], Bg = TF * cfg.bg[1], Bb = TF * cfg.bg[2];
+    if (threadIdx.x == 0) s_wmax = 0;
+    __syncthreads();
+    atomicMax(&s_wmax, walk);
+    __syncthreads();
+    const int wmax = s_wmax;
+
+    float T = 1.f, Pr = 0.f, Pg = 0.f, Pb = 0.f;
+    for (int base = 0; base < wmax; base += kBwdChunk) {
+        const int cnt = min(kBwdChunk, wmax - base);
+        for (int j = threadIdx.x; j < cnt; j += NT) {
+            const uint32_t id = ids[beg + base + j];
+            const float4* src = reinterpret_cast<const float4*>(pv + id);
+            const float4 r0 = src[0], r1 = src[1], r2 = src[2];
+            s_a[j] = make_float4(r0.x, r0.y, r1.y, r0.w);
+            s_b[j] = make_float4(r0.z, r1.x, r1.z, r1.w);
+            s_c[j] = r2.x;
+            s_id[j] = id;
+        }
+        __syncthreads();
+        for (int j = 0; j < cnt; ++j) {
+            float g[kG] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+            bool any = false;
+            if (base + j < walk) {
+                const float4 a = s_a[j];
+                const float4 b = s_b[j];
+                const Gauss e = eval_gauss(a, b, fx, fy);
+                const float al = alpha_of(e, qmax, amin, amax);
+                if (al != 0.f) {
+                    const float dx = e.dx, dy = e.dy, al0 = e.al0;
+                    const float w = __fmul_rn(T, al);
+                    const float cr = b.z, cg = b.w, cb = s_c[j];
+                    Pr = add_weighted(Pr, w, cr);
+                    Pg = add_weighted(Pg, w, cg);
+                    Pb = add_weighted(Pb, w, cb);
+                    const float inv = 1.f / (1.f - al);
+                    const float dLda = gr * (T * cr - (PKr - Pr + Br) * inv) + gg * (T * cg - (PKg - Pg + Bg) * inv) +
+                                       gb * (T * cb - (PKb - Pb + Bb) * inv);
+                    g[6] = gr * w;
+                    g[7] = gg * w;
+                    g[8] = gb * w;
+                    if (al0 < amax) {
+                        g[5] = dLda * e.G;                        // dalpha/do = G
+                        const float dLdq = -0.5f * al0 * dLda;
+                        g[0] = dLdq * 2.f * (b.x * dx + a.w * dy);
+                        g[1] = dLdq * 2.f * (a.w * dx + b.y * dy);
+                        g[2] = dLdq * dx * dx;
+                        g[3] = dLdq * 2.f * dx * dy;
+                        g[4] = dLdq * dy * dy;
+                    }
+                    any = true;
+                    T = next_T(T, al);
+                }
+            }
+            if (__ballot(any)) {
+#pragma unroll
+                for (int c = 0; c < kG; ++c) {
+                    const float s = wave_sum(g[c]);
+                    if (lane == 0) s_part[c][wid][j] = s;
+                }
+            } else if (lane == 0) {
+#pragma unroll
+                for (int c = 0; c < kG; ++c) s_part[c][wid][j] = 0.f;
+            }
+        }
+        __syncthreads();
+        for (int e = threadIdx.x; e < cnt * kG; e += NT) {
+            const int j = e / kG, c = e - j * kG;
+            float t = 0.f;
+#pragma unroll
+            for (int w = 0; w < NW; ++w) t += s_part[c][w][j];
+            if (t != 0.f) unsafeAtomicAdd(grad2d + ((int64_t)v * N + s_id[j]) * kG + c, t);
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------- projection backward (FP64)
+// gradient of the Cartesian real SH basis w.r.t. the (unnormalised) direction
+// components; Y as in k_project
+__device__ inline void sh_basis_grad(double x, double y, double z, int degree, double* Y, double* Gx, double* Gy,
+                                     double* Gz) {
+    for (int k = 0; k < 16; ++k) Y[k] = Gx[k] = Gy[k] = Gz[k] = 0.0;
+    Y[0] = 0.28209479177387814;
+    if (degree < 1) return;
+    const double c1 = 0.4886025119029199;
+    Y[1] = -c1 * y; Gy[1] = -c1;
+    Y[2] = c1 * z;  Gz[2] = c1;
+    Y[3] = -c1 * x; Gx[3] = -c1;
+    if (degree < 2) return;
+    const double xx = x * x, yy = y * y, zz = z * z;
+    const double a2 = 1.0925484305920792, b2 = 0.31539156525252005, c2 = 0.5462742152960396;
+    Y[4] = a2 * x * y;                 Gx[4] = a2 * y; Gy[4] = a2 * x;
+    Y[5] = -a2 * y * z;                Gy[5] = -a2 * z; Gz[5] = -a2 * y;
+    Y[6] = b2 * (2.0 * zz - xx - yy);  Gx[6] = -2.0 * b2 * x; Gy[6] = -2.0 * b2 * y; Gz[6] = 4.0 * b2 * z;
+    Y[7] = -a2 * x * z;                Gx[7] = -a2 * z; Gz[7] = -a2 * x;
+    Y[8] = c2 * (xx - yy);             Gx[8] = 2.0 * c2 * x; Gy[8] = -2.0 * c2 * y;
+    if (degree < 3) return;
+    const double a3 = 0.5900435899266435, b3 = 2.890611442640554, c3 = 0.4570457994644658,
+                 d3 = 0.3731763325901154, e3 = 1.445305721320277;
+    Y[9] = -a3 * y * (3.0 * xx - yy);
+    Gx[9] = -6.0 * a3 * x * y; Gy[9] = -3.0 * a3 * (xx - yy);
+    Y[10] = b3 * x * y * z;
+    Gx[10] = b3 * y * z; Gy[10] = b3 * x * z; Gz[10] = b3 * x * y;
+    Y[11] = -c3 * y * (4.0 * zz - xx - yy);
+    Gx[11] = 2.0 * c3 * x * y; Gy[11] = -c3 * (4.0 * zz - xx - 3.0 * yy); Gz[11] = -8.0 * c3 * y * z;
+    Y[12] = d3 * z * (2.0 * zz - 3.0 * xx - 3.0 * yy);
+    Gx[12] = -6.0 * d3 * x * z; Gy[12] = -6.0 * d3 * y * z; Gz[12] = d3 * (6.0 * zz - 3.0 * xx - 3.0 * yy);
+    Y[13] = -c3 * x * (4.0 * zz - xx - yy);
+    Gx[13] = -c3 * (4.0 * zz - 3.0 * xx - yy); Gy[13] = 2.0 * c3 * x * y; Gz[13] = -8.0 * c3 * x * z;
+    Y[14] = e3 * z * (xx - yy);
+    Gx[14] = 2.0 * e3 * x * z; Gy[14] = -2.0 * e3 * y * z; Gz[14] = e3 * (xx - yy);
+    Y[15] = -a3 * x * (xx - 3.0 * yy);
+    Gx[15] = -3.0 * a3 * (xx - yy); Gy[15] = 6.0 * a3 * x * y;
+}
+
+__global__ __launch_bounds__(256) void k_project_bwd(int64_t N, int32_t v0, int32_t nv, CamBatch cams,
+                                                     potr_config cfg, const float* __restrict__ means,
+                                                     const float* __restrict__ scales,
+                                                     const float* __restrict__ quats, const float* __restrict__ opac,
+                                                     const float* __restrict__ sh, const float* __restrict__ grad2d,
+                                                     float* __restrict__ d_means, float* __restrict__ d_scales,
+                                                     float* __restrict__ d_quats, float* __restrict__ d_opac,
+                                                     float* __restrict__ d_sh) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    const double mx = means[3 * i], my = means[3 * i + 1], mz = means[3 * i + 2];
+    const double q0 = quats[4 * i], q1 = quats[4 * i + 1], q2 = quats[4 * i + 2], q3 = quats[4 * i + 3];
+    const double qn = sqrt(q0 * q0 + q1 * q1 + q2 * q2 + q3 * q3);
+    if (!(qn > 0.0)) return;
+    const double w = q0 / qn, x = q1 / qn, y = q2 / qn, z = q3 / qn;
+    const double M0[9] = {1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y),
+                          2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x),
+                          2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)};
+    const double s[3] = {scales[3 * i], scales[3 * i + 1], scales[3 * i + 2]};
+    double Mm[9], Sg[9];
+    for (int r = 0; r < 3; ++r)
+        for (int k = 0; k < 3; ++k) Mm[3 * r + k] = M0[3 * r + k] * s[k];
+    for (int a = 0; a < 3; ++a)
+        for (int b = a; b < 3; ++b) {
+            const double v = Mm[3 * a] * Mm[3 * b] + Mm[3 * a + 1] * Mm[3 * b + 1] + Mm[3 * a + 2] * Mm[3 * b + 2];
+            Sg[3 * a + b] = v;
+            Sg[3 * b + a] = v;
+        }
+    const int nsh = (cfg.sh_degree + 1) * (cfg.sh_degree + 1);
+    const float* shp = sh + 48 * i;
+
+    double gm[3] = {0, 0, 0}, gSig[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0}, go = 0.0;
+    float gsh[48];
+    for (int k = 0; k < 48; ++k) gsh[k] = 0.f;
+    bool touched = false;
+
+    for (int vv = 0; vv < nv; ++vv) {
+        const float* g2 = grad2d + ((int64_t)(v0 + vv) * N + i) * 9;
+        const double gu = g2[0], gv = g2[1], gA = g2[2], gB = g2[3], gC = g2[4], gO = g2[5];
+        const double gcol[3] = {g2[6], g2[7], g2[8]};
+        if (gu == 0.0 && gv == 0.0 && gA == 0.0 && gB == 0.0 && gC == 0.0 && gO == 0.0 && gcol[0] == 0.0 &&
+            gcol[1] == 0.0 && gcol[2] == 0.0)
+            continue;
+        touched = true;
+        const potr_camera& c = cams.c[vv];
+        double R[9];
+        for (int k = 0; k < 9; ++k) R[k] = c.R[k];
+        const double px = R[0] * mx + R[1] * my + R[2] * mz + (double)c.t[0];
+        const double py = R[3] * mx + R[4] * my + R[5] * mz + (double)c.t[1];
+        const double pz = R[6] * mx + R[7] * my + R[8] * mz + (double)c.t[2];
+        const double fx = c.fx, fy = c.fy;
+        const double limx = (double)cfg.jclamp * 0.5 * c.width / fx;
+        const double limy = (double)cfg.jclamp * 0.5 * c.height / fy;
+        const double rx = px / pz, ry = py / pz;
+        const bool freex = rx > -limx && rx < limx, freey = ry > -limy && ry < limy;
+        const double tx = fmin(limx, fmax(-limx, rx)), ty = fmin(limy, fmax(-limy, ry));
+        const double j00 = fx / pz, j02 = -fx * tx / pz, j11 = fy / pz, j12 = -fy * ty / pz;
+        const double T[6] = {j00 * R[0] + j02 * R[6], j00 * R[1] + j02 * R[7], j00 * R[2] + j02 * R[8],
+                             j11 * R[3] + j12 * R[6], j11 * R[4] + j12 * R[7], j11 * R[5] + j12 * R[8]};
+        double TS[6];
+        for (int a = 0; a < 2; ++a)
+            for (int b = 0; b < 3; ++b)
+                TS[3 * a + b] = T[3 * a] * Sg[b] + T[3 * a + 1] * Sg[3 + b] + T[3 * a + 2] * Sg[6 + b];
+        const double cxx = TS[0] * T[0] + TS[1] * T[1] + TS[2] * T[2] + (double)cfg.eps2d;
+        const double cxy = TS[0] * T[3] + TS[1] * T[4] + TS[2] * T[5];
+        const double cyy = TS[3] * T[3] + TS[4] * T[4] + TS[5] * T[5] + (double)cfg.eps2d;
+        const double det = cxx * cyy - cxy * cxy;
+        const double Qa = cyy / det, Qb = -cxy / det, Qc = cxx / det;
+        // conic -> cov2d: G_S = -Q G_Q Q, G_Q = [[gA, gB/2], [gB/2, gC]]
+        const double h00 = gA * Qa + 0.5 * gB * Qb, h01 = gA * Qb + 0.5 * gB * Qc;
+        const double h10 = 0.5 * gB * Qa + gC * Qb, h11 = 0.5 * gB * Qb + gC * Qc;
+        const double S00 = -(Qa * h00 + Qb * h10), S01 = -(Qa * h01 + Qb * h11);
+        const double S11 = -(Qb * h01 + Qc * h11);
+        // cov2d = T Sigma T^T: G_Sigma = T^T G_S T, G_T = 2 G_S T Sigma
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b)
+                gSig[3 * a + b] += T[a] * (S00 * T[b] + S01 * T[3 + b]) + T[3 + a] * (S01 * T[b] + S11 * T[3 + b]);
+        double GT[6];
+        for (int b = 0; b < 3; ++b) {
+            GT[b] = 2.0 * (S00 * TS[b] + S01 * TS[3 + b]);
+            GT[3 + b] = 2.0 * (S01 * TS[b] + S11 * TS[3 + b]);
+        }
+        // T = J R: G_J = G_T R^T (only the non-zero entries of J are needed)
+        const double gj00 = GT[0] * R[0] + GT[1] * R[1] + GT[2] * R[2];
+        const double gj02 = GT[0] * R[6] + GT[1] * R[7] + GT[2] * R[8];
+        const double gj11 = GT[3] * R[3] + GT[4] * R[4] + GT[5] * R[5];
+        const double gj12 = GT[3] * R[6] + GT[4] * R[7] + GT[5] * R[8];
+        const double iz2 = 1.0 / (pz * pz);
+        double gpx = 0.0, gpy = 0.0, gpz = 0.0;
+        gpz += -gj00 * fx * iz2 - gj11 * fy * iz2;
+        if (freex) gpx += -gj02 * fx * iz2;
+        gpz += gj02 * fx * tx * iz2 * (freex ? 2.0 : 1.0);
+        if (freey) gpy += -gj12 * fy * iz2;
+        gpz += gj12 * fy * ty * iz2 * (freey ? 2.0 : 1.0);
+        // pixel centre u = fx x/z + cx, v = fy y/z + cy
+        gpx += gu * fx / pz;
+        gpy += gv * fy / pz;
+        gpz += -(gu * fx * px + gv * fy * py) * iz2;
+        gm[0] += R[0] * gpx + R[3] * gpy + R[6] * gpz;
+        gm[1] += R[1] * gpx + R[4] * gpy + R[7] * gpz;
+        gm[2] += R[2] * gpx + R[5] * gpy + R[8] * gpz;
+        go += gO;
+        // colour along d = (mu - eye) / |mu - eye|, clamped at 0
+        const double ex = -(R[0] * c.t[0] + R[3] * c.t[1] + R[6] * c.t[2]);
+        const double ey = -(R[1] * c.t[0] + R[4] * c.t[1] + R[7] * c.t[2]);
+        const double ez = -(R[2] * c.t[0] + R[5] * c.t[1] + R[8] * c.t[2]);
+        double ux = mx - ex, uy = my - ey, uz = mz - ez;
+        const double un = sqrt(ux * ux + uy * uy + uz * uz);
+        const double dx = ux / un, dy = uy / un, dz = uz / un;
+        double Y[16], Gx[16], Gy[16], Gz[16];
+        sh_basis_grad(dx, dy, dz, cfg.sh_degree, Y, Gx, Gy, Gz);
+        double gdx = 0.0, gdy = 0.0, gdz = 0.0;
+        for (int ch = 0; ch < 3; ++ch) {
+            double pre = 0.5;
+            for (int k = 0; k < nsh; ++k) pre += (double)shp[3 * k + ch] * Y[k];
+            if (!(pre > 0.0) || gcol[ch] == 0.0) continue;
+            for (int k = 0; k < nsh; ++k) {
+                gsh[3 * k + ch] += (float)(gcol[ch] * Y[k]);
+                const double gy = gcol[ch] * (double)shp[3 * k + ch];
+                gdx += gy * Gx[k];
+                gdy += gy * Gy[k];
+                gdz += gy * Gz[k];
+            }
+        }
+        const double dot = gdx * dx + gdy * dy + gdz * dz;
+        gm[0] += (gdx - dx * dot) / un;
+        gm[1] += (gdy - dy * dot) / un;
+        gm[2] += (gdz - dz * dot) / un;
+    }
+    if (!touched) return;
+    // Sigma = M M^T with M = R(q) diag(s)
+    double GM[9];
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b)
+            GM[3 * a + b] = (gSig[3 * a] + gSig[a]) * Mm[b] + (gSig[3 * a + 1] + gSig[3 + a]) * Mm[3 + b] +
+                            (gSig[3 * a + 2] + gSig[6 + a]) * Mm[6 + b];
+    double GR[9];
+    double gs[3] = {0, 0, 0};
+    for (int r = 0; r < 3; ++r)
+        for (int k = 0; k < 3; ++k) {
+            gs[k] += GM[3 * r + k] * M0[3 * r + k];
+            GR[3 * r + k] = GM[3 * r + k] * s[k];
+        }
+    const double gw = 2 * (-z * GR[1] + y * GR[2] + z * GR[3] - x * GR[5] - y * GR[6] + x * GR[7]);
+    const double gx = 2 * (y * GR[1] + z * GR[2] + y * GR[3] - 2 * x * GR[4] - w * GR[5] + z * GR[6] + w * GR[7] -
+                           2 * x * GR[8]);
+    const double gy = 2 * (-2 * y * GR[0] + x * GR[1] + w * GR[2] + x * GR[3] + z * GR[5] - w * GR[6] + z * GR[7] -
+                           2 * y * GR[8]);
+    const double gz = 2 * (-2 * z * GR[0] - w * GR[1] + x * GR[2] + w * GR[3] - 2 * z * GR[4] + y * GR[5] +
+                           x * GR[6] + y * GR[7]);
+    const double dq = gw * w + gx * x + gy * y + gz * z;
+    d_means[3 * i] += (float)gm[0];
+    d_means[3 * i + 1] += (float)gm[1];
+    d_means[3 * i + 2] += (float)gm[2];
+    for (int k = 0; k < 3; ++k) d_scales[3 * i + k] += (float)gs[k];
+    d_quats[4 * i] += (float)((gw - w * dq) / qn);
+    d_quats[4 * i + 1] += (float)((gx - x * dq) / qn);
+    d_quats[4 * i + 2] += (float)((gy - y * dq) / qn);
+    d_quats[4 * i + 3] += (float)((gz - z * dq) / qn);
+    d_opac[i] += (float)go;
+    for (int k = 0; k < nsh * 3; ++k) d_sh[48 * i + k] += gsh[k];
+}
+
+__global__ void k_fill_f32(float* p, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0.f;
+}
+
+template <int TW, int TH>
+potr_status blend_bwd_shape(int64_t N, int32_t V, const potr_camera& c, const potr_config& cfg,
+                            const potr_proj* proj, const uint32_t* ids, const int32_t* ranges, const float* p_final,
+                            const float* t_final, const int32_t* n_walk, const float* dL, float* grad2d,
+                            hipStream_t s) {
+    const int txs = tiles_x(c, cfg), tpv = txs * tiles_y(c, cfg);
+    hipLaunchKernelGGL((k_blend_bwd<TW, TH>), dim3(tpv, V), dim3(TW * TH), 0, s, N, c.width, c.height, txs, tpv, cfg,
+                       proj, ids, ranges, p_final, t_final, n_walk, dL, grad2d);
+    return check_launch("k_blend_bwd");
+}
+
+}  // namespace
+
+potr_status launch_blend_backward(int64_t N, int32_t V, const potr_camera& c, const potr_config& cfg,
+                                  const potr_proj* proj, const uint32_t* ids, const int32_t* ranges,
+                                  const float* p_final, const float* t_final, const int32_t* n_walk, const float* dL,
+                                  float* grad2d, hipStream_t s) {
+    if (cfg.tile_w == 16 && cfg.tile_h == 16)
+        return blend_bwd_shape<16, 16>(N, V, c, cfg, proj, ids, ranges, p_final, t_final, n_walk, dL, grad2d, s);
+    if (cfg.tile_w == 8 && cfg.tile_h == 8)
+        return blend_bwd_shape<8, 8>(N, V, c, cfg, proj, ids, ranges, p_final, t_final, n_walk, dL, grad2d, s);
+    if (cfg.tile_w == 32 && cfg.tile_h == 8)
+        return blend_bwd_shape<32, 8>(N, V, c, cfg, proj, ids, ranges, p_final, t_final, n_walk, dL, grad2d, s);
+    return fail(POTR_EUNSUPPORTED, "tile %dx%d not built", cfg.tile_w, cfg.tile_h);
+}
+
+potr_status launch_project_backward(int64_t N, int32_t V, const potr_camera* cams, const potr_config& cfg,
+                                    const float* means, const float* scales, const float* quats, const float* opac,
+                                    const float* sh, const float* grad2d, float* d_means, float* d_scales,
+                                    float* d_quats, float* d_opac, float* d_sh, hipStream_t s) {
+    if (N == 0) return POTR_OK;
+    const dim3 grid((unsigned)ceil_div(N, 256));
+    for (int32_t v0 = 0; v0 < V; v0 += kViewsPerLaunch) {
+        const int32_t nv = V - v0 < kViewsPerLaunch ? V - v0 : kViewsPerLaunch;
+        CamBatch cb;
+        for (int k = 0; k < nv; ++k) cb.c[k] = cams[v0 + k];
+        for (int k = nv; k < kViewsPerLaunch; ++k) cb.c[k] = cams[v0];
+        hipLaunchKernelGGL(k_project_bwd, grid, dim3(256), 0, s, N, v0, nv, cb, cfg, means, scales, quats, opac, sh,
+                           grad2d, d_means, d_scales, d_quats, d_opac, d_sh);
+        potr_status st = check_launch("k_project_bwd");
+        if (st != POTR_OK) return st;
+    }
+    return POTR_OK;
+}
+
+potr_status launch_zero(float* p, int64_t n, hipStream_t s) {
+    if (n <= 0) return POTR_OK;
+    hipLaunchKernelGGL(k_fill_f32, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, s, p, n);
+    return check_launch("k_fill_f32");
+}
+
+}  // namespace potr

@@ -14,6 +14,8 @@
 // waves of the tile through LDS, and then added to the per-splat output with one
 // device atomic per (tile, splat) that has a nonzero sum.
 #include "common.h"
+#include "dpp.h"
+#include "raster_eval.h"
 
 namespace potr {
 namespace {
@@ -34,23 +36,6 @@ __device__ inline void stage_batch(const potr_proj* __restrict__ pv, const uint3
         s_c[j] = r2.x;
         if (s_id) s_id[j] = id;
     }
-}
-
-// alpha of a staged record at pixel centre (fx, fy), or 0 where the splat does
-// not count (q > q_max or o*exp(-q/2) < alpha_min). Blend and score both call
-// this, so they take the same decisions on the same FP32 values.
-__device__ inline float eval_alpha(const float4& a, const float4& b, float fx, float fy, float qmax, float amin,
-                                   float amax) {
-    const float dx = a.x - fx, dy = a.y - fy;
-    const float q = b.x * dx * dx + 2.f * a.w * dx * dy + b.y * dy * dy;
-    const float al0 = a.z * __expf(-0.5f * q);
-    return (q <= qmax && al0 >= amin) ? fminf(amax, al0) : 0.f;
-}
-
-__device__ inline float wave_sum(float x) {
-#pragma unroll
-    for (int m = 32; m >= 1; m >>= 1) x += __shfl_xor(x, m, 64);
-    return x;
 }
 
 template <int TW, int TH>
@@ -88,18 +73,18 @@ __global__ __launch_bounds__(TW * TH) void k_blend(int64_t N, int32_t W, int32_t
             for (int j = 0; j < cnt; ++j) {
                 const float4 a = s_a[j];
                 const float4 b = s_b[j];
-                const float al = eval_alpha(a, b, fx, fy, qmax, amin, amax);
+                const float al = alpha_of(eval_gauss(a, b, fx, fy), qmax, amin, amax);
                 if (al == 0.f) continue;
-                const float Tn = T * (1.f - al);
+                const float Tn = next_T(T, al);
                 if (Tn < tmin) {
                     done = true;
                     walk = base - beg + j;
                     break;
                 }
-                const float w = T * al;
-                cr += w * b.z;
-                cg += w * b.w;
-                cb += w * s_c[j];
+                const float w = __fmul_rn(T, al);
+                cr = add_weighted(cr, w, b.z);
+                cg = add_weighted(cg, w, b.w);
+                cb = add_weighted(cb, w, s_c[j]);
                 T = Tn;
                 ++blended;
             }
@@ -185,13 +170,13 @@ __global__ __launch_bounds__(TW * TH) void k_score(int64_t N, int32_t W, int32_t
             if (base + j < walk) {
                 const float4 a = s_a[j];
                 const float4 b = s_b[j];
-                const float al = eval_alpha(a, b, fx, fy, qmax, amin, amax);
+                const float al = alpha_of(eval_gauss(a, b, fx, fy), qmax, amin, amax);
                 if (al != 0.f) {
-                    const float w = T * al;
+                    const float w = __fmul_rn(T, al);
                     const float cr = b.z, cg = b.w, cbl = s_c[j];
-                    Pr += w * cr;
-                    Pg += w * cg;
-                    Pb += w * cbl;
+                    Pr = add_weighted(Pr, w, cr);
+                    Pg = add_weighted(Pg, w, cg);
+                    Pb = add_weighted(Pb, w, cbl);
                     const float k = al / (1.f - al);
                     const float dr = -w * cr + k * (PKr - Pr + Br);
                     const float dg = -w * cg + k * (PKg - Pg + Bg);
@@ -199,7 +184,7 @@ __global__ __launch_bounds__(TW * TH) void k_score(int64_t N, int32_t W, int32_t
                     l1 = fabsf(dr) + fabsf(dg) + fabsf(db);
                     se = dr * dr + dg * dg + db * db + 2.f * (dr * er + dg * eg + db * eb);
                     im = w;
-                    T *= (1.f - al);
+                    T = next_T(T, al);
                 }
             }
             if (want_l1) {

@@ -63,6 +63,16 @@ potr_status launch_score(int64_t N, int32_t V, const potr_camera& cam0, const po
                          const float* target, float* scores, float* scores_se, float* importance,
                          hipStream_t s);
 
+potr_status launch_blend_backward(int64_t N, int32_t V, const potr_camera& cam0, const potr_config& cfg,
+                                  const potr_proj* proj, const uint32_t* sorted_ids, const int32_t* tile_ranges,
+                                  const float* p_final, const float* t_final, const int32_t* n_walk,
+                                  const float* dL_dimage, float* grad2d, hipStream_t s);
+potr_status launch_project_backward(int64_t N, int32_t V, const potr_camera* cams, const potr_config& cfg,
+                                    const float* means, const float* scales, const float* quats, const float* opac,
+                                    const float* sh, const float* grad2d, float* d_means, float* d_scales,
+                                    float* d_quats, float* d_opac, float* d_sh, hipStream_t s);
+potr_status launch_zero(float* p, int64_t n, hipStream_t s);
+
 // ---- device-wide helpers (scan.hip) ----
 // Exclusive scan of n int32 counts into int64 offsets; `total` (device, may be
 // null) receives the sum. `tmp` needs scan_tmp_bytes(n).

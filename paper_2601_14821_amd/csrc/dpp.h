@@ -1,0 +1,28 @@
+// Cross-lane reductions for wave64 built from DPP row operations (VALU only,
+// no LDS traffic). Call with all 64 lanes of the wave active.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace potr {
+
+// value of another lane selected by a DPP control; rows outside ROW_MASK read 0
+template <int CTRL, int ROW_MASK = 0xf>
+__device__ inline float dpp_read(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROW_MASK, 0xf, ROW_MASK == 0xf));
+}
+
+// Sum over the 64 lanes, returned in every lane:
+// pairs (xor 1, xor 2) -> 8-lane mirror -> 16-lane mirror -> row 0 into row 1
+// and row 2 into row 3 -> rows 0..1 into rows 2..3; lane 63 then holds the total.
+__device__ inline float wave_sum(float v) {
+    v += dpp_read<0xB1>(v);        // quad_perm [1,0,3,2]
+    v += dpp_read<0x4E>(v);        // quad_perm [2,3,0,1]
+    v += dpp_read<0x141>(v);       // row_half_mirror
+    v += dpp_read<0x140>(v);       // row_mirror
+    v += dpp_read<0x142, 0xa>(v);  // row_bcast:15
+    v += dpp_read<0x143, 0xc>(v);  // row_bcast:31
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
+}
+
+}  // namespace potr

@@ -163,3 +163,35 @@ class Rasterizer:
             if keep_images:
                 images.append(vb.image.clone())
         return scores, importance, (torch.cat(images) if keep_images else None)
+
+    # -------------------------------------------------------------- backward
+    def backward(self, ds: DeviceScene, vb: ViewBatch, cams, dL_dimage: torch.Tensor, grads=None,
+                 grad2d: torch.Tensor | None = None) -> dict:
+        """Gradients (+=) of the splat parameters for dL/dimage [V,H,W,3] of the views in `vb`.
+        With `grad2d` given ([V*N*9] float32, zeroed by the caller) the screen-space
+        gradients are kept there and chained from it."""
+        N, V = vb.N, vb.V
+        if grads is None:
+            grads = {k: torch.zeros_like(getattr(ds, a)) for k, a in
+                     (("means", "means"), ("scales", "scales"), ("quats", "quats"), ("opacities", "opacities"),
+                      ("sh", "sh"))}
+        g = dL_dimage.contiguous()
+        cams_arr = L.make_cameras(cams)
+        if grad2d is None:
+            b = C.c_size_t(0)
+            L.call("potr_backward_workspace_size", N, V, C.byref(b))
+            ws = self._buf("bwd_ws", b.value)
+            L.call("potr_backward", N, V, cams_arr, C.byref(self.cfg), L.ptr(ds.means), L.ptr(ds.scales),
+                   L.ptr(ds.quats), L.ptr(ds.opacities), L.ptr(ds.sh), L.ptr(vb.proj), L.ptr(vb.sorted_ids),
+                   L.ptr(vb.tile_ranges), L.ptr(vb.p_final), L.ptr(vb.t_final), L.ptr(vb.n_walk), L.ptr(g),
+                   L.ptr(ws), ws.numel(), L.ptr(grads["means"]), L.ptr(grads["scales"]), L.ptr(grads["quats"]),
+                   L.ptr(grads["opacities"]), L.ptr(grads["sh"]), L.stream_handle())
+        else:
+            L.call("potr_blend_backward", N, V, cams_arr, C.byref(self.cfg), L.ptr(vb.proj), L.ptr(vb.sorted_ids),
+                   L.ptr(vb.tile_ranges), L.ptr(vb.p_final), L.ptr(vb.t_final), L.ptr(vb.n_walk), L.ptr(g),
+                   L.ptr(grad2d), L.stream_handle())
+            L.call("potr_project_backward", N, V, cams_arr, C.byref(self.cfg), L.ptr(ds.means), L.ptr(ds.scales),
+                   L.ptr(ds.quats), L.ptr(ds.opacities), L.ptr(ds.sh), L.ptr(grad2d), L.ptr(grads["means"]),
+                   L.ptr(grads["scales"]), L.ptr(grads["quats"]), L.ptr(grads["opacities"]), L.ptr(grads["sh"]),
+                   L.stream_handle())
+        return grads
