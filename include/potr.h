@@ -218,6 +218,76 @@ POTR_API potr_status potr_backward(int64_t N, int32_t V, const potr_camera* cams
                                    float* d_means, float* d_scales, float* d_quats, float* d_opac, float* d_sh,
                                    void* stream);
 
+/* ---------------------------------------------------------------------------
+ * potr_render_score -- potr_blend and potr_score fused in one launch per view
+ * batch: each tile is composited front to back and its walked prefix revisited
+ * for the removal effect, reusing the LDS-staged records. Same results as the
+ * two calls (same per-pixel arithmetic). image may be NULL; scores, importance,
+ * scores_se as in potr_score (+=; at least one non-NULL; scores_se needs target).
+ * ------------------------------------------------------------------------- */
+POTR_API potr_status potr_render_score(int64_t N, int32_t V, const potr_camera* cams, const potr_config* cfg,
+                                       const potr_proj* proj, const uint32_t* sorted_ids,
+                                       const int32_t* tile_ranges, float* image, const float* target,
+                                       float* scores, float* scores_se, float* importance, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * Batched scoring of many scenes and views of uneven sizes (the paper scores
+ * every training view of a model per pruning iteration, Sec. 4.3).
+ *
+ * A job is one scene and a run of its views (one image size per job). The
+ * batch runs project -> bin -> sort per job and then ONE persistent launch of
+ * the fused render + removal pass whose workgroups pull (view, tile) items of
+ * all jobs from a device counter until none is left. All of it can be
+ * recorded into one HIP graph and replayed.
+ *
+ * potr_batch_create: validates, copies the job table (cameras included) and
+ *   counts each job's tile pairs by projecting it once: this call synchronises
+ *   `stream` and uses temporary device memory. Pair capacity per job =
+ *   count * (1 + margin) + 1024.
+ * potr_batch_workspace_size / potr_batch_bind: the caller supplies one device
+ *   workspace; bind uploads the job table into it (synchronises).
+ * potr_batch_pairs: counted pairs and capacities per job (host arrays [n_jobs]).
+ * potr_batch_run: enqueues the whole batch; no allocation, no host sync, safe to
+ *   capture. Scores accumulate (+=) into each job's buffers.
+ * potr_batch_capture / potr_batch_replay: record potr_batch_run into a graph on
+ *   `stream` (not the null stream) / launch it.
+ * potr_batch_overflow: after a run, the number of jobs whose pairs exceeded
+ *   their capacity (synchronises). Such a job contributes nothing; re-create the
+ *   batch with a larger margin.
+ * Calls that share a batch must not overlap.
+ * ------------------------------------------------------------------------- */
+typedef struct potr_job {
+    int64_t N;
+    const float *means, *scales, *quats, *opac, *sh;  /* device, as for potr_project */
+    int32_t V;
+    const potr_camera* cams;                          /* host [V], copied at create */
+    float* scores;                                    /* device [N] += sum |PD|_1 */
+    float* importance;                                /* device [N] += sum T alpha, or NULL */
+} potr_job;
+
+typedef struct potr_batch_s* potr_batch;
+
+POTR_API potr_status potr_batch_create(const potr_job* jobs, int32_t n_jobs, const potr_config* cfg, float margin,
+                                       potr_batch* out, void* stream);
+POTR_API potr_status potr_batch_workspace_size(potr_batch b, size_t* bytes);
+POTR_API potr_status potr_batch_pairs(potr_batch b, int64_t* counted, int64_t* capacity);
+POTR_API potr_status potr_batch_bind(potr_batch b, void* ws, size_t ws_bytes, void* stream);
+POTR_API potr_status potr_batch_run(potr_batch b, void* stream);
+POTR_API potr_status potr_batch_capture(potr_batch b, void* stream);
+POTR_API potr_status potr_batch_replay(potr_batch b, void* stream);
+POTR_API potr_status potr_batch_overflow(potr_batch b, int32_t* n_overflowed, void* stream);
+POTR_API potr_status potr_batch_destroy(potr_batch b);
+
+/* potr_autotune: times every tile shape (16x16, 8x8, 32x8) with every LDS batch
+ * (64, 128, 256, 512) on the given jobs (`reps` timed runs each, after one
+ * warm-up) and writes the fastest tile_w, tile_h, lds_batch into *inout. Uses
+ * temporary device memory and scratch scores (the jobs' outputs are untouched);
+ * synchronises. Optional: best_ms, and the tried configs with their times
+ * (arrays of at least 12) and their count. */
+POTR_API potr_status potr_autotune(const potr_job* jobs, int32_t n_jobs, potr_config* inout, int32_t reps,
+                                   double* best_ms, potr_config* tried, double* tried_ms, int32_t* n_tried,
+                                   void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -37,7 +37,13 @@ class potr_config(C.Structure):
                 ("t_min", C.c_float), ("bg", C.c_float * 3), ("sh_degree", C.c_int32)]
 
 
-_CAM_P, _CFG_P = C.POINTER(potr_camera), C.POINTER(potr_config)
+class potr_job(C.Structure):
+    _fields_ = [("N", C.c_int64), ("means", C.c_void_p), ("scales", C.c_void_p), ("quats", C.c_void_p),
+                ("opac", C.c_void_p), ("sh", C.c_void_p), ("V", C.c_int32), ("cams", C.POINTER(potr_camera)),
+                ("scores", C.c_void_p), ("importance", C.c_void_p)]
+
+
+_CAM_P, _CFG_P, _JOB_P = C.POINTER(potr_camera), C.POINTER(potr_config), C.POINTER(potr_job)
 
 SIGNATURES = {
     "potr_abi_version": (_i32, []),
@@ -53,6 +59,18 @@ SIGNATURES = {
     "potr_project_backward": (_i32, [_i64, _i32, _CAM_P, _CFG_P] + [_vp] * 12),
     "potr_backward_workspace_size": (_i32, [_i64, _i32, C.POINTER(_sz)]),
     "potr_backward": (_i32, [_i64, _i32, _CAM_P, _CFG_P] + [_vp] * 13 + [_sz] + [_vp] * 6),
+    "potr_render_score": (_i32, [_i64, _i32, _CAM_P, _CFG_P] + [_vp] * 9),
+    "potr_batch_create": (_i32, [_JOB_P, _i32, _CFG_P, C.c_float, C.POINTER(_vp), _vp]),
+    "potr_batch_workspace_size": (_i32, [_vp, C.POINTER(_sz)]),
+    "potr_batch_pairs": (_i32, [_vp, C.POINTER(_i64), C.POINTER(_i64)]),
+    "potr_batch_bind": (_i32, [_vp, _vp, _sz, _vp]),
+    "potr_batch_run": (_i32, [_vp, _vp]),
+    "potr_batch_capture": (_i32, [_vp, _vp]),
+    "potr_batch_replay": (_i32, [_vp, _vp]),
+    "potr_batch_overflow": (_i32, [_vp, C.POINTER(_i32), _vp]),
+    "potr_batch_destroy": (_i32, [_vp]),
+    "potr_autotune": (_i32, [_JOB_P, _i32, _CFG_P, _i32, C.POINTER(C.c_double), _CFG_P, C.POINTER(C.c_double),
+                             C.POINTER(_i32), _vp]),
 }
 
 _lib = None

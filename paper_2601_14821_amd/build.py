@@ -20,7 +20,8 @@ LIB = os.path.join(HERE, "libpotr.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("POTR_ARCH", "gfx950")
 
-SOURCES = ["api.cpp", "project.hip", "scan.hip", "sort.hip", "blend.hip", "backward.hip"]
+SOURCES = ["api.cpp", "batch.cpp", "project.hip", "scan.hip", "sort.hip", "blend.hip", "backward.hip", "fused.hip",
+           "batch_kernels.hip"]
 
 FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-fPIC", "-std=c++17", "-Wall", "-fvisibility=hidden",

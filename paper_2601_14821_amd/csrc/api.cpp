@@ -8,6 +8,7 @@
 #include <cstring>
 
 #include "common.h"
+#include "fused.h"
 
 namespace potr {
 
@@ -223,6 +224,46 @@ potr_status potr_backward(int64_t N, int32_t V, const potr_camera* cams, const p
         st = potr_project_backward(N, V, cams, cfg, means, scales, quats, opac, sh, g2, d_means, d_scales, d_quats,
                                    d_opac, d_sh, stream);
     return st;
+}
+
+potr_status potr_render_score(int64_t N, int32_t V, const potr_camera* cams, const potr_config* cfg,
+                              const potr_proj* proj, const uint32_t* sorted_ids, const int32_t* tile_ranges,
+                              float* image, const float* target, float* scores, float* scores_se, float* importance,
+                              void* stream) {
+    potr_status st = check_cfg(cfg);
+    if (st == POTR_OK) st = check_cams(V, cams, cfg);
+    if (st != POTR_OK) return st;
+    if (N < 0) return fail(POTR_EINVAL, "N = %lld", (long long)N);
+    if (!tile_ranges || (N > 0 && (!proj || !sorted_ids))) return fail(POTR_EINVAL, "NULL buffer");
+    if (!image && !scores && !scores_se && !importance) return fail(POTR_EINVAL, "no output requested");
+    if (scores_se && !target) return fail(POTR_EINVAL, "scores_se needs a target image");
+    if (!aligned16(proj)) return fail(POTR_EINVAL, "proj must be 16-byte aligned");
+    const potr_camera& c = cams[0];
+    const int tx = tiles_x(c, *cfg), T = tx * tiles_y(c, *cfg);
+    const int64_t P = (int64_t)c.width * c.height;
+    for (int32_t v0 = 0; v0 < V; v0 += kViewsPerLaunch) {
+        const int32_t nv = V - v0 < kViewsPerLaunch ? V - v0 : kViewsPerLaunch;
+        ViewJobs jobs{};
+        for (int32_t k = 0; k < nv; ++k) {
+            ViewJob& j = jobs.j[k];
+            const int64_t v = v0 + k;
+            j.proj = proj + v * N;
+            j.ids = sorted_ids;
+            j.ranges = tile_ranges + v * T * 2;
+            j.W = c.width;
+            j.H = c.height;
+            j.tiles_x = tx;
+            j.tiles = T;
+            j.image = image ? image + v * P * 3 : nullptr;
+            j.target = target ? target + v * P * 3 : nullptr;
+            j.scores = N > 0 ? scores : nullptr;
+            j.importance = N > 0 ? importance : nullptr;
+            j.scores_se = N > 0 ? scores_se : nullptr;
+        }
+        st = launch_render_score(jobs, nv, T, *cfg, (hipStream_t)stream);
+        if (st != POTR_OK) return st;
+    }
+    return POTR_OK;
 }
 
 }  // extern "C"

@@ -1,0 +1,372 @@
+// Batched scoring of many scenes and views of uneven sizes: a native runtime
+// object that plans the buffers, enqueues project -> bin -> sort per job and one
+// persistent render + removal launch over every (view, tile) of every job, and
+// can record all of it into one HIP graph for replay.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "common.h"
+#include "fused.h"
+
+namespace potr {
+potr_status launch_count_pairs(int64_t N, int32_t V, const potr_camera* cams, const potr_config& cfg,
+                               const float* means, const float* scales, const float* quats, const float* opac,
+                               const float* sh, potr_proj* proj, int32_t* tt, int64_t* counts, hipStream_t s);
+potr_status launch_check_overflow(const int64_t* n_pairs, const int64_t* caps, int32_t n, int32_t* flag,
+                                  hipStream_t s);
+}  // namespace potr
+
+using namespace potr;
+
+struct potr_batch_s {
+    potr_config cfg;
+    std::vector<potr_job> jobs;
+    std::vector<std::vector<potr_camera>> cams;
+    std::vector<int64_t> capacity;       // pairs per job (all its views)
+    std::vector<int64_t> counted;        // pairs counted when planned
+    // workspace layout (byte offsets)
+    struct JobOff { size_t proj, ids, ranges; };
+    std::vector<JobOff> off;
+    size_t off_tt = 0, off_order = 0, off_pairs = 0, off_bin = 0, off_sort = 0;
+    size_t off_table = 0, off_prefix = 0, off_counter = 0, off_npairs = 0, off_caps = 0, off_flag = 0;
+    size_t bytes = 0;
+    int32_t n_view_jobs = 0;
+    int32_t grid = 0;
+    char* ws = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+namespace {
+
+int tiles_of(const potr_camera& c, const potr_config& g) { return tiles_x(c, g) * tiles_y(c, g); }
+
+potr_status hip_ok(hipError_t e, const char* what) {
+    if (e != hipSuccess) return fail(POTR_EHIP, "%s: %s", what, hipGetErrorString(e));
+    return POTR_OK;
+}
+
+void plan_layout(potr_batch_s* b) {
+    size_t o = 0;
+    auto take = [&](size_t n) { size_t r = o; o += align_up(n > 0 ? n : 1); return r; };
+    size_t max_tt = 0, max_bin = 0, max_pairs = 0, max_sort = 0;
+    b->off.resize(b->jobs.size());
+    b->n_view_jobs = 0;
+    for (size_t j = 0; j < b->jobs.size(); ++j) {
+        const potr_job& J = b->jobs[j];
+        const int T = tiles_of(b->cams[j][0], b->cfg);
+        b->off[j].proj = take((size_t)J.V * J.N * sizeof(potr_proj));
+        b->off[j].ids = take((size_t)b->capacity[j] * 4);
+        b->off[j].ranges = take((size_t)J.V * T * 2 * 4);
+        max_tt = std::max(max_tt, (size_t)J.V * J.N * 4);
+        max_bin = std::max(max_bin, bin_workspace_bytes(J.N, J.V));
+        max_pairs = std::max(max_pairs, (size_t)b->capacity[j] * 8);
+        max_sort = std::max(max_sort, sort_workspace_bytes(b->capacity[j], J.V, T));
+        b->n_view_jobs += J.V;
+    }
+    b->off_tt = take(max_tt);
+    b->off_order = take(max_tt);
+    b->off_pairs = take(max_pairs);
+    b->off_bin = take(max_bin);
+    b->off_sort = take(max_sort);
+    b->off_table = take((size_t)b->n_view_jobs * sizeof(ViewJob));
+    b->off_prefix = take((size_t)(b->n_view_jobs + 1) * 8);
+    b->off_counter = take(8);
+    b->off_npairs = take(b->jobs.size() * 8);
+    b->off_caps = take(b->jobs.size() * 8);
+    b->off_flag = take(4);
+    b->bytes = o;
+}
+
+potr_status validate_jobs(const potr_job* jobs, int32_t n_jobs, bool need_scores = true) {
+    if (!jobs || n_jobs < 1) return fail(POTR_EINVAL, "need at least one job");
+    for (int32_t j = 0; j < n_jobs; ++j) {
+        const potr_job& J = jobs[j];
+        if (J.N < 0 || J.V < 1 || J.N * (int64_t)J.V >= (int64_t(1) << 31) || !J.cams)
+            return fail(POTR_EINVAL, "job %d: bad N/V/cams", j);
+        if (J.N > 0 && (!J.means || !J.scales || !J.quats || !J.opac || !J.sh || (need_scores && !J.scores)))
+            return fail(POTR_EINVAL, "job %d: NULL buffer", j);
+    }
+    return POTR_OK;
+}
+
+// Project every job once and count its pairs (synchronises; temporary memory).
+potr_status count_jobs(const std::vector<potr_job>& jobs, const std::vector<std::vector<potr_camera>>& cams,
+                       const potr_config& cfg, std::vector<int64_t>& out, hipStream_t s) {
+    size_t need = 0;
+    for (auto& J : jobs) need = std::max(need, (size_t)J.V * J.N * (sizeof(potr_proj) + 4) + 64 * 8 + 512);
+    char* tmp = nullptr;
+    potr_status st = hip_ok(hipMalloc(&tmp, need), "hipMalloc (pair count)");
+    if (st != POTR_OK) return st;
+    std::vector<int64_t> counts;
+    out.assign(jobs.size(), 0);
+    for (size_t j = 0; j < jobs.size() && st == POTR_OK; ++j) {
+        const potr_job& J = jobs[j];
+        if (J.N == 0) continue;
+        potr_proj* proj = (potr_proj*)tmp;
+        int32_t* tt = (int32_t*)(tmp + align_up((size_t)J.V * J.N * sizeof(potr_proj)));
+        int64_t* cnt = (int64_t*)(tmp + align_up((size_t)J.V * J.N * sizeof(potr_proj)) +
+                                  align_up((size_t)J.V * J.N * 4));
+        for (int32_t v0 = 0; v0 < J.V && st == POTR_OK; v0 += 64) {
+            const int32_t nv = std::min(64, J.V - v0);
+            st = launch_count_pairs(J.N, nv, cams[j].data() + v0, cfg, J.means, J.scales, J.quats, J.opac, J.sh,
+                                    proj, tt, cnt, s);
+            if (st != POTR_OK) break;
+            counts.assign(nv, 0);
+            st = hip_ok(hipMemcpyAsync(counts.data(), cnt, nv * 8, hipMemcpyDeviceToHost, s), "copy counts");
+            if (st == POTR_OK) st = hip_ok(hipStreamSynchronize(s), "sync");
+            for (int32_t k = 0; k < nv; ++k) out[j] += counts[k];
+        }
+    }
+    hipFree(tmp);
+    return st;
+}
+
+}  // namespace
+
+extern "C" {
+
+potr_status potr_batch_create(const potr_job* jobs, int32_t n_jobs, const potr_config* cfg, float margin,
+                              potr_batch* out, void* stream) {
+    if (!out || !cfg) return fail(POTR_EINVAL, "NULL argument");
+    *out = nullptr;
+    potr_status st = validate_jobs(jobs, n_jobs);
+    if (st != POTR_OK) return st;
+    if (!(margin >= 0.f) || margin > 10.f) return fail(POTR_EINVAL, "margin %g not in [0, 10]", margin);
+    auto* b = new potr_batch_s();
+    b->cfg = *cfg;
+    for (int32_t j = 0; j < n_jobs; ++j) {
+        b->jobs.push_back(jobs[j]);
+        b->cams.emplace_back(jobs[j].cams, jobs[j].cams + jobs[j].V);
+        b->jobs.back().cams = nullptr;
+        for (int32_t v = 1; v < jobs[j].V; ++v)
+            if (jobs[j].cams[v].width != jobs[j].cams[0].width || jobs[j].cams[v].height != jobs[j].cams[0].height) {
+                delete b;
+                return fail(POTR_EINVAL, "job %d: all views of a job need the same size", j);
+            }
+    }
+    st = count_jobs(b->jobs, b->cams, b->cfg, b->counted, (hipStream_t)stream);
+    if (st != POTR_OK) {
+        delete b;
+        return st;
+    }
+    b->capacity.resize(n_jobs);
+    for (int32_t j = 0; j < n_jobs; ++j) {
+        const double c = std::ceil((double)b->counted[j] * (1.0 + margin)) + 1024.0;
+        if (c >= 2147483647.0) {
+            delete b;
+            return fail(POTR_EINVAL, "job %d: %lld pairs exceed one call's limit; split its views", j,
+                        (long long)b->counted[j]);
+        }
+        b->capacity[j] = (int64_t)c;
+    }
+    plan_layout(b);
+    b->grid = persistent_grid(b->cfg);
+    *out = b;
+    return POTR_OK;
+}
+
+potr_status potr_batch_workspace_size(potr_batch b, size_t* bytes) {
+    if (!b || !bytes) return fail(POTR_EINVAL, "NULL argument");
+    *bytes = b->bytes;
+    return POTR_OK;
+}
+
+potr_status potr_batch_pairs(potr_batch b, int64_t* counted, int64_t* capacity) {
+    if (!b) return fail(POTR_EINVAL, "NULL batch");
+    for (size_t j = 0; j < b->jobs.size(); ++j) {
+        if (counted) counted[j] = b->counted[j];
+        if (capacity) capacity[j] = b->capacity[j];
+    }
+    return POTR_OK;
+}
+
+potr_status potr_batch_bind(potr_batch b, void* ws, size_t ws_bytes, void* stream) {
+    if (!b || !ws) return fail(POTR_EINVAL, "NULL argument");
+    if (ws_bytes < b->bytes) return fail(POTR_ECAPACITY, "batch workspace %zu < %zu bytes", ws_bytes, b->bytes);
+    b->ws = (char*)ws;
+    std::vector<ViewJob> table;
+    std::vector<int64_t> prefix(1, 0);
+    for (size_t j = 0; j < b->jobs.size(); ++j) {
+        const potr_job& J = b->jobs[j];
+        const potr_camera& c0 = b->cams[j][0];
+        const int T = tiles_of(c0, b->cfg);
+        for (int32_t v = 0; v < J.V; ++v) {
+            ViewJob vj{};
+            vj.proj = (const potr_proj*)(b->ws + b->off[j].proj) + (int64_t)v * J.N;
+            vj.ids = (const uint32_t*)(b->ws + b->off[j].ids);
+            vj.ranges = (const int32_t*)(b->ws + b->off[j].ranges) + (int64_t)v * T * 2;
+            vj.W = c0.width;
+            vj.H = c0.height;
+            vj.tiles_x = tiles_x(c0, b->cfg);
+            vj.tiles = T;
+            vj.scores = J.scores;
+            vj.importance = J.importance;
+            table.push_back(vj);
+            prefix.push_back(prefix.back() + (J.N > 0 ? T : 0));
+        }
+    }
+    hipStream_t s = (hipStream_t)stream;
+    potr_status st = hip_ok(hipMemcpyAsync(b->ws + b->off_table, table.data(), table.size() * sizeof(ViewJob),
+                                           hipMemcpyHostToDevice, s), "upload job table");
+    if (st == POTR_OK)
+        st = hip_ok(hipMemcpyAsync(b->ws + b->off_prefix, prefix.data(), prefix.size() * 8, hipMemcpyHostToDevice, s),
+                    "upload prefix");
+    if (st == POTR_OK)
+        st = hip_ok(hipMemcpyAsync(b->ws + b->off_caps, b->capacity.data(), b->capacity.size() * 8,
+                                   hipMemcpyHostToDevice, s), "upload capacities");
+    if (st == POTR_OK) st = hip_ok(hipStreamSynchronize(s), "sync");
+    return st;
+}
+
+potr_status potr_batch_run(potr_batch b, void* stream) {
+    if (!b || !b->ws) return fail(POTR_EINVAL, "batch not bound to a workspace");
+    hipStream_t s = (hipStream_t)stream;
+    char* ws = b->ws;
+    int64_t* npairs = (int64_t*)(ws + b->off_npairs);
+    for (size_t j = 0; j < b->jobs.size(); ++j) {
+        const potr_job& J = b->jobs[j];
+        const potr_camera* cams = b->cams[j].data();
+        potr_proj* proj = (potr_proj*)(ws + b->off[j].proj);
+        int32_t* tt = (int32_t*)(ws + b->off_tt);
+        uint32_t* order = (uint32_t*)(ws + b->off_order);
+        uint64_t* pairs = (uint64_t*)(ws + b->off_pairs);
+        uint32_t* ids = (uint32_t*)(ws + b->off[j].ids);
+        int32_t* ranges = (int32_t*)(ws + b->off[j].ranges);
+        const int T = tiles_of(cams[0], b->cfg);
+        potr_status st = launch_project(J.N, J.V, cams, b->cfg, J.means, J.scales, J.quats, J.opac, J.sh, proj, tt, s);
+        if (st == POTR_OK)
+            st = launch_bin(J.N, J.V, cams[0], b->cfg, proj, tt, ws + b->off_bin, order, pairs, b->capacity[j],
+                            npairs + j, s);
+        if (st == POTR_OK)
+            st = launch_sort(J.N, J.V, T, npairs + j, b->capacity[j], pairs, order, ws + b->off_sort, ids, ranges, s);
+        if (st != POTR_OK) return st;
+    }
+    potr_status st = launch_render_score_persistent((const ViewJob*)(ws + b->off_table), b->n_view_jobs,
+                                                    (const int64_t*)(ws + b->off_prefix),
+                                                    (int64_t*)(ws + b->off_counter), b->grid, b->cfg, s);
+    if (st != POTR_OK) return st;
+    return launch_check_overflow(npairs, (const int64_t*)(ws + b->off_caps), (int32_t)b->jobs.size(),
+                                 (int32_t*)(ws + b->off_flag), s);
+}
+
+potr_status potr_batch_capture(potr_batch b, void* stream) {
+    if (!b || !b->ws) return fail(POTR_EINVAL, "batch not bound to a workspace");
+    if (!stream) return fail(POTR_EINVAL, "capture needs a stream other than the null stream");
+    hipStream_t s = (hipStream_t)stream;
+    if (b->exec) { hipGraphExecDestroy(b->exec); b->exec = nullptr; }
+    if (b->graph) { hipGraphDestroy(b->graph); b->graph = nullptr; }
+    potr_status st = hip_ok(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal), "begin capture");
+    if (st != POTR_OK) return st;
+    const potr_status run = potr_batch_run(b, stream);
+    hipGraph_t g = nullptr;
+    st = hip_ok(hipStreamEndCapture(s, &g), "end capture");
+    if (run != POTR_OK) {
+        if (g) hipGraphDestroy(g);
+        return run;
+    }
+    if (st != POTR_OK) return st;
+    b->graph = g;
+    return hip_ok(hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0), "graph instantiate");
+}
+
+potr_status potr_batch_replay(potr_batch b, void* stream) {
+    if (!b || !b->exec) return fail(POTR_EINVAL, "no captured graph");
+    return hip_ok(hipGraphLaunch(b->exec, (hipStream_t)stream), "graph launch");
+}
+
+potr_status potr_batch_overflow(potr_batch b, int32_t* n_overflowed, void* stream) {
+    if (!b || !b->ws || !n_overflowed) return fail(POTR_EINVAL, "NULL argument");
+    hipStream_t s = (hipStream_t)stream;
+    potr_status st = hip_ok(hipMemcpyAsync(n_overflowed, b->ws + b->off_flag, 4, hipMemcpyDeviceToHost, s), "copy");
+    if (st == POTR_OK) st = hip_ok(hipStreamSynchronize(s), "sync");
+    return st;
+}
+
+potr_status potr_batch_destroy(potr_batch b) {
+    if (!b) return POTR_OK;
+    if (b->exec) hipGraphExecDestroy(b->exec);
+    if (b->graph) hipGraphDestroy(b->graph);
+    delete b;
+    return POTR_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------- autotuner
+// Times every built tile shape with every LDS batch size on the given jobs and
+// writes the fastest into *inout. Each candidate plans its own batch (pair
+// counts depend on the tile shape) in temporary device memory; scores go to
+// scratch buffers, so the caller's outputs are untouched.
+extern "C" potr_status potr_autotune(const potr_job* jobs, int32_t n_jobs, potr_config* inout, int32_t reps,
+                                     double* best_ms, potr_config* tried, double* tried_ms, int32_t* n_tried,
+                                     void* stream) {
+    if (!inout) return fail(POTR_EINVAL, "NULL config");
+    potr_status st = validate_jobs(jobs, n_jobs, false);
+    if (st != POTR_OK) return st;
+    if (reps < 1) reps = 3;
+    hipStream_t s = (hipStream_t)stream;
+    std::vector<potr_job> scratch(jobs, jobs + n_jobs);
+    std::vector<float*> bufs;
+    for (auto& J : scratch) {
+        float* p = nullptr;
+        st = hip_ok(hipMalloc(&p, (size_t)(J.N > 0 ? J.N : 1) * 4), "hipMalloc (scratch scores)");
+        if (st != POTR_OK) break;
+        bufs.push_back(p);
+        J.scores = p;
+        J.importance = nullptr;
+    }
+    const int shapes[3][2] = {{16, 16}, {8, 8}, {32, 8}};
+    const int batches[4] = {64, 128, 256, 512};
+    double best = 1e300;
+    potr_config best_cfg = *inout;
+    int32_t k = 0;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (st == POTR_OK) st = hip_ok(hipEventCreate(&e0), "event");
+    if (st == POTR_OK) st = hip_ok(hipEventCreate(&e1), "event");
+    for (int sh = 0; sh < 3 && st == POTR_OK; ++sh) {
+        for (int bi = 0; bi < 4 && st == POTR_OK; ++bi) {
+            potr_config c = *inout;
+            c.tile_w = shapes[sh][0];
+            c.tile_h = shapes[sh][1];
+            c.lds_batch = batches[bi];
+            potr_batch b = nullptr;
+            st = potr_batch_create(scratch.data(), n_jobs, &c, 0.05f, &b, stream);
+            if (st != POTR_OK) break;
+            char* ws = nullptr;
+            st = hip_ok(hipMalloc(&ws, b->bytes), "hipMalloc (autotune workspace)");
+            if (st == POTR_OK) st = potr_batch_bind(b, ws, b->bytes, stream);
+            if (st == POTR_OK) st = potr_batch_run(b, stream);       // warm-up
+            float ms = 0.f;
+            if (st == POTR_OK) st = hip_ok(hipEventRecord(e0, s), "event record");
+            for (int r = 0; r < reps && st == POTR_OK; ++r) st = potr_batch_run(b, stream);
+            if (st == POTR_OK) st = hip_ok(hipEventRecord(e1, s), "event record");
+            if (st == POTR_OK) st = hip_ok(hipEventSynchronize(e1), "event sync");
+            if (st == POTR_OK) st = hip_ok(hipEventElapsedTime(&ms, e0, e1), "elapsed");
+            if (ws) hipFree(ws);
+            potr_batch_destroy(b);
+            if (st != POTR_OK) break;
+            const double per = ms / reps;
+            if (tried) tried[k] = c;
+            if (tried_ms) tried_ms[k] = per;
+            ++k;
+            if (per < best) {
+                best = per;
+                best_cfg = c;
+            }
+        }
+    }
+    if (e0) hipEventDestroy(e0);
+    if (e1) hipEventDestroy(e1);
+    for (float* p : bufs) hipFree(p);
+    if (n_tried) *n_tried = k;
+    if (st != POTR_OK) return st;
+    inout->tile_w = best_cfg.tile_w;
+    inout->tile_h = best_cfg.tile_h;
+    inout->lds_batch = best_cfg.lds_batch;
+    if (best_ms) *best_ms = best;
+    return POTR_OK;
+}

@@ -1,0 +1,290 @@
+// Fused forward render + removal pass per tile (paper Sec. 3 compositing and
+// Sec. 4.2 pruning difference), in two launch forms:
+//   k_render_score            one workgroup per (tile, view) of one call
+//   k_render_score_persistent a fixed grid of workgroups that pull (view, tile)
+//                             items of many scenes and views from a device
+//                             counter until the queue is empty
+// Per tile: a blend sweep front to back with early stop gives each pixel's P_K,
+// T_final and stop position; the removal sweep then revisits the walked prefix.
+// When that prefix fits one LDS batch (the usual case: ~100-200 walked entries
+// per tile), the records staged for the blend are reused without a second
+// gather. The arithmetic per (pixel, splat) is that of potr_blend / potr_score
+// (raster_eval.h), so the results are the same.
+#include "common.h"
+#include "dpp.h"
+#include "fused.h"
+#include "raster_eval.h"
+
+namespace potr {
+namespace {
+
+struct Smem {
+    float4* a;
+    float4* b;
+    float* c;
+    uint32_t* id;
+    float* part;       // [n_out][NW][B]
+    int* misc;         // [0]: wmax, [1]: next item
+};
+
+template <int NT>
+__device__ inline void stage(const potr_proj* __restrict__ pv, const uint32_t* __restrict__ ids, int base, int cnt,
+                             const Smem& sm) {
+    for (int j = threadIdx.x; j < cnt; j += NT) {
+        const uint32_t id = ids[base + j];
+        const float4* src = reinterpret_cast<const float4*>(pv + id);
+        const float4 r0 = src[0], r1 = src[1], r2 = src[2];
+        sm.a[j] = make_float4(r0.x, r0.y, r1.y, r0.w);
+        sm.b[j] = make_float4(r0.z, r1.x, r1.z, r1.w);
+        sm.c[j] = r2.x;
+        sm.id[j] = id;
+    }
+}
+
+template <int TW, int TH>
+__device__ void render_score_tile(const ViewJob& J, int tile, const potr_config& cfg, const Smem& sm) {
+    constexpr int NT = TW * TH;
+    constexpr int NW = (NT + 63) / 64;
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const int px = (tile % J.tiles_x) * TW + (int)(threadIdx.x % TW);
+    const int py = (tile / J.tiles_x) * TH + (int)(threadIdx.x / TW);
+    const bool inside = px < J.W && py < J.H;
+    const float fx = (float)px + 0.5f, fy = (float)py + 0.5f;
+    const int beg = J.ranges[2 * tile], end = J.ranges[2 * tile + 1];
+    const int B = cfg.lds_batch;
+    const float qmax = cfg.q_max, amin = cfg.alpha_min, amax = cfg.alpha_max, tmin = cfg.t_min;
+    const int n_out = (J.scores ? 1 : 0) + (J.importance ? 1 : 0) + (J.scores_se ? 1 : 0);
+    const int o_l1 = 0, o_im = J.scores ? 1 : 0, o_se = o_im + (J.importance ? 1 : 0);
+
+    // ---- blend sweep
+    float T = 1.f, cr = 0.f, cg = 0.f, cb = 0.f;
+    bool done = !inside;
+    int walk = 0;
+    int staged = -1;   // list offset of the batch now in LDS
+    for (int base = beg; base < end; base += B) {
+        if (__syncthreads_count(!done) == 0) break;
+        const int cnt = min(B, end - base);
+        stage<NT>(J.proj, J.ids, base, cnt, sm);
+        staged = base;
+        __syncthreads();
+        if (!done) {
+            for (int j = 0; j < cnt; ++j) {
+                const float al = alpha_of(eval_gauss(sm.a[j], sm.b[j], fx, fy), qmax, amin, amax);
+                if (al == 0.f) continue;
+                const float Tn = next_T(T, al);
+                if (Tn < tmin) {
+                    done = true;
+                    walk = base - beg + j;
+                    break;
+                }
+                const float w = __fmul_rn(T, al);
+                cr = add_weighted(cr, w, sm.b[j].z);
+                cg = add_weighted(cg, w, sm.b[j].w);
+                cb = add_weighted(cb, w, sm.c[j]);
+                T = Tn;
+            }
+        }
+    }
+    if (inside && !done) walk = end - beg;
+    const float TF = T, PKr = cr, PKg = cg, PKb = cb;
+    const float Br = TF * cfg.bg[0], Bg = TF * cfg.bg[1], Bb = TF * cfg.bg[2];
+    float er = 0.f, eg = 0.f, eb = 0.f;
+    if (inside) {
+        const int64_t pix = (int64_t)py * J.W + px;
+        if (J.image) {
+            J.image[3 * pix] = cr + TF * cfg.bg[0];
+            J.image[3 * pix + 1] = cg + TF * cfg.bg[1];
+            J.image[3 * pix + 2] = cb + TF * cfg.bg[2];
+        }
+        if (J.scores_se) {
+            er = cr + TF * cfg.bg[0] - J.target[3 * pix];
+            eg = cg + TF * cfg.bg[1] - J.target[3 * pix + 1];
+            eb = cb + TF * cfg.bg[2] - J.target[3 * pix + 2];
+        }
+    }
+    if (n_out == 0) {
+        __syncthreads();
+        return;
+    }
+
+    // ---- removal sweep over the walked prefix
+    if (threadIdx.x == 0) sm.misc[0] = 0;
+    __syncthreads();
+    if (walk > 0) atomicMax(&sm.misc[0], walk);
+    __syncthreads();
+    const int wmax = sm.misc[0];
+    T = 1.f;
+    float Pr = 0.f, Pg = 0.f, Pb = 0.f;
+    for (int base = 0; base < wmax; base += B) {
+        const int cnt = min(B, wmax - base);
+        if (staged != beg + base) {
+            __syncthreads();
+            stage<NT>(J.proj, J.ids, beg + base, cnt, sm);
+            staged = beg + base;
+            __syncthreads();
+        }
+        for (int j = 0; j < cnt; ++j) {
+            float l1 = 0.f, se = 0.f, im = 0.f;
+            if (base + j < walk) {
+                const float4 b = sm.b[j];
+                const float al = alpha_of(eval_gauss(sm.a[j], b, fx, fy), qmax, amin, amax);
+                if (al != 0.f) {
+                    const float w = __fmul_rn(T, al);
+                    const float c0 = b.z, c1 = b.w, c2 = sm.c[j];
+                    Pr = add_weighted(Pr, w, c0);
+                    Pg = add_weighted(Pg, w, c1);
+                    Pb = add_weighted(Pb, w, c2);
+                    const float k = al / (1.f - al);
+                    const float dr = -w * c0 + k * (PKr - Pr + Br);
+                    const float dg = -w * c1 + k * (PKg - Pg + Bg);
+                    const float db = -w * c2 + k * (PKb - Pb + Bb);
+                    l1 = fabsf(dr) + fabsf(dg) + fabsf(db);
+                    se = dr * dr + dg * dg + db * db + 2.f * (dr * er + dg * eg + db * eb);
+                    im = w;
+                    T = next_T(T, al);
+                }
+            }
+            const bool any = __ballot(l1 != 0.f || im != 0.f) != 0;
+            if (J.scores) {
+                const float s = any ? wave_sum(l1) : 0.f;
+                if (lane == 0) sm.part[(o_l1 * NW + wid) * B + j] = s;
+            }
+            if (J.importance) {
+                const float s = any ? wave_sum(im) : 0.f;
+                if (lane == 0) sm.part[(o_im * NW + wid) * B + j] = s;
+            }
+            if (J.scores_se) {
+                const float s = any ? wave_sum(se) : 0.f;
+                if (lane == 0) sm.part[(o_se * NW + wid) * B + j] = s;
+            }
+        }
+        __syncthreads();
+        for (int j = threadIdx.x; j < cnt; j += NT) {
+            const uint32_t id = sm.id[j];
+            float t[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+            for (int o = 0; o < 3; ++o)
+                if (o < n_out)
+#pragma unroll
+                    for (int w = 0; w < NW; ++w) t[o] += sm.part[(o * NW + w) * B + j];
+            if (J.scores && t[o_l1] != 0.f) unsafeAtomicAdd(J.scores + id, t[o_l1]);
+            if (J.importance && t[o_im] != 0.f) unsafeAtomicAdd(J.importance + id, t[o_im]);
+            if (J.scores_se && t[o_se] != 0.f) unsafeAtomicAdd(J.scores_se + id, t[o_se]);
+        }
+    }
+    __syncthreads();
+}
+
+template <int TW, int TH>
+__device__ inline Smem carve(char* base, int B) {
+    constexpr int NW = (TW * TH + 63) / 64;
+    Smem s;
+    s.a = reinterpret_cast<float4*>(base);
+    s.b = s.a + B;
+    s.c = reinterpret_cast<float*>(s.b + B);
+    s.id = reinterpret_cast<uint32_t*>(s.c + B);
+    s.part = reinterpret_cast<float*>(s.id + B);
+    s.misc = reinterpret_cast<int*>(s.part + 3 * NW * B);
+    return s;
+}
+
+template <int TW, int TH>
+__global__ __launch_bounds__(TW * TH) void k_render_score(ViewJobs jobs, potr_config cfg) {
+    extern __shared__ __align__(16) char smem[];
+    const Smem sm = carve<TW, TH>(smem, cfg.lds_batch);
+    const ViewJob J = jobs.j[blockIdx.y];
+    render_score_tile<TW, TH>(J, blockIdx.x, cfg, sm);
+}
+
+// Persistent form: items are (view job, tile) pairs numbered job-major;
+// item_prefix[j] is the first item of job j (item_prefix[n_jobs] = total).
+template <int TW, int TH>
+__global__ __launch_bounds__(TW * TH) void k_render_score_persistent(const ViewJob* __restrict__ jobs, int32_t n_jobs,
+                                                                     const int64_t* __restrict__ item_prefix,
+                                                                     int64_t* __restrict__ counter, potr_config cfg) {
+    extern __shared__ __align__(16) char smem[];
+    const Smem sm = carve<TW, TH>(smem, cfg.lds_batch);
+    const int64_t total = item_prefix[n_jobs];
+    for (;;) {
+        if (threadIdx.x == 0) sm.misc[1] = (int)atomicAdd((unsigned long long*)counter, 1ull);
+        __syncthreads();
+        const int64_t item = sm.misc[1];
+        __syncthreads();
+        if (item >= total) break;
+        int lo = 0, hi = n_jobs - 1;      // last job with item_prefix[j] <= item
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (item_prefix[mid] <= item) lo = mid;
+            else hi = mid - 1;
+        }
+        const ViewJob J = jobs[lo];
+        render_score_tile<TW, TH>(J, (int)(item - item_prefix[lo]), cfg, sm);
+    }
+}
+
+__global__ void k_zero_i64(int64_t* p) { *p = 0; }
+
+template <int TW, int TH>
+size_t smem_bytes(int B) {
+    constexpr int NW = (TW * TH + 63) / 64;
+    return (size_t)B * (16 + 16 + 4 + 4) + (size_t)3 * NW * B * 4 + 16;
+}
+
+}  // namespace
+
+size_t fused_smem_bytes(const potr_config& cfg) {
+    if (cfg.tile_w == 8) return smem_bytes<8, 8>(cfg.lds_batch);
+    if (cfg.tile_w == 32) return smem_bytes<32, 8>(cfg.lds_batch);
+    return smem_bytes<16, 16>(cfg.lds_batch);
+}
+
+potr_status launch_render_score(const ViewJobs& jobs_dev, int32_t n_views, int32_t tiles_per_view,
+                                const potr_config& cfg, hipStream_t s) {
+    const size_t sm = fused_smem_bytes(cfg);
+    const dim3 grid(tiles_per_view, n_views);
+    if (cfg.tile_w == 16 && cfg.tile_h == 16)
+        hipLaunchKernelGGL((k_render_score<16, 16>), grid, dim3(256), sm, s, jobs_dev, cfg);
+    else if (cfg.tile_w == 8 && cfg.tile_h == 8)
+        hipLaunchKernelGGL((k_render_score<8, 8>), grid, dim3(64), sm, s, jobs_dev, cfg);
+    else if (cfg.tile_w == 32 && cfg.tile_h == 8)
+        hipLaunchKernelGGL((k_render_score<32, 8>), grid, dim3(256), sm, s, jobs_dev, cfg);
+    else
+        return fail(POTR_EUNSUPPORTED, "tile %dx%d not built", cfg.tile_w, cfg.tile_h);
+    return check_launch("k_render_score");
+}
+
+int persistent_grid(const potr_config& cfg) {
+    int dev = 0, cus = 256;
+    if (hipGetDevice(&dev) == hipSuccess) hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    const int threads = cfg.tile_w * cfg.tile_h;
+    const size_t sm = fused_smem_bytes(cfg);
+    int by_waves = 32 / ((threads + 63) / 64);              // 32 waves per CU
+    int by_lds = (int)((160 * 1024) / (sm + 256));
+    int per_cu = by_waves < by_lds ? by_waves : by_lds;
+    if (per_cu < 1) per_cu = 1;
+    return cus * per_cu;
+}
+
+potr_status launch_render_score_persistent(const ViewJob* jobs_dev, int32_t n_jobs, const int64_t* item_prefix_dev,
+                                           int64_t* counter_dev, int32_t grid_size, const potr_config& cfg,
+                                           hipStream_t s) {
+    hipLaunchKernelGGL(k_zero_i64, dim3(1), dim3(1), 0, s, counter_dev);
+    potr_status st = check_launch("k_zero_i64");
+    if (st != POTR_OK) return st;
+    const size_t sm = fused_smem_bytes(cfg);
+    const dim3 grid(grid_size);
+    if (cfg.tile_w == 16 && cfg.tile_h == 16)
+        hipLaunchKernelGGL((k_render_score_persistent<16, 16>), grid, dim3(256), sm, s, jobs_dev, n_jobs,
+                           item_prefix_dev, counter_dev, cfg);
+    else if (cfg.tile_w == 8 && cfg.tile_h == 8)
+        hipLaunchKernelGGL((k_render_score_persistent<8, 8>), grid, dim3(64), sm, s, jobs_dev, n_jobs,
+                           item_prefix_dev, counter_dev, cfg);
+    else if (cfg.tile_w == 32 && cfg.tile_h == 8)
+        hipLaunchKernelGGL((k_render_score_persistent<32, 8>), grid, dim3(256), sm, s, jobs_dev, n_jobs,
+                           item_prefix_dev, counter_dev, cfg);
+    else
+        return fail(POTR_EUNSUPPORTED, "tile %dx%d not built", cfg.tile_w, cfg.tile_h);
+    return check_launch("k_render_score_persistent");
+}
+
+}  // namespace potr

@@ -195,3 +195,23 @@ class Rasterizer:
                    L.ptr(grads["scales"]), L.ptr(grads["quats"]), L.ptr(grads["opacities"]), L.ptr(grads["sh"]),
                    L.stream_handle())
         return grads
+
+    # -------------------------------------------------------------- fused forward + removal
+    def render_score(self, vb: ViewBatch, cams, scores=None, importance=None, image=None, scores_se=None,
+                     target=None) -> None:
+        """potr_render_score: composite and score the views of `vb` in one launch."""
+        L.call("potr_render_score", vb.N, vb.V, L.make_cameras(cams), C.byref(self.cfg), L.ptr(vb.proj),
+               L.ptr(vb.sorted_ids), L.ptr(vb.tile_ranges), L.ptr(image), L.ptr(target), L.ptr(scores),
+               L.ptr(scores_se), L.ptr(importance), L.stream_handle())
+
+    def score_views_fused(self, ds: DeviceScene, cams, views_per_batch: int = 8, scores=None, importance=None):
+        """Removal scores over all views with the fused launch (no per-pixel buffers)."""
+        if scores is None:
+            scores = torch.zeros(ds.n, dtype=torch.float32, device=self.device)
+        for v0 in range(0, len(cams), views_per_batch):
+            cb = cams[v0:v0 + views_per_batch]
+            vb = self.project(ds, cb)
+            self.bin(vb, cb)
+            self.sort(vb, cb)
+            self.render_score(vb, cb, scores=scores, importance=importance)
+        return scores

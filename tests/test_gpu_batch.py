@@ -1,0 +1,144 @@
+"""Fused and batched scoring (through the C ABI): the fused launch equals the
+separate blend + score calls, the persistent multi-scene batch equals the
+plain per-view path (and the oracle), graph replays equal eager runs, capacity
+overflow is reported, and the autotuner only chooses among result-neutral
+settings."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2601_14821_amd import batch, raster, synth
+
+pytestmark = pytest.mark.gpu
+
+
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a GPU")
+
+
+def _uneven_scenes(scale=1.0):
+    """Three scenes of uneven size, view count and resolution."""
+    out = []
+    for k, (n, v, wh) in enumerate(((3000, 2, (160, 120)), (20000, 5, (320, 180)), (60000, 3, (200, 133)))):
+        scene = synth.random_scene(int(n * scale), 700 + k, clustered=True)
+        cams = synth.hemisphere_cameras(v, wh[0], wh[1], seed=800 + k)
+        out.append((scene, cams))
+    return out
+
+
+def _close(a, b, rel=2e-5):
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    assert np.abs(a - b).max() <= rel * np.abs(b).max() + 1e-7, np.abs(a - b).max()
+    assert np.abs(a - b).sum() <= rel * np.abs(b).sum() + 1e-7
+
+
+@pytest.mark.parametrize("settings", [synth.RenderSettings(), synth.RenderSettings(tile_w=8, tile_h=8, lds_batch=64),
+                                      synth.RenderSettings(tile_w=32, tile_h=8, lds_batch=512, t_min=0.0)])
+def test_fused_equals_blend_then_score(settings):
+    _need_gpu()
+    scene, cams = synth.workload_small()
+    ds = raster.to_device(scene)
+    rz = raster.Rasterizer(settings)
+    vb = rz.render_views(ds, cams)
+    ref_img = vb.image.clone()
+    s1 = torch.zeros(scene.n, device="cuda")
+    i1 = torch.zeros(scene.n, device="cuda")
+    rz.score(vb, cams, scores=s1, importance=i1)
+    s2 = torch.zeros(scene.n, device="cuda")
+    i2 = torch.zeros(scene.n, device="cuda")
+    img = torch.zeros_like(ref_img)
+    rz.render_score(vb, cams, scores=s2, importance=i2, image=img)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(img.cpu().numpy(), ref_img.cpu().numpy())
+    _close(s2.cpu().numpy(), s1.cpu().numpy())
+    _close(i2.cpu().numpy(), i1.cpu().numpy())
+
+
+def _plain_scores(scene, cams, s):
+    ds = raster.to_device(scene)
+    sc = torch.zeros(scene.n, device="cuda")
+    raster.Rasterizer(s).score_views(ds, cams, scores=sc)
+    return sc.cpu().numpy()
+
+
+def test_batched_persistent_equals_plain_and_oracle():
+    _need_gpu()
+    s = synth.RenderSettings()
+    scenes = _uneven_scenes()
+    devs = [(raster.to_device(sc), cams, torch.zeros(sc.n, device="cuda")) for sc, cams in scenes]
+    bs = batch.BatchScorer(devs, s, views_per_job=2)
+    assert bs.n_jobs == 1 + 3 + 2
+    bs.run()
+    torch.cuda.synchronize()
+    assert bs.overflowed() == 0
+    counted, caps = bs.pairs()
+    assert all(c <= k for c, k in zip(counted, caps))
+    for (scene, cams), (_, _, sc) in zip(scenes, devs):
+        _close(sc.cpu().numpy(), _plain_scores(scene, cams, s))
+    # oracle on the smallest scene, all views
+    scene, cams = scenes[0]
+    tot = sum(oracle.render(scene, c, s, record_f32=True, want=("score_l1",))["score_l1"] for c in cams)
+    got = devs[0][2].cpu().numpy()
+    assert np.abs(got - tot).sum() <= 1e-4 * tot.sum()
+
+
+def test_graph_replay_equals_eager():
+    _need_gpu()
+    s = synth.RenderSettings()
+    scenes = _uneven_scenes(scale=0.5)
+    devs = [(raster.to_device(sc), cams, torch.zeros(sc.n, device="cuda"), torch.zeros(sc.n, device="cuda"))
+            for sc, cams in scenes]
+    bs = batch.BatchScorer(devs, s, views_per_job=3)
+    bs.run()
+    torch.cuda.synchronize()
+    eager = [(d[2].cpu().numpy().copy(), d[3].cpu().numpy().copy()) for d in devs]
+    bs.capture()
+    torch.cuda.synchronize()
+    for rep in range(3):
+        for d in devs:            # eager work between replays
+            d[2].zero_()
+            d[3].zero_()
+        torch.cuda.synchronize()
+        bs.replay()
+        torch.cuda.synchronize()
+        for d, (e_s, e_i) in zip(devs, eager):
+            _close(d[2].cpu().numpy(), e_s)
+            _close(d[3].cpu().numpy(), e_i)
+    assert bs.overflowed() == 0
+
+
+def test_overflow_is_reported_and_contained():
+    """Plan on one scene, then grow every splat in place: the run overflows the
+    planned capacity, reports it, and the overflowed job contributes nothing."""
+    _need_gpu()
+    s = synth.RenderSettings()
+    scene, cams = synth.workload_small()
+    ds = raster.to_device(scene)
+    sc = torch.zeros(scene.n, device="cuda")
+    bs = batch.BatchScorer([(ds, cams, sc)], s, views_per_job=4, margin=0.0)
+    bs.run()
+    assert bs.overflowed() == 0
+    ds.scales.mul_(4.0)            # many more tiles per splat than planned
+    sc.zero_()
+    bs.run()
+    assert bs.overflowed() == 1
+    assert float(sc.abs().sum()) == 0.0
+
+
+def test_autotune_chooses_among_equivalent_settings(tmp_path):
+    _need_gpu()
+    s = synth.RenderSettings()
+    scenes = _uneven_scenes(scale=0.3)
+    devs = [(raster.to_device(sc), cams) for sc, cams in scenes]
+    cache = str(tmp_path / "tune.json")
+    tuned, info = batch.autotune(devs, s, reps=1, cache_path=cache)
+    assert len(info["tried"]) == 12
+    assert (tuned.tile_w, tuned.tile_h) in ((16, 16), (8, 8), (32, 8))
+    assert tuned.lds_batch in (64, 128, 256, 512)
+    again, info2 = batch.autotune(devs, s, reps=1, cache_path=cache)     # from the cache
+    assert (again.tile_w, again.tile_h, again.lds_batch) == (tuned.tile_w, tuned.tile_h, tuned.lds_batch)
+    scene, cams = scenes[1]
+    _close(_plain_scores(scene, cams, tuned), _plain_scores(scene, cams, s))
