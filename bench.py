@@ -1,21 +1,27 @@
 #!/usr/bin/env python3
 """Benchmark of the removal-effect scoring path on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--main-only]
 
-One step = one pass of the whole path over one view of the single-view
-workload (500,000 clustered splats, one 1280x720 view): zero the scores,
-project, bin, sort, blend, score. Inputs are resident in HBM before the timed
-region. Prints one JSON line.
+Main line (the `value`): one step = one pass of the whole path over the
+single-view workload (500,000 clustered splats, one 1280x720 view): zero the
+scores, project, bin, sort, and the fused composite + removal pass, as plain
+per-view launches. Inputs are resident in HBM before the timed region.
 
-The roofline entry is for the kernel that takes the most time; its duration is
-measured with HIP events on the stream the library launches on, around the one
-library call that launches only that kernel. Algorithmic work per launch:
-  k_score: 13 flops per visited (pixel, list entry) + 30 per blended one
-  k_blend: 13 flops per visited + 12 per blended
-  k_project: 288 bytes per splat-view (236 read, 52 written)
-The CPU baseline is the FP64 oracle on the same view (project, tile lists,
-compositing and removal scores), timed on the host.
+Also reported (extra fields):
+  batched: 3M clustered splats x 16 of the 200 hemisphere views at 1600x1064,
+           plain per-view launches vs one HIP-graph replay of the batched
+           persistent scorer (ms per view, Gsplat.views/s);
+  fwd_bwd: 1M splats x 4 views at 1280x720, forward + L1 loss gradient +
+           hand-written backward, ms per view.
+
+Roofline: the kernel that takes the most time in the main line, timed with HIP
+events on the library's stream around the one call that launches only it.
+Algorithmic work per launch:
+  k_render_score: 26 flops per visited (pixel, list entry) + 42 per blended one
+                  (blend sweep 13 + 12, removal sweep 13 + 30)
+  k_project:      288 bytes per splat-view (236 read, 48 + 4 written)
+The CPU baseline is the FP64 oracle on the same view, timed on the host.
 """
 from __future__ import annotations
 
@@ -32,8 +38,7 @@ if ROOT not in sys.path:
 METRIC = "splat-view removal scores/s (Gsplat·views/s) + fwd+bwd ms/view, % HBM peak"
 HBM_PEAK_GBS = 8000.0
 FP32_VECTOR_PEAK_TFLOPS = 157.3
-FLOPS_VISIT = {"score": 13.0, "blend": 13.0}
-FLOPS_BLEND = {"score": 30.0, "blend": 12.0}
+FUSED_FLOPS_VISIT, FUSED_FLOPS_BLEND = 26.0, 42.0
 PROJECT_BYTES_PER_SPLAT_VIEW = 236 + 48 + 4
 
 
@@ -47,33 +52,17 @@ def cpu_baseline(scene, cams, s):
             "sample": (f"the full first view ({scene.n} splats, {cams[0].width}x{cams[0].height}): FP64 "
                        f"projection and tile lists (1 thread) + compositing and removal scores "
                        f"({threads} threads); {dt:.2f} s"),
-            "seconds": dt, "pairs": int(len(r["bins"][1]))}
+            "seconds": round(dt, 3), "pairs": int(len(r["bins"][1]))}
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); multi-GPU scoring shards by view "
-              f"and is not built here", file=sys.stderr)
-        sys.exit(2)
-
-    import numpy as np
-    import torch
-
-    from paper_2601_14821_amd import raster, synth
-
+def main_line(args, torch, raster, synth):
     scene, cams = synth.workload_single_view()
     s = synth.RenderSettings()
     ds = raster.to_device(scene)
     rz = raster.Rasterizer(s)
     N, V = scene.n, len(cams)
     scores = torch.zeros(N, dtype=torch.float32, device="cuda")
-    stages = ("project", "bin", "sort", "blend", "score")
+    stages = ("project", "bin", "sort", "render_score")
     stage_ms = {k: 0.0 for k in stages}
     stream = torch.cuda.current_stream()
 
@@ -91,12 +80,9 @@ def main():
         rz.sort(vb, cams)
         if timed:
             ev[3].record(stream)
-        rz.blend(vb, cams)
+        rz.render_score(vb, cams, scores=scores)
         if timed:
             ev[4].record(stream)
-        rz.score(vb, cams, scores=scores)
-        if timed:
-            ev[5].record(stream)
         return ev
 
     for _ in range(args.warmup):
@@ -119,13 +105,11 @@ def main():
     visited = int(vb.n_walk.sum().item())
     blended = int(vb.n_blend.sum().item())
     torch.cuda.synchronize()
-
     work = {
-        "score": ("alu", (FLOPS_VISIT["score"] * visited + FLOPS_BLEND["score"] * blended) / 1e12),
-        "blend": ("alu", (FLOPS_VISIT["blend"] * visited + FLOPS_BLEND["blend"] * blended) / 1e12),
+        "render_score": ("alu", (FUSED_FLOPS_VISIT * visited + FUSED_FLOPS_BLEND * blended) / 1e12),
         "project": ("hbm", PROJECT_BYTES_PER_SPLAT_VIEW * N * V / 1e9),
     }
-    dom = max(("project", "blend", "score"), key=lambda k: stage_ms[k])
+    dom = max(work, key=lambda k: stage_ms[k])
     bound, amount = work[dom]
     sec = stage_ms[dom] / 1000.0
     if bound == "hbm":
@@ -135,28 +119,125 @@ def main():
     roofline = {"bound": bound, "achieved": round(achieved, 3), "peak": peak, "unit": unit,
                 "frac": round(achieved / peak, 4), "traffic": None, "kernel": f"k_{dom}",
                 "kernel_ms": round(stage_ms[dom], 4)}
+    out = {
+        "value": round(N * V / (ms / 1000.0) / 1e9, 4),
+        "ms_per_step": round(ms, 4),
+        "config": {"workload": "single-view removal scoring: 500k clustered splats, one 1280x720 view",
+                   "splats": N, "views": V, "width": cams[0].width, "height": cams[0].height,
+                   "tile": f"{s.tile_w}x{s.tile_h}", "lds_batch": s.lds_batch, "t_min": s.t_min,
+                   "path": "plain per-view launches, fused composite + removal pass"},
+        "roofline": roofline,
+        "stages_ms": {k: round(v, 4) for k, v in stage_ms.items()},
+        "work": {"pairs": vb.n_pairs, "visited": visited, "blended": blended},
+    }
+    return out, (scene, cams, s)
 
+
+def timed(torch, fn, reps, warm=1):
+    for _ in range(warm):
+        fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) * 1000.0 / reps
+
+
+def batched_section(torch, raster, synth, batch, n_views=16):
+    scene, cams = synth.workload_full_scene(n_views=n_views)
+    s = synth.RenderSettings()
+    ds = raster.to_device(scene)
+    sc = torch.zeros(scene.n, device="cuda")
+    rz = raster.Rasterizer(s)
+
+    def plain():
+        sc.zero_()
+        rz.score_views_fused(ds, cams, views_per_batch=1, scores=sc)
+
+    plain_ms = timed(torch, plain, 2)
+    bs = batch.BatchScorer([(ds, cams, sc)], s, views_per_job=8)
+    bs.capture()
+
+    def replay():
+        sc.zero_()
+        bs.replay()
+
+    graph_ms = timed(torch, replay, 3)
+    over = bs.overflowed()
+    counted, _ = bs.pairs()
+    bs.close()
+    del bs, rz, ds, sc
+    torch.cuda.empty_cache()
+    gs = lambda ms: round(scene.n * n_views / (ms / 1000.0) / 1e9, 4)
+    return {"workload": f"{scene.n} clustered splats x {n_views} of the 200 hemisphere views at 1600x1064",
+            "plain_ms_per_view": round(plain_ms / n_views, 4), "plain_gsplat_views_per_s": gs(plain_ms),
+            "batched_graph_ms_per_view": round(graph_ms / n_views, 4), "batched_gsplat_views_per_s": gs(graph_ms),
+            "pairs_per_view": int(sum(counted) / n_views), "overflowed_jobs": over}
+
+
+def fwd_bwd_section(torch, raster, synth, autograd):
+    scene, cams, target_scene = synth.workload_differentiation()
+    s = synth.RenderSettings()
+    ds = raster.to_device(scene)
+    rz = raster.Rasterizer(s)
+    with torch.no_grad():
+        tgt = raster.Rasterizer(s).render_views(raster.to_device(target_scene), cams).image.clone()
+    params = [t.clone().requires_grad_(True) for t in (ds.means, ds.scales, ds.quats, ds.opacities, ds.sh)]
+
+    def step():
+        for p in params:
+            p.grad = None
+        img = autograd.render(*params, cams, rz)
+        loss = (img - tgt).abs().mean()
+        loss.backward()
+
+    ms = timed(torch, step, 5, warm=2)
+    del params, rz, ds, tgt
+    torch.cuda.empty_cache()
+    return {"workload": f"{scene.n} clustered splats, {len(cams)} views at 1280x720, L1 loss vs a perturbed scene",
+            "ms_per_view": round(ms / len(cams), 4), "ms_per_step": round(ms, 4)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--main-only", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); multi-GPU scoring shards by view "
+              f"and is not built here", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2601_14821_amd import autograd, batch, raster, synth
+
+    main_out, (scene, cams, s) = main_line(args, torch, raster, synth)
     out = {
         "metric": METRIC,
-        "value": round(N * V / (ms / 1000.0) / 1e9, 4),
+        "value": main_out["value"],
         "unit": "Gsplat·views/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(ms, 4),
+        "ms_per_step": main_out["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "single-view removal scoring: 500k clustered splats, one 1280x720 view",
-                   "splats": N, "views": V, "width": cams[0].width, "height": cams[0].height,
-                   "tile": f"{s.tile_w}x{s.tile_h}", "lds_batch": s.lds_batch, "t_min": s.t_min,
-                   "path": "plain per-view launches"},
-        "roofline": roofline,
-        "stages_ms": {k: round(v, 4) for k, v in stage_ms.items()},
-        "work": {"pairs": vb.n_pairs, "visited": visited, "blended": blended},
+        "config": main_out["config"],
+        "roofline": main_out["roofline"],
+        "stages_ms": main_out["stages_ms"],
+        "work": main_out["work"],
     }
+    if not args.main_only:
+        out["batched"] = batched_section(torch, raster, synth, batch)
+        out["fwd_bwd"] = fwd_bwd_section(torch, raster, synth, autograd)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(scene, cams, s)
     print(json.dumps(out), flush=True)
