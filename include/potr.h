@@ -121,7 +121,9 @@ POTR_API potr_status potr_project(int64_t N, int32_t V, const potr_camera* cams,
  * splats by depth key (ties by splat id) and emit one (tile, depth rank) pair per
  * tile of every splat's rect, in depth order.
  *   order  [V*N] uint32 out: order[v*N + r] = id of the splat with depth rank r in view v
- *   pairs  [capacity] uint64 out: ((v*tiles + tile) << 32) | rank
+ *   pairs  [capacity] 8-byte slots out: key (v*tiles + tile, rank); packed into 32 bits
+ *          as ((v*tiles + tile) << rank_bits) | rank when ceil(log2(V*tiles)) +
+ *          ceil(log2 N) <= 32, else 64 bits with the rank in the low word
  *   n_pairs (device) int64 out: total number of pairs. If it exceeds `capacity`,
  *          no pair is written; the caller grows `pairs` and calls again (the
  *          Python wrapper does this). Later stages treat such a count as empty.

@@ -39,12 +39,16 @@ __global__ __launch_bounds__(TW * TH) void k_blend_bwd(int64_t N, int32_t W, int
     __shared__ float4 s_b[kBwdChunk];   // conic.a, conic.c, r, g
     __shared__ float s_c[kBwdChunk];    // b
     __shared__ uint32_t s_id[kBwdChunk];
+    __shared__ uint32_t s_rows[kBwdChunk];
     __shared__ float s_part[kG][NW][kBwdChunk];
     __shared__ int s_wmax;
     const int tile = blockIdx.x, v = blockIdx.y;
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const int row_lo = __builtin_amdgcn_readfirstlane((wid * 64) / TW);
+    const int row_hi = __builtin_amdgcn_readfirstlane((wid * 64 + 63) / TW);
+    const int tile_y0 = (tile / tiles_x) * TH;
     const int px = (tile % tiles_x) * TW + (int)(threadIdx.x % TW);
-    const int py = (tile / tiles_x) * TH + (int)(threadIdx.x / TW);
+    const int py = tile_y0 + (int)(threadIdx.x / TW);
     const bool inside = px < W && py < H;
     const float fx = (float)px + 0.5f, fy = (float)py + 0.5f;
     const int64_t tg = (int64_t)v * tiles_per_view + tile;
@@ -79,13 +83,22 @@ __global__ __launch_bounds__(TW * TH) void k_blend_bwd(int64_t N, int32_t W, int
             const uint32_t id = ids[beg + base + j];
             const float4* src = reinterpret_cast<const float4*>(pv + id);
             const float4 r0 = src[0], r1 = src[1], r2 = src[2];
-            s_a[j] = make_float4(r0.x, r0.y, r1.y, r0.w);
-            s_b[j] = make_float4(r0.z, r1.x, r1.z, r1.w);
+            const float4 a = make_float4(r0.x, r0.y, r1.y, r0.w);
+            const float4 b = make_float4(r0.z, r1.x, r1.z, r1.w);
+            s_a[j] = a;
+            s_b[j] = b;
             s_c[j] = r2.x;
             s_id[j] = id;
+            s_rows[j] = reach_rows(a, b, qmax, tile_y0, TH);
         }
         __syncthreads();
         for (int j = 0; j < cnt; ++j) {
+            if (!rows_overlap(__builtin_amdgcn_readfirstlane(s_rows[j]), row_lo, row_hi)) {
+                if (lane == 0)
+#pragma unroll
+                    for (int c = 0; c < kG; ++c) s_part[c][wid][j] = 0.f;
+                continue;
+            }
             float g[kG] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
             bool any = false;
             if (base + j < walk) {
@@ -100,7 +113,7 @@ __global__ __launch_bounds__(TW * TH) void k_blend_bwd(int64_t N, int32_t W, int
                     Pr = add_weighted(Pr, w, cr);
                     Pg = add_weighted(Pg, w, cg);
                     Pb = add_weighted(Pb, w, cb);
-                    const float inv = 1.f / (1.f - al);
+                    const float inv = __builtin_amdgcn_rcpf(1.f - al);
                     const float dLda = gr * (T * cr - (PKr - Pr + Br) * inv) + gg * (T * cg - (PKg - Pg + Bg) * inv) +
                                        gb * (T * cb - (PKb - Pb + Bb) * inv);
                     g[6] = gr * w;

@@ -22,18 +22,22 @@ namespace {
 
 constexpr int kMaxBatch = 512;
 
-template <int NT>
+template <int NT, int TH>
 __device__ inline void stage_batch(const potr_proj* __restrict__ pv, const uint32_t* __restrict__ ids, int base,
-                                   int cnt, float4* s_a, float4* s_b, float* s_c, uint32_t* s_id) {
+                                   int cnt, float4* s_a, float4* s_b, float* s_c, uint32_t* s_id, uint32_t* s_rows,
+                                   float qmax, int tile_y0) {
     for (int j = threadIdx.x; j < cnt; j += NT) {
         const uint32_t id = ids[base + j];
         const float4* src = reinterpret_cast<const float4*>(pv + id);
         const float4 r0 = src[0];   // mean2d.x, mean2d.y, conic.a, conic.b
         const float4 r1 = src[1];   // conic.c, opacity, r, g
         const float4 r2 = src[2];   // b, depth, rect
-        s_a[j] = make_float4(r0.x, r0.y, r1.y, r0.w);
-        s_b[j] = make_float4(r0.z, r1.x, r1.z, r1.w);
+        const float4 a = make_float4(r0.x, r0.y, r1.y, r0.w);
+        const float4 b = make_float4(r0.z, r1.x, r1.z, r1.w);
+        s_a[j] = a;
+        s_b[j] = b;
         s_c[j] = r2.x;
+        s_rows[j] = reach_rows(a, b, qmax, tile_y0, TH);
         if (s_id) s_id[j] = id;
     }
 }
@@ -50,9 +54,14 @@ __global__ __launch_bounds__(TW * TH) void k_blend(int64_t N, int32_t W, int32_t
     __shared__ float4 s_a[kMaxBatch];
     __shared__ float4 s_b[kMaxBatch];
     __shared__ float s_c[kMaxBatch];
+    __shared__ uint32_t s_rows[kMaxBatch];
     const int tile = blockIdx.x, v = blockIdx.y;
+    const int wid = threadIdx.x >> 6;
+    const int row_lo = __builtin_amdgcn_readfirstlane((wid * 64) / TW);
+    const int row_hi = __builtin_amdgcn_readfirstlane((wid * 64 + 63) / TW);
+    const int tile_y0 = (tile / tiles_x) * TH;
     const int px = (tile % tiles_x) * TW + (int)(threadIdx.x % TW);
-    const int py = (tile / tiles_x) * TH + (int)(threadIdx.x / TW);
+    const int py = tile_y0 + (int)(threadIdx.x / TW);
     const bool inside = px < W && py < H;
     const float fx = (float)px + 0.5f, fy = (float)py + 0.5f;
     const int64_t tg = (int64_t)v * tiles_per_view + tile;
@@ -67,10 +76,11 @@ __global__ __launch_bounds__(TW * TH) void k_blend(int64_t N, int32_t W, int32_t
     for (int base = beg; base < end; base += B) {
         if (__syncthreads_count(!done) == 0) break;
         const int cnt = min(B, end - base);
-        stage_batch<NT>(pv, ids, base, cnt, s_a, s_b, s_c, nullptr);
+        stage_batch<NT, TH>(pv, ids, base, cnt, s_a, s_b, s_c, nullptr, s_rows, qmax, tile_y0);
         __syncthreads();
         if (!done) {
             for (int j = 0; j < cnt; ++j) {
+                if (!rows_overlap(__builtin_amdgcn_readfirstlane(s_rows[j]), row_lo, row_hi)) continue;
                 const float4 a = s_a[j];
                 const float4 b = s_b[j];
                 const float al = alpha_of(eval_gauss(a, b, fx, fy), qmax, amin, amax);
@@ -123,12 +133,16 @@ __global__ __launch_bounds__(TW * TH) void k_score(int64_t N, int32_t W, int32_t
     __shared__ float4 s_b[kMaxBatch];
     __shared__ float s_c[kMaxBatch];
     __shared__ uint32_t s_id[kMaxBatch];
+    __shared__ uint32_t s_rows[kMaxBatch];
     __shared__ float s_part[3][NW][kMaxBatch];
     __shared__ int s_wmax;
     const int tile = blockIdx.x, v = blockIdx.y;
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const int row_lo = __builtin_amdgcn_readfirstlane((wid * 64) / TW);
+    const int row_hi = __builtin_amdgcn_readfirstlane((wid * 64 + 63) / TW);
+    const int tile_y0 = (tile / tiles_x) * TH;
     const int px = (tile % tiles_x) * TW + (int)(threadIdx.x % TW);
-    const int py = (tile / tiles_x) * TH + (int)(threadIdx.x / TW);
+    const int py = tile_y0 + (int)(threadIdx.x / TW);
     const bool inside = px < W && py < H;
     const float fx = (float)px + 0.5f, fy = (float)py + 0.5f;
     const int64_t tg = (int64_t)v * tiles_per_view + tile;
@@ -163,9 +177,13 @@ __global__ __launch_bounds__(TW * TH) void k_score(int64_t N, int32_t W, int32_t
     float T = 1.f, Pr = 0.f, Pg = 0.f, Pb = 0.f;
     for (int base = 0; base < wmax; base += B) {
         const int cnt = min(B, wmax - base);
-        stage_batch<NT>(pv, ids, beg + base, cnt, s_a, s_b, s_c, s_id);
+        stage_batch<NT, TH>(pv, ids, beg + base, cnt, s_a, s_b, s_c, s_id, s_rows, qmax, tile_y0);
         __syncthreads();
         for (int j = 0; j < cnt; ++j) {
+            if (!rows_overlap(__builtin_amdgcn_readfirstlane(s_rows[j]), row_lo, row_hi)) {
+                if (lane == 0) s_part[0][wid][j] = s_part[1][wid][j] = s_part[2][wid][j] = 0.f;
+                continue;
+            }
             float l1 = 0.f, se = 0.f, im = 0.f;
             if (base + j < walk) {
                 const float4 a = s_a[j];
@@ -177,7 +195,7 @@ __global__ __launch_bounds__(TW * TH) void k_score(int64_t N, int32_t W, int32_t
                     Pr = add_weighted(Pr, w, cr);
                     Pg = add_weighted(Pg, w, cg);
                     Pb = add_weighted(Pb, w, cbl);
-                    const float k = al / (1.f - al);
+                    const float k = odds(al);
                     const float dr = -w * cr + k * (PKr - Pr + Br);
                     const float dg = -w * cg + k * (PKg - Pg + Bg);
                     const float db = -w * cbl + k * (PKb - Pb + Bb);

@@ -25,4 +25,22 @@ __device__ inline float wave_sum(float v) {
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
 }
 
+// Sums of four values v0..v3 over the 64 lanes; lane r (r < 4) returns the sum
+// of v_r. Reduce-scatter: after the xor-1 exchange each lane keeps two of the
+// four values (summed over its lane pair), after the xor-2 exchange one of them
+// (summed over its quad, value index = lane & 3); rotations by 4 and 8 within a
+// row and two cross-row exchanges then sum the 16 quads of equal index.
+__device__ inline float wave_sum4(float v0, float v1, float v2, float v3) {
+    const int lane = threadIdx.x & 63;
+    const bool o1 = (lane & 1) != 0, o2 = (lane & 2) != 0;
+    const float a = (o1 ? v1 : v0) + dpp_read<0xB1>(o1 ? v0 : v1);   // quad_perm [1,0,3,2]
+    const float b = (o1 ? v3 : v2) + dpp_read<0xB1>(o1 ? v2 : v3);
+    float c = (o2 ? b : a) + dpp_read<0x4E>(o2 ? a : b);             // quad_perm [2,3,0,1]
+    c += dpp_read<0x124>(c);                                          // row_ror:4
+    c += dpp_read<0x128>(c);                                          // row_ror:8
+    c += __shfl_xor(c, 16, 64);
+    c += __shfl_xor(c, 32, 64);
+    return c;
+}
+
 }  // namespace potr

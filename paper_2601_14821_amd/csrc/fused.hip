@@ -23,37 +23,45 @@ struct Smem {
     float4* b;
     float* c;
     uint32_t* id;
+    uint32_t* rows;    // reach_rows per entry
     float* part;       // [n_out][NW][B]
     int* misc;         // [0]: wmax, [1]: next item
 };
 
-template <int NT>
+template <int NT, int TH>
 __device__ inline void stage(const potr_proj* __restrict__ pv, const uint32_t* __restrict__ ids, int base, int cnt,
-                             const Smem& sm) {
+                             const Smem& sm, float qmax, int tile_y0) {
     for (int j = threadIdx.x; j < cnt; j += NT) {
         const uint32_t id = ids[base + j];
         const float4* src = reinterpret_cast<const float4*>(pv + id);
         const float4 r0 = src[0], r1 = src[1], r2 = src[2];
-        sm.a[j] = make_float4(r0.x, r0.y, r1.y, r0.w);
-        sm.b[j] = make_float4(r0.z, r1.x, r1.z, r1.w);
+        const float4 a = make_float4(r0.x, r0.y, r1.y, r0.w);
+        const float4 b = make_float4(r0.z, r1.x, r1.z, r1.w);
+        sm.a[j] = a;
+        sm.b[j] = b;
         sm.c[j] = r2.x;
         sm.id[j] = id;
+        sm.rows[j] = reach_rows(a, b, qmax, tile_y0, TH);
     }
 }
 
-template <int TW, int TH>
+template <int TW, int TH, bool SE>
 __device__ void render_score_tile(const ViewJob& J, int tile, const potr_config& cfg, const Smem& sm) {
     constexpr int NT = TW * TH;
     constexpr int NW = (NT + 63) / 64;
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const int tile_y0 = (tile / J.tiles_x) * TH;
     const int px = (tile % J.tiles_x) * TW + (int)(threadIdx.x % TW);
-    const int py = (tile / J.tiles_x) * TH + (int)(threadIdx.x / TW);
+    const int py = tile_y0 + (int)(threadIdx.x / TW);
+    // tile rows covered by this wave (wave-uniform, kept in scalar registers)
+    const int row_lo = __builtin_amdgcn_readfirstlane((wid * 64) / TW);
+    const int row_hi = __builtin_amdgcn_readfirstlane((wid * 64 + 63) / TW);
     const bool inside = px < J.W && py < J.H;
     const float fx = (float)px + 0.5f, fy = (float)py + 0.5f;
     const int beg = J.ranges[2 * tile], end = J.ranges[2 * tile + 1];
     const int B = cfg.lds_batch;
     const float qmax = cfg.q_max, amin = cfg.alpha_min, amax = cfg.alpha_max, tmin = cfg.t_min;
-    const int n_out = (J.scores ? 1 : 0) + (J.importance ? 1 : 0) + (J.scores_se ? 1 : 0);
+    const int n_out = (J.scores ? 1 : 0) + (J.importance ? 1 : 0) + (SE ? 1 : 0);
     const int o_l1 = 0, o_im = J.scores ? 1 : 0, o_se = o_im + (J.importance ? 1 : 0);
 
     // ---- blend sweep
@@ -64,25 +72,30 @@ __device__ void render_score_tile(const ViewJob& J, int tile, const potr_config&
     for (int base = beg; base < end; base += B) {
         if (__syncthreads_count(!done) == 0) break;
         const int cnt = min(B, end - base);
-        stage<NT>(J.proj, J.ids, base, cnt, sm);
+        stage<NT, TH>(J.proj, J.ids, base, cnt, sm, qmax, tile_y0);
         staged = base;
         __syncthreads();
-        if (!done) {
-            for (int j = 0; j < cnt; ++j) {
+        bool wave_done = __ballot(!done) == 0;
+        for (int j = 0; j < cnt && !wave_done; ++j) {
+            const uint32_t rr = __builtin_amdgcn_readfirstlane(sm.rows[j]);
+            if (!rows_overlap(rr, row_lo, row_hi)) continue;
+            if (!done) {
                 const float al = alpha_of(eval_gauss(sm.a[j], sm.b[j], fx, fy), qmax, amin, amax);
-                if (al == 0.f) continue;
-                const float Tn = next_T(T, al);
-                if (Tn < tmin) {
-                    done = true;
-                    walk = base - beg + j;
-                    break;
+                if (al != 0.f) {
+                    const float Tn = next_T(T, al);
+                    if (Tn < tmin) {
+                        done = true;
+                        walk = base - beg + j;
+                    } else {
+                        const float w = __fmul_rn(T, al);
+                        cr = add_weighted(cr, w, sm.b[j].z);
+                        cg = add_weighted(cg, w, sm.b[j].w);
+                        cb = add_weighted(cb, w, sm.c[j]);
+                        T = Tn;
+                    }
                 }
-                const float w = __fmul_rn(T, al);
-                cr = add_weighted(cr, w, sm.b[j].z);
-                cg = add_weighted(cg, w, sm.b[j].w);
-                cb = add_weighted(cb, w, sm.c[j]);
-                T = Tn;
             }
+            wave_done = __ballot(!done) == 0;
         }
     }
     if (inside && !done) walk = end - beg;
@@ -96,7 +109,7 @@ __device__ void render_score_tile(const ViewJob& J, int tile, const potr_config&
             J.image[3 * pix + 1] = cg + TF * cfg.bg[1];
             J.image[3 * pix + 2] = cb + TF * cfg.bg[2];
         }
-        if (J.scores_se) {
+        if (SE) {
             er = cr + TF * cfg.bg[0] - J.target[3 * pix];
             eg = cg + TF * cfg.bg[1] - J.target[3 * pix + 1];
             eb = cb + TF * cfg.bg[2] - J.target[3 * pix + 2];
@@ -119,13 +132,24 @@ __device__ void render_score_tile(const ViewJob& J, int tile, const potr_config&
         const int cnt = min(B, wmax - base);
         if (staged != beg + base) {
             __syncthreads();
-            stage<NT>(J.proj, J.ids, beg + base, cnt, sm);
+            stage<NT, TH>(J.proj, J.ids, beg + base, cnt, sm, qmax, tile_y0);
             staged = beg + base;
             __syncthreads();
         }
-        for (int j = 0; j < cnt; ++j) {
-            float l1 = 0.f, se = 0.f, im = 0.f;
-            if (base + j < walk) {
+        // this wave's longest walk bounds its entries; later ones contribute 0
+        int wave_walk = walk;
+#pragma unroll
+        for (int m = 32; m >= 1; m >>= 1) wave_walk = max(wave_walk, __shfl_xor(wave_walk, m, 64));
+        wave_walk = __builtin_amdgcn_readfirstlane(wave_walk);
+        // entries in groups of four: per-lane values first, then one reduce-scatter
+        for (int j0 = 0; j0 < cnt; j0 += 4) {
+            float l1v[4] = {0.f, 0.f, 0.f, 0.f}, imv[4] = {0.f, 0.f, 0.f, 0.f}, sev[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int j = j0 + u;
+                if (j >= cnt || base + j >= wave_walk) continue;
+                const uint32_t rr = __builtin_amdgcn_readfirstlane(sm.rows[j]);
+                if (!rows_overlap(rr, row_lo, row_hi) || base + j >= walk) continue;
                 const float4 b = sm.b[j];
                 const float al = alpha_of(eval_gauss(sm.a[j], b, fx, fy), qmax, amin, amax);
                 if (al != 0.f) {
@@ -134,28 +158,29 @@ __device__ void render_score_tile(const ViewJob& J, int tile, const potr_config&
                     Pr = add_weighted(Pr, w, c0);
                     Pg = add_weighted(Pg, w, c1);
                     Pb = add_weighted(Pb, w, c2);
-                    const float k = al / (1.f - al);
+                    const float k = odds(al);
                     const float dr = -w * c0 + k * (PKr - Pr + Br);
                     const float dg = -w * c1 + k * (PKg - Pg + Bg);
                     const float db = -w * c2 + k * (PKb - Pb + Bb);
-                    l1 = fabsf(dr) + fabsf(dg) + fabsf(db);
-                    se = dr * dr + dg * dg + db * db + 2.f * (dr * er + dg * eg + db * eb);
-                    im = w;
+                    l1v[u] = fabsf(dr) + fabsf(dg) + fabsf(db);
+                    if (SE) sev[u] = dr * dr + dg * dg + db * db + 2.f * (dr * er + dg * eg + db * eb);
+                    imv[u] = w;
                     T = next_T(T, al);
                 }
             }
-            const bool any = __ballot(l1 != 0.f || im != 0.f) != 0;
+            const bool any = __ballot(imv[0] != 0.f || imv[1] != 0.f || imv[2] != 0.f || imv[3] != 0.f) != 0;
+            const bool writer = lane < 4 && j0 + lane < cnt;
             if (J.scores) {
-                const float s = any ? wave_sum(l1) : 0.f;
-                if (lane == 0) sm.part[(o_l1 * NW + wid) * B + j] = s;
+                const float s = any ? wave_sum4(l1v[0], l1v[1], l1v[2], l1v[3]) : 0.f;
+                if (writer) sm.part[(o_l1 * NW + wid) * B + j0 + lane] = s;
             }
             if (J.importance) {
-                const float s = any ? wave_sum(im) : 0.f;
-                if (lane == 0) sm.part[(o_im * NW + wid) * B + j] = s;
+                const float s = any ? wave_sum4(imv[0], imv[1], imv[2], imv[3]) : 0.f;
+                if (writer) sm.part[(o_im * NW + wid) * B + j0 + lane] = s;
             }
-            if (J.scores_se) {
-                const float s = any ? wave_sum(se) : 0.f;
-                if (lane == 0) sm.part[(o_se * NW + wid) * B + j] = s;
+            if (SE) {
+                const float s = any ? wave_sum4(sev[0], sev[1], sev[2], sev[3]) : 0.f;
+                if (writer) sm.part[(o_se * NW + wid) * B + j0 + lane] = s;
             }
         }
         __syncthreads();
@@ -169,7 +194,7 @@ __device__ void render_score_tile(const ViewJob& J, int tile, const potr_config&
                     for (int w = 0; w < NW; ++w) t[o] += sm.part[(o * NW + w) * B + j];
             if (J.scores && t[o_l1] != 0.f) unsafeAtomicAdd(J.scores + id, t[o_l1]);
             if (J.importance && t[o_im] != 0.f) unsafeAtomicAdd(J.importance + id, t[o_im]);
-            if (J.scores_se && t[o_se] != 0.f) unsafeAtomicAdd(J.scores_se + id, t[o_se]);
+            if (SE && t[o_se] != 0.f) unsafeAtomicAdd(J.scores_se + id, t[o_se]);
         }
     }
     __syncthreads();
@@ -183,17 +208,18 @@ __device__ inline Smem carve(char* base, int B) {
     s.b = s.a + B;
     s.c = reinterpret_cast<float*>(s.b + B);
     s.id = reinterpret_cast<uint32_t*>(s.c + B);
-    s.part = reinterpret_cast<float*>(s.id + B);
+    s.rows = s.id + B;
+    s.part = reinterpret_cast<float*>(s.rows + B);
     s.misc = reinterpret_cast<int*>(s.part + 3 * NW * B);
     return s;
 }
 
-template <int TW, int TH>
+template <int TW, int TH, bool SE>
 __global__ __launch_bounds__(TW * TH) void k_render_score(ViewJobs jobs, potr_config cfg) {
     extern __shared__ __align__(16) char smem[];
     const Smem sm = carve<TW, TH>(smem, cfg.lds_batch);
     const ViewJob J = jobs.j[blockIdx.y];
-    render_score_tile<TW, TH>(J, blockIdx.x, cfg, sm);
+    render_score_tile<TW, TH, SE>(J, blockIdx.x, cfg, sm);
 }
 
 // Persistent form: items are (view job, tile) pairs numbered job-major;
@@ -218,7 +244,7 @@ __global__ __launch_bounds__(TW * TH) void k_render_score_persistent(const ViewJ
             else hi = mid - 1;
         }
         const ViewJob J = jobs[lo];
-        render_score_tile<TW, TH>(J, (int)(item - item_prefix[lo]), cfg, sm);
+        render_score_tile<TW, TH, false>(J, (int)(item - item_prefix[lo]), cfg, sm);
     }
 }
 
@@ -227,7 +253,7 @@ __global__ void k_zero_i64(int64_t* p) { *p = 0; }
 template <int TW, int TH>
 size_t smem_bytes(int B) {
     constexpr int NW = (TW * TH + 63) / 64;
-    return (size_t)B * (16 + 16 + 4 + 4) + (size_t)3 * NW * B * 4 + 16;
+    return (size_t)B * (16 + 16 + 4 + 4 + 4) + (size_t)3 * NW * B * 4 + 16;
 }
 
 }  // namespace
@@ -242,14 +268,19 @@ potr_status launch_render_score(const ViewJobs& jobs_dev, int32_t n_views, int32
                                 const potr_config& cfg, hipStream_t s) {
     const size_t sm = fused_smem_bytes(cfg);
     const dim3 grid(tiles_per_view, n_views);
-    if (cfg.tile_w == 16 && cfg.tile_h == 16)
-        hipLaunchKernelGGL((k_render_score<16, 16>), grid, dim3(256), sm, s, jobs_dev, cfg);
-    else if (cfg.tile_w == 8 && cfg.tile_h == 8)
-        hipLaunchKernelGGL((k_render_score<8, 8>), grid, dim3(64), sm, s, jobs_dev, cfg);
-    else if (cfg.tile_w == 32 && cfg.tile_h == 8)
-        hipLaunchKernelGGL((k_render_score<32, 8>), grid, dim3(256), sm, s, jobs_dev, cfg);
-    else
+    const bool se = jobs_dev.j[0].scores_se != nullptr;
+    if (cfg.tile_w == 16 && cfg.tile_h == 16) {
+        if (se) hipLaunchKernelGGL((k_render_score<16, 16, true>), grid, dim3(256), sm, s, jobs_dev, cfg);
+        else hipLaunchKernelGGL((k_render_score<16, 16, false>), grid, dim3(256), sm, s, jobs_dev, cfg);
+    } else if (cfg.tile_w == 8 && cfg.tile_h == 8) {
+        if (se) hipLaunchKernelGGL((k_render_score<8, 8, true>), grid, dim3(64), sm, s, jobs_dev, cfg);
+        else hipLaunchKernelGGL((k_render_score<8, 8, false>), grid, dim3(64), sm, s, jobs_dev, cfg);
+    } else if (cfg.tile_w == 32 && cfg.tile_h == 8) {
+        if (se) hipLaunchKernelGGL((k_render_score<32, 8, true>), grid, dim3(256), sm, s, jobs_dev, cfg);
+        else hipLaunchKernelGGL((k_render_score<32, 8, false>), grid, dim3(256), sm, s, jobs_dev, cfg);
+    } else {
         return fail(POTR_EUNSUPPORTED, "tile %dx%d not built", cfg.tile_w, cfg.tile_h);
+    }
     return check_launch("k_render_score");
 }
 

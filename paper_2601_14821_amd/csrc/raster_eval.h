@@ -39,4 +39,37 @@ __device__ inline float next_T(float T, float al) { return __fmul_rn(T, __fsub_r
 
 __device__ inline float add_weighted(float P, float w, float c) { return __fmaf_rn(w, c, P); }
 
+// Tile rows [r0, r1] (relative to the tile's first row, packed r0 | r1 << 8;
+// r0 > r1 when none) that a staged record can reach: pixel centres within the
+// vertical extent of the ellipse q <= q_max, |dy| <= sqrt(q_max a / (a c - b^2)),
+// widened by 2^-10 relative + 1/64 px so that no FP32 evaluation inside the
+// rows it excludes could pass the visibility test. Used to skip whole waves.
+__device__ inline uint32_t reach_rows(const float4& a, const float4& b, float qmax, int tile_y0, int TH) {
+    // FP64: the products of FP32 values are exact, so det has one rounding even
+    // for very elongated ellipses
+    const double A = b.x, B = a.w, Cc = b.y;
+    const double det = A * Cc - B * B;
+    int r0 = 0, r1 = TH - 1;
+    if (det > 0.0) {
+        const double ry = sqrt((double)qmax * A / det) * (1.0 + 1.0 / 1024.0) + 1.0 / 64.0;
+        if (ry == ry && ry < 1e8) {
+            // rows j with |j + 0.5 - my| <= ry
+            const double lo = ceil((double)a.y - ry - 0.5) - (double)tile_y0;
+            const double hi = floor((double)a.y + ry - 0.5) - (double)tile_y0;
+            r0 = lo < 0.0 ? 0 : (lo > (double)(TH - 1) ? TH : (int)lo);
+            r1 = hi > (double)(TH - 1) ? TH - 1 : (hi < 0.0 ? -1 : (int)hi);
+        }
+    }
+    if (r0 > r1) return 0xffu;          // r0 = 255, r1 = 0: reaches no row
+    return (uint32_t)r0 | ((uint32_t)r1 << 8);
+}
+
+__device__ inline bool rows_overlap(uint32_t rr, int row_lo, int row_hi) {
+    const int r0 = (int)(rr & 0xffu), r1 = (int)(rr >> 8);
+    return r0 <= row_hi && r1 >= row_lo;
+}
+
+// alpha / (1 - alpha) with the hardware reciprocal (1 ulp), 1 - alpha >= 1 - alpha_max
+__device__ inline float odds(float al) { return al * __builtin_amdgcn_rcpf(1.f - al); }
+
 }  // namespace potr

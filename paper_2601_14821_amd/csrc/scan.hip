@@ -89,9 +89,62 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_down(const TI* in, int64_
     }
 }
 
+// Whole scan in one workgroup of 1024 threads (small inputs: one launch instead
+// of three). Items are consumed in tiles of 1024 x 8, blocked per thread.
+constexpr int kOneThreads = 1024, kOneItems = 8;
+
+template <typename T>
+__device__ inline T block_exclusive_scan_1024(T x, T* total) {
+    __shared__ T warp_sums[kOneThreads / 64];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    T inc = wave_inclusive_scan(x);
+    if (lane == 63) warp_sums[w] = inc;
+    __syncthreads();
+    T base = 0, all = 0;
+#pragma unroll
+    for (int k = 0; k < kOneThreads / 64; ++k) {
+        T v = warp_sums[k];
+        if (k < w) base += v;
+        all += v;
+    }
+    __syncthreads();
+    *total = all;
+    return base + inc - x;
+}
+
+template <typename TI, typename TO>
+__global__ __launch_bounds__(kOneThreads) void k_scan_one(const TI* in, int64_t n, TO* out, TO* total) {
+    TO carry = 0;
+    for (int64_t base = 0; base < n; base += (int64_t)kOneThreads * kOneItems) {
+        TO v[kOneItems];
+        TO acc = 0;
+#pragma unroll
+        for (int k = 0; k < kOneItems; ++k) {
+            const int64_t e = base + (int64_t)threadIdx.x * kOneItems + k;
+            v[k] = e < n ? (TO)in[e] : (TO)0;
+            acc += v[k];
+        }
+        TO tot;
+        TO run = carry + block_exclusive_scan_1024<TO>(acc, &tot);
+#pragma unroll
+        for (int k = 0; k < kOneItems; ++k) {
+            const int64_t e = base + (int64_t)threadIdx.x * kOneItems + k;
+            const TO x = v[k];
+            if (e < n) out[e] = run;
+            run += x;
+        }
+        carry += tot;
+    }
+    if (threadIdx.x == 0 && total) *total = carry;
+}
+
 template <typename TI, typename TO>
 potr_status scan_impl(const TI* in, TO* out, int64_t n, TO* total, void* tmp, hipStream_t s) {
     TO* sums = reinterpret_cast<TO*>(tmp);
+    if (n > 0 && n <= (int64_t(1) << 18)) {
+        hipLaunchKernelGGL((k_scan_one<TI, TO>), dim3(1), dim3(kOneThreads), 0, s, in, n, out, total);
+        return check_launch("k_scan_one");
+    }
     if (n <= 0) {
         if (total) {
             hipLaunchKernelGGL(k_scan_top<TO>, dim3(1), dim3(kScanThreads), 0, s, sums, (int64_t)0, total);

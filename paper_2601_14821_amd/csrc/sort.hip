@@ -9,10 +9,14 @@
 //   (view, tile, depth key, splat id) -- the full key -- while only
 //   ceil(log2(V * tiles)) bits are sorted instead of tile + 32 depth bits.
 //
+// Pairs are packed as ((view * tiles + tile) << rank_bits) | rank in 32 bits
+// when both fields fit, else in 64 bits with the rank in the low word.
+//
 // Each radix pass is histogram -> exclusive scan of the [segment][digit][block]
-// counts -> scatter. Blocks take 4096 consecutive elements; within a block the
-// order is (wave, item, lane) and ranks are formed with 64-lane ballots, so the
-// scatter is stable.
+// counts -> scatter. Blocks take ITEMS x 256 consecutive elements; within a
+// block the order is (wave, item, lane) and ranks come from 64-lane ballots, so
+// the scatter is stable. Each block first sorts its elements in LDS, then
+// writes every digit's run to consecutive addresses.
 #include "common.h"
 
 namespace potr {
@@ -36,9 +40,10 @@ __device__ inline uint32_t digit_of(K k, int shift, uint32_t mask) {
     return (uint32_t)(k >> shift) & mask;
 }
 
-template <typename K>
+template <typename K, int ITEMS>
 __global__ __launch_bounds__(kRadixThreads) void k_radix_hist(const K* __restrict__ keys, RadixGeom g, int shift,
                                                               int bits, uint32_t* __restrict__ hist) {
+    constexpr int TILE = kRadixThreads * ITEMS;
     __shared__ uint32_t h[256];
     const int seg = blockIdx.y, b = blockIdx.x;
     const uint32_t radix = 1u << bits, mask = radix - 1;
@@ -47,8 +52,8 @@ __global__ __launch_bounds__(kRadixThreads) void k_radix_hist(const K* __restric
     const int64_t n = seg_n(g);
     const K* base = keys + (int64_t)seg * g.seg_len;
 #pragma unroll 4
-    for (int k = 0; k < kRadixItems; ++k) {
-        const int64_t e = (int64_t)b * kRadixTile + (int64_t)k * kRadixThreads + threadIdx.x;
+    for (int k = 0; k < ITEMS; ++k) {
+        const int64_t e = (int64_t)b * TILE + (int64_t)k * kRadixThreads + threadIdx.x;
         if (e < n) atomicAdd(&h[digit_of(base[e], shift, mask)], 1u);
     }
     __syncthreads();
@@ -58,15 +63,20 @@ __global__ __launch_bounds__(kRadixThreads) void k_radix_hist(const K* __restric
 
 // Scatter one block's keys (and values) to their stable sorted positions.
 // offs: exclusive scan of the histogram (global positions over all segments).
-template <typename K, bool VALS>
+template <typename K, bool VALS, int ITEMS>
 __global__ __launch_bounds__(kRadixThreads) void k_radix_scatter(const K* __restrict__ kin, K* __restrict__ kout,
                                                                  const uint32_t* __restrict__ vin,
                                                                  uint32_t* __restrict__ vout, RadixGeom g,
                                                                  int shift, int bits,
                                                                  const uint32_t* __restrict__ offs) {
     constexpr int NW = kRadixThreads / 64;
+    constexpr int TILE = kRadixThreads * ITEMS;
     __shared__ uint32_t wcnt[NW][256];
     __shared__ uint32_t goff[256];
+    __shared__ uint32_t boff[256];
+    __shared__ uint32_t wsum[NW];
+    __shared__ K s_key[TILE];
+    __shared__ uint32_t s_val[VALS ? TILE : 1];
     const int seg = blockIdx.y, b = blockIdx.x;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const uint32_t radix = 1u << bits, mask = radix - 1;
@@ -77,13 +87,14 @@ __global__ __launch_bounds__(kRadixThreads) void k_radix_scatter(const K* __rest
 
     const int64_t n = seg_n(g);
     const int64_t seg0 = (int64_t)seg * g.seg_len;
-    const int64_t wbase = (int64_t)b * kRadixTile + (int64_t)w * (64 * kRadixItems);
-    K key[kRadixItems];
-    uint32_t val[kRadixItems];
-    uint32_t rnk[kRadixItems];
+    const int64_t blk0 = (int64_t)b * TILE;
+    const int64_t wbase = blk0 + (int64_t)w * (64 * ITEMS);
+    K key[ITEMS];
+    uint32_t val[ITEMS];
+    uint32_t rnk[ITEMS];
     const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
 #pragma unroll
-    for (int k = 0; k < kRadixItems; ++k) {
+    for (int k = 0; k < ITEMS; ++k) {
         const int64_t e = wbase + k * 64 + lane;
         const bool ok = e < n;
         key[k] = ok ? kin[seg0 + e] : (K)0;
@@ -104,40 +115,72 @@ __global__ __launch_bounds__(kRadixThreads) void k_radix_scatter(const K* __rest
         rnk[k] = ok ? r + below : 0xffffffffu;
     }
     __syncthreads();
-    // wave-level exclusive prefix per digit (waves hold consecutive runs)
-    for (uint32_t d = threadIdx.x; d < radix; d += kRadixThreads) {
+    // per digit: exclusive prefix over waves (waves hold consecutive runs) and the block total
+    for (uint32_t d = threadIdx.x; d < 256; d += kRadixThreads) {
         uint32_t run = 0;
+        if (d < radix) {
 #pragma unroll
-        for (int ww = 0; ww < NW; ++ww) {
-            const uint32_t c = wcnt[ww][d];
-            wcnt[ww][d] = run;
-            run += c;
+            for (int ww = 0; ww < NW; ++ww) {
+                const uint32_t c = wcnt[ww][d];
+                wcnt[ww][d] = run;
+                run += c;
+            }
         }
+        boff[d] = run;
     }
     __syncthreads();
+    // exclusive scan of the block's digit totals (256 entries, one per thread)
+    {
+        const uint32_t x = boff[threadIdx.x];
+        uint32_t inc = x;
 #pragma unroll
-    for (int k = 0; k < kRadixItems; ++k) {
+        for (int dd = 1; dd < 64; dd <<= 1) {
+            const uint32_t y = __shfl_up(inc, dd, 64);
+            if (lane >= dd) inc += y;
+        }
+        if (lane == 63) wsum[w] = inc;
+        __syncthreads();
+        uint32_t pre = 0;
+#pragma unroll
+        for (int ww = 0; ww < NW; ++ww)
+            if (ww < w) pre += wsum[ww];
+        boff[threadIdx.x] = pre + inc - x;
+    }
+    __syncthreads();
+    // block-local sort in LDS
+#pragma unroll
+    for (int k = 0; k < ITEMS; ++k) {
         if (rnk[k] == 0xffffffffu) continue;
         const uint32_t d = digit_of(key[k], shift, mask);
-        const int64_t pos = (int64_t)goff[d] + wcnt[w][d] + rnk[k];
-        kout[pos] = key[k];
-        if (VALS) vout[pos] = val[k];
+        const uint32_t p = boff[d] + wcnt[w][d] + rnk[k];
+        s_key[p] = key[k];
+        if (VALS) s_val[p] = val[k];
+    }
+    __syncthreads();
+    // coalesced write-out: digit runs go to consecutive global addresses
+    const int64_t left = n - blk0;
+    const int cnt_blk = left < TILE ? (int)(left > 0 ? left : 0) : TILE;
+    for (int i = threadIdx.x; i < cnt_blk; i += kRadixThreads) {
+        const K kk = s_key[i];
+        const uint32_t d = digit_of(kk, shift, mask);
+        const int64_t pos = (int64_t)goff[d] + (i - (int)boff[d]);
+        kout[pos] = kk;
+        if (VALS) vout[pos] = s_val[i];
     }
 }
 
-// One LSD pass: hist -> scan -> scatter.
-template <typename K, bool VALS>
+template <typename K, bool VALS, int ITEMS>
 potr_status radix_pass(const K* kin, K* kout, const uint32_t* vin, uint32_t* vout, const RadixGeom& g,
                        int32_t n_segs, int shift, int bits, uint32_t* hist, void* scan_tmp, hipStream_t s) {
     const dim3 grid((unsigned)g.blocks_per_seg, (unsigned)n_segs);
-    hipLaunchKernelGGL(k_radix_hist<K>, grid, dim3(kRadixThreads), 0, s, kin, g, shift, bits, hist);
+    hipLaunchKernelGGL((k_radix_hist<K, ITEMS>), grid, dim3(kRadixThreads), 0, s, kin, g, shift, bits, hist);
     potr_status st = check_launch("k_radix_hist");
     if (st != POTR_OK) return st;
     const int64_t nh = (int64_t)n_segs * (1 << bits) * g.blocks_per_seg;
     st = scan_u32(hist, hist, nh, scan_tmp, s);
     if (st != POTR_OK) return st;
-    hipLaunchKernelGGL((k_radix_scatter<K, VALS>), grid, dim3(kRadixThreads), 0, s, kin, kout, vin, vout, g, shift,
-                       bits, (const uint32_t*)hist);
+    hipLaunchKernelGGL((k_radix_scatter<K, VALS, ITEMS>), grid, dim3(kRadixThreads), 0, s, kin, kout, vin, vout, g,
+                       shift, bits, (const uint32_t*)hist);
     return check_launch("k_radix_scatter");
 }
 
@@ -156,23 +199,57 @@ __global__ void k_gather_counts(const uint32_t* __restrict__ order, const int32_
     cnt[i] = tiles_touched[v * N + order[i]];
 }
 
-__global__ void k_emit(const uint32_t* __restrict__ order, const int32_t* __restrict__ cnt,
-                       const int64_t* __restrict__ offs, const potr_proj* __restrict__ proj, int64_t N,
-                       int64_t total, int32_t tiles_x, int32_t tiles_per_view, int64_t capacity,
-                       const int64_t* __restrict__ n_pairs, uint64_t* __restrict__ pairs) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= total) return;
+// Pairs of 256 consecutive (view, rank) entries, written cooperatively by the
+// block so that stores are contiguous: each output slot finds its splat by a
+// binary search over the block's offsets.
+template <typename K>
+__global__ __launch_bounds__(256) void k_emit(const uint32_t* __restrict__ order, const int32_t* __restrict__ cnt,
+                                              const int64_t* __restrict__ offs, const potr_proj* __restrict__ proj,
+                                              int64_t N, int64_t total, int32_t tiles_x, int32_t tiles_per_view,
+                                              int rank_bits, int64_t capacity, const int64_t* __restrict__ n_pairs,
+                                              K* __restrict__ pairs) {
+    __shared__ int64_t s_off[256];
+    __shared__ uint32_t s_key0[256];      // (view * tiles + y0 * tiles_x + x0)
+    __shared__ uint32_t s_rank[256];
+    __shared__ uint16_t s_w[256];
     if (*n_pairs > capacity) return;
-    const int32_t c = cnt[i];
-    if (c == 0) return;
-    const int64_t v = i / N, r = i - v * N;
-    const potr_proj& p = proj[v * N + order[i]];
-    int64_t o = offs[i];
-    const uint64_t lo = (uint64_t)r;
-    const uint64_t gbase = (uint64_t)v * (uint64_t)tiles_per_view;
-    for (int ty = p.rect[1]; ty < p.rect[3]; ++ty)
-        for (int tx = p.rect[0]; tx < p.rect[2]; ++tx)
-            pairs[o++] = ((gbase + (uint64_t)(ty * tiles_x + tx)) << 32) | lo;
+    const int64_t i0 = (int64_t)blockIdx.x * 256;
+    const int64_t i = i0 + threadIdx.x;
+    int64_t my_off = 0;
+    if (i < total) {
+        const int64_t v = i / N, r = i - v * N;
+        const int32_t c = cnt[i];
+        my_off = offs[i];
+        const potr_proj& p = proj[v * N + order[i]];
+        s_key0[threadIdx.x] = (uint32_t)(v * tiles_per_view + p.rect[1] * tiles_x + p.rect[0]);
+        s_rank[threadIdx.x] = (uint32_t)r;
+        s_w[threadIdx.x] = (uint16_t)(c > 0 ? p.rect[2] - p.rect[0] : 1);
+    } else {
+        s_key0[threadIdx.x] = 0;
+        s_rank[threadIdx.x] = 0;
+        s_w[threadIdx.x] = 1;
+    }
+    s_off[threadIdx.x] = my_off;
+    __syncthreads();
+    const int64_t last = (total - i0 < 256 ? total - i0 : 256) - 1;
+    const int64_t beg = s_off[0];
+    const int64_t end = offs[i0 + last] + cnt[i0 + last];
+    for (int64_t p = beg + threadIdx.x; p < end; p += 256) {
+        int lo = 0, hi = (int)last;          // last entry with s_off <= p
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (s_off[mid] <= p) lo = mid;
+            else hi = mid - 1;
+        }
+        const uint32_t t = (uint32_t)(p - s_off[lo]);
+        const uint32_t wdt = s_w[lo];
+        const uint32_t ty = t / wdt, tx = t - ty * wdt;
+        const uint64_t g = (uint64_t)s_key0[lo] + (uint64_t)ty * (uint32_t)tiles_x + tx;
+        if (sizeof(K) == 4)
+            pairs[p] = (K)((g << rank_bits) | s_rank[lo]);
+        else
+            pairs[p] = (K)((g << 32) | s_rank[lo]);
+    }
 }
 
 // ---------------------------------------------------------------- sort kernels
@@ -181,20 +258,45 @@ __global__ void k_fill_i32(int32_t* p, int64_t n, int32_t v) {
     if (i < n) p[i] = v;
 }
 
-__global__ void k_finalize(const uint64_t* __restrict__ sorted, const int64_t* __restrict__ n_pairs, int64_t cap,
-                           const uint32_t* __restrict__ order, int64_t N, int32_t tiles_per_view,
+template <typename K>
+__global__ void k_finalize(const K* __restrict__ sorted, const int64_t* __restrict__ n_pairs, int64_t cap,
+                           const uint32_t* __restrict__ order, int64_t N, int32_t tiles_per_view, int rank_bits,
                            uint32_t* __restrict__ ids, int32_t* __restrict__ ranges) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     int64_t n = *n_pairs;
     if (n > cap) n = 0;
     if (i >= n) return;
-    const uint64_t p = sorted[i];
-    const uint32_t gt = (uint32_t)(p >> 32);
-    const uint32_t r = (uint32_t)p;
+    const int sh = sizeof(K) == 4 ? rank_bits : 32;
+    const uint64_t rmask = sizeof(K) == 4 ? ((1ull << rank_bits) - 1) : 0xffffffffull;
+    const K p = sorted[i];
+    const uint32_t gt = (uint32_t)((uint64_t)p >> sh);
+    const uint32_t r = (uint32_t)((uint64_t)p & rmask);
     const uint32_t v = gt / (uint32_t)tiles_per_view;
     ids[i] = order[(int64_t)v * N + r];
-    if (i == 0 || (uint32_t)(sorted[i - 1] >> 32) != gt) ranges[2 * (int64_t)gt] = (int32_t)i;
-    if (i == n - 1 || (uint32_t)(sorted[i + 1] >> 32) != gt) ranges[2 * (int64_t)gt + 1] = (int32_t)(i + 1);
+    if (i == 0 || (uint32_t)((uint64_t)sorted[i - 1] >> sh) != gt) ranges[2 * (int64_t)gt] = (int32_t)i;
+    if (i == n - 1 || (uint32_t)((uint64_t)sorted[i + 1] >> sh) != gt) ranges[2 * (int64_t)gt + 1] = (int32_t)(i + 1);
+}
+
+constexpr int kDepthItems = 4;       // depth sort: 1024 keys per block (N-sized, fills the GPU)
+constexpr int kPairItems = kRadixItems;
+
+int bit_width(int64_t x) {           // bits to hold 0..x (at least 1)
+    int b = 1;
+    while (b < 62 && (int64_t(1) << b) <= x) ++b;
+    return b;
+}
+
+struct Packing {
+    int tile_bits, rank_bits;
+    bool u32;
+};
+
+Packing packing(int64_t N, int32_t V, int32_t tiles_per_view) {
+    Packing p;
+    p.tile_bits = bit_width((int64_t)V * tiles_per_view - 1);
+    p.rank_bits = bit_width(N > 0 ? N - 1 : 0);
+    p.u32 = p.tile_bits + p.rank_bits <= 32;
+    return p;
 }
 
 struct BinWs {
@@ -207,7 +309,7 @@ struct BinWs {
 
 BinWs bin_layout(int64_t N, int32_t V, char* base) {
     const int64_t VN = N * V;
-    const int64_t bps = ceil_div(N > 0 ? N : 1, kRadixTile);
+    const int64_t bps = ceil_div(N > 0 ? N : 1, kRadixThreads * kDepthItems);
     BinWs w;
     size_t o = 0;
     auto take = [&](size_t b) { char* p = base ? base + o : nullptr; o += align_up(b); return p; };
@@ -224,22 +326,53 @@ BinWs bin_layout(int64_t N, int32_t V, char* base) {
 }
 
 struct SortWs {
-    uint64_t* alt;
+    void* alt;
     uint32_t* hist;
     void* scan_tmp;
     size_t bytes;
 };
 
 SortWs sort_layout(int64_t cap, char* base) {
-    const int64_t nb = ceil_div(cap > 0 ? cap : 1, kRadixTile);
+    const int64_t nb = ceil_div(cap > 0 ? cap : 1, kRadixThreads * kPairItems);
     SortWs w;
     size_t o = 0;
     auto take = [&](size_t b) { char* p = base ? base + o : nullptr; o += align_up(b); return p; };
-    w.alt = (uint64_t*)take(8 * (size_t)(cap > 0 ? cap : 1));
+    w.alt = take(8 * (size_t)(cap > 0 ? cap : 1));
     w.hist = (uint32_t*)take(4 * (size_t)256 * nb);
     w.scan_tmp = take(scan_tmp_bytes(256 * nb));
     w.bytes = o;
     return w;
+}
+
+template <typename K>
+potr_status emit_pairs(const uint32_t* order, const BinWs& w, const potr_proj* proj, int64_t N, int64_t VN,
+                       int txs, int tpv, int rank_bits, int64_t capacity, const int64_t* n_pairs, void* pairs,
+                       hipStream_t s) {
+    hipLaunchKernelGGL(k_emit<K>, dim3((unsigned)ceil_div(VN, 256)), dim3(256), 0, s, order, (const int32_t*)w.cnt,
+                       (const int64_t*)w.offs, proj, N, VN, txs, tpv, rank_bits, capacity, n_pairs, (K*)pairs);
+    return check_launch("k_emit");
+}
+
+template <typename K>
+potr_status sort_pairs(int64_t N, int32_t V, int32_t tpv, const Packing& pk, const int64_t* n_pairs, int64_t n_max,
+                       void* pairs, const uint32_t* order, const SortWs& w, uint32_t* sorted_ids,
+                       int32_t* tile_ranges, hipStream_t s) {
+    const int bits = pk.tile_bits;
+    const int passes = (bits + 7) / 8;
+    const int per = (bits + passes - 1) / passes;
+    const int shift0 = sizeof(K) == 4 ? pk.rank_bits : 32;
+    RadixGeom g{0, n_pairs, n_max, (int32_t)ceil_div(n_max, kRadixThreads * kPairItems)};
+    K *kin = (K*)pairs, *kout = (K*)w.alt;
+    for (int p = 0; p < passes; ++p) {
+        const int b = (p == passes - 1) ? bits - per * p : per;
+        potr_status st = radix_pass<K, false, kPairItems>(kin, kout, nullptr, nullptr, g, 1, shift0 + per * p, b,
+                                                          w.hist, w.scan_tmp, s);
+        if (st != POTR_OK) return st;
+        K* t = kin; kin = kout; kout = t;
+    }
+    hipLaunchKernelGGL(k_finalize<K>, dim3((unsigned)ceil_div(n_max, 256)), dim3(256), 0, s, (const K*)kin, n_pairs,
+                       n_max, order, N, tpv, pk.rank_bits, sorted_ids, tile_ranges);
+    return check_launch("k_finalize");
 }
 
 }  // namespace
@@ -258,11 +391,11 @@ potr_status launch_bin(int64_t N, int32_t V, const potr_camera& cam0, const potr
     potr_status st = check_launch("k_depth_keys");
     if (st != POTR_OK) return st;
     // stable per-view sort of the 32-bit depth keys; four 8-bit passes
-    RadixGeom g{N, nullptr, 0, (int32_t)ceil_div(N, kRadixTile)};
+    RadixGeom g{N, nullptr, 0, (int32_t)ceil_div(N, kRadixThreads * kDepthItems)};
     uint32_t *kin = w.ka, *kout = w.kb, *vin = nullptr, *vout = w.va;
     for (int pass = 0; pass < 4; ++pass) {
         if (pass == 3) vout = order;
-        st = radix_pass<uint32_t, true>(kin, kout, vin, vout, g, V, 8 * pass, 8, w.hist, w.scan_tmp, s);
+        st = radix_pass<uint32_t, true, kDepthItems>(kin, kout, vin, vout, g, V, 8 * pass, 8, w.hist, w.scan_tmp, s);
         if (st != POTR_OK) return st;
         uint32_t* t = kin; kin = kout; kout = t;
         vin = vout;
@@ -274,9 +407,10 @@ potr_status launch_bin(int64_t N, int32_t V, const potr_camera& cam0, const potr
     if (st != POTR_OK) return st;
     st = scan_i32_to_i64(w.cnt, w.offs, VN, n_pairs, w.scan_tmp, s);
     if (st != POTR_OK) return st;
-    hipLaunchKernelGGL(k_emit, dim3(gb), dim3(256), 0, s, (const uint32_t*)order, (const int32_t*)w.cnt,
-                       (const int64_t*)w.offs, proj, N, VN, txs, tpv, capacity, (const int64_t*)n_pairs, pairs);
-    return check_launch("k_emit");
+    const Packing pk = packing(N, V, tpv);
+    if (pk.u32)
+        return emit_pairs<uint32_t>(order, w, proj, N, VN, txs, tpv, pk.rank_bits, capacity, n_pairs, pairs, s);
+    return emit_pairs<uint64_t>(order, w, proj, N, VN, txs, tpv, pk.rank_bits, capacity, n_pairs, pairs, s);
 }
 
 size_t sort_workspace_bytes(int64_t capacity, int32_t, int32_t) { return sort_layout(capacity, nullptr).bytes; }
@@ -289,21 +423,12 @@ potr_status launch_sort(int64_t N, int32_t V, int32_t tiles_per_view, const int6
     hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)ceil_div(ranges_n, 256)), dim3(256), 0, s, tile_ranges, ranges_n, 0);
     potr_status st = check_launch("k_fill_i32");
     if (st != POTR_OK || n_max == 0) return st;
-    int bits = 1;
-    while ((int64_t(1) << bits) < (int64_t)V * tiles_per_view) ++bits;
-    const int passes = (bits + 7) / 8;
-    const int per = (bits + passes - 1) / passes;
-    RadixGeom g{0, n_pairs, n_max, (int32_t)ceil_div(n_max, kRadixTile)};
-    uint64_t *kin = pairs, *kout = w.alt;
-    for (int p = 0; p < passes; ++p) {
-        const int b = (p == passes - 1) ? bits - per * p : per;
-        st = radix_pass<uint64_t, false>(kin, kout, nullptr, nullptr, g, 1, 32 + per * p, b, w.hist, w.scan_tmp, s);
-        if (st != POTR_OK) return st;
-        uint64_t* t = kin; kin = kout; kout = t;
-    }
-    hipLaunchKernelGGL(k_finalize, dim3((unsigned)ceil_div(n_max, 256)), dim3(256), 0, s, (const uint64_t*)kin,
-                       n_pairs, n_max, order, N, tiles_per_view, sorted_ids, tile_ranges);
-    return check_launch("k_finalize");
+    const Packing pk = packing(N, V, tiles_per_view);
+    if (pk.u32)
+        return sort_pairs<uint32_t>(N, V, tiles_per_view, pk, n_pairs, n_max, pairs, order, w, sorted_ids,
+                                    tile_ranges, s);
+    return sort_pairs<uint64_t>(N, V, tiles_per_view, pk, n_pairs, n_max, pairs, order, w, sorted_ids, tile_ranges,
+                                s);
 }
 
 }  // namespace potr

@@ -108,3 +108,36 @@ def test_workspace_too_small_is_capacity_error(lib):
 def test_workspace_sizes_grow(lib):
     assert L.bin_workspace_size(10_000, 1) < L.bin_workspace_size(100_000, 1) < L.bin_workspace_size(100_000, 4)
     assert L.sort_workspace_size(1000, 1, 100) < L.sort_workspace_size(10_000_000, 1, 100)
+
+
+def test_new_entry_points_validate(lib):
+    cfg = _cfg()
+    out = C.c_void_p()
+    # no jobs
+    assert _status("potr_batch_create", None, 0, C.byref(cfg), 0.05, C.byref(out), None) == L.POTR_EINVAL
+    # a job with a NULL buffer
+    j = L.potr_job()
+    j.N, j.V = 100, 1
+    cams = _cams(1)
+    j.cams = C.cast(cams, C.POINTER(L.potr_camera))
+    arr = (L.potr_job * 1)(j)
+    assert _status("potr_batch_create", arr, 1, C.byref(cfg), 0.05, C.byref(out), None) == L.POTR_EINVAL
+    assert "NULL" in lib.potr_last_error().decode()
+    # autotune without jobs
+    assert _status("potr_autotune", None, 0, C.byref(cfg), 1, None, None, None, None, None) == L.POTR_EINVAL
+    # operations on a batch that does not exist
+    assert _status("potr_batch_run", None, None) == L.POTR_EINVAL
+    assert _status("potr_batch_replay", None, None) == L.POTR_EINVAL
+    assert _status("potr_batch_destroy", None) == L.POTR_OK
+    # fused call without any output
+    assert _status("potr_render_score", 10, 1, _cams(), C.byref(cfg), 16, 16, 16, None, None, None, None, None,
+                   None) == L.POTR_EINVAL
+    # squared error without a target
+    assert _status("potr_render_score", 10, 1, _cams(), C.byref(cfg), 16, 16, 16, None, None, None, 16, None,
+                   None) == L.POTR_EINVAL
+    # backward with a workspace that is too small
+    b = C.c_size_t(0)
+    assert _status("potr_backward_workspace_size", 1000, 2, C.byref(b)) == L.POTR_OK
+    assert b.value == 1000 * 2 * 9 * 4
+    args = [1000, 2, _cams(2), C.byref(cfg)] + [16] * 12 + [16, b.value - 4] + [16] * 5 + [None]
+    assert _status("potr_backward", *args) == L.POTR_ECAPACITY

@@ -74,7 +74,9 @@ def _upload_records(rect, depth, V, N):
 
 
 @pytest.mark.parametrize("N,V,tiles,seed", [(1, 1, (3, 2), 1), (300, 1, (7, 5), 2), (5000, 3, (20, 13), 3),
-                                             (20000, 2, (80, 45), 4), (4096 * 3 + 17, 1, (33, 21), 5)])
+                                             (20000, 2, (80, 45), 4), (4096 * 3 + 17, 1, (33, 21), 5),
+                                             # 16 (view, tile) bits + 17 rank bits: 64-bit pairs
+                                             (70000, 3, (128, 128), 6)])
 def test_bin_sort_bit_exact_on_synthetic_records(N, V, tiles, seed):
     _need_gpu()
     tx, ty = tiles
