@@ -121,9 +121,10 @@ POTR_API potr_status potr_project(int64_t N, int32_t V, const potr_camera* cams,
  * splats by depth key (ties by splat id) and emit one (tile, depth rank) pair per
  * tile of every splat's rect, in depth order.
  *   order  [V*N] uint32 out: order[v*N + r] = id of the splat with depth rank r in view v
- *   pairs  [capacity] 8-byte slots out: key (v*tiles + tile, rank); packed into 32 bits
- *          as ((v*tiles + tile) << rank_bits) | rank when ceil(log2(V*tiles)) +
- *          ceil(log2 N) <= 32, else 64 bits with the rank in the low word
+ *   pairs  [capacity] 8-byte slots out: (v*tiles + tile, splat id) in depth-rank
+ *          order; packed into 32 bits as ((v*tiles + tile) << id_bits) | id when
+ *          ceil(log2(V*tiles)) + ceil(log2 N) <= 32, else 64 bits with the id
+ *          in the low word
  *   n_pairs (device) int64 out: total number of pairs. If it exceeds `capacity`,
  *          no pair is written; the caller grows `pairs` and calls again (the
  *          Python wrapper does this). Later stages treat such a count as empty.
@@ -138,6 +139,7 @@ POTR_API potr_status potr_bin(int64_t N, int32_t V, const potr_camera* cams, con
  * potr_sort -- stable radix sort of the pairs by (view, tile); since pairs are
  * emitted in depth-rank order this yields the order (view, tile, depth key,
  * splat id). Writes the splat id of every sorted pair and each tile's range.
+ * N, V and the cameras must be those given to potr_bin (they fix the packing).
  *   n_pairs  (device) from potr_bin; n_max (host) >= the count, bounds the launch
  *            (pass the count itself when known, else the capacity)
  *   pairs    [capacity] in: from potr_bin; clobbered
@@ -147,7 +149,7 @@ POTR_API potr_status potr_bin(int64_t N, int32_t V, const potr_camera* cams, con
  * ------------------------------------------------------------------------- */
 POTR_API potr_status potr_sort_workspace_size(int64_t capacity, int32_t V, int32_t tiles_per_view, size_t* bytes);
 POTR_API potr_status potr_sort(int64_t N, int32_t V, const potr_camera* cams, const potr_config* cfg,
-                      const int64_t* n_pairs, int64_t n_max, uint64_t* pairs, const uint32_t* order,
+                      const int64_t* n_pairs, int64_t n_max, uint64_t* pairs,
                       void* ws, size_t ws_bytes, uint32_t* sorted_ids, int32_t* tile_ranges, void* stream);
 
 /* ---------------------------------------------------------------------------

@@ -52,7 +52,7 @@ SIGNATURES = {
     "potr_bin_workspace_size": (_i32, [_i64, _i32, C.POINTER(_sz)]),
     "potr_bin": (_i32, [_i64, _i32, _CAM_P, _CFG_P, _vp, _vp, _vp, _sz, _vp, _vp, _i64, _vp, _vp]),
     "potr_sort_workspace_size": (_i32, [_i64, _i32, _i32, C.POINTER(_sz)]),
-    "potr_sort": (_i32, [_i64, _i32, _CAM_P, _CFG_P, _vp, _i64, _vp, _vp, _vp, _sz, _vp, _vp, _vp]),
+    "potr_sort": (_i32, [_i64, _i32, _CAM_P, _CFG_P, _vp, _i64, _vp, _vp, _sz, _vp, _vp, _vp]),
     "potr_blend": (_i32, [_i64, _i32, _CAM_P, _CFG_P, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "potr_score": (_i32, [_i64, _i32, _CAM_P, _CFG_P, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "potr_blend_backward": (_i32, [_i64, _i32, _CAM_P, _CFG_P, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),

@@ -118,18 +118,17 @@ potr_status potr_sort_workspace_size(int64_t capacity, int32_t V, int32_t tiles_
 }
 
 potr_status potr_sort(int64_t N, int32_t V, const potr_camera* cams, const potr_config* cfg,
-                      const int64_t* n_pairs, int64_t n_max, uint64_t* pairs, const uint32_t* order, void* ws,
-                      size_t ws_bytes, uint32_t* sorted_ids, int32_t* tile_ranges, void* stream) {
+                      const int64_t* n_pairs, int64_t n_max, uint64_t* pairs, void* ws, size_t ws_bytes, uint32_t* sorted_ids, int32_t* tile_ranges, void* stream) {
     potr_status st = check_cfg(cfg);
     if (st == POTR_OK) st = check_cams(V, cams, cfg);
     if (st != POTR_OK) return st;
     if (n_max < 0 || n_max >= (int64_t(1) << 31)) return fail(POTR_EINVAL, "n_max out of range");
-    if (!n_pairs || !tile_ranges || (n_max > 0 && (!pairs || !order || !ws || !sorted_ids)))
+    if (!n_pairs || !tile_ranges || (n_max > 0 && (!pairs || !ws || !sorted_ids)))
         return fail(POTR_EINVAL, "NULL buffer");
     const int32_t tpv = tiles_x(cams[0], *cfg) * tiles_y(cams[0], *cfg);
     if (ws_bytes < sort_workspace_bytes(n_max, V, tpv))
         return fail(POTR_ECAPACITY, "sort workspace %zu < %zu bytes", ws_bytes, sort_workspace_bytes(n_max, V, tpv));
-    return launch_sort(N, V, tpv, n_pairs, n_max, pairs, order, ws, sorted_ids, tile_ranges, (hipStream_t)stream);
+    return launch_sort(N, V, tpv, n_pairs, n_max, pairs, ws, sorted_ids, tile_ranges, (hipStream_t)stream);
 }
 
 potr_status potr_blend(int64_t N, int32_t V, const potr_camera* cams, const potr_config* cfg,

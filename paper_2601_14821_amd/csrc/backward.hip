@@ -92,16 +92,20 @@ __global__ __launch_bounds__(TW * TH) void k_blend_bwd(int64_t N, int32_t W, int
             s_rows[j] = reach_rows(a, b, qmax, tile_y0, TH);
         }
         __syncthreads();
-        for (int j = 0; j < cnt; ++j) {
-            if (!rows_overlap(__builtin_amdgcn_readfirstlane(s_rows[j]), row_lo, row_hi)) {
-                if (lane == 0)
+        // groups of four entries: per-lane gradients, then one reduce-scatter per component
+        for (int j0 = 0; j0 < cnt; j0 += 4) {
+            float g[4][kG];
 #pragma unroll
-                    for (int c = 0; c < kG; ++c) s_part[c][wid][j] = 0.f;
-                continue;
-            }
-            float g[kG] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int c = 0; c < kG; ++c) g[u][c] = 0.f;
             bool any = false;
-            if (base + j < walk) {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int j = j0 + u;
+                if (j >= cnt) continue;
+                if (!rows_overlap(__builtin_amdgcn_readfirstlane(s_rows[j]), row_lo, row_hi)) continue;
+                if (base + j >= walk) continue;
                 const float4 a = s_a[j];
                 const float4 b = s_b[j];
                 const Gauss e = eval_gauss(a, b, fx, fy);
@@ -116,31 +120,28 @@ __global__ __launch_bounds__(TW * TH) void k_blend_bwd(int64_t N, int32_t W, int
                     const float inv = __builtin_amdgcn_rcpf(1.f - al);
                     const float dLda = gr * (T * cr - (PKr - Pr + Br) * inv) + gg * (T * cg - (PKg - Pg + Bg) * inv) +
                                        gb * (T * cb - (PKb - Pb + Bb) * inv);
-                    g[6] = gr * w;
-                    g[7] = gg * w;
-                    g[8] = gb * w;
+                    g[u][6] = gr * w;
+                    g[u][7] = gg * w;
+                    g[u][8] = gb * w;
                     if (al0 < amax) {
-                        g[5] = dLda * e.G;                        // dalpha/do = G
+                        g[u][5] = dLda * e.G;                      // dalpha/do = G
                         const float dLdq = -0.5f * al0 * dLda;
-                        g[0] = dLdq * 2.f * (b.x * dx + a.w * dy);
-                        g[1] = dLdq * 2.f * (a.w * dx + b.y * dy);
-                        g[2] = dLdq * dx * dx;
-                        g[3] = dLdq * 2.f * dx * dy;
-                        g[4] = dLdq * dy * dy;
+                        g[u][0] = dLdq * 2.f * (b.x * dx + a.w * dy);
+                        g[u][1] = dLdq * 2.f * (a.w * dx + b.y * dy);
+                        g[u][2] = dLdq * dx * dx;
+                        g[u][3] = dLdq * 2.f * dx * dy;
+                        g[u][4] = dLdq * dy * dy;
                     }
                     any = true;
                     T = next_T(T, al);
                 }
             }
-            if (__ballot(any)) {
+            const bool wave_any = __ballot(any) != 0;
+            const bool writer = lane < 4 && j0 + lane < cnt;
 #pragma unroll
-                for (int c = 0; c < kG; ++c) {
-                    const float s = wave_sum(g[c]);
-                    if (lane == 0) s_part[c][wid][j] = s;
-                }
-            } else if (lane == 0) {
-#pragma unroll
-                for (int c = 0; c < kG; ++c) s_part[c][wid][j] = 0.f;
+            for (int c = 0; c < kG; ++c) {
+                const float s = wave_any ? wave_sum4(g[0][c], g[1][c], g[2][c], g[3][c]) : 0.f;
+                if (writer) s_part[c][wid][j0 + lane] = s;
             }
         }
         __syncthreads();

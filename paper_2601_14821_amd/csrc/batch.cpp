@@ -242,7 +242,7 @@ potr_status potr_batch_run(potr_batch b, void* stream) {
             st = launch_bin(J.N, J.V, cams[0], b->cfg, proj, tt, ws + b->off_bin, order, pairs, b->capacity[j],
                             npairs + j, s);
         if (st == POTR_OK)
-            st = launch_sort(J.N, J.V, T, npairs + j, b->capacity[j], pairs, order, ws + b->off_sort, ids, ranges, s);
+            st = launch_sort(J.N, J.V, T, npairs + j, b->capacity[j], pairs, ws + b->off_sort, ids, ranges, s);
         if (st != POTR_OK) return st;
     }
     potr_status st = launch_render_score_persistent((const ViewJob*)(ws + b->off_table), b->n_view_jobs,

@@ -49,8 +49,7 @@ potr_status launch_bin(int64_t N, int32_t V, const potr_camera& cam0, const potr
 
 size_t sort_workspace_bytes(int64_t capacity, int32_t V, int32_t tiles_per_view);
 potr_status launch_sort(int64_t N, int32_t V, int32_t tiles_per_view, const int64_t* n_pairs, int64_t n_max,
-                        uint64_t* pairs, const uint32_t* order, void* ws, uint32_t* sorted_ids,
-                        int32_t* tile_ranges, hipStream_t s);
+                        uint64_t* pairs, void* ws, uint32_t* sorted_ids, int32_t* tile_ranges, hipStream_t s);
 
 potr_status launch_blend(int64_t N, int32_t V, const potr_camera& cam0, const potr_config& cfg,
                          const potr_proj* proj, const uint32_t* sorted_ids, const int32_t* tile_ranges,

@@ -146,10 +146,22 @@ __global__ __launch_bounds__(256) void k_project(int64_t N, int32_t v0, int32_t 
                 double Y[16];
                 sh_basis_d3(dx, dy, dz, cfg.sh_degree, Y);
                 double cr = 0.5, cg = 0.5, cb = 0.5;
-                for (int k = 0; k < nsh; ++k) {
-                    cr += (double)shp[3 * k] * Y[k];
-                    cg += (double)shp[3 * k + 1] * Y[k];
-                    cb += (double)shp[3 * k + 2] * Y[k];
+                // 16-byte loads: four coefficients (r,g,b of k and r of k+1, ...) at a time
+                const float4* sh4 = reinterpret_cast<const float4*>(shp);
+                const int n4 = (3 * nsh + 3) / 4;
+                for (int m = 0; m < n4; ++m) {
+                    const float4 q = sh4[m];
+                    const float f[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+                    for (int t = 0; t < 4; ++t) {
+                        const int e = 4 * m + t;          // flat index k*3 + channel
+                        if (e >= 3 * nsh) break;
+                        const double y = Y[e / 3];
+                        const int ch = e - 3 * (e / 3);
+                        if (ch == 0) cr += (double)f[t] * y;
+                        else if (ch == 1) cg += (double)f[t] * y;
+                        else cb += (double)f[t] * y;
+                    }
                 }
                 rec.rgb[0] = (float)fmax(0.0, cr);
                 rec.rgb[1] = (float)fmax(0.0, cg);

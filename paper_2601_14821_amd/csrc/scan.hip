@@ -89,8 +89,8 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_down(const TI* in, int64_
     }
 }
 
-// Whole scan in one workgroup of 1024 threads (small inputs: one launch instead
-// of three). Items are consumed in tiles of 1024 x 8, blocked per thread.
+// Whole scan in one workgroup of 1024 threads for inputs of at most one tile
+// (1024 x 8 items): one launch instead of three.
 constexpr int kOneThreads = 1024, kOneItems = 8;
 
 template <typename T>
@@ -141,7 +141,7 @@ __global__ __launch_bounds__(kOneThreads) void k_scan_one(const TI* in, int64_t 
 template <typename TI, typename TO>
 potr_status scan_impl(const TI* in, TO* out, int64_t n, TO* total, void* tmp, hipStream_t s) {
     TO* sums = reinterpret_cast<TO*>(tmp);
-    if (n > 0 && n <= (int64_t(1) << 18)) {
+    if (n > 0 && n <= (int64_t)kOneThreads * kOneItems) {
         hipLaunchKernelGGL((k_scan_one<TI, TO>), dim3(1), dim3(kOneThreads), 0, s, in, n, out, total);
         return check_launch("k_scan_one");
     }

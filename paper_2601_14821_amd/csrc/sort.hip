@@ -4,13 +4,14 @@
 // potr_bin: per view, a stable radix sort of the N depth keys (ties keep splat
 //   id order) gives each splat its depth rank; a scan of tiles_touched in rank
 //   order places every splat's (tile, rank) pairs, emitted in rank order.
-// potr_sort: a stable radix sort of the pairs on the (view, tile) bits only. The
-//   rank bits are already ordered, so the result is ordered by
-//   (view, tile, depth key, splat id) -- the full key -- while only
-//   ceil(log2(V * tiles)) bits are sorted instead of tile + 32 depth bits.
+// potr_sort: a stable radix sort of the pairs on the (view, tile) bits only.
+//   Pairs were emitted in depth-rank order and the sort is stable, so the
+//   result is ordered by (view, tile, depth key, splat id) -- the full key --
+//   while only ceil(log2(V * tiles)) bits are sorted instead of tile + 32 depth
+//   bits. The low bits carry the splat id as payload.
 //
-// Pairs are packed as ((view * tiles + tile) << rank_bits) | rank in 32 bits
-// when both fields fit, else in 64 bits with the rank in the low word.
+// Pairs are packed as ((view * tiles + tile) << id_bits) | splat id in 32 bits
+// when both fields fit, else in 64 bits with the id in the low word.
 //
 // Each radix pass is histogram -> exclusive scan of the [segment][digit][block]
 // counts -> scatter. Blocks take ITEMS x 256 consecutive elements; within a
@@ -210,23 +211,24 @@ __global__ __launch_bounds__(256) void k_emit(const uint32_t* __restrict__ order
                                               K* __restrict__ pairs) {
     __shared__ int64_t s_off[256];
     __shared__ uint32_t s_key0[256];      // (view * tiles + y0 * tiles_x + x0)
-    __shared__ uint32_t s_rank[256];
+    __shared__ uint32_t s_sid[256];       // splat id
     __shared__ uint16_t s_w[256];
     if (*n_pairs > capacity) return;
     const int64_t i0 = (int64_t)blockIdx.x * 256;
     const int64_t i = i0 + threadIdx.x;
     int64_t my_off = 0;
     if (i < total) {
-        const int64_t v = i / N, r = i - v * N;
+        const int64_t v = i / N;
         const int32_t c = cnt[i];
         my_off = offs[i];
-        const potr_proj& p = proj[v * N + order[i]];
+        const uint32_t id = order[i];
+        const potr_proj& p = proj[v * N + id];
         s_key0[threadIdx.x] = (uint32_t)(v * tiles_per_view + p.rect[1] * tiles_x + p.rect[0]);
-        s_rank[threadIdx.x] = (uint32_t)r;
+        s_sid[threadIdx.x] = id;
         s_w[threadIdx.x] = (uint16_t)(c > 0 ? p.rect[2] - p.rect[0] : 1);
     } else {
         s_key0[threadIdx.x] = 0;
-        s_rank[threadIdx.x] = 0;
+        s_sid[threadIdx.x] = 0;
         s_w[threadIdx.x] = 1;
     }
     s_off[threadIdx.x] = my_off;
@@ -246,9 +248,9 @@ __global__ __launch_bounds__(256) void k_emit(const uint32_t* __restrict__ order
         const uint32_t ty = t / wdt, tx = t - ty * wdt;
         const uint64_t g = (uint64_t)s_key0[lo] + (uint64_t)ty * (uint32_t)tiles_x + tx;
         if (sizeof(K) == 4)
-            pairs[p] = (K)((g << rank_bits) | s_rank[lo]);
+            pairs[p] = (K)((g << rank_bits) | s_sid[lo]);
         else
-            pairs[p] = (K)((g << 32) | s_rank[lo]);
+            pairs[p] = (K)((g << 32) | s_sid[lo]);
     }
 }
 
@@ -260,8 +262,7 @@ __global__ void k_fill_i32(int32_t* p, int64_t n, int32_t v) {
 
 template <typename K>
 __global__ void k_finalize(const K* __restrict__ sorted, const int64_t* __restrict__ n_pairs, int64_t cap,
-                           const uint32_t* __restrict__ order, int64_t N, int32_t tiles_per_view, int rank_bits,
-                           uint32_t* __restrict__ ids, int32_t* __restrict__ ranges) {
+                           int rank_bits, uint32_t* __restrict__ ids, int32_t* __restrict__ ranges) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     int64_t n = *n_pairs;
     if (n > cap) n = 0;
@@ -270,9 +271,7 @@ __global__ void k_finalize(const K* __restrict__ sorted, const int64_t* __restri
     const uint64_t rmask = sizeof(K) == 4 ? ((1ull << rank_bits) - 1) : 0xffffffffull;
     const K p = sorted[i];
     const uint32_t gt = (uint32_t)((uint64_t)p >> sh);
-    const uint32_t r = (uint32_t)((uint64_t)p & rmask);
-    const uint32_t v = gt / (uint32_t)tiles_per_view;
-    ids[i] = order[(int64_t)v * N + r];
+    ids[i] = (uint32_t)((uint64_t)p & rmask);
     if (i == 0 || (uint32_t)((uint64_t)sorted[i - 1] >> sh) != gt) ranges[2 * (int64_t)gt] = (int32_t)i;
     if (i == n - 1 || (uint32_t)((uint64_t)sorted[i + 1] >> sh) != gt) ranges[2 * (int64_t)gt + 1] = (int32_t)(i + 1);
 }
@@ -355,7 +354,7 @@ potr_status emit_pairs(const uint32_t* order, const BinWs& w, const potr_proj* p
 
 template <typename K>
 potr_status sort_pairs(int64_t N, int32_t V, int32_t tpv, const Packing& pk, const int64_t* n_pairs, int64_t n_max,
-                       void* pairs, const uint32_t* order, const SortWs& w, uint32_t* sorted_ids,
+                       void* pairs, const SortWs& w, uint32_t* sorted_ids,
                        int32_t* tile_ranges, hipStream_t s) {
     const int bits = pk.tile_bits;
     const int passes = (bits + 7) / 8;
@@ -371,7 +370,7 @@ potr_status sort_pairs(int64_t N, int32_t V, int32_t tpv, const Packing& pk, con
         K* t = kin; kin = kout; kout = t;
     }
     hipLaunchKernelGGL(k_finalize<K>, dim3((unsigned)ceil_div(n_max, 256)), dim3(256), 0, s, (const K*)kin, n_pairs,
-                       n_max, order, N, tpv, pk.rank_bits, sorted_ids, tile_ranges);
+                       n_max, pk.rank_bits, sorted_ids, tile_ranges);
     return check_launch("k_finalize");
 }
 
@@ -416,8 +415,7 @@ potr_status launch_bin(int64_t N, int32_t V, const potr_camera& cam0, const potr
 size_t sort_workspace_bytes(int64_t capacity, int32_t, int32_t) { return sort_layout(capacity, nullptr).bytes; }
 
 potr_status launch_sort(int64_t N, int32_t V, int32_t tiles_per_view, const int64_t* n_pairs, int64_t n_max,
-                        uint64_t* pairs, const uint32_t* order, void* ws, uint32_t* sorted_ids,
-                        int32_t* tile_ranges, hipStream_t s) {
+                        uint64_t* pairs, void* ws, uint32_t* sorted_ids, int32_t* tile_ranges, hipStream_t s) {
     SortWs w = sort_layout(n_max, (char*)ws);
     const int64_t ranges_n = 2 * (int64_t)V * tiles_per_view;
     hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)ceil_div(ranges_n, 256)), dim3(256), 0, s, tile_ranges, ranges_n, 0);
@@ -425,9 +423,9 @@ potr_status launch_sort(int64_t N, int32_t V, int32_t tiles_per_view, const int6
     if (st != POTR_OK || n_max == 0) return st;
     const Packing pk = packing(N, V, tiles_per_view);
     if (pk.u32)
-        return sort_pairs<uint32_t>(N, V, tiles_per_view, pk, n_pairs, n_max, pairs, order, w, sorted_ids,
+        return sort_pairs<uint32_t>(N, V, tiles_per_view, pk, n_pairs, n_max, pairs, w, sorted_ids,
                                     tile_ranges, s);
-    return sort_pairs<uint64_t>(N, V, tiles_per_view, pk, n_pairs, n_max, pairs, order, w, sorted_ids, tile_ranges,
+    return sort_pairs<uint64_t>(N, V, tiles_per_view, pk, n_pairs, n_max, pairs, w, sorted_ids, tile_ranges,
                                 s);
 }
 

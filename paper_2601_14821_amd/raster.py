@@ -116,7 +116,7 @@ class Rasterizer:
         ids = self._i32("sorted_ids", n)
         ranges = self._i32("ranges", 2 * vb.V * tx * ty)[: 2 * vb.V * tx * ty]
         L.call("potr_sort", vb.N, vb.V, L.make_cameras(cams), C.byref(self.cfg), L.ptr(vb._n_pairs_dev), n,
-               L.ptr(vb._pairs), L.ptr(vb.order), L.ptr(ws), ws.numel(), L.ptr(ids), L.ptr(ranges),
+               L.ptr(vb._pairs), L.ptr(ws), ws.numel(), L.ptr(ids), L.ptr(ranges),
                L.stream_handle())
         vb.sorted_ids, vb.tile_ranges = ids, ranges
         return vb

@@ -101,7 +101,7 @@ def test_workspace_too_small_is_capacity_error(lib):
     assert st == L.POTR_ECAPACITY
     tx, ty = synth.RenderSettings().tiles(synth.ring_cameras(1, 64, 48)[0])
     need = L.sort_workspace_size(5000, 2, tx * ty)
-    st = _status("potr_sort", 1000, 2, _cams(2), C.byref(cfg), 16, 5000, 16, 16, 16, need - 1, 16, 16, None)
+    st = _status("potr_sort", 1000, 2, _cams(2), C.byref(cfg), 16, 5000, 16, 16, need - 1, 16, 16, None)
     assert st == L.POTR_ECAPACITY
 
 
