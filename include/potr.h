@@ -126,8 +126,10 @@ POTR_API potr_status potr_project(int64_t N, int32_t V, const potr_camera* cams,
  *          ceil(log2(V*tiles)) + ceil(log2 N) <= 32, else 64 bits with the id
  *          in the low word
  *   n_pairs (device) int64 out: total number of pairs. If it exceeds `capacity`,
- *          no pair is written; the caller grows `pairs` and calls again (the
- *          Python wrapper does this). Later stages treat such a count as empty.
+ *          only the first `capacity` pairs are written; the caller grows `pairs`
+ *          and calls again (the Python wrapper does this). Later stages treat
+ *          such a count as empty. -1 reports that a device-side wait of the
+ *          ordering gave up (an internal error; later stages treat it as empty).
  *   ws     workspace of potr_bin_workspace_size bytes.
  * ------------------------------------------------------------------------- */
 POTR_API potr_status potr_bin_workspace_size(int64_t N, int32_t V, size_t* bytes);

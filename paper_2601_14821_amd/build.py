@@ -20,7 +20,7 @@ LIB = os.path.join(HERE, "libpotr.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("POTR_ARCH", "gfx950")
 
-SOURCES = ["api.cpp", "batch.cpp", "project.hip", "scan.hip", "sort.hip", "blend.hip", "backward.hip", "fused.hip",
+SOURCES = ["api.cpp", "batch.cpp", "project.hip", "sort.hip", "blend.hip", "backward.hip", "fused.hip",
            "batch_kernels.hip"]
 
 FLAGS = [

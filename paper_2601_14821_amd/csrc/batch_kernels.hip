@@ -25,7 +25,7 @@ __global__ void k_check_overflow(const int64_t* __restrict__ n_pairs, const int6
                                  int32_t* __restrict__ flag) {
     if (threadIdx.x != 0) return;
     int32_t bad = 0;
-    for (int32_t j = 0; j < n; ++j) bad += n_pairs[j] > caps[j] ? 1 : 0;
+    for (int32_t j = 0; j < n; ++j) bad += (n_pairs[j] > caps[j] || n_pairs[j] < 0) ? 1 : 0;
     *flag = bad;
 }
 

@@ -51,10 +51,12 @@ __global__ __launch_bounds__(TW * TH) void k_blend(int64_t N, int32_t W, int32_t
                                                    float* __restrict__ p_final, float* __restrict__ t_final,
                                                    int32_t* __restrict__ n_walk, int32_t* __restrict__ n_blend) {
     constexpr int NT = TW * TH;
+    constexpr int NW = (NT + 63) / 64;
     __shared__ float4 s_a[kMaxBatch];
     __shared__ float4 s_b[kMaxBatch];
     __shared__ float s_c[kMaxBatch];
     __shared__ uint32_t s_rows[kMaxBatch];
+    __shared__ __align__(8) uint16_t s_list[NW][kMaxBatch];
     const int tile = blockIdx.x, v = blockIdx.y;
     const int wid = threadIdx.x >> 6;
     const int row_lo = __builtin_amdgcn_readfirstlane((wid * 64) / TW);
@@ -78,34 +80,41 @@ __global__ __launch_bounds__(TW * TH) void k_blend(int64_t N, int32_t W, int32_t
         const int cnt = min(B, end - base);
         stage_batch<NT, TH>(pv, ids, base, cnt, s_a, s_b, s_c, nullptr, s_rows, qmax, tile_y0);
         __syncthreads();
-        if (!done) {
-            for (int j = 0; j < cnt; ++j) {
-                if (!rows_overlap(__builtin_amdgcn_readfirstlane(s_rows[j]), row_lo, row_hi)) continue;
-                const float4 a = s_a[j];
+        // this wave's entries (those reaching its rows), each step branch-free: a
+        // finished lane takes alpha = 0, which leaves T and the colour unchanged
+        uint16_t* const L = s_list[wid];
+        const int nl = wave_list(s_rows, cnt, row_lo, row_hi, L);
+        if (__ballot(!done) == 0) continue;
+        for (int i = 0; i < nl; i += 4) {
+            const uint2 q = *reinterpret_cast<const uint2*>(L + i);
+            const int js[4] = {(int)(q.x & 0xffffu), (int)(q.x >> 16), (int)(q.y & 0xffffu), (int)(q.y >> 16)};
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                if (i + u >= nl) break;
+                const int j = js[u];
                 const float4 b = s_b[j];
-                const float al = alpha_of(eval_gauss(a, b, fx, fy), qmax, amin, amax);
-                if (al == 0.f) continue;
+                const float a0 = alpha_of(eval_gauss(s_a[j], b, fx, fy), qmax, amin, amax);
+                const float al = done ? 0.f : a0;
                 const float Tn = next_T(T, al);
-                if (Tn < tmin) {
-                    done = true;
-                    walk = base - beg + j;
-                    break;
-                }
-                const float w = __fmul_rn(T, al);
+                const bool stop = Tn < tmin;       // T >= tmin before, so only when al > 0
+                const float w = stop ? 0.f : __fmul_rn(T, al);
                 cr = add_weighted(cr, w, b.z);
                 cg = add_weighted(cg, w, b.w);
                 cb = add_weighted(cb, w, s_c[j]);
-                T = Tn;
-                ++blended;
+                T = stop ? T : Tn;
+                walk = stop ? base - beg + j : walk;
+                blended += (al != 0.f && !stop) ? 1 : 0;
+                done = done || stop;
             }
+            if (__ballot(!done) == 0) break;
         }
     }
     if (!inside) return;
     if (!done) walk = end - beg;
     const int64_t pix = ((int64_t)v * H + py) * W + px;
-    image[3 * pix] = cr + T * cfg.bg[0];
-    image[3 * pix + 1] = cg + T * cfg.bg[1];
-    image[3 * pix + 2] = cb + T * cfg.bg[2];
+    image[3 * pix] = __fadd_rn(cr, __fmul_rn(T, cfg.bg[0]));
+    image[3 * pix + 1] = __fadd_rn(cg, __fmul_rn(T, cfg.bg[1]));
+    image[3 * pix + 2] = __fadd_rn(cb, __fmul_rn(T, cfg.bg[2]));
     if (p_final) {
         p_final[3 * pix] = cr;
         p_final[3 * pix + 1] = cg;
@@ -153,21 +162,20 @@ __global__ __launch_bounds__(TW * TH) void k_score(int64_t N, int32_t W, int32_t
     const bool want_l1 = scores != nullptr, want_se = scores_se != nullptr, want_im = importance != nullptr;
 
     int walk = 0;
-    float PKr = 0.f, PKg = 0.f, PKb = 0.f, TF = 0.f, er = 0.f, eg = 0.f, eb = 0.f;
+    float Qr = 0.f, Qg = 0.f, Qb = 0.f, er = 0.f, eg = 0.f, eb = 0.f;   // Q = P_K + T_final bg
     const int64_t pix = ((int64_t)v * H + py) * W + px;
     if (inside) {
         walk = n_walk[pix];
-        PKr = p_final[3 * pix];
-        PKg = p_final[3 * pix + 1];
-        PKb = p_final[3 * pix + 2];
-        TF = t_final[pix];
+        const float TF = t_final[pix];
+        Qr = __fadd_rn(p_final[3 * pix], __fmul_rn(TF, cfg.bg[0]));
+        Qg = __fadd_rn(p_final[3 * pix + 1], __fmul_rn(TF, cfg.bg[1]));
+        Qb = __fadd_rn(p_final[3 * pix + 2], __fmul_rn(TF, cfg.bg[2]));
         if (want_se) {   // c - c_t
-            er = PKr + TF * cfg.bg[0] - target[3 * pix];
-            eg = PKg + TF * cfg.bg[1] - target[3 * pix + 1];
-            eb = PKb + TF * cfg.bg[2] - target[3 * pix + 2];
+            er = Qr - target[3 * pix];
+            eg = Qg - target[3 * pix + 1];
+            eb = Qb - target[3 * pix + 2];
         }
     }
-    const float Br = TF * cfg.bg[0], Bg = TF * cfg.bg[1], Bb = TF * cfg.bg[2];
     if (threadIdx.x == 0) s_wmax = 0;
     __syncthreads();
     atomicMax(&s_wmax, walk);
@@ -196,9 +204,9 @@ __global__ __launch_bounds__(TW * TH) void k_score(int64_t N, int32_t W, int32_t
                     Pg = add_weighted(Pg, w, cg);
                     Pb = add_weighted(Pb, w, cbl);
                     const float k = odds(al);
-                    const float dr = -w * cr + k * (PKr - Pr + Br);
-                    const float dg = -w * cg + k * (PKg - Pg + Bg);
-                    const float db = -w * cbl + k * (PKb - Pb + Bb);
+                    const float dr = removal_delta(w, cr, k, Qr, Pr);
+                    const float dg = removal_delta(w, cg, k, Qg, Pg);
+                    const float db = removal_delta(w, cbl, k, Qb, Pb);
                     l1 = fabsf(dr) + fabsf(dg) + fabsf(db);
                     se = dr * dr + dg * dg + db * db + 2.f * (dr * er + dg * eg + db * eb);
                     im = w;

@@ -16,16 +16,6 @@ struct CamBatch {
     potr_camera c[kViewsPerLaunch];
 };
 
-// Radix sort geometry: 256 threads x 16 items per block.
-constexpr int kRadixThreads = 256;
-constexpr int kRadixItems = 16;
-constexpr int kRadixTile = kRadixThreads * kRadixItems;
-
-// Device-wide scan geometry.
-constexpr int kScanThreads = 256;
-constexpr int kScanItems = 16;
-constexpr int kScanTile = kScanThreads * kScanItems;
-
 inline int tiles_x(const potr_camera& c, const potr_config& g) { return (c.width + g.tile_w - 1) / g.tile_w; }
 inline int tiles_y(const potr_camera& c, const potr_config& g) { return (c.height + g.tile_h - 1) / g.tile_h; }
 
@@ -71,14 +61,5 @@ potr_status launch_project_backward(int64_t N, int32_t V, const potr_camera* cam
                                     const float* sh, const float* grad2d, float* d_means, float* d_scales,
                                     float* d_quats, float* d_opac, float* d_sh, hipStream_t s);
 potr_status launch_zero(float* p, int64_t n, hipStream_t s);
-
-// ---- device-wide helpers (scan.hip) ----
-// Exclusive scan of n int32 counts into int64 offsets; `total` (device, may be
-// null) receives the sum. `tmp` needs scan_tmp_bytes(n).
-size_t scan_tmp_bytes(int64_t n);
-potr_status scan_i32_to_i64(const int32_t* in, int64_t* out, int64_t n, int64_t* total, void* tmp,
-                            hipStream_t s);
-// Exclusive scan of n uint32 counts in place-capable form (out may alias in).
-potr_status scan_u32(const uint32_t* in, uint32_t* out, int64_t n, void* tmp, hipStream_t s);
 
 }  // namespace potr

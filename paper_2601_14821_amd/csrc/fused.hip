@@ -24,6 +24,8 @@ struct Smem {
     float* c;
     uint32_t* id;
     uint32_t* rows;    // reach_rows per entry
+    uint16_t* list;    // [NW][B] per-wave lists of the entries reaching the wave's rows
+    uint16_t* hits;    // [NW][B] per-wave lists of the entries some lane of the wave blended
     float* part;       // [n_out][NW][B]
     int* misc;         // [0]: wmax, [1]: next item
 };
@@ -45,6 +47,16 @@ __device__ inline void stage(const potr_proj* __restrict__ pv, const uint32_t* _
     }
 }
 
+// Four consecutive entries of a wave list (i a multiple of 4; entries at or
+// past the list's end are junk and must not be used).
+__device__ inline void list4(const uint16_t* L, int i, int (&j)[4]) {
+    const uint2 q = *reinterpret_cast<const uint2*>(L + i);
+    j[0] = (int)(q.x & 0xffffu);
+    j[1] = (int)(q.x >> 16);
+    j[2] = (int)(q.y & 0xffffu);
+    j[3] = (int)(q.y >> 16);
+}
+
 template <int TW, int TH, bool SE>
 __device__ void render_score_tile(const ViewJob& J, int tile, const potr_config& cfg, const Smem& sm) {
     constexpr int NT = TW * TH;
@@ -63,58 +75,76 @@ __device__ void render_score_tile(const ViewJob& J, int tile, const potr_config&
     const float qmax = cfg.q_max, amin = cfg.alpha_min, amax = cfg.alpha_max, tmin = cfg.t_min;
     const int n_out = (J.scores ? 1 : 0) + (J.importance ? 1 : 0) + (SE ? 1 : 0);
     const int o_l1 = 0, o_im = J.scores ? 1 : 0, o_se = o_im + (J.importance ? 1 : 0);
+    uint16_t* const L = sm.list + wid * B;
+    uint16_t* const Hl = sm.hits + wid * B;
 
-    // ---- blend sweep
+    // ---- blend sweep: each wave walks its own list of the batch; the steps
+    // are branch-free (a finished lane evaluates alpha = 0, which leaves T and
+    // the colour unchanged bit for bit)
     float T = 1.f, cr = 0.f, cg = 0.f, cb = 0.f;
     bool done = !inside;
     int walk = 0;
     int staged = -1;   // list offset of the batch now in LDS
+    int nl = 0;        // length of this wave's list for that batch
+    int nh = 0;        // length of this wave's list of blended entries for that batch
     for (int base = beg; base < end; base += B) {
         if (__syncthreads_count(!done) == 0) break;
         const int cnt = min(B, end - base);
         stage<NT, TH>(J.proj, J.ids, base, cnt, sm, qmax, tile_y0);
         staged = base;
         __syncthreads();
-        bool wave_done = __ballot(!done) == 0;
-        for (int j = 0; j < cnt && !wave_done; ++j) {
-            const uint32_t rr = __builtin_amdgcn_readfirstlane(sm.rows[j]);
-            if (!rows_overlap(rr, row_lo, row_hi)) continue;
-            if (!done) {
-                const float al = alpha_of(eval_gauss(sm.a[j], sm.b[j], fx, fy), qmax, amin, amax);
-                if (al != 0.f) {
-                    const float Tn = next_T(T, al);
-                    if (Tn < tmin) {
-                        done = true;
-                        walk = base - beg + j;
-                    } else {
-                        const float w = __fmul_rn(T, al);
-                        cr = add_weighted(cr, w, sm.b[j].z);
-                        cg = add_weighted(cg, w, sm.b[j].w);
-                        cb = add_weighted(cb, w, sm.c[j]);
-                        T = Tn;
-                    }
+        nl = wave_list(sm.rows, cnt, row_lo, row_hi, L);
+        nh = 0;
+        if (__ballot(!done) == 0) continue;
+        for (int i = 0; i < nl; i += 4) {
+            int js[4];
+            list4(L, i, js);
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                if (i + u >= nl) break;
+                const int j = js[u];
+                const float4 b = sm.b[j];
+                const float a0 = alpha_of(eval_gauss(sm.a[j], b, fx, fy), qmax, amin, amax);
+                const float al = done ? 0.f : a0;
+                const float Tn = next_T(T, al);
+                const bool stop = Tn < tmin;       // T >= tmin before, so only when al > 0
+                const float w = stop ? 0.f : __fmul_rn(T, al);
+                cr = add_weighted(cr, w, b.z);
+                cg = add_weighted(cg, w, b.w);
+                cb = add_weighted(cb, w, sm.c[j]);
+                T = stop ? T : Tn;
+                walk = stop ? base - beg + j : walk;
+                done = done || stop;
+                if (__ballot(al != 0.f && !stop) != 0) {
+                    if (lane == 0) Hl[nh] = (uint16_t)j;
+                    ++nh;
                 }
             }
-            wave_done = __ballot(!done) == 0;
+            if (__ballot(!done) == 0) break;
         }
     }
     if (inside && !done) walk = end - beg;
     const float TF = T, PKr = cr, PKg = cg, PKb = cb;
-    const float Br = TF * cfg.bg[0], Bg = TF * cfg.bg[1], Bb = TF * cfg.bg[2];
+    const float Qr = __fadd_rn(cr, __fmul_rn(TF, cfg.bg[0]));
+    const float Qg = __fadd_rn(cg, __fmul_rn(TF, cfg.bg[1]));
+    const float Qb = __fadd_rn(cb, __fmul_rn(TF, cfg.bg[2]));
     float er = 0.f, eg = 0.f, eb = 0.f;
     if (inside) {
         const int64_t pix = (int64_t)py * J.W + px;
         if (J.image) {
-            J.image[3 * pix] = cr + TF * cfg.bg[0];
-            J.image[3 * pix + 1] = cg + TF * cfg.bg[1];
-            J.image[3 * pix + 2] = cb + TF * cfg.bg[2];
+            J.image[3 * pix] = Qr;
+            J.image[3 * pix + 1] = Qg;
+            J.image[3 * pix + 2] = Qb;
         }
         if (SE) {
-            er = cr + TF * cfg.bg[0] - J.target[3 * pix];
-            eg = cg + TF * cfg.bg[1] - J.target[3 * pix + 1];
-            eb = cb + TF * cfg.bg[2] - J.target[3 * pix + 2];
+            er = Qr - J.target[3 * pix];
+            eg = Qg - J.target[3 * pix + 1];
+            eb = Qb - J.target[3 * pix + 2];
         }
     }
+    (void)PKr;
+    (void)PKg;
+    (void)PKb;
     if (n_out == 0) {
         __syncthreads();
         return;
@@ -126,61 +156,75 @@ __device__ void render_score_tile(const ViewJob& J, int tile, const potr_config&
     if (walk > 0) atomicMax(&sm.misc[0], walk);
     __syncthreads();
     const int wmax = sm.misc[0];
+    // this wave's longest walk bounds its entries; later ones contribute 0
+    int wave_walk = walk;
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) wave_walk = max(wave_walk, __shfl_xor(wave_walk, m, 64));
+    wave_walk = __builtin_amdgcn_readfirstlane(wave_walk);
     T = 1.f;
     float Pr = 0.f, Pg = 0.f, Pb = 0.f;
     for (int base = 0; base < wmax; base += B) {
         const int cnt = min(B, wmax - base);
+        // entries to revisit: those this wave blended when the batch is still the
+        // one the blend sweep left in LDS, else those reaching the wave's rows
+        const uint16_t* LL = Hl;
+        int nv = nh;
         if (staged != beg + base) {
             __syncthreads();
             stage<NT, TH>(J.proj, J.ids, beg + base, cnt, sm, qmax, tile_y0);
             staged = beg + base;
             __syncthreads();
+            nl = wave_list(sm.rows, cnt, row_lo, row_hi, L);
+            nh = 0;
+            LL = L;
+            nv = nl;
         }
-        // this wave's longest walk bounds its entries; later ones contribute 0
-        int wave_walk = walk;
-#pragma unroll
-        for (int m = 32; m >= 1; m >>= 1) wave_walk = max(wave_walk, __shfl_xor(wave_walk, m, 64));
-        wave_walk = __builtin_amdgcn_readfirstlane(wave_walk);
-        // entries in groups of four: per-lane values first, then one reduce-scatter
-        for (int j0 = 0; j0 < cnt; j0 += 4) {
+        // entries of this wave's list from jlim on lie past every lane's walk
+        const int jlim = min(cnt, wave_walk - base);
+        for (int j = lane; j < cnt; j += 64)
+            for (int o = 0; o < n_out; ++o) sm.part[(o * NW + wid) * B + j] = 0.f;
+        for (int i = 0; i < nv; i += 4) {
+            int js[4];
+            list4(LL, i, js);
+            if (js[0] >= jlim) break;
             float l1v[4] = {0.f, 0.f, 0.f, 0.f}, imv[4] = {0.f, 0.f, 0.f, 0.f}, sev[4] = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
-                const int j = j0 + u;
-                if (j >= cnt || base + j >= wave_walk) continue;
-                const uint32_t rr = __builtin_amdgcn_readfirstlane(sm.rows[j]);
-                if (!rows_overlap(rr, row_lo, row_hi) || base + j >= walk) continue;
+                if (i + u >= nv || js[u] >= jlim) break;
+                const int j = js[u];
                 const float4 b = sm.b[j];
-                const float al = alpha_of(eval_gauss(sm.a[j], b, fx, fy), qmax, amin, amax);
-                if (al != 0.f) {
-                    const float w = __fmul_rn(T, al);
-                    const float c0 = b.z, c1 = b.w, c2 = sm.c[j];
-                    Pr = add_weighted(Pr, w, c0);
-                    Pg = add_weighted(Pg, w, c1);
-                    Pb = add_weighted(Pb, w, c2);
-                    const float k = odds(al);
-                    const float dr = -w * c0 + k * (PKr - Pr + Br);
-                    const float dg = -w * c1 + k * (PKg - Pg + Bg);
-                    const float db = -w * c2 + k * (PKb - Pb + Bb);
-                    l1v[u] = fabsf(dr) + fabsf(dg) + fabsf(db);
-                    if (SE) sev[u] = dr * dr + dg * dg + db * db + 2.f * (dr * er + dg * eg + db * eb);
-                    imv[u] = w;
-                    T = next_T(T, al);
-                }
+                const float a0 = alpha_of(eval_gauss(sm.a[j], b, fx, fy), qmax, amin, amax);
+                const float al = base + j < walk ? a0 : 0.f;
+                const float w = __fmul_rn(T, al);
+                const float c0 = b.z, c1 = b.w, c2 = sm.c[j];
+                Pr = add_weighted(Pr, w, c0);
+                Pg = add_weighted(Pg, w, c1);
+                Pb = add_weighted(Pb, w, c2);
+                const float k = odds(al);
+                const float dr = removal_delta(w, c0, k, Qr, Pr);
+                const float dg = removal_delta(w, c1, k, Qg, Pg);
+                const float db = removal_delta(w, c2, k, Qb, Pb);
+                l1v[u] = fabsf(dr) + fabsf(dg) + fabsf(db);
+                if (SE) sev[u] = dr * dr + dg * dg + db * db + 2.f * (dr * er + dg * eg + db * eb);
+                imv[u] = w;
+                T = next_T(T, al);
             }
             const bool any = __ballot(imv[0] != 0.f || imv[1] != 0.f || imv[2] != 0.f || imv[3] != 0.f) != 0;
-            const bool writer = lane < 4 && j0 + lane < cnt;
+            if (!any) continue;
+            // lane u < 4 writes entry js[u] (only entries that are in the list)
+            const int jw = lane == 0 ? js[0] : lane == 1 ? js[1] : lane == 2 ? js[2] : js[3];
+            const bool writer = lane < 4 && i + lane < nv && jw < jlim;
             if (J.scores) {
-                const float s = any ? wave_sum4(l1v[0], l1v[1], l1v[2], l1v[3]) : 0.f;
-                if (writer) sm.part[(o_l1 * NW + wid) * B + j0 + lane] = s;
+                const float s = wave_sum4(l1v[0], l1v[1], l1v[2], l1v[3]);
+                if (writer) sm.part[(o_l1 * NW + wid) * B + jw] = s;
             }
             if (J.importance) {
-                const float s = any ? wave_sum4(imv[0], imv[1], imv[2], imv[3]) : 0.f;
-                if (writer) sm.part[(o_im * NW + wid) * B + j0 + lane] = s;
+                const float s = wave_sum4(imv[0], imv[1], imv[2], imv[3]);
+                if (writer) sm.part[(o_im * NW + wid) * B + jw] = s;
             }
             if (SE) {
-                const float s = any ? wave_sum4(sev[0], sev[1], sev[2], sev[3]) : 0.f;
-                if (writer) sm.part[(o_se * NW + wid) * B + j0 + lane] = s;
+                const float s = wave_sum4(sev[0], sev[1], sev[2], sev[3]);
+                if (writer) sm.part[(o_se * NW + wid) * B + jw] = s;
             }
         }
         __syncthreads();
@@ -209,7 +253,9 @@ __device__ inline Smem carve(char* base, int B) {
     s.c = reinterpret_cast<float*>(s.b + B);
     s.id = reinterpret_cast<uint32_t*>(s.c + B);
     s.rows = s.id + B;
-    s.part = reinterpret_cast<float*>(s.rows + B);
+    s.list = reinterpret_cast<uint16_t*>(s.rows + B);
+    s.hits = s.list + NW * B;
+    s.part = reinterpret_cast<float*>(s.hits + NW * B);
     s.misc = reinterpret_cast<int*>(s.part + 3 * NW * B);
     return s;
 }
@@ -253,7 +299,7 @@ __global__ void k_zero_i64(int64_t* p) { *p = 0; }
 template <int TW, int TH>
 size_t smem_bytes(int B) {
     constexpr int NW = (TW * TH + 63) / 64;
-    return (size_t)B * (16 + 16 + 4 + 4 + 4) + (size_t)3 * NW * B * 4 + 16;
+    return (size_t)B * (16 + 16 + 4 + 4 + 4) + (size_t)NW * B * 4 + (size_t)3 * NW * B * 4 + 16;
 }
 
 }  // namespace

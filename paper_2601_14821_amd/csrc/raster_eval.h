@@ -25,7 +25,8 @@ __device__ inline Gauss eval_gauss(const float4& a, const float4& b, float fx, f
     const float bd = __fmul_rn(__fmul_rn(2.f, a.w), r.dx);
     const float cd = __fmul_rn(b.y, r.dy);
     r.q = __fmaf_rn(ad, r.dx, __fmaf_rn(bd, r.dy, __fmul_rn(cd, r.dy)));
-    r.G = __expf(__fmul_rn(-0.5f, r.q));
+    // exp(-q/2) = exp2(q * (-log2(e) / 2)); halving the FP32 log2(e) is exact
+    r.G = __builtin_amdgcn_exp2f(__fmul_rn(r.q, -0x1.715476p-1f));
     r.al0 = __fmul_rn(a.z, r.G);
     return r;
 }
@@ -71,5 +72,30 @@ __device__ inline bool rows_overlap(uint32_t rr, int row_lo, int row_hi) {
 
 // alpha / (1 - alpha) with the hardware reciprocal (1 ulp), 1 - alpha >= 1 - alpha_max
 __device__ inline float odds(float al) { return al * __builtin_amdgcn_rcpf(1.f - al); }
+
+// Removal effect of one splat on one channel of one pixel:
+//   -w c + odds (Q - P),  Q = P_K + T_final bg,  P = partial colour through the splat.
+__device__ inline float removal_delta(float w, float c, float k, float Q, float P) {
+    return __fmaf_rn(-w, c, __fmul_rn(k, __fsub_rn(Q, P)));
+}
+
+// Per-wave list of the staged entries [0, cnt) whose reachable tile rows meet
+// the wave's rows [row_lo, row_hi], in increasing order; returns its length.
+// The list is written and read by the same wave only (LDS operations of one
+// wave complete in order).
+__device__ inline int wave_list(const uint32_t* rows, int cnt, int row_lo, int row_hi, uint16_t* list) {
+    const int lane = threadIdx.x & 63;
+    const uint64_t below = (1ull << lane) - 1ull;
+    int n = 0;
+    for (int c0 = 0; c0 < cnt; c0 += 64) {
+        const int j = c0 + lane;
+        const bool ok = j < cnt && rows_overlap(rows[j], row_lo, row_hi);
+        const uint64_t m = __ballot(ok);
+        if (ok) list[n + __popcll(m & below)] = (uint16_t)j;
+        n += __popcll(m);
+    }
+    __builtin_amdgcn_wave_barrier();
+    return n;
+}
 
 }  // namespace potr

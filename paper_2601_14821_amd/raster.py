@@ -100,6 +100,8 @@ class Rasterizer:
                    L.ptr(ws), ws.numel(), L.ptr(order), L.ptr(pairs), self.capacity, L.ptr(n_pairs),
                    L.stream_handle())
             n = int(n_pairs.item())
+            if n < 0:
+                raise L.PotrError("potr_bin", L.POTR_EHIP, "device-side ordering did not complete")
             if n <= self.capacity:
                 break
             self.capacity = int(n * 1.25) + 4096
