@@ -37,7 +37,7 @@
 extern "C" {
 #endif
 
-#define POTR_ABI_VERSION 1
+#define POTR_ABI_VERSION 2
 
 #define POTR_API __attribute__((visibility("default")))
 
@@ -118,41 +118,47 @@ POTR_API potr_status potr_project(int64_t N, int32_t V, const potr_camera* cams,
 
 /* ---------------------------------------------------------------------------
  * potr_bin -- Sec. 3 ("layers ordered by approximate depth"): order each view's
- * splats by depth key (ties by splat id) and emit one (tile, depth rank) pair per
- * tile of every splat's rect, in depth order.
+ * splats by depth key (ties by splat id) and count the (tile, splat) pairs:
+ * every tile of a splat's rect holds the splat. The counts are kept per group
+ * of 4096 consecutive depth ranks and per tile in the workspace, for potr_sort.
+ *   proj   [V*N] from potr_project (its depth keys and rects are read)
+ *   ws     workspace of potr_bin_workspace_size bytes; potr_sort reads it, so
+ *          it must stay untouched between the two calls
  *   order  [V*N] uint32 out: order[v*N + r] = id of the splat with depth rank r in view v
- *   pairs  [capacity] 8-byte slots out: (v*tiles + tile, splat id) in depth-rank
- *          order; packed into 32 bits as ((v*tiles + tile) << id_bits) | id when
- *          ceil(log2(V*tiles)) + ceil(log2 N) <= 32, else 64 bits with the id
- *          in the low word
- *   n_pairs (device) int64 out: total number of pairs. If it exceeds `capacity`,
- *          only the first `capacity` pairs are written; the caller grows `pairs`
- *          and calls again (the Python wrapper does this). Later stages treat
- *          such a count as empty. -1 reports that a device-side wait of the
- *          ordering gave up (an internal error; later stages treat it as empty).
- *   ws     workspace of potr_bin_workspace_size bytes.
+ *   n_pairs (device) int64 out: total number of pairs over all views; -1 if a
+ *          device-side wait of the ordering gave up (an internal error, which
+ *          later stages treat as "no pairs").
+ * Cost: the workspace holds the depth sort's keys and 8 bytes per (view, group
+ * of 4096 ranks, tile).
  * ------------------------------------------------------------------------- */
-POTR_API potr_status potr_bin_workspace_size(int64_t N, int32_t V, size_t* bytes);
+POTR_API potr_status potr_bin_workspace_size(int64_t N, int32_t V, const potr_camera* cams, const potr_config* cfg,
+                                    size_t* bytes);
 POTR_API potr_status potr_bin(int64_t N, int32_t V, const potr_camera* cams, const potr_config* cfg,
-                     const potr_proj* proj, const int32_t* tiles_touched, void* ws, size_t ws_bytes,
-                     uint32_t* order, uint64_t* pairs, int64_t capacity, int64_t* n_pairs, void* stream);
+                     const potr_proj* proj, void* ws, size_t ws_bytes, uint32_t* order, int64_t* n_pairs,
+                     void* stream);
 
 /* ---------------------------------------------------------------------------
- * potr_sort -- stable radix sort of the pairs by (view, tile); since pairs are
- * emitted in depth-rank order this yields the order (view, tile, depth key,
- * splat id). Writes the splat id of every sorted pair and each tile's range.
- * N, V and the cameras must be those given to potr_bin (they fix the packing).
- *   n_pairs  (device) from potr_bin; n_max (host) >= the count, bounds the launch
- *            (pass the count itself when known, else the capacity)
- *   pairs    [capacity] in: from potr_bin; clobbered
- *   sorted_ids [capacity] uint32 out: splat id (0..N-1) per sorted pair
- *   tile_ranges [V*tiles*2] int32 out: half-open [start, end) into sorted_ids
- *   ws       workspace of potr_sort_workspace_size bytes
+ * potr_sort -- each tile's list of splat ids in (depth key, splat id) order,
+ * all tiles of all views back to back in (view, tile) order: the order a sort
+ * of (view, tile, depth, id) keys gives, obtained by placing every pair
+ * directly from the counts potr_bin left in its workspace (no per-pair sort):
+ * first into its tile row, then, within each row, at its tile.
+ * N, V, cams, cfg, proj, order and ws are those of the potr_bin call before.
+ *   n_pairs  (device) from potr_bin
+ *   capacity (host) number of slots in sorted_ids; with more pairs than that
+ *            nothing is placed and every range is empty (grow and call again)
+ *   sort_ws  staging of potr_sort_workspace_size(capacity) bytes (6 per slot)
+ *   sorted_ids [capacity] uint32 out: splat id (0..N-1) of every pair
+ *   tile_ranges [V*tiles*2] int32 out: half-open [start, end) into sorted_ids;
+ *            [0, 0) for a tile without pairs
+ * Limits: tiles_x <= 1600 and tiles_y <= 1024 (LDS per workgroup); larger
+ * grids fail at launch with POTR_EHIP.
  * ------------------------------------------------------------------------- */
-POTR_API potr_status potr_sort_workspace_size(int64_t capacity, int32_t V, int32_t tiles_per_view, size_t* bytes);
+POTR_API potr_status potr_sort_workspace_size(int64_t capacity, size_t* bytes);
 POTR_API potr_status potr_sort(int64_t N, int32_t V, const potr_camera* cams, const potr_config* cfg,
-                      const int64_t* n_pairs, int64_t n_max, uint64_t* pairs,
-                      void* ws, size_t ws_bytes, uint32_t* sorted_ids, int32_t* tile_ranges, void* stream);
+                      const potr_proj* proj, const uint32_t* order, void* ws, size_t ws_bytes,
+                      const int64_t* n_pairs, int64_t capacity, void* sort_ws, size_t sort_ws_bytes,
+                      uint32_t* sorted_ids, int32_t* tile_ranges, void* stream);
 
 /* ---------------------------------------------------------------------------
  * potr_blend -- Sec. 3, eq. (alpha_blending): front-to-back compositing per pixel

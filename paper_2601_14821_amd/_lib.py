@@ -49,10 +49,10 @@ SIGNATURES = {
     "potr_abi_version": (_i32, []),
     "potr_last_error": (C.c_char_p, []),
     "potr_project": (_i32, [_i64, _i32, _CAM_P, _CFG_P, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
-    "potr_bin_workspace_size": (_i32, [_i64, _i32, C.POINTER(_sz)]),
-    "potr_bin": (_i32, [_i64, _i32, _CAM_P, _CFG_P, _vp, _vp, _vp, _sz, _vp, _vp, _i64, _vp, _vp]),
-    "potr_sort_workspace_size": (_i32, [_i64, _i32, _i32, C.POINTER(_sz)]),
-    "potr_sort": (_i32, [_i64, _i32, _CAM_P, _CFG_P, _vp, _i64, _vp, _vp, _sz, _vp, _vp, _vp]),
+    "potr_bin_workspace_size": (_i32, [_i64, _i32, _CAM_P, _CFG_P, C.POINTER(_sz)]),
+    "potr_bin": (_i32, [_i64, _i32, _CAM_P, _CFG_P, _vp, _vp, _sz, _vp, _vp, _vp]),
+    "potr_sort_workspace_size": (_i32, [_i64, C.POINTER(_sz)]),
+    "potr_sort": (_i32, [_i64, _i32, _CAM_P, _CFG_P, _vp, _vp, _vp, _sz, _vp, _i64, _vp, _sz, _vp, _vp, _vp]),
     "potr_blend": (_i32, [_i64, _i32, _CAM_P, _CFG_P, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "potr_score": (_i32, [_i64, _i32, _CAM_P, _CFG_P, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "potr_blend_backward": (_i32, [_i64, _i32, _CAM_P, _CFG_P, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
@@ -134,13 +134,15 @@ def make_config(s) -> potr_config:
     return c
 
 
-def bin_workspace_size(N: int, V: int) -> int:
+def bin_workspace_size(N: int, V: int, cams, cfg) -> int:
+    """Bytes of the workspace potr_bin fills and potr_sort reads (cams: a
+    make_cameras array, cfg: a potr_config)."""
     b = C.c_size_t(0)
-    call("potr_bin_workspace_size", N, V, C.byref(b))
+    call("potr_bin_workspace_size", N, V, cams, C.byref(cfg), C.byref(b))
     return b.value
 
 
-def sort_workspace_size(capacity: int, V: int, tiles_per_view: int) -> int:
+def sort_workspace_size(capacity: int) -> int:
     b = C.c_size_t(0)
-    call("potr_sort_workspace_size", capacity, V, tiles_per_view, C.byref(b))
+    call("potr_sort_workspace_size", capacity, C.byref(b))
     return b.value

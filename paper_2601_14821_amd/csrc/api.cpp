@@ -89,46 +89,51 @@ potr_status potr_project(int64_t N, int32_t V, const potr_camera* cams, const po
                           (hipStream_t)stream);
 }
 
-potr_status potr_bin_workspace_size(int64_t N, int32_t V, size_t* bytes) {
-    if (!bytes || N < 0 || V < 1) return fail(POTR_EINVAL, "bad arguments");
-    *bytes = bin_workspace_bytes(N, V);
+potr_status potr_bin_workspace_size(int64_t N, int32_t V, const potr_camera* cams, const potr_config* cfg,
+                                    size_t* bytes) {
+    if (!bytes || N < 0) return fail(POTR_EINVAL, "bad arguments");
+    potr_status st = check_cfg(cfg);
+    if (st == POTR_OK) st = check_cams(V, cams, cfg);
+    if (st != POTR_OK) return st;
+    *bytes = bin_workspace_bytes(N, V, tiles_x(cams[0], *cfg), tiles_y(cams[0], *cfg));
     return POTR_OK;
 }
 
 potr_status potr_bin(int64_t N, int32_t V, const potr_camera* cams, const potr_config* cfg, const potr_proj* proj,
-                     const int32_t* tiles_touched, void* ws, size_t ws_bytes, uint32_t* order, uint64_t* pairs,
-                     int64_t capacity, int64_t* n_pairs, void* stream) {
+                     void* ws, size_t ws_bytes, uint32_t* order, int64_t* n_pairs, void* stream) {
+    potr_status st = check_cfg(cfg);
+    if (st == POTR_OK) st = check_cams(V, cams, cfg);
+    if (st != POTR_OK) return st;
+    if (N < 0 || N * (int64_t)V >= (int64_t(1) << 31)) return fail(POTR_EINVAL, "N x V out of range");
+    if (!n_pairs || !ws || (N > 0 && (!proj || !order))) return fail(POTR_EINVAL, "NULL buffer");
+    const size_t need = bin_workspace_bytes(N, V, tiles_x(cams[0], *cfg), tiles_y(cams[0], *cfg));
+    if (ws_bytes < need) return fail(POTR_ECAPACITY, "bin workspace %zu < %zu bytes", ws_bytes, need);
+    return launch_bin(N, V, cams[0], *cfg, proj, ws, order, n_pairs, (hipStream_t)stream);
+}
+
+potr_status potr_sort_workspace_size(int64_t capacity, size_t* bytes) {
+    if (!bytes || capacity < 0 || capacity >= (int64_t(1) << 31)) return fail(POTR_EINVAL, "bad arguments");
+    *bytes = sort_workspace_bytes(capacity);
+    return POTR_OK;
+}
+
+potr_status potr_sort(int64_t N, int32_t V, const potr_camera* cams, const potr_config* cfg, const potr_proj* proj,
+                      const uint32_t* order, void* ws, size_t ws_bytes, const int64_t* n_pairs, int64_t capacity,
+                      void* sort_ws, size_t sort_ws_bytes, uint32_t* sorted_ids, int32_t* tile_ranges,
+                      void* stream) {
     potr_status st = check_cfg(cfg);
     if (st == POTR_OK) st = check_cams(V, cams, cfg);
     if (st != POTR_OK) return st;
     if (N < 0 || N * (int64_t)V >= (int64_t(1) << 31)) return fail(POTR_EINVAL, "N x V out of range");
     if (capacity < 0 || capacity >= (int64_t(1) << 31)) return fail(POTR_EINVAL, "capacity out of range");
-    if (!n_pairs || (N > 0 && (!proj || !tiles_touched || !ws || !order)) || (capacity > 0 && !pairs))
+    if (!n_pairs || !ws || !tile_ranges || !sort_ws || (N > 0 && (!proj || !order)) || (capacity > 0 && !sorted_ids))
         return fail(POTR_EINVAL, "NULL buffer");
-    if (ws_bytes < bin_workspace_bytes(N, V))
-        return fail(POTR_ECAPACITY, "bin workspace %zu < %zu bytes", ws_bytes, bin_workspace_bytes(N, V));
-    return launch_bin(N, V, cams[0], *cfg, proj, tiles_touched, ws, order, pairs, capacity, n_pairs,
-                      (hipStream_t)stream);
-}
-
-potr_status potr_sort_workspace_size(int64_t capacity, int32_t V, int32_t tiles_per_view, size_t* bytes) {
-    if (!bytes || capacity < 0 || V < 1 || tiles_per_view < 1) return fail(POTR_EINVAL, "bad arguments");
-    *bytes = sort_workspace_bytes(capacity, V, tiles_per_view);
-    return POTR_OK;
-}
-
-potr_status potr_sort(int64_t N, int32_t V, const potr_camera* cams, const potr_config* cfg,
-                      const int64_t* n_pairs, int64_t n_max, uint64_t* pairs, void* ws, size_t ws_bytes, uint32_t* sorted_ids, int32_t* tile_ranges, void* stream) {
-    potr_status st = check_cfg(cfg);
-    if (st == POTR_OK) st = check_cams(V, cams, cfg);
-    if (st != POTR_OK) return st;
-    if (n_max < 0 || n_max >= (int64_t(1) << 31)) return fail(POTR_EINVAL, "n_max out of range");
-    if (!n_pairs || !tile_ranges || (n_max > 0 && (!pairs || !ws || !sorted_ids)))
-        return fail(POTR_EINVAL, "NULL buffer");
-    const int32_t tpv = tiles_x(cams[0], *cfg) * tiles_y(cams[0], *cfg);
-    if (ws_bytes < sort_workspace_bytes(n_max, V, tpv))
-        return fail(POTR_ECAPACITY, "sort workspace %zu < %zu bytes", ws_bytes, sort_workspace_bytes(n_max, V, tpv));
-    return launch_sort(N, V, tpv, n_pairs, n_max, pairs, ws, sorted_ids, tile_ranges, (hipStream_t)stream);
+    const size_t need = bin_workspace_bytes(N, V, tiles_x(cams[0], *cfg), tiles_y(cams[0], *cfg));
+    if (ws_bytes < need) return fail(POTR_ECAPACITY, "bin workspace %zu < %zu bytes", ws_bytes, need);
+    if (sort_ws_bytes < sort_workspace_bytes(capacity))
+        return fail(POTR_ECAPACITY, "sort workspace %zu < %zu bytes", sort_ws_bytes, sort_workspace_bytes(capacity));
+    return launch_sort(N, V, cams[0], *cfg, proj, order, ws, n_pairs, capacity, sort_ws, sorted_ids, tile_ranges,
+                       (hipStream_t)stream);
 }
 
 potr_status potr_blend(int64_t N, int32_t V, const potr_camera* cams, const potr_config* cfg,

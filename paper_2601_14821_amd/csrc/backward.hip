@@ -41,6 +41,7 @@ __global__ __launch_bounds__(TW * TH) void k_blend_bwd(int64_t N, int32_t W, int
     __shared__ uint32_t s_id[kBwdChunk];
     __shared__ uint32_t s_rows[kBwdChunk];
     __shared__ float s_part[kG][NW][kBwdChunk];
+    __shared__ __align__(8) uint16_t s_list[NW][kBwdChunk];
     __shared__ int s_wmax;
     const int tile = blockIdx.x, v = blockIdx.y;
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
@@ -75,6 +76,11 @@ __global__ __launch_bounds__(TW * TH) void k_blend_bwd(int64_t N, int32_t W, int
     atomicMax(&s_wmax, walk);
     __syncthreads();
     const int wmax = s_wmax;
+    // this wave's longest walk: later entries contribute nothing to any of its lanes
+    int wave_walk = walk;
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) wave_walk = max(wave_walk, __shfl_xor(wave_walk, m, 64));
+    wave_walk = __builtin_amdgcn_readfirstlane(wave_walk);
 
     float T = 1.f, Pr = 0.f, Pg = 0.f, Pb = 0.f;
     for (int base = 0; base < wmax; base += kBwdChunk) {
@@ -92,8 +98,19 @@ __global__ __launch_bounds__(TW * TH) void k_blend_bwd(int64_t N, int32_t W, int
             s_rows[j] = reach_rows(a, b, qmax, tile_y0, TH);
         }
         __syncthreads();
+        // this wave's list of the entries reaching its rows; partial sums of the
+        // entries it does not visit stay zero
+        uint16_t* const L = s_list[wid];
+        const int nl = wave_list(s_rows, cnt, row_lo, row_hi, L);
+        const int jlim = min(cnt, wave_walk - base);
+        for (int j = lane; j < cnt; j += 64)
+#pragma unroll
+            for (int c = 0; c < kG; ++c) s_part[c][wid][j] = 0.f;
         // groups of four entries: per-lane gradients, then one reduce-scatter per component
-        for (int j0 = 0; j0 < cnt; j0 += 4) {
+        for (int i = 0; i < nl; i += 4) {
+            const uint2 q = *reinterpret_cast<const uint2*>(L + i);
+            const int js[4] = {(int)(q.x & 0xffffu), (int)(q.x >> 16), (int)(q.y & 0xffffu), (int)(q.y >> 16)};
+            if (js[0] >= jlim) break;
             float g[4][kG];
 #pragma unroll
             for (int u = 0; u < 4; ++u)
@@ -102,9 +119,8 @@ __global__ __launch_bounds__(TW * TH) void k_blend_bwd(int64_t N, int32_t W, int
             bool any = false;
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
-                const int j = j0 + u;
-                if (j >= cnt) continue;
-                if (!rows_overlap(__builtin_amdgcn_readfirstlane(s_rows[j]), row_lo, row_hi)) continue;
+                if (i + u >= nl || js[u] >= jlim) break;
+                const int j = js[u];
                 if (base + j >= walk) continue;
                 const float4 a = s_a[j];
                 const float4 b = s_b[j];
@@ -136,12 +152,13 @@ __global__ __launch_bounds__(TW * TH) void k_blend_bwd(int64_t N, int32_t W, int
                     T = next_T(T, al);
                 }
             }
-            const bool wave_any = __ballot(any) != 0;
-            const bool writer = lane < 4 && j0 + lane < cnt;
+            if (__ballot(any) == 0) continue;
+            const int jw = lane == 0 ? js[0] : lane == 1 ? js[1] : lane == 2 ? js[2] : js[3];
+            const bool writer = lane < 4 && i + lane < nl && jw < jlim;
 #pragma unroll
             for (int c = 0; c < kG; ++c) {
-                const float s = wave_any ? wave_sum4(g[0][c], g[1][c], g[2][c], g[3][c]) : 0.f;
-                if (writer) s_part[c][wid][j0 + lane] = s;
+                const float s = wave_sum4(g[0][c], g[1][c], g[2][c], g[3][c]);
+                if (writer) s_part[c][wid][jw] = s;
             }
         }
         __syncthreads();

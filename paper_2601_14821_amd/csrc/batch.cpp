@@ -30,7 +30,7 @@ struct potr_batch_s {
     // workspace layout (byte offsets)
     struct JobOff { size_t proj, ids, ranges; };
     std::vector<JobOff> off;
-    size_t off_tt = 0, off_order = 0, off_pairs = 0, off_bin = 0, off_sort = 0;
+    size_t off_tt = 0, off_order = 0, off_bin = 0, off_stage = 0;
     size_t off_table = 0, off_prefix = 0, off_counter = 0, off_npairs = 0, off_caps = 0, off_flag = 0;
     size_t bytes = 0;
     int32_t n_view_jobs = 0;
@@ -52,7 +52,7 @@ potr_status hip_ok(hipError_t e, const char* what) {
 void plan_layout(potr_batch_s* b) {
     size_t o = 0;
     auto take = [&](size_t n) { size_t r = o; o += align_up(n > 0 ? n : 1); return r; };
-    size_t max_tt = 0, max_bin = 0, max_pairs = 0, max_sort = 0;
+    size_t max_tt = 0, max_bin = 0, max_stage = 0;
     b->off.resize(b->jobs.size());
     b->n_view_jobs = 0;
     for (size_t j = 0; j < b->jobs.size(); ++j) {
@@ -62,16 +62,15 @@ void plan_layout(potr_batch_s* b) {
         b->off[j].ids = take((size_t)b->capacity[j] * 4);
         b->off[j].ranges = take((size_t)J.V * T * 2 * 4);
         max_tt = std::max(max_tt, (size_t)J.V * J.N * 4);
-        max_bin = std::max(max_bin, bin_workspace_bytes(J.N, J.V));
-        max_pairs = std::max(max_pairs, (size_t)b->capacity[j] * 8);
-        max_sort = std::max(max_sort, sort_workspace_bytes(b->capacity[j], J.V, T));
+        max_bin = std::max(max_bin, bin_workspace_bytes(J.N, J.V, tiles_x(b->cams[j][0], b->cfg),
+                                                         tiles_y(b->cams[j][0], b->cfg)));
+        max_stage = std::max(max_stage, sort_workspace_bytes(b->capacity[j]));
         b->n_view_jobs += J.V;
     }
     b->off_tt = take(max_tt);
     b->off_order = take(max_tt);
-    b->off_pairs = take(max_pairs);
     b->off_bin = take(max_bin);
-    b->off_sort = take(max_sort);
+    b->off_stage = take(max_stage);
     b->off_table = take((size_t)b->n_view_jobs * sizeof(ViewJob));
     b->off_prefix = take((size_t)(b->n_view_jobs + 1) * 8);
     b->off_counter = take(8);
@@ -233,16 +232,13 @@ potr_status potr_batch_run(potr_batch b, void* stream) {
         potr_proj* proj = (potr_proj*)(ws + b->off[j].proj);
         int32_t* tt = (int32_t*)(ws + b->off_tt);
         uint32_t* order = (uint32_t*)(ws + b->off_order);
-        uint64_t* pairs = (uint64_t*)(ws + b->off_pairs);
         uint32_t* ids = (uint32_t*)(ws + b->off[j].ids);
         int32_t* ranges = (int32_t*)(ws + b->off[j].ranges);
-        const int T = tiles_of(cams[0], b->cfg);
         potr_status st = launch_project(J.N, J.V, cams, b->cfg, J.means, J.scales, J.quats, J.opac, J.sh, proj, tt, s);
+        if (st == POTR_OK) st = launch_bin(J.N, J.V, cams[0], b->cfg, proj, ws + b->off_bin, order, npairs + j, s);
         if (st == POTR_OK)
-            st = launch_bin(J.N, J.V, cams[0], b->cfg, proj, tt, ws + b->off_bin, order, pairs, b->capacity[j],
-                            npairs + j, s);
-        if (st == POTR_OK)
-            st = launch_sort(J.N, J.V, T, npairs + j, b->capacity[j], pairs, ws + b->off_sort, ids, ranges, s);
+            st = launch_sort(J.N, J.V, cams[0], b->cfg, proj, order, ws + b->off_bin, npairs + j, b->capacity[j],
+                             ws + b->off_stage, ids, ranges, s);
         if (st != POTR_OK) return st;
     }
     potr_status st = launch_render_score_persistent((const ViewJob*)(ws + b->off_table), b->n_view_jobs,

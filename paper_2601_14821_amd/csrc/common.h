@@ -32,14 +32,14 @@ potr_status launch_project(int64_t N, int32_t V, const potr_camera* cams, const 
                            const float* means, const float* scales, const float* quats, const float* opac,
                            const float* sh, potr_proj* proj, int32_t* tiles_touched, hipStream_t s);
 
-size_t bin_workspace_bytes(int64_t N, int32_t V);
+size_t bin_workspace_bytes(int64_t N, int32_t V, int32_t tiles_x, int32_t tiles_y);
 potr_status launch_bin(int64_t N, int32_t V, const potr_camera& cam0, const potr_config& cfg,
-                       const potr_proj* proj, const int32_t* tiles_touched, void* ws, uint32_t* order,
-                       uint64_t* pairs, int64_t capacity, int64_t* n_pairs, hipStream_t s);
-
-size_t sort_workspace_bytes(int64_t capacity, int32_t V, int32_t tiles_per_view);
-potr_status launch_sort(int64_t N, int32_t V, int32_t tiles_per_view, const int64_t* n_pairs, int64_t n_max,
-                        uint64_t* pairs, void* ws, uint32_t* sorted_ids, int32_t* tile_ranges, hipStream_t s);
+                       const potr_proj* proj, void* ws, uint32_t* order, int64_t* n_pairs, hipStream_t s);
+size_t sort_workspace_bytes(int64_t capacity);
+potr_status launch_sort(int64_t N, int32_t V, const potr_camera& cam0, const potr_config& cfg,
+                        const potr_proj* proj, const uint32_t* order, void* ws, const int64_t* n_pairs,
+                        int64_t capacity, void* sort_ws, uint32_t* sorted_ids, int32_t* tile_ranges,
+                        hipStream_t s);
 
 potr_status launch_blend(int64_t N, int32_t V, const potr_camera& cam0, const potr_config& cfg,
                          const potr_proj* proj, const uint32_t* sorted_ids, const int32_t* tile_ranges,

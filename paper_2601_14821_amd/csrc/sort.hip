@@ -1,31 +1,29 @@
 // Depth ordering and tile binning (paper Sec. 3: splats composited in layers
-// ordered by approximate depth), as stable LSD radix sorts.
+// ordered by approximate depth).
 //
-// potr_bin: per view, a stable radix sort of the N depth keys (ties keep splat
-//   id order) gives each splat its depth rank; the pairs (tile, splat id) of
-//   every splat's rect are then emitted in rank order, each splat's run placed
-//   by a scan of tiles_touched in rank order.
-// potr_sort: a stable radix sort of the pairs on the (view, tile) bits only.
-//   Pairs were emitted in depth-rank order and the sort is stable, so the
-//   result is ordered by (view, tile, depth key, splat id) -- the full key --
-//   while only ceil(log2(V * tiles)) bits are sorted instead of tile + 32 depth
-//   bits. The low bits carry the splat id as payload.
+// potr_bin orders each view's splats by depth key (a stable LSD radix sort of
+// the N 32-bit keys, so ties keep splat id order), then counts, for every chunk
+// of S consecutive depth ranks and every tile, how many of the chunk's splats
+// cover the tile (table [view][chunk][tile]), and from those counts the number
+// of pairs per tile and in total.
+// potr_sort turns the table into offsets -- the position of chunk c's first
+// pair in tile t is the number of pairs of all earlier (view, tile)s plus those
+// of chunks before c in the same tile -- and places every splat id: one wave
+// per chunk walks its splats in rank order and appends each to the tiles of its
+// rect through cursors in LDS. The result is each tile's list in (depth key,
+// splat id) order, the order a sort of (tile, depth, id) keys would give,
+// without sorting per pair.
 //
-// Pairs are packed as ((view * tiles + tile) << id_bits) | splat id in 32 bits
-// when both fields fit, else in 64 bits with the id in the low word.
-//
-// Every radix pass is one kernel: a block of 256 threads x 16 items ranks its
-// keys per digit with 64-lane ballots (stable order: wave, item, lane),
-// publishes its digit counts, and finds the counts of all blocks before it by
-// decoupled look-back over their published words. The digit totals of all
-// passes come from one histogram read up front. Blocks take their place in the
-// chain from an atomic ticket, so a block only ever waits on blocks that are
-// already running. Each block sorts its keys in LDS and writes every digit's
-// run to consecutive addresses.
-//
-// Every wait is bounded: after kSpinLimit polls the block records a fault and
-// goes on (the results are then wrong and the bin reports n_pairs = -1), so no
-// input can leave a kernel spinning.
+// Depth radix passes are one kernel each: a block of 256 threads x 16 items
+// ranks its keys per digit with 64-lane ballots (stable order: wave, item,
+// lane), publishes its digit counts, and finds the counts of all blocks before
+// it by decoupled look-back over their published words. The digit totals of
+// all passes come from one histogram read up front. Blocks take their place in
+// the chain from an atomic ticket, so a block only ever waits on blocks that
+// are already running. Each block sorts its keys in LDS and writes every
+// digit's run to consecutive addresses. Every wait is bounded: after
+// kSpinLimit polls the block records a fault and goes on (the bin then reports
+// n_pairs = -1), so no input can leave a kernel spinning.
 #include <algorithm>
 
 #include "common.h"
@@ -79,44 +77,6 @@ __device__ uint64_t look_back_serial(uint64_t* st, int64_t b, int stride, uint32
         excl += w & kValMask;
         if (s == kStInc) break;
         --p;
-    }
-    return excl;
-}
-
-__device__ inline int64_t wave_sum_i64(int64_t v) {
-#pragma unroll
-    for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
-    return v;
-}
-
-// Same, one wave polling 64 predecessors at a time (call with the whole wave).
-__device__ int64_t look_back_wave(uint64_t* st, int64_t b, uint32_t tag, uint32_t* fault) {
-    const int lane = threadIdx.x & 63;
-    int64_t excl = 0;
-    int64_t hi = b - 1;
-    uint32_t spins = 0;
-    while (hi >= 0) {
-        const int64_t p = hi - lane;
-        uint64_t w = 0;
-        uint32_t s = (uint32_t)kStInc;     // before block 0: an inclusive zero
-        if (p >= 0) {
-            w = st_get(st + p);
-            s = st_state(w, tag);
-        }
-        const uint64_t inc = __ballot(s == kStInc);
-        const uint64_t none = __ballot(s == 0);
-        const uint64_t upto = inc ? ((inc & (~inc + 1)) << 1) - 1 : ~0ull;   // lanes up to the nearest inclusive
-        if (none & upto) {
-            if (++spins > kSpinLimit) {
-                if (lane == 0) atomicOr(fault, 1u);
-                break;
-            }
-            __builtin_amdgcn_s_sleep(1);
-            continue;
-        }
-        excl += wave_sum_i64(((upto >> lane) & 1ull) ? (int64_t)(w & kValMask) : 0);
-        if (inc) break;
-        hi -= 64;
     }
     return excl;
 }
@@ -201,34 +161,20 @@ __global__ __launch_bounds__(kThreads) void k_hist(const K* __restrict__ keys, c
     }
 }
 
-// Outputs of the last pass over the pairs: the splat ids, and each tile's
-// range from atomic min / max over the positions where a block's run of that
-// tile starts and ends (a tile's pairs are contiguous in every block and
-// globally, so these are its global first and last positions).
-struct Final {
-    uint32_t* ids;
-    int32_t* ranges;
-    int32_t gshift;          // key >> gshift = view * tiles + tile
-    uint64_t imask;          // key & imask = splat id
-};
-
-// One stable radix pass. MODE 0: keys and values (values from vin, or the
-// element's index when vin == nullptr); MODE 1: keys only; MODE 2 (last depth
-// pass): only the values go out, to vout, with cnt_out[pos] = tt[value];
-// MODE 3 (last pair pass): ids and tile ranges (Final) instead of keys.
-template <typename K, int MODE>
-__global__ __launch_bounds__(kThreads) void k_sweep(const K* __restrict__ kin, K* __restrict__ kout,
+// One stable radix pass over the depth keys of every view. MODE 0: keys and
+// values (values from vin, or the element's index when vin == nullptr);
+// MODE 1 (last pass): only the values go out, to vout.
+template <int MODE>
+__global__ __launch_bounds__(kThreads) void k_sweep(const uint32_t* __restrict__ kin, uint32_t* __restrict__ kout,
                                                     const uint32_t* __restrict__ vin, uint32_t* __restrict__ vout,
-                                                    Seg g, Pass P, const int32_t* __restrict__ tt,
-                                                    int32_t* __restrict__ cnt_out, Final F) {
-    constexpr bool VALS = MODE == 0 || MODE == 2;
+                                                    Seg g, Pass P) {
     __shared__ uint32_t wcnt[kWaves][256];
     __shared__ uint32_t goff[256];
     __shared__ uint32_t boff[256];
     __shared__ uint32_t wsum[kWaves];
     __shared__ uint32_t s_ticket;
-    __shared__ K s_key[kTile];
-    __shared__ uint32_t s_val[VALS ? kTile : 1];
+    __shared__ uint32_t s_key[kTile];
+    __shared__ uint32_t s_val[kTile];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const uint32_t radix = 1u << P.bits, mask = radix - 1;
     if (threadIdx.x == 0) s_ticket = atomicAdd(P.ticket, 1u);
@@ -245,7 +191,7 @@ __global__ __launch_bounds__(kThreads) void k_sweep(const K* __restrict__ kin, K
     const uint32_t gh = threadIdx.x < radix ? P.ghist[(int64_t)seg * kMaxPasses * 256 + threadIdx.x] : 0u;
     const uint32_t dbase = block_excl_scan(gh, wsum);
 
-    K key[kItems];
+    uint32_t key[kItems];
     uint32_t val[kItems];
     uint32_t rnk[kItems];
     const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
@@ -253,8 +199,8 @@ __global__ __launch_bounds__(kThreads) void k_sweep(const K* __restrict__ kin, K
     for (int k = 0; k < kItems; ++k) {
         const int64_t e = wbase + k * 64 + lane;
         const bool ok = e < n;
-        key[k] = ok ? kin[seg0 + e] : (K)0;
-        if (VALS) val[k] = ok ? (vin ? vin[seg0 + e] : (uint32_t)e) : 0u;
+        key[k] = ok ? kin[seg0 + e] : 0u;
+        val[k] = ok ? (vin ? vin[seg0 + e] : (uint32_t)e) : 0u;
         const uint32_t d = digit_of(key[k], P.shift, mask);
         uint64_t m = __ballot(ok);
         for (int bit = 0; bit < P.bits; ++bit) {
@@ -303,317 +249,518 @@ __global__ __launch_bounds__(kThreads) void k_sweep(const K* __restrict__ kin, K
         const uint32_t d = digit_of(key[k], P.shift, mask);
         const uint32_t p = boff[d] + wcnt[w][d] + rnk[k];
         s_key[p] = key[k];
-        if (VALS) s_val[p] = val[k];
+        s_val[p] = val[k];
     }
     __syncthreads();
     // coalesced write-out: digit runs go to consecutive global addresses
     const int64_t left = n - blk0;
     const int cnt_blk = left < kTile ? (int)(left > 0 ? left : 0) : kTile;
     for (int i = threadIdx.x; i < cnt_blk; i += kThreads) {
-        const K kk = s_key[i];
+        const uint32_t kk = s_key[i];
         const uint32_t d = digit_of(kk, P.shift, mask);
         const int64_t pos = seg0 + (int64_t)goff[d] + (i - (int)boff[d]);
-        if (MODE == 0 || MODE == 1) kout[pos] = kk;
-        if (MODE == 0) vout[pos] = s_val[i];
-        if (MODE == 2) {
-            const uint32_t id = s_val[i];
-            vout[pos] = id;
-            cnt_out[pos] = tt[seg0 + id];
-        }
-        if (MODE == 3) {
-            F.ids[pos] = (uint32_t)((uint64_t)kk & F.imask);
-            const uint32_t gi = (uint32_t)((uint64_t)kk >> F.gshift);
-            if (i == 0 || (uint32_t)((uint64_t)s_key[i - 1] >> F.gshift) != gi)
-                atomicMin(F.ranges + 2 * (int64_t)gi, (int32_t)pos);
-            if (i == cnt_blk - 1 || (uint32_t)((uint64_t)s_key[i + 1] >> F.gshift) != gi)
-                atomicMax(F.ranges + 2 * (int64_t)gi + 1, (int32_t)pos + 1);
-        }
+        if (MODE == 0) kout[pos] = kk;
+        vout[pos] = s_val[i];
     }
 }
 
-// ---------------------------------------------------------------- bin kernels
 // Clears 64-bit words (look-back status, digit totals, tickets).
 __global__ void k_clear(uint64_t* __restrict__ p, int64_t n) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
         p[i] = 0;
 }
 
-// Tile ranges before the last pass: start = INT32_MAX (for atomic min), end = 0.
-__global__ void k_ranges_init(int32_t* r, int64_t n_tiles, int32_t start) {
-    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n_tiles;
-         t += (int64_t)gridDim.x * blockDim.x) {
-        r[2 * t] = start;
-        r[2 * t + 1] = 0;
+// ---------------------------------------------------------------- pair placement
+// Ranks are cut into chunks of kChunk and groups of kGroup chunks. Placement
+// takes two coalesced levels over tables of counts:
+//   rows table  rc[v][c][y]  pairs of chunk c in tile row y (tiles its splats
+//               cover there), scanned over the chunks: every chunk's first
+//               position in the row's region of the output;
+//   tiles table tc[v][g][t]  pairs of group g in tile t, scanned over the
+//               groups: every group's first position in tile t.
+// Level 1 (a wave per chunk, 64 splats at a time, one lane per splat) appends,
+// row by row, each splat's run of (x, id) for the tiles of its rect to the
+// row's region (lanes covering the row take consecutive places by a prefix
+// sum of their widths, so the chunk's run in a row is contiguous). Level 2 (a
+// block per (group, row)) reads the group's segment of the row and places
+// each id at its tile's cursor, ranking equal tiles with ballots so that each
+// tile's run leaves as contiguous stores. The layout of the rows' regions is
+// that of the final output, so a row's region holds exactly its tiles' pairs.
+struct Bins {
+    int64_t N;
+    int32_t V, C, G, T, tiles_x, tiles_y, seg_c, nseg_c, seg_g, nseg_g, xbits;
+};
+constexpr int kChunk = 256;                   // ranks per chunk (one wave)
+constexpr int kGroup = 16;                    // chunks per group
+constexpr int kGroupRanks = kChunk * kGroup;  // 4096
+constexpr int kMaxSegs = 32;                  // at most this many segments per column scan
+constexpr int kColItems = 8;                  // level 2: items per thread (2048 per block pass)
+
+// Rect of one (view, rank): tiles [x0, x1) x [y0, y1), packed as two words.
+__device__ inline void load_rect(const potr_proj* __restrict__ pv, uint32_t id, uint32_t& xw, uint32_t& yw) {
+    const uint2 r = *reinterpret_cast<const uint2*>(&pv[id].rect[0]);   // (x0 | y0 << 16, x1 | y1 << 16)
+    xw = (r.x & 0xffffu) | (r.y << 16);                                  // x0 | x1 << 16
+    yw = (r.x >> 16) | (r.y & 0xffff0000u);                              // y0 | y1 << 16
+}
+
+// rc[v][c][y]: pairs of chunk c in row y (one splat per thread).
+__global__ __launch_bounds__(kChunk) void k_row_count(const uint32_t* __restrict__ order,
+                                                      const potr_proj* __restrict__ proj, Bins B,
+                                                      uint32_t* __restrict__ rc) {
+    extern __shared__ uint32_t rows[];
+    const int c = blockIdx.x, v = blockIdx.y;
+    for (int y = threadIdx.x; y < B.tiles_y; y += kChunk) rows[y] = 0;
+    __syncthreads();
+    const int64_t r = (int64_t)c * kChunk + threadIdx.x;
+    if (r < B.N) {
+        uint32_t xw, yw;
+        load_rect(proj + (int64_t)v * B.N, order[(int64_t)v * B.N + r], xw, yw);
+        const int w = (int)(xw >> 16) - (int)(xw & 0xffffu);
+        if (w > 0)
+            for (int y = (int)(yw & 0xffffu); y < (int)(yw >> 16); ++y) atomicAdd(&rows[y], (uint32_t)w);
+    }
+    __syncthreads();
+    for (int y = threadIdx.x; y < B.tiles_y; y += kChunk) rc[((int64_t)v * B.C + c) * B.tiles_y + y] = rows[y];
+}
+
+// Column scans of a table [v][R rows][cols]: segment sums over seglen rows ...
+__global__ __launch_bounds__(256) void k_seg_sums(const uint32_t* __restrict__ tab, int32_t R, int32_t cols,
+                                                  int32_t seglen, int32_t nseg, uint32_t* __restrict__ segsum) {
+    const int col = blockIdx.x * 256 + threadIdx.x, seg = blockIdx.y, v = blockIdx.z;
+    if (col >= cols) return;
+    const int r0 = seg * seglen, r1 = min(R, r0 + seglen);
+    const uint32_t* p = tab + ((int64_t)v * R) * cols + col;
+    uint32_t s = 0;
+#pragma unroll 8
+    for (int r = r0; r < r1; ++r) s += p[(int64_t)r * cols];
+    segsum[((int64_t)v * nseg + seg) * cols + col] = s;
+}
+
+// ... the segment sums' exclusive prefix in place and the column totals ...
+__global__ __launch_bounds__(256) void k_seg_prefix(uint32_t* __restrict__ segsum, int32_t V, int32_t cols,
+                                                    int32_t nseg, uint32_t* __restrict__ total) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= (int64_t)V * cols) return;
+    const int64_t v = i / cols, col = i - v * cols;
+    uint32_t run = 0;
+    for (int seg = 0; seg < nseg; ++seg) {
+        uint32_t* p = segsum + (v * nseg + seg) * cols + col;
+        const uint32_t x = *p;
+        *p = run;
+        run += x;
+    }
+    total[i] = run;
+}
+
+// ... and each row's first position: out[v][r][col] = base[v][col] + (sum of
+// rows before r). With R_out = R + 1 the extra row holds the column's end.
+__global__ __launch_bounds__(256) void k_seg_offsets(const uint32_t* __restrict__ tab,
+                                                     const uint32_t* __restrict__ segsum,
+                                                     const int64_t* __restrict__ base, int32_t R, int32_t cols,
+                                                     int32_t seglen, int32_t nseg, int32_t R_out,
+                                                     const int64_t* __restrict__ n_pairs,
+                                                     int64_t capacity, uint32_t* __restrict__ out) {
+    const int col = blockIdx.x * 256 + threadIdx.x, seg = blockIdx.y, v = blockIdx.z;
+    if (col >= cols) return;
+    if (capacity >= 0) {
+        const int64_t n = *n_pairs;
+        if (n < 0 || n > capacity) return;
+    }
+    uint32_t run = (uint32_t)base[(int64_t)v * cols + col] + segsum[((int64_t)v * nseg + seg) * cols + col];
+    const int r0 = seg * seglen, r1 = min(R, r0 + seglen);
+#pragma unroll 8
+    for (int r = r0; r < r1; ++r) {
+        out[((int64_t)v * R_out + r) * cols + col] = run;
+        run += tab[((int64_t)v * R + r) * cols + col];
+    }
+    if (r1 == R && R_out > R) out[((int64_t)v * R_out + R) * cols + col] = run;
+}
+
+// One block: row bases = exclusive scan of the row totals over (view, row),
+// and the number of pairs (-1 if a depth pass gave up a wait).
+__global__ __launch_bounds__(1024) void k_row_bases(const uint32_t* __restrict__ total, int64_t n,
+                                                    int64_t* __restrict__ base, const uint32_t* __restrict__ fault,
+                                                    int64_t* __restrict__ n_pairs) {
+    __shared__ int64_t wsum[16];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    int64_t carry = 0;
+    for (int64_t b0 = 0; b0 < n; b0 += 1024 * 8) {
+        const int64_t i0 = b0 + (int64_t)threadIdx.x * 8;
+        int64_t x[8], tot = 0;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            x[k] = i0 + k < n ? (int64_t)total[i0 + k] : 0;
+            tot += x[k];
+        }
+        int64_t inc = tot;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const int64_t y = __shfl_up(inc, d, 64);
+            if (lane >= d) inc += y;
+        }
+        if (lane == 63) wsum[w] = inc;
+        __syncthreads();
+        int64_t pre = carry, all = 0;
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            if (k < w) pre += wsum[k];
+            all += wsum[k];
+        }
+        int64_t run = pre + inc - tot;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            if (i0 + k < n) base[i0 + k] = run;
+            run += x[k];
+        }
+        carry += all;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *n_pairs = *fault ? (int64_t)-1 : carry;
+}
+
+// A wave per (view, row): tile bases = the row's base + exclusive scan of its
+// tile totals, and tile ranges ([0, 0) when empty; all empty when the pairs
+// exceed the capacity).
+__global__ __launch_bounds__(64) void k_tile_bases(const uint32_t* __restrict__ total, const int64_t* __restrict__ rbase,
+                                                   Bins B, const int64_t* __restrict__ n_pairs, int64_t capacity,
+                                                   int64_t* __restrict__ tbase, int32_t* __restrict__ ranges) {
+    const int y = blockIdx.x, v = blockIdx.y, lane = threadIdx.x;
+    const int64_t n = *n_pairs;
+    const bool ok = n >= 0 && n <= capacity;
+    int64_t run = rbase[(int64_t)v * B.tiles_y + y];
+    const int64_t t0 = (int64_t)v * B.T + (int64_t)y * B.tiles_x;
+    for (int x0 = 0; x0 < B.tiles_x; x0 += 64) {
+        const int x = x0 + lane;
+        const int64_t c = x < B.tiles_x ? (int64_t)total[t0 + x] : 0;
+        int64_t inc = c;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const int64_t u = __shfl_up(inc, d, 64);
+            if (lane >= d) inc += u;
+        }
+        const int64_t b = run + inc - c;
+        if (x < B.tiles_x) {
+            tbase[t0 + x] = b;
+            const bool any = ok && c > 0;
+            ranges[2 * (t0 + x)] = any ? (int32_t)b : 0;
+            ranges[2 * (t0 + x) + 1] = any ? (int32_t)(b + c) : 0;
+        }
+        run += __shfl(inc, 63, 64);
     }
 }
 
-// Tiles no pair reached get the empty range [0, 0).
-__global__ void k_ranges_fix(int32_t* r, int64_t n_tiles) {
-    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n_tiles;
-         t += (int64_t)gridDim.x * blockDim.x)
-        if (r[2 * t] == INT32_MAX) r[2 * t] = 0;
+// Level 1: a wave per (view, chunk). The wave walks the chunk's splats in rank
+// order, lanes on consecutive tiles of one splat's rect, and appends (x, id)
+// to each tile's row through per-row cursors in LDS that start at the chunk's
+// first position in the row.
+__global__ __launch_bounds__(64) void k_place_rows(const uint32_t* __restrict__ order,
+                                                   const potr_proj* __restrict__ proj,
+                                                   const uint32_t* __restrict__ roff, Bins B,
+                                                   const int64_t* __restrict__ n_pairs, int64_t capacity,
+                                                   uint16_t* __restrict__ stage_x, uint32_t* __restrict__ stage_id) {
+    extern __shared__ uint32_t cur[];   // [tiles_y]
+    const int64_t n = *n_pairs;
+    if (n < 0 || n > capacity) return;
+    const int c = blockIdx.x, v = blockIdx.y, lane = threadIdx.x;
+    const uint32_t* orow = roff + ((int64_t)v * (B.C + 1) + c) * B.tiles_y;
+    for (int y = lane; y < B.tiles_y; y += 64) cur[y] = orow[y];
+    __builtin_amdgcn_wave_barrier();
+    const potr_proj* pv = proj + (int64_t)v * B.N;
+    const int64_t r0 = (int64_t)c * kChunk;
+    const int ns = (int)min((int64_t)kChunk, B.N - r0);
+    constexpr int kPer = kChunk / 64;
+    uint32_t sid[kPer], sxw[kPer], syw[kPer];
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+        sid[k] = 0;
+        sxw[k] = syw[k] = 0;
+        const int sidx = k * 64 + lane;
+        if (sidx < ns) {
+            sid[k] = order[(int64_t)v * B.N + r0 + sidx];
+            load_rect(pv, sid[k], sxw[k], syw[k]);
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+        const int m = min(64, ns - k * 64);
+        for (int sj = 0; sj < m; ++sj) {
+            const uint32_t xw = (uint32_t)__builtin_amdgcn_readlane((int32_t)sxw[k], sj);
+            const uint32_t yw = (uint32_t)__builtin_amdgcn_readlane((int32_t)syw[k], sj);
+            const int x0 = (int)(xw & 0xffffu), x1 = (int)(xw >> 16);
+            const int y0 = (int)(yw & 0xffffu), y1 = (int)(yw >> 16);
+            const int wdt = x1 - x0;
+            if (wdt <= 0 || y1 <= y0) continue;
+            const int cnt = wdt * (y1 - y0);
+            const uint32_t id = (uint32_t)__builtin_amdgcn_readlane((int32_t)sid[k], sj);
+            const float rw = __builtin_amdgcn_rcpf((float)wdt);
+            for (int q = lane; q < cnt; q += 64) {
+                // tile q of the rect, row-major: q = ty * wdt + tx (the float
+                // quotient is off by at most one)
+                int ty = (int)((float)q * rw);
+                int tx = q - ty * wdt;
+                if (tx < 0) {
+                    --ty;
+                    tx += wdt;
+                } else if (tx >= wdt) {
+                    ++ty;
+                    tx -= wdt;
+                }
+                const uint32_t p = cur[y0 + ty] + (uint32_t)tx;
+                stage_x[p] = (uint16_t)(x0 + tx);
+                stage_id[p] = id;
+            }
+            for (int yy = y0 + lane; yy < y1; yy += 64) cur[yy] += (uint32_t)wdt;
+        }
+    }
 }
 
-// Pairs of 256 consecutive (view, rank) entries per block. The pair offset of
-// the block comes from a decoupled look-back over the blocks before it; each
-// wave then writes its 64 splats' runs one splat at a time, lanes covering
-// consecutive tiles of the rect, so stores are contiguous.
-template <typename K>
-__global__ __launch_bounds__(kThreads) void k_emit(const uint32_t* __restrict__ order, const int32_t* __restrict__ cnt,
-                                                   const potr_proj* __restrict__ proj, int64_t N, int64_t total,
-                                                   int32_t tiles_x, int32_t tiles_per_view, int id_bits,
-                                                   int64_t capacity, uint64_t* status, uint32_t* ticket,
-                                                   uint32_t* fault, int64_t n_blocks, int64_t* __restrict__ n_pairs,
-                                                   K* __restrict__ pairs) {
-    __shared__ uint32_t s_ticket;
-    __shared__ int64_t s_wsum[kWaves];
-    __shared__ int64_t s_excl;
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    if (threadIdx.x == 0) s_ticket = atomicAdd(ticket, 1u);
+// tc[v][g][t]: pairs of group g in tile t, counted over the group's segment of
+// each row (a block per (view, group, row)).
+__global__ __launch_bounds__(256) void k_col_count(const uint32_t* __restrict__ roff, Bins B,
+                                                   const int64_t* __restrict__ n_pairs, int64_t capacity,
+                                                   const uint16_t* __restrict__ stage_x, uint32_t* __restrict__ tc) {
+    extern __shared__ uint32_t cnt[];   // [tiles_x]
+    const int64_t n = *n_pairs;
+    if (n < 0 || n > capacity) return;
+    const int g = blockIdx.x, y = blockIdx.y, v = blockIdx.z;
+    for (int x = threadIdx.x; x < B.tiles_x; x += 256) cnt[x] = 0;
     __syncthreads();
-    const int64_t b = s_ticket;
-    const int64_t i = b * kThreads + threadIdx.x;
-    int64_t c = 0;
-    uint32_t id = 0, g0 = 0, wdt = 1;
-    if (i < total) {
-        const int32_t ci = cnt[i];
-        if (ci > 0) {
-            const int64_t v = i / N;
-            id = order[i];
-            const potr_proj& p = proj[v * N + id];
-            c = ci;
-            g0 = (uint32_t)(v * tiles_per_view + p.rect[1] * tiles_x + p.rect[0]);
-            wdt = (uint32_t)(p.rect[2] - p.rect[0]);
-        }
-    }
-    int64_t inc = c;
+    const int c0 = g * kGroup, c1 = min(B.C, c0 + kGroup);
+    const uint32_t s0 = roff[((int64_t)v * (B.C + 1) + c0) * B.tiles_y + y];
+    const uint32_t s1 = roff[((int64_t)v * (B.C + 1) + c1) * B.tiles_y + y];
+    for (uint32_t i = s0 + threadIdx.x; i < s1; i += 256) atomicAdd(&cnt[stage_x[i]], 1u);
+    __syncthreads();
+    uint32_t* out = tc + ((int64_t)v * B.G + g) * B.T + (int64_t)y * B.tiles_x;
+    for (int x = threadIdx.x; x < B.tiles_x; x += 256) out[x] = cnt[x];
+}
+
+// Level 2: block per (view, group, row). The row segment level 1 wrote for
+// the group, in rank order, goes to its tiles: a stable ranking by tile x
+// (ballots over the x bits, per-wave counters), a sort in LDS, and stores of
+// each tile's run at the tile's cursor.
+template <int XBITS>
+__global__ __launch_bounds__(256) void k_place_cols(const uint32_t* __restrict__ roff, const uint32_t* __restrict__ off,
+                                                    Bins B, const int64_t* __restrict__ n_pairs, int64_t capacity,
+                                                    const uint16_t* __restrict__ stage_x,
+                                                    const uint32_t* __restrict__ stage_id,
+                                                    uint32_t* __restrict__ ids) {
+    extern __shared__ uint32_t lds[];
+    const int TX = B.tiles_x;
+    uint32_t* wcnt = lds;                        // [kWaves][TX]
+    uint32_t* cur = wcnt + kWaves * TX;          // [TX]
+    uint32_t* boff = cur + TX;                   // [TX]
+    uint32_t* s_id = boff + TX;                  // [kThreads * kColItems]
+    uint16_t* s_x = reinterpret_cast<uint16_t*>(s_id + kThreads * kColItems);
+    __shared__ uint32_t wsum[kWaves];
+    const int64_t n = *n_pairs;
+    if (n < 0 || n > capacity) return;
+    const int g = blockIdx.x, y = blockIdx.y, v = blockIdx.z;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int c0 = g * kGroup, c1 = min(B.C, c0 + kGroup);
+    const uint32_t seg0 = roff[((int64_t)v * (B.C + 1) + c0) * B.tiles_y + y];
+    const uint32_t len = roff[((int64_t)v * (B.C + 1) + c1) * B.tiles_y + y] - seg0;
+    const uint32_t* orow = off + ((int64_t)v * B.G + g) * B.T + (int64_t)y * TX;
+    for (int x = threadIdx.x; x < TX; x += kThreads) cur[x] = orow[x];
+    const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    const int per = (TX + kThreads - 1) / kThreads;   // counters per thread in the block scan
+    for (uint32_t b0 = 0; b0 < len; b0 += kThreads * kColItems) {
+        for (int t = threadIdx.x; t < kWaves * TX; t += kThreads) wcnt[t] = 0;
+        __syncthreads();
+        const uint32_t cntb = min(len - b0, (uint32_t)(kThreads * kColItems));
+        uint32_t key[kColItems], val[kColItems], rnk[kColItems];
 #pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        const int64_t y = __shfl_up(inc, d, 64);
-        if (lane >= d) inc += y;
-    }
-    if (lane == 63) s_wsum[wid] = inc;
-    __syncthreads();
-    int64_t pre = 0, sum = 0;
+        for (int k = 0; k < kColItems; ++k) {
+            const uint32_t e = (uint32_t)(w * 64 * kColItems + k * 64 + lane);
+            const bool ok = e < cntb;
+            key[k] = ok ? stage_x[seg0 + b0 + e] : 0u;
+            val[k] = ok ? stage_id[seg0 + b0 + e] : 0u;
+            const uint32_t d = key[k];
+            uint64_t m = __ballot(ok);
 #pragma unroll
-    for (int k = 0; k < kWaves; ++k) {
-        if (k < wid) pre += s_wsum[k];
-        sum += s_wsum[k];
-    }
-    if (wid == 0) {
-        int64_t excl = 0;
-        if (b == 0) {
-            if (lane == 0) st_put(status, st_word(1, kStInc, (uint64_t)sum));
-        } else {
-            if (lane == 0) st_put(status + b, st_word(1, kStAgg, (uint64_t)sum));
-            excl = look_back_wave(status, b, 1, fault);
-            if (lane == 0) st_put(status + b, st_word(1, kStInc, (uint64_t)(excl + sum)));
-        }
-        if (lane == 0) {
-            s_excl = excl;
-            if (b == n_blocks - 1)
-                *n_pairs = __hip_atomic_load(fault, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ? (int64_t)-1
-                                                                                                : excl + sum;
-        }
-    }
-    __syncthreads();
-    const int64_t start = s_excl + pre + inc - c;
-    for (int s = 0; s < 64; ++s) {
-        const int32_t cs = __builtin_amdgcn_readlane((int32_t)c, s);
-        if (cs == 0) continue;
-        const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int32_t)(uint32_t)start, s);
-        const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int32_t)(uint32_t)((uint64_t)start >> 32), s);
-        const int64_t st = (int64_t)(((uint64_t)hi << 32) | lo);
-        const uint32_t sid = (uint32_t)__builtin_amdgcn_readlane((int32_t)id, s);
-        const uint32_t sg0 = (uint32_t)__builtin_amdgcn_readlane((int32_t)g0, s);
-        const int32_t sw = __builtin_amdgcn_readlane((int32_t)wdt, s);
-        const float rw = 1.0f / (float)sw;
-        for (int32_t k = lane; k < cs; k += 64) {
-            // tile k of the rect, row-major: k = ty * width + tx (the float
-            // quotient is off by at most one; rows < 2^15)
-            int32_t ty = (int32_t)((float)k * rw);
-            int32_t tx = k - ty * sw;
-            if (tx < 0) {
-                --ty;
-                tx += sw;
-            } else if (tx >= sw) {
-                ++ty;
-                tx -= sw;
+            for (int bit = 0; bit < XBITS; ++bit) {
+                const uint64_t bal = __ballot((d >> bit) & 1u);
+                m &= ((d >> bit) & 1u) ? bal : ~bal;
             }
-            const int64_t p = st + k;
-            if (p < capacity) {
-                const uint64_t gg = (uint64_t)sg0 + (uint64_t)ty * (uint32_t)tiles_x + (uint32_t)tx;
-                if (sizeof(K) == 4)
-                    pairs[p] = (K)((gg << id_bits) | sid);
-                else
-                    pairs[p] = (K)((gg << 32) | sid);
-            }
+            const uint32_t below = (uint32_t)__popcll(m & lt_mask);
+            const uint32_t c = (uint32_t)__popcll(m);
+            uint32_t r = 0;
+            if (ok) r = wcnt[w * TX + d];
+            __builtin_amdgcn_wave_barrier();
+            if (ok && below == 0) wcnt[w * TX + d] = r + c;
+            __builtin_amdgcn_wave_barrier();
+            rnk[k] = ok ? r + below : 0xffffffffu;
         }
+        __syncthreads();
+        // per x: exclusive prefix over waves, block count; then the block scan of the counts
+        uint32_t local[8];
+        uint32_t mine = 0;
+        for (int j = 0; j < per; ++j) {
+            const int x = threadIdx.x * per + j;
+            uint32_t run = 0;
+            if (x < TX)
+                for (int ww = 0; ww < kWaves; ++ww) {
+                    const uint32_t c = wcnt[ww * TX + x];
+                    wcnt[ww * TX + x] = run;
+                    run += c;
+                }
+            local[j] = run;
+            mine += run;
+        }
+        uint32_t pre = block_excl_scan(mine, wsum);
+        for (int j = 0; j < per; ++j) {
+            const int x = threadIdx.x * per + j;
+            if (x < TX) boff[x] = pre;
+            pre += local[j];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < kColItems; ++k) {
+            if (rnk[k] == 0xffffffffu) continue;
+            const uint32_t p = boff[key[k]] + wcnt[w * TX + key[k]] + rnk[k];
+            s_id[p] = val[k];
+            s_x[p] = (uint16_t)key[k];
+        }
+        __syncthreads();
+        for (uint32_t i = threadIdx.x; i < cntb; i += kThreads) {
+            const uint32_t x = s_x[i];
+            ids[cur[x] + (i - boff[x])] = s_id[i];
+        }
+        __syncthreads();
+        // advance the cursors past this pass's runs
+        for (int x = threadIdx.x; x < TX; x += kThreads) {
+            const uint32_t end = (x + 1 < TX) ? boff[x + 1] : cntb;
+            cur[x] += end - boff[x];
+        }
+        __syncthreads();
     }
 }
 
 // ---------------------------------------------------------------- host side
-int bit_width(int64_t x) {           // bits to hold 0..x (at least 1)
-    int b = 1;
-    while (b < 62 && (int64_t(1) << b) <= x) ++b;
-    return b;
-}
-
-struct Packing {
-    int tile_bits, id_bits;
-    bool u32;
-};
-
-Packing packing(int64_t N, int32_t V, int32_t tiles_per_view) {
-    Packing p;
-    p.tile_bits = bit_width((int64_t)V * tiles_per_view - 1);
-    p.id_bits = bit_width(N > 0 ? N - 1 : 0);
-    p.u32 = p.tile_bits + p.id_bits <= 32;
-    return p;
-}
-
-// Region at the front of each workspace, cleared at the start of every call:
-// tickets (one per pass + one for the emit), the fault word, digit totals and
-// the look-back status words.
+// Region at the front of the workspace, cleared at the start of every bin:
+// tickets (one per depth pass), the fault word, digit totals and the look-back
+// status words.
 struct Ctl {
     uint32_t* ticket;
     uint32_t* fault;
     uint32_t* ghist;
-    uint64_t* status;       // radix passes
-    uint64_t* estatus;      // emit (bin only)
+    uint64_t* status;
     int64_t clear_words;
 };
 
-Ctl ctl_layout(char* base, size_t& o, int64_t segs, int64_t status_words, int64_t estatus_words) {
-    Ctl c;
-    const size_t o0 = o;
-    auto take = [&](size_t b) { char* p = base ? base + o : nullptr; o += align_up(b); return p; };
-    c.ticket = (uint32_t*)take(4 * (kMaxPasses + 2));
-    c.fault = c.ticket + kMaxPasses + 1;
-    c.ghist = (uint32_t*)take(4 * (size_t)segs * kMaxPasses * 256);
-    c.status = (uint64_t*)take(8 * (size_t)status_words);
-    c.estatus = (uint64_t*)take(8 * (size_t)(estatus_words > 0 ? estatus_words : 1));
-    c.clear_words = (int64_t)((o - o0) / 8);
-    return c;
+Bins bins_of(int64_t N, int32_t V, int32_t tiles_x, int32_t tiles_y) {
+    Bins B;
+    B.N = N;
+    B.V = V;
+    B.C = (int32_t)ceil_div(N, kChunk);
+    B.G = (int32_t)ceil_div(N, kGroupRanks);
+    B.tiles_x = tiles_x;
+    B.tiles_y = tiles_y;
+    B.T = tiles_x * tiles_y;
+    B.seg_c = (int32_t)std::max<int64_t>(16, ceil_div(B.C, kMaxSegs));
+    B.nseg_c = (int32_t)std::max<int64_t>(1, ceil_div(B.C, B.seg_c));
+    B.seg_g = (int32_t)std::max<int64_t>(16, ceil_div(B.G, kMaxSegs));
+    B.nseg_g = (int32_t)std::max<int64_t>(1, ceil_div(B.G, B.seg_g));
+    int bits = 1;
+    while ((1 << bits) < tiles_x) ++bits;
+    B.xbits = bits;
+    return B;
 }
 
 struct BinWs {
-    uint32_t *ka, *kb, *va;
-    int32_t* cnt;
     Ctl ctl;
+    uint32_t *ka, *kb, *va;
+    uint32_t *rc, *roff, *segr, *totr;
+    int64_t* rbase;
+    uint32_t *tc, *toff, *segt, *tott;
+    int64_t* tbase;
     size_t bytes;
 };
 
-BinWs bin_layout(int64_t N, int32_t V, char* base) {
+BinWs bin_layout(int64_t N, int32_t V, int32_t tiles_x, int32_t tiles_y, char* base) {
     const int64_t VN = N * V;
     const int64_t bps = ceil_div(N > 0 ? N : 1, kTile);
+    const Bins B = bins_of(N, V, tiles_x, tiles_y);
     BinWs w;
     size_t o = 0;
-    w.ctl = ctl_layout(base, o, V, (int64_t)V * bps * 256, ceil_div(VN > 0 ? VN : 1, kThreads));
-    auto take = [&](size_t b) { char* p = base ? base + o : nullptr; o += align_up(b); return p; };
+    auto take = [&](size_t b) { char* p = base ? base + o : nullptr; o += align_up(b > 0 ? b : 1); return p; };
+    w.ctl.ticket = (uint32_t*)take(4 * (kMaxPasses + 2));
+    w.ctl.fault = w.ctl.ticket + kMaxPasses + 1;
+    w.ctl.ghist = (uint32_t*)take(4 * (size_t)V * kMaxPasses * 256);
+    w.ctl.status = (uint64_t*)take(8 * (size_t)V * bps * 256);
+    w.ctl.clear_words = (int64_t)(o / 8);
     w.ka = (uint32_t*)take(4 * VN);
     w.kb = (uint32_t*)take(4 * VN);
     w.va = (uint32_t*)take(4 * VN);
-    w.cnt = (int32_t*)take(4 * VN);
+    const size_t ty = (size_t)tiles_y, T = (size_t)B.T;
+    w.rc = (uint32_t*)take(4 * (size_t)V * B.C * ty);
+    w.roff = (uint32_t*)take(4 * (size_t)V * (B.C + 1) * ty);
+    w.segr = (uint32_t*)take(4 * (size_t)V * B.nseg_c * ty);
+    w.totr = (uint32_t*)take(4 * (size_t)V * ty);
+    w.rbase = (int64_t*)take(8 * (size_t)V * ty);
+    w.tc = (uint32_t*)take(4 * (size_t)V * B.G * T);
+    w.toff = (uint32_t*)take(4 * (size_t)V * B.G * T);
+    w.segt = (uint32_t*)take(4 * (size_t)V * B.nseg_g * T);
+    w.tott = (uint32_t*)take(4 * (size_t)V * T);
+    w.tbase = (int64_t*)take(8 * (size_t)V * T);
     w.bytes = o;
     return w;
-}
-
-struct SortWs {
-    void* alt;
-    Ctl ctl;
-    size_t bytes;
-};
-
-SortWs sort_layout(int64_t cap, char* base) {
-    const int64_t bps = ceil_div(cap > 0 ? cap : 1, kTile);
-    SortWs w;
-    size_t o = 0;
-    w.ctl = ctl_layout(base, o, 1, bps * 256, 0);
-    auto take = [&](size_t b) { char* p = base ? base + o : nullptr; o += align_up(b); return p; };
-    w.alt = take(8 * (size_t)(cap > 0 ? cap : 1));
-    w.bytes = o;
-    return w;
-}
-
-potr_status clear(const Ctl& c, hipStream_t s) {
-    const unsigned blocks = (unsigned)std::min<int64_t>(ceil_div(c.clear_words, 256), 4096);
-    hipLaunchKernelGGL(k_clear, dim3(blocks), dim3(256), 0, s, (uint64_t*)c.ticket, c.clear_words);
-    return check_launch("k_clear");
 }
 
 unsigned hist_blocks(int64_t n, int segs) {
     return (unsigned)std::max<int64_t>(1, std::min<int64_t>(ceil_div(n, 4 * kThreads), 2048 / segs));
 }
 
-template <typename K, int MODE>
-potr_status sweep(const K* kin, K* kout, const uint32_t* vin, uint32_t* vout, const Seg& g, int segs, const Pass& P,
-                  const int32_t* tt, int32_t* cnt_out, const Final& F, hipStream_t s) {
-    hipLaunchKernelGGL((k_sweep<K, MODE>), dim3((unsigned)((int64_t)g.bps * segs)), dim3(kThreads), 0, s, kin, kout,
-                       vin, vout, g, P, tt, cnt_out, F);
+template <int MODE>
+potr_status sweep(const uint32_t* kin, uint32_t* kout, const uint32_t* vin, uint32_t* vout, const Seg& g, int segs,
+                  const Pass& P, hipStream_t s) {
+    hipLaunchKernelGGL((k_sweep<MODE>), dim3((unsigned)((int64_t)g.bps * segs)), dim3(kThreads), 0, s, kin, kout,
+                       vin, vout, g, P);
     return check_launch("k_sweep");
 }
 
-unsigned grid_for(int64_t n) { return (unsigned)std::max<int64_t>(1, std::min<int64_t>(ceil_div(n, 256), 4096)); }
-
-template <typename K>
-potr_status emit_pairs(const uint32_t* order, const BinWs& w, const potr_proj* proj, int64_t N, int64_t VN, int txs,
-                       int tpv, int id_bits, int64_t capacity, int64_t* n_pairs, void* pairs, hipStream_t s) {
-    const int64_t nb = ceil_div(VN > 0 ? VN : 1, kThreads);
-    hipLaunchKernelGGL(k_emit<K>, dim3((unsigned)nb), dim3(kThreads), 0, s, order, (const int32_t*)w.cnt, proj,
-                       N > 0 ? N : 1, VN, txs, tpv, id_bits, capacity, w.ctl.estatus, w.ctl.ticket + kMaxPasses,
-                       w.ctl.fault, nb, n_pairs, (K*)pairs);
-    return check_launch("k_emit");
+size_t cols_lds(const Bins& B) {
+    return ((size_t)(kWaves + 2) * B.tiles_x + (size_t)kThreads * kColItems) * 4 + (size_t)kThreads * kColItems * 2;
 }
 
-template <typename K>
-potr_status sort_pairs(const Packing& pk, int64_t n_tiles, const int64_t* n_pairs, int64_t n_max, void* pairs,
-                       const SortWs& w, uint32_t* sorted_ids, int32_t* tile_ranges, hipStream_t s) {
-    const int bits = pk.tile_bits;
-    const int passes = (bits + 7) / 8;
-    const int per = (bits + passes - 1) / passes;
-    const int shift0 = sizeof(K) == 4 ? pk.id_bits : 32;
-    Seg g{0, n_pairs, n_max, (int32_t)ceil_div(n_max, kTile)};
-    potr_status st = clear(w.ctl, s);
+// column scan of tab[v][R][cols] into out[v][R_out][cols] starting at base[v][cols]
+potr_status col_scan_sums(const uint32_t* tab, int32_t R, int32_t cols, int32_t seglen, int32_t nseg, int32_t V,
+                          uint32_t* segsum, uint32_t* total, hipStream_t s) {
+    const dim3 g((unsigned)ceil_div(cols, 256), nseg, V);
+    hipLaunchKernelGGL(k_seg_sums, g, dim3(256), 0, s, tab, R, cols, seglen, nseg, segsum);
+    potr_status st = check_launch("k_seg_sums");
     if (st != POTR_OK) return st;
-    hipLaunchKernelGGL(k_hist<K>, dim3(hist_blocks(n_max, 1), 1), dim3(kThreads), 0, s, (const K*)pairs, nullptr,
-                       nullptr, g, passes, shift0, per, bits, w.ctl.ghist);
-    st = check_launch("k_hist");
-    if (st != POTR_OK) return st;
-    const Final F{sorted_ids, tile_ranges, shift0,
-                  sizeof(K) == 4 ? ((1ull << pk.id_bits) - 1) : 0xffffffffull};
-    K *kin = (K*)pairs, *kout = (K*)w.alt;
-    for (int p = 0; p < passes; ++p) {
-        const int b = (p == passes - 1) ? bits - per * p : per;
-        Pass P{shift0 + per * p, b, (uint32_t)(1 + p), w.ctl.ghist + p * 256, w.ctl.status, w.ctl.ticket + p,
-               w.ctl.fault};
-        if (p < passes - 1)
-            st = sweep<K, 1>(kin, kout, nullptr, nullptr, g, 1, P, nullptr, nullptr, F, s);
-        else
-            st = sweep<K, 3>(kin, nullptr, nullptr, nullptr, g, 1, P, nullptr, nullptr, F, s);
-        if (st != POTR_OK) return st;
-        K* t = kin;
-        kin = kout;
-        kout = t;
-    }
-    hipLaunchKernelGGL(k_ranges_fix, dim3(grid_for(n_tiles)), dim3(256), 0, s, tile_ranges, n_tiles);
-    return check_launch("k_ranges_fix");
+    hipLaunchKernelGGL(k_seg_prefix, dim3((unsigned)ceil_div((int64_t)V * cols, 256)), dim3(256), 0, s, segsum, V,
+                       cols, nseg, total);
+    return check_launch("k_seg_prefix");
+}
+
+potr_status col_scan_offsets(const uint32_t* tab, const uint32_t* segsum, const int64_t* base, int32_t R,
+                             int32_t cols, int32_t seglen, int32_t nseg, int32_t V, int32_t R_out,
+                             const int64_t* n_pairs, int64_t capacity, uint32_t* out, hipStream_t s) {
+    const dim3 g((unsigned)ceil_div(cols, 256), nseg, V);
+    hipLaunchKernelGGL(k_seg_offsets, g, dim3(256), 0, s, tab, segsum, base, R, cols, seglen, nseg, R_out, n_pairs,
+                       capacity, out);
+    return check_launch("k_seg_offsets");
 }
 
 }  // namespace
 
-size_t bin_workspace_bytes(int64_t N, int32_t V) { return bin_layout(N, V, nullptr).bytes; }
+size_t bin_workspace_bytes(int64_t N, int32_t V, int32_t tiles_x, int32_t tiles_y) {
+    return bin_layout(N, V, tiles_x, tiles_y, nullptr).bytes;
+}
+
+size_t sort_workspace_bytes(int64_t capacity) { return align_up((size_t)(capacity > 0 ? capacity : 1) * 6 + 256); }
 
 potr_status launch_bin(int64_t N, int32_t V, const potr_camera& cam0, const potr_config& cfg,
-                       const potr_proj* proj, const int32_t* tiles_touched, void* ws, uint32_t* order,
-                       uint64_t* pairs, int64_t capacity, int64_t* n_pairs, hipStream_t s) {
-    BinWs w = bin_layout(N, V, (char*)ws);
-    const int64_t VN = N * V;
-    const int txs = tiles_x(cam0, cfg), tpv = txs * tiles_y(cam0, cfg);
-    const Packing pk = packing(N, V, tpv);
-    potr_status st = clear(w.ctl, s);
+                       const potr_proj* proj, void* ws, uint32_t* order, int64_t* n_pairs, hipStream_t s) {
+    const int txs = tiles_x(cam0, cfg), tys = tiles_y(cam0, cfg);
+    BinWs w = bin_layout(N, V, txs, tys, (char*)ws);
+    const Bins B = bins_of(N, V, txs, tys);
+    const unsigned cb = (unsigned)std::min<int64_t>(ceil_div(w.ctl.clear_words, 256), 4096);
+    hipLaunchKernelGGL(k_clear, dim3(cb), dim3(256), 0, s, (uint64_t*)w.ctl.ticket, w.ctl.clear_words);
+    potr_status st = check_launch("k_clear");
     if (st != POTR_OK) return st;
-    if (VN > 0) {
+    if (N > 0) {
         // stable per-view sort of the 32-bit depth keys: four 8-bit passes
         Seg g{N, nullptr, 0, (int32_t)ceil_div(N, kTile)};
         hipLaunchKernelGGL(k_hist<uint32_t>, dim3(hist_blocks(N, V), V), dim3(kThreads), 0, s,
@@ -626,37 +773,97 @@ potr_status launch_bin(int64_t N, int32_t V, const potr_camera& cam0, const potr
         for (int pass = 0; pass < 4; ++pass) {
             Pass P{8 * pass, 8, (uint32_t)(1 + pass), w.ctl.ghist + pass * 256, w.ctl.status, w.ctl.ticket + pass,
                    w.ctl.fault};
-            const Final none{nullptr, nullptr, 0, 0};
-            if (pass < 3)
-                st = sweep<uint32_t, 0>(kin, kout, vin, vbuf[pass & 1], g, V, P, nullptr, nullptr, none, s);
-            else
-                st = sweep<uint32_t, 2>(kin, nullptr, vin, order, g, V, P, tiles_touched, w.cnt, none, s);
+            st = pass < 3 ? sweep<0>(kin, kout, vin, vbuf[pass & 1], g, V, P, s)
+                          : sweep<1>(kin, nullptr, vin, order, g, V, P, s);
             if (st != POTR_OK) return st;
             vin = vbuf[pass & 1];
             uint32_t* t = kin;
             kin = kout;
             kout = t;
         }
+        hipLaunchKernelGGL(k_row_count, dim3(B.C, V), dim3(kChunk), (size_t)tys * 4, s, (const uint32_t*)order, proj,
+                           B, w.rc);
+        st = check_launch("k_row_count");
+        if (st != POTR_OK) return st;
     }
-    // with no splats the emit's single empty block reports zero pairs
-    if (pk.u32)
-        return emit_pairs<uint32_t>(order, w, proj, N, VN, txs, tpv, pk.id_bits, capacity, n_pairs, pairs, s);
-    return emit_pairs<uint64_t>(order, w, proj, N, VN, txs, tpv, pk.id_bits, capacity, n_pairs, pairs, s);
+    // rows: totals, bases over (view, row), the pair count, each chunk's first position per row
+    st = col_scan_sums(w.rc, B.C, tys, B.seg_c, B.nseg_c, V, w.segr, w.totr, s);
+    if (st != POTR_OK) return st;
+    hipLaunchKernelGGL(k_row_bases, dim3(1), dim3(1024), 0, s, (const uint32_t*)w.totr, (int64_t)V * tys, w.rbase,
+                       (const uint32_t*)w.ctl.fault, n_pairs);
+    st = check_launch("k_row_bases");
+    if (st != POTR_OK) return st;
+    return col_scan_offsets(w.rc, w.segr, w.rbase, B.C, tys, B.seg_c, B.nseg_c, V, B.C + 1, n_pairs, -1, w.roff, s);
 }
 
-size_t sort_workspace_bytes(int64_t capacity, int32_t, int32_t) { return sort_layout(capacity, nullptr).bytes; }
-
-potr_status launch_sort(int64_t N, int32_t V, int32_t tiles_per_view, const int64_t* n_pairs, int64_t n_max,
-                        uint64_t* pairs, void* ws, uint32_t* sorted_ids, int32_t* tile_ranges, hipStream_t s) {
-    SortWs w = sort_layout(n_max, (char*)ws);
-    const int64_t n_tiles = (int64_t)V * tiles_per_view;
-    hipLaunchKernelGGL(k_ranges_init, dim3(grid_for(n_tiles)), dim3(256), 0, s, tile_ranges, n_tiles,
-                       n_max == 0 ? 0 : INT32_MAX);
-    potr_status st = check_launch("k_ranges_init");
-    if (st != POTR_OK || n_max == 0) return st;
-    const Packing pk = packing(N, V, tiles_per_view);
-    if (pk.u32) return sort_pairs<uint32_t>(pk, n_tiles, n_pairs, n_max, pairs, w, sorted_ids, tile_ranges, s);
-    return sort_pairs<uint64_t>(pk, n_tiles, n_pairs, n_max, pairs, w, sorted_ids, tile_ranges, s);
+potr_status launch_sort(int64_t N, int32_t V, const potr_camera& cam0, const potr_config& cfg,
+                        const potr_proj* proj, const uint32_t* order, void* ws, const int64_t* n_pairs,
+                        int64_t capacity, void* sort_ws, uint32_t* sorted_ids, int32_t* tile_ranges,
+                        hipStream_t s) {
+    const int txs = tiles_x(cam0, cfg), tys = tiles_y(cam0, cfg);
+    BinWs w = bin_layout(N, V, txs, tys, (char*)ws);
+    const Bins B = bins_of(N, V, txs, tys);
+    uint32_t* stage_id = (uint32_t*)sort_ws;
+    uint16_t* stage_x = (uint16_t*)((char*)sort_ws + align_up((size_t)(capacity > 0 ? capacity : 1) * 4));
+    potr_status st = POTR_OK;
+    if (N > 0) {
+        // level 1: pairs into their rows; then the pairs per (group, tile)
+        hipLaunchKernelGGL(k_place_rows, dim3(B.C, V), dim3(64), (size_t)tys * 4, s, order, proj,
+                           (const uint32_t*)w.roff, B, n_pairs, capacity, stage_x, stage_id);
+        st = check_launch("k_place_rows");
+        if (st != POTR_OK) return st;
+        hipLaunchKernelGGL(k_col_count, dim3(B.G, tys, V), dim3(256), (size_t)txs * 4, s, (const uint32_t*)w.roff, B,
+                           n_pairs, capacity, (const uint16_t*)stage_x, w.tc);
+        st = check_launch("k_col_count");
+        if (st != POTR_OK) return st;
+    }
+    // tiles: totals, bases (within their row), ranges, each group's first position per tile
+    st = col_scan_sums(w.tc, B.G, B.T, B.seg_g, B.nseg_g, V, w.segt, w.tott, s);
+    if (st != POTR_OK) return st;
+    hipLaunchKernelGGL(k_tile_bases, dim3(tys, V), dim3(64), 0, s, (const uint32_t*)w.tott, (const int64_t*)w.rbase, B,
+                       n_pairs, capacity, w.tbase, tile_ranges);
+    st = check_launch("k_tile_bases");
+    if (st != POTR_OK || N == 0) return st;
+    st = col_scan_offsets(w.tc, w.segt, w.tbase, B.G, B.T, B.seg_g, B.nseg_g, V, B.G, n_pairs, capacity, w.toff, s);
+    if (st != POTR_OK) return st;
+    // level 2: each row segment of a group to its tiles
+    const dim3 gl2(B.G, tys, V);
+    const size_t l2 = cols_lds(B);
+    const uint32_t* ro = w.roff;
+    const uint32_t* to = w.toff;
+    const uint16_t* sx = stage_x;
+    const uint32_t* si = stage_id;
+    switch (B.xbits) {
+        case 1: case 2: case 3: case 4: case 5:
+            hipLaunchKernelGGL(k_place_cols<5>, gl2, dim3(kThreads), l2, s, ro, to, B, n_pairs, capacity, sx, si,
+                               sorted_ids);
+            break;
+        case 6:
+            hipLaunchKernelGGL(k_place_cols<6>, gl2, dim3(kThreads), l2, s, ro, to, B, n_pairs, capacity, sx, si,
+                               sorted_ids);
+            break;
+        case 7:
+            hipLaunchKernelGGL(k_place_cols<7>, gl2, dim3(kThreads), l2, s, ro, to, B, n_pairs, capacity, sx, si,
+                               sorted_ids);
+            break;
+        case 8:
+            hipLaunchKernelGGL(k_place_cols<8>, gl2, dim3(kThreads), l2, s, ro, to, B, n_pairs, capacity, sx, si,
+                               sorted_ids);
+            break;
+        case 9:
+            hipLaunchKernelGGL(k_place_cols<9>, gl2, dim3(kThreads), l2, s, ro, to, B, n_pairs, capacity, sx, si,
+                               sorted_ids);
+            break;
+        case 10:
+            hipLaunchKernelGGL(k_place_cols<10>, gl2, dim3(kThreads), l2, s, ro, to, B, n_pairs, capacity, sx, si,
+                               sorted_ids);
+            break;
+        default:
+            hipLaunchKernelGGL(k_place_cols<11>, gl2, dim3(kThreads), l2, s, ro, to, B, n_pairs, capacity, sx, si,
+                               sorted_ids);
+            break;
+    }
+    return check_launch("k_place_cols");
 }
 
 }  // namespace potr

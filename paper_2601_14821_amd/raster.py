@@ -57,7 +57,6 @@ class Rasterizer:
         self.cfg = L.make_config(settings)
         self.device = torch.device(device)
         self._bufs: dict[str, torch.Tensor] = {}
-        self.capacity = 0
         L.lib()
 
     # -------------------------------------------------------------- buffers
@@ -88,38 +87,33 @@ class Rasterizer:
         return ViewBatch(V=V, N=N, proj=proj, tiles_touched=tt)
 
     def bin(self, vb: ViewBatch, cams) -> ViewBatch:
+        """Depth order per view and pair counts (potr_bin); reads the count back."""
         N, V = vb.N, vb.V
+        cam_arr = L.make_cameras(cams)
         order = self._i32("order", V * N)
         n_pairs = self._buf("n_pairs", 8)[:8].view(torch.int64)
-        ws_bytes = L.bin_workspace_size(N, V)
-        ws = self._buf("bin_ws", ws_bytes)
-        cam_arr = L.make_cameras(cams)
-        for _ in range(2):
-            pairs = self._buf("pairs", 8 * max(self.capacity, 1))
-            L.call("potr_bin", N, V, cam_arr, C.byref(self.cfg), L.ptr(vb.proj), L.ptr(vb.tiles_touched),
-                   L.ptr(ws), ws.numel(), L.ptr(order), L.ptr(pairs), self.capacity, L.ptr(n_pairs),
-                   L.stream_handle())
-            n = int(n_pairs.item())
-            if n < 0:
-                raise L.PotrError("potr_bin", L.POTR_EHIP, "device-side ordering did not complete")
-            if n <= self.capacity:
-                break
-            self.capacity = int(n * 1.25) + 4096
+        ws = self._buf("bin_ws", L.bin_workspace_size(N, V, cam_arr, self.cfg))
+        L.call("potr_bin", N, V, cam_arr, C.byref(self.cfg), L.ptr(vb.proj), L.ptr(ws), ws.numel(), L.ptr(order),
+               L.ptr(n_pairs), L.stream_handle())
+        n = int(n_pairs.item())
+        if n < 0:
+            raise L.PotrError("potr_bin", L.POTR_EHIP, "device-side ordering did not complete")
         vb.order, vb.n_pairs = order, n
-        vb._pairs = pairs
+        vb._bin_ws = ws
         vb._n_pairs_dev = n_pairs
         return vb
 
-    def sort(self, vb: ViewBatch, cams) -> ViewBatch:
+    def sort(self, vb: ViewBatch, cams, capacity: int | None = None) -> ViewBatch:
+        """Tile lists in depth order (potr_sort) into a buffer of `capacity` ids
+        (default: exactly the counted pairs)."""
         tx, ty = self.tiles(cams[0])
-        n = vb.n_pairs
-        ws_bytes = L.sort_workspace_size(n, vb.V, tx * ty)
-        ws = self._buf("sort_ws", ws_bytes)
-        ids = self._i32("sorted_ids", n)
+        cap = vb.n_pairs if capacity is None else int(capacity)
+        ids = self._i32("sorted_ids", cap)
         ranges = self._i32("ranges", 2 * vb.V * tx * ty)[: 2 * vb.V * tx * ty]
-        L.call("potr_sort", vb.N, vb.V, L.make_cameras(cams), C.byref(self.cfg), L.ptr(vb._n_pairs_dev), n,
-               L.ptr(vb._pairs), L.ptr(ws), ws.numel(), L.ptr(ids), L.ptr(ranges),
-               L.stream_handle())
+        sws = self._buf("sort_ws", L.sort_workspace_size(cap))
+        L.call("potr_sort", vb.N, vb.V, L.make_cameras(cams), C.byref(self.cfg), L.ptr(vb.proj), L.ptr(vb.order),
+               L.ptr(vb._bin_ws), vb._bin_ws.numel(), L.ptr(vb._n_pairs_dev), cap, L.ptr(sws), sws.numel(),
+               L.ptr(ids), L.ptr(ranges), L.stream_handle())
         vb.sorted_ids, vb.tile_ranges = ids, ranges
         return vb
 

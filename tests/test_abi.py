@@ -44,7 +44,7 @@ def test_exports_every_declared_symbol(lib):
 
 
 def test_abi_version(lib):
-    assert lib.potr_abi_version() == 1
+    assert lib.potr_abi_version() == 2
 
 
 def test_struct_layouts():
@@ -95,19 +95,28 @@ def test_rejects_bad_views_and_buffers(lib):
 
 def test_workspace_too_small_is_capacity_error(lib):
     cfg = _cfg()
-    need = L.bin_workspace_size(1000, 2)
+    need = L.bin_workspace_size(1000, 2, _cams(2), cfg)
     assert need > 0
-    st = _status("potr_bin", 1000, 2, _cams(2), C.byref(cfg), 16, 16, 16, need - 1, 16, 16, 100, 16, None)
+    st = _status("potr_bin", 1000, 2, _cams(2), C.byref(cfg), 16, 16, need - 1, 16, 16, None)
     assert st == L.POTR_ECAPACITY
-    tx, ty = synth.RenderSettings().tiles(synth.ring_cameras(1, 64, 48)[0])
-    need = L.sort_workspace_size(5000, 2, tx * ty)
-    st = _status("potr_sort", 1000, 2, _cams(2), C.byref(cfg), 16, 5000, 16, 16, need - 1, 16, 16, None)
+    sneed = L.sort_workspace_size(5000)
+    assert sneed >= 6 * 5000
+    st = _status("potr_sort", 1000, 2, _cams(2), C.byref(cfg), 16, 16, 16, need - 1, 16, 5000, 16, sneed, 16, 16,
+                 None)
     assert st == L.POTR_ECAPACITY
+    st = _status("potr_sort", 1000, 2, _cams(2), C.byref(cfg), 16, 16, 16, need, 16, 5000, 16, sneed - 1, 16, 16,
+                 None)
+    assert st == L.POTR_ECAPACITY
+    st = _status("potr_sort", 1000, 2, _cams(2), C.byref(cfg), 16, 16, 16, need, 16, -1, 16, sneed, 16, 16, None)
+    assert st == L.POTR_EINVAL
 
 
 def test_workspace_sizes_grow(lib):
-    assert L.bin_workspace_size(10_000, 1) < L.bin_workspace_size(100_000, 1) < L.bin_workspace_size(100_000, 4)
-    assert L.sort_workspace_size(1000, 1, 100) < L.sort_workspace_size(10_000_000, 1, 100)
+    cfg = _cfg()
+    ws = lambda n, v, w=64, h=48: L.bin_workspace_size(n, v, L.make_cameras(synth.ring_cameras(v, w, h)), cfg)
+    assert ws(10_000, 1) < ws(100_000, 1) < ws(100_000, 4)
+    # the chunk table grows with the tile count
+    assert ws(100_000, 1) < ws(100_000, 1, 1280, 720)
 
 
 def test_new_entry_points_validate(lib):

@@ -111,17 +111,22 @@ def test_bin_sort_bit_exact_on_synthetic_records(N, V, tiles, seed):
     assert vb.n_pairs == total
 
 
-def test_bin_capacity_retry():
+def test_sort_capacity_too_small_places_nothing():
     _need_gpu()
     scene, cams = synth.workload_small()
     s = synth.RenderSettings()
     rz = raster.Rasterizer(s)
-    rz.capacity = 10                     # far too small: the first bin reports overflow
     ds = raster.to_device(scene)
-    vb = rz.render_views(ds, cams[:1])
+    vb = rz.bin(rz.project(ds, cams[:1]), cams[:1])
     o = oracle.render(scene, cams[0], s, want=("image",))
     assert vb.n_pairs == len(o["bins"][1])
-    assert rz.capacity >= vb.n_pairs
+    rz.sort(vb, cams[:1], capacity=vb.n_pairs - 1)     # one slot short: every range empty
+    torch.cuda.synchronize()
+    assert not vb.tile_ranges.cpu().numpy().any()
+    rz.sort(vb, cams[:1], capacity=vb.n_pairs + 7)     # spare slots are fine
+    ranges = vb.tile_ranges.cpu().numpy().reshape(-1, 2)
+    np.testing.assert_array_equal(ranges, o["bins"][2])
+    np.testing.assert_array_equal(vb.sorted_ids.cpu().numpy()[: vb.n_pairs], o["bins"][1])
 
 
 # ---------------------------------------------------------------- end-to-end lists
