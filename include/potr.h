@@ -120,7 +120,8 @@ POTR_API potr_status potr_project(int64_t N, int32_t V, const potr_camera* cams,
  * potr_bin -- Sec. 3 ("layers ordered by approximate depth"): order each view's
  * splats by depth key (ties by splat id) and count the (tile, splat) pairs:
  * every tile of a splat's rect holds the splat. The counts are kept per group
- * of 4096 consecutive depth ranks and per tile in the workspace, for potr_sort.
+ * of 4096 consecutive depth ranks and per tile, and per chunk of 64 ranks and
+ * per row of tiles, in the workspace, for potr_sort.
  *   proj   [V*N] from potr_project (its depth keys and rects are read)
  *   ws     workspace of potr_bin_workspace_size bytes; potr_sort reads it, so
  *          it must stay untouched between the two calls

@@ -32,9 +32,11 @@ namespace potr {
 namespace {
 
 constexpr int kThreads = 256;
-constexpr int kItems = 16;
-constexpr int kTile = kThreads * kItems;     // keys per block
 constexpr int kWaves = kThreads / 64;
+constexpr int kSwThreads = 1024;              // depth radix pass: 16 waves x 4 keys per lane
+constexpr int kSwItems = 4;
+constexpr int kSwWaves = kSwThreads / 64;
+constexpr int kTile = kSwThreads * kSwItems;  // keys per block
 constexpr int kMaxPasses = 4;
 constexpr uint32_t kSpinLimit = 1u << 20;
 
@@ -59,14 +61,40 @@ __device__ inline uint32_t st_state(uint64_t w, uint32_t tag) {
 }
 
 // Exclusive prefix of one counter over blocks 0..b-1 (words at st[p * stride]):
-// adds aggregates walking back until an inclusive prefix is found.
-__device__ uint64_t look_back_serial(uint64_t* st, int64_t b, int stride, uint32_t tag, uint32_t* fault) {
+// adds aggregates walking back until an inclusive prefix is found, reading W
+// predecessors per round (their loads are independent, so a round costs one
+// memory latency). Aggregates before a not yet published word are taken
+// before waiting on it.
+template <int W>
+__device__ uint64_t look_back(uint64_t* st, int64_t b, int stride, uint32_t tag, uint32_t* fault) {
     uint64_t excl = 0;
     uint32_t spins = 0;
-    for (int64_t p = b - 1; p >= 0;) {
-        const uint64_t w = st_get(st + p * stride);
-        const uint32_t s = st_state(w, tag);
-        if (s == 0) {
+    int64_t hi = b - 1;
+    while (hi >= 0) {
+        uint64_t wv[W];
+#pragma unroll
+        for (int k = 0; k < W; ++k) wv[k] = hi - k >= 0 ? st_get(st + (hi - k) * stride) : 0ull;
+        int k = 0;
+        bool found = false, gap = false;
+        for (; k < W; ++k) {
+            if (hi - k < 0) {          // before block 0: an inclusive zero
+                found = true;
+                break;
+            }
+            const uint32_t s = st_state(wv[k], tag);
+            if (s == 0) {
+                gap = true;
+                break;
+            }
+            excl += wv[k] & kValMask;
+            if (s == kStInc) {
+                found = true;
+                break;
+            }
+        }
+        if (found) break;
+        if (gap) {
+            hi -= k;
             if (++spins > kSpinLimit) {
                 atomicOr(fault, 1u);
                 break;
@@ -74,14 +102,13 @@ __device__ uint64_t look_back_serial(uint64_t* st, int64_t b, int stride, uint32
             __builtin_amdgcn_s_sleep(1);
             continue;
         }
-        excl += w & kValMask;
-        if (s == kStInc) break;
-        --p;
+        hi -= W;
     }
     return excl;
 }
 
-// Exclusive scan of one value per thread over the block (256 threads).
+// Exclusive scan of one value per thread over the block (NT threads).
+template <int NT>
 __device__ inline uint32_t block_excl_scan(uint32_t x, uint32_t* wsum) {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     uint32_t inc = x;
@@ -94,7 +121,7 @@ __device__ inline uint32_t block_excl_scan(uint32_t x, uint32_t* wsum) {
     __syncthreads();
     uint32_t pre = 0;
 #pragma unroll
-    for (int k = 0; k < kWaves; ++k)
+    for (int k = 0; k < NT / 64; ++k)
         if (k < w) pre += wsum[k];
     __syncthreads();
     return pre + inc - x;
@@ -165,38 +192,38 @@ __global__ __launch_bounds__(kThreads) void k_hist(const K* __restrict__ keys, c
 // values (values from vin, or the element's index when vin == nullptr);
 // MODE 1 (last pass): only the values go out, to vout.
 template <int MODE>
-__global__ __launch_bounds__(kThreads) void k_sweep(const uint32_t* __restrict__ kin, uint32_t* __restrict__ kout,
+__global__ __launch_bounds__(kSwThreads) void k_sweep(const uint32_t* __restrict__ kin, uint32_t* __restrict__ kout,
                                                     const uint32_t* __restrict__ vin, uint32_t* __restrict__ vout,
                                                     Seg g, Pass P) {
-    __shared__ uint32_t wcnt[kWaves][256];
+    __shared__ uint32_t wcnt[kSwWaves][256];
     __shared__ uint32_t goff[256];
     __shared__ uint32_t boff[256];
-    __shared__ uint32_t wsum[kWaves];
+    __shared__ uint32_t wsum[kSwWaves];
     __shared__ uint32_t s_ticket;
     __shared__ uint32_t s_key[kTile];
     __shared__ uint32_t s_val[kTile];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const uint32_t radix = 1u << P.bits, mask = radix - 1;
     if (threadIdx.x == 0) s_ticket = atomicAdd(P.ticket, 1u);
-    for (int t = threadIdx.x; t < kWaves * 256; t += kThreads) (&wcnt[0][0])[t] = 0;
+    for (int t = threadIdx.x; t < kSwWaves * 256; t += kSwThreads) (&wcnt[0][0])[t] = 0;
     __syncthreads();
     const int seg = (int)(s_ticket / (uint32_t)g.bps);
     const int64_t b = (int64_t)(s_ticket - (uint32_t)seg * (uint32_t)g.bps);
     const int64_t n = seg_n(g);
     const int64_t seg0 = (int64_t)seg * g.len;
     const int64_t blk0 = b * kTile;
-    const int64_t wbase = blk0 + (int64_t)w * (64 * kItems);
+    const int64_t wbase = blk0 + (int64_t)w * (64 * kSwItems);
 
     // this segment's digit bases: exclusive scan of the pass's digit totals
     const uint32_t gh = threadIdx.x < radix ? P.ghist[(int64_t)seg * kMaxPasses * 256 + threadIdx.x] : 0u;
-    const uint32_t dbase = block_excl_scan(gh, wsum);
+    const uint32_t dbase = block_excl_scan<kSwThreads>(gh, wsum);
 
-    uint32_t key[kItems];
-    uint32_t val[kItems];
-    uint32_t rnk[kItems];
+    uint32_t key[kSwItems];
+    uint32_t val[kSwItems];
+    uint32_t rnk[kSwItems];
     const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
 #pragma unroll
-    for (int k = 0; k < kItems; ++k) {
+    for (int k = 0; k < kSwItems; ++k) {
         const int64_t e = wbase + k * 64 + lane;
         const bool ok = e < n;
         key[k] = ok ? kin[seg0 + e] : 0u;
@@ -222,7 +249,7 @@ __global__ __launch_bounds__(kThreads) void k_sweep(const uint32_t* __restrict__
     if (threadIdx.x < radix) {
         const uint32_t d = threadIdx.x;
 #pragma unroll
-        for (int ww = 0; ww < kWaves; ++ww) {
+        for (int ww = 0; ww < kSwWaves; ++ww) {
             const uint32_t c = wcnt[ww][d];
             wcnt[ww][d] = run;
             run += c;
@@ -234,17 +261,18 @@ __global__ __launch_bounds__(kThreads) void k_sweep(const uint32_t* __restrict__
             st_put(st, st_word(P.tag, kStInc, run));
         } else {
             st_put(st + b * radix, st_word(P.tag, kStAgg, run));
-            excl = look_back_serial(st, b, (int)radix, P.tag, P.fault);
+            excl = look_back<8>(st, b, (int)radix, P.tag, P.fault);
             st_put(st + b * radix, st_word(P.tag, kStInc, excl + run));
         }
         goff[d] = dbase + (uint32_t)excl;
     }
     // exclusive scan of the block's digit counts: LDS position of each digit's run
-    boff[threadIdx.x] = block_excl_scan(run, wsum);
+    const uint32_t bo = block_excl_scan<kSwThreads>(run, wsum);
+    if (threadIdx.x < 256) boff[threadIdx.x] = bo;
     __syncthreads();
     // block-local sort in LDS
 #pragma unroll
-    for (int k = 0; k < kItems; ++k) {
+    for (int k = 0; k < kSwItems; ++k) {
         if (rnk[k] == 0xffffffffu) continue;
         const uint32_t d = digit_of(key[k], P.shift, mask);
         const uint32_t p = boff[d] + wcnt[w][d] + rnk[k];
@@ -255,7 +283,7 @@ __global__ __launch_bounds__(kThreads) void k_sweep(const uint32_t* __restrict__
     // coalesced write-out: digit runs go to consecutive global addresses
     const int64_t left = n - blk0;
     const int cnt_blk = left < kTile ? (int)(left > 0 ? left : 0) : kTile;
-    for (int i = threadIdx.x; i < cnt_blk; i += kThreads) {
+    for (int i = threadIdx.x; i < cnt_blk; i += kSwThreads) {
         const uint32_t kk = s_key[i];
         const uint32_t d = digit_of(kk, P.shift, mask);
         const int64_t pos = seg0 + (int64_t)goff[d] + (i - (int)boff[d]);
@@ -290,8 +318,8 @@ struct Bins {
     int64_t N;
     int32_t V, C, G, T, tiles_x, tiles_y, seg_c, nseg_c, seg_g, nseg_g, xbits;
 };
-constexpr int kChunk = 256;                   // ranks per chunk (one wave)
-constexpr int kGroup = 16;                    // chunks per group
+constexpr int kChunk = 64;                    // ranks per chunk (one wave, one rank per lane)
+constexpr int kGroup = 64;                    // chunks per group
 constexpr int kGroupRanks = kChunk * kGroup;  // 4096
 constexpr int kMaxSegs = 32;                  // at most this many segments per column scan
 constexpr int kColItems = 8;                  // level 2: items per thread (2048 per block pass)
@@ -606,7 +634,7 @@ __global__ __launch_bounds__(256) void k_place_cols(const uint32_t* __restrict__
             local[j] = run;
             mine += run;
         }
-        uint32_t pre = block_excl_scan(mine, wsum);
+        uint32_t pre = block_excl_scan<kThreads>(mine, wsum);
         for (int j = 0; j < per; ++j) {
             const int x = threadIdx.x * per + j;
             if (x < TX) boff[x] = pre;
@@ -713,7 +741,7 @@ unsigned hist_blocks(int64_t n, int segs) {
 template <int MODE>
 potr_status sweep(const uint32_t* kin, uint32_t* kout, const uint32_t* vin, uint32_t* vout, const Seg& g, int segs,
                   const Pass& P, hipStream_t s) {
-    hipLaunchKernelGGL((k_sweep<MODE>), dim3((unsigned)((int64_t)g.bps * segs)), dim3(kThreads), 0, s, kin, kout,
+    hipLaunchKernelGGL((k_sweep<MODE>), dim3((unsigned)((int64_t)g.bps * segs)), dim3(kSwThreads), 0, s, kin, kout,
                        vin, vout, g, P);
     return check_launch("k_sweep");
 }
