@@ -42,6 +42,26 @@ FUSED_FLOPS_VISIT, FUSED_FLOPS_BLEND = 26.0, 42.0
 PROJECT_BYTES_PER_SPLAT_VIEW = 236 + 48 + 4
 
 
+def measured_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed counter record, or
+    None when there is none or the kernel's sources changed since it was taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "render_score_traffic.json")
+    try:
+        rec = json.load(open(path))
+    except (OSError, ValueError):
+        return None
+    if rec.get("kernel") != kernel:
+        return None
+    h = hashlib.sha256()
+    for p in rec["sources"]:
+        try:
+            h.update(open(os.path.join(ROOT, p), "rb").read())
+        except OSError:
+            return None
+    return int(rec["bytes_per_launch"]) if h.hexdigest() == rec["sources_sha256"] else None
+
+
 def cpu_baseline(scene, cams, s):
     import oracle
     threads = oracle.default_threads()
@@ -65,6 +85,10 @@ def main_line(args, torch, raster, synth):
     stages = ("project", "bin", "sort", "render_score")
     stage_ms = {k: 0.0 for k in stages}
     stream = torch.cuda.current_stream()
+    # the pair count of this view, from an untimed pass; the timed steps sort into
+    # that many slots without reading the count back (no host synchronisation
+    # inside a step), and the last step's count is checked against it afterwards
+    cap = rz.bin(rz.project(ds, cams), cams).n_pairs
 
     def step(timed: bool):
         ev = [torch.cuda.Event(enable_timing=True) for _ in range(len(stages) + 1)] if timed else None
@@ -74,24 +98,27 @@ def main_line(args, torch, raster, synth):
         vb = rz.project(ds, cams)
         if timed:
             ev[1].record(stream)
-        rz.bin(vb, cams)
+        rz.bin(vb, cams, read_count=False)
         if timed:
             ev[2].record(stream)
-        rz.sort(vb, cams)
+        rz.sort(vb, cams, capacity=cap)
         if timed:
             ev[3].record(stream)
         rz.render_score(vb, cams, scores=scores)
         if timed:
             ev[4].record(stream)
-        return ev
+        return ev, vb
 
     for _ in range(args.warmup):
         step(False)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    evs = [step(True) for _ in range(args.steps)]
+    runs = [step(True) for _ in range(args.steps)]
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    if not rz.pairs_fit(runs[-1][1]):
+        raise RuntimeError("the timed steps ran out of pair slots")
+    evs = [r[0] for r in runs]
     for ev in evs:
         for i, k in enumerate(stages):
             stage_ms[k] += ev[i].elapsed_time(ev[i + 1]) / args.steps
@@ -117,7 +144,7 @@ def main_line(args, torch, raster, synth):
     else:
         achieved, peak, unit = amount / sec, FP32_VECTOR_PEAK_TFLOPS, "TFLOP/s"
     roofline = {"bound": bound, "achieved": round(achieved, 3), "peak": peak, "unit": unit,
-                "frac": round(achieved / peak, 4), "traffic": None, "kernel": f"k_{dom}",
+                "frac": round(achieved / peak, 4), "traffic": measured_traffic(f"k_{dom}"), "kernel": f"k_{dom}",
                 "kernel_ms": round(stage_ms[dom], 4)}
     out = {
         "value": round(N * V / (ms / 1000.0) / 1e9, 4),

@@ -107,6 +107,7 @@ POTR_API const char* potr_last_error(void);
  * inverse (the conic), the SH colour along the camera-to-centre direction, the
  * depth key and the tile rectangle, for N splats x V views.
  *   cams  (host) [V]
+ *   sh    [N,16,3] FP32, 16-byte aligned (read as float4)
  *   proj  [V*N] potr_proj, view-major (proj[v*N + i])
  *   tiles_touched [V*N] int32: number of tiles in rect (0 if culled)
  * Arithmetic: the projection runs in FP64 and stores FP32.

@@ -85,6 +85,7 @@ potr_status potr_project(int64_t N, int32_t V, const potr_camera* cams, const po
     if (N > 0 && (!means || !scales || !quats || !opac || !sh || !proj || !tiles_touched))
         return fail(POTR_EINVAL, "NULL buffer");
     if (!aligned16(proj)) return fail(POTR_EINVAL, "proj must be 16-byte aligned");
+    if (N > 0 && !aligned16(sh)) return fail(POTR_EINVAL, "sh must be 16-byte aligned");
     return launch_project(N, V, cams, *cfg, means, scales, quats, opac, sh, proj, tiles_touched,
                           (hipStream_t)stream);
 }

@@ -88,6 +88,8 @@ potr_status validate_jobs(const potr_job* jobs, int32_t n_jobs, bool need_scores
             return fail(POTR_EINVAL, "job %d: bad N/V/cams", j);
         if (J.N > 0 && (!J.means || !J.scales || !J.quats || !J.opac || !J.sh || (need_scores && !J.scores)))
             return fail(POTR_EINVAL, "job %d: NULL buffer", j);
+        if (J.N > 0 && (reinterpret_cast<uintptr_t>(J.sh) & 15u) != 0)
+            return fail(POTR_EINVAL, "job %d: sh must be 16-byte aligned", j);
     }
     return POTR_OK;
 }

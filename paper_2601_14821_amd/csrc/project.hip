@@ -2,6 +2,9 @@
 //
 // One thread per splat; the thread reads the splat's 236 bytes once and loops
 // over the views of the launch, so a batch of views costs one parameter read.
+// The block's SH coefficients (192 B per splat, contiguous) are loaded with
+// coalesced 16-byte loads into LDS, 13 float4 per splat (an odd stride, so a
+// wave's per-splat 16-byte reads hit distinct banks).
 // All arithmetic is FP64: CDNA's FP64 vector rate is half its FP32 rate and this
 // kernel is bound by HBM (236 B in, 52 B out per splat-view for ~300 flops), so
 // FP64 is free here and keeps every stored FP32 value correctly rounded from a
@@ -42,12 +45,28 @@ __device__ inline void sh_basis_d3(double x, double y, double z, int degree, dou
     Y[15] = -0.5900435899266435 * x * (xx - 3.0 * yy);
 }
 
-__global__ __launch_bounds__(256) void k_project(int64_t N, int32_t v0, int32_t nv, CamBatch cams,
+constexpr int kProjThreads = 128;
+constexpr int kShStride = 13;   // float4 per splat in LDS (12 used)
+
+__global__ __launch_bounds__(kProjThreads) void k_project(int64_t N, int32_t v0, int32_t nv, CamBatch cams,
                                                  potr_config cfg, const float* __restrict__ means,
                                                  const float* __restrict__ scales, const float* __restrict__ quats,
                                                  const float* __restrict__ opac, const float* __restrict__ sh,
                                                  potr_proj* __restrict__ proj, int32_t* __restrict__ tiles_touched) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    __shared__ float4 s_sh[kProjThreads * kShStride];
+    const int64_t i0 = (int64_t)blockIdx.x * kProjThreads;
+    const int64_t i = i0 + threadIdx.x;
+    {
+        // the float4s holding the 3 (degree + 1)^2 coefficients in use
+        const int nb = (int)min((int64_t)kProjThreads, N - i0);
+        const int n4 = (3 * (cfg.sh_degree + 1) * (cfg.sh_degree + 1) + 3) / 4;
+        const float4* g4 = reinterpret_cast<const float4*>(sh + 48 * i0);
+        for (int f = threadIdx.x; f < nb * n4; f += kProjThreads) {
+            const int t = f / n4, m = f - t * n4;
+            s_sh[t * kShStride + m] = g4[t * 12 + m];
+        }
+    }
+    __syncthreads();
     if (i >= N) return;
 
     const float mx = means[3 * i], my = means[3 * i + 1], mz = means[3 * i + 2];
@@ -75,7 +94,6 @@ __global__ __launch_bounds__(256) void k_project(int64_t N, int32_t v0, int32_t 
         S22 = M[6] * M[6] * s0 + M[7] * M[7] * s1 + M[8] * M[8] * s2;
     }
     const int nsh = (cfg.sh_degree + 1) * (cfg.sh_degree + 1);
-    const float* shp = sh + 48 * i;
 
     for (int vv = 0; vv < nv; ++vv) {
         const potr_camera& c = cams.c[vv];
@@ -147,7 +165,7 @@ __global__ __launch_bounds__(256) void k_project(int64_t N, int32_t v0, int32_t 
                 sh_basis_d3(dx, dy, dz, cfg.sh_degree, Y);
                 double cr = 0.5, cg = 0.5, cb = 0.5;
                 // 16-byte loads: four coefficients (r,g,b of k and r of k+1, ...) at a time
-                const float4* sh4 = reinterpret_cast<const float4*>(shp);
+                const float4* sh4 = s_sh + threadIdx.x * kShStride;
                 const int n4 = (3 * nsh + 3) / 4;
                 for (int m = 0; m < n4; ++m) {
                     const float4 q = sh4[m];
@@ -189,14 +207,14 @@ potr_status launch_project(int64_t N, int32_t V, const potr_camera* cams, const 
                            const float* means, const float* scales, const float* quats, const float* opac,
                            const float* sh, potr_proj* proj, int32_t* tiles_touched, hipStream_t s) {
     if (N == 0) return POTR_OK;
-    const dim3 grid((unsigned)ceil_div(N, 256));
+    const dim3 grid((unsigned)ceil_div(N, kProjThreads));
     for (int32_t v0 = 0; v0 < V; v0 += kViewsPerLaunch) {
         const int32_t nv = V - v0 < kViewsPerLaunch ? V - v0 : kViewsPerLaunch;
         CamBatch cb;
         for (int k = 0; k < nv; ++k) cb.c[k] = cams[v0 + k];
         for (int k = nv; k < kViewsPerLaunch; ++k) cb.c[k] = cams[v0];
-        hipLaunchKernelGGL(k_project, grid, dim3(256), 0, s, N, v0, nv, cb, cfg, means, scales, quats, opac, sh,
-                           proj, tiles_touched);
+        hipLaunchKernelGGL(k_project, grid, dim3(kProjThreads), 0, s, N, v0, nv, cb, cfg, means, scales, quats, opac,
+                           sh, proj, tiles_touched);
         potr_status st = check_launch("k_project");
         if (st != POTR_OK) return st;
     }

@@ -86,8 +86,10 @@ class Rasterizer:
                L.ptr(ds.quats), L.ptr(ds.opacities), L.ptr(ds.sh), L.ptr(proj), L.ptr(tt), L.stream_handle())
         return ViewBatch(V=V, N=N, proj=proj, tiles_touched=tt)
 
-    def bin(self, vb: ViewBatch, cams) -> ViewBatch:
-        """Depth order per view and pair counts (potr_bin); reads the count back."""
+    def bin(self, vb: ViewBatch, cams, read_count: bool = True) -> ViewBatch:
+        """Depth order per view and pair counts (potr_bin). With read_count the
+        pair count is read back (a host synchronisation); without, vb.n_pairs
+        stays None and sort() needs an explicit capacity (see pairs_fit)."""
         N, V = vb.N, vb.V
         cam_arr = L.make_cameras(cams)
         order = self._i32("order", V * N)
@@ -95,9 +97,11 @@ class Rasterizer:
         ws = self._buf("bin_ws", L.bin_workspace_size(N, V, cam_arr, self.cfg))
         L.call("potr_bin", N, V, cam_arr, C.byref(self.cfg), L.ptr(vb.proj), L.ptr(ws), ws.numel(), L.ptr(order),
                L.ptr(n_pairs), L.stream_handle())
-        n = int(n_pairs.item())
-        if n < 0:
-            raise L.PotrError("potr_bin", L.POTR_EHIP, "device-side ordering did not complete")
+        n = None
+        if read_count:
+            n = int(n_pairs.item())
+            if n < 0:
+                raise L.PotrError("potr_bin", L.POTR_EHIP, "device-side ordering did not complete")
         vb.order, vb.n_pairs = order, n
         vb._bin_ws = ws
         vb._n_pairs_dev = n_pairs
@@ -107,6 +111,8 @@ class Rasterizer:
         """Tile lists in depth order (potr_sort) into a buffer of `capacity` ids
         (default: exactly the counted pairs)."""
         tx, ty = self.tiles(cams[0])
+        if capacity is None and vb.n_pairs is None:
+            raise ValueError("sort() after bin(read_count=False) needs a capacity")
         cap = vb.n_pairs if capacity is None else int(capacity)
         ids = self._i32("sorted_ids", cap)
         ranges = self._i32("ranges", 2 * vb.V * tx * ty)[: 2 * vb.V * tx * ty]
@@ -115,7 +121,16 @@ class Rasterizer:
                L.ptr(vb._bin_ws), vb._bin_ws.numel(), L.ptr(vb._n_pairs_dev), cap, L.ptr(sws), sws.numel(),
                L.ptr(ids), L.ptr(ranges), L.stream_handle())
         vb.sorted_ids, vb.tile_ranges = ids, ranges
+        vb._capacity = cap
         return vb
+
+    @staticmethod
+    def pairs_fit(vb: ViewBatch) -> bool:
+        """Whether the last sort had room for every pair (reads the count back)."""
+        n = int(vb._n_pairs_dev.item())
+        if vb.n_pairs is None:
+            vb.n_pairs = n
+        return 0 <= n <= vb._capacity
 
     def blend(self, vb: ViewBatch, cams, count_blended: bool = False) -> ViewBatch:
         V, H, W = vb.V, cams[0].height, cams[0].width

@@ -73,16 +73,19 @@ def _upload_records(rect, depth, V, N):
     return proj, tt
 
 
-@pytest.mark.parametrize("N,V,tiles,seed", [(1, 1, (3, 2), 1), (300, 1, (7, 5), 2), (5000, 3, (20, 13), 3),
-                                             (20000, 2, (80, 45), 4), (4096 * 3 + 17, 1, (33, 21), 5),
-                                             # 16 (view, tile) bits + 17 rank bits: 64-bit pairs
-                                             (70000, 3, (128, 128), 6)])
-def test_bin_sort_bit_exact_on_synthetic_records(N, V, tiles, seed):
+@pytest.mark.parametrize("N,V,tiles,seed,big", [
+    (1, 1, (3, 2), 1, None), (300, 1, (7, 5), 2, None), (5000, 3, (20, 13), 3, None),
+    (20000, 2, (80, 45), 4, None), (4096 * 3 + 17, 1, (33, 21), 5, None), (70000, 3, (128, 128), 6, None),
+    # wide rows (9 bits of tile column), tall images, and splats covering up to 1200 tiles
+    (3000, 2, (300, 7), 7, None), (3000, 1, (3, 500), 8, None), (4000, 1, (40, 30), 9, (40, 30)),
+    (64 * 5 + 3, 2, (17, 9), 10, (17, 9))])
+def test_bin_sort_bit_exact_on_synthetic_records(N, V, tiles, seed, big):
     _need_gpu()
     tx, ty = tiles
     rects, depths = [], []
     for v in range(V):
-        r, d = synth.random_tile_records(N, tx, ty, seed * 10 + v)
+        kw = {} if big is None else dict(max_w=big[0], max_h=big[1])
+        r, d = synth.random_tile_records(N, tx, ty, seed * 10 + v, **kw)
         rects.append(r)
         depths.append(d)
     rect, depth = np.stack(rects), np.stack(depths)
@@ -96,19 +99,17 @@ def test_bin_sort_bit_exact_on_synthetic_records(N, V, tiles, seed):
     rz.sort(vb, cams)
     ids = vb.sorted_ids.cpu().numpy()[: vb.n_pairs]
     ranges = vb.tile_ranges.cpu().numpy().reshape(V, tx * ty, 2)
-    total = 0
+    # views back to back: each view's lists follow the previous view's; empty tiles are [0, 0)
+    exp_ids, base = [], 0
     for v in range(V):
         _, oid, orng = oracle.bin_sort(rect[v].astype(np.int32), depth[v].view(np.uint32), tx, ty)
-        base = ranges[v][:, 0].min() if len(oid) else 0
-        for t in range(tx * ty):
-            ob, oe = orng[t]
-            gb, ge = ranges[v][t]
-            assert ge - gb == oe - ob, (v, t)
-            if oe > ob:
-                np.testing.assert_array_equal(ids[gb:ge], oid[ob:oe])
-        total += len(oid)
-        del base
-    assert vb.n_pairs == total
+        nonempty = orng[:, 1] > orng[:, 0]
+        exp_rng = np.where(nonempty[:, None], orng + base, 0)
+        np.testing.assert_array_equal(ranges[v], exp_rng, err_msg=f"view {v}")
+        exp_ids.append(oid)
+        base += len(oid)
+    assert vb.n_pairs == base
+    np.testing.assert_array_equal(ids, np.concatenate(exp_ids).astype(np.uint32))
 
 
 def test_sort_capacity_too_small_places_nothing():
