@@ -35,7 +35,7 @@ __global__ __launch_bounds__(TW * TH) void k_blend_bwd(int64_t N, int32_t W, int
                                                        float* __restrict__ grad2d) {
     constexpr int NT = TW * TH;
     constexpr int NW = (NT + 63) / 64;
-    __shared__ float4 s_a[kBwdChunk];   // mean2d.x, mean2d.y, opacity, conic.b
+    __shared__ float4 s_a[kBwdChunk];   // mean2d.x, mean2d.y, opacity, 2 conic.b
     __shared__ float4 s_b[kBwdChunk];   // conic.a, conic.c, r, g
     __shared__ float s_c[kBwdChunk];    // b
     __shared__ uint32_t s_id[kBwdChunk];
@@ -89,7 +89,7 @@ __global__ __launch_bounds__(TW * TH) void k_blend_bwd(int64_t N, int32_t W, int
             const uint32_t id = ids[beg + base + j];
             const float4* src = reinterpret_cast<const float4*>(pv + id);
             const float4 r0 = src[0], r1 = src[1], r2 = src[2];
-            const float4 a = make_float4(r0.x, r0.y, r1.y, r0.w);
+            const float4 a = make_float4(r0.x, r0.y, r1.y, 2.f * r0.w);
             const float4 b = make_float4(r0.z, r1.x, r1.z, r1.w);
             s_a[j] = a;
             s_b[j] = b;
@@ -109,7 +109,8 @@ __global__ __launch_bounds__(TW * TH) void k_blend_bwd(int64_t N, int32_t W, int
         // groups of four entries: per-lane gradients, then one reduce-scatter per component
         for (int i = 0; i < nl; i += 4) {
             const uint2 q = *reinterpret_cast<const uint2*>(L + i);
-            const int js[4] = {(int)(q.x & 0xffffu), (int)(q.x >> 16), (int)(q.y & 0xffffu), (int)(q.y >> 16)};
+            const uint32_t qx = __builtin_amdgcn_readfirstlane(q.x), qy = __builtin_amdgcn_readfirstlane(q.y);
+            const int js[4] = {(int)(qx & 0xffffu), (int)(qx >> 16), (int)(qy & 0xffffu), (int)(qy >> 16)};
             if (js[0] >= jlim) break;
             float g[4][kG];
 #pragma unroll
@@ -142,8 +143,9 @@ __global__ __launch_bounds__(TW * TH) void k_blend_bwd(int64_t N, int32_t W, int
                     if (al0 < amax) {
                         g[u][5] = dLda * e.G;                      // dalpha/do = G
                         const float dLdq = -0.5f * al0 * dLda;
-                        g[u][0] = dLdq * 2.f * (b.x * dx + a.w * dy);
-                        g[u][1] = dLdq * 2.f * (a.w * dx + b.y * dy);
+                        const float cb = 0.5f * a.w;    // conic.b (staged doubled)
+                        g[u][0] = dLdq * 2.f * (b.x * dx + cb * dy);
+                        g[u][1] = dLdq * 2.f * (cb * dx + b.y * dy);
                         g[u][2] = dLdq * dx * dx;
                         g[u][3] = dLdq * 2.f * dx * dy;
                         g[u][4] = dLdq * dy * dy;

@@ -32,7 +32,7 @@ __device__ inline void stage_batch(const potr_proj* __restrict__ pv, const uint3
         const float4 r0 = src[0];   // mean2d.x, mean2d.y, conic.a, conic.b
         const float4 r1 = src[1];   // conic.c, opacity, r, g
         const float4 r2 = src[2];   // b, depth, rect
-        const float4 a = make_float4(r0.x, r0.y, r1.y, r0.w);
+        const float4 a = make_float4(r0.x, r0.y, r1.y, 2.f * r0.w);
         const float4 b = make_float4(r0.z, r1.x, r1.z, r1.w);
         s_a[j] = a;
         s_b[j] = b;
@@ -87,7 +87,8 @@ __global__ __launch_bounds__(TW * TH) void k_blend(int64_t N, int32_t W, int32_t
         if (__ballot(!done) == 0) continue;
         for (int i = 0; i < nl; i += 4) {
             const uint2 q = *reinterpret_cast<const uint2*>(L + i);
-            const int js[4] = {(int)(q.x & 0xffffu), (int)(q.x >> 16), (int)(q.y & 0xffffu), (int)(q.y >> 16)};
+            const uint32_t qx = __builtin_amdgcn_readfirstlane(q.x), qy = __builtin_amdgcn_readfirstlane(q.y);
+            const int js[4] = {(int)(qx & 0xffffu), (int)(qx >> 16), (int)(qy & 0xffffu), (int)(qy >> 16)};
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 if (i + u >= nl) break;

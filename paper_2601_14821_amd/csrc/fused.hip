@@ -37,7 +37,7 @@ __device__ inline void stage(const potr_proj* __restrict__ pv, const uint32_t* _
         const uint32_t id = ids[base + j];
         const float4* src = reinterpret_cast<const float4*>(pv + id);
         const float4 r0 = src[0], r1 = src[1], r2 = src[2];
-        const float4 a = make_float4(r0.x, r0.y, r1.y, r0.w);
+        const float4 a = make_float4(r0.x, r0.y, r1.y, 2.f * r0.w);
         const float4 b = make_float4(r0.z, r1.x, r1.z, r1.w);
         sm.a[j] = a;
         sm.b[j] = b;
@@ -48,13 +48,15 @@ __device__ inline void stage(const potr_proj* __restrict__ pv, const uint32_t* _
 }
 
 // Four consecutive entries of a wave list (i a multiple of 4; entries at or
-// past the list's end are junk and must not be used).
+// past the list's end are junk and must not be used). Every lane reads the same
+// words; taking them into scalar registers keeps the loop's tests on them scalar.
 __device__ inline void list4(const uint16_t* L, int i, int (&j)[4]) {
     const uint2 q = *reinterpret_cast<const uint2*>(L + i);
-    j[0] = (int)(q.x & 0xffffu);
-    j[1] = (int)(q.x >> 16);
-    j[2] = (int)(q.y & 0xffffu);
-    j[3] = (int)(q.y >> 16);
+    const uint32_t x = __builtin_amdgcn_readfirstlane(q.x), y = __builtin_amdgcn_readfirstlane(q.y);
+    j[0] = (int)(x & 0xffffu);
+    j[1] = (int)(x >> 16);
+    j[2] = (int)(y & 0xffffu);
+    j[3] = (int)(y >> 16);
 }
 
 template <int TW, int TH, bool SE>
@@ -99,19 +101,31 @@ __device__ void render_score_tile(const ViewJob& J, int tile, const potr_config&
         for (int i = 0; i < nl; i += 4) {
             int js[4];
             list4(L, i, js);
+            // the group's records, read before any of them is used (slots past
+            // the list's end read entry js[0] and are skipped)
+            const int nv = min(4, nl - i);
+            float4 ra[4], rb[4];
+            float rc[4];
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
-                if (i + u >= nl) break;
+                const int jj = u < nv ? js[u] : js[0];
+                ra[u] = sm.a[jj];
+                rb[u] = sm.b[jj];
+                rc[u] = sm.c[jj];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                if (u >= nv) break;
                 const int j = js[u];
-                const float4 b = sm.b[j];
-                const float a0 = alpha_of(eval_gauss(sm.a[j], b, fx, fy), qmax, amin, amax);
+                const float4 b = rb[u];
+                const float a0 = alpha_of(eval_gauss(ra[u], b, fx, fy), qmax, amin, amax);
                 const float al = done ? 0.f : a0;
                 const float Tn = next_T(T, al);
                 const bool stop = Tn < tmin;       // T >= tmin before, so only when al > 0
                 const float w = stop ? 0.f : __fmul_rn(T, al);
                 cr = add_weighted(cr, w, b.z);
                 cg = add_weighted(cg, w, b.w);
-                cb = add_weighted(cb, w, sm.c[j]);
+                cb = add_weighted(cb, w, rc[u]);
                 T = stop ? T : Tn;
                 walk = stop ? base - beg + j : walk;
                 done = done || stop;
@@ -187,16 +201,29 @@ __device__ void render_score_tile(const ViewJob& J, int tile, const potr_config&
             int js[4];
             list4(LL, i, js);
             if (js[0] >= jlim) break;
+            // the group's valid slots (the list is increasing, so they are a prefix)
+            int ng = 1;
+#pragma unroll
+            for (int u = 1; u < 4; ++u) ng += (ng == u && i + u < nv && js[u] < jlim) ? 1 : 0;
+            float4 ra[4], rb[4];
+            float rc[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int jj = u < ng ? js[u] : js[0];
+                ra[u] = sm.a[jj];
+                rb[u] = sm.b[jj];
+                rc[u] = sm.c[jj];
+            }
             float l1v[4] = {0.f, 0.f, 0.f, 0.f}, imv[4] = {0.f, 0.f, 0.f, 0.f}, sev[4] = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
-                if (i + u >= nv || js[u] >= jlim) break;
+                if (u >= ng) break;
                 const int j = js[u];
-                const float4 b = sm.b[j];
-                const float a0 = alpha_of(eval_gauss(sm.a[j], b, fx, fy), qmax, amin, amax);
+                const float4 b = rb[u];
+                const float a0 = alpha_of(eval_gauss(ra[u], b, fx, fy), qmax, amin, amax);
                 const float al = base + j < walk ? a0 : 0.f;
                 const float w = __fmul_rn(T, al);
-                const float c0 = b.z, c1 = b.w, c2 = sm.c[j];
+                const float c0 = b.z, c1 = b.w, c2 = rc[u];
                 Pr = add_weighted(Pr, w, c0);
                 Pg = add_weighted(Pg, w, c1);
                 Pb = add_weighted(Pb, w, c2);
@@ -213,7 +240,7 @@ __device__ void render_score_tile(const ViewJob& J, int tile, const potr_config&
             if (!any) continue;
             // lane u < 4 writes entry js[u] (only entries that are in the list)
             const int jw = lane == 0 ? js[0] : lane == 1 ? js[1] : lane == 2 ? js[2] : js[3];
-            const bool writer = lane < 4 && i + lane < nv && jw < jlim;
+            const bool writer = lane < ng;
             if (J.scores) {
                 const float s = wave_sum4(l1v[0], l1v[1], l1v[2], l1v[3]);
                 if (writer) sm.part[(o_l1 * NW + wid) * B + jw] = s;

@@ -9,7 +9,8 @@
 
 namespace potr {
 
-// Staged record: a = (mean2d.x, mean2d.y, opacity, conic.b), b = (conic.a, conic.c, r, g), c = blue.
+// Staged record: a = (mean2d.x, mean2d.y, opacity, 2 conic.b), b = (conic.a, conic.c, r, g), c = blue.
+// (Doubling conic.b is exact, so the quadratic form keeps its rounding.)
 struct Gauss {
     float dx, dy;   // centre minus pixel centre
     float q;        // a dx^2 + 2 b dx dy + c dy^2
@@ -22,7 +23,7 @@ __device__ inline Gauss eval_gauss(const float4& a, const float4& b, float fx, f
     r.dx = __fsub_rn(a.x, fx);
     r.dy = __fsub_rn(a.y, fy);
     const float ad = __fmul_rn(b.x, r.dx);
-    const float bd = __fmul_rn(__fmul_rn(2.f, a.w), r.dx);
+    const float bd = __fmul_rn(a.w, r.dx);
     const float cd = __fmul_rn(b.y, r.dy);
     r.q = __fmaf_rn(ad, r.dx, __fmaf_rn(bd, r.dy, __fmul_rn(cd, r.dy)));
     // exp(-q/2) = exp2(q * (-log2(e) / 2)); halving the FP32 log2(e) is exact
@@ -48,7 +49,7 @@ __device__ inline float add_weighted(float P, float w, float c) { return __fmaf_
 __device__ inline uint32_t reach_rows(const float4& a, const float4& b, float qmax, int tile_y0, int TH) {
     // FP64: the products of FP32 values are exact, so det has one rounding even
     // for very elongated ellipses
-    const double A = b.x, B = a.w, Cc = b.y;
+    const double A = b.x, B = 0.5 * (double)a.w, Cc = b.y;
     const double det = A * Cc - B * B;
     int r0 = 0, r1 = TH - 1;
     if (det > 0.0) {
