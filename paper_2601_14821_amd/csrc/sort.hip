@@ -306,10 +306,9 @@ __global__ void k_clear(uint64_t* __restrict__ p, int64_t n) {
 //               position in the row's region of the output;
 //   tiles table tc[v][g][t]  pairs of group g in tile t, scanned over the
 //               groups: every group's first position in tile t.
-// Level 1 (a wave per chunk, 64 splats at a time, one lane per splat) appends,
-// row by row, each splat's run of (x, id) for the tiles of its rect to the
-// row's region (lanes covering the row take consecutive places by a prefix
-// sum of their widths, so the chunk's run in a row is contiguous). Level 2 (a
+// Level 1 (a wave per chunk, its splats in rank order, lanes on the tiles of
+// one splat) appends (x, id) for every tile of the rect to its row's region
+// through per-row cursors, so the chunk's run in a row is contiguous. Level 2 (a
 // block per (group, row)) reads the group's segment of the row and places
 // each id at its tile's cursor, ranking equal tiles with ballots so that each
 // tile's run leaves as contiguous stores. The layout of the rows' regions is
