@@ -123,10 +123,11 @@ __global__ __launch_bounds__(kProjThreads) void k_project(int64_t N, int32_t v0,
             const double fx = c.fx, fy = c.fy;
             const double limx = (double)cfg.jclamp * 0.5 * c.width / fx;
             const double limy = (double)cfg.jclamp * 0.5 * c.height / fy;
-            const double tx = fmin(limx, fmax(-limx, px / pz));
-            const double ty = fmin(limy, fmax(-limy, py / pz));
+            const double iz = 1.0 / pz;   // one FP64 division; the quotients below are products
+            const double tx = fmin(limx, fmax(-limx, px * iz));
+            const double ty = fmin(limy, fmax(-limy, py * iz));
             // T = J W (2x3); J = [[fx/z, 0, -fx tx/z], [0, fy/z, -fy ty/z]]
-            const double j00 = fx / pz, j02 = -fx * tx / pz, j11 = fy / pz, j12 = -fy * ty / pz;
+            const double j00 = fx * iz, j02 = -fx * tx * iz, j11 = fy * iz, j12 = -fy * ty * iz;
             const double T00 = j00 * R0 + j02 * R6, T01 = j00 * R1 + j02 * R7, T02 = j00 * R2 + j02 * R8;
             const double T10 = j11 * R3 + j12 * R6, T11 = j11 * R4 + j12 * R7, T12 = j11 * R5 + j12 * R8;
             // cov2d = T Sigma T^T
@@ -140,8 +141,8 @@ __global__ __launch_bounds__(kProjThreads) void k_project(int64_t N, int32_t v0,
             const double cxy = a0 * T10 + a1 * T11 + a2 * T12;
             const double cyy = b0 * T10 + b1 * T11 + b2 * T12 + (double)cfg.eps2d;
             const double det = cxx * cyy - cxy * cxy;
-            const double u = fx * px / pz + (double)c.cx;
-            const double v = fy * py / pz + (double)c.cy;
+            const double u = fx * px * iz + (double)c.cx;
+            const double v = fy * py * iz + (double)c.cy;
             const double t_cut = fmin((double)cfg.q_max, 2.0 * log(o / (double)cfg.alpha_min));
             const double rx = sqrt(t_cut * cxx) * (1.0 + 1.0 / 1024.0) + 1.0 / 64.0;
             const double ry = sqrt(t_cut * cyy) * (1.0 + 1.0 / 1024.0) + 1.0 / 64.0;
@@ -149,9 +150,10 @@ __global__ __launch_bounds__(kProjThreads) void k_project(int64_t N, int32_t v0,
             if (ok) {
                 rec.mean2d[0] = (float)u;
                 rec.mean2d[1] = (float)v;
-                rec.conic[0] = (float)(cyy / det);
-                rec.conic[1] = (float)(-cxy / det);
-                rec.conic[2] = (float)(cxx / det);
+                const double idet = 1.0 / det;
+                rec.conic[0] = (float)(cyy * idet);
+                rec.conic[1] = (float)(-cxy * idet);
+                rec.conic[2] = (float)(cxx * idet);
                 rec.opacity = (float)o;
 
                 // colour along the camera -> centre direction

@@ -330,10 +330,12 @@ __device__ inline void load_rect(const potr_proj* __restrict__ pv, uint32_t id, 
     yw = (r.x >> 16) | (r.y & 0xffff0000u);                              // y0 | y1 << 16
 }
 
-// rc[v][c][y]: pairs of chunk c in row y (one splat per thread).
+// rc[v][c][y]: pairs of chunk c in row y (one splat per thread), also added
+// into the row's sum over the chunk's segment of the column scan (segr,
+// cleared beforehand).
 __global__ __launch_bounds__(kChunk) void k_row_count(const uint32_t* __restrict__ order,
                                                       const potr_proj* __restrict__ proj, Bins B,
-                                                      uint32_t* __restrict__ rc) {
+                                                      uint32_t* __restrict__ rc, uint32_t* __restrict__ segr) {
     extern __shared__ uint32_t rows[];
     const int c = blockIdx.x, v = blockIdx.y;
     for (int y = threadIdx.x; y < B.tiles_y; y += kChunk) rows[y] = 0;
@@ -347,40 +349,19 @@ __global__ __launch_bounds__(kChunk) void k_row_count(const uint32_t* __restrict
             for (int y = (int)(yw & 0xffffu); y < (int)(yw >> 16); ++y) atomicAdd(&rows[y], (uint32_t)w);
     }
     __syncthreads();
-    for (int y = threadIdx.x; y < B.tiles_y; y += kChunk) rc[((int64_t)v * B.C + c) * B.tiles_y + y] = rows[y];
-}
-
-// Column scans of a table [v][R rows][cols]: segment sums over seglen rows ...
-__global__ __launch_bounds__(256) void k_seg_sums(const uint32_t* __restrict__ tab, int32_t R, int32_t cols,
-                                                  int32_t seglen, int32_t nseg, uint32_t* __restrict__ segsum) {
-    const int col = blockIdx.x * 256 + threadIdx.x, seg = blockIdx.y, v = blockIdx.z;
-    if (col >= cols) return;
-    const int r0 = seg * seglen, r1 = min(R, r0 + seglen);
-    const uint32_t* p = tab + ((int64_t)v * R) * cols + col;
-    uint32_t s = 0;
-#pragma unroll 8
-    for (int r = r0; r < r1; ++r) s += p[(int64_t)r * cols];
-    segsum[((int64_t)v * nseg + seg) * cols + col] = s;
-}
-
-// ... the segment sums' exclusive prefix in place and the column totals ...
-__global__ __launch_bounds__(256) void k_seg_prefix(uint32_t* __restrict__ segsum, int32_t V, int32_t cols,
-                                                    int32_t nseg, uint32_t* __restrict__ total) {
-    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (i >= (int64_t)V * cols) return;
-    const int64_t v = i / cols, col = i - v * cols;
-    uint32_t run = 0;
-    for (int seg = 0; seg < nseg; ++seg) {
-        uint32_t* p = segsum + (v * nseg + seg) * cols + col;
-        const uint32_t x = *p;
-        *p = run;
-        run += x;
+    uint32_t* sg = segr + ((int64_t)v * B.nseg_c + c / B.seg_c) * B.tiles_y;
+    for (int y = threadIdx.x; y < B.tiles_y; y += kChunk) {
+        const uint32_t x = rows[y];
+        rc[((int64_t)v * B.C + c) * B.tiles_y + y] = x;
+        if (x) atomicAdd(sg + y, x);
     }
-    total[i] = run;
 }
 
-// ... and each row's first position: out[v][r][col] = base[v][col] + (sum of
-// rows before r). With R_out = R + 1 the extra row holds the column's end.
+// Column scans of a table [v][R rows][cols] go by segments of seglen rows: the
+// count kernels add each segment's sums (segsum[v][seg][col]), the base kernels
+// turn them into exclusive prefixes in place, and each row's first position
+// is out[v][r][col] = base[v][col] + (sum of rows before r). With R_out = R + 1
+// the extra row holds the column's end.
 __global__ __launch_bounds__(256) void k_seg_offsets(const uint32_t* __restrict__ tab,
                                                      const uint32_t* __restrict__ segsum,
                                                      const int64_t* __restrict__ base, int32_t R, int32_t cols,
@@ -403,27 +384,44 @@ __global__ __launch_bounds__(256) void k_seg_offsets(const uint32_t* __restrict_
     if (r1 == R && R_out > R) out[((int64_t)v * R_out + R) * cols + col] = run;
 }
 
-// One block: row bases = exclusive scan of the row totals over (view, row),
-// and the number of pairs (-1 if a depth pass gave up a wait).
-__global__ __launch_bounds__(1024) void k_row_bases(const uint32_t* __restrict__ total, int64_t n,
+// Turns the nseg (<= kMaxSegs) segment sums p[0], p[stride], ... into
+// exclusive prefixes in place and returns their total. All loads are issued
+// before the first store.
+__device__ inline uint32_t seg_prefix(uint32_t* __restrict__ p, int64_t stride, int nseg) {
+    uint32_t x[kMaxSegs];
+#pragma unroll
+    for (int k = 0; k < kMaxSegs; ++k) x[k] = k < nseg ? p[k * stride] : 0u;
+    uint32_t run = 0;
+#pragma unroll
+    for (int k = 0; k < kMaxSegs; ++k) {
+        if (k < nseg) p[k * stride] = run;
+        run += x[k];
+    }
+    return run;
+}
+
+// One block: per (view, row), the segment sums become exclusive prefixes in
+// place and give the row's total; row bases = exclusive scan of the totals over
+// (view, row); the number of pairs (-1 if a depth pass gave up a wait).
+__global__ __launch_bounds__(1024) void k_row_bases(uint32_t* __restrict__ segr, Bins B,
                                                     int64_t* __restrict__ base, const uint32_t* __restrict__ fault,
                                                     int64_t* __restrict__ n_pairs) {
     __shared__ int64_t wsum[16];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int64_t n = (int64_t)B.V * B.tiles_y;
     int64_t carry = 0;
-    for (int64_t b0 = 0; b0 < n; b0 += 1024 * 8) {
-        const int64_t i0 = b0 + (int64_t)threadIdx.x * 8;
-        int64_t x[8], tot = 0;
-#pragma unroll
-        for (int k = 0; k < 8; ++k) {
-            x[k] = i0 + k < n ? (int64_t)total[i0 + k] : 0;
-            tot += x[k];
+    for (int64_t b0 = 0; b0 < n; b0 += 1024) {
+        const int64_t i = b0 + threadIdx.x;
+        int64_t tot = 0;
+        if (i < n) {
+            const int64_t v = i / B.tiles_y, y = i - v * B.tiles_y;
+            tot = seg_prefix(segr + v * B.nseg_c * B.tiles_y + y, B.tiles_y, B.nseg_c);
         }
         int64_t inc = tot;
 #pragma unroll
         for (int d = 1; d < 64; d <<= 1) {
-            const int64_t y = __shfl_up(inc, d, 64);
-            if (lane >= d) inc += y;
+            const int64_t u = __shfl_up(inc, d, 64);
+            if (lane >= d) inc += u;
         }
         if (lane == 63) wsum[w] = inc;
         __syncthreads();
@@ -433,22 +431,18 @@ __global__ __launch_bounds__(1024) void k_row_bases(const uint32_t* __restrict__
             if (k < w) pre += wsum[k];
             all += wsum[k];
         }
-        int64_t run = pre + inc - tot;
-#pragma unroll
-        for (int k = 0; k < 8; ++k) {
-            if (i0 + k < n) base[i0 + k] = run;
-            run += x[k];
-        }
+        if (i < n) base[i] = pre + inc - tot;
         carry += all;
         __syncthreads();
     }
     if (threadIdx.x == 0) *n_pairs = *fault ? (int64_t)-1 : carry;
 }
 
-// A wave per (view, row): tile bases = the row's base + exclusive scan of its
-// tile totals, and tile ranges ([0, 0) when empty; all empty when the pairs
-// exceed the capacity).
-__global__ __launch_bounds__(64) void k_tile_bases(const uint32_t* __restrict__ total, const int64_t* __restrict__ rbase,
+// A wave per (view, row): per tile, the segment sums become exclusive prefixes
+// in place and give the tile's total; tile bases = the row's base + exclusive
+// scan of its tile totals; tile ranges ([0, 0) when empty; all empty when the
+// pairs exceed the capacity).
+__global__ __launch_bounds__(64) void k_tile_bases(uint32_t* __restrict__ segt, const int64_t* __restrict__ rbase,
                                                    Bins B, const int64_t* __restrict__ n_pairs, int64_t capacity,
                                                    int64_t* __restrict__ tbase, int32_t* __restrict__ ranges) {
     const int y = blockIdx.x, v = blockIdx.y, lane = threadIdx.x;
@@ -458,7 +452,8 @@ __global__ __launch_bounds__(64) void k_tile_bases(const uint32_t* __restrict__ 
     const int64_t t0 = (int64_t)v * B.T + (int64_t)y * B.tiles_x;
     for (int x0 = 0; x0 < B.tiles_x; x0 += 64) {
         const int x = x0 + lane;
-        const int64_t c = x < B.tiles_x ? (int64_t)total[t0 + x] : 0;
+        int64_t c = 0;
+        if (x < B.tiles_x) c = seg_prefix(segt + (int64_t)v * B.nseg_g * B.T + (int64_t)y * B.tiles_x + x, B.T, B.nseg_g);
         int64_t inc = c;
 #pragma unroll
         for (int d = 1; d < 64; d <<= 1) {
@@ -484,8 +479,13 @@ __global__ __launch_bounds__(64) void k_place_rows(const uint32_t* __restrict__ 
                                                    const potr_proj* __restrict__ proj,
                                                    const uint32_t* __restrict__ roff, Bins B,
                                                    const int64_t* __restrict__ n_pairs, int64_t capacity,
-                                                   uint16_t* __restrict__ stage_x, uint32_t* __restrict__ stage_id) {
+                                                   uint16_t* __restrict__ stage_x, uint32_t* __restrict__ stage_id,
+                                                   uint32_t* __restrict__ segt, int64_t segt_n) {
     extern __shared__ uint32_t cur[];   // [tiles_y]
+    // clear the tile segment sums the column counts add into (next kernel)
+    for (int64_t i = ((int64_t)blockIdx.y * gridDim.x + blockIdx.x) * 64 + threadIdx.x; i < segt_n;
+         i += (int64_t)gridDim.x * gridDim.y * 64)
+        segt[i] = 0;
     const int64_t n = *n_pairs;
     if (n < 0 || n > capacity) return;
     const int c = blockIdx.x, v = blockIdx.y, lane = threadIdx.x;
@@ -545,7 +545,8 @@ __global__ __launch_bounds__(64) void k_place_rows(const uint32_t* __restrict__ 
 // each row (a block per (view, group, row)).
 __global__ __launch_bounds__(256) void k_col_count(const uint32_t* __restrict__ roff, Bins B,
                                                    const int64_t* __restrict__ n_pairs, int64_t capacity,
-                                                   const uint16_t* __restrict__ stage_x, uint32_t* __restrict__ tc) {
+                                                   const uint16_t* __restrict__ stage_x, uint32_t* __restrict__ tc,
+                                                   uint32_t* __restrict__ segt) {
     extern __shared__ uint32_t cnt[];   // [tiles_x]
     const int64_t n = *n_pairs;
     if (n < 0 || n > capacity) return;
@@ -558,7 +559,11 @@ __global__ __launch_bounds__(256) void k_col_count(const uint32_t* __restrict__ 
     for (uint32_t i = s0 + threadIdx.x; i < s1; i += 256) atomicAdd(&cnt[stage_x[i]], 1u);
     __syncthreads();
     uint32_t* out = tc + ((int64_t)v * B.G + g) * B.T + (int64_t)y * B.tiles_x;
-    for (int x = threadIdx.x; x < B.tiles_x; x += 256) out[x] = cnt[x];
+    uint32_t* sg = segt + ((int64_t)v * B.nseg_g + g / B.seg_g) * B.T + (int64_t)y * B.tiles_x;
+    for (int x = threadIdx.x; x < B.tiles_x; x += 256) {
+        out[x] = cnt[x];
+        if (cnt[x]) atomicAdd(sg + x, cnt[x]);
+    }
 }
 
 // Level 2: block per (view, group, row). The row segment level 1 wrote for
@@ -696,9 +701,10 @@ Bins bins_of(int64_t N, int32_t V, int32_t tiles_x, int32_t tiles_y) {
 struct BinWs {
     Ctl ctl;
     uint32_t *ka, *kb, *va;
-    uint32_t *rc, *roff, *segr, *totr;
+    uint32_t *rc, *roff, *segr;
     int64_t* rbase;
-    uint32_t *tc, *toff, *segt, *tott;
+    uint32_t *tc, *toff, *segt;
+    int64_t segt_n;
     int64_t* tbase;
     size_t bytes;
 };
@@ -714,20 +720,19 @@ BinWs bin_layout(int64_t N, int32_t V, int32_t tiles_x, int32_t tiles_y, char* b
     w.ctl.fault = w.ctl.ticket + kMaxPasses + 1;
     w.ctl.ghist = (uint32_t*)take(4 * (size_t)V * kMaxPasses * 256);
     w.ctl.status = (uint64_t*)take(8 * (size_t)V * bps * 256);
+    const size_t ty = (size_t)tiles_y, T = (size_t)B.T;
+    w.segr = (uint32_t*)take(4 * (size_t)V * B.nseg_c * ty);   // cleared with the control words
     w.ctl.clear_words = (int64_t)(o / 8);
     w.ka = (uint32_t*)take(4 * VN);
     w.kb = (uint32_t*)take(4 * VN);
     w.va = (uint32_t*)take(4 * VN);
-    const size_t ty = (size_t)tiles_y, T = (size_t)B.T;
     w.rc = (uint32_t*)take(4 * (size_t)V * B.C * ty);
     w.roff = (uint32_t*)take(4 * (size_t)V * (B.C + 1) * ty);
-    w.segr = (uint32_t*)take(4 * (size_t)V * B.nseg_c * ty);
-    w.totr = (uint32_t*)take(4 * (size_t)V * ty);
     w.rbase = (int64_t*)take(8 * (size_t)V * ty);
     w.tc = (uint32_t*)take(4 * (size_t)V * B.G * T);
     w.toff = (uint32_t*)take(4 * (size_t)V * B.G * T);
-    w.segt = (uint32_t*)take(4 * (size_t)V * B.nseg_g * T);
-    w.tott = (uint32_t*)take(4 * (size_t)V * T);
+    w.segt_n = (int64_t)V * B.nseg_g * (int64_t)T;
+    w.segt = (uint32_t*)take(4 * (size_t)w.segt_n);
     w.tbase = (int64_t*)take(8 * (size_t)V * T);
     w.bytes = o;
     return w;
@@ -750,17 +755,6 @@ size_t cols_lds(const Bins& B) {
 }
 
 // column scan of tab[v][R][cols] into out[v][R_out][cols] starting at base[v][cols]
-potr_status col_scan_sums(const uint32_t* tab, int32_t R, int32_t cols, int32_t seglen, int32_t nseg, int32_t V,
-                          uint32_t* segsum, uint32_t* total, hipStream_t s) {
-    const dim3 g((unsigned)ceil_div(cols, 256), nseg, V);
-    hipLaunchKernelGGL(k_seg_sums, g, dim3(256), 0, s, tab, R, cols, seglen, nseg, segsum);
-    potr_status st = check_launch("k_seg_sums");
-    if (st != POTR_OK) return st;
-    hipLaunchKernelGGL(k_seg_prefix, dim3((unsigned)ceil_div((int64_t)V * cols, 256)), dim3(256), 0, s, segsum, V,
-                       cols, nseg, total);
-    return check_launch("k_seg_prefix");
-}
-
 potr_status col_scan_offsets(const uint32_t* tab, const uint32_t* segsum, const int64_t* base, int32_t R,
                              int32_t cols, int32_t seglen, int32_t nseg, int32_t V, int32_t R_out,
                              const int64_t* n_pairs, int64_t capacity, uint32_t* out, hipStream_t s) {
@@ -809,15 +803,13 @@ potr_status launch_bin(int64_t N, int32_t V, const potr_camera& cam0, const potr
             kout = t;
         }
         hipLaunchKernelGGL(k_row_count, dim3(B.C, V), dim3(kChunk), (size_t)tys * 4, s, (const uint32_t*)order, proj,
-                           B, w.rc);
+                           B, w.rc, w.segr);
         st = check_launch("k_row_count");
         if (st != POTR_OK) return st;
     }
-    // rows: totals, bases over (view, row), the pair count, each chunk's first position per row
-    st = col_scan_sums(w.rc, B.C, tys, B.seg_c, B.nseg_c, V, w.segr, w.totr, s);
-    if (st != POTR_OK) return st;
-    hipLaunchKernelGGL(k_row_bases, dim3(1), dim3(1024), 0, s, (const uint32_t*)w.totr, (int64_t)V * tys, w.rbase,
-                       (const uint32_t*)w.ctl.fault, n_pairs);
+    // rows: bases over (view, row), the pair count, each chunk's first position per row
+    hipLaunchKernelGGL(k_row_bases, dim3(1), dim3(1024), 0, s, w.segr, B, w.rbase, (const uint32_t*)w.ctl.fault,
+                       n_pairs);
     st = check_launch("k_row_bases");
     if (st != POTR_OK) return st;
     return col_scan_offsets(w.rc, w.segr, w.rbase, B.C, tys, B.seg_c, B.nseg_c, V, B.C + 1, n_pairs, -1, w.roff, s);
@@ -835,20 +827,23 @@ potr_status launch_sort(int64_t N, int32_t V, const potr_camera& cam0, const pot
     potr_status st = POTR_OK;
     if (N > 0) {
         // level 1: pairs into their rows; then the pairs per (group, tile)
+        // (level 1 also clears the tile segment sums the column counts add into)
         hipLaunchKernelGGL(k_place_rows, dim3(B.C, V), dim3(64), (size_t)tys * 4, s, order, proj,
-                           (const uint32_t*)w.roff, B, n_pairs, capacity, stage_x, stage_id);
+                           (const uint32_t*)w.roff, B, n_pairs, capacity, stage_x, stage_id, w.segt, w.segt_n);
         st = check_launch("k_place_rows");
         if (st != POTR_OK) return st;
         hipLaunchKernelGGL(k_col_count, dim3(B.G, tys, V), dim3(256), (size_t)txs * 4, s, (const uint32_t*)w.roff, B,
-                           n_pairs, capacity, (const uint16_t*)stage_x, w.tc);
+                           n_pairs, capacity, (const uint16_t*)stage_x, w.tc, w.segt);
         st = check_launch("k_col_count");
-        if (st != POTR_OK) return st;
+    } else {
+        const unsigned cb = (unsigned)std::min<int64_t>(ceil_div((w.segt_n + 1) / 2, 256), 4096);
+        hipLaunchKernelGGL(k_clear, dim3(cb), dim3(256), 0, s, (uint64_t*)w.segt, (w.segt_n + 1) / 2);
+        st = check_launch("k_clear");
     }
-    // tiles: totals, bases (within their row), ranges, each group's first position per tile
-    st = col_scan_sums(w.tc, B.G, B.T, B.seg_g, B.nseg_g, V, w.segt, w.tott, s);
     if (st != POTR_OK) return st;
-    hipLaunchKernelGGL(k_tile_bases, dim3(tys, V), dim3(64), 0, s, (const uint32_t*)w.tott, (const int64_t*)w.rbase, B,
-                       n_pairs, capacity, w.tbase, tile_ranges);
+    // tiles: bases (within their row), ranges, each group's first position per tile
+    hipLaunchKernelGGL(k_tile_bases, dim3(tys, V), dim3(64), 0, s, w.segt, (const int64_t*)w.rbase, B, n_pairs,
+                       capacity, w.tbase, tile_ranges);
     st = check_launch("k_tile_bases");
     if (st != POTR_OK || N == 0) return st;
     st = col_scan_offsets(w.tc, w.segt, w.tbase, B.G, B.T, B.seg_g, B.nseg_g, V, B.G, n_pairs, capacity, w.toff, s);
