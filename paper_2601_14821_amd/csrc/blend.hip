@@ -183,7 +183,7 @@ __global__ __launch_bounds__(TW * TH) void k_score(int64_t N, int32_t W, int32_t
     __syncthreads();
     const int wmax = s_wmax;
 
-    float T = 1.f, Pr = 0.f, Pg = 0.f, Pb = 0.f;
+    float T = 1.f, Rr = Qr, Rg = Qg, Rb = Qb;   // Q - P: colour still to come
     for (int base = 0; base < wmax; base += B) {
         const int cnt = min(B, wmax - base);
         stage_batch<NT, TH>(pv, ids, beg + base, cnt, s_a, s_b, s_c, s_id, s_rows, qmax, tile_y0);
@@ -201,13 +201,14 @@ __global__ __launch_bounds__(TW * TH) void k_score(int64_t N, int32_t W, int32_t
                 if (al != 0.f) {
                     const float w = __fmul_rn(T, al);
                     const float cr = b.z, cg = b.w, cbl = s_c[j];
-                    Pr = add_weighted(Pr, w, cr);
-                    Pg = add_weighted(Pg, w, cg);
-                    Pb = add_weighted(Pb, w, cbl);
-                    const float k = odds(al);
-                    const float dr = removal_delta(w, cr, k, Qr, Pr);
-                    const float dg = removal_delta(w, cg, k, Qg, Pg);
-                    const float db = removal_delta(w, cbl, k, Qb, Pb);
+                    const float r0 = Rr, r1 = Rg, r2 = Rb;
+                    Rr = sub_weighted(Rr, w, cr);
+                    Rg = sub_weighted(Rg, w, cg);
+                    Rb = sub_weighted(Rb, w, cbl);
+                    const float inv = inv_keep(al);
+                    const float dr = removal_delta(inv, Rr, r0);
+                    const float dg = removal_delta(inv, Rg, r1);
+                    const float db = removal_delta(inv, Rb, r2);
                     l1 = fabsf(dr) + fabsf(dg) + fabsf(db);
                     se = dr * dr + dg * dg + db * db + 2.f * (dr * er + dg * eg + db * eb);
                     im = w;

@@ -21,7 +21,8 @@ struct ViewJobs {
     ViewJob j[kViewsPerLaunch];
 };
 
-size_t fused_smem_bytes(const potr_config& cfg);
+// dynamic LDS bytes of the fused pass with n_out per-splat outputs
+size_t fused_smem_bytes(const potr_config& cfg, int n_out);
 int persistent_grid(const potr_config& cfg);
 potr_status launch_render_score(const ViewJobs& jobs, int32_t n_views, int32_t tiles_per_view,
                                 const potr_config& cfg, hipStream_t s);

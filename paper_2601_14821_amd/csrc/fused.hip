@@ -18,16 +18,20 @@
 namespace potr {
 namespace {
 
+// One staged splat: a, b and (blue, -, -, -) side by side, so that a sweep
+// reads all three with one address and immediate offsets.
+struct Rec {
+    float4 a, b, c;
+};
+
 struct Smem {
-    float4* a;
-    float4* b;
-    float* c;
+    Rec* rec;
     uint32_t* id;
     uint32_t* rows;    // reach_rows per entry
     uint16_t* list;    // [NW][B] per-wave lists of the entries reaching the wave's rows
     uint16_t* hits;    // [NW][B] per-wave lists of the entries some lane of the wave blended
-    float* part;       // [n_out][NW][B]
     int* misc;         // [0]: wmax, [1]: next item
+    float* part;       // [n_out][NW][B], n_out = number of per-splat outputs (last, sized by the launch)
 };
 
 template <int NT, int TH>
@@ -39,9 +43,9 @@ __device__ inline void stage(const potr_proj* __restrict__ pv, const uint32_t* _
         const float4 r0 = src[0], r1 = src[1], r2 = src[2];
         const float4 a = make_float4(r0.x, r0.y, r1.y, 2.f * r0.w);
         const float4 b = make_float4(r0.z, r1.x, r1.z, r1.w);
-        sm.a[j] = a;
-        sm.b[j] = b;
-        sm.c[j] = r2.x;
+        sm.rec[j].a = a;
+        sm.rec[j].b = b;
+        sm.rec[j].c = make_float4(r2.x, 0.f, 0.f, 0.f);
         sm.id[j] = id;
         sm.rows[j] = reach_rows(a, b, qmax, tile_y0, TH);
     }
@@ -109,9 +113,9 @@ __device__ void render_score_tile(const ViewJob& J, int tile, const potr_config&
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 const int jj = u < nv ? js[u] : js[0];
-                ra[u] = sm.a[jj];
-                rb[u] = sm.b[jj];
-                rc[u] = sm.c[jj];
+                ra[u] = sm.rec[jj].a;
+                rb[u] = sm.rec[jj].b;
+                rc[u] = sm.rec[jj].c.x;
             }
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
@@ -176,7 +180,7 @@ __device__ void render_score_tile(const ViewJob& J, int tile, const potr_config&
     for (int m = 32; m >= 1; m >>= 1) wave_walk = max(wave_walk, __shfl_xor(wave_walk, m, 64));
     wave_walk = __builtin_amdgcn_readfirstlane(wave_walk);
     T = 1.f;
-    float Pr = 0.f, Pg = 0.f, Pb = 0.f;
+    float Rr = Qr, Rg = Qg, Rb = Qb;   // Q - P: colour still to come
     for (int base = 0; base < wmax; base += B) {
         const int cnt = min(B, wmax - base);
         // entries to revisit: those this wave blended when the batch is still the
@@ -210,9 +214,9 @@ __device__ void render_score_tile(const ViewJob& J, int tile, const potr_config&
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 const int jj = u < ng ? js[u] : js[0];
-                ra[u] = sm.a[jj];
-                rb[u] = sm.b[jj];
-                rc[u] = sm.c[jj];
+                ra[u] = sm.rec[jj].a;
+                rb[u] = sm.rec[jj].b;
+                rc[u] = sm.rec[jj].c.x;
             }
             float l1v[4] = {0.f, 0.f, 0.f, 0.f}, imv[4] = {0.f, 0.f, 0.f, 0.f}, sev[4] = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
@@ -224,13 +228,14 @@ __device__ void render_score_tile(const ViewJob& J, int tile, const potr_config&
                 const float al = base + j < walk ? a0 : 0.f;
                 const float w = __fmul_rn(T, al);
                 const float c0 = b.z, c1 = b.w, c2 = rc[u];
-                Pr = add_weighted(Pr, w, c0);
-                Pg = add_weighted(Pg, w, c1);
-                Pb = add_weighted(Pb, w, c2);
-                const float k = odds(al);
-                const float dr = removal_delta(w, c0, k, Qr, Pr);
-                const float dg = removal_delta(w, c1, k, Qg, Pg);
-                const float db = removal_delta(w, c2, k, Qb, Pb);
+                const float r0 = Rr, r1 = Rg, r2 = Rb;
+                Rr = sub_weighted(Rr, w, c0);
+                Rg = sub_weighted(Rg, w, c1);
+                Rb = sub_weighted(Rb, w, c2);
+                const float inv = inv_keep(al);
+                const float dr = removal_delta(inv, Rr, r0);
+                const float dg = removal_delta(inv, Rg, r1);
+                const float db = removal_delta(inv, Rb, r2);
                 l1v[u] = fabsf(dr) + fabsf(dg) + fabsf(db);
                 if (SE) sev[u] = dr * dr + dg * dg + db * db + 2.f * (dr * er + dg * eg + db * eb);
                 imv[u] = w;
@@ -275,15 +280,13 @@ template <int TW, int TH>
 __device__ inline Smem carve(char* base, int B) {
     constexpr int NW = (TW * TH + 63) / 64;
     Smem s;
-    s.a = reinterpret_cast<float4*>(base);
-    s.b = s.a + B;
-    s.c = reinterpret_cast<float*>(s.b + B);
-    s.id = reinterpret_cast<uint32_t*>(s.c + B);
+    s.rec = reinterpret_cast<Rec*>(base);
+    s.id = reinterpret_cast<uint32_t*>(s.rec + B);
     s.rows = s.id + B;
     s.list = reinterpret_cast<uint16_t*>(s.rows + B);
     s.hits = s.list + NW * B;
-    s.part = reinterpret_cast<float*>(s.hits + NW * B);
-    s.misc = reinterpret_cast<int*>(s.part + 3 * NW * B);
+    s.misc = reinterpret_cast<int*>(s.hits + NW * B);
+    s.part = reinterpret_cast<float*>(s.misc + 4);
     return s;
 }
 
@@ -324,22 +327,25 @@ __global__ __launch_bounds__(TW * TH) void k_render_score_persistent(const ViewJ
 __global__ void k_zero_i64(int64_t* p) { *p = 0; }
 
 template <int TW, int TH>
-size_t smem_bytes(int B) {
+size_t smem_bytes(int B, int n_out) {
     constexpr int NW = (TW * TH + 63) / 64;
-    return (size_t)B * (16 + 16 + 4 + 4 + 4) + (size_t)NW * B * 4 + (size_t)3 * NW * B * 4 + 16;
+    return (size_t)B * (sizeof(Rec) + 4 + 4) + (size_t)NW * B * 4 + 16 + (size_t)n_out * NW * B * 4;
 }
 
 }  // namespace
 
-size_t fused_smem_bytes(const potr_config& cfg) {
-    if (cfg.tile_w == 8) return smem_bytes<8, 8>(cfg.lds_batch);
-    if (cfg.tile_w == 32) return smem_bytes<32, 8>(cfg.lds_batch);
-    return smem_bytes<16, 16>(cfg.lds_batch);
+size_t fused_smem_bytes(const potr_config& cfg, int n_out) {
+    if (cfg.tile_w == 8) return smem_bytes<8, 8>(cfg.lds_batch, n_out);
+    if (cfg.tile_w == 32) return smem_bytes<32, 8>(cfg.lds_batch, n_out);
+    return smem_bytes<16, 16>(cfg.lds_batch, n_out);
 }
 
 potr_status launch_render_score(const ViewJobs& jobs_dev, int32_t n_views, int32_t tiles_per_view,
                                 const potr_config& cfg, hipStream_t s) {
-    const size_t sm = fused_smem_bytes(cfg);
+    // the views of one call share their set of outputs
+    const ViewJob& j0 = jobs_dev.j[0];
+    const int n_out = (j0.scores ? 1 : 0) + (j0.importance ? 1 : 0) + (j0.scores_se ? 1 : 0);
+    const size_t sm = fused_smem_bytes(cfg, n_out);
     const dim3 grid(tiles_per_view, n_views);
     const bool se = jobs_dev.j[0].scores_se != nullptr;
     if (cfg.tile_w == 16 && cfg.tile_h == 16) {
@@ -361,7 +367,7 @@ int persistent_grid(const potr_config& cfg) {
     int dev = 0, cus = 256;
     if (hipGetDevice(&dev) == hipSuccess) hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     const int threads = cfg.tile_w * cfg.tile_h;
-    const size_t sm = fused_smem_bytes(cfg);
+    const size_t sm = fused_smem_bytes(cfg, 2);
     int by_waves = 32 / ((threads + 63) / 64);              // 32 waves per CU
     int by_lds = (int)((160 * 1024) / (sm + 256));
     int per_cu = by_waves < by_lds ? by_waves : by_lds;
@@ -375,7 +381,7 @@ potr_status launch_render_score_persistent(const ViewJob* jobs_dev, int32_t n_jo
     hipLaunchKernelGGL(k_zero_i64, dim3(1), dim3(1), 0, s, counter_dev);
     potr_status st = check_launch("k_zero_i64");
     if (st != POTR_OK) return st;
-    const size_t sm = fused_smem_bytes(cfg);
+    const size_t sm = fused_smem_bytes(cfg, 2);   // scores and importance
     const dim3 grid(grid_size);
     if (cfg.tile_w == 16 && cfg.tile_h == 16)
         hipLaunchKernelGGL((k_render_score_persistent<16, 16>), grid, dim3(256), sm, s, jobs_dev, n_jobs,

@@ -71,14 +71,17 @@ __device__ inline bool rows_overlap(uint32_t rr, int row_lo, int row_hi) {
     return r0 <= row_hi && r1 >= row_lo;
 }
 
-// alpha / (1 - alpha) with the hardware reciprocal (1 ulp), 1 - alpha >= 1 - alpha_max
-__device__ inline float odds(float al) { return al * __builtin_amdgcn_rcpf(1.f - al); }
+// 1 / (1 - alpha) with the hardware reciprocal (1 ulp), 1 - alpha >= 1 - alpha_max
+__device__ inline float inv_keep(float al) { return __builtin_amdgcn_rcpf(__fsub_rn(1.f, al)); }
 
-// Removal effect of one splat on one channel of one pixel:
-//   -w c + odds (Q - P),  Q = P_K + T_final bg,  P = partial colour through the splat.
-__device__ inline float removal_delta(float w, float c, float k, float Q, float P) {
-    return __fmaf_rn(-w, c, __fmul_rn(k, __fsub_rn(Q, P)));
-}
+// Colour still to come behind a splat: R = Q - P with Q = P_K + T_final bg and
+// P the partial colour through the splat; each blended splat takes w c off it.
+__device__ inline float sub_weighted(float R, float w, float c) { return __fmaf_rn(-w, c, R); }
+
+// Removal effect of one splat on one channel of one pixel, -w c + alpha/(1-alpha) R
+// with R = Q - P through the splat. Since R_prev = R + w c is the value before the
+// splat, it equals R / (1 - alpha) - R_prev: one FMA per channel.
+__device__ inline float removal_delta(float inv, float R, float R_prev) { return __fmaf_rn(inv, R, -R_prev); }
 
 // Per-wave list of the staged entries [0, cnt) whose reachable tile rows meet
 // the wave's rows [row_lo, row_hi], in increasing order; returns its length.
