@@ -46,9 +46,18 @@ __device__ inline void sh_basis_d3(double x, double y, double z, int degree, dou
 }
 
 constexpr int kProjThreads = 128;
+
+// Per-view tangent-plane clamps jclamp * (width / 2) / fx and jclamp * (height / 2) / fy,
+// each one FP64 product and one correctly rounded division, formed once per launch.
+struct Lims {
+    double x[kViewsPerLaunch], y[kViewsPerLaunch];
+};
 constexpr int kShStride = 13;   // float4 per splat in LDS (12 used)
 
-__global__ __launch_bounds__(kProjThreads) void k_project(int64_t N, int32_t v0, int32_t nv, CamBatch cams,
+// DEG: the SH degree in use (0..3), a template argument so that the colour sum
+// is fully unrolled with every coefficient and basis value in a register.
+template <int DEG>
+__global__ __launch_bounds__(kProjThreads) void k_project(int64_t N, int32_t v0, int32_t nv, CamBatch cams, Lims lims,
                                                  potr_config cfg, const float* __restrict__ means,
                                                  const float* __restrict__ scales, const float* __restrict__ quats,
                                                  const float* __restrict__ opac, const float* __restrict__ sh,
@@ -59,7 +68,7 @@ __global__ __launch_bounds__(kProjThreads) void k_project(int64_t N, int32_t v0,
     {
         // the float4s holding the 3 (degree + 1)^2 coefficients in use
         const int nb = (int)min((int64_t)kProjThreads, N - i0);
-        const int n4 = (3 * (cfg.sh_degree + 1) * (cfg.sh_degree + 1) + 3) / 4;
+        constexpr int n4 = (3 * (DEG + 1) * (DEG + 1) + 3) / 4;
         const float4* g4 = reinterpret_cast<const float4*>(sh + 48 * i0);
         for (int f = threadIdx.x; f < nb * n4; f += kProjThreads) {
             const int t = f / n4, m = f - t * n4;
@@ -93,7 +102,7 @@ __global__ __launch_bounds__(kProjThreads) void k_project(int64_t N, int32_t v0,
         S12 = M[3] * M[6] * s0 + M[4] * M[7] * s1 + M[5] * M[8] * s2;
         S22 = M[6] * M[6] * s0 + M[7] * M[7] * s1 + M[8] * M[8] * s2;
     }
-    const int nsh = (cfg.sh_degree + 1) * (cfg.sh_degree + 1);
+    constexpr int nsh = (DEG + 1) * (DEG + 1);
 
     for (int vv = 0; vv < nv; ++vv) {
         const potr_camera& c = cams.c[vv];
@@ -121,8 +130,7 @@ __global__ __launch_bounds__(kProjThreads) void k_project(int64_t N, int32_t v0,
             const double py = R3 * mx + R4 * my + R5 * mz + (double)c.t[1];
             const double pz = R6 * mx + R7 * my + R8 * mz + (double)c.t[2];
             const double fx = c.fx, fy = c.fy;
-            const double limx = (double)cfg.jclamp * 0.5 * c.width / fx;
-            const double limy = (double)cfg.jclamp * 0.5 * c.height / fy;
+            const double limx = lims.x[vv], limy = lims.y[vv];
             const double iz = 1.0 / pz;   // one FP64 division; the quotients below are products
             const double tx = fmin(limx, fmax(-limx, px * iz));
             const double ty = fmin(limy, fmax(-limy, py * iz));
@@ -164,24 +172,25 @@ __global__ __launch_bounds__(kProjThreads) void k_project(int64_t N, int32_t v0,
                 const double dn = 1.0 / sqrt(dx * dx + dy * dy + dz * dz);
                 dx *= dn; dy *= dn; dz *= dn;
                 double Y[16];
-                sh_basis_d3(dx, dy, dz, cfg.sh_degree, Y);
+                sh_basis_d3(dx, dy, dz, DEG, Y);
                 double cr = 0.5, cg = 0.5, cb = 0.5;
                 // 16-byte loads: four coefficients (r,g,b of k and r of k+1, ...) at a time
+                constexpr int n4 = (3 * nsh + 3) / 4;
                 const float4* sh4 = s_sh + threadIdx.x * kShStride;
-                const int n4 = (3 * nsh + 3) / 4;
+                float f[4 * n4];
+#pragma unroll
                 for (int m = 0; m < n4; ++m) {
                     const float4 q = sh4[m];
-                    const float f[4] = {q.x, q.y, q.z, q.w};
+                    f[4 * m] = q.x;
+                    f[4 * m + 1] = q.y;
+                    f[4 * m + 2] = q.z;
+                    f[4 * m + 3] = q.w;
+                }
 #pragma unroll
-                    for (int t = 0; t < 4; ++t) {
-                        const int e = 4 * m + t;          // flat index k*3 + channel
-                        if (e >= 3 * nsh) break;
-                        const double y = Y[e / 3];
-                        const int ch = e - 3 * (e / 3);
-                        if (ch == 0) cr += (double)f[t] * y;
-                        else if (ch == 1) cg += (double)f[t] * y;
-                        else cb += (double)f[t] * y;
-                    }
+                for (int k = 0; k < nsh; ++k) {
+                    cr += (double)f[3 * k] * Y[k];
+                    cg += (double)f[3 * k + 1] * Y[k];
+                    cb += (double)f[3 * k + 2] * Y[k];
                 }
                 rec.rgb[0] = (float)fmax(0.0, cr);
                 rec.rgb[1] = (float)fmax(0.0, cg);
@@ -215,8 +224,29 @@ potr_status launch_project(int64_t N, int32_t V, const potr_camera* cams, const 
         CamBatch cb;
         for (int k = 0; k < nv; ++k) cb.c[k] = cams[v0 + k];
         for (int k = nv; k < kViewsPerLaunch; ++k) cb.c[k] = cams[v0];
-        hipLaunchKernelGGL(k_project, grid, dim3(kProjThreads), 0, s, N, v0, nv, cb, cfg, means, scales, quats, opac,
-                           sh, proj, tiles_touched);
+        Lims lm;
+        for (int k = 0; k < kViewsPerLaunch; ++k) {
+            lm.x[k] = (double)cfg.jclamp * 0.5 * cb.c[k].width / (double)cb.c[k].fx;
+            lm.y[k] = (double)cfg.jclamp * 0.5 * cb.c[k].height / (double)cb.c[k].fy;
+        }
+        switch (cfg.sh_degree) {
+            case 0:
+                hipLaunchKernelGGL(k_project<0>, grid, dim3(kProjThreads), 0, s, N, v0, nv, cb, lm, cfg, means, scales,
+                                   quats, opac, sh, proj, tiles_touched);
+                break;
+            case 1:
+                hipLaunchKernelGGL(k_project<1>, grid, dim3(kProjThreads), 0, s, N, v0, nv, cb, lm, cfg, means, scales,
+                                   quats, opac, sh, proj, tiles_touched);
+                break;
+            case 2:
+                hipLaunchKernelGGL(k_project<2>, grid, dim3(kProjThreads), 0, s, N, v0, nv, cb, lm, cfg, means, scales,
+                                   quats, opac, sh, proj, tiles_touched);
+                break;
+            default:
+                hipLaunchKernelGGL(k_project<3>, grid, dim3(kProjThreads), 0, s, N, v0, nv, cb, lm, cfg, means, scales,
+                                   quats, opac, sh, proj, tiles_touched);
+                break;
+        }
         potr_status st = check_launch("k_project");
         if (st != POTR_OK) return st;
     }

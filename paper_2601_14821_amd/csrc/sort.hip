@@ -438,20 +438,21 @@ __global__ __launch_bounds__(1024) void k_row_bases(uint32_t* __restrict__ segr,
     if (threadIdx.x == 0) *n_pairs = *fault ? (int64_t)-1 : carry;
 }
 
-// A wave per (view, row): per tile, the segment sums become exclusive prefixes
+// A block per (view, row): per tile, the segment sums become exclusive prefixes
 // in place and give the tile's total; tile bases = the row's base + exclusive
 // scan of its tile totals; tile ranges ([0, 0) when empty; all empty when the
 // pairs exceed the capacity).
-__global__ __launch_bounds__(64) void k_tile_bases(uint32_t* __restrict__ segt, const int64_t* __restrict__ rbase,
-                                                   Bins B, const int64_t* __restrict__ n_pairs, int64_t capacity,
-                                                   int64_t* __restrict__ tbase, int32_t* __restrict__ ranges) {
-    const int y = blockIdx.x, v = blockIdx.y, lane = threadIdx.x;
+__global__ __launch_bounds__(256) void k_tile_bases(uint32_t* __restrict__ segt, const int64_t* __restrict__ rbase,
+                                                    Bins B, const int64_t* __restrict__ n_pairs, int64_t capacity,
+                                                    int64_t* __restrict__ tbase, int32_t* __restrict__ ranges) {
+    __shared__ int64_t wsum[4];
+    const int y = blockIdx.x, v = blockIdx.y, lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int64_t n = *n_pairs;
     const bool ok = n >= 0 && n <= capacity;
     int64_t run = rbase[(int64_t)v * B.tiles_y + y];
     const int64_t t0 = (int64_t)v * B.T + (int64_t)y * B.tiles_x;
-    for (int x0 = 0; x0 < B.tiles_x; x0 += 64) {
-        const int x = x0 + lane;
+    for (int x0 = 0; x0 < B.tiles_x; x0 += 256) {
+        const int x = x0 + threadIdx.x;
         int64_t c = 0;
         if (x < B.tiles_x) c = seg_prefix(segt + (int64_t)v * B.nseg_g * B.T + (int64_t)y * B.tiles_x + x, B.T, B.nseg_g);
         int64_t inc = c;
@@ -460,14 +461,23 @@ __global__ __launch_bounds__(64) void k_tile_bases(uint32_t* __restrict__ segt, 
             const int64_t u = __shfl_up(inc, d, 64);
             if (lane >= d) inc += u;
         }
-        const int64_t b = run + inc - c;
+        if (lane == 63) wsum[w] = inc;
+        __syncthreads();
+        int64_t pre = run, all = 0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            if (k < w) pre += wsum[k];
+            all += wsum[k];
+        }
+        const int64_t b = pre + inc - c;
         if (x < B.tiles_x) {
             tbase[t0 + x] = b;
             const bool any = ok && c > 0;
             ranges[2 * (t0 + x)] = any ? (int32_t)b : 0;
             ranges[2 * (t0 + x) + 1] = any ? (int32_t)(b + c) : 0;
         }
-        run += __shfl(inc, 63, 64);
+        run += all;
+        __syncthreads();
     }
 }
 
@@ -842,7 +852,7 @@ potr_status launch_sort(int64_t N, int32_t V, const potr_camera& cam0, const pot
     }
     if (st != POTR_OK) return st;
     // tiles: bases (within their row), ranges, each group's first position per tile
-    hipLaunchKernelGGL(k_tile_bases, dim3(tys, V), dim3(64), 0, s, w.segt, (const int64_t*)w.rbase, B, n_pairs,
+    hipLaunchKernelGGL(k_tile_bases, dim3(tys, V), dim3(256), 0, s, w.segt, (const int64_t*)w.rbase, B, n_pairs,
                        capacity, w.tbase, tile_ranges);
     st = check_launch("k_tile_bases");
     if (st != POTR_OK || N == 0) return st;
