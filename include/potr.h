@@ -120,18 +120,21 @@ POTR_API potr_status potr_project(int64_t N, int32_t V, const potr_camera* cams,
 /* ---------------------------------------------------------------------------
  * potr_bin -- Sec. 3 ("layers ordered by approximate depth"): order each view's
  * splats by depth key (ties by splat id) and count the (tile, splat) pairs:
- * every tile of a splat's rect holds the splat. The counts are kept per group
- * of 4096 consecutive depth ranks and per tile, and per chunk of 64 ranks and
- * per row of tiles, in the workspace, for potr_sort.
- *   proj   [V*N] from potr_project (its depth keys and rects are read)
+ * every tile of a splat's rect holds the splat. The counts per group of 4096
+ * consecutive depth ranks and tile, and per chunk of 64 ranks and row of tiles,
+ * their offsets, and the rects in depth order are kept in the workspace for
+ * potr_sort, which only reads it (so potr_sort may be called again, e.g. with
+ * a larger capacity, without binning again).
+ *   proj   [V*N] from potr_project, 16-byte aligned (its depth keys and rects are read)
  *   ws     workspace of potr_bin_workspace_size bytes; potr_sort reads it, so
  *          it must stay untouched between the two calls
  *   order  [V*N] uint32 out: order[v*N + r] = id of the splat with depth rank r in view v
  *   n_pairs (device) int64 out: total number of pairs over all views; -1 if a
  *          device-side wait of the ordering gave up (an internal error, which
  *          later stages treat as "no pairs").
- * Cost: the workspace holds the depth sort's keys and 8 bytes per (view, group
- * of 4096 ranks, tile).
+ * Cost: the workspace holds 28 bytes per (view, splat) (depth sort keys and
+ * values, rects by id and in depth order), 8 bytes per (view, group of 4096
+ * ranks, tile) and 8 bytes per (view, chunk of 64 ranks, tile row).
  * ------------------------------------------------------------------------- */
 POTR_API potr_status potr_bin_workspace_size(int64_t N, int32_t V, const potr_camera* cams, const potr_config* cfg,
                                     size_t* bytes);
@@ -145,11 +148,12 @@ POTR_API potr_status potr_bin(int64_t N, int32_t V, const potr_camera* cams, con
  * of (view, tile, depth, id) keys gives, obtained by placing every pair
  * directly from the counts potr_bin left in its workspace (no per-pair sort):
  * first into its tile row, then, within each row, at its tile.
- * N, V, cams, cfg, proj, order and ws are those of the potr_bin call before.
+ * N, V, cams, cfg, proj, order and ws are those of the potr_bin call before
+ * (ws is read, not changed).
  *   n_pairs  (device) from potr_bin
  *   capacity (host) number of slots in sorted_ids; with more pairs than that
  *            nothing is placed and every range is empty (grow and call again)
- *   sort_ws  staging of potr_sort_workspace_size(capacity) bytes (6 per slot)
+ *   sort_ws  staging of potr_sort_workspace_size(capacity) bytes (4 per slot)
  *   sorted_ids [capacity] uint32 out: splat id (0..N-1) of every pair
  *   tile_ranges [V*tiles*2] int32 out: half-open [start, end) into sorted_ids;
  *            [0, 0) for a tile without pairs

@@ -107,6 +107,7 @@ potr_status potr_bin(int64_t N, int32_t V, const potr_camera* cams, const potr_c
     if (st != POTR_OK) return st;
     if (N < 0 || N * (int64_t)V >= (int64_t(1) << 31)) return fail(POTR_EINVAL, "N x V out of range");
     if (!n_pairs || !ws || (N > 0 && (!proj || !order))) return fail(POTR_EINVAL, "NULL buffer");
+    if (N > 0 && !aligned16(proj)) return fail(POTR_EINVAL, "proj must be 16-byte aligned");
     const size_t need = bin_workspace_bytes(N, V, tiles_x(cams[0], *cfg), tiles_y(cams[0], *cfg));
     if (ws_bytes < need) return fail(POTR_ECAPACITY, "bin workspace %zu < %zu bytes", ws_bytes, need);
     return launch_bin(N, V, cams[0], *cfg, proj, ws, order, n_pairs, (hipStream_t)stream);

@@ -2,19 +2,15 @@
 // ordered by approximate depth).
 //
 // potr_bin orders each view's splats by depth key (a stable LSD radix sort of
-// the N 32-bit keys, so ties keep splat id order), then counts, for every chunk
-// of S consecutive depth ranks and every tile, how many of the chunk's splats
-// cover the tile (table [view][chunk][tile]), and from those counts the number
-// of pairs per tile and in total.
-// potr_sort turns the table into offsets -- the position of chunk c's first
-// pair in tile t is the number of pairs of all earlier (view, tile)s plus those
-// of chunks before c in the same tile -- and places every splat id: one wave
-// per chunk walks its splats in rank order and appends each to the tiles of its
-// rect through cursors in LDS. The result is each tile's list in (depth key,
+// the N 32-bit keys, so ties keep splat id order) and counts, for every chunk
+// of 64 consecutive depth ranks and every tile row, the pairs the chunk's
+// splats make there; from those counts come the number of pairs per row and in
+// total. potr_sort places every (tile, splat) pair in two levels (see the
+// pair placement section below) so that each tile's list is in (depth key,
 // splat id) order, the order a sort of (tile, depth, id) keys would give,
 // without sorting per pair.
 //
-// Depth radix passes are one kernel each: a block of 256 threads x 16 items
+// Depth radix passes are one kernel each: a block of 1024 threads x 4 items
 // ranks its keys per digit with 64-lane ballots (stable order: wave, item,
 // lane), publishes its digit counts, and finds the counts of all blocks before
 // it by decoupled look-back over their published words. The digit totals of
@@ -157,11 +153,14 @@ struct Pass {
 
 // Digit totals of every pass for each segment, in one read of the keys. With
 // proj != nullptr the keys are the depth bits of the records and are written
-// to keys_out on the way.
+// to keys_out on the way, with the rects to rect_out: the two sit in the same
+// 16 bytes of a record. A rect of tiles [x0, x1) x [y0, y1) is packed as the
+// two words (x0 | x1 << 16, y0 | y1 << 16).
 template <typename K>
 __global__ __launch_bounds__(kThreads) void k_hist(const K* __restrict__ keys, const potr_proj* __restrict__ proj,
-                                                   uint32_t* __restrict__ keys_out, Seg g, int n_passes,
-                                                   int shift0, int per, int bits_total, uint32_t* __restrict__ ghist) {
+                                                   uint32_t* __restrict__ keys_out, uint2* __restrict__ rect_out,
+                                                   Seg g, int n_passes, int shift0, int per, int bits_total,
+                                                   uint32_t* __restrict__ ghist) {
     __shared__ uint32_t h[kMaxPasses][256];
     for (int t = threadIdx.x; t < kMaxPasses * 256; t += kThreads) (&h[0][0])[t] = 0;
     __syncthreads();
@@ -171,8 +170,11 @@ __global__ __launch_bounds__(kThreads) void k_hist(const K* __restrict__ keys, c
     for (int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x; e < n; e += (int64_t)gridDim.x * kThreads) {
         K k;
         if (proj) {
-            k = (K)__float_as_uint(proj[seg0 + e].depth);
-            keys_out[seg0 + e] = (uint32_t)k;
+            // bytes 32..47 of the record: rgb[2], depth, rect
+            const uint4 q = reinterpret_cast<const uint4*>(proj + seg0 + e)[2];
+            k = (K)q.y;
+            keys_out[seg0 + e] = q.y;
+            rect_out[seg0 + e] = make_uint2((q.z & 0xffffu) | (q.w << 16), (q.z >> 16) | (q.w & 0xffff0000u));
         } else {
             k = keys[seg0 + e];
         }
@@ -307,11 +309,12 @@ __global__ void k_clear(uint64_t* __restrict__ p, int64_t n) {
 //   tiles table tc[v][g][t]  pairs of group g in tile t, scanned over the
 //               groups: every group's first position in tile t.
 // Level 1 (a wave per chunk, its splats in rank order, lanes on the tiles of
-// one splat) appends (x, id) for every tile of the rect to its row's region
-// through per-row cursors, so the chunk's run in a row is contiguous. Level 2 (a
-// block per (group, row)) reads the group's segment of the row and places
-// each id at its tile's cursor, ranking equal tiles with ballots so that each
-// tile's run leaves as contiguous stores. The layout of the rows' regions is
+// one splat) appends one word (tile x, rank within the group) for every tile of
+// the rect to its row's region through per-row cursors, so the chunk's run in a
+// row is contiguous. Level 2 (a block per (group, row)) reads the group's
+// segment of the row, maps each rank to its splat id and places the id at its
+// tile's cursor, ranking equal tiles with ballots so that each tile's run
+// leaves as contiguous stores. The layout of the rows' regions is
 // that of the final output, so a row's region holds exactly its tiles' pairs.
 struct Bins {
     int64_t N;
@@ -322,28 +325,27 @@ constexpr int kGroup = 64;                    // chunks per group
 constexpr int kGroupRanks = kChunk * kGroup;  // 4096
 constexpr int kMaxSegs = 32;                  // at most this many segments per column scan
 constexpr int kColItems = 8;                  // level 2: items per thread (2048 per block pass)
-
-// Rect of one (view, rank): tiles [x0, x1) x [y0, y1), packed as two words.
-__device__ inline void load_rect(const potr_proj* __restrict__ pv, uint32_t id, uint32_t& xw, uint32_t& yw) {
-    const uint2 r = *reinterpret_cast<const uint2*>(&pv[id].rect[0]);   // (x0 | y0 << 16, x1 | y1 << 16)
-    xw = (r.x & 0xffffu) | (r.y << 16);                                  // x0 | x1 << 16
-    yw = (r.x >> 16) | (r.y & 0xffff0000u);                              // y0 | y1 << 16
-}
+// A staged pair is one word: tile x << kRankBits | rank of the splat within its group.
+constexpr int kRankBits = 12;
+static_assert(kGroupRanks == 1 << kRankBits, "a group's ranks fill the rank field");
 
 // rc[v][c][y]: pairs of chunk c in row y (one splat per thread), also added
 // into the row's sum over the chunk's segment of the column scan (segr,
-// cleared beforehand).
+// cleared beforehand). The packed rects are also written out in depth order
+// (srect[v][rank]) for level 1.
 __global__ __launch_bounds__(kChunk) void k_row_count(const uint32_t* __restrict__ order,
-                                                      const potr_proj* __restrict__ proj, Bins B,
-                                                      uint32_t* __restrict__ rc, uint32_t* __restrict__ segr) {
+                                                      const uint2* __restrict__ crect, Bins B,
+                                                      uint32_t* __restrict__ rc, uint32_t* __restrict__ segr,
+                                                      uint2* __restrict__ srect) {
     extern __shared__ uint32_t rows[];
     const int c = blockIdx.x, v = blockIdx.y;
     for (int y = threadIdx.x; y < B.tiles_y; y += kChunk) rows[y] = 0;
     __syncthreads();
     const int64_t r = (int64_t)c * kChunk + threadIdx.x;
     if (r < B.N) {
-        uint32_t xw, yw;
-        load_rect(proj + (int64_t)v * B.N, order[(int64_t)v * B.N + r], xw, yw);
+        const uint2 rr = crect[(int64_t)v * B.N + order[(int64_t)v * B.N + r]];
+        const uint32_t xw = rr.x, yw = rr.y;
+        srect[(int64_t)v * B.N + r] = rr;
         const int w = (int)(xw >> 16) - (int)(xw & 0xffffu);
         if (w > 0)
             for (int y = (int)(yw & 0xffffu); y < (int)(yw >> 16); ++y) atomicAdd(&rows[y], (uint32_t)w);
@@ -440,15 +442,11 @@ __global__ __launch_bounds__(1024) void k_row_bases(uint32_t* __restrict__ segr,
 
 // A block per (view, row): per tile, the segment sums become exclusive prefixes
 // in place and give the tile's total; tile bases = the row's base + exclusive
-// scan of its tile totals; tile ranges ([0, 0) when empty; all empty when the
-// pairs exceed the capacity).
+// scan of its tile totals (so over all (view, tile) they are one exclusive scan).
 __global__ __launch_bounds__(256) void k_tile_bases(uint32_t* __restrict__ segt, const int64_t* __restrict__ rbase,
-                                                    Bins B, const int64_t* __restrict__ n_pairs, int64_t capacity,
-                                                    int64_t* __restrict__ tbase, int32_t* __restrict__ ranges) {
+                                                    Bins B, int64_t* __restrict__ tbase) {
     __shared__ int64_t wsum[4];
     const int y = blockIdx.x, v = blockIdx.y, lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int64_t n = *n_pairs;
-    const bool ok = n >= 0 && n <= capacity;
     int64_t run = rbase[(int64_t)v * B.tiles_y + y];
     const int64_t t0 = (int64_t)v * B.T + (int64_t)y * B.tiles_x;
     for (int x0 = 0; x0 < B.tiles_x; x0 += 256) {
@@ -469,52 +467,56 @@ __global__ __launch_bounds__(256) void k_tile_bases(uint32_t* __restrict__ segt,
             if (k < w) pre += wsum[k];
             all += wsum[k];
         }
-        const int64_t b = pre + inc - c;
-        if (x < B.tiles_x) {
-            tbase[t0 + x] = b;
-            const bool any = ok && c > 0;
-            ranges[2 * (t0 + x)] = any ? (int32_t)b : 0;
-            ranges[2 * (t0 + x) + 1] = any ? (int32_t)(b + c) : 0;
-        }
+        if (x < B.tiles_x) tbase[t0 + x] = pre + inc - c;
         run += all;
         __syncthreads();
     }
 }
 
 // Level 1: a wave per (view, chunk). The wave walks the chunk's splats in rank
-// order, lanes on consecutive tiles of one splat's rect, and appends (x, id)
-// to each tile's row through per-row cursors in LDS that start at the chunk's
-// first position in the row.
-__global__ __launch_bounds__(64) void k_place_rows(const uint32_t* __restrict__ order,
-                                                   const potr_proj* __restrict__ proj,
-                                                   const uint32_t* __restrict__ roff, Bins B,
+// order (rects read in depth order), lanes on consecutive tiles of one splat's
+// rect, and appends (x, rank within the group) to each tile's row through
+// per-row cursors in LDS that start at the chunk's first position in the row.
+__global__ __launch_bounds__(64) void k_place_rows(const uint2* __restrict__ srect,
+                                                   const uint32_t* __restrict__ roff,
+                                                   const int64_t* __restrict__ tbase, Bins B,
                                                    const int64_t* __restrict__ n_pairs, int64_t capacity,
-                                                   uint16_t* __restrict__ stage_x, uint32_t* __restrict__ stage_id,
-                                                   uint32_t* __restrict__ segt, int64_t segt_n) {
+                                                   uint32_t* __restrict__ stage, int32_t* __restrict__ ranges) {
     extern __shared__ uint32_t cur[];   // [tiles_y]
-    // clear the tile segment sums the column counts add into (next kernel)
-    for (int64_t i = ((int64_t)blockIdx.y * gridDim.x + blockIdx.x) * 64 + threadIdx.x; i < segt_n;
-         i += (int64_t)gridDim.x * gridDim.y * 64)
-        segt[i] = 0;
     const int64_t n = *n_pairs;
-    if (n < 0 || n > capacity) return;
+    const bool fits = n >= 0 && n <= capacity;
+    {
+        // tile ranges: the tile bases are one exclusive scan over (view, tile),
+        // so a tile ends where the next one starts; [0, 0) when empty, and all
+        // empty when the pairs exceed the capacity
+        const int64_t nt = (int64_t)B.V * B.T;
+        for (int64_t i = ((int64_t)blockIdx.y * gridDim.x + blockIdx.x) * 64 + threadIdx.x; i < nt;
+             i += (int64_t)gridDim.x * gridDim.y * 64) {
+            const int64_t b = tbase[i], e = i + 1 < nt ? tbase[i + 1] : n;
+            const bool any = fits && e > b;
+            ranges[2 * i] = any ? (int32_t)b : 0;
+            ranges[2 * i + 1] = any ? (int32_t)e : 0;
+        }
+    }
+    if (!fits) return;
     const int c = blockIdx.x, v = blockIdx.y, lane = threadIdx.x;
     const uint32_t* orow = roff + ((int64_t)v * (B.C + 1) + c) * B.tiles_y;
     for (int y = lane; y < B.tiles_y; y += 64) cur[y] = orow[y];
     __builtin_amdgcn_wave_barrier();
-    const potr_proj* pv = proj + (int64_t)v * B.N;
     const int64_t r0 = (int64_t)c * kChunk;
     const int ns = (int)min((int64_t)kChunk, B.N - r0);
+    // rank within the group of the chunk's first splat
+    const uint32_t rg0 = (uint32_t)(c % kGroup) * kChunk;
     constexpr int kPer = kChunk / 64;
-    uint32_t sid[kPer], sxw[kPer], syw[kPer];
+    uint32_t sxw[kPer], syw[kPer];
 #pragma unroll
     for (int k = 0; k < kPer; ++k) {
-        sid[k] = 0;
         sxw[k] = syw[k] = 0;
         const int sidx = k * 64 + lane;
         if (sidx < ns) {
-            sid[k] = order[(int64_t)v * B.N + r0 + sidx];
-            load_rect(pv, sid[k], sxw[k], syw[k]);
+            const uint2 rr = srect[(int64_t)v * B.N + r0 + sidx];
+            sxw[k] = rr.x;
+            syw[k] = rr.y;
         }
     }
 #pragma unroll
@@ -528,7 +530,7 @@ __global__ __launch_bounds__(64) void k_place_rows(const uint32_t* __restrict__ 
             const int wdt = x1 - x0;
             if (wdt <= 0 || y1 <= y0) continue;
             const int cnt = wdt * (y1 - y0);
-            const uint32_t id = (uint32_t)__builtin_amdgcn_readlane((int32_t)sid[k], sj);
+            const uint32_t rk = rg0 + (uint32_t)(k * 64 + sj);
             const float rw = __builtin_amdgcn_rcpf((float)wdt);
             for (int q = lane; q < cnt; q += 64) {
                 // tile q of the rect, row-major: q = ty * wdt + tx (the float
@@ -543,36 +545,91 @@ __global__ __launch_bounds__(64) void k_place_rows(const uint32_t* __restrict__ 
                     tx -= wdt;
                 }
                 const uint32_t p = cur[y0 + ty] + (uint32_t)tx;
-                stage_x[p] = (uint16_t)(x0 + tx);
-                stage_id[p] = id;
+                stage[p] = ((uint32_t)(x0 + tx) << kRankBits) | rk;
             }
             for (int yy = y0 + lane; yy < y1; yy += 64) cur[yy] += (uint32_t)wdt;
         }
     }
 }
 
-// tc[v][g][t]: pairs of group g in tile t, counted over the group's segment of
-// each row (a block per (view, group, row)).
-__global__ __launch_bounds__(256) void k_col_count(const uint32_t* __restrict__ roff, Bins B,
-                                                   const int64_t* __restrict__ n_pairs, int64_t capacity,
-                                                   const uint16_t* __restrict__ stage_x, uint32_t* __restrict__ tc,
-                                                   uint32_t* __restrict__ segt) {
-    extern __shared__ uint32_t cnt[];   // [tiles_x]
-    const int64_t n = *n_pairs;
-    if (n < 0 || n > capacity) return;
-    const int g = blockIdx.x, y = blockIdx.y, v = blockIdx.z;
-    for (int x = threadIdx.x; x < B.tiles_x; x += 256) cnt[x] = 0;
-    __syncthreads();
-    const int c0 = g * kGroup, c1 = min(B.C, c0 + kGroup);
-    const uint32_t s0 = roff[((int64_t)v * (B.C + 1) + c0) * B.tiles_y + y];
-    const uint32_t s1 = roff[((int64_t)v * (B.C + 1) + c1) * B.tiles_y + y];
-    for (uint32_t i = s0 + threadIdx.x; i < s1; i += 256) atomicAdd(&cnt[stage_x[i]], 1u);
-    __syncthreads();
-    uint32_t* out = tc + ((int64_t)v * B.G + g) * B.T + (int64_t)y * B.tiles_x;
-    uint32_t* sg = segt + ((int64_t)v * B.nseg_g + g / B.seg_g) * B.T + (int64_t)y * B.tiles_x;
-    for (int x = threadIdx.x; x < B.tiles_x; x += 256) {
-        out[x] = cnt[x];
-        if (cnt[x]) atomicAdd(sg + x, cnt[x]);
+// tc[v][g][t]: pairs of group g in tile t (a block per (group, view)), from a
+// 2D difference array in LDS: every splat of the group adds +1 / -1 at the four
+// corners of its rect, and prefix sums down the columns, then along the rows,
+// give every tile's count. Images taller than the band go in bands of rows.
+// Each count is also added into its tile's sum over the group's segment of
+// the column scan (segt, cleared beforehand).
+constexpr int kGcThreads = 1024;
+constexpr int kGcItems = kGroupRanks / kGcThreads;
+constexpr int kGcBand = 64;                       // rows per band at most (one lane each)
+constexpr size_t kGcLds = 48 * 1024;              // LDS budget of the difference array
+
+__global__ __launch_bounds__(kGcThreads) void k_group_count(const uint2* __restrict__ srect, Bins B, int band,
+                                                           uint32_t* __restrict__ tc, uint32_t* __restrict__ segt) {
+    extern __shared__ uint32_t d[];   // [band + 1][tiles_x + 1]
+    const int g = blockIdx.x, v = blockIdx.y;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    constexpr int NW = kGcThreads / 64;
+    const int TX = B.tiles_x, W1 = TX + 1;
+    const int64_t r0 = (int64_t)g * kGroupRanks;
+    const int ns = (int)min((int64_t)kGroupRanks, B.N - r0);
+    uint2 rr[kGcItems];
+#pragma unroll
+    for (int k = 0; k < kGcItems; ++k) {
+        const int idx = k * kGcThreads + (int)threadIdx.x;
+        rr[k] = idx < ns ? srect[(int64_t)v * B.N + r0 + idx] : make_uint2(0u, 0u);
+    }
+    uint32_t* out = tc + ((int64_t)v * B.G + g) * B.T;
+    uint32_t* sg = segt + ((int64_t)v * B.nseg_g + g / B.seg_g) * B.T;
+    for (int yb0 = 0; yb0 < B.tiles_y; yb0 += band) {
+        const int yb1 = min(B.tiles_y, yb0 + band), H = yb1 - yb0;
+        for (int i = threadIdx.x; i < (H + 1) * W1; i += kGcThreads) d[i] = 0u;
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < kGcItems; ++k) {
+            const int x0 = (int)(rr[k].x & 0xffffu), x1 = (int)(rr[k].x >> 16);
+            const int y0 = max((int)(rr[k].y & 0xffffu), yb0) - yb0, y1 = min((int)(rr[k].y >> 16), yb1) - yb0;
+            if (x0 < x1 && y0 < y1) {
+                atomicAdd(&d[y0 * W1 + x0], 1u);
+                atomicSub(&d[y0 * W1 + x1], 1u);
+                atomicSub(&d[y1 * W1 + x0], 1u);
+                atomicAdd(&d[y1 * W1 + x1], 1u);
+            }
+        }
+        __syncthreads();
+        // down the columns: a wave per column, one lane per row (H <= 64)
+        for (int x = w; x < TX; x += NW) {
+            const uint32_t val = lane < H ? d[lane * W1 + x] : 0u;
+            uint32_t inc = val;
+#pragma unroll
+            for (int o = 1; o < 64; o <<= 1) {
+                const uint32_t u = __shfl_up(inc, o, 64);
+                if (lane >= o) inc += u;
+            }
+            if (lane < H) d[lane * W1 + x] = inc;
+        }
+        __syncthreads();
+        // along the rows: a wave per row, lanes over 64 columns at a time
+        for (int y = w; y < H; y += NW) {
+            uint32_t carry = 0;
+            for (int xc = 0; xc < TX; xc += 64) {
+                const int x = xc + lane;
+                const uint32_t val = x < TX ? d[y * W1 + x] : 0u;
+                uint32_t inc = val;
+#pragma unroll
+                for (int o = 1; o < 64; o <<= 1) {
+                    const uint32_t u = __shfl_up(inc, o, 64);
+                    if (lane >= o) inc += u;
+                }
+                const uint32_t c = carry + inc;
+                if (x < TX) {
+                    const int64_t t = (int64_t)(yb0 + y) * TX + x;
+                    out[t] = c;
+                    if (c) atomicAdd(sg + t, c);
+                }
+                carry += __shfl(inc, 63, 64);
+            }
+        }
+        __syncthreads();
     }
 }
 
@@ -583,8 +640,8 @@ __global__ __launch_bounds__(256) void k_col_count(const uint32_t* __restrict__ 
 template <int XBITS>
 __global__ __launch_bounds__(256) void k_place_cols(const uint32_t* __restrict__ roff, const uint32_t* __restrict__ off,
                                                     Bins B, const int64_t* __restrict__ n_pairs, int64_t capacity,
-                                                    const uint16_t* __restrict__ stage_x,
-                                                    const uint32_t* __restrict__ stage_id,
+                                                    const uint32_t* __restrict__ stage,
+                                                    const uint32_t* __restrict__ order,
                                                     uint32_t* __restrict__ ids) {
     extern __shared__ uint32_t lds[];
     const int TX = B.tiles_x;
@@ -602,6 +659,7 @@ __global__ __launch_bounds__(256) void k_place_cols(const uint32_t* __restrict__
     const uint32_t seg0 = roff[((int64_t)v * (B.C + 1) + c0) * B.tiles_y + y];
     const uint32_t len = roff[((int64_t)v * (B.C + 1) + c1) * B.tiles_y + y] - seg0;
     const uint32_t* orow = off + ((int64_t)v * B.G + g) * B.T + (int64_t)y * TX;
+    const uint32_t* gorder = order + (int64_t)v * B.N + (int64_t)g * kGroupRanks;
     for (int x = threadIdx.x; x < TX; x += kThreads) cur[x] = orow[x];
     const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     const int per = (TX + kThreads - 1) / kThreads;   // counters per thread in the block scan
@@ -610,13 +668,25 @@ __global__ __launch_bounds__(256) void k_place_cols(const uint32_t* __restrict__
         __syncthreads();
         const uint32_t cntb = min(len - b0, (uint32_t)(kThreads * kColItems));
         uint32_t key[kColItems], val[kColItems], rnk[kColItems];
+        // all staged words first, then all id gathers, without branches, so that
+        // the loads stay in flight together (slots past the pass's end load its
+        // last word and are not used)
+#pragma unroll
+        for (int k = 0; k < kColItems; ++k) {
+            const uint32_t e = (uint32_t)(w * 64 * kColItems + k * 64 + lane);
+            key[k] = stage[seg0 + b0 + min(e, cntb - 1)];
+        }
+#pragma unroll
+        for (int k = 0; k < kColItems; ++k) {
+            val[k] = gorder[key[k] & (kGroupRanks - 1)];   // the splat id
+            key[k] >>= kRankBits;
+        }
 #pragma unroll
         for (int k = 0; k < kColItems; ++k) {
             const uint32_t e = (uint32_t)(w * 64 * kColItems + k * 64 + lane);
             const bool ok = e < cntb;
-            key[k] = ok ? stage_x[seg0 + b0 + e] : 0u;
-            val[k] = ok ? stage_id[seg0 + b0 + e] : 0u;
-            const uint32_t d = key[k];
+            const uint32_t d = ok ? key[k] : 0u;
+            key[k] = d;
             uint64_t m = __ballot(ok);
 #pragma unroll
             for (int bit = 0; bit < XBITS; ++bit) {
@@ -711,10 +781,10 @@ Bins bins_of(int64_t N, int32_t V, int32_t tiles_x, int32_t tiles_y) {
 struct BinWs {
     Ctl ctl;
     uint32_t *ka, *kb, *va;
+    uint2 *crect, *srect;   // rects by splat id, and in depth order
     uint32_t *rc, *roff, *segr;
     int64_t* rbase;
     uint32_t *tc, *toff, *segt;
-    int64_t segt_n;
     int64_t* tbase;
     size_t bytes;
 };
@@ -731,18 +801,20 @@ BinWs bin_layout(int64_t N, int32_t V, int32_t tiles_x, int32_t tiles_y, char* b
     w.ctl.ghist = (uint32_t*)take(4 * (size_t)V * kMaxPasses * 256);
     w.ctl.status = (uint64_t*)take(8 * (size_t)V * bps * 256);
     const size_t ty = (size_t)tiles_y, T = (size_t)B.T;
-    w.segr = (uint32_t*)take(4 * (size_t)V * B.nseg_c * ty);   // cleared with the control words
+    // cleared with the control words: the segment sums the count kernels add into
+    w.segr = (uint32_t*)take(4 * (size_t)V * B.nseg_c * ty);
+    w.segt = (uint32_t*)take(4 * (size_t)V * B.nseg_g * T);
     w.ctl.clear_words = (int64_t)(o / 8);
     w.ka = (uint32_t*)take(4 * VN);
     w.kb = (uint32_t*)take(4 * VN);
     w.va = (uint32_t*)take(4 * VN);
+    w.crect = (uint2*)take(8 * VN);
+    w.srect = (uint2*)take(8 * VN);
     w.rc = (uint32_t*)take(4 * (size_t)V * B.C * ty);
     w.roff = (uint32_t*)take(4 * (size_t)V * (B.C + 1) * ty);
     w.rbase = (int64_t*)take(8 * (size_t)V * ty);
     w.tc = (uint32_t*)take(4 * (size_t)V * B.G * T);
     w.toff = (uint32_t*)take(4 * (size_t)V * B.G * T);
-    w.segt_n = (int64_t)V * B.nseg_g * (int64_t)T;
-    w.segt = (uint32_t*)take(4 * (size_t)w.segt_n);
     w.tbase = (int64_t*)take(8 * (size_t)V * T);
     w.bytes = o;
     return w;
@@ -758,6 +830,12 @@ potr_status sweep(const uint32_t* kin, uint32_t* kout, const uint32_t* vin, uint
     hipLaunchKernelGGL((k_sweep<MODE>), dim3((unsigned)((int64_t)g.bps * segs)), dim3(kSwThreads), 0, s, kin, kout,
                        vin, vout, g, P);
     return check_launch("k_sweep");
+}
+
+// rows per band of the group counts' difference array
+int gc_band(int tiles_x) {
+    const int rows = (int)(kGcLds / (4 * (size_t)(tiles_x + 1))) - 1;
+    return std::max(1, std::min(kGcBand, rows));
 }
 
 size_t cols_lds(const Bins& B) {
@@ -780,7 +858,7 @@ size_t bin_workspace_bytes(int64_t N, int32_t V, int32_t tiles_x, int32_t tiles_
     return bin_layout(N, V, tiles_x, tiles_y, nullptr).bytes;
 }
 
-size_t sort_workspace_bytes(int64_t capacity) { return align_up((size_t)(capacity > 0 ? capacity : 1) * 6 + 256); }
+size_t sort_workspace_bytes(int64_t capacity) { return align_up((size_t)(capacity > 0 ? capacity : 1) * 4 + 256); }
 
 potr_status launch_bin(int64_t N, int32_t V, const potr_camera& cam0, const potr_config& cfg,
                        const potr_proj* proj, void* ws, uint32_t* order, int64_t* n_pairs, hipStream_t s) {
@@ -795,7 +873,7 @@ potr_status launch_bin(int64_t N, int32_t V, const potr_camera& cam0, const potr
         // stable per-view sort of the 32-bit depth keys: four 8-bit passes
         Seg g{N, nullptr, 0, (int32_t)ceil_div(N, kTile)};
         hipLaunchKernelGGL(k_hist<uint32_t>, dim3(hist_blocks(N, V), V), dim3(kThreads), 0, s,
-                           (const uint32_t*)nullptr, proj, w.ka, g, 4, 0, 8, 32, w.ctl.ghist);
+                           (const uint32_t*)nullptr, proj, w.ka, w.crect, g, 4, 0, 8, 32, w.ctl.ghist);
         st = check_launch("k_hist");
         if (st != POTR_OK) return st;
         uint32_t *kin = w.ka, *kout = w.kb;
@@ -812,9 +890,14 @@ potr_status launch_bin(int64_t N, int32_t V, const potr_camera& cam0, const potr
             kin = kout;
             kout = t;
         }
-        hipLaunchKernelGGL(k_row_count, dim3(B.C, V), dim3(kChunk), (size_t)tys * 4, s, (const uint32_t*)order, proj,
-                           B, w.rc, w.segr);
+        hipLaunchKernelGGL(k_row_count, dim3(B.C, V), dim3(kChunk), (size_t)tys * 4, s, (const uint32_t*)order,
+                           (const uint2*)w.crect, B, w.rc, w.segr, w.srect);
         st = check_launch("k_row_count");
+        if (st != POTR_OK) return st;
+        const int band = gc_band(txs);
+        hipLaunchKernelGGL(k_group_count, dim3(B.G, V), dim3(kGcThreads), (size_t)(band + 1) * (txs + 1) * 4, s,
+                           (const uint2*)w.srect, B, band, w.tc, w.segt);
+        st = check_launch("k_group_count");
         if (st != POTR_OK) return st;
     }
     // rows: bases over (view, row), the pair count, each chunk's first position per row
@@ -822,7 +905,13 @@ potr_status launch_bin(int64_t N, int32_t V, const potr_camera& cam0, const potr
                        n_pairs);
     st = check_launch("k_row_bases");
     if (st != POTR_OK) return st;
-    return col_scan_offsets(w.rc, w.segr, w.rbase, B.C, tys, B.seg_c, B.nseg_c, V, B.C + 1, n_pairs, -1, w.roff, s);
+    st = col_scan_offsets(w.rc, w.segr, w.rbase, B.C, tys, B.seg_c, B.nseg_c, V, B.C + 1, n_pairs, -1, w.roff, s);
+    if (st != POTR_OK) return st;
+    // tiles: bases (one scan over (view, tile)), each group's first position per tile
+    hipLaunchKernelGGL(k_tile_bases, dim3(tys, V), dim3(256), 0, s, w.segt, (const int64_t*)w.rbase, B, w.tbase);
+    st = check_launch("k_tile_bases");
+    if (st != POTR_OK || N == 0) return st;
+    return col_scan_offsets(w.tc, w.segt, w.tbase, B.G, B.T, B.seg_g, B.nseg_g, V, B.G, n_pairs, -1, w.toff, s);
 }
 
 potr_status launch_sort(int64_t N, int32_t V, const potr_camera& cam0, const potr_config& cfg,
@@ -832,66 +921,53 @@ potr_status launch_sort(int64_t N, int32_t V, const potr_camera& cam0, const pot
     const int txs = tiles_x(cam0, cfg), tys = tiles_y(cam0, cfg);
     BinWs w = bin_layout(N, V, txs, tys, (char*)ws);
     const Bins B = bins_of(N, V, txs, tys);
-    uint32_t* stage_id = (uint32_t*)sort_ws;
-    uint16_t* stage_x = (uint16_t*)((char*)sort_ws + align_up((size_t)(capacity > 0 ? capacity : 1) * 4));
+    uint32_t* stage = (uint32_t*)sort_ws;
     potr_status st = POTR_OK;
-    if (N > 0) {
-        // level 1: pairs into their rows; then the pairs per (group, tile)
-        // (level 1 also clears the tile segment sums the column counts add into)
-        hipLaunchKernelGGL(k_place_rows, dim3(B.C, V), dim3(64), (size_t)tys * 4, s, order, proj,
-                           (const uint32_t*)w.roff, B, n_pairs, capacity, stage_x, stage_id, w.segt, w.segt_n);
-        st = check_launch("k_place_rows");
-        if (st != POTR_OK) return st;
-        hipLaunchKernelGGL(k_col_count, dim3(B.G, tys, V), dim3(256), (size_t)txs * 4, s, (const uint32_t*)w.roff, B,
-                           n_pairs, capacity, (const uint16_t*)stage_x, w.tc, w.segt);
-        st = check_launch("k_col_count");
-    } else {
-        const unsigned cb = (unsigned)std::min<int64_t>(ceil_div((w.segt_n + 1) / 2, 256), 4096);
-        hipLaunchKernelGGL(k_clear, dim3(cb), dim3(256), 0, s, (uint64_t*)w.segt, (w.segt_n + 1) / 2);
-        st = check_launch("k_clear");
+    if (N == 0) {
+        // no pairs: every tile range is [0, 0)
+        const int64_t words = (int64_t)V * B.T;
+        hipLaunchKernelGGL(k_clear, dim3((unsigned)std::max<int64_t>(1, std::min<int64_t>(ceil_div(words, 256), 4096))),
+                           dim3(256), 0, s, (uint64_t*)tile_ranges, words);
+        return check_launch("k_clear");
     }
-    if (st != POTR_OK) return st;
-    // tiles: bases (within their row), ranges, each group's first position per tile
-    hipLaunchKernelGGL(k_tile_bases, dim3(tys, V), dim3(256), 0, s, w.segt, (const int64_t*)w.rbase, B, n_pairs,
-                       capacity, w.tbase, tile_ranges);
-    st = check_launch("k_tile_bases");
-    if (st != POTR_OK || N == 0) return st;
-    st = col_scan_offsets(w.tc, w.segt, w.tbase, B.G, B.T, B.seg_g, B.nseg_g, V, B.G, n_pairs, capacity, w.toff, s);
+    // level 1: pairs into their rows (and the tile ranges)
+    hipLaunchKernelGGL(k_place_rows, dim3(B.C, V), dim3(64), (size_t)tys * 4, s, (const uint2*)w.srect,
+                       (const uint32_t*)w.roff, (const int64_t*)w.tbase, B, n_pairs, capacity, stage, tile_ranges);
+    st = check_launch("k_place_rows");
     if (st != POTR_OK) return st;
     // level 2: each row segment of a group to its tiles
     const dim3 gl2(B.G, tys, V);
     const size_t l2 = cols_lds(B);
     const uint32_t* ro = w.roff;
     const uint32_t* to = w.toff;
-    const uint16_t* sx = stage_x;
-    const uint32_t* si = stage_id;
+    const uint32_t* stg = stage;
     switch (B.xbits) {
         case 1: case 2: case 3: case 4: case 5:
-            hipLaunchKernelGGL(k_place_cols<5>, gl2, dim3(kThreads), l2, s, ro, to, B, n_pairs, capacity, sx, si,
+            hipLaunchKernelGGL(k_place_cols<5>, gl2, dim3(kThreads), l2, s, ro, to, B, n_pairs, capacity, stg, order,
                                sorted_ids);
             break;
         case 6:
-            hipLaunchKernelGGL(k_place_cols<6>, gl2, dim3(kThreads), l2, s, ro, to, B, n_pairs, capacity, sx, si,
+            hipLaunchKernelGGL(k_place_cols<6>, gl2, dim3(kThreads), l2, s, ro, to, B, n_pairs, capacity, stg, order,
                                sorted_ids);
             break;
         case 7:
-            hipLaunchKernelGGL(k_place_cols<7>, gl2, dim3(kThreads), l2, s, ro, to, B, n_pairs, capacity, sx, si,
+            hipLaunchKernelGGL(k_place_cols<7>, gl2, dim3(kThreads), l2, s, ro, to, B, n_pairs, capacity, stg, order,
                                sorted_ids);
             break;
         case 8:
-            hipLaunchKernelGGL(k_place_cols<8>, gl2, dim3(kThreads), l2, s, ro, to, B, n_pairs, capacity, sx, si,
+            hipLaunchKernelGGL(k_place_cols<8>, gl2, dim3(kThreads), l2, s, ro, to, B, n_pairs, capacity, stg, order,
                                sorted_ids);
             break;
         case 9:
-            hipLaunchKernelGGL(k_place_cols<9>, gl2, dim3(kThreads), l2, s, ro, to, B, n_pairs, capacity, sx, si,
+            hipLaunchKernelGGL(k_place_cols<9>, gl2, dim3(kThreads), l2, s, ro, to, B, n_pairs, capacity, stg, order,
                                sorted_ids);
             break;
         case 10:
-            hipLaunchKernelGGL(k_place_cols<10>, gl2, dim3(kThreads), l2, s, ro, to, B, n_pairs, capacity, sx, si,
+            hipLaunchKernelGGL(k_place_cols<10>, gl2, dim3(kThreads), l2, s, ro, to, B, n_pairs, capacity, stg, order,
                                sorted_ids);
             break;
         default:
-            hipLaunchKernelGGL(k_place_cols<11>, gl2, dim3(kThreads), l2, s, ro, to, B, n_pairs, capacity, sx, si,
+            hipLaunchKernelGGL(k_place_cols<11>, gl2, dim3(kThreads), l2, s, ro, to, B, n_pairs, capacity, stg, order,
                                sorted_ids);
             break;
     }
