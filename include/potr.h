@@ -134,7 +134,7 @@ POTR_API potr_status potr_project(int64_t N, int32_t V, const potr_camera* cams,
  *          later stages treat as "no pairs").
  * Cost: the workspace holds 28 bytes per (view, splat) (depth sort keys and
  * values, rects by id and in depth order), 8 bytes per (view, group of 4096
- * ranks, tile) and 8 bytes per (view, chunk of 64 ranks, tile row).
+ * ranks, tile) and 4 bytes per (view, chunk of 64 ranks, tile row).
  * ------------------------------------------------------------------------- */
 POTR_API potr_status potr_bin_workspace_size(int64_t N, int32_t V, const potr_camera* cams, const potr_config* cfg,
                                     size_t* bytes);

@@ -301,24 +301,25 @@ __global__ void k_clear(uint64_t* __restrict__ p, int64_t n) {
 }
 
 // ---------------------------------------------------------------- pair placement
-// Ranks are cut into chunks of kChunk and groups of kGroup chunks. Placement
-// takes two coalesced levels over tables of counts:
-//   rows table  rc[v][c][y]  pairs of chunk c in tile row y (tiles its splats
-//               cover there), scanned over the chunks: every chunk's first
-//               position in the row's region of the output;
-//   tiles table tc[v][g][t]  pairs of group g in tile t, scanned over the
-//               groups: every group's first position in tile t.
+// Ranks are cut into chunks of kChunk and groups of kGroup chunks. One count
+// kernel (a block per group) forms, per tile row y, every chunk's pairs before
+// it in its group (rcx[v][c][y]) and the group's pairs (gsum, scanned over the
+// groups into gpre[v][y][g]), and per tile t the group's pairs (tc[v][g][t],
+// scanned over the groups into toff). With the row bases rbase (one scan over
+// (view, row)), chunk c of group g starts row y at
+//   rbase[v][y] + gpre[v][y][g] + rcx[v][c][y],
+// and group g's pairs of tile t start at toff[v][g][t].
 // Level 1 (a wave per chunk, its splats in rank order, lanes on the tiles of
 // one splat) appends one word (tile x, rank within the group) for every tile of
 // the rect to its row's region through per-row cursors, so the chunk's run in a
 // row is contiguous. Level 2 (a block per (group, row)) reads the group's
 // segment of the row, maps each rank to its splat id and places the id at its
 // tile's cursor, ranking equal tiles with ballots so that each tile's run
-// leaves as contiguous stores. The layout of the rows' regions is
-// that of the final output, so a row's region holds exactly its tiles' pairs.
+// leaves as contiguous stores. The layout of the rows' regions is that of the
+// final output, so a row's region holds exactly its tiles' pairs.
 struct Bins {
     int64_t N;
-    int32_t V, C, G, T, tiles_x, tiles_y, seg_c, nseg_c, seg_g, nseg_g, xbits;
+    int32_t V, C, G, T, tiles_x, tiles_y, seg_g, nseg_g, xbits;
 };
 constexpr int kChunk = 64;                    // ranks per chunk (one wave, one rank per lane)
 constexpr int kGroup = 64;                    // chunks per group
@@ -328,36 +329,6 @@ constexpr int kColItems = 8;                  // level 2: items per thread (2048
 // A staged pair is one word: tile x << kRankBits | rank of the splat within its group.
 constexpr int kRankBits = 12;
 static_assert(kGroupRanks == 1 << kRankBits, "a group's ranks fill the rank field");
-
-// rc[v][c][y]: pairs of chunk c in row y (one splat per thread), also added
-// into the row's sum over the chunk's segment of the column scan (segr,
-// cleared beforehand). The packed rects are also written out in depth order
-// (srect[v][rank]) for level 1.
-__global__ __launch_bounds__(kChunk) void k_row_count(const uint32_t* __restrict__ order,
-                                                      const uint2* __restrict__ crect, Bins B,
-                                                      uint32_t* __restrict__ rc, uint32_t* __restrict__ segr,
-                                                      uint2* __restrict__ srect) {
-    extern __shared__ uint32_t rows[];
-    const int c = blockIdx.x, v = blockIdx.y;
-    for (int y = threadIdx.x; y < B.tiles_y; y += kChunk) rows[y] = 0;
-    __syncthreads();
-    const int64_t r = (int64_t)c * kChunk + threadIdx.x;
-    if (r < B.N) {
-        const uint2 rr = crect[(int64_t)v * B.N + order[(int64_t)v * B.N + r]];
-        const uint32_t xw = rr.x, yw = rr.y;
-        srect[(int64_t)v * B.N + r] = rr;
-        const int w = (int)(xw >> 16) - (int)(xw & 0xffffu);
-        if (w > 0)
-            for (int y = (int)(yw & 0xffffu); y < (int)(yw >> 16); ++y) atomicAdd(&rows[y], (uint32_t)w);
-    }
-    __syncthreads();
-    uint32_t* sg = segr + ((int64_t)v * B.nseg_c + c / B.seg_c) * B.tiles_y;
-    for (int y = threadIdx.x; y < B.tiles_y; y += kChunk) {
-        const uint32_t x = rows[y];
-        rc[((int64_t)v * B.C + c) * B.tiles_y + y] = x;
-        if (x) atomicAdd(sg + y, x);
-    }
-}
 
 // Column scans of a table [v][R rows][cols] go by segments of seglen rows: the
 // count kernels add each segment's sums (segsum[v][seg][col]), the base kernels
@@ -402,10 +373,31 @@ __device__ inline uint32_t seg_prefix(uint32_t* __restrict__ p, int64_t stride, 
     return run;
 }
 
-// One block: per (view, row), the segment sums become exclusive prefixes in
-// place and give the row's total; row bases = exclusive scan of the totals over
-// (view, row); the number of pairs (-1 if a depth pass gave up a wait).
-__global__ __launch_bounds__(1024) void k_row_bases(uint32_t* __restrict__ segr, Bins B,
+// A wave per (view, row): the row's group sums become exclusive prefixes over
+// the groups in place (gsum -> gpre), and the row's total goes to rtot.
+__global__ __launch_bounds__(64) void k_group_prefix(uint32_t* __restrict__ gsum, Bins B,
+                                                     uint32_t* __restrict__ rtot) {
+    const int y = blockIdx.x, v = blockIdx.y, lane = threadIdx.x;
+    uint32_t* row = gsum + ((int64_t)v * B.tiles_y + y) * B.G;
+    uint32_t run = 0;
+    for (int g0 = 0; g0 < B.G; g0 += 64) {
+        const int g = g0 + lane;
+        const uint32_t val = g < B.G ? row[g] : 0u;
+        uint32_t inc = val;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t u = __shfl_up(inc, o, 64);
+            if (lane >= o) inc += u;
+        }
+        if (g < B.G) row[g] = run + inc - val;
+        run += __shfl(inc, 63, 64);
+    }
+    if (lane == 0) rtot[(int64_t)v * B.tiles_y + y] = run;
+}
+
+// One block: row bases = exclusive scan of the row totals over (view, row);
+// the number of pairs (-1 if a depth pass gave up a wait).
+__global__ __launch_bounds__(1024) void k_row_bases(const uint32_t* __restrict__ rtot, Bins B,
                                                     int64_t* __restrict__ base, const uint32_t* __restrict__ fault,
                                                     int64_t* __restrict__ n_pairs) {
     __shared__ int64_t wsum[16];
@@ -414,11 +406,7 @@ __global__ __launch_bounds__(1024) void k_row_bases(uint32_t* __restrict__ segr,
     int64_t carry = 0;
     for (int64_t b0 = 0; b0 < n; b0 += 1024) {
         const int64_t i = b0 + threadIdx.x;
-        int64_t tot = 0;
-        if (i < n) {
-            const int64_t v = i / B.tiles_y, y = i - v * B.tiles_y;
-            tot = seg_prefix(segr + v * B.nseg_c * B.tiles_y + y, B.tiles_y, B.nseg_c);
-        }
+        const int64_t tot = i < n ? (int64_t)rtot[i] : 0;
         int64_t inc = tot;
 #pragma unroll
         for (int d = 1; d < 64; d <<= 1) {
@@ -478,7 +466,9 @@ __global__ __launch_bounds__(256) void k_tile_bases(uint32_t* __restrict__ segt,
 // rect, and appends (x, rank within the group) to each tile's row through
 // per-row cursors in LDS that start at the chunk's first position in the row.
 __global__ __launch_bounds__(64) void k_place_rows(const uint2* __restrict__ srect,
-                                                   const uint32_t* __restrict__ roff,
+                                                   const int64_t* __restrict__ rbase,
+                                                   const uint32_t* __restrict__ gpre,
+                                                   const uint32_t* __restrict__ rcx,
                                                    const int64_t* __restrict__ tbase, Bins B,
                                                    const int64_t* __restrict__ n_pairs, int64_t capacity,
                                                    uint32_t* __restrict__ stage, int32_t* __restrict__ ranges) {
@@ -500,8 +490,12 @@ __global__ __launch_bounds__(64) void k_place_rows(const uint2* __restrict__ sre
     }
     if (!fits) return;
     const int c = blockIdx.x, v = blockIdx.y, lane = threadIdx.x;
-    const uint32_t* orow = roff + ((int64_t)v * (B.C + 1) + c) * B.tiles_y;
-    for (int y = lane; y < B.tiles_y; y += 64) cur[y] = orow[y];
+    const int g = c / kGroup;
+    const uint32_t* crow = rcx + ((int64_t)v * B.C + c) * B.tiles_y;
+    for (int y = lane; y < B.tiles_y; y += 64) {
+        const int64_t vy = (int64_t)v * B.tiles_y + y;
+        cur[y] = (uint32_t)(rbase[vy] + gpre[vy * B.G + g] + crow[y]);
+    }
     __builtin_amdgcn_wave_barrier();
     const int64_t r0 = (int64_t)c * kChunk;
     const int ns = (int)min((int64_t)kChunk, B.N - r0);
@@ -552,37 +546,53 @@ __global__ __launch_bounds__(64) void k_place_rows(const uint2* __restrict__ sre
     }
 }
 
-// tc[v][g][t]: pairs of group g in tile t (a block per (group, view)), from a
-// 2D difference array in LDS: every splat of the group adds +1 / -1 at the four
-// corners of its rect, and prefix sums down the columns, then along the rows,
-// give every tile's count. Images taller than the band go in bands of rows.
-// Each count is also added into its tile's sum over the group's segment of
-// the column scan (segt, cleared beforehand).
+// The counts of one group (a block per (group, view)), band by band of tile
+// rows, from difference arrays in LDS:
+//  - per tile: every splat of the group adds +1 / -1 at the four corners of its
+//    rect; prefix sums down the columns, then along the rows, give the group's
+//    pairs in every tile: tc[v][g][t], also added into the tile's sum over the
+//    group's segment of the column scan (segt, cleared beforehand);
+//  - per (chunk, row): every splat adds its rect width at its first row and
+//    takes it off past its last; a prefix sum down the rows gives the chunk's
+//    pairs per row, and an exclusive scan over the group's chunks gives
+//    rcx[v][c][y] and the group's total per row, gsum[v][y][g].
+// The group's rects are gathered in depth order once (and written to srect
+// for level 1).
 constexpr int kGcThreads = 1024;
 constexpr int kGcItems = kGroupRanks / kGcThreads;
 constexpr int kGcBand = 64;                       // rows per band at most (one lane each)
-constexpr size_t kGcLds = 48 * 1024;              // LDS budget of the difference array
+constexpr size_t kGcLds = 40 * 1024;              // LDS budget of the tile difference array
+static_assert(kGroup == 64, "one lane per chunk of a group");
 
-__global__ __launch_bounds__(kGcThreads) void k_group_count(const uint2* __restrict__ srect, Bins B, int band,
-                                                           uint32_t* __restrict__ tc, uint32_t* __restrict__ segt) {
-    extern __shared__ uint32_t d[];   // [band + 1][tiles_x + 1]
+__global__ __launch_bounds__(kGcThreads) void k_count(const uint32_t* __restrict__ order,
+                                                     const uint2* __restrict__ crect, Bins B, int band,
+                                                     uint2* __restrict__ srect, uint32_t* __restrict__ rcx,
+                                                     uint32_t* __restrict__ gsum, uint32_t* __restrict__ tc,
+                                                     uint32_t* __restrict__ segt) {
+    extern __shared__ uint32_t d[];   // [band + 1][tiles_x + 1], then rows [kGroup][band + 1]
     const int g = blockIdx.x, v = blockIdx.y;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     constexpr int NW = kGcThreads / 64;
-    const int TX = B.tiles_x, W1 = TX + 1;
+    const int TX = B.tiles_x, W1 = TX + 1, RS = band + 1;
+    uint32_t* rows = d + RS * W1;
     const int64_t r0 = (int64_t)g * kGroupRanks;
     const int ns = (int)min((int64_t)kGroupRanks, B.N - r0);
     uint2 rr[kGcItems];
 #pragma unroll
     for (int k = 0; k < kGcItems; ++k) {
         const int idx = k * kGcThreads + (int)threadIdx.x;
-        rr[k] = idx < ns ? srect[(int64_t)v * B.N + r0 + idx] : make_uint2(0u, 0u);
+        rr[k] = make_uint2(0u, 0u);
+        if (idx < ns) {
+            const int64_t r = (int64_t)v * B.N + r0 + idx;
+            rr[k] = crect[(int64_t)v * B.N + order[r]];
+            srect[r] = rr[k];
+        }
     }
     uint32_t* out = tc + ((int64_t)v * B.G + g) * B.T;
     uint32_t* sg = segt + ((int64_t)v * B.nseg_g + g / B.seg_g) * B.T;
     for (int yb0 = 0; yb0 < B.tiles_y; yb0 += band) {
         const int yb1 = min(B.tiles_y, yb0 + band), H = yb1 - yb0;
-        for (int i = threadIdx.x; i < (H + 1) * W1; i += kGcThreads) d[i] = 0u;
+        for (int i = threadIdx.x; i < RS * W1 + kGroup * RS; i += kGcThreads) d[i] = 0u;
         __syncthreads();
 #pragma unroll
         for (int k = 0; k < kGcItems; ++k) {
@@ -593,22 +603,28 @@ __global__ __launch_bounds__(kGcThreads) void k_group_count(const uint2* __restr
                 atomicSub(&d[y0 * W1 + x1], 1u);
                 atomicSub(&d[y1 * W1 + x0], 1u);
                 atomicAdd(&d[y1 * W1 + x1], 1u);
+                const int ch = (k * kGcThreads + (int)threadIdx.x) / kChunk;
+                atomicAdd(&rows[ch * RS + y0], (uint32_t)(x1 - x0));
+                atomicSub(&rows[ch * RS + y1], (uint32_t)(x1 - x0));
             }
         }
         __syncthreads();
-        // down the columns: a wave per column, one lane per row (H <= 64)
-        for (int x = w; x < TX; x += NW) {
-            const uint32_t val = lane < H ? d[lane * W1 + x] : 0u;
+        // down the columns of the tile array (a wave per column, a lane per row),
+        // and down the rows of each chunk (a wave per chunk)
+        for (int x = w; x < TX + kGroup; x += NW) {
+            uint32_t* p = x < TX ? d + x : rows + (x - TX) * RS;
+            const int stride = x < TX ? W1 : 1;
+            const uint32_t val = lane < H ? p[lane * stride] : 0u;
             uint32_t inc = val;
 #pragma unroll
             for (int o = 1; o < 64; o <<= 1) {
                 const uint32_t u = __shfl_up(inc, o, 64);
                 if (lane >= o) inc += u;
             }
-            if (lane < H) d[lane * W1 + x] = inc;
+            if (lane < H) p[lane * stride] = inc;
         }
         __syncthreads();
-        // along the rows: a wave per row, lanes over 64 columns at a time
+        // along the rows of the tile array (a wave per row, lanes over columns)
         for (int y = w; y < H; y += NW) {
             uint32_t carry = 0;
             for (int xc = 0; xc < TX; xc += 64) {
@@ -629,6 +645,19 @@ __global__ __launch_bounds__(kGcThreads) void k_group_count(const uint2* __restr
                 carry += __shfl(inc, 63, 64);
             }
         }
+        // across the group's chunks per row (a wave per row, a lane per chunk)
+        for (int y = w; y < H; y += NW) {
+            const uint32_t val = rows[lane * RS + y];
+            uint32_t inc = val;
+#pragma unroll
+            for (int o = 1; o < 64; o <<= 1) {
+                const uint32_t u = __shfl_up(inc, o, 64);
+                if (lane >= o) inc += u;
+            }
+            const int64_t c = (int64_t)g * kGroup + lane;
+            if (c < B.C) rcx[((int64_t)v * B.C + c) * B.tiles_y + yb0 + y] = inc - val;
+            if (lane == 63) gsum[((int64_t)v * B.tiles_y + yb0 + y) * B.G + g] = inc;
+        }
         __syncthreads();
     }
 }
@@ -638,7 +667,10 @@ __global__ __launch_bounds__(kGcThreads) void k_group_count(const uint2* __restr
 // (ballots over the x bits, per-wave counters), a sort in LDS, and stores of
 // each tile's run at the tile's cursor.
 template <int XBITS>
-__global__ __launch_bounds__(256) void k_place_cols(const uint32_t* __restrict__ roff, const uint32_t* __restrict__ off,
+__global__ __launch_bounds__(256) void k_place_cols(const int64_t* __restrict__ rbase,
+                                                    const uint32_t* __restrict__ gpre,
+                                                    const uint32_t* __restrict__ rtot,
+                                                    const uint32_t* __restrict__ off,
                                                     Bins B, const int64_t* __restrict__ n_pairs, int64_t capacity,
                                                     const uint32_t* __restrict__ stage,
                                                     const uint32_t* __restrict__ order,
@@ -655,9 +687,10 @@ __global__ __launch_bounds__(256) void k_place_cols(const uint32_t* __restrict__
     if (n < 0 || n > capacity) return;
     const int g = blockIdx.x, y = blockIdx.y, v = blockIdx.z;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int c0 = g * kGroup, c1 = min(B.C, c0 + kGroup);
-    const uint32_t seg0 = roff[((int64_t)v * (B.C + 1) + c0) * B.tiles_y + y];
-    const uint32_t len = roff[((int64_t)v * (B.C + 1) + c1) * B.tiles_y + y] - seg0;
+    const int64_t vy = (int64_t)v * B.tiles_y + y;
+    const uint32_t gp = gpre[vy * B.G + g];
+    const uint32_t seg0 = (uint32_t)rbase[vy] + gp;
+    const uint32_t len = (g + 1 < B.G ? gpre[vy * B.G + g + 1] : rtot[vy]) - gp;
     const uint32_t* orow = off + ((int64_t)v * B.G + g) * B.T + (int64_t)y * TX;
     const uint32_t* gorder = order + (int64_t)v * B.N + (int64_t)g * kGroupRanks;
     for (int x = threadIdx.x; x < TX; x += kThreads) cur[x] = orow[x];
@@ -768,8 +801,6 @@ Bins bins_of(int64_t N, int32_t V, int32_t tiles_x, int32_t tiles_y) {
     B.tiles_x = tiles_x;
     B.tiles_y = tiles_y;
     B.T = tiles_x * tiles_y;
-    B.seg_c = (int32_t)std::max<int64_t>(16, ceil_div(B.C, kMaxSegs));
-    B.nseg_c = (int32_t)std::max<int64_t>(1, ceil_div(B.C, B.seg_c));
     B.seg_g = (int32_t)std::max<int64_t>(16, ceil_div(B.G, kMaxSegs));
     B.nseg_g = (int32_t)std::max<int64_t>(1, ceil_div(B.G, B.seg_g));
     int bits = 1;
@@ -782,7 +813,7 @@ struct BinWs {
     Ctl ctl;
     uint32_t *ka, *kb, *va;
     uint2 *crect, *srect;   // rects by splat id, and in depth order
-    uint32_t *rc, *roff, *segr;
+    uint32_t *rcx, *gsum, *rtot;   // gsum becomes gpre in place
     int64_t* rbase;
     uint32_t *tc, *toff, *segt;
     int64_t* tbase;
@@ -801,8 +832,7 @@ BinWs bin_layout(int64_t N, int32_t V, int32_t tiles_x, int32_t tiles_y, char* b
     w.ctl.ghist = (uint32_t*)take(4 * (size_t)V * kMaxPasses * 256);
     w.ctl.status = (uint64_t*)take(8 * (size_t)V * bps * 256);
     const size_t ty = (size_t)tiles_y, T = (size_t)B.T;
-    // cleared with the control words: the segment sums the count kernels add into
-    w.segr = (uint32_t*)take(4 * (size_t)V * B.nseg_c * ty);
+    // cleared with the control words: the segment sums the group counts add into
     w.segt = (uint32_t*)take(4 * (size_t)V * B.nseg_g * T);
     w.ctl.clear_words = (int64_t)(o / 8);
     w.ka = (uint32_t*)take(4 * VN);
@@ -810,8 +840,9 @@ BinWs bin_layout(int64_t N, int32_t V, int32_t tiles_x, int32_t tiles_y, char* b
     w.va = (uint32_t*)take(4 * VN);
     w.crect = (uint2*)take(8 * VN);
     w.srect = (uint2*)take(8 * VN);
-    w.rc = (uint32_t*)take(4 * (size_t)V * B.C * ty);
-    w.roff = (uint32_t*)take(4 * (size_t)V * (B.C + 1) * ty);
+    w.rcx = (uint32_t*)take(4 * (size_t)V * B.C * ty);
+    w.gsum = (uint32_t*)take(4 * (size_t)V * ty * B.G);
+    w.rtot = (uint32_t*)take(4 * (size_t)V * ty);
     w.rbase = (int64_t*)take(8 * (size_t)V * ty);
     w.tc = (uint32_t*)take(4 * (size_t)V * B.G * T);
     w.toff = (uint32_t*)take(4 * (size_t)V * B.G * T);
@@ -832,11 +863,12 @@ potr_status sweep(const uint32_t* kin, uint32_t* kout, const uint32_t* vin, uint
     return check_launch("k_sweep");
 }
 
-// rows per band of the group counts' difference array
+// rows per band of the group counts' difference arrays, and their LDS bytes
 int gc_band(int tiles_x) {
     const int rows = (int)(kGcLds / (4 * (size_t)(tiles_x + 1))) - 1;
     return std::max(1, std::min(kGcBand, rows));
 }
+size_t gc_lds(int band, int tiles_x) { return (size_t)(band + 1) * (tiles_x + 1 + kGroup) * 4; }
 
 size_t cols_lds(const Bins& B) {
     return ((size_t)(kWaves + 2) * B.tiles_x + (size_t)kThreads * kColItems) * 4 + (size_t)kThreads * kColItems * 2;
@@ -890,22 +922,24 @@ potr_status launch_bin(int64_t N, int32_t V, const potr_camera& cam0, const potr
             kin = kout;
             kout = t;
         }
-        hipLaunchKernelGGL(k_row_count, dim3(B.C, V), dim3(kChunk), (size_t)tys * 4, s, (const uint32_t*)order,
-                           (const uint2*)w.crect, B, w.rc, w.segr, w.srect);
-        st = check_launch("k_row_count");
-        if (st != POTR_OK) return st;
         const int band = gc_band(txs);
-        hipLaunchKernelGGL(k_group_count, dim3(B.G, V), dim3(kGcThreads), (size_t)(band + 1) * (txs + 1) * 4, s,
-                           (const uint2*)w.srect, B, band, w.tc, w.segt);
-        st = check_launch("k_group_count");
+        hipLaunchKernelGGL(k_count, dim3(B.G, V), dim3(kGcThreads), gc_lds(band, txs), s, (const uint32_t*)order,
+                           (const uint2*)w.crect, B, band, w.srect, w.rcx, w.gsum, w.tc, w.segt);
+        st = check_launch("k_count");
+        if (st != POTR_OK) return st;
+        hipLaunchKernelGGL(k_group_prefix, dim3(tys, V), dim3(64), 0, s, w.gsum, B, w.rtot);
+        st = check_launch("k_group_prefix");
+        if (st != POTR_OK) return st;
+    } else {
+        // no splats: every row total is 0
+        hipLaunchKernelGGL(k_clear, dim3(1), dim3(256), 0, s, (uint64_t*)w.rtot, ((int64_t)V * tys + 1) / 2);
+        st = check_launch("k_clear");
         if (st != POTR_OK) return st;
     }
-    // rows: bases over (view, row), the pair count, each chunk's first position per row
-    hipLaunchKernelGGL(k_row_bases, dim3(1), dim3(1024), 0, s, w.segr, B, w.rbase, (const uint32_t*)w.ctl.fault,
-                       n_pairs);
+    // row bases over (view, row) and the pair count
+    hipLaunchKernelGGL(k_row_bases, dim3(1), dim3(1024), 0, s, (const uint32_t*)w.rtot, B, w.rbase,
+                       (const uint32_t*)w.ctl.fault, n_pairs);
     st = check_launch("k_row_bases");
-    if (st != POTR_OK) return st;
-    st = col_scan_offsets(w.rc, w.segr, w.rbase, B.C, tys, B.seg_c, B.nseg_c, V, B.C + 1, n_pairs, -1, w.roff, s);
     if (st != POTR_OK) return st;
     // tiles: bases (one scan over (view, tile)), each group's first position per tile
     hipLaunchKernelGGL(k_tile_bases, dim3(tys, V), dim3(256), 0, s, w.segt, (const int64_t*)w.rbase, B, w.tbase);
@@ -932,42 +966,45 @@ potr_status launch_sort(int64_t N, int32_t V, const potr_camera& cam0, const pot
     }
     // level 1: pairs into their rows (and the tile ranges)
     hipLaunchKernelGGL(k_place_rows, dim3(B.C, V), dim3(64), (size_t)tys * 4, s, (const uint2*)w.srect,
-                       (const uint32_t*)w.roff, (const int64_t*)w.tbase, B, n_pairs, capacity, stage, tile_ranges);
+                       (const int64_t*)w.rbase, (const uint32_t*)w.gsum, (const uint32_t*)w.rcx,
+                       (const int64_t*)w.tbase, B, n_pairs, capacity, stage, tile_ranges);
     st = check_launch("k_place_rows");
     if (st != POTR_OK) return st;
     // level 2: each row segment of a group to its tiles
     const dim3 gl2(B.G, tys, V);
     const size_t l2 = cols_lds(B);
-    const uint32_t* ro = w.roff;
+    const int64_t* rb = w.rbase;
+    const uint32_t* gp = w.gsum;
+    const uint32_t* rt = w.rtot;
     const uint32_t* to = w.toff;
     const uint32_t* stg = stage;
     switch (B.xbits) {
         case 1: case 2: case 3: case 4: case 5:
-            hipLaunchKernelGGL(k_place_cols<5>, gl2, dim3(kThreads), l2, s, ro, to, B, n_pairs, capacity, stg, order,
+            hipLaunchKernelGGL(k_place_cols<5>, gl2, dim3(kThreads), l2, s, rb, gp, rt, to, B, n_pairs, capacity, stg, order,
                                sorted_ids);
             break;
         case 6:
-            hipLaunchKernelGGL(k_place_cols<6>, gl2, dim3(kThreads), l2, s, ro, to, B, n_pairs, capacity, stg, order,
+            hipLaunchKernelGGL(k_place_cols<6>, gl2, dim3(kThreads), l2, s, rb, gp, rt, to, B, n_pairs, capacity, stg, order,
                                sorted_ids);
             break;
         case 7:
-            hipLaunchKernelGGL(k_place_cols<7>, gl2, dim3(kThreads), l2, s, ro, to, B, n_pairs, capacity, stg, order,
+            hipLaunchKernelGGL(k_place_cols<7>, gl2, dim3(kThreads), l2, s, rb, gp, rt, to, B, n_pairs, capacity, stg, order,
                                sorted_ids);
             break;
         case 8:
-            hipLaunchKernelGGL(k_place_cols<8>, gl2, dim3(kThreads), l2, s, ro, to, B, n_pairs, capacity, stg, order,
+            hipLaunchKernelGGL(k_place_cols<8>, gl2, dim3(kThreads), l2, s, rb, gp, rt, to, B, n_pairs, capacity, stg, order,
                                sorted_ids);
             break;
         case 9:
-            hipLaunchKernelGGL(k_place_cols<9>, gl2, dim3(kThreads), l2, s, ro, to, B, n_pairs, capacity, stg, order,
+            hipLaunchKernelGGL(k_place_cols<9>, gl2, dim3(kThreads), l2, s, rb, gp, rt, to, B, n_pairs, capacity, stg, order,
                                sorted_ids);
             break;
         case 10:
-            hipLaunchKernelGGL(k_place_cols<10>, gl2, dim3(kThreads), l2, s, ro, to, B, n_pairs, capacity, stg, order,
+            hipLaunchKernelGGL(k_place_cols<10>, gl2, dim3(kThreads), l2, s, rb, gp, rt, to, B, n_pairs, capacity, stg, order,
                                sorted_ids);
             break;
         default:
-            hipLaunchKernelGGL(k_place_cols<11>, gl2, dim3(kThreads), l2, s, ro, to, B, n_pairs, capacity, stg, order,
+            hipLaunchKernelGGL(k_place_cols<11>, gl2, dim3(kThreads), l2, s, rb, gp, rt, to, B, n_pairs, capacity, stg, order,
                                sorted_ids);
             break;
     }
