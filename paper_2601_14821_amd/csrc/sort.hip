@@ -224,12 +224,18 @@ __global__ __launch_bounds__(kSwThreads) void k_sweep(const uint32_t* __restrict
     uint32_t val[kSwItems];
     uint32_t rnk[kSwItems];
     const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    // all loads first and without branches (slots past the end load the last
+    // element and are not used), so that they are in flight together
+#pragma unroll
+    for (int k = 0; k < kSwItems; ++k) {
+        const int64_t e = max((int64_t)0, min(wbase + k * 64 + lane, n - 1));
+        key[k] = kin[seg0 + e];
+        val[k] = vin ? vin[seg0 + e] : (uint32_t)e;
+    }
 #pragma unroll
     for (int k = 0; k < kSwItems; ++k) {
         const int64_t e = wbase + k * 64 + lane;
         const bool ok = e < n;
-        key[k] = ok ? kin[seg0 + e] : 0u;
-        val[k] = ok ? (vin ? vin[seg0 + e] : (uint32_t)e) : 0u;
         const uint32_t d = digit_of(key[k], P.shift, mask);
         uint64_t m = __ballot(ok);
         for (int bit = 0; bit < P.bits; ++bit) {
