@@ -151,42 +151,45 @@ struct Pass {
     uint32_t* fault;
 };
 
-// Digit totals of every pass for each segment, in one read of the keys. With
-// proj != nullptr the keys are the depth bits of the records and are written
-// to keys_out on the way, with the rects to rect_out: the two sit in the same
-// 16 bytes of a record. A rect of tiles [x0, x1) x [y0, y1) is packed as the
-// two words (x0 | x1 << 16, y0 | y1 << 16).
-template <typename K>
-__global__ __launch_bounds__(kThreads) void k_hist(const K* __restrict__ keys, const potr_proj* __restrict__ proj,
-                                                   uint32_t* __restrict__ keys_out, uint2* __restrict__ rect_out,
-                                                   Seg g, int n_passes, int shift0, int per, int bits_total,
-                                                   uint32_t* __restrict__ ghist) {
+// Depth keys, rects and the digit totals of every pass, per view, in one read
+// of the records (the depth and the rect sit in the same 16 bytes of a record).
+// The keys go to keys_out, the rects to rect_out, packed as the two words
+// (x0 | x1 << 16, y0 | y1 << 16) for tiles [x0, x1) x [y0, y1). Large blocks
+// keep the global atomics that merge the block histograms few.
+constexpr int kHistThreads = 1024;
+constexpr int kHistItems = 8;
+
+__global__ __launch_bounds__(kHistThreads) void k_hist(const potr_proj* __restrict__ proj, int64_t N,
+                                                      uint32_t* __restrict__ keys_out, uint2* __restrict__ rect_out,
+                                                      uint32_t* __restrict__ ghist) {
     __shared__ uint32_t h[kMaxPasses][256];
-    for (int t = threadIdx.x; t < kMaxPasses * 256; t += kThreads) (&h[0][0])[t] = 0;
+    for (int t = threadIdx.x; t < kMaxPasses * 256; t += kHistThreads) (&h[0][0])[t] = 0;
     __syncthreads();
-    const int seg = blockIdx.y;
-    const int64_t n = seg_n(g);
-    const int64_t seg0 = (int64_t)seg * g.len;
-    for (int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x; e < n; e += (int64_t)gridDim.x * kThreads) {
-        K k;
-        if (proj) {
-            // bytes 32..47 of the record: rgb[2], depth, rect
-            const uint4 q = reinterpret_cast<const uint4*>(proj + seg0 + e)[2];
-            k = (K)q.y;
-            keys_out[seg0 + e] = q.y;
-            rect_out[seg0 + e] = make_uint2((q.z & 0xffffu) | (q.w << 16), (q.z >> 16) | (q.w & 0xffff0000u));
-        } else {
-            k = keys[seg0 + e];
-        }
-        for (int p = 0; p < n_passes; ++p) {
-            const int b = (p == n_passes - 1) ? bits_total - per * p : per;
-            atomicAdd(&h[p][digit_of(k, shift0 + per * p, (1u << b) - 1)], 1u);
+    const int v = blockIdx.y;
+    const int64_t base = (int64_t)v * N;
+    const int64_t e0 = (int64_t)blockIdx.x * (kHistThreads * kHistItems) + threadIdx.x;
+    // all loads first, without branches (slots past the end load the last record)
+    uint4 q[kHistItems];
+#pragma unroll
+    for (int k = 0; k < kHistItems; ++k) {
+        const int64_t e = min(e0 + (int64_t)k * kHistThreads, N - 1);
+        q[k] = reinterpret_cast<const uint4*>(proj + base + e)[2];   // rgb[2], depth, rect
+    }
+#pragma unroll
+    for (int k = 0; k < kHistItems; ++k) {
+        const int64_t e = e0 + (int64_t)k * kHistThreads;
+        if (e < N) {
+            const uint32_t key = q[k].y;
+            keys_out[base + e] = key;
+            rect_out[base + e] = make_uint2((q[k].z & 0xffffu) | (q[k].w << 16), (q[k].z >> 16) | (q[k].w & 0xffff0000u));
+#pragma unroll
+            for (int p = 0; p < kMaxPasses; ++p) atomicAdd(&h[p][(key >> (8 * p)) & 255u], 1u);
         }
     }
     __syncthreads();
-    for (int t = threadIdx.x; t < n_passes * 256; t += kThreads) {
+    for (int t = threadIdx.x; t < kMaxPasses * 256; t += kHistThreads) {
         const uint32_t c = (&h[0][0])[t];
-        if (c) atomicAdd(ghist + (int64_t)seg * kMaxPasses * 256 + t, c);
+        if (c) atomicAdd(ghist + (int64_t)v * kMaxPasses * 256 + t, c);
     }
 }
 
@@ -857,9 +860,6 @@ BinWs bin_layout(int64_t N, int32_t V, int32_t tiles_x, int32_t tiles_y, char* b
     return w;
 }
 
-unsigned hist_blocks(int64_t n, int segs) {
-    return (unsigned)std::max<int64_t>(1, std::min<int64_t>(ceil_div(n, 4 * kThreads), 2048 / segs));
-}
 
 template <int MODE>
 potr_status sweep(const uint32_t* kin, uint32_t* kout, const uint32_t* vin, uint32_t* vout, const Seg& g, int segs,
@@ -910,8 +910,8 @@ potr_status launch_bin(int64_t N, int32_t V, const potr_camera& cam0, const potr
     if (N > 0) {
         // stable per-view sort of the 32-bit depth keys: four 8-bit passes
         Seg g{N, nullptr, 0, (int32_t)ceil_div(N, kTile)};
-        hipLaunchKernelGGL(k_hist<uint32_t>, dim3(hist_blocks(N, V), V), dim3(kThreads), 0, s,
-                           (const uint32_t*)nullptr, proj, w.ka, w.crect, g, 4, 0, 8, 32, w.ctl.ghist);
+        hipLaunchKernelGGL(k_hist, dim3((unsigned)ceil_div(N, kHistThreads * kHistItems), V), dim3(kHistThreads), 0,
+                           s, proj, N, w.ka, w.crect, w.ctl.ghist);
         st = check_launch("k_hist");
         if (st != POTR_OK) return st;
         uint32_t *kin = w.ka, *kout = w.kb;
