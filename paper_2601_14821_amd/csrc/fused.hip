@@ -224,8 +224,7 @@ __device__ void render_score_tile(const ViewJob& J, int tile, const potr_config&
                 if (u >= ng) break;
                 const int j = js[u];
                 const float4 b = rb[u];
-                const float a0 = alpha_of(eval_gauss(ra[u], b, fx, fy), qmax, amin, amax);
-                const float al = base + j < walk ? a0 : 0.f;
+                const float al = alpha_if(eval_gauss(ra[u], b, fx, fy), qmax, amin, amax, base + j < walk);
                 const float w = __fmul_rn(T, al);
                 const float c0 = b.z, c1 = b.w, c2 = rc[u];
                 const float r0 = Rr, r1 = Rg, r2 = Rb;

@@ -37,6 +37,11 @@ __device__ inline float alpha_of(const Gauss& g, float qmax, float amin, float a
     return (g.q <= qmax && g.al0 >= amin) ? fminf(amax, g.al0) : 0.f;
 }
 
+// the same, and 0 where `live` is false (one select for all three tests)
+__device__ inline float alpha_if(const Gauss& g, float qmax, float amin, float amax, bool live) {
+    return (live && g.q <= qmax && g.al0 >= amin) ? fminf(amax, g.al0) : 0.f;
+}
+
 __device__ inline float next_T(float T, float al) { return __fmul_rn(T, __fsub_rn(1.f, al)); }
 
 __device__ inline float add_weighted(float P, float w, float c) { return __fmaf_rn(w, c, P); }

@@ -103,6 +103,25 @@ __device__ uint64_t look_back(uint64_t* st, int64_t b, int stride, uint32_t tag,
     return excl;
 }
 
+// Lanes of the wave (among those with ok set) whose BITS-bit key d equals this
+// lane's: how many there are (cnt) and how many sit below this lane (below).
+// Per bit, the bit spread over the word (0 or all ones), its ballot, and a
+// mask update that keeps the lanes whose bit agrees: m &= ~(ballot ^ spread).
+template <int BITS>
+__device__ inline void match_rank(uint32_t d, bool ok, uint32_t& below, uint32_t& cnt) {
+    const uint64_t okb = __ballot(ok);
+    uint32_t mlo = (uint32_t)okb, mhi = (uint32_t)(okb >> 32);
+#pragma unroll
+    for (int bit = 0; bit < BITS; ++bit) {
+        const uint32_t r = (uint32_t)((int32_t)(d << (31 - bit)) >> 31);
+        const uint64_t bal = __ballot(r != 0u);
+        mlo &= ~((uint32_t)bal ^ r);
+        mhi &= ~((uint32_t)(bal >> 32) ^ r);
+    }
+    below = __builtin_amdgcn_mbcnt_hi(mhi, __builtin_amdgcn_mbcnt_lo(mlo, 0u));
+    cnt = (uint32_t)(__popc(mlo) + __popc(mhi));
+}
+
 // Exclusive scan of one value per thread over the block (NT threads).
 template <int NT>
 __device__ inline uint32_t block_excl_scan(uint32_t x, uint32_t* wsum) {
@@ -226,7 +245,6 @@ __global__ __launch_bounds__(kSwThreads) void k_sweep(const uint32_t* __restrict
     uint32_t key[kSwItems];
     uint32_t val[kSwItems];
     uint32_t rnk[kSwItems];
-    const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     // all loads first and without branches (slots past the end load the last
     // element and are not used), so that they are in flight together
 #pragma unroll
@@ -240,13 +258,8 @@ __global__ __launch_bounds__(kSwThreads) void k_sweep(const uint32_t* __restrict
         const int64_t e = wbase + k * 64 + lane;
         const bool ok = e < n;
         const uint32_t d = digit_of(key[k], P.shift, mask);
-        uint64_t m = __ballot(ok);
-        for (int bit = 0; bit < P.bits; ++bit) {
-            const uint64_t bal = __ballot((d >> bit) & 1u);
-            m &= ((d >> bit) & 1u) ? bal : ~bal;
-        }
-        const uint32_t below = (uint32_t)__popcll(m & lt_mask);
-        const uint32_t cnt = (uint32_t)__popcll(m);
+        uint32_t below, cnt;
+        match_rank<8>(d, ok, below, cnt);
         uint32_t r = 0;
         if (ok) r = wcnt[w][d];
         __builtin_amdgcn_wave_barrier();
@@ -703,7 +716,6 @@ __global__ __launch_bounds__(256) void k_place_cols(const int64_t* __restrict__ 
     const uint32_t* orow = off + ((int64_t)v * B.G + g) * B.T + (int64_t)y * TX;
     const uint32_t* gorder = order + (int64_t)v * B.N + (int64_t)g * kGroupRanks;
     for (int x = threadIdx.x; x < TX; x += kThreads) cur[x] = orow[x];
-    const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     const int per = (TX + kThreads - 1) / kThreads;   // counters per thread in the block scan
     for (uint32_t b0 = 0; b0 < len; b0 += kThreads * kColItems) {
         for (int t = threadIdx.x; t < kWaves * TX; t += kThreads) wcnt[t] = 0;
@@ -729,14 +741,8 @@ __global__ __launch_bounds__(256) void k_place_cols(const int64_t* __restrict__ 
             const bool ok = e < cntb;
             const uint32_t d = ok ? key[k] : 0u;
             key[k] = d;
-            uint64_t m = __ballot(ok);
-#pragma unroll
-            for (int bit = 0; bit < XBITS; ++bit) {
-                const uint64_t bal = __ballot((d >> bit) & 1u);
-                m &= ((d >> bit) & 1u) ? bal : ~bal;
-            }
-            const uint32_t below = (uint32_t)__popcll(m & lt_mask);
-            const uint32_t c = (uint32_t)__popcll(m);
+            uint32_t below, c;
+            match_rank<XBITS>(d, ok, below, c);
             uint32_t r = 0;
             if (ok) r = wcnt[w * TX + d];
             __builtin_amdgcn_wave_barrier();
