@@ -35,8 +35,9 @@ __global__ __launch_bounds__(TW * TH) void k_blend_bwd(int64_t N, int32_t W, int
                                                        float* __restrict__ grad2d) {
     constexpr int NT = TW * TH;
     constexpr int NW = (NT + 63) / 64;
-    __shared__ float4 s_a[kBwdChunk];   // mean2d.x, mean2d.y, opacity, 2 conic.b
-    __shared__ float4 s_b[kBwdChunk];   // conic.a, conic.c, r, g
+    __shared__ float4 s_a[kBwdChunk];   // mean2d.x, mean2d.y, opacity, s 2 conic.b (the blend's record)
+    __shared__ float4 s_b[kBwdChunk];   // s conic.a, s conic.c, r, g
+    __shared__ float4 s_u[kBwdChunk];   // conic.a, conic.b, conic.c (unscaled, for the gradients)
     __shared__ float s_c[kBwdChunk];    // b
     __shared__ uint32_t s_id[kBwdChunk];
     __shared__ uint32_t s_rows[kBwdChunk];
@@ -56,6 +57,7 @@ __global__ __launch_bounds__(TW * TH) void k_blend_bwd(int64_t N, int32_t W, int
     const int beg = ranges[2 * tg];
     const potr_proj* pv = proj + (int64_t)v * N;
     const float qmax = cfg.q_max, amin = cfg.alpha_min, amax = cfg.alpha_max;
+    const float emin = exp_floor(qmax);
 
     int walk = 0;
     float PKr = 0.f, PKg = 0.f, PKb = 0.f, TF = 0.f, gr = 0.f, gg = 0.f, gb = 0.f;
@@ -89,10 +91,11 @@ __global__ __launch_bounds__(TW * TH) void k_blend_bwd(int64_t N, int32_t W, int
             const uint32_t id = ids[beg + base + j];
             const float4* src = reinterpret_cast<const float4*>(pv + id);
             const float4 r0 = src[0], r1 = src[1], r2 = src[2];
-            const float4 a = make_float4(r0.x, r0.y, r1.y, 2.f * r0.w);
-            const float4 b = make_float4(r0.z, r1.x, r1.z, r1.w);
+            float4 a, b;
+            make_rec(r0, r1, a, b);
             s_a[j] = a;
             s_b[j] = b;
+            s_u[j] = make_float4(r0.z, r0.w, r1.x, 0.f);
             s_c[j] = r2.x;
             s_id[j] = id;
             s_rows[j] = reach_rows(a, b, qmax, tile_y0, TH);
@@ -126,7 +129,7 @@ __global__ __launch_bounds__(TW * TH) void k_blend_bwd(int64_t N, int32_t W, int
                 const float4 a = s_a[j];
                 const float4 b = s_b[j];
                 const Gauss e = eval_gauss(a, b, fx, fy);
-                const float al = alpha_of(e, qmax, amin, amax);
+                const float al = alpha_of(e, emin, amin, amax);
                 if (al != 0.f) {
                     const float dx = e.dx, dy = e.dy, al0 = e.al0;
                     const float w = __fmul_rn(T, al);
@@ -143,9 +146,9 @@ __global__ __launch_bounds__(TW * TH) void k_blend_bwd(int64_t N, int32_t W, int
                     if (al0 < amax) {
                         g[u][5] = dLda * e.G;                      // dalpha/do = G
                         const float dLdq = -0.5f * al0 * dLda;
-                        const float cb = 0.5f * a.w;    // conic.b (staged doubled)
-                        g[u][0] = dLdq * 2.f * (b.x * dx + cb * dy);
-                        g[u][1] = dLdq * 2.f * (cb * dx + b.y * dy);
+                        const float4 cn = s_u[j];       // conic a, b, c
+                        g[u][0] = dLdq * 2.f * (cn.x * dx + cn.y * dy);
+                        g[u][1] = dLdq * 2.f * (cn.y * dx + cn.z * dy);
                         g[u][2] = dLdq * dx * dx;
                         g[u][3] = dLdq * 2.f * dx * dy;
                         g[u][4] = dLdq * dy * dy;

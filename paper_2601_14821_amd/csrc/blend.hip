@@ -32,8 +32,8 @@ __device__ inline void stage_batch(const potr_proj* __restrict__ pv, const uint3
         const float4 r0 = src[0];   // mean2d.x, mean2d.y, conic.a, conic.b
         const float4 r1 = src[1];   // conic.c, opacity, r, g
         const float4 r2 = src[2];   // b, depth, rect
-        const float4 a = make_float4(r0.x, r0.y, r1.y, 2.f * r0.w);
-        const float4 b = make_float4(r0.z, r1.x, r1.z, r1.w);
+        float4 a, b;
+        make_rec(r0, r1, a, b);
         s_a[j] = a;
         s_b[j] = b;
         s_c[j] = r2.x;
@@ -71,6 +71,7 @@ __global__ __launch_bounds__(TW * TH) void k_blend(int64_t N, int32_t W, int32_t
     const potr_proj* pv = proj + (int64_t)v * N;
     const int B = cfg.lds_batch;
     const float qmax = cfg.q_max, amin = cfg.alpha_min, amax = cfg.alpha_max, tmin = cfg.t_min;
+    const float emin = exp_floor(qmax);
 
     float T = 1.f, cr = 0.f, cg = 0.f, cb = 0.f;
     bool done = !inside;
@@ -94,7 +95,7 @@ __global__ __launch_bounds__(TW * TH) void k_blend(int64_t N, int32_t W, int32_t
                 if (i + u >= nl) break;
                 const int j = js[u];
                 const float4 b = s_b[j];
-                const float a0 = alpha_of(eval_gauss(s_a[j], b, fx, fy), qmax, amin, amax);
+                const float a0 = alpha_of(eval_gauss(s_a[j], b, fx, fy), emin, amin, amax);
                 const float al = done ? 0.f : a0;
                 const float Tn = next_T(T, al);
                 const bool stop = Tn < tmin;       // T >= tmin before, so only when al > 0
@@ -160,6 +161,7 @@ __global__ __launch_bounds__(TW * TH) void k_score(int64_t N, int32_t W, int32_t
     const potr_proj* pv = proj + (int64_t)v * N;
     const int B = cfg.lds_batch;
     const float qmax = cfg.q_max, amin = cfg.alpha_min, amax = cfg.alpha_max;
+    const float emin = exp_floor(qmax);
     const bool want_l1 = scores != nullptr, want_se = scores_se != nullptr, want_im = importance != nullptr;
 
     int walk = 0;
@@ -197,7 +199,7 @@ __global__ __launch_bounds__(TW * TH) void k_score(int64_t N, int32_t W, int32_t
             if (base + j < walk) {
                 const float4 a = s_a[j];
                 const float4 b = s_b[j];
-                const float al = alpha_of(eval_gauss(a, b, fx, fy), qmax, amin, amax);
+                const float al = alpha_of(eval_gauss(a, b, fx, fy), emin, amin, amax);
                 if (al != 0.f) {
                     const float w = __fmul_rn(T, al);
                     const float cr = b.z, cg = b.w, cbl = s_c[j];

@@ -41,8 +41,8 @@ __device__ inline void stage(const potr_proj* __restrict__ pv, const uint32_t* _
         const uint32_t id = ids[base + j];
         const float4* src = reinterpret_cast<const float4*>(pv + id);
         const float4 r0 = src[0], r1 = src[1], r2 = src[2];
-        const float4 a = make_float4(r0.x, r0.y, r1.y, 2.f * r0.w);
-        const float4 b = make_float4(r0.z, r1.x, r1.z, r1.w);
+        float4 a, b;
+        make_rec(r0, r1, a, b);
         sm.rec[j].a = a;
         sm.rec[j].b = b;
         sm.rec[j].c = make_float4(r2.x, 0.f, 0.f, 0.f);
@@ -79,6 +79,7 @@ __device__ void render_score_tile(const ViewJob& J, int tile, const potr_config&
     const int beg = J.ranges[2 * tile], end = J.ranges[2 * tile + 1];
     const int B = cfg.lds_batch;
     const float qmax = cfg.q_max, amin = cfg.alpha_min, amax = cfg.alpha_max, tmin = cfg.t_min;
+    const float emin = exp_floor(qmax);
     const int n_out = (J.scores ? 1 : 0) + (J.importance ? 1 : 0) + (SE ? 1 : 0);
     const int o_l1 = 0, o_im = J.scores ? 1 : 0, o_se = o_im + (J.importance ? 1 : 0);
     uint16_t* const L = sm.list + wid * B;
@@ -122,7 +123,7 @@ __device__ void render_score_tile(const ViewJob& J, int tile, const potr_config&
                 if (u >= nv) break;
                 const int j = js[u];
                 const float4 b = rb[u];
-                const float a0 = alpha_of(eval_gauss(ra[u], b, fx, fy), qmax, amin, amax);
+                const float a0 = alpha_of(eval_gauss(ra[u], b, fx, fy), emin, amin, amax);
                 const float al = done ? 0.f : a0;
                 const float Tn = next_T(T, al);
                 const bool stop = Tn < tmin;       // T >= tmin before, so only when al > 0
@@ -224,7 +225,7 @@ __device__ void render_score_tile(const ViewJob& J, int tile, const potr_config&
                 if (u >= ng) break;
                 const int j = js[u];
                 const float4 b = rb[u];
-                const float al = alpha_if(eval_gauss(ra[u], b, fx, fy), qmax, amin, amax, base + j < walk);
+                const float al = alpha_if(eval_gauss(ra[u], b, fx, fy), emin, amin, amax, base + j < walk);
                 const float w = __fmul_rn(T, al);
                 const float c0 = b.z, c1 = b.w, c2 = rc[u];
                 const float r0 = Rr, r1 = Rg, r2 = Rb;

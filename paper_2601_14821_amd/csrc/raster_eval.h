@@ -9,12 +9,27 @@
 
 namespace potr {
 
-// Staged record: a = (mean2d.x, mean2d.y, opacity, 2 conic.b), b = (conic.a, conic.c, r, g), c = blue.
-// (Doubling conic.b is exact, so the quadratic form keeps its rounding.)
+// exp(-q/2) = exp2(s q) with s = -log2(e)/2 (halving the FP32 log2(e) is exact).
+// Staged records carry the conic pre-multiplied by s, so a sweep forms the
+// exponent e = s q of the quadratic form directly.
+constexpr float kExpScale = -0x1.715476p-1f;
+
+// Staged record from the first two 16-byte words of a potr_proj
+// (r0 = mean2d.x, mean2d.y, conic.a, conic.b; r1 = conic.c, opacity, r, g):
+//   a = (mean2d.x, mean2d.y, opacity, s 2 conic.b), b = (s conic.a, s conic.c, r, g)
+// (blue is staged separately). Each scaled value is one FP32 rounding.
+__device__ inline void make_rec(const float4& r0, const float4& r1, float4& a, float4& b) {
+    a = make_float4(r0.x, r0.y, r1.y, __fmul_rn(2.f * r0.w, kExpScale));
+    b = make_float4(__fmul_rn(r0.z, kExpScale), __fmul_rn(r1.x, kExpScale), r1.z, r1.w);
+}
+
+// The q <= q_max test as a test on the exponent: e >= emin
+__device__ inline float exp_floor(float qmax) { return __fmul_rn(qmax, kExpScale); }
+
 struct Gauss {
     float dx, dy;   // centre minus pixel centre
-    float q;        // a dx^2 + 2 b dx dy + c dy^2
-    float G;        // exp(-q/2)
+    float e;        // s (a dx^2 + 2 b dx dy + c dy^2) = s q
+    float G;        // exp2(e) = exp(-q/2)
     float al0;      // o G (before the alpha_max clamp)
 };
 
@@ -22,24 +37,23 @@ __device__ inline Gauss eval_gauss(const float4& a, const float4& b, float fx, f
     Gauss r;
     r.dx = __fsub_rn(a.x, fx);
     r.dy = __fsub_rn(a.y, fy);
-    const float ad = __fmul_rn(b.x, r.dx);
-    const float bd = __fmul_rn(a.w, r.dx);
-    const float cd = __fmul_rn(b.y, r.dy);
-    r.q = __fmaf_rn(ad, r.dx, __fmaf_rn(bd, r.dy, __fmul_rn(cd, r.dy)));
-    // exp(-q/2) = exp2(q * (-log2(e) / 2)); halving the FP32 log2(e) is exact
-    r.G = __builtin_amdgcn_exp2f(__fmul_rn(r.q, -0x1.715476p-1f));
+    // e = dx (sa dx + s2b dy) + (sc dy) dy
+    const float t = __fmaf_rn(b.x, r.dx, __fmul_rn(a.w, r.dy));
+    const float u = __fmul_rn(b.y, r.dy);
+    r.e = __fmaf_rn(r.dx, t, __fmul_rn(u, r.dy));
+    r.G = __builtin_amdgcn_exp2f(r.e);
     r.al0 = __fmul_rn(a.z, r.G);
     return r;
 }
 
 // alpha where the splat counts at this pixel (q <= q_max, o G >= alpha_min), else 0
-__device__ inline float alpha_of(const Gauss& g, float qmax, float amin, float amax) {
-    return (g.q <= qmax && g.al0 >= amin) ? fminf(amax, g.al0) : 0.f;
+__device__ inline float alpha_of(const Gauss& g, float emin, float amin, float amax) {
+    return (g.e >= emin && g.al0 >= amin) ? fminf(amax, g.al0) : 0.f;
 }
 
 // the same, and 0 where `live` is false (one select for all three tests)
-__device__ inline float alpha_if(const Gauss& g, float qmax, float amin, float amax, bool live) {
-    return (live && g.q <= qmax && g.al0 >= amin) ? fminf(amax, g.al0) : 0.f;
+__device__ inline float alpha_if(const Gauss& g, float emin, float amin, float amax, bool live) {
+    return (live && g.e >= emin && g.al0 >= amin) ? fminf(amax, g.al0) : 0.f;
 }
 
 __device__ inline float next_T(float T, float al) { return __fmul_rn(T, __fsub_rn(1.f, al)); }
@@ -53,12 +67,14 @@ __device__ inline float add_weighted(float P, float w, float c) { return __fmaf_
 // rows it excludes could pass the visibility test. Used to skip whole waves.
 __device__ inline uint32_t reach_rows(const float4& a, const float4& b, float qmax, int tile_y0, int TH) {
     // FP64: the products of FP32 values are exact, so det has one rounding even
-    // for very elongated ellipses
+    // for very elongated ellipses. The staged conic is s times the conic
+    // (s < 0): its det is s^2 times the conic's, so (A s) / det here is the
+    // conic's a / det.
     const double A = b.x, B = 0.5 * (double)a.w, Cc = b.y;
     const double det = A * Cc - B * B;
     int r0 = 0, r1 = TH - 1;
     if (det > 0.0) {
-        const double ry = sqrt((double)qmax * A / det) * (1.0 + 1.0 / 1024.0) + 1.0 / 64.0;
+        const double ry = sqrt((double)qmax * A * (double)kExpScale / det) * (1.0 + 1.0 / 1024.0) + 1.0 / 64.0;
         if (ry == ry && ry < 1e8) {
             // rows j with |j + 0.5 - my| <= ry
             const double lo = ceil((double)a.y - ry - 0.5) - (double)tile_y0;
