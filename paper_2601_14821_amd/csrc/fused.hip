@@ -220,12 +220,14 @@ __device__ void render_score_tile(const ViewJob& J, int tile, const potr_config&
                 rc[u] = sm.rec[jj].c.x;
             }
             float l1v[4] = {0.f, 0.f, 0.f, 0.f}, imv[4] = {0.f, 0.f, 0.f, 0.f}, sev[4] = {0.f, 0.f, 0.f, 0.f};
+            // branch-free: a slot past the group's valid prefix takes alpha = 0,
+            // which leaves T and R unchanged and gives a zero removal effect
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
-                if (u >= ng) break;
                 const int j = js[u];
                 const float4 b = rb[u];
-                const float al = alpha_if(eval_gauss(ra[u], b, fx, fy), emin, amin, amax, base + j < walk);
+                const float al =
+                    alpha_if(eval_gauss(ra[u], b, fx, fy), emin, amin, amax, u < ng && base + j < walk);
                 const float w = __fmul_rn(T, al);
                 const float c0 = b.z, c1 = b.w, c2 = rc[u];
                 const float r0 = Rr, r1 = Rg, r2 = Rb;
@@ -291,7 +293,7 @@ __device__ inline Smem carve(char* base, int B) {
 }
 
 template <int TW, int TH, bool SE>
-__global__ __launch_bounds__(TW * TH) void k_render_score(ViewJobs jobs, potr_config cfg) {
+__global__ __launch_bounds__(TW * TH) __attribute__((amdgpu_waves_per_eu(7))) void k_render_score(ViewJobs jobs, potr_config cfg) {
     extern __shared__ __align__(16) char smem[];
     const Smem sm = carve<TW, TH>(smem, cfg.lds_batch);
     const ViewJob J = jobs.j[blockIdx.y];
