@@ -121,8 +121,8 @@ POTR_API potr_status potr_project(int64_t N, int32_t V, const potr_camera* cams,
  * potr_bin -- Sec. 3 ("layers ordered by approximate depth"): order each view's
  * splats by depth key (ties by splat id) and count the (tile, splat) pairs:
  * every tile of a splat's rect holds the splat. The counts per group of 4096
- * consecutive depth ranks and tile, and per chunk of 64 ranks and row of tiles,
- * their offsets, and the rects in depth order are kept in the workspace for
+ * consecutive depth ranks and tile, and per group and row of tiles, their
+ * offsets, and the rects in depth order are kept in the workspace for
  * potr_sort, which only reads it (so potr_sort may be called again, e.g. with
  * a larger capacity, without binning again).
  *   proj   [V*N] from potr_project, 16-byte aligned (its depth keys and rects are read)
@@ -134,7 +134,7 @@ POTR_API potr_status potr_project(int64_t N, int32_t V, const potr_camera* cams,
  *          later stages treat as "no pairs").
  * Cost: the workspace holds 28 bytes per (view, splat) (depth sort keys and
  * values, rects by id and in depth order), 8 bytes per (view, group of 4096
- * ranks, tile) and 4 bytes per (view, chunk of 64 ranks, tile row).
+ * ranks, tile) and 4 bytes per (view, group, tile row).
  * ------------------------------------------------------------------------- */
 POTR_API potr_status potr_bin_workspace_size(int64_t N, int32_t V, const potr_camera* cams, const potr_config* cfg,
                                     size_t* bytes);
@@ -147,13 +147,15 @@ POTR_API potr_status potr_bin(int64_t N, int32_t V, const potr_camera* cams, con
  * all tiles of all views back to back in (view, tile) order: the order a sort
  * of (view, tile, depth, id) keys gives, obtained by placing every pair
  * directly from the counts potr_bin left in its workspace (no per-pair sort):
- * first into its tile row, then, within each row, at its tile.
+ * per (group of 4096 depth ranks, tile row), the group's pairs in the row are
+ * laid out on chip and stored at their tiles' offsets.
  * N, V, cams, cfg, proj, order and ws are those of the potr_bin call before
  * (ws is read, not changed).
  *   n_pairs  (device) from potr_bin
  *   capacity (host) number of slots in sorted_ids; with more pairs than that
  *            nothing is placed and every range is empty (grow and call again)
- *   sort_ws  staging of potr_sort_workspace_size(capacity) bytes (4 per slot)
+ *   sort_ws  workspace of potr_sort_workspace_size(capacity) bytes (a 256-byte
+ *            placeholder: nothing per pair is staged in global memory)
  *   sorted_ids [capacity] uint32 out: splat id (0..N-1) of every pair
  *   tile_ranges [V*tiles*2] int32 out: half-open [start, end) into sorted_ids;
  *            [0, 0) for a tile without pairs

@@ -323,60 +323,46 @@ __global__ void k_clear(uint64_t* __restrict__ p, int64_t n) {
 }
 
 // ---------------------------------------------------------------- pair placement
-// Ranks are cut into chunks of kChunk and groups of kGroup chunks. One count
-// kernel (a block per group) forms, per tile row y, every chunk's pairs before
-// it in its group (rcx[v][c][y]) and the group's pairs (gsum, scanned over the
-// groups into gpre[v][y][g]), and per tile t the group's pairs (tc[v][g][t],
-// scanned over the groups into toff). With the row bases rbase (one scan over
-// (view, row)), chunk c of group g starts row y at
-//   rbase[v][y] + gpre[v][y][g] + rcx[v][c][y],
-// and group g's pairs of tile t start at toff[v][g][t].
-// Level 1 (a wave per chunk, its splats in rank order, lanes on the tiles of
-// one splat) appends one word (tile x, rank within the group) for every tile of
-// the rect to its row's region through per-row cursors, so the chunk's run in a
-// row is contiguous. Level 2 (a block per (group, row)) reads the group's
-// segment of the row, maps each rank to its splat id and places the id at its
-// tile's cursor, ranking equal tiles with ballots so that each tile's run
-// leaves as contiguous stores. The layout of the rows' regions is that of the
-// final output, so a row's region holds exactly its tiles' pairs.
+// Ranks are cut into groups of kGroupRanks. One count kernel (a block per
+// group) forms the group's pairs per tile, tc[v][g][t] (scanned over the groups
+// into toff: the group's first position in the tile), and per tile row,
+// gsum[v][y][g] (whose sums over the groups are the row totals). Placement (a
+// block per (group, row)) lays the group's runs in the row out in LDS and puts
+// each pair at its tile's cursor, so every tile's run of a group leaves as
+// contiguous stores; nothing per pair is staged in global memory.
 struct Bins {
     int64_t N;
-    int32_t V, C, G, T, tiles_x, tiles_y, seg_g, nseg_g, xbits;
+    int32_t V, G, T, tiles_x, tiles_y, seg_g, nseg_g, xbits;
 };
-constexpr int kChunk = 64;                    // ranks per chunk (one wave, one rank per lane)
-constexpr int kGroup = 64;                    // chunks per group
-constexpr int kGroupRanks = kChunk * kGroup;  // 4096
+constexpr int kGroupRanks = 4096;             // depth ranks per group
 constexpr int kMaxSegs = 32;                  // at most this many segments per column scan
 constexpr int kColItems = 8;                  // level 2: items per thread (2048 per block pass)
-// A staged pair is one word: tile x << kRankBits | rank of the splat within its group.
+// A pair in LDS is one word: tile x << kRankBits | rank of the splat within its group.
 constexpr int kRankBits = 12;
 static_assert(kGroupRanks == 1 << kRankBits, "a group's ranks fill the rank field");
 
-// Column scans of a table [v][R rows][cols] go by segments of seglen rows: the
-// count kernels add each segment's sums (segsum[v][seg][col]), the base kernels
-// turn them into exclusive prefixes in place, and each row's first position
-// is out[v][r][col] = base[v][col] + (sum of rows before r). With R_out = R + 1
-// the extra row holds the column's end.
-__global__ __launch_bounds__(256) void k_seg_offsets(const uint32_t* __restrict__ tab,
-                                                     const uint32_t* __restrict__ segsum,
-                                                     const int64_t* __restrict__ base, int32_t R, int32_t cols,
-                                                     int32_t seglen, int32_t nseg, int32_t R_out,
-                                                     const int64_t* __restrict__ n_pairs,
-                                                     int64_t capacity, uint32_t* __restrict__ out) {
-    const int col = blockIdx.x * 256 + threadIdx.x, seg = blockIdx.y, v = blockIdx.z;
-    if (col >= cols) return;
-    if (capacity >= 0) {
-        const int64_t n = *n_pairs;
-        if (n < 0 || n > capacity) return;
-    }
-    uint32_t run = (uint32_t)base[(int64_t)v * cols + col] + segsum[((int64_t)v * nseg + seg) * cols + col];
-    const int r0 = seg * seglen, r1 = min(R, r0 + seglen);
+// The group counts' column scan goes by segments of seg_g groups: the count
+// kernel adds each segment's sums (segt[v][seg][t]), the tile kernel turns them
+// into exclusive prefixes in place, and every group's first position in tile t
+// is toff[v][g][t] = tile base + (pairs of the groups before g), the tile base
+// being rbase[v][y] + trel[v][t].
+__global__ __launch_bounds__(256) void k_tile_offsets(const uint32_t* __restrict__ tc,
+                                                      const uint32_t* __restrict__ segt,
+                                                      const int64_t* __restrict__ rbase,
+                                                      const uint32_t* __restrict__ trel, Bins B,
+                                                      uint32_t* __restrict__ toff) {
+    const int t = blockIdx.x * 256 + threadIdx.x, seg = blockIdx.y, v = blockIdx.z;
+    if (t >= B.T) return;
+    const int64_t vt = (int64_t)v * B.T + t;
+    uint32_t run = (uint32_t)rbase[(int64_t)v * B.tiles_y + t / B.tiles_x] + trel[vt] +
+                   segt[((int64_t)v * B.nseg_g + seg) * B.T + t];
+    const int g0 = seg * B.seg_g, g1 = min(B.G, g0 + B.seg_g);
 #pragma unroll 8
-    for (int r = r0; r < r1; ++r) {
-        out[((int64_t)v * R_out + r) * cols + col] = run;
-        run += tab[((int64_t)v * R + r) * cols + col];
+    for (int g = g0; g < g1; ++g) {
+        const int64_t i = ((int64_t)v * B.G + g) * B.T + t;
+        toff[i] = run;
+        run += tc[i];
     }
-    if (r1 == R && R_out > R) out[((int64_t)v * R_out + R) * cols + col] = run;
 }
 
 // Turns the nseg (<= kMaxSegs) segment sums p[0], p[stride], ... into
@@ -393,28 +379,6 @@ __device__ inline uint32_t seg_prefix(uint32_t* __restrict__ p, int64_t stride, 
         run += x[k];
     }
     return run;
-}
-
-// A wave per (view, row): the row's group sums become exclusive prefixes over
-// the groups in place (gsum -> gpre), and the row's total goes to rtot.
-__global__ __launch_bounds__(64) void k_group_prefix(uint32_t* __restrict__ gsum, Bins B,
-                                                     uint32_t* __restrict__ rtot) {
-    const int y = blockIdx.x, v = blockIdx.y, lane = threadIdx.x;
-    uint32_t* row = gsum + ((int64_t)v * B.tiles_y + y) * B.G;
-    uint32_t run = 0;
-    for (int g0 = 0; g0 < B.G; g0 += 64) {
-        const int g = g0 + lane;
-        const uint32_t val = g < B.G ? row[g] : 0u;
-        uint32_t inc = val;
-#pragma unroll
-        for (int o = 1; o < 64; o <<= 1) {
-            const uint32_t u = __shfl_up(inc, o, 64);
-            if (lane >= o) inc += u;
-        }
-        if (g < B.G) row[g] = run + inc - val;
-        run += __shfl(inc, 63, 64);
-    }
-    if (lane == 0) rtot[(int64_t)v * B.tiles_y + y] = run;
 }
 
 // One block: row bases = exclusive scan of the row totals over (view, row);
@@ -451,152 +415,60 @@ __global__ __launch_bounds__(1024) void k_row_bases(const uint32_t* __restrict__
 }
 
 // A block per (view, row): per tile, the segment sums become exclusive prefixes
-// in place and give the tile's total; tile bases = the row's base + exclusive
-// scan of its tile totals (so over all (view, tile) they are one exclusive scan).
-__global__ __launch_bounds__(256) void k_tile_bases(uint32_t* __restrict__ segt, const int64_t* __restrict__ rbase,
-                                                    Bins B, int64_t* __restrict__ tbase) {
-    __shared__ int64_t wsum[4];
+// in place and give the tile's total; trel = exclusive scan of the row's tile
+// totals (the tile's start relative to the row's), rtot = the row's total.
+__global__ __launch_bounds__(256) void k_tile_bases(uint32_t* __restrict__ segt, Bins B,
+                                                    uint32_t* __restrict__ trel, uint32_t* __restrict__ rtot) {
+    __shared__ uint32_t wsum[4];
     const int y = blockIdx.x, v = blockIdx.y, lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    int64_t run = rbase[(int64_t)v * B.tiles_y + y];
+    uint32_t run = 0;
     const int64_t t0 = (int64_t)v * B.T + (int64_t)y * B.tiles_x;
     for (int x0 = 0; x0 < B.tiles_x; x0 += 256) {
         const int x = x0 + threadIdx.x;
-        int64_t c = 0;
+        uint32_t c = 0;
         if (x < B.tiles_x) c = seg_prefix(segt + (int64_t)v * B.nseg_g * B.T + (int64_t)y * B.tiles_x + x, B.T, B.nseg_g);
-        int64_t inc = c;
+        uint32_t inc = c;
 #pragma unroll
         for (int d = 1; d < 64; d <<= 1) {
-            const int64_t u = __shfl_up(inc, d, 64);
+            const uint32_t u = __shfl_up(inc, d, 64);
             if (lane >= d) inc += u;
         }
         if (lane == 63) wsum[w] = inc;
         __syncthreads();
-        int64_t pre = run, all = 0;
+        uint32_t pre = run, all = 0;
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
             if (k < w) pre += wsum[k];
             all += wsum[k];
         }
-        if (x < B.tiles_x) tbase[t0 + x] = pre + inc - c;
+        if (x < B.tiles_x) trel[t0 + x] = pre + inc - c;
         run += all;
         __syncthreads();
     }
-}
-
-// Level 1: a wave per (view, chunk). The wave walks the chunk's splats in rank
-// order (rects read in depth order), lanes on consecutive tiles of one splat's
-// rect, and appends (x, rank within the group) to each tile's row through
-// per-row cursors in LDS that start at the chunk's first position in the row.
-__global__ __launch_bounds__(64) void k_place_rows(const uint2* __restrict__ srect,
-                                                   const int64_t* __restrict__ rbase,
-                                                   const uint32_t* __restrict__ gpre,
-                                                   const uint32_t* __restrict__ rcx,
-                                                   const int64_t* __restrict__ tbase, Bins B,
-                                                   const int64_t* __restrict__ n_pairs, int64_t capacity,
-                                                   uint32_t* __restrict__ stage, int32_t* __restrict__ ranges) {
-    extern __shared__ uint32_t cur[];   // [tiles_y]
-    const int64_t n = *n_pairs;
-    const bool fits = n >= 0 && n <= capacity;
-    {
-        // tile ranges: the tile bases are one exclusive scan over (view, tile),
-        // so a tile ends where the next one starts; [0, 0) when empty, and all
-        // empty when the pairs exceed the capacity
-        const int64_t nt = (int64_t)B.V * B.T;
-        for (int64_t i = ((int64_t)blockIdx.y * gridDim.x + blockIdx.x) * 64 + threadIdx.x; i < nt;
-             i += (int64_t)gridDim.x * gridDim.y * 64) {
-            const int64_t b = tbase[i], e = i + 1 < nt ? tbase[i + 1] : n;
-            const bool any = fits && e > b;
-            ranges[2 * i] = any ? (int32_t)b : 0;
-            ranges[2 * i + 1] = any ? (int32_t)e : 0;
-        }
-    }
-    if (!fits) return;
-    const int c = blockIdx.x, v = blockIdx.y, lane = threadIdx.x;
-    const int g = c / kGroup;
-    const uint32_t* crow = rcx + ((int64_t)v * B.C + c) * B.tiles_y;
-    for (int y = lane; y < B.tiles_y; y += 64) {
-        const int64_t vy = (int64_t)v * B.tiles_y + y;
-        cur[y] = (uint32_t)(rbase[vy] + gpre[vy * B.G + g] + crow[y]);
-    }
-    __builtin_amdgcn_wave_barrier();
-    const int64_t r0 = (int64_t)c * kChunk;
-    const int ns = (int)min((int64_t)kChunk, B.N - r0);
-    // rank within the group of the chunk's first splat
-    const uint32_t rg0 = (uint32_t)(c % kGroup) * kChunk;
-    constexpr int kPer = kChunk / 64;
-    uint32_t sxw[kPer], syw[kPer];
-#pragma unroll
-    for (int k = 0; k < kPer; ++k) {
-        sxw[k] = syw[k] = 0;
-        const int sidx = k * 64 + lane;
-        if (sidx < ns) {
-            const uint2 rr = srect[(int64_t)v * B.N + r0 + sidx];
-            sxw[k] = rr.x;
-            syw[k] = rr.y;
-        }
-    }
-#pragma unroll
-    for (int k = 0; k < kPer; ++k) {
-        const int m = min(64, ns - k * 64);
-        for (int sj = 0; sj < m; ++sj) {
-            const uint32_t xw = (uint32_t)__builtin_amdgcn_readlane((int32_t)sxw[k], sj);
-            const uint32_t yw = (uint32_t)__builtin_amdgcn_readlane((int32_t)syw[k], sj);
-            const int x0 = (int)(xw & 0xffffu), x1 = (int)(xw >> 16);
-            const int y0 = (int)(yw & 0xffffu), y1 = (int)(yw >> 16);
-            const int wdt = x1 - x0;
-            if (wdt <= 0 || y1 <= y0) continue;
-            const int cnt = wdt * (y1 - y0);
-            const uint32_t rk = rg0 + (uint32_t)(k * 64 + sj);
-            const float rw = __builtin_amdgcn_rcpf((float)wdt);
-            for (int q = lane; q < cnt; q += 64) {
-                // tile q of the rect, row-major: q = ty * wdt + tx (the float
-                // quotient is off by at most one)
-                int ty = (int)((float)q * rw);
-                int tx = q - ty * wdt;
-                if (tx < 0) {
-                    --ty;
-                    tx += wdt;
-                } else if (tx >= wdt) {
-                    ++ty;
-                    tx -= wdt;
-                }
-                const uint32_t p = cur[y0 + ty] + (uint32_t)tx;
-                stage[p] = ((uint32_t)(x0 + tx) << kRankBits) | rk;
-            }
-            for (int yy = y0 + lane; yy < y1; yy += 64) cur[yy] += (uint32_t)wdt;
-        }
-    }
+    if (threadIdx.x == 0) rtot[(int64_t)v * B.tiles_y + y] = run;
 }
 
 // The counts of one group (a block per (group, view)), band by band of tile
-// rows, from difference arrays in LDS:
-//  - per tile: every splat of the group adds +1 / -1 at the four corners of its
-//    rect; prefix sums down the columns, then along the rows, give the group's
-//    pairs in every tile: tc[v][g][t], also added into the tile's sum over the
-//    group's segment of the column scan (segt, cleared beforehand);
-//  - per (chunk, row): every splat adds its rect width at its first row and
-//    takes it off past its last; a prefix sum down the rows gives the chunk's
-//    pairs per row, and an exclusive scan over the group's chunks gives
-//    rcx[v][c][y] and the group's total per row, gsum[v][y][g].
-// The group's rects are gathered in depth order once (and written to srect
-// for level 1).
+// rows, from a difference array in LDS: every splat of the group adds +1 / -1
+// at the four corners of its rect; prefix sums down the columns, then along the
+// rows, give the group's pairs in every tile: tc[v][g][t], also added into the
+// tile's sum over the group's segment of the column scan (segt, cleared
+// beforehand), and the group's pairs per row, gsum[v][y][g]. The group's rects
+// are gathered in depth order once (and written to srect for the placement).
 constexpr int kGcThreads = 1024;
 constexpr int kGcItems = kGroupRanks / kGcThreads;
 constexpr int kGcBand = 64;                       // rows per band at most (one lane each)
-constexpr size_t kGcLds = 40 * 1024;              // LDS budget of the tile difference array
-static_assert(kGroup == 64, "one lane per chunk of a group");
+constexpr size_t kGcLds = 48 * 1024;              // LDS budget of the difference array
 
 __global__ __launch_bounds__(kGcThreads) void k_count(const uint32_t* __restrict__ order,
                                                      const uint2* __restrict__ crect, Bins B, int band,
-                                                     uint2* __restrict__ srect, uint32_t* __restrict__ rcx,
-                                                     uint32_t* __restrict__ gsum, uint32_t* __restrict__ tc,
-                                                     uint32_t* __restrict__ segt) {
-    extern __shared__ uint32_t d[];   // [band + 1][tiles_x + 1], then rows [kGroup][band + 1]
+                                                     uint2* __restrict__ srect, uint32_t* __restrict__ gsum,
+                                                     uint32_t* __restrict__ tc, uint32_t* __restrict__ segt) {
+    extern __shared__ uint32_t d[];   // [band + 1][tiles_x + 1]
     const int g = blockIdx.x, v = blockIdx.y;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     constexpr int NW = kGcThreads / 64;
-    const int TX = B.tiles_x, W1 = TX + 1, RS = band + 1;
-    uint32_t* rows = d + RS * W1;
+    const int TX = B.tiles_x, W1 = TX + 1;
     const int64_t r0 = (int64_t)g * kGroupRanks;
     const int ns = (int)min((int64_t)kGroupRanks, B.N - r0);
     uint2 rr[kGcItems];
@@ -614,7 +486,7 @@ __global__ __launch_bounds__(kGcThreads) void k_count(const uint32_t* __restrict
     uint32_t* sg = segt + ((int64_t)v * B.nseg_g + g / B.seg_g) * B.T;
     for (int yb0 = 0; yb0 < B.tiles_y; yb0 += band) {
         const int yb1 = min(B.tiles_y, yb0 + band), H = yb1 - yb0;
-        for (int i = threadIdx.x; i < RS * W1 + kGroup * RS; i += kGcThreads) d[i] = 0u;
+        for (int i = threadIdx.x; i < (H + 1) * W1; i += kGcThreads) d[i] = 0u;
         __syncthreads();
 #pragma unroll
         for (int k = 0; k < kGcItems; ++k) {
@@ -625,30 +497,25 @@ __global__ __launch_bounds__(kGcThreads) void k_count(const uint32_t* __restrict
                 atomicSub(&d[y0 * W1 + x1], 1u);
                 atomicSub(&d[y1 * W1 + x0], 1u);
                 atomicAdd(&d[y1 * W1 + x1], 1u);
-                const int ch = (k * kGcThreads + (int)threadIdx.x) / kChunk;
-                atomicAdd(&rows[ch * RS + y0], (uint32_t)(x1 - x0));
-                atomicSub(&rows[ch * RS + y1], (uint32_t)(x1 - x0));
             }
         }
         __syncthreads();
-        // down the columns of the tile array (a wave per column, a lane per row),
-        // and down the rows of each chunk (a wave per chunk)
-        for (int x = w; x < TX + kGroup; x += NW) {
-            uint32_t* p = x < TX ? d + x : rows + (x - TX) * RS;
-            const int stride = x < TX ? W1 : 1;
-            const uint32_t val = lane < H ? p[lane * stride] : 0u;
+        // down the columns (a wave per column, a lane per row)
+        for (int x = w; x < TX; x += NW) {
+            const uint32_t val = lane < H ? d[lane * W1 + x] : 0u;
             uint32_t inc = val;
 #pragma unroll
             for (int o = 1; o < 64; o <<= 1) {
                 const uint32_t u = __shfl_up(inc, o, 64);
                 if (lane >= o) inc += u;
             }
-            if (lane < H) p[lane * stride] = inc;
+            if (lane < H) d[lane * W1 + x] = inc;
         }
         __syncthreads();
-        // along the rows of the tile array (a wave per row, lanes over columns)
+        // along the rows (a wave per row, lanes over columns); the row's total
+        // is the group's pairs in the row
         for (int y = w; y < H; y += NW) {
-            uint32_t carry = 0;
+            uint32_t carry = 0, rowsum = 0;
             for (int xc = 0; xc < TX; xc += 64) {
                 const int x = xc + lane;
                 const uint32_t val = x < TX ? d[y * W1 + x] : 0u;
@@ -658,140 +525,241 @@ __global__ __launch_bounds__(kGcThreads) void k_count(const uint32_t* __restrict
                     const uint32_t u = __shfl_up(inc, o, 64);
                     if (lane >= o) inc += u;
                 }
-                const uint32_t c = carry + inc;
+                const uint32_t c = carry + inc;   // the tile's count
                 if (x < TX) {
                     const int64_t t = (int64_t)(yb0 + y) * TX + x;
                     out[t] = c;
                     if (c) atomicAdd(sg + t, c);
+                    rowsum += c;
                 }
                 carry += __shfl(inc, 63, 64);
             }
-        }
-        // across the group's chunks per row (a wave per row, a lane per chunk)
-        for (int y = w; y < H; y += NW) {
-            const uint32_t val = rows[lane * RS + y];
-            uint32_t inc = val;
 #pragma unroll
-            for (int o = 1; o < 64; o <<= 1) {
-                const uint32_t u = __shfl_up(inc, o, 64);
-                if (lane >= o) inc += u;
-            }
-            const int64_t c = (int64_t)g * kGroup + lane;
-            if (c < B.C) rcx[((int64_t)v * B.C + c) * B.tiles_y + yb0 + y] = inc - val;
-            if (lane == 63) gsum[((int64_t)v * B.tiles_y + yb0 + y) * B.G + g] = inc;
+            for (int o = 32; o >= 1; o >>= 1) rowsum += __shfl_xor(rowsum, o, 64);
+            if (lane == 0) gsum[((int64_t)v * B.tiles_y + yb0 + y) * B.G + g] = rowsum;
         }
         __syncthreads();
     }
 }
 
-// Level 2: block per (view, group, row). The row segment level 1 wrote for
-// the group, in rank order, goes to its tiles: a stable ranking by tile x
-// (ballots over the x bits, per-wave counters), a sort in LDS, and stores of
-// each tile's run at the tile's cursor.
+// Pair placement, a block per (view, group, row). The group's splats that cover
+// the row, in rank order, each make a run of pairs over the tiles x0..x1-1 of
+// their rect; laid back to back these runs are the group's pairs of the row in
+// (rank, x) order. Per round of 2048 ranks the covering ranks' runs go to LDS
+// as a compact list (a scan of the run widths gives their starts, ballots of
+// the cover flags their places in the list);
+// per pass of up to 2048 pairs every thread expands eight consecutive pairs
+// (one binary search for the run holding its first pair, then a walk over the
+// runs) into words (tile x, rank within the group), the block ranks them
+// stably by tile x (ballots over the x bits, per-wave counters), maps each rank
+// to its splat id, sorts in LDS and stores each tile's run at the tile's cursor
+// (the group's first position in the tile, advanced per pass).
+// Blocks of group 0 also write the row's tile ranges, [0, 0) when empty and all
+// empty when the pairs exceed the capacity.
+constexpr int kPlRound = 2048;                       // ranks per round
+constexpr int kPlSlots = kPlRound / kThreads;        // ranks per lane per round
+constexpr int kPlPer = kThreads * kColItems / kThreads;   // pairs each thread expands per pass
+
 template <int XBITS>
-__global__ __launch_bounds__(256) void k_place_cols(const int64_t* __restrict__ rbase,
-                                                    const uint32_t* __restrict__ gpre,
-                                                    const uint32_t* __restrict__ rtot,
-                                                    const uint32_t* __restrict__ off,
-                                                    Bins B, const int64_t* __restrict__ n_pairs, int64_t capacity,
-                                                    const uint32_t* __restrict__ stage,
-                                                    const uint32_t* __restrict__ order,
-                                                    uint32_t* __restrict__ ids) {
+__global__ __launch_bounds__(256) void k_place(const uint2* __restrict__ srect, const uint32_t* __restrict__ gsum,
+                                               const uint32_t* __restrict__ off, const int64_t* __restrict__ rbase,
+                                               const uint32_t* __restrict__ trel, const uint32_t* __restrict__ rtot,
+                                               Bins B, const int64_t* __restrict__ n_pairs, int64_t capacity,
+                                               const uint32_t* __restrict__ order, uint32_t* __restrict__ ids,
+                                               int32_t* __restrict__ ranges) {
     extern __shared__ uint32_t lds[];
     const int TX = B.tiles_x;
-    uint32_t* wcnt = lds;                        // [kWaves][TX]
-    uint32_t* cur = wcnt + kWaves * TX;          // [TX]
-    uint32_t* boff = cur + TX;                   // [TX]
-    uint32_t* s_id = boff + TX;                  // [kThreads * kColItems]
-    uint16_t* s_x = reinterpret_cast<uint16_t*>(s_id + kThreads * kColItems);
+    uint32_t* wcnt = lds;                              // [kWaves][TX]
+    uint32_t* cur = wcnt + kWaves * TX;                // [TX]
+    uint32_t* boff = cur + TX;                         // [TX]
+    uint32_t* s_id = boff + TX;                        // [2048]: a pass's pair words, then its ids
+    uint32_t* s_off = s_id + kThreads * kColItems;     // [kPlRound]: start of each covering rank's run
+    uint16_t* s_x = reinterpret_cast<uint16_t*>(s_off + kPlRound);   // [2048]
+    uint16_t* s_x0 = s_x + kThreads * kColItems;       // [kPlRound]: its first tile
+    uint16_t* s_rk = s_x0 + kPlRound;                  // [kPlRound]: its rank within the round
     __shared__ uint32_t wsum[kWaves];
-    const int64_t n = *n_pairs;
-    if (n < 0 || n > capacity) return;
+    __shared__ uint32_t wcov[kWaves];
     const int g = blockIdx.x, y = blockIdx.y, v = blockIdx.z;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int64_t n = *n_pairs;
+    const bool fits = n >= 0 && n <= capacity;
     const int64_t vy = (int64_t)v * B.tiles_y + y;
-    const uint32_t gp = gpre[vy * B.G + g];
-    const uint32_t seg0 = (uint32_t)rbase[vy] + gp;
-    const uint32_t len = (g + 1 < B.G ? gpre[vy * B.G + g + 1] : rtot[vy]) - gp;
+    if (g == 0) {
+        const int64_t rb = rbase[vy];
+        for (int x = threadIdx.x; x < TX; x += kThreads) {
+            const int64_t i = (int64_t)v * B.T + (int64_t)y * TX + x;
+            const int64_t b = rb + trel[i], e = rb + (x + 1 < TX ? trel[i + 1] : rtot[vy]);
+            const bool any = fits && e > b;
+            ranges[2 * i] = any ? (int32_t)b : 0;
+            ranges[2 * i + 1] = any ? (int32_t)e : 0;
+        }
+    }
+    if (!fits) return;
+    const uint32_t len = gsum[vy * B.G + g];   // the group's pairs in the row
+    if (len == 0) return;
     const uint32_t* orow = off + ((int64_t)v * B.G + g) * B.T + (int64_t)y * TX;
     const uint32_t* gorder = order + (int64_t)v * B.N + (int64_t)g * kGroupRanks;
+    const uint2* grect = srect + (int64_t)v * B.N + (int64_t)g * kGroupRanks;
     for (int x = threadIdx.x; x < TX; x += kThreads) cur[x] = orow[x];
+    const int ns = (int)min((int64_t)kGroupRanks, B.N - (int64_t)g * kGroupRanks);
     const int per = (TX + kThreads - 1) / kThreads;   // counters per thread in the block scan
-    for (uint32_t b0 = 0; b0 < len; b0 += kThreads * kColItems) {
-        for (int t = threadIdx.x; t < kWaves * TX; t += kThreads) wcnt[t] = 0;
+    uint32_t placed = 0;
+    for (int h0 = 0; h0 < ns; h0 += kPlRound) {
+        const int nh = min(kPlRound, ns - h0);
+        // lane l of wave w holds the round's ranks 512 w + 64 k + l (k < kPlSlots)
+        uint32_t wd[kPlSlots], x0v[kPlSlots];
+#pragma unroll
+        for (int k = 0; k < kPlSlots; ++k) {
+            const int rk = w * 64 * kPlSlots + k * 64 + lane;
+            const uint2 rr = grect[h0 + min(rk, nh - 1)];
+            const uint32_t x0 = rr.x & 0xffffu, x1 = rr.x >> 16;
+            const int y0 = (int)(rr.y & 0xffffu), y1 = (int)(rr.y >> 16);
+            wd[k] = (rk < nh && y0 <= y && y < y1 && x0 < x1) ? x1 - x0 : 0u;
+            x0v[k] = x0;
+        }
+        // exclusive scans in rank order (slot-major in a wave, then waves): of
+        // the widths (run starts) and of the cover flags (places in the list)
+        uint32_t carry = 0, ccnt = 0, ofs[kPlSlots], pos[kPlSlots];
+#pragma unroll
+        for (int k = 0; k < kPlSlots; ++k) {
+            uint32_t inc = wd[k];
+#pragma unroll
+            for (int o = 1; o < 64; o <<= 1) {
+                const uint32_t u = __shfl_up(inc, o, 64);
+                if (lane >= o) inc += u;
+            }
+            ofs[k] = carry + inc - wd[k];
+            carry += (uint32_t)__builtin_amdgcn_readlane((int32_t)inc, 63);
+            const uint64_t cb = __ballot(wd[k] != 0u);
+            pos[k] = ccnt + __builtin_amdgcn_mbcnt_hi((uint32_t)(cb >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)cb, 0u));
+            ccnt += (uint32_t)__popcll(cb);
+        }
+        if (lane == 0) {
+            wsum[w] = carry;
+            wcov[w] = ccnt;
+        }
         __syncthreads();
-        const uint32_t cntb = min(len - b0, (uint32_t)(kThreads * kColItems));
-        uint32_t key[kColItems], val[kColItems], rnk[kColItems];
-        // all staged words first, then all id gathers, without branches, so that
-        // the loads stay in flight together (slots past the pass's end load its
-        // last word and are not used)
+        uint32_t wb = 0, tot = 0, cb0 = 0, call = 0;
 #pragma unroll
-        for (int k = 0; k < kColItems; ++k) {
-            const uint32_t e = (uint32_t)(w * 64 * kColItems + k * 64 + lane);
-            key[k] = stage[seg0 + b0 + min(e, cntb - 1)];
+        for (int k = 0; k < kWaves; ++k) {
+            if (k < w) {
+                wb += wsum[k];
+                cb0 += wcov[k];
+            }
+            tot += wsum[k];
+            call += wcov[k];
         }
+        const int ncov = (int)call;   // covering ranks of the round; tot: their pairs
 #pragma unroll
-        for (int k = 0; k < kColItems; ++k) {
-            val[k] = gorder[key[k] & (kGroupRanks - 1)];   // the splat id
-            key[k] >>= kRankBits;
-        }
-#pragma unroll
-        for (int k = 0; k < kColItems; ++k) {
-            const uint32_t e = (uint32_t)(w * 64 * kColItems + k * 64 + lane);
-            const bool ok = e < cntb;
-            const uint32_t d = ok ? key[k] : 0u;
-            key[k] = d;
-            uint32_t below, c;
-            match_rank<XBITS>(d, ok, below, c);
-            uint32_t r = 0;
-            if (ok) r = wcnt[w * TX + d];
-            __builtin_amdgcn_wave_barrier();
-            if (ok && below == 0) wcnt[w * TX + d] = r + c;
-            __builtin_amdgcn_wave_barrier();
-            rnk[k] = ok ? r + below : 0xffffffffu;
+        for (int k = 0; k < kPlSlots; ++k) {
+            if (wd[k] != 0u) {
+                const uint32_t idx = cb0 + pos[k];
+                s_off[idx] = wb + ofs[k];
+                s_x0[idx] = (uint16_t)x0v[k];
+                s_rk[idx] = (uint16_t)(w * 64 * kPlSlots + k * 64 + lane);
+            }
         }
         __syncthreads();
-        // per x: exclusive prefix over waves, block count; then the block scan of the counts
-        uint32_t local[8];
-        uint32_t mine = 0;
-        for (int j = 0; j < per; ++j) {
-            const int x = threadIdx.x * per + j;
-            uint32_t run = 0;
-            if (x < TX)
-                for (int ww = 0; ww < kWaves; ++ww) {
-                    const uint32_t c = wcnt[ww * TX + x];
-                    wcnt[ww * TX + x] = run;
-                    run += c;
+        if (placed + tot > len) return;   // cannot happen: the counts come from the same rects
+        placed += tot;
+        for (uint32_t b0 = 0; b0 < tot; b0 += kThreads * kColItems) {
+            const uint32_t cntb = min(tot - b0, (uint32_t)(kThreads * kColItems));
+            // expand pairs i0 .. i0 + kPlPer - 1 of the pass
+            const uint32_t i0 = threadIdx.x * kPlPer;
+            if (i0 < cntb) {
+                const uint32_t q0 = b0 + i0;
+                int lo = 0, hi = ncov - 1;   // last run starting at or before q0
+                while (lo < hi) {
+                    const int mid = (lo + hi + 1) >> 1;
+                    if (s_off[mid] <= q0) lo = mid;
+                    else hi = mid - 1;
                 }
-            local[j] = run;
-            mine += run;
-        }
-        uint32_t pre = block_excl_scan<kThreads>(mine, wsum);
-        for (int j = 0; j < per; ++j) {
-            const int x = threadIdx.x * per + j;
-            if (x < TX) boff[x] = pre;
-            pre += local[j];
-        }
-        __syncthreads();
+                int r = lo;
+                uint32_t o = s_off[r], end = r + 1 < ncov ? s_off[r + 1] : tot;
+                const uint32_t i1 = min(i0 + kPlPer, cntb);
+                for (uint32_t i = i0; i < i1; ++i) {
+                    const uint32_t q = b0 + i;
+                    if (q >= end) {   // runs are never empty: q is in the next one
+                        ++r;
+                        o = end;
+                        end = r + 1 < ncov ? s_off[r + 1] : tot;
+                    }
+                    s_id[i] = (((uint32_t)s_x0[r] + (q - o)) << kRankBits) | (uint32_t)(h0 + s_rk[r]);
+                }
+            }
+            for (int t = threadIdx.x; t < kWaves * TX; t += kThreads) wcnt[t] = 0;
+            __syncthreads();
+            uint32_t key[kColItems], val[kColItems], rnk[kColItems];
 #pragma unroll
-        for (int k = 0; k < kColItems; ++k) {
-            if (rnk[k] == 0xffffffffu) continue;
-            const uint32_t p = boff[key[k]] + wcnt[w * TX + key[k]] + rnk[k];
-            s_id[p] = val[k];
-            s_x[p] = (uint16_t)key[k];
+            for (int k = 0; k < kColItems; ++k) {
+                const uint32_t e = (uint32_t)(w * 64 * kColItems + k * 64 + lane);
+                key[k] = s_id[min(e, cntb - 1)];
+            }
+            // all id gathers first, without branches, so that they stay in flight together
+#pragma unroll
+            for (int k = 0; k < kColItems; ++k) {
+                val[k] = gorder[key[k] & (kGroupRanks - 1)];   // the splat id
+                key[k] >>= kRankBits;
+            }
+#pragma unroll
+            for (int k = 0; k < kColItems; ++k) {
+                const uint32_t e = (uint32_t)(w * 64 * kColItems + k * 64 + lane);
+                const bool ok = e < cntb;
+                const uint32_t d = ok ? key[k] : 0u;
+                key[k] = d;
+                uint32_t below, c;
+                match_rank<XBITS>(d, ok, below, c);
+                uint32_t r = 0;
+                if (ok) r = wcnt[w * TX + d];
+                __builtin_amdgcn_wave_barrier();
+                if (ok && below == 0) wcnt[w * TX + d] = r + c;
+                __builtin_amdgcn_wave_barrier();
+                rnk[k] = ok ? r + below : 0xffffffffu;
+            }
+            __syncthreads();
+            // per x: exclusive prefix over waves, block count; then the block scan of the counts
+            uint32_t local[8];
+            uint32_t mine = 0;
+            for (int j = 0; j < per; ++j) {
+                const int x = threadIdx.x * per + j;
+                uint32_t run = 0;
+                if (x < TX)
+                    for (int ww = 0; ww < kWaves; ++ww) {
+                        const uint32_t c = wcnt[ww * TX + x];
+                        wcnt[ww * TX + x] = run;
+                        run += c;
+                    }
+                local[j] = run;
+                mine += run;
+            }
+            uint32_t pre = block_excl_scan<kThreads>(mine, wsum);
+            for (int j = 0; j < per; ++j) {
+                const int x = threadIdx.x * per + j;
+                if (x < TX) boff[x] = pre;
+                pre += local[j];
+            }
+            __syncthreads();
+#pragma unroll
+            for (int k = 0; k < kColItems; ++k) {
+                if (rnk[k] == 0xffffffffu) continue;
+                const uint32_t p = boff[key[k]] + wcnt[w * TX + key[k]] + rnk[k];
+                s_id[p] = val[k];
+                s_x[p] = (uint16_t)key[k];
+            }
+            __syncthreads();
+            for (uint32_t i = threadIdx.x; i < cntb; i += kThreads) {
+                const uint32_t x = s_x[i];
+                ids[cur[x] + (i - boff[x])] = s_id[i];
+            }
+            __syncthreads();
+            // advance the cursors past this pass's runs
+            for (int x = threadIdx.x; x < TX; x += kThreads) {
+                const uint32_t end = (x + 1 < TX) ? boff[x + 1] : cntb;
+                cur[x] += end - boff[x];
+            }
+            __syncthreads();
         }
-        __syncthreads();
-        for (uint32_t i = threadIdx.x; i < cntb; i += kThreads) {
-            const uint32_t x = s_x[i];
-            ids[cur[x] + (i - boff[x])] = s_id[i];
-        }
-        __syncthreads();
-        // advance the cursors past this pass's runs
-        for (int x = threadIdx.x; x < TX; x += kThreads) {
-            const uint32_t end = (x + 1 < TX) ? boff[x + 1] : cntb;
-            cur[x] += end - boff[x];
-        }
-        __syncthreads();
+        __syncthreads();   // the next round rewrites wsum and the run offsets
     }
 }
 
@@ -811,7 +779,6 @@ Bins bins_of(int64_t N, int32_t V, int32_t tiles_x, int32_t tiles_y) {
     Bins B;
     B.N = N;
     B.V = V;
-    B.C = (int32_t)ceil_div(N, kChunk);
     B.G = (int32_t)ceil_div(N, kGroupRanks);
     B.tiles_x = tiles_x;
     B.tiles_y = tiles_y;
@@ -828,10 +795,9 @@ struct BinWs {
     Ctl ctl;
     uint32_t *ka, *kb, *va;
     uint2 *crect, *srect;   // rects by splat id, and in depth order
-    uint32_t *rcx, *gsum, *rtot;   // gsum becomes gpre in place
+    uint32_t *gsum, *rtot;
     int64_t* rbase;
-    uint32_t *tc, *toff, *segt;
-    int64_t* tbase;
+    uint32_t *tc, *toff, *segt, *trel;
     size_t bytes;
 };
 
@@ -847,7 +813,7 @@ BinWs bin_layout(int64_t N, int32_t V, int32_t tiles_x, int32_t tiles_y, char* b
     w.ctl.ghist = (uint32_t*)take(4 * (size_t)V * kMaxPasses * 256);
     w.ctl.status = (uint64_t*)take(8 * (size_t)V * bps * 256);
     const size_t ty = (size_t)tiles_y, T = (size_t)B.T;
-    // cleared with the control words: the segment sums the group counts add into
+    // cleared with the control words: the sums the group counts add into
     w.segt = (uint32_t*)take(4 * (size_t)V * B.nseg_g * T);
     w.ctl.clear_words = (int64_t)(o / 8);
     w.ka = (uint32_t*)take(4 * VN);
@@ -855,13 +821,12 @@ BinWs bin_layout(int64_t N, int32_t V, int32_t tiles_x, int32_t tiles_y, char* b
     w.va = (uint32_t*)take(4 * VN);
     w.crect = (uint2*)take(8 * VN);
     w.srect = (uint2*)take(8 * VN);
-    w.rcx = (uint32_t*)take(4 * (size_t)V * B.C * ty);
     w.gsum = (uint32_t*)take(4 * (size_t)V * ty * B.G);
     w.rtot = (uint32_t*)take(4 * (size_t)V * ty);
     w.rbase = (int64_t*)take(8 * (size_t)V * ty);
     w.tc = (uint32_t*)take(4 * (size_t)V * B.G * T);
     w.toff = (uint32_t*)take(4 * (size_t)V * B.G * T);
-    w.tbase = (int64_t*)take(8 * (size_t)V * T);
+    w.trel = (uint32_t*)take(4 * (size_t)V * T);
     w.bytes = o;
     return w;
 }
@@ -875,26 +840,20 @@ potr_status sweep(const uint32_t* kin, uint32_t* kout, const uint32_t* vin, uint
     return check_launch("k_sweep");
 }
 
-// rows per band of the group counts' difference arrays, and their LDS bytes
+// rows per band of the group counts' difference array, and its LDS bytes
 int gc_band(int tiles_x) {
     const int rows = (int)(kGcLds / (4 * (size_t)(tiles_x + 1))) - 1;
     return std::max(1, std::min(kGcBand, rows));
 }
-size_t gc_lds(int band, int tiles_x) { return (size_t)(band + 1) * (tiles_x + 1 + kGroup) * 4; }
+size_t gc_lds(int band, int tiles_x) { return (size_t)(band + 1) * (tiles_x + 1) * 4; }
 
-size_t cols_lds(const Bins& B) {
-    return ((size_t)(kWaves + 2) * B.tiles_x + (size_t)kThreads * kColItems) * 4 + (size_t)kThreads * kColItems * 2;
+// LDS of the placement: per-wave counters, cursors and bases per tile, a pass
+// of pair words / ids and tile x, and a round's runs (start, first tile, rank)
+size_t place_lds(const Bins& B) {
+    return ((size_t)(kWaves + 2) * B.tiles_x + (size_t)kThreads * kColItems + kPlRound) * 4 +
+           ((size_t)kThreads * kColItems + 2 * kPlRound) * 2;
 }
 
-// column scan of tab[v][R][cols] into out[v][R_out][cols] starting at base[v][cols]
-potr_status col_scan_offsets(const uint32_t* tab, const uint32_t* segsum, const int64_t* base, int32_t R,
-                             int32_t cols, int32_t seglen, int32_t nseg, int32_t V, int32_t R_out,
-                             const int64_t* n_pairs, int64_t capacity, uint32_t* out, hipStream_t s) {
-    const dim3 g((unsigned)ceil_div(cols, 256), nseg, V);
-    hipLaunchKernelGGL(k_seg_offsets, g, dim3(256), 0, s, tab, segsum, base, R, cols, seglen, nseg, R_out, n_pairs,
-                       capacity, out);
-    return check_launch("k_seg_offsets");
-}
 
 }  // namespace
 
@@ -902,7 +861,9 @@ size_t bin_workspace_bytes(int64_t N, int32_t V, int32_t tiles_x, int32_t tiles_
     return bin_layout(N, V, tiles_x, tiles_y, nullptr).bytes;
 }
 
-size_t sort_workspace_bytes(int64_t capacity) { return align_up((size_t)(capacity > 0 ? capacity : 1) * 4 + 256); }
+// The placement stages nothing in global memory; the workspace stays in the ABI
+// as a placeholder of one aligned block.
+size_t sort_workspace_bytes(int64_t) { return align_up(256); }
 
 potr_status launch_bin(int64_t N, int32_t V, const potr_camera& cam0, const potr_config& cfg,
                        const potr_proj* proj, void* ws, uint32_t* order, int64_t* n_pairs, hipStream_t s) {
@@ -936,28 +897,23 @@ potr_status launch_bin(int64_t N, int32_t V, const potr_camera& cam0, const potr
         }
         const int band = gc_band(txs);
         hipLaunchKernelGGL(k_count, dim3(B.G, V), dim3(kGcThreads), gc_lds(band, txs), s, (const uint32_t*)order,
-                           (const uint2*)w.crect, B, band, w.srect, w.rcx, w.gsum, w.tc, w.segt);
+                           (const uint2*)w.crect, B, band, w.srect, w.gsum, w.tc, w.segt);
         st = check_launch("k_count");
         if (st != POTR_OK) return st;
-        hipLaunchKernelGGL(k_group_prefix, dim3(tys, V), dim3(64), 0, s, w.gsum, B, w.rtot);
-        st = check_launch("k_group_prefix");
-        if (st != POTR_OK) return st;
-    } else {
-        // no splats: every row total is 0
-        hipLaunchKernelGGL(k_clear, dim3(1), dim3(256), 0, s, (uint64_t*)w.rtot, ((int64_t)V * tys + 1) / 2);
-        st = check_launch("k_clear");
-        if (st != POTR_OK) return st;
     }
-    // row bases over (view, row) and the pair count
+    // tile starts within their rows and row totals, then row bases over
+    // (view, row), the pair count, and every group's first position per tile
+    hipLaunchKernelGGL(k_tile_bases, dim3(tys, V), dim3(256), 0, s, w.segt, B, w.trel, w.rtot);
+    st = check_launch("k_tile_bases");
+    if (st != POTR_OK) return st;
     hipLaunchKernelGGL(k_row_bases, dim3(1), dim3(1024), 0, s, (const uint32_t*)w.rtot, B, w.rbase,
                        (const uint32_t*)w.ctl.fault, n_pairs);
     st = check_launch("k_row_bases");
-    if (st != POTR_OK) return st;
-    // tiles: bases (one scan over (view, tile)), each group's first position per tile
-    hipLaunchKernelGGL(k_tile_bases, dim3(tys, V), dim3(256), 0, s, w.segt, (const int64_t*)w.rbase, B, w.tbase);
-    st = check_launch("k_tile_bases");
     if (st != POTR_OK || N == 0) return st;
-    return col_scan_offsets(w.tc, w.segt, w.tbase, B.G, B.T, B.seg_g, B.nseg_g, V, B.G, n_pairs, -1, w.toff, s);
+    hipLaunchKernelGGL(k_tile_offsets, dim3((unsigned)ceil_div(B.T, 256), B.nseg_g, V), dim3(256), 0, s,
+                       (const uint32_t*)w.tc, (const uint32_t*)w.segt, (const int64_t*)w.rbase,
+                       (const uint32_t*)w.trel, B, w.toff);
+    return check_launch("k_tile_offsets");
 }
 
 potr_status launch_sort(int64_t N, int32_t V, const potr_camera& cam0, const potr_config& cfg,
@@ -967,8 +923,7 @@ potr_status launch_sort(int64_t N, int32_t V, const potr_camera& cam0, const pot
     const int txs = tiles_x(cam0, cfg), tys = tiles_y(cam0, cfg);
     BinWs w = bin_layout(N, V, txs, tys, (char*)ws);
     const Bins B = bins_of(N, V, txs, tys);
-    uint32_t* stage = (uint32_t*)sort_ws;
-    potr_status st = POTR_OK;
+    (void)sort_ws;   // nothing is staged in global memory
     if (N == 0) {
         // no pairs: every tile range is [0, 0)
         const int64_t words = (int64_t)V * B.T;
@@ -976,51 +931,46 @@ potr_status launch_sort(int64_t N, int32_t V, const potr_camera& cam0, const pot
                            dim3(256), 0, s, (uint64_t*)tile_ranges, words);
         return check_launch("k_clear");
     }
-    // level 1: pairs into their rows (and the tile ranges)
-    hipLaunchKernelGGL(k_place_rows, dim3(B.C, V), dim3(64), (size_t)tys * 4, s, (const uint2*)w.srect,
-                       (const int64_t*)w.rbase, (const uint32_t*)w.gsum, (const uint32_t*)w.rcx,
-                       (const int64_t*)w.tbase, B, n_pairs, capacity, stage, tile_ranges);
-    st = check_launch("k_place_rows");
-    if (st != POTR_OK) return st;
-    // level 2: each row segment of a group to its tiles
-    const dim3 gl2(B.G, tys, V);
-    const size_t l2 = cols_lds(B);
-    const int64_t* rb = w.rbase;
-    const uint32_t* gp = w.gsum;
-    const uint32_t* rt = w.rtot;
+    // every (group, row) segment to its tiles (and the tile ranges)
+    const dim3 gp(B.G, tys, V);
+    const size_t lds = place_lds(B);
+    const uint2* sr = w.srect;
+    const uint32_t* gs = w.gsum;
     const uint32_t* to = w.toff;
-    const uint32_t* stg = stage;
+    const int64_t* rb = w.rbase;
+    const uint32_t* tr = w.trel;
+    const uint32_t* rt = w.rtot;
     switch (B.xbits) {
         case 1: case 2: case 3: case 4: case 5:
-            hipLaunchKernelGGL(k_place_cols<5>, gl2, dim3(kThreads), l2, s, rb, gp, rt, to, B, n_pairs, capacity, stg, order,
-                               sorted_ids);
+            hipLaunchKernelGGL(k_place<5>, gp, dim3(kThreads), lds, s, sr, gs, to, rb, tr, rt, B, n_pairs, capacity, order,
+                               sorted_ids, tile_ranges);
             break;
         case 6:
-            hipLaunchKernelGGL(k_place_cols<6>, gl2, dim3(kThreads), l2, s, rb, gp, rt, to, B, n_pairs, capacity, stg, order,
-                               sorted_ids);
+            hipLaunchKernelGGL(k_place<6>, gp, dim3(kThreads), lds, s, sr, gs, to, rb, tr, rt, B, n_pairs, capacity, order,
+                               sorted_ids, tile_ranges);
             break;
         case 7:
-            hipLaunchKernelGGL(k_place_cols<7>, gl2, dim3(kThreads), l2, s, rb, gp, rt, to, B, n_pairs, capacity, stg, order,
-                               sorted_ids);
+            hipLaunchKernelGGL(k_place<7>, gp, dim3(kThreads), lds, s, sr, gs, to, rb, tr, rt, B, n_pairs, capacity, order,
+                               sorted_ids, tile_ranges);
             break;
         case 8:
-            hipLaunchKernelGGL(k_place_cols<8>, gl2, dim3(kThreads), l2, s, rb, gp, rt, to, B, n_pairs, capacity, stg, order,
-                               sorted_ids);
+            hipLaunchKernelGGL(k_place<8>, gp, dim3(kThreads), lds, s, sr, gs, to, rb, tr, rt, B, n_pairs, capacity, order,
+                               sorted_ids, tile_ranges);
             break;
         case 9:
-            hipLaunchKernelGGL(k_place_cols<9>, gl2, dim3(kThreads), l2, s, rb, gp, rt, to, B, n_pairs, capacity, stg, order,
-                               sorted_ids);
+            hipLaunchKernelGGL(k_place<9>, gp, dim3(kThreads), lds, s, sr, gs, to, rb, tr, rt, B, n_pairs, capacity, order,
+                               sorted_ids, tile_ranges);
             break;
         case 10:
-            hipLaunchKernelGGL(k_place_cols<10>, gl2, dim3(kThreads), l2, s, rb, gp, rt, to, B, n_pairs, capacity, stg, order,
-                               sorted_ids);
+            hipLaunchKernelGGL(k_place<10>, gp, dim3(kThreads), lds, s, sr, gs, to, rb, tr, rt, B, n_pairs, capacity, order,
+                               sorted_ids, tile_ranges);
             break;
         default:
-            hipLaunchKernelGGL(k_place_cols<11>, gl2, dim3(kThreads), l2, s, rb, gp, rt, to, B, n_pairs, capacity, stg, order,
-                               sorted_ids);
+            hipLaunchKernelGGL(k_place<11>, gp, dim3(kThreads), lds, s, sr, gs, to, rb, tr, rt, B, n_pairs, capacity, order,
+                               sorted_ids, tile_ranges);
             break;
     }
-    return check_launch("k_place_cols");
+    return check_launch("k_place");
 }
 
 }  // namespace potr
