@@ -12,6 +12,25 @@ __device__ inline float dpp_read(float v) {
     return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROW_MASK, 0xf, ROW_MASK == 0xf));
 }
 
+template <int CTRL, int ROW_MASK = 0xf>
+__device__ inline uint32_t dpp_read_u32(uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, ROW_MASK, 0xf, ROW_MASK == 0xf);
+}
+
+// Inclusive prefix sum over the 64 lanes (lane l gets the sum of lanes 0..l):
+// shifts by 1, 2, 4, 8 within each row of 16, then row 0's total into row 1
+// and row 2's into row 3 (row_bcast:15), then lane 31's into rows 2 and 3
+// (row_bcast:31). Six VALU operations, no LDS.
+__device__ inline uint32_t wave_incl_scan(uint32_t v) {
+    v += dpp_read_u32<0x111>(v);        // row_shr:1
+    v += dpp_read_u32<0x112>(v);        // row_shr:2
+    v += dpp_read_u32<0x114>(v);        // row_shr:4
+    v += dpp_read_u32<0x118>(v);        // row_shr:8
+    v += dpp_read_u32<0x142, 0xa>(v);   // row_bcast:15
+    v += dpp_read_u32<0x143, 0xc>(v);   // row_bcast:31
+    return v;
+}
+
 // Sum over the 64 lanes, returned in every lane:
 // pairs (xor 1, xor 2) -> 8-lane mirror -> 16-lane mirror -> row 0 into row 1
 // and row 2 into row 3 -> rows 0..1 into rows 2..3; lane 63 then holds the total.

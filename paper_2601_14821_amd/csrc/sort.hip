@@ -23,6 +23,7 @@
 #include <algorithm>
 
 #include "common.h"
+#include "dpp.h"
 
 namespace potr {
 namespace {
@@ -126,12 +127,7 @@ __device__ inline void match_rank(uint32_t d, bool ok, uint32_t& below, uint32_t
 template <int NT>
 __device__ inline uint32_t block_excl_scan(uint32_t x, uint32_t* wsum) {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    uint32_t inc = x;
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        const uint32_t y = __shfl_up(inc, d, 64);
-        if (lane >= d) inc += y;
-    }
+    const uint32_t inc = wave_incl_scan(x);
     if (lane == 63) wsum[w] = inc;
     __syncthreads();
     uint32_t pre = 0;
@@ -427,12 +423,7 @@ __global__ __launch_bounds__(256) void k_tile_bases(uint32_t* __restrict__ segt,
         const int x = x0 + threadIdx.x;
         uint32_t c = 0;
         if (x < B.tiles_x) c = seg_prefix(segt + (int64_t)v * B.nseg_g * B.T + (int64_t)y * B.tiles_x + x, B.T, B.nseg_g);
-        uint32_t inc = c;
-#pragma unroll
-        for (int d = 1; d < 64; d <<= 1) {
-            const uint32_t u = __shfl_up(inc, d, 64);
-            if (lane >= d) inc += u;
-        }
+        const uint32_t inc = wave_incl_scan(c);
         if (lane == 63) wsum[w] = inc;
         __syncthreads();
         uint32_t pre = run, all = 0;
@@ -503,12 +494,7 @@ __global__ __launch_bounds__(kGcThreads) void k_count(const uint32_t* __restrict
         // down the columns (a wave per column, a lane per row)
         for (int x = w; x < TX; x += NW) {
             const uint32_t val = lane < H ? d[lane * W1 + x] : 0u;
-            uint32_t inc = val;
-#pragma unroll
-            for (int o = 1; o < 64; o <<= 1) {
-                const uint32_t u = __shfl_up(inc, o, 64);
-                if (lane >= o) inc += u;
-            }
+            const uint32_t inc = wave_incl_scan(val);
             if (lane < H) d[lane * W1 + x] = inc;
         }
         __syncthreads();
@@ -519,12 +505,7 @@ __global__ __launch_bounds__(kGcThreads) void k_count(const uint32_t* __restrict
             for (int xc = 0; xc < TX; xc += 64) {
                 const int x = xc + lane;
                 const uint32_t val = x < TX ? d[y * W1 + x] : 0u;
-                uint32_t inc = val;
-#pragma unroll
-                for (int o = 1; o < 64; o <<= 1) {
-                    const uint32_t u = __shfl_up(inc, o, 64);
-                    if (lane >= o) inc += u;
-                }
+                const uint32_t inc = wave_incl_scan(val);
                 const uint32_t c = carry + inc;   // the tile's count
                 if (x < TX) {
                     const int64_t t = (int64_t)(yb0 + y) * TX + x;
@@ -532,11 +513,10 @@ __global__ __launch_bounds__(kGcThreads) void k_count(const uint32_t* __restrict
                     if (c) atomicAdd(sg + t, c);
                     rowsum += c;
                 }
-                carry += __shfl(inc, 63, 64);
+                carry += (uint32_t)__builtin_amdgcn_readlane((int)inc, 63);
             }
-#pragma unroll
-            for (int o = 32; o >= 1; o >>= 1) rowsum += __shfl_xor(rowsum, o, 64);
-            if (lane == 0) gsum[((int64_t)v * B.tiles_y + yb0 + y) * B.G + g] = rowsum;
+            rowsum = wave_incl_scan(rowsum);   // lane 63: the row's total
+            if (lane == 63) gsum[((int64_t)v * B.tiles_y + yb0 + y) * B.G + g] = rowsum;
         }
         __syncthreads();
     }
@@ -603,7 +583,82 @@ __global__ __launch_bounds__(256) void k_place(const uint2* __restrict__ srect, 
     for (int x = threadIdx.x; x < TX; x += kThreads) cur[x] = orow[x];
     const int ns = (int)min((int64_t)kGroupRanks, B.N - (int64_t)g * kGroupRanks);
     const int per = (TX + kThreads - 1) / kThreads;   // counters per thread in the block scan
-    uint32_t placed = 0;
+    uint32_t placed = 0, expanded = 0, fill = 0;
+    // one pass over the pair words s_id[0, cntb): rank by tile x, sort in LDS,
+    // store each tile's run at its cursor and advance the cursors
+    auto place_pass = [&](const uint32_t cntb) {
+        for (int t = threadIdx.x; t < kWaves * TX; t += kThreads) wcnt[t] = 0;
+        __syncthreads();
+        uint32_t key[kColItems], val[kColItems], rnk[kColItems];
+#pragma unroll
+        for (int k = 0; k < kColItems; ++k) {
+            const uint32_t e = (uint32_t)(w * 64 * kColItems + k * 64 + lane);
+            key[k] = s_id[min(e, cntb - 1)];
+        }
+        // all id gathers first, without branches, so that they stay in flight together
+#pragma unroll
+        for (int k = 0; k < kColItems; ++k) {
+            val[k] = gorder[key[k] & (kGroupRanks - 1)];   // the splat id
+            key[k] >>= kRankBits;
+        }
+#pragma unroll
+        for (int k = 0; k < kColItems; ++k) {
+            const uint32_t e = (uint32_t)(w * 64 * kColItems + k * 64 + lane);
+            const bool ok = e < cntb;
+            const uint32_t d = ok ? key[k] : 0u;
+            key[k] = d;
+            uint32_t below, c;
+            match_rank<XBITS>(d, ok, below, c);
+            uint32_t r = 0;
+            if (ok) r = wcnt[w * TX + d];
+            __builtin_amdgcn_wave_barrier();
+            if (ok && below == 0) wcnt[w * TX + d] = r + c;
+            __builtin_amdgcn_wave_barrier();
+            rnk[k] = ok ? r + below : 0xffffffffu;
+        }
+        __syncthreads();
+        // per x: exclusive prefix over waves, block count; then the block scan of the counts
+        uint32_t local[8];
+        uint32_t mine = 0;
+        for (int j = 0; j < per; ++j) {
+            const int x = threadIdx.x * per + j;
+            uint32_t run = 0;
+            if (x < TX)
+                for (int ww = 0; ww < kWaves; ++ww) {
+                    const uint32_t c = wcnt[ww * TX + x];
+                    wcnt[ww * TX + x] = run;
+                    run += c;
+                }
+            local[j] = run;
+            mine += run;
+        }
+        uint32_t pre = block_excl_scan<kThreads>(mine, wsum);
+        for (int j = 0; j < per; ++j) {
+            const int x = threadIdx.x * per + j;
+            if (x < TX) boff[x] = pre;
+            pre += local[j];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < kColItems; ++k) {
+            if (rnk[k] == 0xffffffffu) continue;
+            const uint32_t p = boff[key[k]] + wcnt[w * TX + key[k]] + rnk[k];
+            s_id[p] = val[k];
+            s_x[p] = (uint16_t)key[k];
+        }
+        __syncthreads();
+        for (uint32_t i = threadIdx.x; i < cntb; i += kThreads) {
+            const uint32_t x = s_x[i];
+            ids[cur[x] + (i - boff[x])] = s_id[i];
+        }
+        __syncthreads();
+        // advance the cursors past this pass's runs
+        for (int x = threadIdx.x; x < TX; x += kThreads) {
+            const uint32_t end = (x + 1 < TX) ? boff[x + 1] : cntb;
+            cur[x] += end - boff[x];
+        }
+        __syncthreads();
+    };
     for (int h0 = 0; h0 < ns; h0 += kPlRound) {
         const int nh = min(kPlRound, ns - h0);
         // lane l of wave w holds the round's ranks 512 w + 64 k + l (k < kPlSlots)
@@ -622,12 +677,7 @@ __global__ __launch_bounds__(256) void k_place(const uint2* __restrict__ srect, 
         uint32_t carry = 0, ccnt = 0, ofs[kPlSlots], pos[kPlSlots];
 #pragma unroll
         for (int k = 0; k < kPlSlots; ++k) {
-            uint32_t inc = wd[k];
-#pragma unroll
-            for (int o = 1; o < 64; o <<= 1) {
-                const uint32_t u = __shfl_up(inc, o, 64);
-                if (lane >= o) inc += u;
-            }
+            const uint32_t inc = wave_incl_scan(wd[k]);
             ofs[k] = carry + inc - wd[k];
             carry += (uint32_t)__builtin_amdgcn_readlane((int32_t)inc, 63);
             const uint64_t cb = __ballot(wd[k] != 0u);
@@ -662,102 +712,38 @@ __global__ __launch_bounds__(256) void k_place(const uint2* __restrict__ srect, 
         __syncthreads();
         if (placed + tot > len) return;   // cannot happen: the counts come from the same rects
         placed += tot;
-        for (uint32_t b0 = 0; b0 < tot; b0 += kThreads * kColItems) {
-            const uint32_t cntb = min(tot - b0, (uint32_t)(kThreads * kColItems));
-            // expand pairs i0 .. i0 + kPlPer - 1 of the pass
-            const uint32_t i0 = threadIdx.x * kPlPer;
-            if (i0 < cntb) {
-                const uint32_t q0 = b0 + i0;
-                int lo = 0, hi = ncov - 1;   // last run starting at or before q0
+        // expand the round's pairs into the pass buffer behind those already there
+        for (uint32_t q0 = 0; q0 < tot;) {
+            const uint32_t take = min(tot - q0, (uint32_t)(kThreads * kColItems) - fill);
+            const uint32_t j0 = threadIdx.x * kPlPer;   // this thread's pairs j0 .. j0 + kPlPer - 1
+            if (j0 < take) {
+                const uint32_t qa = q0 + j0;
+                int lo = 0, hi = ncov - 1;   // last run starting at or before qa
                 while (lo < hi) {
                     const int mid = (lo + hi + 1) >> 1;
-                    if (s_off[mid] <= q0) lo = mid;
+                    if (s_off[mid] <= qa) lo = mid;
                     else hi = mid - 1;
                 }
                 int r = lo;
                 uint32_t o = s_off[r], end = r + 1 < ncov ? s_off[r + 1] : tot;
-                const uint32_t i1 = min(i0 + kPlPer, cntb);
-                for (uint32_t i = i0; i < i1; ++i) {
-                    const uint32_t q = b0 + i;
+                const uint32_t j1 = min(j0 + kPlPer, take);
+                for (uint32_t j = j0; j < j1; ++j) {
+                    const uint32_t q = q0 + j;
                     if (q >= end) {   // runs are never empty: q is in the next one
                         ++r;
                         o = end;
                         end = r + 1 < ncov ? s_off[r + 1] : tot;
                     }
-                    s_id[i] = (((uint32_t)s_x0[r] + (q - o)) << kRankBits) | (uint32_t)(h0 + s_rk[r]);
+                    s_id[fill + j] = (((uint32_t)s_x0[r] + (q - o)) << kRankBits) | (uint32_t)(h0 + s_rk[r]);
                 }
             }
-            for (int t = threadIdx.x; t < kWaves * TX; t += kThreads) wcnt[t] = 0;
-            __syncthreads();
-            uint32_t key[kColItems], val[kColItems], rnk[kColItems];
-#pragma unroll
-            for (int k = 0; k < kColItems; ++k) {
-                const uint32_t e = (uint32_t)(w * 64 * kColItems + k * 64 + lane);
-                key[k] = s_id[min(e, cntb - 1)];
+            fill += take;
+            q0 += take;
+            expanded += take;
+            if (fill == (uint32_t)(kThreads * kColItems) || expanded == len) {
+                place_pass(fill);
+                fill = 0;
             }
-            // all id gathers first, without branches, so that they stay in flight together
-#pragma unroll
-            for (int k = 0; k < kColItems; ++k) {
-                val[k] = gorder[key[k] & (kGroupRanks - 1)];   // the splat id
-                key[k] >>= kRankBits;
-            }
-#pragma unroll
-            for (int k = 0; k < kColItems; ++k) {
-                const uint32_t e = (uint32_t)(w * 64 * kColItems + k * 64 + lane);
-                const bool ok = e < cntb;
-                const uint32_t d = ok ? key[k] : 0u;
-                key[k] = d;
-                uint32_t below, c;
-                match_rank<XBITS>(d, ok, below, c);
-                uint32_t r = 0;
-                if (ok) r = wcnt[w * TX + d];
-                __builtin_amdgcn_wave_barrier();
-                if (ok && below == 0) wcnt[w * TX + d] = r + c;
-                __builtin_amdgcn_wave_barrier();
-                rnk[k] = ok ? r + below : 0xffffffffu;
-            }
-            __syncthreads();
-            // per x: exclusive prefix over waves, block count; then the block scan of the counts
-            uint32_t local[8];
-            uint32_t mine = 0;
-            for (int j = 0; j < per; ++j) {
-                const int x = threadIdx.x * per + j;
-                uint32_t run = 0;
-                if (x < TX)
-                    for (int ww = 0; ww < kWaves; ++ww) {
-                        const uint32_t c = wcnt[ww * TX + x];
-                        wcnt[ww * TX + x] = run;
-                        run += c;
-                    }
-                local[j] = run;
-                mine += run;
-            }
-            uint32_t pre = block_excl_scan<kThreads>(mine, wsum);
-            for (int j = 0; j < per; ++j) {
-                const int x = threadIdx.x * per + j;
-                if (x < TX) boff[x] = pre;
-                pre += local[j];
-            }
-            __syncthreads();
-#pragma unroll
-            for (int k = 0; k < kColItems; ++k) {
-                if (rnk[k] == 0xffffffffu) continue;
-                const uint32_t p = boff[key[k]] + wcnt[w * TX + key[k]] + rnk[k];
-                s_id[p] = val[k];
-                s_x[p] = (uint16_t)key[k];
-            }
-            __syncthreads();
-            for (uint32_t i = threadIdx.x; i < cntb; i += kThreads) {
-                const uint32_t x = s_x[i];
-                ids[cur[x] + (i - boff[x])] = s_id[i];
-            }
-            __syncthreads();
-            // advance the cursors past this pass's runs
-            for (int x = threadIdx.x; x < TX; x += kThreads) {
-                const uint32_t end = (x + 1 < TX) ? boff[x + 1] : cntb;
-                cur[x] += end - boff[x];
-            }
-            __syncthreads();
         }
         __syncthreads();   // the next round rewrites wsum and the run offsets
     }
