@@ -281,7 +281,7 @@ __global__ __launch_bounds__(kSwThreads) void k_sweep(const uint32_t* __restrict
             st_put(st, st_word(P.tag, kStInc, run));
         } else {
             st_put(st + b * radix, st_word(P.tag, kStAgg, run));
-            excl = look_back<8>(st, b, (int)radix, P.tag, P.fault);
+            excl = look_back<4>(st, b, (int)radix, P.tag, P.fault);
             st_put(st + b * radix, st_word(P.tag, kStInc, excl + run));
         }
         goff[d] = dbase + (uint32_t)excl;
