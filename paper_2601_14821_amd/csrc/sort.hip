@@ -559,7 +559,12 @@ __global__ __launch_bounds__(256) void k_place(const uint2* __restrict__ srect, 
     uint16_t* s_rk = s_x0 + kPlRound;                  // [kPlRound]: its rank within the round
     __shared__ uint32_t wsum[kWaves];
     __shared__ uint32_t wcov[kWaves];
-    const int g = blockIdx.x, y = blockIdx.y, v = blockIdx.z;
+    // workgroups go to the 8 XCDs round-robin by linear id: block b runs on XCD
+    // b % 8, and XCD x takes the groups x, x + 8, ... with all their rows, so a
+    // group's rects, ids and offsets are read through one XCD's L2
+    const int xcd = (int)(blockIdx.x & 7u), m = (int)(blockIdx.x >> 3), v = blockIdx.y;
+    const int j = m / B.tiles_y, y = m - j * B.tiles_y, g = xcd + 8 * j;
+    if (g >= B.G) return;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int64_t n = *n_pairs;
     const bool fits = n >= 0 && n <= capacity;
@@ -601,8 +606,15 @@ __global__ __launch_bounds__(256) void k_place(const uint2* __restrict__ srect, 
             val[k] = gorder[key[k] & (kGroupRanks - 1)];   // the splat id
             key[k] >>= kRankBits;
         }
+        // slots of this wave that hold pairs of the pass (the rest are skipped)
+        const uint32_t wb0 = (uint32_t)(w * 64 * kColItems);
+        const int kn = cntb > wb0 ? (int)min((uint32_t)kColItems, (cntb - wb0 + 63) / 64) : 0;
 #pragma unroll
         for (int k = 0; k < kColItems; ++k) {
+            if (k >= kn) {
+                rnk[k] = 0xffffffffu;
+                continue;
+            }
             const uint32_t e = (uint32_t)(w * 64 * kColItems + k * 64 + lane);
             const bool ok = e < cntb;
             const uint32_t d = ok ? key[k] : 0u;
@@ -918,7 +930,7 @@ potr_status launch_sort(int64_t N, int32_t V, const potr_camera& cam0, const pot
         return check_launch("k_clear");
     }
     // every (group, row) segment to its tiles (and the tile ranges)
-    const dim3 gp(B.G, tys, V);
+    const dim3 gp((unsigned)(8 * ceil_div(B.G, 8) * tys), V);   // see the XCD mapping in k_place
     const size_t lds = place_lds(B);
     const uint2* sr = w.srect;
     const uint32_t* gs = w.gsum;
