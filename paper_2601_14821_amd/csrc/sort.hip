@@ -2,13 +2,13 @@
 // ordered by approximate depth).
 //
 // potr_bin orders each view's splats by depth key (a stable LSD radix sort of
-// the N 32-bit keys, so ties keep splat id order) and counts, for every chunk
-// of 64 consecutive depth ranks and every tile row, the pairs the chunk's
-// splats make there; from those counts come the number of pairs per row and in
-// total. potr_sort places every (tile, splat) pair in two levels (see the
-// pair placement section below) so that each tile's list is in (depth key,
-// splat id) order, the order a sort of (tile, depth, id) keys would give,
-// without sorting per pair.
+// the N 32-bit keys, so ties keep splat id order) and counts, for every group
+// of 4096 consecutive depth ranks, the pairs its splats make in every tile and
+// every tile row; from those counts come every tile's start and the number of
+// pairs. potr_sort places every (tile, splat) pair (see the pair placement
+// section below) so that each tile's list is in (depth key, splat id) order,
+// the order a sort of (tile, depth, id) keys would give, without sorting per
+// pair.
 //
 // Depth radix passes are one kernel each: a block of 1024 threads x 4 items
 // ranks its keys per digit with 64-lane ballots (stable order: wave, item,
@@ -332,7 +332,7 @@ struct Bins {
 };
 constexpr int kGroupRanks = 4096;             // depth ranks per group
 constexpr int kMaxSegs = 32;                  // at most this many segments per column scan
-constexpr int kColItems = 8;                  // level 2: items per thread (2048 per block pass)
+constexpr int kColItems = 8;                  // placement: pairs per thread (2048 per block pass)
 // A pair in LDS is one word: tile x << kRankBits | rank of the splat within its group.
 constexpr int kRankBits = 12;
 static_assert(kGroupRanks == 1 << kRankBits, "a group's ranks fill the rank field");
