@@ -169,9 +169,10 @@ struct Pass {
 // Depth keys, rects and the digit totals of every pass, per view, in one read
 // of the records (the depth and the rect sit in the same 16 bytes of a record).
 // The keys go to keys_out, the rects to rect_out, packed as the two words
-// (x0 | x1 << 16, y0 | y1 << 16) for tiles [x0, x1) x [y0, y1). Large blocks
-// keep the global atomics that merge the block histograms few.
-constexpr int kHistThreads = 1024;
+// (x0 | x1 << 16, y0 | y1 << 16) for tiles [x0, x1) x [y0, y1). Eight records
+// per thread keep the global atomics that merge the block histograms few while
+// leaving enough blocks to keep loads in flight.
+constexpr int kHistThreads = 256;
 constexpr int kHistItems = 8;
 
 __global__ __launch_bounds__(kHistThreads) void k_hist(const potr_proj* __restrict__ proj, int64_t N,
