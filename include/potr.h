@@ -299,7 +299,7 @@ POTR_API potr_status potr_batch_overflow(potr_batch b, int32_t* n_overflowed, vo
 POTR_API potr_status potr_batch_destroy(potr_batch b);
 
 /* potr_autotune: times every tile shape (16x16, 8x8, 32x8) with every LDS batch
- * (64, 128, 256, 512) on the given jobs (`reps` timed runs each, after one
+ * (64, 128, 320, 512) on the given jobs (`reps` timed runs each, after one
  * warm-up) and writes the fastest tile_w, tile_h, lds_batch into *inout. Uses
  * temporary device memory and scratch scores (the jobs' outputs are untouched);
  * synchronises. Optional: best_ms, and the tried configs with their times

@@ -318,7 +318,7 @@ extern "C" potr_status potr_autotune(const potr_job* jobs, int32_t n_jobs, potr_
         J.importance = nullptr;
     }
     const int shapes[3][2] = {{16, 16}, {8, 8}, {32, 8}};
-    const int batches[4] = {64, 128, 256, 512};
+    const int batches[4] = {64, 128, 320, 512};
     double best = 1e300;
     potr_config best_cfg = *inout;
     int32_t k = 0;

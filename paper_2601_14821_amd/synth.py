@@ -214,7 +214,7 @@ class RenderSettings:
     """
     tile_w: int = 16
     tile_h: int = 16
-    lds_batch: int = 256
+    lds_batch: int = 320
     eps2d: float = 0.3
     near: float = 0.2
     jclamp: float = 1.3
