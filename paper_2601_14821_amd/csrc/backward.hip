@@ -12,6 +12,8 @@
 //
 // k_project_bwd chains those to the splat parameters in FP64, one thread per
 // splat, looping over the views of the call.
+#include <type_traits>
+
 #include "common.h"
 #include "dpp.h"
 #include "raster_eval.h"
@@ -179,44 +181,66 @@ __global__ __launch_bounds__(TW * TH) void k_blend_bwd(int64_t N, int32_t W, int
 }
 
 // ---------------------------------------------------------------- projection backward (FP64)
-// gradient of the Cartesian real SH basis w.r.t. the (unnormalised) direction
-// components; Y as in k_project
-__device__ inline void sh_basis_grad(double x, double y, double z, int degree, double* Y, double* Gx, double* Gy,
-                                     double* Gz) {
-    for (int k = 0; k < 16; ++k) Y[k] = Gx[k] = Gy[k] = Gz[k] = 0.0;
-    Y[0] = 0.28209479177387814;
-    if (degree < 1) return;
-    const double c1 = 0.4886025119029199;
-    Y[1] = -c1 * y; Gy[1] = -c1;
-    Y[2] = c1 * z;  Gz[2] = c1;
-    Y[3] = -c1 * x; Gx[3] = -c1;
-    if (degree < 2) return;
-    const double xx = x * x, yy = y * y, zz = z * z;
-    const double a2 = 1.0925484305920792, b2 = 0.31539156525252005, c2 = 0.5462742152960396;
-    Y[4] = a2 * x * y;                 Gx[4] = a2 * y; Gy[4] = a2 * x;
-    Y[5] = -a2 * y * z;                Gy[5] = -a2 * z; Gz[5] = -a2 * y;
-    Y[6] = b2 * (2.0 * zz - xx - yy);  Gx[6] = -2.0 * b2 * x; Gy[6] = -2.0 * b2 * y; Gz[6] = 4.0 * b2 * z;
-    Y[7] = -a2 * x * z;                Gx[7] = -a2 * z; Gz[7] = -a2 * x;
-    Y[8] = c2 * (xx - yy);             Gx[8] = 2.0 * c2 * x; Gy[8] = -2.0 * c2 * y;
-    if (degree < 3) return;
-    const double a3 = 0.5900435899266435, b3 = 2.890611442640554, c3 = 0.4570457994644658,
-                 d3 = 0.3731763325901154, e3 = 1.445305721320277;
-    Y[9] = -a3 * y * (3.0 * xx - yy);
-    Gx[9] = -6.0 * a3 * x * y; Gy[9] = -3.0 * a3 * (xx - yy);
-    Y[10] = b3 * x * y * z;
-    Gx[10] = b3 * y * z; Gy[10] = b3 * x * z; Gz[10] = b3 * x * y;
-    Y[11] = -c3 * y * (4.0 * zz - xx - yy);
-    Gx[11] = 2.0 * c3 * x * y; Gy[11] = -c3 * (4.0 * zz - xx - 3.0 * yy); Gz[11] = -8.0 * c3 * y * z;
-    Y[12] = d3 * z * (2.0 * zz - 3.0 * xx - 3.0 * yy);
-    Gx[12] = -6.0 * d3 * x * z; Gy[12] = -6.0 * d3 * y * z; Gz[12] = d3 * (6.0 * zz - 3.0 * xx - 3.0 * yy);
-    Y[13] = -c3 * x * (4.0 * zz - xx - yy);
-    Gx[13] = -c3 * (4.0 * zz - 3.0 * xx - yy); Gy[13] = 2.0 * c3 * x * y; Gz[13] = -8.0 * c3 * x * z;
-    Y[14] = e3 * z * (xx - yy);
-    Gx[14] = 2.0 * e3 * x * z; Gy[14] = -2.0 * e3 * y * z; Gz[14] = e3 * (xx - yy);
-    Y[15] = -a3 * x * (xx - 3.0 * yy);
-    Gx[15] = -3.0 * a3 * (xx - yy); Gy[15] = 6.0 * a3 * x * y;
+// Term K of the Cartesian real SH basis (Y as in k_project) and its gradient
+// with respect to the direction components, as compile-time expressions so
+// that a fully unrolled loop over K keeps everything in registers.
+template <int K>
+__device__ inline void sh_term(double x, double y, double z, double& Y, double& Gx, double& Gy, double& Gz) {
+    constexpr double c1 = 0.4886025119029199;
+    constexpr double a2 = 1.0925484305920792, b2 = 0.31539156525252005, c2 = 0.5462742152960396;
+    constexpr double a3 = 0.5900435899266435, b3 = 2.890611442640554, c3 = 0.4570457994644658,
+                     d3 = 0.3731763325901154, e3 = 1.445305721320277;
+    Gx = Gy = Gz = 0.0;
+    if constexpr (K == 0) {
+        Y = 0.28209479177387814;
+    } else if constexpr (K == 1) {
+        Y = -c1 * y; Gy = -c1;
+    } else if constexpr (K == 2) {
+        Y = c1 * z; Gz = c1;
+    } else if constexpr (K == 3) {
+        Y = -c1 * x; Gx = -c1;
+    } else if constexpr (K == 4) {
+        Y = a2 * x * y; Gx = a2 * y; Gy = a2 * x;
+    } else if constexpr (K == 5) {
+        Y = -a2 * y * z; Gy = -a2 * z; Gz = -a2 * y;
+    } else if constexpr (K == 6) {
+        Y = b2 * (2.0 * z * z - x * x - y * y); Gx = -2.0 * b2 * x; Gy = -2.0 * b2 * y; Gz = 4.0 * b2 * z;
+    } else if constexpr (K == 7) {
+        Y = -a2 * x * z; Gx = -a2 * z; Gz = -a2 * x;
+    } else if constexpr (K == 8) {
+        Y = c2 * (x * x - y * y); Gx = 2.0 * c2 * x; Gy = -2.0 * c2 * y;
+    } else if constexpr (K == 9) {
+        Y = -a3 * y * (3.0 * x * x - y * y); Gx = -6.0 * a3 * x * y; Gy = -3.0 * a3 * (x * x - y * y);
+    } else if constexpr (K == 10) {
+        Y = b3 * x * y * z; Gx = b3 * y * z; Gy = b3 * x * z; Gz = b3 * x * y;
+    } else if constexpr (K == 11) {
+        Y = -c3 * y * (4.0 * z * z - x * x - y * y);
+        Gx = 2.0 * c3 * x * y; Gy = -c3 * (4.0 * z * z - x * x - 3.0 * y * y); Gz = -8.0 * c3 * y * z;
+    } else if constexpr (K == 12) {
+        Y = d3 * z * (2.0 * z * z - 3.0 * x * x - 3.0 * y * y);
+        Gx = -6.0 * d3 * x * z; Gy = -6.0 * d3 * y * z; Gz = d3 * (6.0 * z * z - 3.0 * x * x - 3.0 * y * y);
+    } else if constexpr (K == 13) {
+        Y = -c3 * x * (4.0 * z * z - x * x - y * y);
+        Gx = -c3 * (4.0 * z * z - 3.0 * x * x - y * y); Gy = 2.0 * c3 * x * y; Gz = -8.0 * c3 * x * z;
+    } else if constexpr (K == 14) {
+        Y = e3 * z * (x * x - y * y); Gx = 2.0 * e3 * x * z; Gy = -2.0 * e3 * y * z; Gz = e3 * (x * x - y * y);
+    } else {
+        Y = -a3 * x * (x * x - 3.0 * y * y); Gx = -3.0 * a3 * (x * x - y * y); Gy = 6.0 * a3 * x * y;
+    }
 }
 
+// f(integral_constant<int, K>) for K = 0 .. N-1, unrolled at compile time
+template <int K, int N, typename F>
+__device__ inline void static_for(F&& f) {
+    if constexpr (K < N) {
+        f(std::integral_constant<int, K>{});
+        static_for<K + 1, N>(f);
+    }
+}
+
+// DEG: the SH degree in use (0..3), a template argument so that every SH loop is
+// unrolled with compile-time indices (no register arrays indexed at run time).
+template <int DEG>
 __global__ __launch_bounds__(256) void k_project_bwd(int64_t N, int32_t v0, int32_t nv, CamBatch cams,
                                                      potr_config cfg, const float* __restrict__ means,
                                                      const float* __restrict__ scales,
@@ -245,12 +269,13 @@ __global__ __launch_bounds__(256) void k_project_bwd(int64_t N, int32_t v0, int3
             Sg[3 * a + b] = v;
             Sg[3 * b + a] = v;
         }
-    const int nsh = (cfg.sh_degree + 1) * (cfg.sh_degree + 1);
+    constexpr int nsh = (DEG + 1) * (DEG + 1);
     const float* shp = sh + 48 * i;
 
     double gm[3] = {0, 0, 0}, gSig[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0}, go = 0.0;
-    float gsh[48];
-    for (int k = 0; k < 48; ++k) gsh[k] = 0.f;
+    float gsh[3 * nsh];
+#pragma unroll
+    for (int k = 0; k < 3 * nsh; ++k) gsh[k] = 0.f;
     bool touched = false;
 
     for (int vv = 0; vv < nv; ++vv) {
@@ -326,21 +351,33 @@ __global__ __launch_bounds__(256) void k_project_bwd(int64_t N, int32_t v0, int3
         double ux = mx - ex, uy = my - ey, uz = mz - ez;
         const double un = sqrt(ux * ux + uy * uy + uz * uz);
         const double dx = ux / un, dy = uy / un, dz = uz / un;
-        double Y[16], Gx[16], Gy[16], Gz[16];
-        sh_basis_grad(dx, dy, dz, cfg.sh_degree, Y, Gx, Gy, Gz);
+        // colour before the clamp, per channel; the clamp passes the gradient
+        // where it is positive
+        double pre[3] = {0.5, 0.5, 0.5};
+        static_for<0, nsh>([&](auto kc) {
+            constexpr int k = decltype(kc)::value;
+            double Yk, gxk, gyk, gzk;
+            sh_term<k>(dx, dy, dz, Yk, gxk, gyk, gzk);
+#pragma unroll
+            for (int ch = 0; ch < 3; ++ch) pre[ch] += (double)shp[3 * k + ch] * Yk;
+        });
+        double gc[3];
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) gc[ch] = (pre[ch] > 0.0) ? gcol[ch] : 0.0;
         double gdx = 0.0, gdy = 0.0, gdz = 0.0;
-        for (int ch = 0; ch < 3; ++ch) {
-            double pre = 0.5;
-            for (int k = 0; k < nsh; ++k) pre += (double)shp[3 * k + ch] * Y[k];
-            if (!(pre > 0.0) || gcol[ch] == 0.0) continue;
-            for (int k = 0; k < nsh; ++k) {
-                gsh[3 * k + ch] += (float)(gcol[ch] * Y[k]);
-                const double gy = gcol[ch] * (double)shp[3 * k + ch];
-                gdx += gy * Gx[k];
-                gdy += gy * Gy[k];
-                gdz += gy * Gz[k];
+        static_for<0, nsh>([&](auto kc) {
+            constexpr int k = decltype(kc)::value;
+            double Yk, Gxk, Gyk, Gzk;
+            sh_term<k>(dx, dy, dz, Yk, Gxk, Gyk, Gzk);
+#pragma unroll
+            for (int ch = 0; ch < 3; ++ch) {
+                gsh[3 * k + ch] += (float)(gc[ch] * Yk);
+                const double gy = gc[ch] * (double)shp[3 * k + ch];
+                gdx += gy * Gxk;
+                gdy += gy * Gyk;
+                gdz += gy * Gzk;
             }
-        }
+        });
         const double dot = gdx * dx + gdy * dy + gdz * dz;
         gm[0] += (gdx - dx * dot) / un;
         gm[1] += (gdy - dy * dot) / un;
@@ -377,6 +414,7 @@ __global__ __launch_bounds__(256) void k_project_bwd(int64_t N, int32_t v0, int3
     d_quats[4 * i + 2] += (float)((gy - y * dq) / qn);
     d_quats[4 * i + 3] += (float)((gz - z * dq) / qn);
     d_opac[i] += (float)go;
+#pragma unroll
     for (int k = 0; k < nsh * 3; ++k) d_sh[48 * i + k] += gsh[k];
 }
 
@@ -422,8 +460,24 @@ potr_status launch_project_backward(int64_t N, int32_t V, const potr_camera* cam
         CamBatch cb;
         for (int k = 0; k < nv; ++k) cb.c[k] = cams[v0 + k];
         for (int k = nv; k < kViewsPerLaunch; ++k) cb.c[k] = cams[v0];
-        hipLaunchKernelGGL(k_project_bwd, grid, dim3(256), 0, s, N, v0, nv, cb, cfg, means, scales, quats, opac, sh,
-                           grad2d, d_means, d_scales, d_quats, d_opac, d_sh);
+        switch (cfg.sh_degree) {
+            case 0:
+                hipLaunchKernelGGL(k_project_bwd<0>, grid, dim3(256), 0, s, N, v0, nv, cb, cfg, means, scales, quats,
+                                   opac, sh, grad2d, d_means, d_scales, d_quats, d_opac, d_sh);
+                break;
+            case 1:
+                hipLaunchKernelGGL(k_project_bwd<1>, grid, dim3(256), 0, s, N, v0, nv, cb, cfg, means, scales, quats,
+                                   opac, sh, grad2d, d_means, d_scales, d_quats, d_opac, d_sh);
+                break;
+            case 2:
+                hipLaunchKernelGGL(k_project_bwd<2>, grid, dim3(256), 0, s, N, v0, nv, cb, cfg, means, scales, quats,
+                                   opac, sh, grad2d, d_means, d_scales, d_quats, d_opac, d_sh);
+                break;
+            default:
+                hipLaunchKernelGGL(k_project_bwd<3>, grid, dim3(256), 0, s, N, v0, nv, cb, cfg, means, scales, quats,
+                                   opac, sh, grad2d, d_means, d_scales, d_quats, d_opac, d_sh);
+                break;
+        }
         potr_status st = check_launch("k_project_bwd");
         if (st != POTR_OK) return st;
     }
