@@ -4,9 +4,10 @@
     loss = (img - target).abs().mean(); loss.backward()
 
 `scales` and `opacities` are the activated values (apply exp / sigmoid in torch
-before calling, and autograd carries the chain). The forward keeps copies of the
-per-view records and tile lists for the backward, so several renders may be
-alive at once.
+before calling, and autograd carries the chain). The forward keeps the per-view
+records and tile lists for the backward (the rasterizer hands those buffers
+over and allocates new ones for later calls), so several renders may be alive
+at once.
 """
 from __future__ import annotations
 
@@ -20,12 +21,15 @@ class RenderFunction(torch.autograd.Function):
     def forward(ctx, means, scales, quats, opacities, sh, cams, rz: Rasterizer):
         ds = DeviceScene(*(t.detach().contiguous() for t in (means, scales, quats, opacities, sh)))
         vb = rz.render_views(ds, cams)
-        keep = ViewBatch(V=vb.V, N=vb.N, proj=vb.proj.clone(), tiles_touched=vb.tiles_touched,
-                         order=None, n_pairs=vb.n_pairs, sorted_ids=vb.sorted_ids[: max(vb.n_pairs, 1)].clone(),
-                         tile_ranges=vb.tile_ranges.clone(), image=None, p_final=vb.p_final.clone(),
-                         t_final=vb.t_final.clone(), n_walk=vb.n_walk.clone())
+        # the records, lists and per-pixel state stay with this node for the
+        # backward; the rasterizer's later calls get new buffers
+        rz.release()
+        keep = ViewBatch(V=vb.V, N=vb.N, proj=vb.proj, tiles_touched=vb.tiles_touched,
+                         order=None, n_pairs=vb.n_pairs, sorted_ids=vb.sorted_ids[: max(vb.n_pairs, 1)],
+                         tile_ranges=vb.tile_ranges, image=None, p_final=vb.p_final,
+                         t_final=vb.t_final, n_walk=vb.n_walk)
         ctx.rz, ctx.cams, ctx.vb, ctx.ds = rz, cams, keep, ds
-        return vb.image.clone()
+        return vb.image
 
     @staticmethod
     def backward(ctx, grad_image):

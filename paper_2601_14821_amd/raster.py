@@ -68,6 +68,11 @@ class Rasterizer:
             self._bufs[name] = b
         return b
 
+    def release(self) -> None:
+        """Hand every buffer the rasterizer holds over to whoever references it:
+        later calls allocate new ones instead of overwriting them."""
+        self._bufs = {}
+
     def _i32(self, name: str, n: int) -> torch.Tensor:
         return self._buf(name, 4 * n)[: 4 * max(n, 1)].view(torch.int32)
 
