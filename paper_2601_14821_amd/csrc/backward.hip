@@ -21,7 +21,7 @@
 namespace potr {
 namespace {
 
-constexpr int kBwdChunk = 256;   // entries staged per round
+constexpr int kBwdChunk = 128;   // entries staged per round
 constexpr int kG = 9;            // gradient components per (view, splat)
 
 template <int TW, int TH>
@@ -43,7 +43,7 @@ __global__ __launch_bounds__(TW * TH) void k_blend_bwd(int64_t N, int32_t W, int
     __shared__ float s_c[kBwdChunk];    // b
     __shared__ uint32_t s_id[kBwdChunk];
     __shared__ uint32_t s_rows[kBwdChunk];
-    __shared__ float s_acc[kG][kBwdChunk];   // per entry: the waves' sums, added in LDS
+    __shared__ float s_part[kG][NW][kBwdChunk];
     __shared__ __align__(8) uint16_t s_list[NW][kBwdChunk];
     __shared__ int s_wmax;
     const int tile = blockIdx.x, v = blockIdx.y;
@@ -108,10 +108,9 @@ __global__ __launch_bounds__(TW * TH) void k_blend_bwd(int64_t N, int32_t W, int
         uint16_t* const L = s_list[wid];
         const int nl = wave_list(s_rows, cnt, row_lo, row_hi, L);
         const int jlim = min(cnt, wave_walk - base);
-        for (int j = threadIdx.x; j < cnt; j += NT)
+        for (int j = lane; j < cnt; j += 64)
 #pragma unroll
-            for (int c = 0; c < kG; ++c) s_acc[c][j] = 0.f;
-        __syncthreads();
+            for (int c = 0; c < kG; ++c) s_part[c][wid][j] = 0.f;
         // groups of four entries: per-lane gradients, then one reduce-scatter per component
         for (int i = 0; i < nl; i += 4) {
             const uint2 q = *reinterpret_cast<const uint2*>(L + i);
@@ -166,13 +165,15 @@ __global__ __launch_bounds__(TW * TH) void k_blend_bwd(int64_t N, int32_t W, int
 #pragma unroll
             for (int c = 0; c < kG; ++c) {
                 const float s = wave_sum4(g[0][c], g[1][c], g[2][c], g[3][c]);
-                if (writer && s != 0.f) atomicAdd(&s_acc[c][jw], s);
+                if (writer) s_part[c][wid][jw] = s;
             }
         }
         __syncthreads();
         for (int e = threadIdx.x; e < cnt * kG; e += NT) {
             const int j = e / kG, c = e - j * kG;
-            const float t = s_acc[c][j];
+            float t = 0.f;
+#pragma unroll
+            for (int w = 0; w < NW; ++w) t += s_part[c][w][j];
             if (t != 0.f) unsafeAtomicAdd(grad2d + ((int64_t)v * N + s_id[j]) * kG + c, t);
         }
         __syncthreads();
