@@ -378,45 +378,20 @@ __device__ inline uint32_t seg_prefix(uint32_t* __restrict__ p, int64_t stride, 
     return run;
 }
 
-// One block: row bases = exclusive scan of the row totals over (view, row);
-// the number of pairs (-1 if a depth pass gave up a wait).
-__global__ __launch_bounds__(1024) void k_row_bases(const uint32_t* __restrict__ rtot, Bins B,
-                                                    int64_t* __restrict__ base, const uint32_t* __restrict__ fault,
-                                                    int64_t* __restrict__ n_pairs) {
-    __shared__ int64_t wsum[16];
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int64_t n = (int64_t)B.V * B.tiles_y;
-    int64_t carry = 0;
-    for (int64_t b0 = 0; b0 < n; b0 += 1024) {
-        const int64_t i = b0 + threadIdx.x;
-        const int64_t tot = i < n ? (int64_t)rtot[i] : 0;
-        int64_t inc = tot;
-#pragma unroll
-        for (int d = 1; d < 64; d <<= 1) {
-            const int64_t u = __shfl_up(inc, d, 64);
-            if (lane >= d) inc += u;
-        }
-        if (lane == 63) wsum[w] = inc;
-        __syncthreads();
-        int64_t pre = carry, all = 0;
-#pragma unroll
-        for (int k = 0; k < 16; ++k) {
-            if (k < w) pre += wsum[k];
-            all += wsum[k];
-        }
-        if (i < n) base[i] = pre + inc - tot;
-        carry += all;
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) *n_pairs = *fault ? (int64_t)-1 : carry;
-}
-
 // A block per (view, row): per tile, the segment sums become exclusive prefixes
 // in place and give the tile's total; trel = exclusive scan of the row's tile
-// totals (the tile's start relative to the row's), rtot = the row's total.
+// totals (the tile's start relative to the row's), rtot = the row's total. The
+// block that finishes last (a counter, cleared with the control words) then
+// forms the row bases, an exclusive scan of the row totals over (view, row),
+// and the number of pairs (-1 if a depth pass gave up a wait).
 __global__ __launch_bounds__(256) void k_tile_bases(uint32_t* __restrict__ segt, Bins B,
-                                                    uint32_t* __restrict__ trel, uint32_t* __restrict__ rtot) {
+                                                    uint32_t* __restrict__ trel, uint32_t* __restrict__ rtot,
+                                                    uint32_t* __restrict__ rows_done,
+                                                    const uint32_t* __restrict__ fault,
+                                                    int64_t* __restrict__ rbase, int64_t* __restrict__ n_pairs) {
     __shared__ uint32_t wsum[4];
+    __shared__ int64_t wsum64[4];
+    __shared__ bool s_last;
     const int y = blockIdx.x, v = blockIdx.y, lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     uint32_t run = 0;
     const int64_t t0 = (int64_t)v * B.T + (int64_t)y * B.tiles_x;
@@ -437,7 +412,38 @@ __global__ __launch_bounds__(256) void k_tile_bases(uint32_t* __restrict__ segt,
         run += all;
         __syncthreads();
     }
-    if (threadIdx.x == 0) rtot[(int64_t)v * B.tiles_y + y] = run;
+    if (threadIdx.x == 0) {
+        rtot[(int64_t)v * B.tiles_y + y] = run;
+        __threadfence();
+        s_last = atomicAdd(rows_done, 1u) == gridDim.x * gridDim.y - 1;
+    }
+    __syncthreads();
+    if (!s_last) return;
+    __threadfence();   // every block's row total is visible past its counter increment
+    const int64_t nr = (int64_t)B.V * B.tiles_y;
+    int64_t carry = 0;
+    for (int64_t b0 = 0; b0 < nr; b0 += 256) {
+        const int64_t i = b0 + threadIdx.x;
+        const int64_t tot = i < nr ? (int64_t)rtot[i] : 0;
+        int64_t inc = tot;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const int64_t u = __shfl_up(inc, d, 64);
+            if (lane >= d) inc += u;
+        }
+        if (lane == 63) wsum64[w] = inc;
+        __syncthreads();
+        int64_t pre = carry, all = 0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            if (k < w) pre += wsum64[k];
+            all += wsum64[k];
+        }
+        if (i < nr) rbase[i] = pre + inc - tot;
+        carry += all;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *n_pairs = *fault ? (int64_t)-1 : carry;
 }
 
 // The counts of one group (a block per (group, view)), band by band of tile
@@ -807,6 +813,7 @@ BinWs bin_layout(int64_t N, int32_t V, int32_t tiles_x, int32_t tiles_y, char* b
     BinWs w;
     size_t o = 0;
     auto take = [&](size_t b) { char* p = base ? base + o : nullptr; o += align_up(b > 0 ? b : 1); return p; };
+    // a ticket per depth pass, the tile-row counter of k_tile_bases, the fault word
     w.ctl.ticket = (uint32_t*)take(4 * (kMaxPasses + 2));
     w.ctl.fault = w.ctl.ticket + kMaxPasses + 1;
     w.ctl.ghist = (uint32_t*)take(4 * (size_t)V * kMaxPasses * 256);
@@ -902,12 +909,9 @@ potr_status launch_bin(int64_t N, int32_t V, const potr_camera& cam0, const potr
     }
     // tile starts within their rows and row totals, then row bases over
     // (view, row), the pair count, and every group's first position per tile
-    hipLaunchKernelGGL(k_tile_bases, dim3(tys, V), dim3(256), 0, s, w.segt, B, w.trel, w.rtot);
+    hipLaunchKernelGGL(k_tile_bases, dim3(tys, V), dim3(256), 0, s, w.segt, B, w.trel, w.rtot, w.ctl.ticket + kMaxPasses,
+                       (const uint32_t*)w.ctl.fault, w.rbase, n_pairs);
     st = check_launch("k_tile_bases");
-    if (st != POTR_OK) return st;
-    hipLaunchKernelGGL(k_row_bases, dim3(1), dim3(1024), 0, s, (const uint32_t*)w.rtot, B, w.rbase,
-                       (const uint32_t*)w.ctl.fault, n_pairs);
-    st = check_launch("k_row_bases");
     if (st != POTR_OK || N == 0) return st;
     hipLaunchKernelGGL(k_tile_offsets, dim3((unsigned)ceil_div(B.T, 256), B.nseg_g, V), dim3(256), 0, s,
                        (const uint32_t*)w.tc, (const uint32_t*)w.segt, (const int64_t*)w.rbase,
