@@ -159,8 +159,9 @@ POTR_API potr_status potr_bin(int64_t N, int32_t V, const potr_camera* cams, con
  *   sorted_ids [capacity] uint32 out: splat id (0..N-1) of every pair
  *   tile_ranges [V*tiles*2] int32 out: half-open [start, end) into sorted_ids;
  *            [0, 0) for a tile without pairs
- * Limits: tiles_x <= 1600 and tiles_y <= 1024 (LDS per workgroup); larger
- * grids fail at launch with POTR_EHIP.
+ * Limits: every image the camera checks accept (at most 16384 px a side, so
+ * up to 2048 tile columns of 8 px) fits the per-workgroup LDS (61 KB at 2048
+ * columns).
  * ------------------------------------------------------------------------- */
 POTR_API potr_status potr_sort_workspace_size(int64_t capacity, size_t* bytes);
 POTR_API potr_status potr_sort(int64_t N, int32_t V, const potr_camera* cams, const potr_config* cfg,

@@ -556,12 +556,12 @@ __global__ __launch_bounds__(256) void k_place(const uint2* __restrict__ srect, 
                                                int32_t* __restrict__ ranges) {
     extern __shared__ uint32_t lds[];
     const int TX = B.tiles_x;
-    uint32_t* wcnt = lds;                              // [kWaves][TX]
-    uint32_t* cur = wcnt + kWaves * TX;                // [TX]
+    uint32_t* cur = lds;                               // [TX]
     uint32_t* boff = cur + TX;                         // [TX]
     uint32_t* s_id = boff + TX;                        // [2048]: a pass's pair words, then its ids
     uint32_t* s_off = s_id + kThreads * kColItems;     // [kPlRound]: start of each covering rank's run
-    uint16_t* s_x = reinterpret_cast<uint16_t*>(s_off + kPlRound);   // [2048]
+    uint16_t* wcnt = reinterpret_cast<uint16_t*>(s_off + kPlRound);   // [kWaves][TX] (a pass has <= 2048 pairs)
+    uint16_t* s_x = wcnt + kWaves * TX;                // [2048]
     uint16_t* s_x0 = s_x + kThreads * kColItems;       // [kPlRound]: its first tile
     uint16_t* s_rk = s_x0 + kPlRound;                  // [kPlRound]: its rank within the round
     __shared__ uint32_t wsum[kWaves];
@@ -631,7 +631,7 @@ __global__ __launch_bounds__(256) void k_place(const uint2* __restrict__ srect, 
             uint32_t r = 0;
             if (ok) r = wcnt[w * TX + d];
             __builtin_amdgcn_wave_barrier();
-            if (ok && below == 0) wcnt[w * TX + d] = r + c;
+            if (ok && below == 0) wcnt[w * TX + d] = (uint16_t)(r + c);
             __builtin_amdgcn_wave_barrier();
             rnk[k] = ok ? r + below : 0xffffffffu;
         }
@@ -645,7 +645,7 @@ __global__ __launch_bounds__(256) void k_place(const uint2* __restrict__ srect, 
             if (x < TX)
                 for (int ww = 0; ww < kWaves; ++ww) {
                     const uint32_t c = wcnt[ww * TX + x];
-                    wcnt[ww * TX + x] = run;
+                    wcnt[ww * TX + x] = (uint16_t)run;
                     run += c;
                 }
             local[j] = run;
@@ -853,11 +853,12 @@ int gc_band(int tiles_x) {
 }
 size_t gc_lds(int band, int tiles_x) { return (size_t)(band + 1) * (tiles_x + 1) * 4; }
 
-// LDS of the placement: per-wave counters, cursors and bases per tile, a pass
-// of pair words / ids and tile x, and a round's runs (start, first tile, rank)
+// LDS of the placement: cursors and bases per tile, a pass of pair words / ids,
+// a round's run starts, 16-bit per-wave counters per tile, a pass's tile x, and
+// a round's first tiles and ranks (54 KB at 1600 tile columns)
 size_t place_lds(const Bins& B) {
-    return ((size_t)(kWaves + 2) * B.tiles_x + (size_t)kThreads * kColItems + kPlRound) * 4 +
-           ((size_t)kThreads * kColItems + 2 * kPlRound) * 2;
+    return ((size_t)2 * B.tiles_x + (size_t)kThreads * kColItems + kPlRound) * 4 +
+           ((size_t)kWaves * B.tiles_x + (size_t)kThreads * kColItems + 2 * kPlRound) * 2;
 }
 
 

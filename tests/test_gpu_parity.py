@@ -78,10 +78,16 @@ def _upload_records(rect, depth, V, N):
     (20000, 2, (80, 45), 4, None), (4096 * 3 + 17, 1, (33, 21), 5, None), (70000, 3, (128, 128), 6, None),
     # wide rows (9 bits of tile column), tall images, and splats covering up to 1200 tiles
     (3000, 2, (300, 7), 7, None), (3000, 1, (3, 500), 8, None), (4000, 1, (40, 30), 9, (40, 30)),
-    (64 * 5 + 3, 2, (17, 9), 10, (17, 9))])
+    (64 * 5 + 3, 2, (17, 9), 10, (17, 9)),
+    # the widest image (16384 px: 1024 columns of 16-px tiles), several row bands
+    # in the group counts, and runs of up to 300 tiles (a row segment of many passes)
+    (2000, 1, (1024, 20), 11, (300, 8)),
+    # 8-px tiles at the widest image: 2048 tile columns (11 bits of tile column)
+    (1500, 1, (2048, 6), 12, (400, 4, 8))])
 def test_bin_sort_bit_exact_on_synthetic_records(N, V, tiles, seed, big):
     _need_gpu()
     tx, ty = tiles
+    tile = 16 if big is None or len(big) < 3 else big[2]
     rects, depths = [], []
     for v in range(V):
         kw = {} if big is None else dict(max_w=big[0], max_h=big[1])
@@ -89,8 +95,8 @@ def test_bin_sort_bit_exact_on_synthetic_records(N, V, tiles, seed, big):
         rects.append(r)
         depths.append(d)
     rect, depth = np.stack(rects), np.stack(depths)
-    s = synth.RenderSettings()
-    cam = synth.Camera(np.eye(3, dtype=np.float32), np.zeros(3, np.float32), 1.0, 1.0, 0.0, 0.0, tx * 16, ty * 16)
+    s = synth.RenderSettings(tile_w=tile, tile_h=tile, lds_batch=64 if tile == 8 else 320)
+    cam = synth.Camera(np.eye(3, dtype=np.float32), np.zeros(3, np.float32), 1.0, 1.0, 0.0, 0.0, tx * tile, ty * tile)
     cams = [cam] * V
     rz = raster.Rasterizer(s)
     proj, tt = _upload_records(rect, depth, V, N)
