@@ -12,6 +12,10 @@ Also reported (extra fields):
   batched: 3M clustered splats x 16 of the 200 hemisphere views at 1600x1064,
            plain per-view launches vs one HIP-graph replay of the batched
            persistent scorer (ms per view, Gsplat.views/s);
+  multi_scene: 16 clustered scenes of uneven size (50k..2M splats, 8..32
+           views each, 640x480 / 1280x720 / 1600x1064): tile shape and LDS
+           batch picked by the autotuner on the whole batch, then one HIP-graph
+           replay of the batched persistent scorer;
   fwd_bwd: 1M splats x 4 views at 1280x720, forward + L1 loss gradient +
            hand-written backward, ms per view.
 
@@ -205,14 +209,16 @@ def batched_section(torch, raster, synth, batch, n_views=16):
 
 def multi_scene_section(torch, raster, synth, batch):
     """16 scenes of uneven size (50 k..2 M splats, 8..32 views, three image sizes) scored
-    in one batch: per-job project/bin/sort and one persistent render + removal launch,
-    replayed as one HIP graph."""
+    in one batch: the autotuner picks tile shape and LDS batch on the whole batch, then
+    per-job project/bin/sort and one persistent render + removal launch are replayed as
+    one HIP graph."""
     work = synth.workload_batched()
-    s = synth.RenderSettings()
     items = []
     for scene, cams in work:
         ds = raster.to_device(scene)
         items.append((ds, cams, torch.zeros(scene.n, device="cuda")))
+    s, tune = batch.autotune(items, synth.RenderSettings(), reps=1)
+    torch.cuda.empty_cache()
     bs = batch.BatchScorer(items, s, views_per_job=8)
     bs.capture()
 
@@ -232,6 +238,8 @@ def multi_scene_section(torch, raster, synth, batch):
     torch.cuda.empty_cache()
     return {"workload": f"{len(work)} clustered scenes, {ns} splats in all (50k..2M log-uniform), {nv} views "
                         f"(8..32 per scene) at 640x480, 1280x720 and 1600x1064",
+            "autotuned": f"{s.tile_w}x{s.tile_h} tiles, LDS batch {s.lds_batch}",
+            "autotune_ms": {f"{c['tile']}/{c['lds_batch']}": round(c["ms"], 2) for c in tune["tried"]},
             "ms_per_batch": round(ms, 3), "ms_per_view": round(ms / nv, 4),
             "gsplat_views_per_s": round(sv / (ms / 1000.0) / 1e9, 4),
             "pairs": int(sum(counted)), "overflowed_jobs": over}

@@ -303,8 +303,10 @@ POTR_API potr_status potr_batch_destroy(potr_batch b);
  * (64, 128, 320, 512) on the given jobs (`reps` timed runs each, after one
  * warm-up) and writes the fastest tile_w, tile_h, lds_batch into *inout. Uses
  * temporary device memory and scratch scores (the jobs' outputs are untouched);
- * synchronises. Optional: best_ms, and the tried configs with their times
- * (arrays of at least 12) and their count. */
+ * synchronises. A shape at which some job's pairs exceed one call's limit
+ * (2^31 - 1) is skipped; POTR_EINVAL when no candidate fits. Optional:
+ * best_ms, and the tried configs with their times (arrays of at least 12) and
+ * their count. */
 POTR_API potr_status potr_autotune(const potr_job* jobs, int32_t n_jobs, potr_config* inout, int32_t reps,
                                    double* best_ms, potr_config* tried, double* tried_ms, int32_t* n_tried,
                                    void* stream);

@@ -333,6 +333,10 @@ extern "C" potr_status potr_autotune(const potr_job* jobs, int32_t n_jobs, potr_
             c.lds_batch = batches[bi];
             potr_batch b = nullptr;
             st = potr_batch_create(scratch.data(), n_jobs, &c, 0.05f, &b, stream);
+            if (st == POTR_EINVAL) {   // a job's pairs exceed one call's limit at this shape: not a candidate
+                st = POTR_OK;
+                continue;
+            }
             if (st != POTR_OK) break;
             char* ws = nullptr;
             st = hip_ok(hipMalloc(&ws, b->bytes), "hipMalloc (autotune workspace)");
@@ -362,6 +366,7 @@ extern "C" potr_status potr_autotune(const potr_job* jobs, int32_t n_jobs, potr_
     for (float* p : bufs) hipFree(p);
     if (n_tried) *n_tried = k;
     if (st != POTR_OK) return st;
+    if (k == 0) return fail(POTR_EINVAL, "no candidate fits: a job's pairs exceed one call's limit at every shape");
     inout->tile_w = best_cfg.tile_w;
     inout->tile_h = best_cfg.tile_h;
     inout->lds_batch = best_cfg.lds_batch;
