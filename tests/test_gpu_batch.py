@@ -7,8 +7,8 @@ import numpy as np
 import pytest
 import torch
 
-import oracle
 from paper_2601_14821_amd import batch, raster, synth
+from score_tolerance import compare_scores, oracle_views
 
 pytestmark = pytest.mark.gpu
 
@@ -64,9 +64,11 @@ def _plain_scores(scene, cams, s):
     return sc.cpu().numpy()
 
 
-def test_batched_persistent_equals_plain_and_oracle():
+@pytest.mark.parametrize("s", [synth.RenderSettings(), synth.RenderSettings(tile_w=8, tile_h=8, lds_batch=64, t_min=0.0),
+                               synth.RenderSettings(tile_w=32, tile_h=8, lds_batch=512, bg=(0.3, 0.5, 0.7))],
+                         ids=["16x16", "8x8-exact", "32x8-bg"])
+def test_batched_persistent_equals_plain_and_oracle(s):
     _need_gpu()
-    s = synth.RenderSettings()
     scenes = _uneven_scenes()
     devs = [(raster.to_device(sc), cams, torch.zeros(sc.n, device="cuda")) for sc, cams in scenes]
     bs = batch.BatchScorer(devs, s, views_per_job=2)
@@ -76,13 +78,13 @@ def test_batched_persistent_equals_plain_and_oracle():
     assert bs.overflowed() == 0
     counted, caps = bs.pairs()
     assert all(c <= k for c, k in zip(counted, caps))
-    for (scene, cams), (_, _, sc) in zip(scenes, devs):
-        _close(sc.cpu().numpy(), _plain_scores(scene, cams, s))
-    # oracle on the smallest scene, all views
-    scene, cams = scenes[0]
-    tot = sum(oracle.render(scene, c, s, record_f32=True, want=("score_l1",))["score_l1"] for c in cams)
-    got = devs[0][2].cpu().numpy()
-    assert np.abs(got - tot).sum() <= 1e-4 * tot.sum()
+    for k, ((scene, cams), (_, _, sc)) in enumerate(zip(scenes, devs)):
+        got = sc.cpu().numpy()
+        _close(got, _plain_scores(scene, cams, s))
+        # every scene, every splat, against the oracle over all of its views
+        tot, _ = oracle_views(scene, cams, s)
+        n_floor = compare_scores(got, tot["score_l1"], tot["magnitude"], tot["flag_mass"])
+        print(f"scene {k}: {scene.n} splats x {len(cams)} views, {n_floor} needed the flag allowance", flush=True)
 
 
 def test_graph_replay_equals_eager():

@@ -14,6 +14,7 @@ import torch
 import oracle
 from paper_2601_14821_amd import _lib as L
 from paper_2601_14821_amd import raster, synth
+from score_tolerance import compare_scores, oracle_views
 
 pytestmark = pytest.mark.gpu
 
@@ -165,16 +166,6 @@ def _compare_view(img_gpu, o, atol=1e-4, max_flag_frac=0.02):
     return err, int(flag.sum())
 
 
-def _compare_scores(sg, ref, mag, flag_mass, rtol=1e-3, mfloor=1e-5):
-    base = rtol * np.abs(ref) + mfloor * mag
-    tol = base + flag_mass
-    d = np.abs(sg.astype(np.float64) - ref)
-    bad = d > tol
-    assert not bad.any(), (f"{bad.sum()} splats out of tolerance; worst idx {np.argmax(d - tol)} "
-                           f"gpu {sg[np.argmax(d - tol)]} ref {ref[np.argmax(d - tol)]}")
-    return int((d > base).sum())
-
-
 def _run_gpu(scene, cams, s, views_per_batch=8, target=None, want_se=False):
     ds = raster.to_device(scene)
     rz = raster.Rasterizer(s)
@@ -187,22 +178,6 @@ def _run_gpu(scene, cams, s, views_per_batch=8, target=None, want_se=False):
                                   scores_se=se, targets=tg, keep_images=True)
     torch.cuda.synchronize()
     return (images.cpu().numpy(), sc.cpu().numpy(), im.cpu().numpy(), None if se is None else se.cpu().numpy())
-
-
-def _oracle_views(scene, cams, s, target=None):
-    want = ("image", "score_l1", "importance", "magnitude", "flag_mass", "pixel_flag")
-    if target is not None:
-        want = want + ("score_se",)
-    tot = {}
-    views = []
-    for v, cam in enumerate(cams):
-        r = oracle.render(scene, cam, s, record_f32=True, want=want,
-                          target=None if target is None else target[v])
-        views.append(r)
-        for k in ("score_l1", "importance", "magnitude", "flag_mass", "score_se"):
-            if k in r:
-                tot[k] = tot.get(k, 0.0) + r[k]
-    return tot, views
 
 
 CASES = {
@@ -223,12 +198,12 @@ def test_blend_and_score_small(case):
     scene, cams = synth.workload_small()
     print(f"case {case}", flush=True)
     img, sc, im, _ = _run_gpu(scene, cams, s, views_per_batch=3)
-    tot, views = _oracle_views(scene, cams, s)
+    tot, views = oracle_views(scene, cams, s)
     for v in range(len(cams)):
         err, nf = _compare_view(img[v], views[v])
         print(f"view {v}: max err {err:.3g}, flagged {nf}", flush=True)
-    n_floor = _compare_scores(sc, tot["score_l1"], tot["magnitude"], tot["flag_mass"])
-    _compare_scores(im, tot["importance"], tot["magnitude"], tot["flag_mass"], rtol=1e-4, mfloor=0.0)
+    n_floor = compare_scores(sc, tot["score_l1"], tot["magnitude"], tot["flag_mass"])
+    compare_scores(im, tot["importance"], tot["magnitude"], tot["flag_mass"], rtol=1e-4, mfloor=0.0)
     assert (tot["score_l1"] > 0).sum() > 500
     print(f"splats needing the flag allowance: {n_floor}", flush=True)
 
@@ -240,9 +215,9 @@ def test_squared_error_mode():
     rng = np.random.default_rng(77)
     target = rng.uniform(0, 1, (len(cams), cams[0].height, cams[0].width, 3)).astype(np.float32)
     img, sc, im, se = _run_gpu(scene, cams, s, target=target, want_se=True)
-    tot, _ = _oracle_views(scene, cams, s, target=target)
+    tot, _ = oracle_views(scene, cams, s, target=target)
     # dSE = PD^2 + 2 PD (c - c_t): bounded by |PD| (|PD| + 2 |c - c_t|) <= 3 |PD|_1 here
-    _compare_scores(se, tot["score_se"], 3 * tot["magnitude"], 3 * tot["flag_mass"] + 3e-3 * tot["score_l1"])
+    compare_scores(se, tot["score_se"], 3 * tot["magnitude"], 3 * tot["flag_mass"] + 3e-3 * tot["score_l1"])
 
 
 def test_ragged_image_and_edge_cases():
@@ -251,16 +226,16 @@ def test_ragged_image_and_edge_cases():
     scene, _ = synth.workload_small()
     cams = synth.ring_cameras(2, 100, 75)          # tiles do not divide the image
     img, sc, _, _ = _run_gpu(scene, cams, s)
-    tot, views = _oracle_views(scene, cams, s)
+    tot, views = oracle_views(scene, cams, s)
     for v in range(2):
         _compare_view(img[v], views[v])
-    _compare_scores(sc, tot["score_l1"], tot["magnitude"], tot["flag_mass"])
+    compare_scores(sc, tot["score_l1"], tot["magnitude"], tot["flag_mass"])
     # one splat
     one = scene.subset([5])
     img, sc, _, _ = _run_gpu(one, cams[:1], s)
-    tot, views = _oracle_views(one, cams[:1], s)
+    tot, views = oracle_views(one, cams[:1], s)
     _compare_view(img[0], views[0])
-    _compare_scores(sc, tot["score_l1"], tot["magnitude"], tot["flag_mass"])
+    compare_scores(sc, tot["score_l1"], tot["magnitude"], tot["flag_mass"])
     # everything behind the camera: background only
     behind = scene.subset(np.arange(50))
     cam = synth.look_at((0, 0, 3), target=(0, 0, 10), width=64, height=48)
@@ -299,10 +274,10 @@ def test_single_view_full_size():
     print("gpu run", flush=True)
     img, sc, im, _ = _run_gpu(scene, cams, s)
     print("oracle run", flush=True)
-    tot, views = _oracle_views(scene, cams, s)
+    tot, views = oracle_views(scene, cams, s)
     err, nf = _compare_view(img[0], views[0])
     print(f"max err {err:.3g}, flagged {nf} of {img[0].shape[0] * img[0].shape[1]}", flush=True)
-    n_floor = _compare_scores(sc, tot["score_l1"], tot["magnitude"], tot["flag_mass"])
+    n_floor = compare_scores(sc, tot["score_l1"], tot["magnitude"], tot["flag_mass"])
     print(f"scored splats {(tot['score_l1'] > 0).sum()}, needing the flag allowance {n_floor}", flush=True)
     # the bulk of the score mass agrees to the tight bound
     ref = tot["score_l1"]
