@@ -535,9 +535,10 @@ __global__ __launch_bounds__(kGcThreads) void k_count(const uint32_t* __restrict
 // (rank, x) order. Per round of 2048 ranks the covering ranks' runs go to LDS
 // as a compact list (a scan of the run widths gives their starts, ballots of
 // the cover flags their places in the list);
-// per pass of up to 2048 pairs every thread expands eight consecutive pairs
-// (one binary search for the run holding its first pair, then a walk over the
-// runs) into words (tile x, rank within the group), the block ranks them
+// per pass of up to 2048 pairs every thread fills eight consecutive slots of
+// the pass buffer (one binary search for the run holding its first pair, then a
+// walk over the runs; two 16-byte LDS stores) with words (tile x, rank within
+// the group), the block ranks them
 // stably by tile x (ballots over the x bits, per-wave counters), maps each rank
 // to its splat id, sorts in LDS and stores each tile's run at the tile's cursor
 // (the group's first position in the tile, advanced per pass).
@@ -546,6 +547,7 @@ __global__ __launch_bounds__(kGcThreads) void k_count(const uint32_t* __restrict
 constexpr int kPlRound = 2048;                       // ranks per round
 constexpr int kPlSlots = kPlRound / kThreads;        // ranks per lane per round
 constexpr int kPlPer = kThreads * kColItems / kThreads;   // pairs each thread expands per pass
+static_assert(kPlPer == 8, "the expansion stores a thread's slots as two 16-byte words");
 
 template <int XBITS>
 __global__ __launch_bounds__(256) void k_place(const uint2* __restrict__ srect, const uint32_t* __restrict__ gsum,
@@ -554,12 +556,12 @@ __global__ __launch_bounds__(256) void k_place(const uint2* __restrict__ srect, 
                                                Bins B, const int64_t* __restrict__ n_pairs, int64_t capacity,
                                                const uint32_t* __restrict__ order, uint32_t* __restrict__ ids,
                                                int32_t* __restrict__ ranges) {
-    extern __shared__ uint32_t lds[];
+    extern __shared__ __align__(16) uint32_t lds[];
     const int TX = B.tiles_x;
-    uint32_t* cur = lds;                               // [TX]
+    uint32_t* s_id = lds;                              // [2048]: a pass's pair words, then its ids (16-byte aligned)
+    uint32_t* cur = s_id + kThreads * kColItems;       // [TX]
     uint32_t* boff = cur + TX;                         // [TX]
-    uint32_t* s_id = boff + TX;                        // [2048]: a pass's pair words, then its ids
-    uint32_t* s_off = s_id + kThreads * kColItems;     // [kPlRound]: start of each covering rank's run
+    uint32_t* s_off = boff + TX;                       // [kPlRound]: start of each covering rank's run
     uint16_t* wcnt = reinterpret_cast<uint16_t*>(s_off + kPlRound);   // [kWaves][TX] (a pass has <= 2048 pairs)
     uint16_t* s_x = wcnt + kWaves * TX;                // [2048]
     uint16_t* s_x0 = s_x + kThreads * kColItems;       // [kPlRound]: its first tile
@@ -734,9 +736,11 @@ __global__ __launch_bounds__(256) void k_place(const uint2* __restrict__ srect, 
         // expand the round's pairs into the pass buffer behind those already there
         for (uint32_t q0 = 0; q0 < tot;) {
             const uint32_t take = min(tot - q0, (uint32_t)(kThreads * kColItems) - fill);
-            const uint32_t j0 = threadIdx.x * kPlPer;   // this thread's pairs j0 .. j0 + kPlPer - 1
-            if (j0 < take) {
-                const uint32_t qa = q0 + j0;
+            // this thread fills the buffer slots b0 .. b0 + kPlPer - 1 that this expansion reaches
+            const uint32_t b0 = threadIdx.x * kPlPer;
+            const uint32_t blo = max(b0, fill), bhi = min(b0 + kPlPer, fill + take);
+            if (blo < bhi) {
+                const uint32_t qa = q0 + (blo - fill);
                 int lo = 0, hi = ncov - 1;   // last run starting at or before qa
                 while (lo < hi) {
                     const int mid = (lo + hi + 1) >> 1;
@@ -745,15 +749,29 @@ __global__ __launch_bounds__(256) void k_place(const uint2* __restrict__ srect, 
                 }
                 int r = lo;
                 uint32_t o = s_off[r], end = r + 1 < ncov ? s_off[r + 1] : tot;
-                const uint32_t j1 = min(j0 + kPlPer, take);
-                for (uint32_t j = j0; j < j1; ++j) {
-                    const uint32_t q = q0 + j;
-                    if (q >= end) {   // runs are never empty: q is in the next one
-                        ++r;
-                        o = end;
-                        end = r + 1 < ncov ? s_off[r + 1] : tot;
+                uint32_t wv[kPlPer];
+#pragma unroll
+                for (int i = 0; i < kPlPer; ++i) {
+                    const uint32_t b = b0 + i;
+                    wv[i] = 0u;
+                    if (b >= blo && b < bhi) {
+                        const uint32_t q = q0 + (b - fill);
+                        if (q >= end) {   // runs are never empty: q is in the next one
+                            ++r;
+                            o = end;
+                            end = r + 1 < ncov ? s_off[r + 1] : tot;
+                        }
+                        wv[i] = (((uint32_t)s_x0[r] + (q - o)) << kRankBits) | (uint32_t)(h0 + s_rk[r]);
                     }
-                    s_id[fill + j] = (((uint32_t)s_x0[r] + (q - o)) << kRankBits) | (uint32_t)(h0 + s_rk[r]);
+                }
+                if (blo == b0 && bhi == b0 + kPlPer) {   // whole slot block: two 16-byte stores
+                    uint4* dst = reinterpret_cast<uint4*>(s_id + b0);
+                    dst[0] = make_uint4(wv[0], wv[1], wv[2], wv[3]);
+                    dst[1] = make_uint4(wv[4], wv[5], wv[6], wv[7]);
+                } else {
+#pragma unroll
+                    for (int i = 0; i < kPlPer; ++i)
+                        if (b0 + i >= blo && b0 + i < bhi) s_id[b0 + i] = wv[i];
                 }
             }
             fill += take;
