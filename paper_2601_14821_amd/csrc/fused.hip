@@ -18,16 +18,18 @@
 namespace potr {
 namespace {
 
-// One staged splat: a, b and (blue, -, -, -) side by side, so that a sweep
-// reads all three with one address and immediate offsets.
+// One staged splat: a, b and (blue, splat id, reachable tile rows, -) side by
+// side, so that a sweep reads all three with one address and immediate offsets
+// and no per-entry array besides them is needed.
 struct Rec {
     float4 a, b, c;
 };
+constexpr int kRecWords = sizeof(Rec) / 4;
+constexpr int kRowsWord = 10;   // word of a Rec holding the reachable rows
+static_assert(sizeof(Rec) == 48 && kRowsWord == 8 + 2, "rows are c.z, after a and b");
 
 struct Smem {
     Rec* rec;
-    uint32_t* id;
-    uint32_t* rows;    // reach_rows per entry
     uint16_t* list;    // [NW][B] per-wave lists of the entries reaching the wave's rows
     uint16_t* hits;    // [NW][B] per-wave lists of the entries some lane of the wave blended
     int* misc;         // [0]: wmax, [1]: next item
@@ -45,9 +47,7 @@ __device__ inline void stage(const potr_proj* __restrict__ pv, const uint32_t* _
         make_rec(r0, r1, a, b);
         sm.rec[j].a = a;
         sm.rec[j].b = b;
-        sm.rec[j].c = make_float4(r2.x, 0.f, 0.f, 0.f);
-        sm.id[j] = id;
-        sm.rows[j] = reach_rows(a, b, qmax, tile_y0, TH);
+        sm.rec[j].c = make_float4(r2.x, __uint_as_float(id), __uint_as_float(reach_rows(a, b, qmax, tile_y0, TH)), 0.f);
     }
 }
 
@@ -100,7 +100,7 @@ __device__ void render_score_tile(const ViewJob& J, int tile, const potr_config&
         stage<NT, TH>(J.proj, J.ids, base, cnt, sm, qmax, tile_y0);
         staged = base;
         __syncthreads();
-        nl = wave_list(sm.rows, cnt, row_lo, row_hi, L);
+        nl = wave_list<kRecWords>(reinterpret_cast<const uint32_t*>(sm.rec) + kRowsWord, cnt, row_lo, row_hi, L);
         nh = 0;
         if (__ballot(!done) == 0) continue;
         for (int i = 0; i < nl; i += 4) {
@@ -193,7 +193,7 @@ __device__ void render_score_tile(const ViewJob& J, int tile, const potr_config&
             stage<NT, TH>(J.proj, J.ids, beg + base, cnt, sm, qmax, tile_y0);
             staged = beg + base;
             __syncthreads();
-            nl = wave_list(sm.rows, cnt, row_lo, row_hi, L);
+            nl = wave_list<kRecWords>(reinterpret_cast<const uint32_t*>(sm.rec) + kRowsWord, cnt, row_lo, row_hi, L);
             nh = 0;
             LL = L;
             nv = nl;
@@ -263,7 +263,7 @@ __device__ void render_score_tile(const ViewJob& J, int tile, const potr_config&
         }
         __syncthreads();
         for (int j = threadIdx.x; j < cnt; j += NT) {
-            const uint32_t id = sm.id[j];
+            const uint32_t id = __float_as_uint(sm.rec[j].c.y);
             float t[3] = {0.f, 0.f, 0.f};
 #pragma unroll
             for (int o = 0; o < 3; ++o)
@@ -283,9 +283,7 @@ __device__ inline Smem carve(char* base, int B) {
     constexpr int NW = (TW * TH + 63) / 64;
     Smem s;
     s.rec = reinterpret_cast<Rec*>(base);
-    s.id = reinterpret_cast<uint32_t*>(s.rec + B);
-    s.rows = s.id + B;
-    s.list = reinterpret_cast<uint16_t*>(s.rows + B);
+    s.list = reinterpret_cast<uint16_t*>(s.rec + B);
     s.hits = s.list + NW * B;
     s.misc = reinterpret_cast<int*>(s.hits + NW * B);
     s.part = reinterpret_cast<float*>(s.misc + 4);
@@ -331,7 +329,7 @@ __global__ void k_zero_i64(int64_t* p) { *p = 0; }
 template <int TW, int TH>
 size_t smem_bytes(int B, int n_out) {
     constexpr int NW = (TW * TH + 63) / 64;
-    return (size_t)B * (sizeof(Rec) + 4 + 4) + (size_t)NW * B * 4 + 16 + (size_t)n_out * NW * B * 4;
+    return (size_t)B * sizeof(Rec) + (size_t)NW * B * 4 + 16 + (size_t)n_out * NW * B * 4;
 }
 
 }  // namespace

@@ -104,17 +104,19 @@ __device__ inline float sub_weighted(float R, float w, float c) { return __fmaf_
 // splat, it equals R / (1 - alpha) - R_prev: one FMA per channel.
 __device__ inline float removal_delta(float inv, float R, float R_prev) { return __fmaf_rn(inv, R, -R_prev); }
 
-// Per-wave list of the staged entries [0, cnt) whose reachable tile rows meet
-// the wave's rows [row_lo, row_hi], in increasing order; returns its length.
+// Per-wave list of the staged entries [0, cnt) whose reachable tile rows
+// (rows[j * STRIDE] for entry j) meet the wave's rows [row_lo, row_hi], in
+// increasing order; returns its length.
 // The list is written and read by the same wave only (LDS operations of one
 // wave complete in order).
+template <int STRIDE = 1>
 __device__ inline int wave_list(const uint32_t* rows, int cnt, int row_lo, int row_hi, uint16_t* list) {
     const int lane = threadIdx.x & 63;
     const uint64_t below = (1ull << lane) - 1ull;
     int n = 0;
     for (int c0 = 0; c0 < cnt; c0 += 64) {
         const int j = c0 + lane;
-        const bool ok = j < cnt && rows_overlap(rows[j], row_lo, row_hi);
+        const bool ok = j < cnt && rows_overlap(rows[j * STRIDE], row_lo, row_hi);
         const uint64_t m = __ballot(ok);
         if (ok) list[n + __popcll(m & below)] = (uint16_t)j;
         n += __popcll(m);
