@@ -33,7 +33,7 @@ struct Smem {
     uint16_t* list;    // [NW][B] per-wave lists of the entries reaching the wave's rows
     uint16_t* hits;    // [NW][B] per-wave lists of the entries some lane of the wave blended
     int* misc;         // [0]: wmax, [1]: next item
-    float* part;       // [n_out][NW][B], n_out = number of per-splat outputs (last, sized by the launch)
+    float* part;       // [n_out][B] per-entry sums over the waves, n_out = number of per-splat outputs (last, sized by the launch)
 };
 
 template <int NT, int TH>
@@ -171,6 +171,8 @@ __device__ void render_score_tile(const ViewJob& J, int tile, const potr_config&
 
     // ---- removal sweep over the walked prefix
     if (threadIdx.x == 0) sm.misc[0] = 0;
+    // per-entry sums start at zero (the flush clears what it reads)
+    for (int j = threadIdx.x; j < n_out * B; j += NT) sm.part[j] = 0.f;
     __syncthreads();
     if (walk > 0) atomicMax(&sm.misc[0], walk);
     __syncthreads();
@@ -200,8 +202,6 @@ __device__ void render_score_tile(const ViewJob& J, int tile, const potr_config&
         }
         // entries of this wave's list from jlim on lie past every lane's walk
         const int jlim = min(cnt, wave_walk - base);
-        for (int j = lane; j < cnt; j += 64)
-            for (int o = 0; o < n_out; ++o) sm.part[(o * NW + wid) * B + j] = 0.f;
         for (int i = 0; i < nv; i += 4) {
             int js[4];
             list4(LL, i, js);
@@ -250,15 +250,15 @@ __device__ void render_score_tile(const ViewJob& J, int tile, const potr_config&
             const bool writer = lane < ng;
             if (J.scores) {
                 const float s = wave_sum4(l1v[0], l1v[1], l1v[2], l1v[3]);
-                if (writer) sm.part[(o_l1 * NW + wid) * B + jw] = s;
+                if (writer) atomicAdd(&sm.part[o_l1 * B + jw], s);
             }
             if (J.importance) {
                 const float s = wave_sum4(imv[0], imv[1], imv[2], imv[3]);
-                if (writer) sm.part[(o_im * NW + wid) * B + jw] = s;
+                if (writer) atomicAdd(&sm.part[o_im * B + jw], s);
             }
             if (SE) {
                 const float s = wave_sum4(sev[0], sev[1], sev[2], sev[3]);
-                if (writer) sm.part[(o_se * NW + wid) * B + jw] = s;
+                if (writer) atomicAdd(&sm.part[o_se * B + jw], s);
             }
         }
         __syncthreads();
@@ -267,9 +267,10 @@ __device__ void render_score_tile(const ViewJob& J, int tile, const potr_config&
             float t[3] = {0.f, 0.f, 0.f};
 #pragma unroll
             for (int o = 0; o < 3; ++o)
-                if (o < n_out)
-#pragma unroll
-                    for (int w = 0; w < NW; ++w) t[o] += sm.part[(o * NW + w) * B + j];
+                if (o < n_out) {
+                    t[o] = sm.part[o * B + j];
+                    sm.part[o * B + j] = 0.f;
+                }
             if (J.scores && t[o_l1] != 0.f) unsafeAtomicAdd(J.scores + id, t[o_l1]);
             if (J.importance && t[o_im] != 0.f) unsafeAtomicAdd(J.importance + id, t[o_im]);
             if (SE && t[o_se] != 0.f) unsafeAtomicAdd(J.scores_se + id, t[o_se]);
@@ -329,7 +330,7 @@ __global__ void k_zero_i64(int64_t* p) { *p = 0; }
 template <int TW, int TH>
 size_t smem_bytes(int B, int n_out) {
     constexpr int NW = (TW * TH + 63) / 64;
-    return (size_t)B * sizeof(Rec) + (size_t)NW * B * 4 + 16 + (size_t)n_out * NW * B * 4;
+    return (size_t)B * sizeof(Rec) + (size_t)NW * B * 4 + 16 + (size_t)n_out * B * 4;
 }
 
 }  // namespace
