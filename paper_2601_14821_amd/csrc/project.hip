@@ -2,9 +2,13 @@
 //
 // One thread per splat; the thread reads the splat's 236 bytes once and loops
 // over the views of the launch, so a batch of views costs one parameter read.
-// The block's SH coefficients (192 B per splat, contiguous) are loaded with
-// coalesced 16-byte loads into LDS, 13 float4 per splat (an odd stride, so a
-// wave's per-splat 16-byte reads hit distinct banks).
+// SH coefficients (192 B per splat, contiguous): with one view per launch each
+// thread reads its splat's as twelve 16-byte loads issued together (a wave's
+// loads cover one contiguous 12 KB span, so every line fetched is used whole
+// through the caches; no barrier, no LDS); with several views per launch the
+// block's coefficients are first staged in LDS with coalesced 16-byte loads,
+// 13 float4 per splat (an odd stride, so a wave's per-splat 16-byte reads hit
+// distinct banks), so that the views after the first do not read them again.
 // All arithmetic is FP64: CDNA's FP64 vector rate is half its FP32 rate and this
 // kernel is bound by HBM (236 B in, 52 B out per splat-view for ~300 flops), so
 // FP64 is free here and keeps every stored FP32 value correctly rounded from a
@@ -52,20 +56,23 @@ constexpr int kProjThreads = 128;
 struct Lims {
     double x[kViewsPerLaunch], y[kViewsPerLaunch];
 };
+
 constexpr int kShStride = 13;   // float4 per splat in LDS (12 used)
 
 // DEG: the SH degree in use (0..3), a template argument so that the colour sum
 // is fully unrolled with every coefficient and basis value in a register.
-template <int DEG>
+// STAGED: SH coefficients staged in LDS (launches of several views).
+template <int DEG, bool STAGED>
 __global__ __launch_bounds__(kProjThreads) void k_project(int64_t N, int32_t v0, int32_t nv, CamBatch cams, Lims lims,
                                                  potr_config cfg, const float* __restrict__ means,
                                                  const float* __restrict__ scales, const float* __restrict__ quats,
                                                  const float* __restrict__ opac, const float* __restrict__ sh,
                                                  potr_proj* __restrict__ proj, int32_t* __restrict__ tiles_touched) {
-    __shared__ float4 s_sh[kProjThreads * kShStride];
     const int64_t i0 = (int64_t)blockIdx.x * kProjThreads;
     const int64_t i = i0 + threadIdx.x;
-    {
+    const float4* sh4;   // this splat's coefficients, 16 bytes at a time
+    if constexpr (STAGED) {
+        __shared__ float4 s_sh[kProjThreads * kShStride];
         // the float4s holding the 3 (degree + 1)^2 coefficients in use
         const int nb = (int)min((int64_t)kProjThreads, N - i0);
         constexpr int n4 = (3 * (DEG + 1) * (DEG + 1) + 3) / 4;
@@ -74,8 +81,11 @@ __global__ __launch_bounds__(kProjThreads) void k_project(int64_t N, int32_t v0,
             const int t = f / n4, m = f - t * n4;
             s_sh[t * kShStride + m] = g4[t * 12 + m];
         }
+        __syncthreads();
+        sh4 = s_sh + threadIdx.x * kShStride;
+    } else {
+        sh4 = reinterpret_cast<const float4*>(sh) + 12 * i;
     }
-    __syncthreads();
     if (i >= N) return;
 
     const float mx = means[3 * i], my = means[3 * i + 1], mz = means[3 * i + 2];
@@ -176,7 +186,6 @@ __global__ __launch_bounds__(kProjThreads) void k_project(int64_t N, int32_t v0,
                 double cr = 0.5, cg = 0.5, cb = 0.5;
                 // 16-byte loads: four coefficients (r,g,b of k and r of k+1, ...) at a time
                 constexpr int n4 = (3 * nsh + 3) / 4;
-                const float4* sh4 = s_sh + threadIdx.x * kShStride;
                 float f[4 * n4];
 #pragma unroll
                 for (int m = 0; m < n4; ++m) {
@@ -229,23 +238,16 @@ potr_status launch_project(int64_t N, int32_t V, const potr_camera* cams, const 
             lm.x[k] = (double)cfg.jclamp * 0.5 * cb.c[k].width / (double)cb.c[k].fx;
             lm.y[k] = (double)cfg.jclamp * 0.5 * cb.c[k].height / (double)cb.c[k].fy;
         }
+        const bool staged = nv > 1;
+        auto go = [&](auto kern) {
+            hipLaunchKernelGGL(kern, grid, dim3(kProjThreads), 0, s, N, v0, nv, cb, lm, cfg, means, scales, quats, opac,
+                               sh, proj, tiles_touched);
+        };
         switch (cfg.sh_degree) {
-            case 0:
-                hipLaunchKernelGGL(k_project<0>, grid, dim3(kProjThreads), 0, s, N, v0, nv, cb, lm, cfg, means, scales,
-                                   quats, opac, sh, proj, tiles_touched);
-                break;
-            case 1:
-                hipLaunchKernelGGL(k_project<1>, grid, dim3(kProjThreads), 0, s, N, v0, nv, cb, lm, cfg, means, scales,
-                                   quats, opac, sh, proj, tiles_touched);
-                break;
-            case 2:
-                hipLaunchKernelGGL(k_project<2>, grid, dim3(kProjThreads), 0, s, N, v0, nv, cb, lm, cfg, means, scales,
-                                   quats, opac, sh, proj, tiles_touched);
-                break;
-            default:
-                hipLaunchKernelGGL(k_project<3>, grid, dim3(kProjThreads), 0, s, N, v0, nv, cb, lm, cfg, means, scales,
-                                   quats, opac, sh, proj, tiles_touched);
-                break;
+            case 0: staged ? go(k_project<0, true>) : go(k_project<0, false>); break;
+            case 1: staged ? go(k_project<1, true>) : go(k_project<1, false>); break;
+            case 2: staged ? go(k_project<2, true>) : go(k_project<2, false>); break;
+            default: staged ? go(k_project<3, true>) : go(k_project<3, false>); break;
         }
         potr_status st = check_launch("k_project");
         if (st != POTR_OK) return st;
