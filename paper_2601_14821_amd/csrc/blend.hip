@@ -51,12 +51,14 @@ __global__ __launch_bounds__(TW * TH) void k_blend(int64_t N, int32_t W, int32_t
                                                    float* __restrict__ p_final, float* __restrict__ t_final,
                                                    int32_t* __restrict__ n_walk, int32_t* __restrict__ n_blend) {
     constexpr int NT = TW * TH;
-    constexpr int NW = (NT + 63) / 64;
-    __shared__ float4 s_a[kMaxBatch];
-    __shared__ float4 s_b[kMaxBatch];
-    __shared__ float s_c[kMaxBatch];
-    __shared__ uint32_t s_rows[kMaxBatch];
-    __shared__ __align__(8) uint16_t s_list[NW][kMaxBatch];
+    // LDS sized by the run's batch (blend_lds_bytes): records, reachable rows, per-wave lists
+    extern __shared__ __align__(16) char smem[];
+    const int B = cfg.lds_batch;
+    float4* const s_a = reinterpret_cast<float4*>(smem);
+    float4* const s_b = s_a + B;
+    float* const s_c = reinterpret_cast<float*>(s_b + B);
+    uint32_t* const s_rows = reinterpret_cast<uint32_t*>(s_c + B);
+    uint16_t* const s_list = reinterpret_cast<uint16_t*>(s_rows + B);   // [NW][B]
     const int tile = blockIdx.x, v = blockIdx.y;
     const int wid = threadIdx.x >> 6;
     const int row_lo = __builtin_amdgcn_readfirstlane((wid * 64) / TW);
@@ -69,7 +71,6 @@ __global__ __launch_bounds__(TW * TH) void k_blend(int64_t N, int32_t W, int32_t
     const int64_t tg = (int64_t)v * tiles_per_view + tile;
     const int beg = ranges[2 * tg], end = ranges[2 * tg + 1];
     const potr_proj* pv = proj + (int64_t)v * N;
-    const int B = cfg.lds_batch;
     const float qmax = cfg.q_max, amin = cfg.alpha_min, amax = cfg.alpha_max, tmin = cfg.t_min;
     const float emin = exp_floor(qmax);
 
@@ -83,7 +84,7 @@ __global__ __launch_bounds__(TW * TH) void k_blend(int64_t N, int32_t W, int32_t
         __syncthreads();
         // this wave's entries (those reaching its rows), each step branch-free: a
         // finished lane takes alpha = 0, which leaves T and the colour unchanged
-        uint16_t* const L = s_list[wid];
+        uint16_t* const L = s_list + wid * B;
         const int nl = wave_list(s_rows, cnt, row_lo, row_hi, L);
         if (__ballot(!done) == 0) continue;
         for (int i = 0; i < nl; i += 4) {
@@ -261,7 +262,9 @@ potr_status blend_shape(int64_t N, int32_t V, const potr_camera& c, const potr_c
                         const uint32_t* ids, const int32_t* ranges, float* image, float* p_final, float* t_final,
                         int32_t* n_walk, int32_t* n_blend, hipStream_t s) {
     const int txs = tiles_x(c, cfg), tpv = txs * tiles_y(c, cfg);
-    hipLaunchKernelGGL((k_blend<TW, TH>), dim3(tpv, V), dim3(TW * TH), 0, s, N, c.width, c.height, txs, tpv, cfg,
+    constexpr int NW = (TW * TH + 63) / 64;
+    const size_t lds = (size_t)cfg.lds_batch * (16 + 16 + 4 + 4 + 2 * NW);
+    hipLaunchKernelGGL((k_blend<TW, TH>), dim3(tpv, V), dim3(TW * TH), lds, s, N, c.width, c.height, txs, tpv, cfg,
                        proj, ids, ranges, image, p_final, t_final, n_walk, n_blend);
     return check_launch("k_blend");
 }
