@@ -25,6 +25,9 @@ Algorithmic work per launch:
   k_render_score: 26 flops per visited (pixel, list entry) + 42 per blended one
                   (blend sweep 13 + 12, removal sweep 13 + 30)
   k_project:      288 bytes per splat-view (236 read, 48 + 4 written)
+`traffic` (HBM bytes) and `valu_issue` (VALU instructions over the chip's issue
+limit of one wave64 instruction per CU per cycle, for the live kernel time) come
+from the committed counter record, null once the kernel's sources differ.
 The CPU baseline is the FP64 oracle on the same view, timed on the host.
 """
 from __future__ import annotations
@@ -42,13 +45,15 @@ if ROOT not in sys.path:
 METRIC = "splat-view removal scores/s (Gsplat·views/s) + fwd+bwd ms/view, % HBM peak"
 HBM_PEAK_GBS = 8000.0
 FP32_VECTOR_PEAK_TFLOPS = 157.3
+VALU_ISSUE_PER_S = 256 * 2.4e9   # wave64 VALU instructions per second, one per CU per cycle
 FUSED_FLOPS_VISIT, FUSED_FLOPS_BLEND = 26.0, 42.0
 PROJECT_BYTES_PER_SPLAT_VIEW = 236 + 48 + 4
 
 
-def measured_traffic(kernel: str):
-    """HBM bytes per launch of `kernel` from the committed counter record, or
-    None when there is none or the kernel's sources changed since it was taken."""
+def measured_counters(kernel: str):
+    """The committed counter record of `kernel` (HBM bytes and VALU instructions
+    per launch), or None when there is none or the kernel's sources changed since
+    it was taken."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "render_score_traffic.json")
     try:
@@ -63,7 +68,13 @@ def measured_traffic(kernel: str):
             h.update(open(os.path.join(ROOT, p), "rb").read())
         except OSError:
             return None
-    return int(rec["bytes_per_launch"]) if h.hexdigest() == rec["sources_sha256"] else None
+    return rec if h.hexdigest() == rec["sources_sha256"] else None
+
+
+def measured_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed counter record, or None."""
+    rec = measured_counters(kernel)
+    return None if rec is None else int(rec["bytes_per_launch"])
 
 
 def cpu_baseline(scene, cams, s):
@@ -147,9 +158,14 @@ def main_line(args, torch, raster, synth):
         achieved, peak, unit = amount / sec, HBM_PEAK_GBS, "GB/s"
     else:
         achieved, peak, unit = amount / sec, FP32_VECTOR_PEAK_TFLOPS, "TFLOP/s"
+    ctr = measured_counters(f"k_{dom}")
+    # VALU issue: the record's wave instructions per launch over the chip's issue limit
+    # (one wave64 VALU instruction per CU per cycle) for the live kernel time
+    valu = ctr.get("valu_insts_per_launch") if ctr else None
     roofline = {"bound": bound, "achieved": round(achieved, 3), "peak": peak, "unit": unit,
                 "frac": round(achieved / peak, 4), "traffic": measured_traffic(f"k_{dom}"), "kernel": f"k_{dom}",
-                "kernel_ms": round(stage_ms[dom], 4)}
+                "kernel_ms": round(stage_ms[dom], 4),
+                "valu_issue": None if valu is None else round(valu / (VALU_ISSUE_PER_S * sec), 4)}
     out = {
         "value": round(N * V / (ms / 1000.0) / 1e9, 4),
         "ms_per_step": round(ms, 4),
