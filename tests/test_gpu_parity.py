@@ -13,7 +13,7 @@ import torch
 
 import oracle
 from paper_2601_14821_amd import _lib as L
-from paper_2601_14821_amd import raster, synth
+from paper_2601_14821_amd import batch, raster, synth
 from score_tolerance import compare_scores, oracle_views
 
 pytestmark = pytest.mark.gpu
@@ -283,3 +283,37 @@ def test_single_view_full_size():
     ref = tot["score_l1"]
     rel = np.abs(sc - ref).sum() / ref.sum()
     assert rel < 1e-4, rel
+
+
+# ---------------------------------------------------------------- full size: 3M splats, 1600x1064
+def test_full_scene_view_and_batched_graph():
+    """One view of the 3M-splat full scene against the oracle; then the batched
+    persistent scorer, replayed as a HIP graph over two views, against the plain
+    per-view path on the same views."""
+    _need_gpu()
+    s = synth.RenderSettings()
+    scene, cams = synth.workload_full_scene(n_views=2)
+    print("gpu run", flush=True)
+    img, sc, _, _ = _run_gpu(scene, cams[:1], s)
+    print("oracle run", flush=True)
+    tot, views = oracle_views(scene, cams[:1], s)
+    err, nf = _compare_view(img[0], views[0])
+    print(f"max err {err:.3g}, flagged {nf} of {img[0].shape[0] * img[0].shape[1]}", flush=True)
+    n_floor = compare_scores(sc, tot["score_l1"], tot["magnitude"], tot["flag_mass"])
+    ref = tot["score_l1"]
+    print(f"scored splats {(ref > 0).sum()}, needing the flag allowance {n_floor}", flush=True)
+    assert np.abs(sc - ref).sum() / ref.sum() < 1e-4
+    print("batched run", flush=True)
+    ds = raster.to_device(scene)
+    plain = torch.zeros(scene.n, device="cuda")
+    raster.Rasterizer(s).score_views(ds, cams, views_per_batch=1, scores=plain)
+    got = torch.zeros(scene.n, device="cuda")
+    bs = batch.BatchScorer([(ds, cams, got)], s, views_per_job=2)
+    bs.capture()
+    bs.replay()
+    torch.cuda.synchronize()
+    assert bs.overflowed() == 0
+    bs.close()
+    a, b = got.cpu().numpy().astype(np.float64), plain.cpu().numpy().astype(np.float64)
+    assert np.abs(a - b).max() <= 2e-5 * np.abs(b).max() + 1e-7
+    assert np.abs(a - b).sum() <= 2e-5 * np.abs(b).sum()
