@@ -242,9 +242,12 @@ POTR_API potr_status potr_backward(int64_t N, int32_t V, const potr_camera* cams
 /* ---------------------------------------------------------------------------
  * potr_render_score -- potr_blend and potr_score fused in one launch per view
  * batch: each tile is composited front to back and its walked prefix revisited
- * for the removal effect, reusing the LDS-staged records. Same results as the
- * two calls (same per-pixel arithmetic). image may be NULL; scores, importance,
- * scores_se as in potr_score (+=; at least one non-NULL; scores_se needs target).
+ * for the removal effect, reusing the LDS-staged records. Same per-pixel
+ * arithmetic as the two calls: the image is bit-identical to potr_blend's, the
+ * per-splat sums equal up to the order of their float additions (over a tile's
+ * waves in LDS, over tiles and views in device atomics). image may be NULL;
+ * scores, importance, scores_se as in potr_score (+=; at least one non-NULL;
+ * scores_se needs target).
  * ------------------------------------------------------------------------- */
 POTR_API potr_status potr_render_score(int64_t N, int32_t V, const potr_camera* cams, const potr_config* cfg,
                                        const potr_proj* proj, const uint32_t* sorted_ids,
