@@ -9,7 +9,8 @@
 // When that prefix fits one LDS batch (the usual case: ~100-200 walked entries
 // per tile), the records staged for the blend are reused without a second
 // gather. The arithmetic per (pixel, splat) is that of potr_blend / potr_score
-// (raster_eval.h), so the results are the same.
+// (raster_eval.h): the images are the same bit for bit, the per-splat sums up to
+// the order of their float additions.
 #include "common.h"
 #include "dpp.h"
 #include "fused.h"
