@@ -132,7 +132,7 @@ POTR_API potr_status potr_project(int64_t N, int32_t V, const potr_camera* cams,
  *   n_pairs (device) int64 out: total number of pairs over all views; -1 if a
  *          device-side wait of the ordering gave up (an internal error, which
  *          later stages treat as "no pairs").
- * Cost: the workspace holds 28 bytes per (view, splat) (depth sort keys and
+ * Cost: the workspace holds 32 bytes per (view, splat) (depth sort keys and
  * values, rects by id and in depth order), 8 bytes per (view, group of 4096
  * ranks, tile) and 4 bytes per (view, group, tile row).
  * ------------------------------------------------------------------------- */

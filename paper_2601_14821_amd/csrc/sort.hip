@@ -13,8 +13,11 @@
 // Depth radix passes are one kernel each: a block of 1024 threads x 4 items
 // ranks its keys per digit with 64-lane ballots (stable order: wave, item,
 // lane), publishes its digit counts, and finds the counts of all blocks before
-// it by decoupled look-back over their published words. The digit totals of
-// all passes come from one histogram read up front. Blocks take their place in
+// it by decoupled look-back over their published words. The passes sort by
+// key - min over the view's keys: a view whose keys span fewer than 2^24 (2^16,
+// 2^8) values needs three (two, one) passes, and the rest return at once. The
+// key range, then the digit totals of the passes needed, come from two reads
+// up front. Blocks take their place in
 // the chain from an atomic ticket, so a block only ever waits on blocks that
 // are already running. Each block sorts its keys in LDS and writes every
 // digit's run to consecutive addresses. Every wait is bounded: after
@@ -158,7 +161,7 @@ __device__ inline int64_t seg_n(const Seg& g) {
 }
 
 struct Pass {
-    int32_t shift, bits;
+    int32_t pass, shift, bits;
     uint32_t tag;             // 1 + pass index
     const uint32_t* ghist;    // this pass's digit totals at ghist[seg * kMaxPasses * 256 + digit]
     uint64_t* status;         // [seg][bps][1 << bits]
@@ -166,20 +169,20 @@ struct Pass {
     uint32_t* fault;
 };
 
-// Depth keys, rects and the digit totals of every pass, per view, in one read
-// of the records (the depth and the rect sit in the same 16 bytes of a record).
-// The keys go to keys_out, the rects to rect_out, packed as the two words
-// (x0 | x1 << 16, y0 | y1 << 16) for tiles [x0, x1) x [y0, y1). Eight records
-// per thread keep the global atomics that merge the block histograms few while
-// leaving enough blocks to keep loads in flight.
+// Depth keys, rects and the range of the keys, per view, in one read of the
+// records (the depth and the rect sit in the same 16 bytes of a record). The
+// keys go to keys_out, the rects to rect_out, packed as the two words
+// (x0 | x1 << 16, y0 | y1 << 16) for tiles [x0, x1) x [y0, y1); krange[v] gets
+// the largest key and the largest complemented key (so the smallest key is its
+// complement, and the cleared words are the identity of both maxima).
 constexpr int kHistThreads = 256;
 constexpr int kHistItems = 8;
 
-__global__ __launch_bounds__(kHistThreads) void k_hist(const potr_proj* __restrict__ proj, int64_t N,
+__global__ __launch_bounds__(kHistThreads) void k_keys(const potr_proj* __restrict__ proj, int64_t N,
                                                       uint32_t* __restrict__ keys_out, uint2* __restrict__ rect_out,
-                                                      uint32_t* __restrict__ ghist) {
-    __shared__ uint32_t h[kMaxPasses][256];
-    for (int t = threadIdx.x; t < kMaxPasses * 256; t += kHistThreads) (&h[0][0])[t] = 0;
+                                                      uint32_t* __restrict__ krange) {
+    __shared__ uint32_t s_hi, s_lo;
+    if (threadIdx.x == 0) s_hi = s_lo = 0u;
     __syncthreads();
     const int v = blockIdx.y;
     const int64_t base = (int64_t)v * N;
@@ -191,6 +194,7 @@ __global__ __launch_bounds__(kHistThreads) void k_hist(const potr_proj* __restri
         const int64_t e = min(e0 + (int64_t)k * kHistThreads, N - 1);
         q[k] = reinterpret_cast<const uint4*>(proj + base + e)[2];   // rgb[2], depth, rect
     }
+    uint32_t hi = 0u, lo = 0u;   // largest key, largest complemented key
 #pragma unroll
     for (int k = 0; k < kHistItems; ++k) {
         const int64_t e = e0 + (int64_t)k * kHistThreads;
@@ -198,24 +202,71 @@ __global__ __launch_bounds__(kHistThreads) void k_hist(const potr_proj* __restri
             const uint32_t key = q[k].y;
             keys_out[base + e] = key;
             rect_out[base + e] = make_uint2((q[k].z & 0xffffu) | (q[k].w << 16), (q[k].z >> 16) | (q[k].w & 0xffff0000u));
-#pragma unroll
-            for (int p = 0; p < kMaxPasses; ++p) atomicAdd(&h[p][(key >> (8 * p)) & 255u], 1u);
+            hi = max(hi, key);
+            lo = max(lo, ~key);
         }
     }
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) {
+        hi = max(hi, (uint32_t)__shfl_xor((int)hi, m, 64));
+        lo = max(lo, (uint32_t)__shfl_xor((int)lo, m, 64));
+    }
+    if ((threadIdx.x & 63) == 0) {
+        atomicMax(&s_hi, hi);
+        atomicMax(&s_lo, lo);
+    }
     __syncthreads();
-    for (int t = threadIdx.x; t < kMaxPasses * 256; t += kHistThreads) {
+    if (threadIdx.x == 0) {
+        atomicMax(krange + 2 * v, s_hi);
+        atomicMax(krange + 2 * v + 1, s_lo);
+    }
+}
+
+// Radix passes needed for the offsets key - min of one view: 8 bits each, at
+// least one (which then also writes the identity order of equal keys).
+__device__ inline int passes_of(const uint32_t* krange, int v, uint32_t& kmin) {
+    const uint32_t hi = krange[2 * v];
+    kmin = ~krange[2 * v + 1];
+    const uint32_t span = hi >= kmin ? hi - kmin : 0u;
+    const int bits = span ? 32 - __clz((int)span) : 0;
+    return max(1, (bits + 7) / 8);
+}
+
+// Digit totals of the passes a view needs, over the offsets key - min.
+__global__ __launch_bounds__(kHistThreads) void k_digits(const uint32_t* __restrict__ keys, int64_t N,
+                                                        const uint32_t* __restrict__ krange,
+                                                        uint32_t* __restrict__ ghist) {
+    __shared__ uint32_t h[kMaxPasses][256];
+    for (int t = threadIdx.x; t < kMaxPasses * 256; t += kHistThreads) (&h[0][0])[t] = 0;
+    __syncthreads();
+    const int v = blockIdx.y;
+    uint32_t kmin;
+    const int np = passes_of(krange, v, kmin);
+    const int64_t base = (int64_t)v * N;
+    const int64_t e0 = (int64_t)blockIdx.x * (kHistThreads * kHistItems) + threadIdx.x;
+    uint32_t d[kHistItems];
+#pragma unroll
+    for (int k = 0; k < kHistItems; ++k) d[k] = keys[base + min(e0 + (int64_t)k * kHistThreads, N - 1)] - kmin;
+#pragma unroll
+    for (int k = 0; k < kHistItems; ++k)
+        if (e0 + (int64_t)k * kHistThreads < N)
+            for (int p = 0; p < np; ++p) atomicAdd(&h[p][(d[k] >> (8 * p)) & 255u], 1u);
+    __syncthreads();
+    for (int t = threadIdx.x; t < np * 256; t += kHistThreads) {
         const uint32_t c = (&h[0][0])[t];
         if (c) atomicAdd(ghist + (int64_t)v * kMaxPasses * 256 + t, c);
     }
 }
 
-// One stable radix pass over the depth keys of every view. MODE 0: keys and
-// values (values from vin, or the element's index when vin == nullptr);
-// MODE 1 (last pass): only the values go out, to vout.
-template <int MODE>
+// One stable radix pass over the depth keys of every view, by the digits of
+// key - min (the view's passes_of decides how many passes it needs; the later
+// ones return at once). Values come from vin, or are the element's index when
+// vin == nullptr. A view's last pass writes only the values, to vfinal; the
+// others write keys to kout and values to vout.
 __global__ __launch_bounds__(kSwThreads) void k_sweep(const uint32_t* __restrict__ kin, uint32_t* __restrict__ kout,
                                                     const uint32_t* __restrict__ vin, uint32_t* __restrict__ vout,
-                                                    Seg g, Pass P) {
+                                                    uint32_t* __restrict__ vfinal, Seg g, Pass P,
+                                                    const uint32_t* __restrict__ krange) {
     __shared__ uint32_t wcnt[kSwWaves][256];
     __shared__ uint32_t goff[256];
     __shared__ uint32_t boff[256];
@@ -230,6 +281,10 @@ __global__ __launch_bounds__(kSwThreads) void k_sweep(const uint32_t* __restrict
     __syncthreads();
     const int seg = (int)(s_ticket / (uint32_t)g.bps);
     const int64_t b = (int64_t)(s_ticket - (uint32_t)seg * (uint32_t)g.bps);
+    uint32_t kmin;
+    const int np = passes_of(krange, seg, kmin);
+    if (P.pass >= np) return;   // every block of this view returns: nobody waits on them
+    const bool last = P.pass == np - 1;
     const int64_t n = seg_n(g);
     const int64_t seg0 = (int64_t)seg * g.len;
     const int64_t blk0 = b * kTile;
@@ -254,7 +309,7 @@ __global__ __launch_bounds__(kSwThreads) void k_sweep(const uint32_t* __restrict
     for (int k = 0; k < kSwItems; ++k) {
         const int64_t e = wbase + k * 64 + lane;
         const bool ok = e < n;
-        const uint32_t d = digit_of(key[k], P.shift, mask);
+        const uint32_t d = digit_of(key[k] - kmin, P.shift, mask);
         uint32_t below, cnt;
         match_rank<8>(d, ok, below, cnt);
         uint32_t r = 0;
@@ -295,7 +350,7 @@ __global__ __launch_bounds__(kSwThreads) void k_sweep(const uint32_t* __restrict
 #pragma unroll
     for (int k = 0; k < kSwItems; ++k) {
         if (rnk[k] == 0xffffffffu) continue;
-        const uint32_t d = digit_of(key[k], P.shift, mask);
+        const uint32_t d = digit_of(key[k] - kmin, P.shift, mask);
         const uint32_t p = boff[d] + wcnt[w][d] + rnk[k];
         s_key[p] = key[k];
         s_val[p] = val[k];
@@ -306,14 +361,18 @@ __global__ __launch_bounds__(kSwThreads) void k_sweep(const uint32_t* __restrict
     const int cnt_blk = left < kTile ? (int)(left > 0 ? left : 0) : kTile;
     for (int i = threadIdx.x; i < cnt_blk; i += kSwThreads) {
         const uint32_t kk = s_key[i];
-        const uint32_t d = digit_of(kk, P.shift, mask);
+        const uint32_t d = digit_of(kk - kmin, P.shift, mask);
         const int64_t pos = seg0 + (int64_t)goff[d] + (i - (int)boff[d]);
-        if (MODE == 0) kout[pos] = kk;
-        vout[pos] = s_val[i];
+        if (last) {
+            vfinal[pos] = s_val[i];
+        } else {
+            kout[pos] = kk;
+            vout[pos] = s_val[i];
+        }
     }
 }
 
-// Clears 64-bit words (look-back status, digit totals, tickets).
+// Clears 64-bit words (look-back status, digit totals, key range, tickets).
 __global__ void k_clear(uint64_t* __restrict__ p, int64_t n) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
         p[i] = 0;
@@ -788,12 +847,13 @@ __global__ __launch_bounds__(256) void k_place(const uint2* __restrict__ srect, 
 
 // ---------------------------------------------------------------- host side
 // Region at the front of the workspace, cleared at the start of every bin:
-// tickets (one per depth pass), the fault word, digit totals and the look-back
-// status words.
+// tickets (one per depth pass), the fault word, digit totals, the key range and
+// the look-back status words.
 struct Ctl {
     uint32_t* ticket;
     uint32_t* fault;
     uint32_t* ghist;
+    uint32_t* krange;   // per view: largest key, largest complemented key
     uint64_t* status;
     int64_t clear_words;
 };
@@ -816,7 +876,7 @@ Bins bins_of(int64_t N, int32_t V, int32_t tiles_x, int32_t tiles_y) {
 
 struct BinWs {
     Ctl ctl;
-    uint32_t *ka, *kb, *va;
+    uint32_t *ka, *kb, *va, *vb;
     uint2 *crect, *srect;   // rects by splat id, and in depth order
     uint32_t *gsum, *rtot;
     int64_t* rbase;
@@ -835,6 +895,7 @@ BinWs bin_layout(int64_t N, int32_t V, int32_t tiles_x, int32_t tiles_y, char* b
     w.ctl.ticket = (uint32_t*)take(4 * (kMaxPasses + 2));
     w.ctl.fault = w.ctl.ticket + kMaxPasses + 1;
     w.ctl.ghist = (uint32_t*)take(4 * (size_t)V * kMaxPasses * 256);
+    w.ctl.krange = (uint32_t*)take(4 * 2 * (size_t)V);
     w.ctl.status = (uint64_t*)take(8 * (size_t)V * bps * 256);
     const size_t ty = (size_t)tiles_y, T = (size_t)B.T;
     // cleared with the control words: the sums the group counts add into
@@ -843,6 +904,7 @@ BinWs bin_layout(int64_t N, int32_t V, int32_t tiles_x, int32_t tiles_y, char* b
     w.ka = (uint32_t*)take(4 * VN);
     w.kb = (uint32_t*)take(4 * VN);
     w.va = (uint32_t*)take(4 * VN);
+    w.vb = (uint32_t*)take(4 * VN);
     w.crect = (uint2*)take(8 * VN);
     w.srect = (uint2*)take(8 * VN);
     w.gsum = (uint32_t*)take(4 * (size_t)V * ty * B.G);
@@ -856,11 +918,10 @@ BinWs bin_layout(int64_t N, int32_t V, int32_t tiles_x, int32_t tiles_y, char* b
 }
 
 
-template <int MODE>
-potr_status sweep(const uint32_t* kin, uint32_t* kout, const uint32_t* vin, uint32_t* vout, const Seg& g, int segs,
-                  const Pass& P, hipStream_t s) {
-    hipLaunchKernelGGL((k_sweep<MODE>), dim3((unsigned)((int64_t)g.bps * segs)), dim3(kSwThreads), 0, s, kin, kout,
-                       vin, vout, g, P);
+potr_status sweep(const uint32_t* kin, uint32_t* kout, const uint32_t* vin, uint32_t* vout, uint32_t* vfinal,
+                  const Seg& g, int segs, const Pass& P, const uint32_t* krange, hipStream_t s) {
+    hipLaunchKernelGGL(k_sweep, dim3((unsigned)((int64_t)g.bps * segs)), dim3(kSwThreads), 0, s, kin, kout, vin, vout,
+                       vfinal, g, P, krange);
     return check_launch("k_sweep");
 }
 
@@ -900,20 +961,24 @@ potr_status launch_bin(int64_t N, int32_t V, const potr_camera& cam0, const potr
     potr_status st = check_launch("k_clear");
     if (st != POTR_OK) return st;
     if (N > 0) {
-        // stable per-view sort of the 32-bit depth keys: four 8-bit passes
+        // stable per-view sort of the 32-bit depth keys by key - min: as many
+        // 8-bit passes as the view's span of keys needs (the rest return at once)
         Seg g{N, nullptr, 0, (int32_t)ceil_div(N, kTile)};
-        hipLaunchKernelGGL(k_hist, dim3((unsigned)ceil_div(N, kHistThreads * kHistItems), V), dim3(kHistThreads), 0,
-                           s, proj, N, w.ka, w.crect, w.ctl.ghist);
-        st = check_launch("k_hist");
+        const dim3 kg((unsigned)ceil_div(N, kHistThreads * kHistItems), V);
+        hipLaunchKernelGGL(k_keys, kg, dim3(kHistThreads), 0, s, proj, N, w.ka, w.crect, w.ctl.krange);
+        st = check_launch("k_keys");
+        if (st != POTR_OK) return st;
+        hipLaunchKernelGGL(k_digits, kg, dim3(kHistThreads), 0, s, (const uint32_t*)w.ka, N,
+                           (const uint32_t*)w.ctl.krange, w.ctl.ghist);
+        st = check_launch("k_digits");
         if (st != POTR_OK) return st;
         uint32_t *kin = w.ka, *kout = w.kb;
         const uint32_t* vin = nullptr;
-        uint32_t* vbuf[2] = {w.va, order};
-        for (int pass = 0; pass < 4; ++pass) {
-            Pass P{8 * pass, 8, (uint32_t)(1 + pass), w.ctl.ghist + pass * 256, w.ctl.status, w.ctl.ticket + pass,
-                   w.ctl.fault};
-            st = pass < 3 ? sweep<0>(kin, kout, vin, vbuf[pass & 1], g, V, P, s)
-                          : sweep<1>(kin, nullptr, vin, order, g, V, P, s);
+        uint32_t* vbuf[2] = {w.va, w.vb};   // never the output: a view's last pass may be any of them
+        for (int pass = 0; pass < kMaxPasses; ++pass) {
+            Pass P{pass, 8 * pass, 8, (uint32_t)(1 + pass), w.ctl.ghist + pass * 256, w.ctl.status,
+                   w.ctl.ticket + pass, w.ctl.fault};
+            st = sweep(kin, kout, vin, vbuf[pass & 1], order, g, V, P, w.ctl.krange, s);
             if (st != POTR_OK) return st;
             vin = vbuf[pass & 1];
             uint32_t* t = kin;

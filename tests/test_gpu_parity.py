@@ -95,7 +95,28 @@ def test_bin_sort_bit_exact_on_synthetic_records(N, V, tiles, seed, big):
         r, d = synth.random_tile_records(N, tx, ty, seed * 10 + v, **kw)
         rects.append(r)
         depths.append(d)
-    rect, depth = np.stack(rects), np.stack(depths)
+    _check_bin_sort(np.stack(rects), np.stack(depths), V, N, tx, ty, tile)
+
+
+@pytest.mark.parametrize("spread", [1, 200, 60_000, 5_000_000, 1 << 28])
+def test_bin_sort_narrow_depth_spans(spread):
+    """Depth keys spanning 1 value (all equal), under 2^8, 2^16, 2^24 and over 2^24
+    values: the depth sort takes 1, 1, 2, 3 and 4 passes over key - min, views of
+    one call may need different counts, and the order must be the oracle's."""
+    _need_gpu()
+    N, V, tx, ty = 20000, 3, 40, 23
+    rects, depths = [], []
+    for v in range(V):
+        r, _ = synth.random_tile_records(N, tx, ty, 900 + v)
+        rng = np.random.default_rng(950 + v)
+        span = spread if v < 2 else 1 << 28   # the last view always takes four passes
+        keys = np.uint32(0x3FC00000) + rng.integers(0, span, N).astype(np.uint32)   # 1.5f upward, ties included
+        rects.append(r)
+        depths.append(keys.view(np.float32))
+    _check_bin_sort(np.stack(rects), np.stack(depths), V, N, tx, ty, 16)
+
+
+def _check_bin_sort(rect, depth, V, N, tx, ty, tile):
     s = synth.RenderSettings(tile_w=tile, tile_h=tile, lds_batch=64 if tile == 8 else 320)
     cam = synth.Camera(np.eye(3, dtype=np.float32), np.zeros(3, np.float32), 1.0, 1.0, 0.0, 0.0, tx * tile, ty * tile)
     cams = [cam] * V
