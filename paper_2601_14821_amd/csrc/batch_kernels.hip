@@ -10,15 +10,22 @@ __global__ void k_zero_counts(int64_t* c, int32_t n) {
     if (i < n) c[i] = 0;
 }
 
-// counts[v] += sum of tiles_touched over the N splats of view v
+// counts[v] += sum of tiles_touched over the N splats of view v: one device
+// atomic per block (atomics on one word serialise, so there are few blocks)
 __global__ __launch_bounds__(256) void k_sum_tiles(const int32_t* __restrict__ tt, int64_t N,
                                                    int64_t* __restrict__ counts) {
+    __shared__ int64_t s_w[4];
     const int v = blockIdx.y;
     int64_t acc = 0;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (int64_t)gridDim.x * blockDim.x)
         acc += tt[(int64_t)v * N + i];
     for (int m = 32; m >= 1; m >>= 1) acc += __shfl_xor(acc, m, 64);
-    if ((threadIdx.x & 63) == 0 && acc != 0) atomicAdd((unsigned long long*)&counts[v], (unsigned long long)acc);
+    if ((threadIdx.x & 63) == 0) s_w[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const int64_t b = s_w[0] + s_w[1] + s_w[2] + s_w[3];
+        if (b != 0) atomicAdd((unsigned long long*)&counts[v], (unsigned long long)b);
+    }
 }
 
 __global__ void k_check_overflow(const int64_t* __restrict__ n_pairs, const int64_t* __restrict__ caps, int32_t n,
@@ -39,8 +46,8 @@ potr_status launch_count_pairs(int64_t N, int32_t V, const potr_camera* cams, co
     if (st != POTR_OK) return st;
     st = launch_project(N, V, cams, cfg, means, scales, quats, opac, sh, proj, tt, s);
     if (st != POTR_OK || N == 0) return st;
-    int64_t blocks = ceil_div(N, 256);
-    if (blocks > 1024) blocks = 1024;
+    int64_t blocks = ceil_div(N, 256 * 16);   // at least 16 values per thread, at most 128 atomics per view
+    if (blocks > 128) blocks = 128;
     hipLaunchKernelGGL(k_sum_tiles, dim3((unsigned)blocks, V), dim3(256), 0, s, tt, N, counts);
     return check_launch("k_sum_tiles");
 }
