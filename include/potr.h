@@ -272,7 +272,10 @@ POTR_API potr_status potr_render_score(int64_t N, int32_t V, const potr_camera* 
  *   workspace; bind uploads the job table into it (synchronises).
  * potr_batch_pairs: counted pairs and capacities per job (host arrays [n_jobs]).
  * potr_batch_run: enqueues the whole batch; no allocation, no host sync, safe to
- *   capture. Scores accumulate (+=) into each job's buffers.
+ *   capture. Jobs run in up to four lanes (own scratch in the workspace, own
+ *   default-priority stream created with the batch), forked from `stream` after
+ *   the work already on it and joined back before the render launch. Scores
+ *   accumulate (+=) into each job's buffers.
  * potr_batch_capture / potr_batch_replay: record potr_batch_run into a graph on
  *   `stream` (not the null stream) / launch it.
  * potr_batch_overflow: after a run, the number of jobs whose pairs exceeded

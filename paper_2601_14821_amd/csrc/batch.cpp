@@ -30,7 +30,13 @@ struct potr_batch_s {
     // workspace layout (byte offsets)
     struct JobOff { size_t proj, ids, ranges; };
     std::vector<JobOff> off;
-    size_t off_tt = 0, off_order = 0, off_bin = 0, off_stage = 0;
+    // jobs run in lanes (job j in lane j % lanes): each lane has its own scratch
+    // (tiles_touched, depth order, bin and sort workspaces) and, with more than
+    // one lane, its own stream, forked from and joined back into the caller's
+    struct LaneOff { size_t tt, order, bin, stage; };
+    std::vector<LaneOff> lane_off;
+    std::vector<hipStream_t> lane_s;
+    std::vector<hipEvent_t> lane_ev;   // [0]: fork; [1 + l]: lane l done
     size_t off_table = 0, off_prefix = 0, off_counter = 0, off_npairs = 0, off_caps = 0, off_flag = 0;
     size_t bytes = 0;
     int32_t n_view_jobs = 0;
@@ -41,6 +47,8 @@ struct potr_batch_s {
 };
 
 namespace {
+
+constexpr size_t kLanes = 4;   // jobs in flight at once (streams of default priority)
 
 int tiles_of(const potr_camera& c, const potr_config& g) { return tiles_x(c, g) * tiles_y(c, g); }
 
@@ -67,10 +75,13 @@ void plan_layout(potr_batch_s* b) {
         max_stage = std::max(max_stage, sort_workspace_bytes(b->capacity[j]));
         b->n_view_jobs += J.V;
     }
-    b->off_tt = take(max_tt);
-    b->off_order = take(max_tt);
-    b->off_bin = take(max_bin);
-    b->off_stage = take(max_stage);
+    b->lane_off.resize(std::min(kLanes, b->jobs.size()));
+    for (auto& L : b->lane_off) {
+        L.tt = take(max_tt);
+        L.order = take(max_tt);
+        L.bin = take(max_bin);
+        L.stage = take(max_stage);
+    }
     b->off_table = take((size_t)b->n_view_jobs * sizeof(ViewJob));
     b->off_prefix = take((size_t)(b->n_view_jobs + 1) * 8);
     b->off_counter = take(8);
@@ -166,6 +177,23 @@ potr_status potr_batch_create(const potr_job* jobs, int32_t n_jobs, const potr_c
     }
     plan_layout(b);
     b->grid = persistent_grid(b->cfg);
+    if (b->lane_off.size() > 1) {
+        st = POTR_OK;
+        for (size_t l = 0; l < b->lane_off.size() && st == POTR_OK; ++l) {
+            hipStream_t ls = nullptr;
+            st = hip_ok(hipStreamCreateWithFlags(&ls, hipStreamNonBlocking), "lane stream");
+            if (st == POTR_OK) b->lane_s.push_back(ls);
+        }
+        for (size_t e = 0; e < 1 + b->lane_off.size() && st == POTR_OK; ++e) {
+            hipEvent_t ev = nullptr;
+            st = hip_ok(hipEventCreateWithFlags(&ev, hipEventDisableTiming), "lane event");
+            if (st == POTR_OK) b->lane_ev.push_back(ev);
+        }
+        if (st != POTR_OK) {
+            potr_batch_destroy(b);
+            return st;
+        }
+    }
     *out = b;
     return POTR_OK;
 }
@@ -228,19 +256,36 @@ potr_status potr_batch_run(potr_batch b, void* stream) {
     hipStream_t s = (hipStream_t)stream;
     char* ws = b->ws;
     int64_t* npairs = (int64_t*)(ws + b->off_npairs);
+    // fork: every lane starts after what the caller enqueued before this run
+    if (!b->lane_s.empty()) {
+        potr_status st = hip_ok(hipEventRecord(b->lane_ev[0], s), "fork record");
+        for (size_t l = 0; l < b->lane_s.size() && st == POTR_OK; ++l)
+            st = hip_ok(hipStreamWaitEvent(b->lane_s[l], b->lane_ev[0], 0), "fork wait");
+        if (st != POTR_OK) return st;
+    }
     for (size_t j = 0; j < b->jobs.size(); ++j) {
         const potr_job& J = b->jobs[j];
         const potr_camera* cams = b->cams[j].data();
         potr_proj* proj = (potr_proj*)(ws + b->off[j].proj);
-        int32_t* tt = (int32_t*)(ws + b->off_tt);
-        uint32_t* order = (uint32_t*)(ws + b->off_order);
+        const size_t lane = j % b->lane_off.size();
+        const auto& L = b->lane_off[lane];
+        const hipStream_t ls = b->lane_s.empty() ? s : b->lane_s[lane];
+        int32_t* tt = (int32_t*)(ws + L.tt);
+        uint32_t* order = (uint32_t*)(ws + L.order);
         uint32_t* ids = (uint32_t*)(ws + b->off[j].ids);
         int32_t* ranges = (int32_t*)(ws + b->off[j].ranges);
-        potr_status st = launch_project(J.N, J.V, cams, b->cfg, J.means, J.scales, J.quats, J.opac, J.sh, proj, tt, s);
-        if (st == POTR_OK) st = launch_bin(J.N, J.V, cams[0], b->cfg, proj, ws + b->off_bin, order, npairs + j, s);
+        potr_status st =
+            launch_project(J.N, J.V, cams, b->cfg, J.means, J.scales, J.quats, J.opac, J.sh, proj, tt, ls);
+        if (st == POTR_OK) st = launch_bin(J.N, J.V, cams[0], b->cfg, proj, ws + L.bin, order, npairs + j, ls);
         if (st == POTR_OK)
-            st = launch_sort(J.N, J.V, cams[0], b->cfg, proj, order, ws + b->off_bin, npairs + j, b->capacity[j],
-                             ws + b->off_stage, ids, ranges, s);
+            st = launch_sort(J.N, J.V, cams[0], b->cfg, proj, order, ws + L.bin, npairs + j, b->capacity[j],
+                             ws + L.stage, ids, ranges, ls);
+        if (st != POTR_OK) return st;
+    }
+    // join: the render waits for every lane
+    for (size_t l = 0; l < b->lane_s.size(); ++l) {
+        potr_status st = hip_ok(hipEventRecord(b->lane_ev[1 + l], b->lane_s[l]), "join record");
+        if (st == POTR_OK) st = hip_ok(hipStreamWaitEvent(s, b->lane_ev[1 + l], 0), "join wait");
         if (st != POTR_OK) return st;
     }
     potr_status st = launch_render_score_persistent((const ViewJob*)(ws + b->off_table), b->n_view_jobs,
@@ -288,6 +333,11 @@ potr_status potr_batch_destroy(potr_batch b) {
     if (!b) return POTR_OK;
     if (b->exec) hipGraphExecDestroy(b->exec);
     if (b->graph) hipGraphDestroy(b->graph);
+    for (hipStream_t ls : b->lane_s) {
+        hipStreamSynchronize(ls);
+        hipStreamDestroy(ls);
+    }
+    for (hipEvent_t ev : b->lane_ev) hipEventDestroy(ev);
     delete b;
     return POTR_OK;
 }
