@@ -4,14 +4,17 @@
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--main-only]
 
 Main line (the `value`): one step = one pass of the whole path over the
-single-view workload (500,000 clustered splats, one 1280x720 view): zero the
-scores, project, bin, sort, and the fused composite + removal pass, as plain
-per-view launches. Inputs are resident in HBM before the timed region.
+full-scene workload (3,000,000 clustered splats, all 200 hemisphere views at
+1600x1064, removal scores accumulated over the views): the batched path
+replayed as one HIP graph (per job of 8 views: project, bin, sort; then one
+persistent fused composite + removal launch over every (view, tile) of all
+jobs). Inputs are resident in HBM before the timed region. The same pass as
+plain per-view launches (project, bin, sort, fused render + removal per view)
+is reported beside it.
 
 Also reported (extra fields):
-  batched: 3M clustered splats x 16 of the 200 hemisphere views at 1600x1064,
-           plain per-view launches vs one HIP-graph replay of the batched
-           persistent scorer (ms per view, Gsplat.views/s);
+  single_view: 500,000 clustered splats, one 1280x720 view, plain launches,
+           with the time of each stage;
   multi_scene: 16 clustered scenes of uneven size (50k..2M splats, 8..32
            views each, 640x480 / 1280x720 / 1600x1064): tile shape and LDS
            batch picked by the autotuner on the whole batch, then one HIP-graph
@@ -19,16 +22,19 @@ Also reported (extra fields):
   fwd_bwd: 1M splats x 4 views at 1280x720, forward + L1 loss gradient +
            hand-written backward, ms per view.
 
-Roofline: the kernel that takes the most time in the main line, timed with HIP
-events on the library's stream around the one call that launches only it.
+Roofline: the persistent render + removal kernel, which takes most of the main
+line's time, timed with HIP events on the stream it runs on around
+potr_batch_render (that launch alone, over the lists of the last replay).
 Algorithmic work per launch:
-  k_render_score: 26 flops per visited (pixel, list entry) + 42 per blended one
-                  (blend sweep 13 + 12, removal sweep 13 + 30)
-  k_project:      288 bytes per splat-view (236 read, 48 + 4 written)
-`traffic` (HBM bytes) and `valu_issue` (VALU instructions over the chip's issue
-limit of one wave64 instruction per CU per cycle, for the live kernel time) come
-from the committed counter record, null once the kernel's sources differ.
-The CPU baseline is the FP64 oracle on the same view, timed on the host.
+  26 flops per visited (pixel, list entry) + 42 per blended one
+  (blend sweep 13 + 12, removal sweep 13 + 30), visited and blended counted
+  over all 200 views outside the timed region.
+`traffic` (HBM bytes per launch) and `valu_issue` (VALU instructions over the
+chip's issue limit of one wave64 instruction per CU per cycle, for the live
+kernel time) come from the committed counter record of that kernel on this
+workload, null once the kernel's sources differ.
+The CPU baseline is the FP64 oracle on view 0 of the same scene, timed on the
+host with all its cores and with one.
 """
 from __future__ import annotations
 
@@ -47,15 +53,16 @@ HBM_PEAK_GBS = 8000.0
 FP32_VECTOR_PEAK_TFLOPS = 157.3
 VALU_ISSUE_PER_S = 256 * 2.4e9   # wave64 VALU instructions per second, one per CU per cycle
 FUSED_FLOPS_VISIT, FUSED_FLOPS_BLEND = 26.0, 42.0
-PROJECT_BYTES_PER_SPLAT_VIEW = 236 + 48 + 4
+VIEWS_PER_JOB = 8
+COUNTER_RECORD = "render_score_persistent_full_scene_counters.json"
 
 
-def measured_counters(kernel: str):
-    """The committed counter record of `kernel` (HBM bytes and VALU instructions
-    per launch), or None when there is none or the kernel's sources changed since
-    it was taken."""
+def measured_counters(kernel: str, record: str):
+    """The committed counter record `record` of `kernel` (HBM bytes and VALU
+    instructions per launch), or None when there is none or the kernel's sources
+    changed since it was taken."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "render_score_traffic.json")
+    path = os.path.join(ROOT, "profiles", record)
     try:
         rec = json.load(open(path))
     except (OSError, ValueError):
@@ -71,26 +78,155 @@ def measured_counters(kernel: str):
     return rec if h.hexdigest() == rec["sources_sha256"] else None
 
 
-def measured_traffic(kernel: str):
-    """HBM bytes per launch of `kernel` from the committed counter record, or None."""
-    rec = measured_counters(kernel)
-    return None if rec is None else int(rec["bytes_per_launch"])
+def host_cpu():
+    """Host CPU model and the CPUs this process may run on."""
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count()
+    return {"model": model, "nproc": os.cpu_count(), "usable": usable}
 
 
 def cpu_baseline(scene, cams, s):
+    """The FP64 oracle on view 0: projection and tile lists (single-threaded in the
+    oracle), then compositing and removal scores with all usable cores (at most
+    16, the host share of one GPU) and again with one core."""
     import oracle
     threads = oracle.default_threads()
+    cam = cams[0]
     t0 = time.perf_counter()
-    r = oracle.render(scene, cams[0], s, threads=threads, want=("image", "score_l1"))
-    dt = time.perf_counter() - t0
-    return {"value": scene.n * 1 / dt / 1e9, "unit": "Gsplat·views/s", "cores": threads, "kind": "oracle",
-            "sample": (f"the full first view ({scene.n} splats, {cams[0].width}x{cams[0].height}): FP64 "
-                       f"projection and tile lists (1 thread) + compositing and removal scores "
-                       f"({threads} threads); {dt:.2f} s"),
-            "seconds": round(dt, 3), "pairs": int(len(r["bins"][1]))}
+    proj = oracle.project(scene, cam, s)
+    t1 = time.perf_counter()
+    bins = oracle.bin_sort(proj["rect"], proj["depth_key"], *s.tiles(cam))
+    t2 = time.perf_counter()
+    oracle.render(scene, cam, s, proj=proj, bins=bins, threads=threads, want=("image", "score_l1"))
+    t3 = time.perf_counter()
+    oracle.render(scene, cam, s, proj=proj, bins=bins, threads=1, want=("image", "score_l1"))
+    t4 = time.perf_counter()
+    prep = t2 - t0
+    all_s, one_s = prep + (t3 - t2), prep + (t4 - t3)
+    return {"value": scene.n / all_s / 1e9, "unit": "Gsplat·views/s", "cores": threads, "kind": "oracle",
+            "sample": (f"view 0 of the {len(cams)} ({scene.n} splats, {cam.width}x{cam.height}): FP64 projection "
+                       f"and tile lists (1 thread, {prep:.2f} s), compositing and removal scores with {threads} "
+                       f"threads ({t3 - t2:.2f} s) and with 1 ({t4 - t3:.2f} s)"),
+            "seconds": round(all_s, 3), "one_core": {"value": scene.n / one_s / 1e9, "seconds": round(one_s, 3)},
+            "pairs": int(len(bins[1])), "host": host_cpu()}
 
 
-def main_line(args, torch, raster, synth):
+def view_work(torch, rz, ds, cams):
+    """(pairs, visited, blended) over the views: list entries walked and splats
+    blended per pixel, summed (the blend's own counters, one view at a time)."""
+    pairs = visited = blended = 0
+    for cam in cams:
+        vb = rz.project(ds, [cam])
+        rz.bin(vb, [cam])
+        rz.sort(vb, [cam])
+        rz.blend(vb, [cam], count_blended=True)
+        pairs += vb.n_pairs
+        visited += int(vb.n_walk.sum(dtype=torch.int64).item())
+        blended += int(vb.n_blend.sum(dtype=torch.int64).item())
+    return pairs, visited, blended
+
+
+def main_line(args, torch, raster, synth, batch):
+    scene, cams = synth.workload_full_scene()
+    s = synth.RenderSettings()
+    ds = raster.to_device(scene)
+    N, V = scene.n, len(cams)
+    scores = torch.zeros(N, dtype=torch.float32, device="cuda")
+    bs = batch.BatchScorer([(ds, cams, scores)], s, views_per_job=VIEWS_PER_JOB)
+    bs.capture()
+
+    def step():
+        scores.zero_()
+        bs.replay()
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms = (t1 - t0) * 1000.0 / args.steps
+    if bs.overflowed():
+        raise RuntimeError("a job ran out of pair slots")
+    batched = scores.double().cpu()
+
+    # the dominant kernel alone, with HIP events on the stream it is launched on
+    stream = torch.cuda.current_stream()
+    reps = max(3, min(10, args.steps))
+    bs.render()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        bs.render()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    kernel_ms = e0.elapsed_time(e1) / reps
+    counted, _ = bs.pairs()
+    bs.close()
+    del bs
+    torch.cuda.empty_cache()
+
+    # the same pass as plain per-view launches
+    rz = raster.Rasterizer(s)
+
+    def plain():
+        scores.zero_()
+        rz.score_views_fused(ds, cams, views_per_batch=1, scores=scores)
+
+    plain_ms = timed(torch, plain, 2)
+    plain_scores = scores.double().cpu()
+    agree = float((batched - plain_scores).abs().sum() / plain_scores.abs().sum())
+
+    # work counts (outside the timed region)
+    pairs, visited, blended = view_work(torch, rz, ds, cams)
+    rz.release()
+    del rz
+    torch.cuda.empty_cache()
+    flops = FUSED_FLOPS_VISIT * visited + FUSED_FLOPS_BLEND * blended
+    achieved = flops / 1e12 / (kernel_ms / 1000.0)
+    kernel = "k_render_score_persistent"
+    ctr = measured_counters(kernel, COUNTER_RECORD)
+    valu = ctr.get("valu_insts_per_launch") if ctr else None
+    roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(achieved / FP32_VECTOR_PEAK_TFLOPS, 4),
+                "traffic": None if ctr is None else int(ctr["bytes_per_launch"]), "kernel": kernel,
+                "kernel_ms": round(kernel_ms, 4),
+                "valu_issue": None if valu is None else round(valu / (VALU_ISSUE_PER_S * kernel_ms / 1000.0), 4)}
+    gs = lambda t: round(N * V / (t / 1000.0) / 1e9, 4)
+    out = {
+        "value": gs(ms),
+        "ms_per_step": round(ms, 4),
+        "config": {"workload": (f"full-scene removal scoring: {N} clustered splats x {V} hemisphere views at "
+                                f"{cams[0].width}x{cams[0].height}, scores accumulated over all views"),
+                   "splats": N, "views": V, "width": cams[0].width, "height": cams[0].height,
+                   "tile": f"{s.tile_w}x{s.tile_h}", "lds_batch": s.lds_batch, "t_min": s.t_min,
+                   "path": (f"batched: project, bin and sort per job of {VIEWS_PER_JOB} views, then one persistent "
+                            f"fused composite + removal launch over every (view, tile), replayed as one HIP graph")},
+        "roofline": roofline,
+        "plain": {"path": "plain per-view launches: project, bin, sort, fused composite + removal",
+                  "ms_per_step": round(plain_ms, 4), "ms_per_view": round(plain_ms / V, 4),
+                  "gsplat_views_per_s": gs(plain_ms), "batched_speedup": round(plain_ms / ms, 3),
+                  "scores_rel_l1_vs_batched": agree},
+        "ms_per_view": round(ms / V, 4),
+        "work": {"pairs": pairs, "pairs_planned": int(sum(counted)), "visited": visited, "blended": blended},
+    }
+    return out, (scene, cams, s)
+
+
+def single_view_section(args, torch, raster, synth):
+    """500k splats, one 1280x720 view, plain launches, with the time of each stage."""
     scene, cams = synth.workload_single_view()
     s = synth.RenderSettings()
     ds = raster.to_device(scene)
@@ -105,22 +241,22 @@ def main_line(args, torch, raster, synth):
     # inside a step), and the last step's count is checked against it afterwards
     cap = rz.bin(rz.project(ds, cams), cams).n_pairs
 
-    def step(timed: bool):
-        ev = [torch.cuda.Event(enable_timing=True) for _ in range(len(stages) + 1)] if timed else None
-        if timed:
+    def step(timed_: bool):
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(len(stages) + 1)] if timed_ else None
+        if timed_:
             ev[0].record(stream)
         scores.zero_()
         vb = rz.project(ds, cams)
-        if timed:
+        if timed_:
             ev[1].record(stream)
         rz.bin(vb, cams, read_count=False)
-        if timed:
+        if timed_:
             ev[2].record(stream)
         rz.sort(vb, cams, capacity=cap)
-        if timed:
+        if timed_:
             ev[3].record(stream)
         rz.render_score(vb, cams, scores=scores)
-        if timed:
+        if timed_:
             ev[4].record(stream)
         return ev, vb
 
@@ -133,51 +269,20 @@ def main_line(args, torch, raster, synth):
     t1 = time.perf_counter()
     if not rz.pairs_fit(runs[-1][1]):
         raise RuntimeError("the timed steps ran out of pair slots")
-    evs = [r[0] for r in runs]
-    for ev in evs:
+    for ev, _ in runs:
         for i, k in enumerate(stages):
             stage_ms[k] += ev[i].elapsed_time(ev[i + 1]) / args.steps
     ms = (t1 - t0) * 1000.0 / args.steps
-
-    # work counts of the measured view (outside the timed region)
-    vb = rz.project(ds, cams)
-    rz.bin(vb, cams)
-    rz.sort(vb, cams)
-    rz.blend(vb, cams, count_blended=True)
-    visited = int(vb.n_walk.sum().item())
-    blended = int(vb.n_blend.sum().item())
-    torch.cuda.synchronize()
-    work = {
-        "render_score": ("alu", (FUSED_FLOPS_VISIT * visited + FUSED_FLOPS_BLEND * blended) / 1e12),
-        "project": ("hbm", PROJECT_BYTES_PER_SPLAT_VIEW * N * V / 1e9),
-    }
-    dom = max(work, key=lambda k: stage_ms[k])
-    bound, amount = work[dom]
-    sec = stage_ms[dom] / 1000.0
-    if bound == "hbm":
-        achieved, peak, unit = amount / sec, HBM_PEAK_GBS, "GB/s"
-    else:
-        achieved, peak, unit = amount / sec, FP32_VECTOR_PEAK_TFLOPS, "TFLOP/s"
-    ctr = measured_counters(f"k_{dom}")
-    # VALU issue: the record's wave instructions per launch over the chip's issue limit
-    # (one wave64 VALU instruction per CU per cycle) for the live kernel time
-    valu = ctr.get("valu_insts_per_launch") if ctr else None
-    roofline = {"bound": bound, "achieved": round(achieved, 3), "peak": peak, "unit": unit,
-                "frac": round(achieved / peak, 4), "traffic": measured_traffic(f"k_{dom}"), "kernel": f"k_{dom}",
-                "kernel_ms": round(stage_ms[dom], 4),
-                "valu_issue": None if valu is None else round(valu / (VALU_ISSUE_PER_S * sec), 4)}
-    out = {
-        "value": round(N * V / (ms / 1000.0) / 1e9, 4),
-        "ms_per_step": round(ms, 4),
-        "config": {"workload": "single-view removal scoring: 500k clustered splats, one 1280x720 view",
-                   "splats": N, "views": V, "width": cams[0].width, "height": cams[0].height,
-                   "tile": f"{s.tile_w}x{s.tile_h}", "lds_batch": s.lds_batch, "t_min": s.t_min,
-                   "path": "plain per-view launches, fused composite + removal pass"},
-        "roofline": roofline,
-        "stages_ms": {k: round(v, 4) for k, v in stage_ms.items()},
-        "work": {"pairs": vb.n_pairs, "visited": visited, "blended": blended},
-    }
-    return out, (scene, cams, s)
+    pairs, visited, blended = view_work(torch, rz, ds, cams)
+    flops = FUSED_FLOPS_VISIT * visited + FUSED_FLOPS_BLEND * blended
+    rz.release()
+    del rz, ds
+    torch.cuda.empty_cache()
+    return {"workload": f"{N} clustered splats, one {cams[0].width}x{cams[0].height} view, plain launches",
+            "ms_per_step": round(ms, 4), "gsplat_views_per_s": round(N * V / (ms / 1000.0) / 1e9, 4),
+            "stages_ms": {k: round(v, 4) for k, v in stage_ms.items()},
+            "render_score_tflops": round(flops / 1e12 / (stage_ms["render_score"] / 1000.0), 3),
+            "work": {"pairs": pairs, "visited": visited, "blended": blended}}
 
 
 def timed(torch, fn, reps, warm=1):
@@ -189,38 +294,6 @@ def timed(torch, fn, reps, warm=1):
         fn()
     torch.cuda.synchronize()
     return (time.perf_counter() - t0) * 1000.0 / reps
-
-
-def batched_section(torch, raster, synth, batch, n_views=16):
-    scene, cams = synth.workload_full_scene(n_views=n_views)
-    s = synth.RenderSettings()
-    ds = raster.to_device(scene)
-    sc = torch.zeros(scene.n, device="cuda")
-    rz = raster.Rasterizer(s)
-
-    def plain():
-        sc.zero_()
-        rz.score_views_fused(ds, cams, views_per_batch=1, scores=sc)
-
-    plain_ms = timed(torch, plain, 2)
-    bs = batch.BatchScorer([(ds, cams, sc)], s, views_per_job=8)
-    bs.capture()
-
-    def replay():
-        sc.zero_()
-        bs.replay()
-
-    graph_ms = timed(torch, replay, 3)
-    over = bs.overflowed()
-    counted, _ = bs.pairs()
-    bs.close()
-    del bs, rz, ds, sc
-    torch.cuda.empty_cache()
-    gs = lambda ms: round(scene.n * n_views / (ms / 1000.0) / 1e9, 4)
-    return {"workload": f"{scene.n} clustered splats x {n_views} of the 200 hemisphere views at 1600x1064",
-            "plain_ms_per_view": round(plain_ms / n_views, 4), "plain_gsplat_views_per_s": gs(plain_ms),
-            "batched_graph_ms_per_view": round(graph_ms / n_views, 4), "batched_gsplat_views_per_s": gs(graph_ms),
-            "pairs_per_view": int(sum(counted) / n_views), "overflowed_jobs": over}
 
 
 def multi_scene_section(torch, raster, synth, batch):
@@ -303,7 +376,8 @@ def main():
 
     from paper_2601_14821_amd import autograd, batch, raster, synth
 
-    main_out, (scene, cams, s) = main_line(args, torch, raster, synth)
+    log("main line: full scene, batched graph and plain per-view launches")
+    main_out, (scene, cams, s) = main_line(args, torch, raster, synth, batch)
     if args.copy_probe:
         src = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
@@ -326,16 +400,25 @@ def main():
         "data": "synthetic",
         "config": main_out["config"],
         "roofline": main_out["roofline"],
-        "stages_ms": main_out["stages_ms"],
+        "ms_per_view": main_out["ms_per_view"],
+        "plain": main_out["plain"],
         "work": main_out["work"],
     }
     if not args.main_only:
-        out["batched"] = batched_section(torch, raster, synth, batch)
+        log("single view")
+        out["single_view"] = single_view_section(args, torch, raster, synth)
+        log("multi scene")
         out["multi_scene"] = multi_scene_section(torch, raster, synth, batch)
+        log("forward + backward")
         out["fwd_bwd"] = fwd_bwd_section(torch, raster, synth, autograd)
     if not args.no_cpu_baseline:
+        log("cpu baseline")
         out["cpu_baseline"] = cpu_baseline(scene, cams, s)
     print(json.dumps(out), flush=True)
+
+
+def log(msg: str) -> None:
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
 if __name__ == "__main__":

@@ -276,6 +276,10 @@ POTR_API potr_status potr_render_score(int64_t N, int32_t V, const potr_camera* 
  *   default-priority stream created with the batch), forked from `stream` after
  *   the work already on it and joined back before the render launch. Scores
  *   accumulate (+=) into each job's buffers.
+ * potr_batch_render: enqueues only the persistent render + removal launch over
+ *   the tile lists the last run (or replay) left in the workspace; scores
+ *   accumulate (+=) again. With the lists unchanged it adds the same sums (up to
+ *   float addition order): a way to time or repeat the dominant launch alone.
  * potr_batch_capture / potr_batch_replay: record potr_batch_run into a graph on
  *   `stream` (not the null stream) / launch it.
  * potr_batch_overflow: after a run, the number of jobs whose pairs exceeded
@@ -300,6 +304,7 @@ POTR_API potr_status potr_batch_workspace_size(potr_batch b, size_t* bytes);
 POTR_API potr_status potr_batch_pairs(potr_batch b, int64_t* counted, int64_t* capacity);
 POTR_API potr_status potr_batch_bind(potr_batch b, void* ws, size_t ws_bytes, void* stream);
 POTR_API potr_status potr_batch_run(potr_batch b, void* stream);
+POTR_API potr_status potr_batch_render(potr_batch b, void* stream);
 POTR_API potr_status potr_batch_capture(potr_batch b, void* stream);
 POTR_API potr_status potr_batch_replay(potr_batch b, void* stream);
 POTR_API potr_status potr_batch_overflow(potr_batch b, int32_t* n_overflowed, void* stream);

@@ -65,6 +65,7 @@ SIGNATURES = {
     "potr_batch_pairs": (_i32, [_vp, C.POINTER(_i64), C.POINTER(_i64)]),
     "potr_batch_bind": (_i32, [_vp, _vp, _sz, _vp]),
     "potr_batch_run": (_i32, [_vp, _vp]),
+    "potr_batch_render": (_i32, [_vp, _vp]),
     "potr_batch_capture": (_i32, [_vp, _vp]),
     "potr_batch_replay": (_i32, [_vp, _vp]),
     "potr_batch_overflow": (_i32, [_vp, C.POINTER(_i32), _vp]),

@@ -64,6 +64,10 @@ class BatchScorer:
     def run(self) -> None:
         L.call("potr_batch_run", self._handle, L.stream_handle())
 
+    def render(self) -> None:
+        """Only the persistent render + removal launch over the lists of the last run."""
+        L.call("potr_batch_render", self._handle, L.stream_handle())
+
     def capture(self) -> None:
         """Record run() into a HIP graph on a side stream (default priority)."""
         if self._graph_stream is None:

@@ -238,6 +238,8 @@ potr_status potr_batch_bind(potr_batch b, void* ws, size_t ws_bytes, void* strea
             prefix.push_back(prefix.back() + (J.N > 0 ? T : 0));
         }
     }
+    if (prefix.back() >= (int64_t(1) << 40))
+        return fail(POTR_EINVAL, "%lld (view, tile) items in one batch", (long long)prefix.back());
     hipStream_t s = (hipStream_t)stream;
     potr_status st = hip_ok(hipMemcpyAsync(b->ws + b->off_table, table.data(), table.size() * sizeof(ViewJob),
                                            hipMemcpyHostToDevice, s), "upload job table");
@@ -294,6 +296,14 @@ potr_status potr_batch_run(potr_batch b, void* stream) {
     if (st != POTR_OK) return st;
     return launch_check_overflow(npairs, (const int64_t*)(ws + b->off_caps), (int32_t)b->jobs.size(),
                                  (int32_t*)(ws + b->off_flag), s);
+}
+
+potr_status potr_batch_render(potr_batch b, void* stream) {
+    if (!b || !b->ws) return fail(POTR_EINVAL, "batch not bound to a workspace");
+    char* ws = b->ws;
+    return launch_render_score_persistent((const ViewJob*)(ws + b->off_table), b->n_view_jobs,
+                                          (const int64_t*)(ws + b->off_prefix), (int64_t*)(ws + b->off_counter),
+                                          b->grid, b->cfg, (hipStream_t)stream);
 }
 
 potr_status potr_batch_capture(potr_batch b, void* stream) {

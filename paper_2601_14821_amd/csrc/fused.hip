@@ -33,7 +33,7 @@ struct Smem {
     Rec* rec;
     uint16_t* list;    // [NW][B] per-wave lists of the entries reaching the wave's rows
     uint16_t* hits;    // [NW][B] per-wave lists of the entries some lane of the wave blended
-    int* misc;         // [0]: wmax, [1]: next item
+    int* misc;         // [0]: wmax
     float* part;       // [n_out][B] per-entry sums over the waves, n_out = number of per-splat outputs (last, sized by the launch)
 };
 
@@ -307,12 +307,13 @@ __global__ __launch_bounds__(TW * TH) void k_render_score_persistent(const ViewJ
                                                                      const int64_t* __restrict__ item_prefix,
                                                                      int64_t* __restrict__ counter, potr_config cfg) {
     extern __shared__ __align__(16) char smem[];
+    __shared__ int64_t s_item;   // the item this workgroup took (64-bit: totals may pass 2^31)
     const Smem sm = carve<TW, TH>(smem, cfg.lds_batch);
     const int64_t total = item_prefix[n_jobs];
     for (;;) {
-        if (threadIdx.x == 0) sm.misc[1] = (int)atomicAdd((unsigned long long*)counter, 1ull);
+        if (threadIdx.x == 0) s_item = (int64_t)atomicAdd((unsigned long long*)counter, 1ull);
         __syncthreads();
-        const int64_t item = sm.misc[1];
+        const int64_t item = s_item;
         __syncthreads();
         if (item >= total) break;
         int lo = 0, hi = n_jobs - 1;      // last job with item_prefix[j] <= item
