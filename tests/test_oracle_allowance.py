@@ -1,0 +1,173 @@
+"""The oracle's allowance for FP32 decision flips, checked against FP32 evaluations.
+
+The rasterizer composites in FP32. Near a threshold (q against q_max, o G against
+alpha_min, T (1 - alpha) against t_min) an FP32 evaluation can take a decision
+the FP64 oracle takes the other way. The oracle flags such pixels and adds to
+every splat's score tolerance an allowance F_k. Nothing in the oracle checks that
+its error bounds actually cover FP32, so this test composites the same records
+(the projected values rounded to FP32, as they are stored) in FP32 with numpy,
+independently of the oracle and of the HIP path, in two evaluation orders
+(q then exp(-q/2); the conic pre-scaled by -log2(e)/2 and exp2 with fused
+multiply-adds), with every exponential moved by a random -1, 0 or +1 unit in the
+last place (a hardware exponential is not correctly rounded), and checks:
+  - every pixel whose FP32 image differs from the oracle's by more than the image
+    tolerance (1e-4 absolute) is a flagged pixel;
+  - every splat's removal score from the FP32 decisions is within
+    1e-3 |s| + 1e-5 M_k + F_k of the oracle's (the GPU tests' bar);
+and, in production mode on a dense crop, that the FP32 evaluations do take
+decisions the oracle takes the other way (so the flags are exercised).
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2601_14821_amd import synth
+
+f32 = np.float32
+EXP_SCALE = f32(-0.5 / math.log(2.0))      # exp(-q/2) = exp2(EXP_SCALE q)
+
+
+def _fma(a, b, c):
+    """a b + c with one FP32 rounding (FP32 products are exact in FP64)."""
+    return (a.astype(np.float64) * b.astype(np.float64) + c.astype(np.float64)).astype(f32)
+
+
+def _jitter(x, rng):
+    """x moved by -1, 0 or +1 FP32 ulp at random."""
+    step = rng.integers(-1, 2, x.shape)
+    up = np.nextafter(x, f32(np.inf))
+    dn = np.nextafter(x, f32(-np.inf))
+    return np.where(step > 0, up, np.where(step < 0, dn, x)).astype(f32)
+
+
+def fp32_composite(proj, bins, opac, cam, s, variant, rng):
+    """FP32 compositing of one view over the oracle's tile lists. Returns the image,
+    per-pixel (walk, blended) counts and per-splat L1 removal scores computed in FP64
+    from the FP32 alphas (so only the decisions and alpha's rounding differ)."""
+    _, ids, ranges = bins
+    W, H = cam.width, cam.height
+    tx, ty = s.tiles(cam)
+    mx, my = proj["mean2d"][:, 0].astype(f32), proj["mean2d"][:, 1].astype(f32)
+    A, B, Cc = (proj["conic"][:, j].astype(f32) for j in range(3))
+    rgb = proj["rgb"].astype(f32)
+    o = np.asarray(opac, f32)
+    qmax, amin, amax, tmin = f32(s.q_max), f32(s.alpha_min), f32(s.alpha_max), f32(s.t_min)
+    bg = np.asarray(s.bg, f32)
+    emin = f32(qmax * EXP_SCALE)
+    image = np.zeros((H, W, 3))
+    n_walk = np.zeros((H, W), np.int64)
+    n_blend = np.zeros((H, W), np.int64)
+    score = np.zeros(len(o))
+    for t in range(tx * ty):
+        x0, y0 = (t % tx) * s.tile_w, (t // tx) * s.tile_h
+        xs, ys = np.meshgrid(np.arange(x0, min(x0 + s.tile_w, W)), np.arange(y0, min(y0 + s.tile_h, H)))
+        xs, ys = xs.ravel(), ys.ravel()
+        fx, fy = (xs + 0.5).astype(f32), (ys + 0.5).astype(f32)
+        npx = len(xs)
+        T = np.ones(npx, f32)
+        col = np.zeros((npx, 3), f32)
+        done = np.zeros(npx, bool)
+        walk = np.full(npx, ranges[t, 1])      # list position of the stop (absolute), else the list end
+        hist = []     # (splat, alpha per pixel where blended else 0)
+        for pos in range(ranges[t, 0], ranges[t, 1]):
+            k = ids[pos]
+            dx, dy = mx[k] - fx, my[k] - fy
+            if variant == 0:
+                q = (A[k] * dx * dx + f32(2.0) * B[k] * dx * dy) + Cc[k] * dy * dy
+                G = _jitter(np.exp(-0.5 * q.astype(np.float64)).astype(f32), rng)
+                vis = q <= qmax
+            else:
+                sa, s2b, sc = A[k] * EXP_SCALE, (f32(2.0) * B[k]) * EXP_SCALE, Cc[k] * EXP_SCALE
+                e = _fma(dx, _fma(np.full_like(dx, sa), dx, s2b * dy), (sc * dy) * dy)
+                G = _jitter(np.exp2(e.astype(np.float64)).astype(f32), rng)
+                vis = e >= emin
+            al0 = o[k] * G
+            al = np.where(vis & (al0 >= amin) & ~done, np.minimum(amax, al0), f32(0.0)).astype(f32)
+            Tn = T * (f32(1.0) - al)
+            stop = (Tn < tmin) & (al > 0)
+            bl = (al > 0) & ~stop
+            w = np.where(bl, T * al, f32(0.0)).astype(f32)
+            col = _fma(np.repeat(w[:, None], 3, 1), np.broadcast_to(rgb[k], col.shape), col)
+            walk = np.where(stop & ~done, pos, walk)
+            T = np.where(stop, T, Tn).astype(f32)
+            done |= stop
+            if bl.any():
+                hist.append((k, np.where(bl, al, f32(0.0)).astype(np.float64)))
+            if done.all():
+                break
+        img = (col + T[:, None] * bg).astype(np.float64)
+        image[ys, xs] = img
+        n_walk[ys, xs] = walk
+        # removal scores in FP64 from the FP32 alphas: PD_k = -c a T + a/(1-a) (S_k + T_f bg)
+        if hist:
+            al = np.stack([h[1] for h in hist])                       # [K, npx]
+            c = np.stack([rgb[h[0]].astype(np.float64) for h in hist])  # [K, 3]
+            Tk = np.cumprod(np.vstack([np.ones((1, npx)), 1.0 - al[:-1]]), axis=0)
+            wk = Tk * al
+            P = np.cumsum(wk[:, :, None] * c[:, None, :], axis=0)      # P_{k+1}
+            PK, TF = P[-1], Tk[-1] * (1.0 - al[-1])
+            S = PK[None] - P
+            r = al / (1.0 - al)
+            pd = -wk[:, :, None] * c[:, None, :] + r[:, :, None] * (S + (TF[:, None] * bg.astype(np.float64))[None])
+            l1 = np.abs(pd).sum(axis=2).sum(axis=1)
+            for (k, _), v in zip(hist, l1):
+                score[k] += v
+            n_blend[ys, xs] = (al > 0).sum(axis=0)
+    return image, n_walk, n_blend, score
+
+
+def _crop(cam, x0, y0, w, h):
+    """The pixels [x0, x0 + w) x [y0, y0 + h) of `cam` as a camera of their own."""
+    return synth.Camera(cam.R, cam.t, cam.fx, cam.fy, cam.cx - x0, cam.cy - y0, w, h)
+
+
+def _check(scene, cams, s, draws, seed):
+    rng = np.random.default_rng(seed)
+    n_diff_pix = n_diff_dec = n_need_F = 0
+    n_flagged = n_pix = 0
+    for cam in cams:
+        r = oracle.render(scene, cam, s, record_f32=True,
+                          want=("image", "n_walk", "n_blend", "score_l1", "magnitude", "flag_mass", "pixel_flag"))
+        flag = r["pixel_flag"].astype(bool)
+        n_flagged += int(flag.sum())
+        n_pix += flag.size
+        for variant in (0, 1):
+            for _ in range(draws):
+                img, nw, nb, sc = fp32_composite(r["proj"], r["bins"], scene.opacities, cam, s, variant, rng)
+                off = np.abs(img - r["image"]).max(axis=2) > 1e-4
+                n_diff_pix += int(off.sum())
+                assert not (off & ~flag).any(), (
+                    f"unflagged pixel off by more than 1e-4: {np.argwhere(off & ~flag)[:5]}")
+                dec = (nw != r["n_walk"]) | (nb != r["n_blend"])
+                n_diff_dec += int(dec.sum())
+                assert not (dec & ~flag).any(), f"decision changed at an unflagged pixel: {np.argwhere(dec & ~flag)[:5]}"
+                ref, mag, F = r["score_l1"], r["magnitude"], r["flag_mass"]
+                d = np.abs(sc - ref)
+                base = 1e-3 * np.abs(ref) + 1e-5 * mag
+                assert not (d > base + F).any(), f"{(d > base + F).sum()} splats beyond the allowance"
+                n_need_F += int((d > base).sum())
+    return dict(pixels=n_pix, flagged=n_flagged, off_pixels=n_diff_pix, changed_decisions=n_diff_dec,
+                needing_F=n_need_F)
+
+
+def test_allowance_covers_fp32_on_small_scene():
+    scene, cams = synth.workload_small()
+    out = _check(scene, cams, synth.RenderSettings(), draws=2, seed=5)
+    print(out)
+
+
+@pytest.mark.parametrize("t_min,size,draws", [(1e-4, (256, 144), 2), (0.0, (64, 48), 1)])
+def test_allowance_covers_fp32_on_dense_crop(t_min, size, draws):
+    """A crop of the 500k-splat 1280x720 view: thousands of splats per tile, early
+    stops in every pixel (production mode) or none (exact mode)."""
+    scene, cams = synth.workload_single_view()
+    w, h = size
+    cam = _crop(cams[0], 640 - w // 2, 360 - h // 2, w, h)
+    out = _check(scene, [cam], synth.RenderSettings(t_min=t_min), draws=draws, seed=7)
+    print(out)
+    if t_min > 0.0:
+        # the FP32 evaluations do take decisions the oracle takes the other way
+        # here (all of them in flagged pixels, as checked above)
+        assert out["changed_decisions"] > 0, out

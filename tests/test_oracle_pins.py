@@ -362,3 +362,85 @@ def test_bin_sort_brute_force_with_ties():
         assert list(ids[b:e]) == exp
         assert np.all(tile[b:e] == t)
     assert len(ids) == sum(max(0, a) * max(0, b) for a, b in zip(x1 - x0, y1 - y0))
+
+
+# ---------------------------------------------------------------- early stop and alpha clamp (hand-worked)
+@pytest.mark.parametrize("method", [0, 1])
+def test_early_stop_pixel(method):
+    """Where the stop falls (strictly below t_min), what the truncated list gives,
+    and the literal deletion with the stop rerun (tests/golden/early_stop_pixel.json)."""
+    g = json.load(open(os.path.join(GOLDEN, "early_stop_pixel.json")))
+    for case in g["cases"]:
+        scene, cam, proj = _one_pixel_proj(g["alpha"], g["colour"])
+        s = synth.RenderSettings(bg=tuple(case["bg"]), t_min=case["t_min"])
+        r = oracle.render(scene, cam, s, proj=proj, method=method,
+                          want=("image", "t_final", "n_walk", "n_blend", "score_l1", "importance"))
+        assert r["n_walk"][0, 0] == case["n_walk"] and r["n_blend"][0, 0] == case["n_blend"]
+        assert r["t_final"][0, 0] == case["t_final"]
+        np.testing.assert_array_equal(r["image"][0, 0], case["image"])
+        np.testing.assert_array_equal(r["importance"], case["weights"])
+        np.testing.assert_allclose(r["score_l1"], case["pd_l1"], rtol=0, atol=1e-15)
+        for k in range(3):
+            lit = oracle.render_without(scene, cam, s, k, proj=proj)
+            np.testing.assert_array_equal(lit[0, 0], case["literal"][k])
+
+
+@pytest.mark.parametrize("method", [0, 1])
+def test_alpha_clamp_pixel(method):
+    """alpha = alpha_max where o G exceeds it (tests/golden/alpha_clamp_pixel.json)."""
+    g = json.load(open(os.path.join(GOLDEN, "alpha_clamp_pixel.json")))
+    for case in g["cases"]:
+        scene, cam, proj = _one_pixel_proj(case["opacity"], case["colour"])
+        s = synth.RenderSettings(bg=tuple(case["bg"]), alpha_max=g["alpha_max"], t_min=0.0)
+        r = oracle.render(scene, cam, s, proj=proj, method=method,
+                          want=("image", "t_final", "score_l1", "importance"))
+        np.testing.assert_array_equal(r["image"][0, 0], case["image"])
+        assert r["t_final"][0, 0] == case["t_final"]
+        np.testing.assert_array_equal(r["importance"], case["weights"])
+        np.testing.assert_allclose(r["score_l1"], case["pd_l1"], rtol=0, atol=1e-15)
+
+
+def test_default_alpha_clamp_and_visibility_floor():
+    """Default settings: o = 0.995 blends with alpha = alpha_max = 0.99 (FP32 value of
+    the setting), PD = alpha (bg - c); o below alpha_min = 1/255 is not blended."""
+    s = synth.RenderSettings(bg=(1.0, 1.0, 1.0), t_min=0.0)
+    a_max = float(np.float32(s.alpha_max))
+    scene, cam, proj = _one_pixel_proj([0.995], [[0.25, 0.5, 0.75]])
+    r = oracle.render(scene, cam, s, proj=proj, want=("image", "score_l1", "importance"))
+    assert r["importance"][0] == a_max
+    expect = a_max * (0.75 + 0.5 + 0.25)
+    assert abs(r["score_l1"][0] - expect) <= 1e-15
+    below = float(np.float32(1.0 / 255.0)) * 0.999
+    scene, cam, proj = _one_pixel_proj([below], [[0.25, 0.5, 0.75]])
+    r = oracle.render(scene, cam, s, proj=proj, want=("image", "score_l1", "n_blend"))
+    assert r["n_blend"][0, 0] == 0 and r["score_l1"][0] == 0.0
+    np.testing.assert_array_equal(r["image"][0, 0], [1.0, 1.0, 1.0])
+
+
+# ---------------------------------------------------------------- SH direction (Sec. 3)
+@pytest.mark.parametrize("index,axis,sign", [(3, 0, -1.0), (1, 1, -1.0), (2, 2, 1.0)])
+def test_sh_degree1_direction_from_camera_to_splat(index, axis, sign):
+    """Real SH of degree 1 with the Condon-Shortley phase are Y_{1,1} = -k x,
+    Y_{1,-1} = -k y, Y_{1,0} = k z with k = sqrt(3 / (4 pi)), at index l(l+1)+m
+    (0-based). The colour is evaluated along d = unit vector from the camera
+    centre to the splat (Sec. 3): a splat at the origin holding only that
+    coefficient L has colour 0.5 + L Y(d), with d = -axis seen from a camera on
+    the +axis and d = +axis from the -axis, so the two sides see the degree-1
+    term with opposite signs (a flipped direction or phase swaps them)."""
+    k = math.sqrt(3.0 / (4.0 * math.pi))
+    L = np.array([0.2, -0.1, 0.3])
+    scene = synth.Scene(np.zeros((1, 3), np.float32), np.full((1, 3), 0.05, np.float32),
+                        np.float32([[1, 0, 0, 0]]), np.float32([0.9]), np.zeros((1, 16, 3), np.float32))
+    scene.sh[0, index, :] = L
+    s = synth.RenderSettings(sh_degree=1)
+    up = (0.0, 0.0, 1.0) if axis == 1 else (0.0, 1.0, 0.0)
+    for side in (1.0, -1.0):
+        eye = [0.0, 0.0, 0.0]
+        eye[axis] = 3.0 * side
+        cam = synth.look_at(eye, up=up, width=64, height=64)
+        o = oracle.project(scene, cam, s)
+        d = -np.array(eye) / 3.0                     # camera -> splat at the origin
+        expect = 0.5 + L.astype(np.float32).astype(float) * sign * k * d[axis]
+        np.testing.assert_allclose(o["rgb"][0], expect, rtol=0, atol=1e-6)
+        # the +axis camera sees 0.5 - sign k L, the -axis camera 0.5 + sign k L
+        np.testing.assert_allclose(o["rgb"][0] - 0.5, -side * sign * k * L, rtol=0, atol=2e-7)
