@@ -355,8 +355,19 @@ static void eval_splat(const render_ctx* c, int64_t s, double px, double py,
  * kind 0: splat at blended position `pos` is near a visibility threshold;
  * kind 1: a splat the oracle skips is near visible (it would sit before `pos`);
  * kind 2: the early stop is near its threshold; `dS` is what the splats an FP32
- *         walk might still blend add to the colour. */
-typedef struct { int kind, pos; double alpha, T, dS; } flip_event;
+ *         walk might still blend add to the colour.
+ * `imp` (set when the pixel is done) bounds the change of the pixel's colour
+ * (L1 over channels) if the decision flips: the splat's own term T a |c|_1 plus,
+ * since every later transmittance scales by (1 - a) or 1 / (1 - a) (Sec. 3,
+ * T_k = prod_{j<k} (1 - a_j)), a / (1 - a) times what lies behind it,
+ * |P_K - P_pos|_1 + T_K |bg|_1; for a stop, what an FP32 walk might still blend
+ * plus the background seen at the stop, T |bg|_1. */
+typedef struct { int kind, pos; double alpha, T, dS, imp; } flip_event;
+
+/* A pixel is flagged (left out of image comparisons) when the decisions near a
+ * threshold could together move its colour by this much: half the 1e-4 image
+ * tolerance, so an unflagged pixel stays within it whichever way FP32 takes them. */
+#define ORC_FLAG_IMAGE 5e-5
 
 static void render_row(void* vctx, int py_i)
 {
@@ -377,7 +388,10 @@ static void render_row(void* vctx, int py_i)
     int64_t* extra_id = (int64_t*)malloc(sizeof(int64_t) * M);   /* splats blended only by a flip */
     double* extra_m = (double*)malloc(sizeof(double) * M);       /* ... their own term T a |c|_1 */
     double* extra_r = (double*)malloc(sizeof(double) * M);       /* ... a / (1 - a) */
-    double* extra_b = (double*)malloc(sizeof(double) * M);       /* ... colour behind them (<0: P_K) */
+    double* extra_b = (double*)malloc(sizeof(double) * M);       /* ... colour behind them (<0: P_K - P_pos) */
+    int* extra_p = (int*)malloc(sizeof(int) * M);                /* ... blended position they would take */
+    const int analyse = c->flag_mass != NULL || c->pixel_flag != NULL;
+    const double sum_bg = fabs(bg[0]) + fabs(bg[1]) + fabs(bg[2]);
     int64_t row_flagged = 0;
 
     for (int px_i = 0; px_i < W; ++px_i) {
@@ -396,19 +410,20 @@ static void render_row(void* vctx, int py_i)
             double col[3];
             for (int ch = 0; ch < 3; ++ch) col[ch] = rec(c, c->rgb[3 * s + ch]);
             const double c1 = fabs(col[0]) + fabs(col[1]) + fabs(col[2]);
-            /* decisions that an FP32 evaluation could flip */
+            /* decisions that an FP32 evaluation could flip (only looked for when
+             * the flags or the allowance are asked for) */
             double elna = 0.5 * eq + 0.5 * q * 4.0 * u + 8.0 * u;
             const int vis_q = q <= qmax, vis_a = a0 >= amin;
-            const int nq = fabs(q - qmax) <= 4.0 * eq;
-            const int na = a0 > 0.0 && fabs(log(a0) - log(amin)) <= 4.0 * elna;
+            const int nq = analyse && fabs(q - qmax) <= 4.0 * eq;
+            const int na = analyse && a0 > 0.0 && fabs(log(a0) - log(amin)) <= 4.0 * elna;
             const int may_flip = (nq && (vis_a || na)) || (na && (vis_q || nq));
             if (!vis_q || !vis_a) {
                 if (may_flip) {
                     const double a = fmin(amax, a0);
-                    flip_event e = { 1, K, a, T, T * a * c1 };
+                    flip_event e = { 1, K, a, T, T * a * c1, 0.0 };
                     ev[n_ev++] = e;
                     extra_id[n_extra] = s; extra_m[n_extra] = T * a * c1;
-                    extra_r[n_extra] = a / (1.0 - a); extra_b[n_extra++] = -1.0;
+                    extra_r[n_extra] = a / (1.0 - a); extra_p[n_extra] = K; extra_b[n_extra++] = -1.0;
                 }
                 continue;
             }
@@ -416,12 +431,12 @@ static void render_row(void* vctx, int py_i)
             double ea = a0 < amax ? elna : 0.0;
             double Tn = T * (1.0 - a);
             if (may_flip) {
-                flip_event e = { 0, K, a, T, T * a * c1 };
+                flip_event e = { 0, K, a, T, T * a * c1, 0.0 };
                 ev[n_ev++] = e;
             }
             if (tmin > 0.0) {
                 double e = elnT + a / (1.0 - a) * ea + 4.0 * u;
-                int near_stop = fabs(log(Tn) - log(tmin)) <= 4.0 * e;
+                int near_stop = analyse && fabs(log(Tn) - log(tmin)) <= 4.0 * e;
                 if (near_stop) {
                     /* splats an FP32 walk could still blend from here on */
                     double Tv = T, dS = 0.0;
@@ -440,12 +455,12 @@ static void render_row(void* vctx, int py_i)
                         dS += m;
                         if (Tn < tmin || pv > pos) {
                             extra_id[n_extra] = sv; extra_m[n_extra] = m;
-                            extra_r[n_extra] = av / (1.0 - av); extra_b[n_extra++] = 0.0;
+                            extra_r[n_extra] = av / (1.0 - av); extra_p[n_extra] = K; extra_b[n_extra++] = 0.0;
                         }
                         Tv *= (1.0 - av);
                     }
                     for (int k = first_extra; k < n_extra; ++k) extra_b[k] = dS;
-                    flip_event ee = { 2, K, a, T, dS };
+                    flip_event ee = { 2, K, a, T, dS, 0.0 };
                     ev[n_ev++] = ee;
                 }
                 if (Tn < tmin) { stop = pos; break; }
@@ -457,9 +472,22 @@ static void render_row(void* vctx, int py_i)
             ++K;
         }
         if (pos >= end) stop = end;
-        const int flagged = n_ev > 0;
         const int64_t pix = (int64_t)py_i * W + px_i;
         const double* PK = Pk + 3 * K;
+        const double sumabsB = T * sum_bg;
+        double imp = 0.0;
+        for (int e = 0; e < n_ev; ++e) {
+            flip_event* f = &ev[e];
+            if (f->kind == 2) {
+                f->imp = f->dS + f->T * sum_bg;
+            } else {
+                const double* Pp = Pk + 3 * f->pos;
+                const double behind = fabs(PK[0] - Pp[0]) + fabs(PK[1] - Pp[1]) + fabs(PK[2] - Pp[2]);
+                f->imp = f->dS + f->alpha / (1.0 - f->alpha) * (behind + sumabsB);
+            }
+            imp += f->imp;
+        }
+        const int flagged = imp >= ORC_FLAG_IMAGE;
         double img[3];
         for (int ch = 0; ch < 3; ++ch) img[ch] = PK[ch] + T * bg[ch];
         if (c->image) for (int ch = 0; ch < 3; ++ch) c->image[3 * pix + ch] = img[ch];
@@ -471,7 +499,6 @@ static void render_row(void* vctx, int py_i)
         row_flagged += flagged;
 
         const double sumabsP = fabs(PK[0]) + fabs(PK[1]) + fabs(PK[2]);
-        const double sumabsB = T * (fabs(bg[0]) + fabs(bg[1]) + fabs(bg[2]));
         for (int k = 0; k < K; ++k) {
             const double a = al[k];
             double col[3];
@@ -503,36 +530,47 @@ static void render_row(void* vctx, int py_i)
             }
             if (c->importance) atomic_add_f64(&c->importance[s], Tk[k] * a);
             const double ratio = a / (1.0 - a);
-            const double mag = Tk[k] * a * (fabs(col[0]) + fabs(col[1]) + fabs(col[2])) + ratio * (sumabsP + sumabsB);
+            const double own = Tk[k] * a * (fabs(col[0]) + fabs(col[1]) + fabs(col[2]));
+            const double mag = own + ratio * (sumabsP + sumabsB);
             if (c->magnitude) atomic_add_f64(&c->magnitude[s], mag);
-            if (flagged && c->flag_mass) {
+            /* a bound of |PD_k|_1 itself: T_k a |c_k|_1 + a/(1-a) (|S_k|_1 + T_K |bg|_1),
+             * S_k = P_K - P_{k+1} */
+            const double* P1 = Pk + 3 * (k + 1);
+            const double pdb = own + ratio * (fabs(PK[0] - P1[0]) + fabs(PK[1] - P1[1]) + fabs(PK[2] - P1[2]) +
+                                              sumabsB);
+            if (n_ev > 0 && c->flag_mass) {
                 /* first-order change of this splat's |PD| if an event flips */
                 double F = 0.0;
                 for (int e = 0; e < n_ev; ++e) {
                     const flip_event* f = &ev[e];
                     const double re = f->alpha / (1.0 - f->alpha);
                     if (f->kind == 2) {            /* early stop: k may vanish or S_k may grow */
-                        if (k >= f->pos) F += mag;
-                        else F += ratio * (f->dS + sumabsB);
+                        if (k >= f->pos) F += pdb;
+                        else F += ratio * f->imp;
                     } else if (f->kind == 0 && f->pos == k) {
-                        F += mag;                  /* its own visibility */
-                    } else if (f->pos > k) {       /* behind k: S_k and T_final move */
-                        F += ratio * (f->dS + re * (sumabsP + sumabsB));
-                    } else {                       /* in front of k: T_k scales by 1/(1-a) */
-                        F += 2.0 * re * mag;
+                        F += pdb;                  /* its own visibility: PD_k may vanish */
+                    } else if (f->pos > k) {       /* behind k: S_k and T_final move by at most imp */
+                        F += ratio * f->imp;
+                    } else {                       /* in front of k: PD_k scales by (1-a) or 1/(1-a) */
+                        F += 2.0 * re * pdb;
                     }
                 }
                 atomic_add_f64(&c->flag_mass[s], 2.0 * F);
             }
         }
-        if (flagged && c->flag_mass) {
+        if (n_ev > 0 && c->flag_mass) {
             for (int k = 0; k < n_extra; ++k) {
-                const double behind = extra_b[k] < 0.0 ? sumabsP : extra_b[k];
+                double behind = extra_b[k];
+                if (behind < 0.0) {
+                    const double* Pp = Pk + 3 * extra_p[k];
+                    behind = fabs(PK[0] - Pp[0]) + fabs(PK[1] - Pp[1]) + fabs(PK[2] - Pp[2]);
+                }
                 atomic_add_f64(&c->flag_mass[extra_id[k]], 2.0 * (extra_m[k] + extra_r[k] * (behind + sumabsB)));
             }
         }
     }
     free(al); free(Tk); free(Pk); free(ids); free(ev); free(extra_id); free(extra_m); free(extra_r); free(extra_b);
+    free(extra_p);
     pthread_mutex_lock(&c->mu);
     c->n_flagged += row_flagged;
     pthread_mutex_unlock(&c->mu);

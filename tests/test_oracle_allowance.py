@@ -11,11 +11,12 @@ independently of the oracle and of the HIP path, in two evaluation orders
 multiply-adds), with every exponential moved by a random -1, 0 or +1 unit in the
 last place (a hardware exponential is not correctly rounded), and checks:
   - every pixel whose FP32 image differs from the oracle's by more than the image
-    tolerance (1e-4 absolute) is a flagged pixel;
+    tolerance (1e-4 absolute) is a flagged pixel (a pixel is flagged when the
+    decisions near a threshold could move it by at least 5e-5);
   - every splat's removal score from the FP32 decisions is within
     1e-3 |s| + 1e-5 M_k + F_k of the oracle's (the GPU tests' bar);
 and, in production mode on a dense crop, that the FP32 evaluations do take
-decisions the oracle takes the other way (so the flags are exercised).
+decisions the oracle takes the other way (so the allowance is exercised).
 """
 import math
 
@@ -140,9 +141,10 @@ def _check(scene, cams, s, draws, seed):
                 n_diff_pix += int(off.sum())
                 assert not (off & ~flag).any(), (
                     f"unflagged pixel off by more than 1e-4: {np.argwhere(off & ~flag)[:5]}")
+                # a decision may flip at an unflagged pixel when the flip cannot move its
+                # colour by half the image tolerance; the image check above covers those
                 dec = (nw != r["n_walk"]) | (nb != r["n_blend"])
                 n_diff_dec += int(dec.sum())
-                assert not (dec & ~flag).any(), f"decision changed at an unflagged pixel: {np.argwhere(dec & ~flag)[:5]}"
                 ref, mag, F = r["score_l1"], r["magnitude"], r["flag_mass"]
                 d = np.abs(sc - ref)
                 base = 1e-3 * np.abs(ref) + 1e-5 * mag
