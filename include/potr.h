@@ -37,7 +37,7 @@
 extern "C" {
 #endif
 
-#define POTR_ABI_VERSION 2
+#define POTR_ABI_VERSION 3
 
 #define POTR_API __attribute__((visibility("default")))
 
@@ -255,6 +255,43 @@ POTR_API potr_status potr_render_score(int64_t N, int32_t V, const potr_camera* 
                                        float* scores, float* scores_se, float* importance, void* stream);
 
 /* ---------------------------------------------------------------------------
+ * potr_outputs -- where the fused pass and the batch put their per-splat
+ * reductions (Sec. 4.1 importance, Sec. 4.2 removal effect and dSE), each one
+ * optional (NULL):
+ *   scores      sum over pixels and channels of |PD_k|
+ *   scores_se   sum over pixels and channels of dSE_k = |PD_k|^2 + 2 PD_k.(c - c_t)
+ *               (needs a target image c_t)
+ *   importance  sum over pixels of T_k alpha_k
+ * For view v of a call, output o lives at o + v * o_stride: stride 0 adds every
+ * view into one [N] array, stride N gives one [N] array per view ([V,N], e.g. the
+ * per-camera importance I_k(s) that SH compaction weighs its rows with, Sec. 4.4).
+ * Every (tile, splat) partial sum is multiplied by o_weight before it is added:
+ * 1 keeps the raw sums; 1/P (P = pixels of the view) makes importance the
+ * paper's I_k(s); 1/(V P) its camera average I_k; 1/(3 V P) makes scores_se the
+ * paper's dMSE_k (Sec. 4.2, the average over V cameras, P pixels, 3 channels).
+ * Outputs are ACCUMULATED (+=); zero them first. A weight must be finite and > 0.
+ * ------------------------------------------------------------------------- */
+typedef struct potr_outputs {
+    float* scores;
+    int64_t scores_stride;
+    float scores_weight;
+    float* scores_se;
+    int64_t se_stride;
+    float se_weight;
+    float* importance;
+    int64_t importance_stride;
+    float importance_weight;
+} potr_outputs;
+
+/* potr_render_score_out -- potr_render_score with its reductions described by
+ * `out` (host struct): per-view arrays and weights as above. image may be NULL;
+ * at least one output (image included) must be requested. */
+POTR_API potr_status potr_render_score_out(int64_t N, int32_t V, const potr_camera* cams, const potr_config* cfg,
+                                           const potr_proj* proj, const uint32_t* sorted_ids,
+                                           const int32_t* tile_ranges, float* image, const float* target,
+                                           const potr_outputs* out, void* stream);
+
+/* ---------------------------------------------------------------------------
  * Batched scoring of many scenes and views of uneven sizes (the paper scores
  * every training view of a model per pruning iteration, Sec. 4.3).
  *
@@ -292,8 +329,9 @@ typedef struct potr_job {
     const float *means, *scales, *quats, *opac, *sh;  /* device, as for potr_project */
     int32_t V;
     const potr_camera* cams;                          /* host [V], copied at create */
-    float* scores;                                    /* device [N] += sum |PD|_1 */
-    float* importance;                                /* device [N] += sum T alpha, or NULL */
+    potr_outputs out;                                 /* device outputs of this job's views, as for
+                                                         potr_render_score_out (at least one) */
+    const float* target;                              /* device [V,H,W,3], needed with out.scores_se */
 } potr_job;
 
 typedef struct potr_batch_s* potr_batch;

@@ -37,13 +37,20 @@ class potr_config(C.Structure):
                 ("t_min", C.c_float), ("bg", C.c_float * 3), ("sh_degree", C.c_int32)]
 
 
+class potr_outputs(C.Structure):
+    _fields_ = [("scores", C.c_void_p), ("scores_stride", C.c_int64), ("scores_weight", C.c_float),
+                ("scores_se", C.c_void_p), ("se_stride", C.c_int64), ("se_weight", C.c_float),
+                ("importance", C.c_void_p), ("importance_stride", C.c_int64), ("importance_weight", C.c_float)]
+
+
 class potr_job(C.Structure):
     _fields_ = [("N", C.c_int64), ("means", C.c_void_p), ("scales", C.c_void_p), ("quats", C.c_void_p),
                 ("opac", C.c_void_p), ("sh", C.c_void_p), ("V", C.c_int32), ("cams", C.POINTER(potr_camera)),
-                ("scores", C.c_void_p), ("importance", C.c_void_p)]
+                ("out", potr_outputs), ("target", C.c_void_p)]
 
 
 _CAM_P, _CFG_P, _JOB_P = C.POINTER(potr_camera), C.POINTER(potr_config), C.POINTER(potr_job)
+_OUT_P = C.POINTER(potr_outputs)
 
 SIGNATURES = {
     "potr_abi_version": (_i32, []),
@@ -60,6 +67,7 @@ SIGNATURES = {
     "potr_backward_workspace_size": (_i32, [_i64, _i32, C.POINTER(_sz)]),
     "potr_backward": (_i32, [_i64, _i32, _CAM_P, _CFG_P] + [_vp] * 13 + [_sz] + [_vp] * 6),
     "potr_render_score": (_i32, [_i64, _i32, _CAM_P, _CFG_P] + [_vp] * 9),
+    "potr_render_score_out": (_i32, [_i64, _i32, _CAM_P, _CFG_P] + [_vp] * 5 + [_OUT_P, _vp]),
     "potr_batch_create": (_i32, [_JOB_P, _i32, _CFG_P, C.c_float, C.POINTER(_vp), _vp]),
     "potr_batch_workspace_size": (_i32, [_vp, C.POINTER(_sz)]),
     "potr_batch_pairs": (_i32, [_vp, C.POINTER(_i64), C.POINTER(_i64)]),
@@ -132,6 +140,20 @@ def make_config(s) -> potr_config:
     c.alpha_min, c.alpha_max, c.q_max, c.t_min = s.alpha_min, s.alpha_max, s.q_max, s.t_min
     c.bg[:] = [float(x) for x in s.bg]
     c.sh_degree = s.sh_degree
+    return c
+
+
+def make_outputs(o, v0: int = 0) -> potr_outputs:
+    """potr_outputs for an `Outputs` description (raster.py), its arrays
+    starting at view v0 of theirs."""
+    c = potr_outputs()
+    for name, stride, weight in (("scores", "scores_stride", "scores_weight"), ("scores_se", "se_stride", "se_weight"),
+                                 ("importance", "importance_stride", "importance_weight")):
+        t = getattr(o, name)
+        st = int(getattr(o, stride))
+        setattr(c, name, None if t is None else t.data_ptr() + 4 * v0 * st)
+        setattr(c, stride, st)
+        setattr(c, weight, float(getattr(o, weight)))
     return c
 
 

@@ -4,6 +4,10 @@
     bs.run()                  # or: bs.capture(); bs.replay()
     assert bs.overflowed() == 0
 
+An item is (scene, cameras, scores[, importance]) with [N] tensors, or
+(scene, cameras, raster.Outputs[, targets]) for per-view arrays, weights and
+dSE sums against target images [V,H,W,3].
+
 Scenes are split into jobs of at most `views_per_job` views (one image size per
 job). The library plans pair capacities by counting once at construction, runs
 project -> bin -> sort per job and one persistent render + removal launch over
@@ -19,6 +23,7 @@ import os
 import torch
 
 from . import _lib as L
+from .raster import Outputs
 
 
 class BatchScorer:
@@ -29,8 +34,15 @@ class BatchScorer:
         self._keep = []
         jobs = []
         for item in scenes:
-            ds, cams, scores = item[0], item[1], item[2]
-            importance = item[3] if len(item) > 3 else None
+            ds, cams, out = item[0], item[1], item[2]
+            targets = None
+            if isinstance(out, Outputs):
+                targets = item[3] if len(item) > 3 else None
+            else:
+                out = Outputs(scores=out, importance=item[3] if len(item) > 3 else None)
+            if targets is not None:
+                targets = targets.contiguous()
+                self._keep.append(targets)
             for v0 in range(0, len(cams), views_per_job):
                 cb = cams[v0:v0 + views_per_job]
                 arr = L.make_cameras(cb)
@@ -41,8 +53,8 @@ class BatchScorer:
                 j.opac, j.sh = L.ptr(ds.opacities), L.ptr(ds.sh)
                 j.V = len(cb)
                 j.cams = C.cast(arr, C.POINTER(L.potr_camera))
-                j.scores = L.ptr(scores)
-                j.importance = L.ptr(importance)
+                j.out = L.make_outputs(out, v0)
+                j.target = None if targets is None else targets[v0].data_ptr()
                 jobs.append(j)
         self.n_jobs = len(jobs)
         self.jobs = (L.potr_job * self.n_jobs)(*jobs)

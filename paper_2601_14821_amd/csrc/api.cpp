@@ -232,17 +232,18 @@ potr_status potr_backward(int64_t N, int32_t V, const potr_camera* cams, const p
     return st;
 }
 
-potr_status potr_render_score(int64_t N, int32_t V, const potr_camera* cams, const potr_config* cfg,
-                              const potr_proj* proj, const uint32_t* sorted_ids, const int32_t* tile_ranges,
-                              float* image, const float* target, float* scores, float* scores_se, float* importance,
-                              void* stream) {
+potr_status potr_render_score_out(int64_t N, int32_t V, const potr_camera* cams, const potr_config* cfg,
+                                  const potr_proj* proj, const uint32_t* sorted_ids, const int32_t* tile_ranges,
+                                  float* image, const float* target, const potr_outputs* out, void* stream) {
     potr_status st = check_cfg(cfg);
     if (st == POTR_OK) st = check_cams(V, cams, cfg);
     if (st != POTR_OK) return st;
     if (N < 0) return fail(POTR_EINVAL, "N = %lld", (long long)N);
+    if (!out) return fail(POTR_EINVAL, "NULL outputs");
+    st = check_outputs(*out, N, V, target);
+    if (st != POTR_OK) return st;
     if (!tile_ranges || (N > 0 && (!proj || !sorted_ids))) return fail(POTR_EINVAL, "NULL buffer");
-    if (!image && !scores && !scores_se && !importance) return fail(POTR_EINVAL, "no output requested");
-    if (scores_se && !target) return fail(POTR_EINVAL, "scores_se needs a target image");
+    if (!image && !out->scores && !out->scores_se && !out->importance) return fail(POTR_EINVAL, "no output requested");
     if (!aligned16(proj)) return fail(POTR_EINVAL, "proj must be 16-byte aligned");
     const potr_camera& c = cams[0];
     const int tx = tiles_x(c, *cfg), T = tx * tiles_y(c, *cfg);
@@ -262,14 +263,24 @@ potr_status potr_render_score(int64_t N, int32_t V, const potr_camera* cams, con
             j.tiles = T;
             j.image = image ? image + v * P * 3 : nullptr;
             j.target = target ? target + v * P * 3 : nullptr;
-            j.scores = N > 0 ? scores : nullptr;
-            j.importance = N > 0 ? importance : nullptr;
-            j.scores_se = N > 0 ? scores_se : nullptr;
+            set_outputs(j, *out, N, v);
         }
         st = launch_render_score(jobs, nv, T, *cfg, (hipStream_t)stream);
         if (st != POTR_OK) return st;
     }
     return POTR_OK;
+}
+
+potr_status potr_render_score(int64_t N, int32_t V, const potr_camera* cams, const potr_config* cfg,
+                              const potr_proj* proj, const uint32_t* sorted_ids, const int32_t* tile_ranges,
+                              float* image, const float* target, float* scores, float* scores_se, float* importance,
+                              void* stream) {
+    potr_outputs o{};
+    o.scores = scores;
+    o.scores_se = scores_se;
+    o.importance = importance;
+    o.scores_weight = o.se_weight = o.importance_weight = 1.f;
+    return potr_render_score_out(N, V, cams, cfg, proj, sorted_ids, tile_ranges, image, target, &o, stream);
 }
 
 }  // extern "C"

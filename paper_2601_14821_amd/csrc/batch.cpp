@@ -6,6 +6,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <string>
 #include <vector>
 
 #include "common.h"
@@ -41,6 +42,7 @@ struct potr_batch_s {
     size_t bytes = 0;
     int32_t n_view_jobs = 0;
     int32_t grid = 0;
+    bool with_se = false;   // some job asks for dSE sums
     char* ws = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -91,14 +93,20 @@ void plan_layout(potr_batch_s* b) {
     b->bytes = o;
 }
 
-potr_status validate_jobs(const potr_job* jobs, int32_t n_jobs, bool need_scores = true) {
+bool has_output(const potr_job& J) { return J.out.scores || J.out.scores_se || J.out.importance; }
+
+potr_status validate_jobs(const potr_job* jobs, int32_t n_jobs, bool need_output = true) {
     if (!jobs || n_jobs < 1) return fail(POTR_EINVAL, "need at least one job");
     for (int32_t j = 0; j < n_jobs; ++j) {
         const potr_job& J = jobs[j];
         if (J.N < 0 || J.V < 1 || J.N * (int64_t)J.V >= (int64_t(1) << 31) || !J.cams)
             return fail(POTR_EINVAL, "job %d: bad N/V/cams", j);
-        if (J.N > 0 && (!J.means || !J.scales || !J.quats || !J.opac || !J.sh || (need_scores && !J.scores)))
+        if (J.N > 0 && (!J.means || !J.scales || !J.quats || !J.opac || !J.sh || (need_output && !has_output(J))))
             return fail(POTR_EINVAL, "job %d: NULL buffer", j);
+        if (check_outputs(J.out, J.N, J.V, J.target) != POTR_OK) {
+            const std::string why = potr_last_error();
+            return fail(POTR_EINVAL, "job %d: %s", j, why.c_str());
+        }
         if (J.N > 0 && (reinterpret_cast<uintptr_t>(J.sh) & 15u) != 0)
             return fail(POTR_EINVAL, "job %d: sh must be 16-byte aligned", j);
     }
@@ -176,7 +184,9 @@ potr_status potr_batch_create(const potr_job* jobs, int32_t n_jobs, const potr_c
         b->capacity[j] = (int64_t)c;
     }
     plan_layout(b);
-    b->grid = persistent_grid(b->cfg);
+    b->with_se = false;
+    for (auto& J : b->jobs) b->with_se = b->with_se || (J.N > 0 && J.out.scores_se != nullptr);
+    b->grid = persistent_grid(b->cfg, b->with_se);
     if (b->lane_off.size() > 1) {
         st = POTR_OK;
         for (size_t l = 0; l < b->lane_off.size() && st == POTR_OK; ++l) {
@@ -232,8 +242,8 @@ potr_status potr_batch_bind(potr_batch b, void* ws, size_t ws_bytes, void* strea
             vj.H = c0.height;
             vj.tiles_x = tiles_x(c0, b->cfg);
             vj.tiles = T;
-            vj.scores = J.scores;
-            vj.importance = J.importance;
+            vj.target = J.target ? J.target + (int64_t)v * c0.width * c0.height * 3 : nullptr;
+            set_outputs(vj, J.out, J.N, v);
             table.push_back(vj);
             prefix.push_back(prefix.back() + (J.N > 0 ? T : 0));
         }
@@ -292,7 +302,8 @@ potr_status potr_batch_run(potr_batch b, void* stream) {
     }
     potr_status st = launch_render_score_persistent((const ViewJob*)(ws + b->off_table), b->n_view_jobs,
                                                     (const int64_t*)(ws + b->off_prefix),
-                                                    (int64_t*)(ws + b->off_counter), b->grid, b->cfg, s);
+                                                    (int64_t*)(ws + b->off_counter), b->grid, b->cfg,
+                                                    b->with_se, s);
     if (st != POTR_OK) return st;
     return launch_check_overflow(npairs, (const int64_t*)(ws + b->off_caps), (int32_t)b->jobs.size(),
                                  (int32_t*)(ws + b->off_flag), s);
@@ -303,7 +314,7 @@ potr_status potr_batch_render(potr_batch b, void* stream) {
     char* ws = b->ws;
     return launch_render_score_persistent((const ViewJob*)(ws + b->off_table), b->n_view_jobs,
                                           (const int64_t*)(ws + b->off_prefix), (int64_t*)(ws + b->off_counter),
-                                          b->grid, b->cfg, (hipStream_t)stream);
+                                          b->grid, b->cfg, b->with_se, (hipStream_t)stream);
 }
 
 potr_status potr_batch_capture(potr_batch b, void* stream) {
@@ -367,15 +378,27 @@ extern "C" potr_status potr_autotune(const potr_job* jobs, int32_t n_jobs, potr_
     if (st != POTR_OK) return st;
     if (reps < 1) reps = 3;
     hipStream_t s = (hipStream_t)stream;
+    // scratch outputs of the jobs' shapes (a job without outputs gets scores)
     std::vector<potr_job> scratch(jobs, jobs + n_jobs);
     std::vector<float*> bufs;
     for (auto& J : scratch) {
-        float* p = nullptr;
-        st = hip_ok(hipMalloc(&p, (size_t)(J.N > 0 ? J.N : 1) * 4), "hipMalloc (scratch scores)");
+        if (!has_output(J)) {
+            J.out.scores = reinterpret_cast<float*>(1);
+            J.out.scores_stride = 0;
+            J.out.scores_weight = 1.f;
+        }
+        float** outs[3] = {&J.out.scores, &J.out.scores_se, &J.out.importance};
+        const int64_t strides[3] = {J.out.scores_stride, J.out.se_stride, J.out.importance_stride};
+        for (int o = 0; o < 3 && st == POTR_OK; ++o) {
+            if (!*outs[o]) continue;
+            const int64_t n = strides[o] > 0 ? (int64_t)(J.V - 1) * strides[o] + J.N : J.N;
+            float* p = nullptr;
+            st = hip_ok(hipMalloc(&p, (size_t)(n > 0 ? n : 1) * 4), "hipMalloc (scratch outputs)");
+            if (st != POTR_OK) break;
+            bufs.push_back(p);
+            *outs[o] = p;
+        }
         if (st != POTR_OK) break;
-        bufs.push_back(p);
-        J.scores = p;
-        J.importance = nullptr;
     }
     const int shapes[3][2] = {{16, 16}, {8, 8}, {32, 8}};
     const int batches[4] = {64, 128, 320, 512};

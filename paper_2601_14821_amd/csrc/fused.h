@@ -15,19 +15,48 @@ struct ViewJob {
     float* scores;            // [N] += sum |PD|_1, or null
     float* importance;        // [N] += sum T alpha, or null
     float* scores_se;         // [N] += sum dSE, or null
+    float w_l1, w_im, w_se;   // factors applied to each (tile, splat) partial sum before it is added
 };
 
 struct ViewJobs {
     ViewJob j[kViewsPerLaunch];
 };
 
+// An output description for N splats x V views: each stride 0 or at least N
+// (views must not overlap), each weight finite and > 0, dSE only with a target.
+inline potr_status check_outputs(const potr_outputs& o, int64_t N, int32_t V, const float* target) {
+    const float* const w[3] = {&o.scores_weight, &o.se_weight, &o.importance_weight};
+    const int64_t st[3] = {o.scores_stride, o.se_stride, o.importance_stride};
+    const void* const p[3] = {o.scores, o.scores_se, o.importance};
+    for (int k = 0; k < 3; ++k) {
+        if (!p[k]) continue;
+        if (!(*w[k] > 0.f) || *w[k] > 3.0e38f) return fail(POTR_EINVAL, "output %d: weight %g", k, (double)*w[k]);
+        if (st[k] < 0 || (st[k] > 0 && st[k] < N) || (st[k] > 0 && V > 1 && st[k] > (int64_t(1) << 40)))
+            return fail(POTR_EINVAL, "output %d: stride %lld for N = %lld", k, (long long)st[k], (long long)N);
+    }
+    if (o.scores_se && !target) return fail(POTR_EINVAL, "scores_se needs a target image");
+    return POTR_OK;
+}
+
+// View v's output pointers and weights (no outputs when the scene is empty).
+inline void set_outputs(ViewJob& j, const potr_outputs& o, int64_t N, int64_t v) {
+    j.scores = (N > 0 && o.scores) ? o.scores + v * o.scores_stride : nullptr;
+    j.scores_se = (N > 0 && o.scores_se) ? o.scores_se + v * o.se_stride : nullptr;
+    j.importance = (N > 0 && o.importance) ? o.importance + v * o.importance_stride : nullptr;
+    j.w_l1 = o.scores_weight;
+    j.w_se = o.se_weight;
+    j.w_im = o.importance_weight;
+}
+
 // dynamic LDS bytes of the fused pass with n_out per-splat outputs
 size_t fused_smem_bytes(const potr_config& cfg, int n_out);
-int persistent_grid(const potr_config& cfg);
+int persistent_grid(const potr_config& cfg, bool with_se);
 potr_status launch_render_score(const ViewJobs& jobs, int32_t n_views, int32_t tiles_per_view,
                                 const potr_config& cfg, hipStream_t s);
+// with_se: some job of the table has scores_se (the kernel then also keeps the
+// per-entry dSE sums; jobs without it skip them)
 potr_status launch_render_score_persistent(const ViewJob* jobs_dev, int32_t n_jobs, const int64_t* item_prefix_dev,
                                            int64_t* counter_dev, int32_t grid, const potr_config& cfg,
-                                           hipStream_t s);
+                                           bool with_se, hipStream_t s);
 
 }  // namespace potr

@@ -81,7 +81,9 @@ __device__ void render_score_tile(const ViewJob& J, int tile, const potr_config&
     const int B = cfg.lds_batch;
     const float qmax = cfg.q_max, amin = cfg.alpha_min, amax = cfg.alpha_max, tmin = cfg.t_min;
     const float emin = exp_floor(qmax);
-    const int n_out = (J.scores ? 1 : 0) + (J.importance ? 1 : 0) + (SE ? 1 : 0);
+    // SE instantiations serve jobs with and without dSE output
+    const bool se = SE && J.scores_se != nullptr;
+    const int n_out = (J.scores ? 1 : 0) + (J.importance ? 1 : 0) + (se ? 1 : 0);
     const int o_l1 = 0, o_im = J.scores ? 1 : 0, o_se = o_im + (J.importance ? 1 : 0);
     uint16_t* const L = sm.list + wid * B;
     uint16_t* const Hl = sm.hits + wid * B;
@@ -156,7 +158,7 @@ __device__ void render_score_tile(const ViewJob& J, int tile, const potr_config&
             J.image[3 * pix + 1] = Qg;
             J.image[3 * pix + 2] = Qb;
         }
-        if (SE) {
+        if (se) {
             er = Qr - J.target[3 * pix];
             eg = Qg - J.target[3 * pix + 1];
             eb = Qb - J.target[3 * pix + 2];
@@ -257,7 +259,7 @@ __device__ void render_score_tile(const ViewJob& J, int tile, const potr_config&
                 const float s = wave_sum4(imv[0], imv[1], imv[2], imv[3]);
                 if (writer) atomicAdd(&sm.part[o_im * B + jw], s);
             }
-            if (SE) {
+            if (se) {
                 const float s = wave_sum4(sev[0], sev[1], sev[2], sev[3]);
                 if (writer) atomicAdd(&sm.part[o_se * B + jw], s);
             }
@@ -272,9 +274,9 @@ __device__ void render_score_tile(const ViewJob& J, int tile, const potr_config&
                     t[o] = sm.part[o * B + j];
                     sm.part[o * B + j] = 0.f;
                 }
-            if (J.scores && t[o_l1] != 0.f) unsafeAtomicAdd(J.scores + id, t[o_l1]);
-            if (J.importance && t[o_im] != 0.f) unsafeAtomicAdd(J.importance + id, t[o_im]);
-            if (SE && t[o_se] != 0.f) unsafeAtomicAdd(J.scores_se + id, t[o_se]);
+            if (J.scores && t[o_l1] != 0.f) unsafeAtomicAdd(J.scores + id, t[o_l1] * J.w_l1);
+            if (J.importance && t[o_im] != 0.f) unsafeAtomicAdd(J.importance + id, t[o_im] * J.w_im);
+            if (se && t[o_se] != 0.f) unsafeAtomicAdd(J.scores_se + id, t[o_se] * J.w_se);
         }
     }
     __syncthreads();
@@ -302,7 +304,7 @@ __global__ __launch_bounds__(TW * TH) __attribute__((amdgpu_waves_per_eu(7))) vo
 
 // Persistent form: items are (view job, tile) pairs numbered job-major;
 // item_prefix[j] is the first item of job j (item_prefix[n_jobs] = total).
-template <int TW, int TH>
+template <int TW, int TH, bool SE>
 __global__ __launch_bounds__(TW * TH) void k_render_score_persistent(const ViewJob* __restrict__ jobs, int32_t n_jobs,
                                                                      const int64_t* __restrict__ item_prefix,
                                                                      int64_t* __restrict__ counter, potr_config cfg) {
@@ -323,7 +325,7 @@ __global__ __launch_bounds__(TW * TH) void k_render_score_persistent(const ViewJ
             else hi = mid - 1;
         }
         const ViewJob J = jobs[lo];
-        render_score_tile<TW, TH, false>(J, (int)(item - item_prefix[lo]), cfg, sm);
+        render_score_tile<TW, TH, SE>(J, (int)(item - item_prefix[lo]), cfg, sm);
     }
 }
 
@@ -366,11 +368,11 @@ potr_status launch_render_score(const ViewJobs& jobs_dev, int32_t n_views, int32
     return check_launch("k_render_score");
 }
 
-int persistent_grid(const potr_config& cfg) {
+int persistent_grid(const potr_config& cfg, bool with_se) {
     int dev = 0, cus = 256;
     if (hipGetDevice(&dev) == hipSuccess) hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     const int threads = cfg.tile_w * cfg.tile_h;
-    const size_t sm = fused_smem_bytes(cfg, 2);
+    const size_t sm = fused_smem_bytes(cfg, with_se ? 3 : 2);
     int by_waves = 32 / ((threads + 63) / 64);              // 32 waves per CU
     int by_lds = (int)((160 * 1024) / (sm + 256));
     int per_cu = by_waves < by_lds ? by_waves : by_lds;
@@ -378,26 +380,33 @@ int persistent_grid(const potr_config& cfg) {
     return cus * per_cu;
 }
 
-potr_status launch_render_score_persistent(const ViewJob* jobs_dev, int32_t n_jobs, const int64_t* item_prefix_dev,
-                                           int64_t* counter_dev, int32_t grid_size, const potr_config& cfg,
-                                           hipStream_t s) {
-    hipLaunchKernelGGL(k_zero_i64, dim3(1), dim3(1), 0, s, counter_dev);
-    potr_status st = check_launch("k_zero_i64");
-    if (st != POTR_OK) return st;
-    const size_t sm = fused_smem_bytes(cfg, 2);   // scores and importance
+template <bool SE>
+potr_status launch_persistent(const ViewJob* jobs_dev, int32_t n_jobs, const int64_t* item_prefix_dev,
+                              int64_t* counter_dev, int32_t grid_size, const potr_config& cfg, hipStream_t s) {
+    const size_t sm = fused_smem_bytes(cfg, SE ? 3 : 2);   // scores, importance (and dSE)
     const dim3 grid(grid_size);
     if (cfg.tile_w == 16 && cfg.tile_h == 16)
-        hipLaunchKernelGGL((k_render_score_persistent<16, 16>), grid, dim3(256), sm, s, jobs_dev, n_jobs,
+        hipLaunchKernelGGL((k_render_score_persistent<16, 16, SE>), grid, dim3(256), sm, s, jobs_dev, n_jobs,
                            item_prefix_dev, counter_dev, cfg);
     else if (cfg.tile_w == 8 && cfg.tile_h == 8)
-        hipLaunchKernelGGL((k_render_score_persistent<8, 8>), grid, dim3(64), sm, s, jobs_dev, n_jobs,
+        hipLaunchKernelGGL((k_render_score_persistent<8, 8, SE>), grid, dim3(64), sm, s, jobs_dev, n_jobs,
                            item_prefix_dev, counter_dev, cfg);
     else if (cfg.tile_w == 32 && cfg.tile_h == 8)
-        hipLaunchKernelGGL((k_render_score_persistent<32, 8>), grid, dim3(256), sm, s, jobs_dev, n_jobs,
+        hipLaunchKernelGGL((k_render_score_persistent<32, 8, SE>), grid, dim3(256), sm, s, jobs_dev, n_jobs,
                            item_prefix_dev, counter_dev, cfg);
     else
         return fail(POTR_EUNSUPPORTED, "tile %dx%d not built", cfg.tile_w, cfg.tile_h);
     return check_launch("k_render_score_persistent");
+}
+
+potr_status launch_render_score_persistent(const ViewJob* jobs_dev, int32_t n_jobs, const int64_t* item_prefix_dev,
+                                           int64_t* counter_dev, int32_t grid_size, const potr_config& cfg,
+                                           bool with_se, hipStream_t s) {
+    hipLaunchKernelGGL(k_zero_i64, dim3(1), dim3(1), 0, s, counter_dev);
+    potr_status st = check_launch("k_zero_i64");
+    if (st != POTR_OK) return st;
+    return with_se ? launch_persistent<true>(jobs_dev, n_jobs, item_prefix_dev, counter_dev, grid_size, cfg, s)
+                   : launch_persistent<false>(jobs_dev, n_jobs, item_prefix_dev, counter_dev, grid_size, cfg, s);
 }
 
 }  // namespace potr

@@ -51,6 +51,26 @@ class ViewBatch:
     n_blend: torch.Tensor | None = None
 
 
+@dataclasses.dataclass
+class Outputs:
+    """Per-splat reductions of the fused pass (potr_outputs): each tensor is
+    optional; view v of a call adds into tensor[v * stride :][:N] (stride 0: all
+    views into one [N] array; stride N: a [V, N] array), every partial sum
+    multiplied by the weight first."""
+    scores: torch.Tensor | None = None
+    scores_stride: int = 0
+    scores_weight: float = 1.0
+    scores_se: torch.Tensor | None = None
+    se_stride: int = 0
+    se_weight: float = 1.0
+    importance: torch.Tensor | None = None
+    importance_stride: int = 0
+    importance_weight: float = 1.0
+
+    def any(self) -> bool:
+        return self.scores is not None or self.scores_se is not None or self.importance is not None
+
+
 class Rasterizer:
     def __init__(self, settings, device="cuda"):
         self.s = settings
@@ -220,14 +240,49 @@ class Rasterizer:
                L.ptr(vb.sorted_ids), L.ptr(vb.tile_ranges), L.ptr(image), L.ptr(target), L.ptr(scores),
                L.ptr(scores_se), L.ptr(importance), L.stream_handle())
 
-    def score_views_fused(self, ds: DeviceScene, cams, views_per_batch: int = 8, scores=None, importance=None):
-        """Removal scores over all views with the fused launch (no per-pixel buffers)."""
-        if scores is None:
-            scores = torch.zeros(ds.n, dtype=torch.float32, device=self.device)
+    def render_score_out(self, vb: ViewBatch, cams, out: Outputs, v0: int = 0, image=None, target=None) -> None:
+        """potr_render_score_out: the views of `vb` are views v0.. of `out`'s arrays."""
+        o = L.make_outputs(out, v0)
+        L.call("potr_render_score_out", vb.N, vb.V, L.make_cameras(cams), C.byref(self.cfg), L.ptr(vb.proj),
+               L.ptr(vb.sorted_ids), L.ptr(vb.tile_ranges), L.ptr(image), L.ptr(target), C.byref(o),
+               L.stream_handle())
+
+    def score_views_fused(self, ds: DeviceScene, cams, views_per_batch: int = 8, scores=None, importance=None,
+                          out: Outputs | None = None, targets=None):
+        """Removal scores over all views with the fused launch (no per-pixel buffers).
+        With `out`, its description is used (per-view arrays, weights, dSE with
+        `targets` [V,H,W,3]); otherwise scores (and importance) accumulate raw."""
+        if out is None:
+            if scores is None:
+                scores = torch.zeros(ds.n, dtype=torch.float32, device=self.device)
+            out = Outputs(scores=scores, importance=importance)
         for v0 in range(0, len(cams), views_per_batch):
             cb = cams[v0:v0 + views_per_batch]
             vb = self.project(ds, cb)
             self.bin(vb, cb)
             self.sort(vb, cb)
-            self.render_score(vb, cb, scores=scores, importance=importance)
-        return scores
+            tgt = None if targets is None else targets[v0:v0 + len(cb)].contiguous()
+            self.render_score_out(vb, cb, out, v0=v0, target=tgt)
+        return out.scores
+
+    def removal_statistics(self, ds: DeviceScene, cams, targets, per_view_importance: bool = False,
+                           views_per_batch: int = 8):
+        """The pruning controller's inputs, normalised as in the paper: dMSE_k
+        (Sec. 4.2, the camera-, pixel- and channel-averaged dSE against the
+        target images [V,H,W,3]) and I_k (Sec. 4.1, the camera average of the
+        image fraction I_k(s)); with per_view_importance also I_k(s) [V, N].
+        Every view must have the same size. Returns (dmse, importance, per_view)."""
+        N, V = ds.n, len(cams)
+        P = cams[0].width * cams[0].height
+        if any(c.width * c.height != P for c in cams):
+            raise ValueError("removal_statistics needs views of one size")
+        dmse = torch.zeros(N, dtype=torch.float32, device=self.device)
+        imp = torch.zeros(N, dtype=torch.float32, device=self.device)
+        out = Outputs(scores_se=dmse, se_weight=1.0 / (3.0 * V * P), importance=imp, importance_weight=1.0 / (V * P))
+        self.score_views_fused(ds, cams, views_per_batch, out=out, targets=targets)
+        per_view = None
+        if per_view_importance:
+            per_view = torch.zeros(V, N, dtype=torch.float32, device=self.device)
+            self.score_views_fused(ds, cams, views_per_batch,
+                                   out=Outputs(importance=per_view, importance_stride=N, importance_weight=1.0 / P))
+        return dmse, imp, per_view

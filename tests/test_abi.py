@@ -44,13 +44,17 @@ def test_exports_every_declared_symbol(lib):
 
 
 def test_abi_version(lib):
-    assert lib.potr_abi_version() == 2
+    assert lib.potr_abi_version() == 3
 
 
 def test_struct_layouts():
     assert C.sizeof(L.potr_camera) == 72
     assert C.sizeof(L.potr_config) == 56
     assert L.PROJ_DTYPE.itemsize == 48
+    # three (pointer, int64 stride, float weight) triples, each padded to 24 bytes
+    assert C.sizeof(L.potr_outputs) == 72
+    assert L.potr_outputs.importance_weight.offset == 64
+    assert C.sizeof(L.potr_job) == 8 * 6 + 8 + 8 + 72 + 8
 
 
 def _cfg(**kw):
@@ -150,3 +154,38 @@ def test_new_entry_points_validate(lib):
     assert b.value == 1000 * 2 * 9 * 4
     args = [1000, 2, _cams(2), C.byref(cfg)] + [16] * 12 + [16, b.value - 4] + [16] * 5 + [None]
     assert _status("potr_backward", *args) == L.POTR_ECAPACITY
+
+
+def _render_score_out(out, target=None, N=100, V=2):
+    return _status("potr_render_score_out", N, V, _cams(V), C.byref(_cfg()), 16, 16, 16, None, target,
+                   C.byref(out), None)
+
+
+@pytest.mark.parametrize("field, value, msg", [
+    ("scores_weight", 0.0, "weight"), ("scores_weight", -1.0, "weight"), ("scores_weight", float("inf"), "weight"),
+    ("scores_stride", -1, "stride"), ("scores_stride", 50, "stride")])
+def test_outputs_are_validated(lib, field, value, msg):
+    o = L.potr_outputs()
+    o.scores, o.scores_weight = 16, 1.0
+    setattr(o, field, value)
+    assert _render_score_out(o) == L.POTR_EINVAL
+    assert msg in lib.potr_last_error().decode()
+
+
+def test_outputs_se_needs_target_and_some_output(lib):
+    o = L.potr_outputs()
+    assert _render_score_out(o) == L.POTR_EINVAL                       # nothing requested
+    o.scores_se, o.se_weight = 16, 1.0
+    assert _render_score_out(o) == L.POTR_EINVAL
+    assert "target" in lib.potr_last_error().decode()
+    # a job's outputs are checked by the batch the same way
+    j = L.potr_job()
+    j.N, j.V = 100, 1
+    cams = _cams(1)
+    j.cams = C.cast(cams, C.POINTER(L.potr_camera))
+    j.means = j.scales = j.quats = j.opac = j.sh = 16
+    j.out.importance, j.out.importance_weight, j.out.importance_stride = 16, 1.0, 7
+    out = C.c_void_p()
+    arr = (L.potr_job * 1)(j)
+    assert _status("potr_batch_create", arr, 1, C.byref(_cfg()), 0.05, C.byref(out), None) == L.POTR_EINVAL
+    assert "job 0" in lib.potr_last_error().decode() and "stride" in lib.potr_last_error().decode()
