@@ -348,6 +348,45 @@ POTR_API potr_status potr_batch_replay(potr_batch b, void* stream);
 POTR_API potr_status potr_batch_overflow(potr_batch b, int32_t* n_overflowed, void* stream);
 POTR_API potr_status potr_batch_destroy(potr_batch b);
 
+/* ---------------------------------------------------------------------------
+ * Pruning controller (Sec. 4.3), one iteration on the device.
+ *
+ * potr_prune_select: which splats one iteration removes, from every splat's
+ *   dMSE_k and importance I_k (Sec. 4.1, 4.2; normalised as the paper defines
+ *   them, e.g. by potr_render_score_out's weights). Candidates are the splats with
+ *   dMSE_k < dmse_max; the budget is B = (sum of the candidates' I_k) / remaining,
+ *   `remaining` the iterations still to run, this one included; candidates are
+ *   taken in ascending order of m(dMSE_k / dmse_max), m(x) = x for x >= 0 and
+ *   (sqrt(1 - 2 a x) - 1) / a for x < 0, ties by index, until B <= the importance
+ *   taken (that splat included). Nothing is removed when B = 0; a splat with
+ *   dMSE_k >= dmse_max is never removed.
+ *   Exact rules: x and m(x) are correctly rounded FP64 operations in that order;
+ *   each I_k is rounded to a multiple of 2^-52 and the budget is compared in
+ *   those integers (first prefix reaching ceil(total / remaining)), so no
+ *   summation order moves the cut.
+ *   dmse, importance [N] FP32 (device); importance must lie in [0, 1] with a
+ *     candidate sum of at most 2 (an image fraction), else *n_removed = -1 and
+ *     nothing is removed
+ *   dmse_max > 0 (the paper's dMSE_MAX), a > 0 (the paper uses 10), remaining >= 1
+ *   ws     workspace of potr_prune_workspace_size(N) bytes
+ *   remove [N] uint8 out: 1 for a removed splat
+ *   n_removed (device) int64 out: how many (or -1, see above)
+ * potr_prune_compact: the survivors (remove[k] == 0) in index order: each splat
+ *   array of potr_project's layout is copied to its *_out array (N_kept rows),
+ *   ids_out gets ids[k] (or k when ids is NULL), *n_kept (device int64) the
+ *   count. Outputs must not overlap the inputs; quats and sh 16-byte aligned.
+ * Both only enqueue work (no allocation, no host synchronisation).
+ * ------------------------------------------------------------------------- */
+POTR_API potr_status potr_prune_workspace_size(int64_t N, size_t* bytes);
+POTR_API potr_status potr_prune_select(int64_t N, const float* dmse, const float* importance, double dmse_max,
+                                       int32_t remaining, double a, void* ws, size_t ws_bytes, uint8_t* remove,
+                                       int64_t* n_removed, void* stream);
+POTR_API potr_status potr_prune_compact(int64_t N, const uint8_t* remove, const float* means, const float* scales,
+                                        const float* quats, const float* opac, const float* sh, const int32_t* ids,
+                                        void* ws, size_t ws_bytes, float* means_out, float* scales_out,
+                                        float* quats_out, float* opac_out, float* sh_out, int32_t* ids_out,
+                                        int64_t* n_kept, void* stream);
+
 /* potr_autotune: times every tile shape (16x16, 8x8, 32x8) with every LDS batch
  * (64, 128, 320, 512) on the given jobs (`reps` timed runs each, after one
  * warm-up) and writes the fastest tile_w, tile_h, lds_batch into *inout. Uses

@@ -9,6 +9,7 @@
 
 #include "common.h"
 #include "fused.h"
+#include "prune.h"
 
 namespace potr {
 
@@ -281,6 +282,43 @@ potr_status potr_render_score(int64_t N, int32_t V, const potr_camera* cams, con
     o.importance = importance;
     o.scores_weight = o.se_weight = o.importance_weight = 1.f;
     return potr_render_score_out(N, V, cams, cfg, proj, sorted_ids, tile_ranges, image, target, &o, stream);
+}
+
+potr_status potr_prune_workspace_size(int64_t N, size_t* bytes) {
+    if (!bytes || N < 0) return fail(POTR_EINVAL, "bad argument");
+    const size_t a = prune_select_scratch_bytes(), b = prune_compact_scratch_bytes(N);
+    *bytes = a > b ? a : b;
+    return POTR_OK;
+}
+
+potr_status potr_prune_select(int64_t N, const float* dmse, const float* importance, double dmse_max,
+                              int32_t remaining, double a, void* ws, size_t ws_bytes, uint8_t* remove,
+                              int64_t* n_removed, void* stream) {
+    if (N < 0 || N >= (int64_t(1) << 31)) return fail(POTR_EINVAL, "N = %lld", (long long)N);
+    if (!(dmse_max > 0.0) || dmse_max > 1e300) return fail(POTR_EINVAL, "dmse_max = %g", dmse_max);
+    if (!(a > 0.0) || a > 1e300) return fail(POTR_EINVAL, "a = %g", a);
+    if (remaining < 1) return fail(POTR_EINVAL, "remaining = %d", remaining);
+    if (!ws || !n_removed || (N > 0 && (!dmse || !importance || !remove))) return fail(POTR_EINVAL, "NULL buffer");
+    if (ws_bytes < prune_select_scratch_bytes()) return fail(POTR_ECAPACITY, "prune workspace %zu bytes", ws_bytes);
+    return launch_prune_select(N, dmse, importance, dmse_max, remaining, a, ws, remove, n_removed,
+                               (hipStream_t)stream);
+}
+
+potr_status potr_prune_compact(int64_t N, const uint8_t* remove, const float* means, const float* scales,
+                               const float* quats, const float* opac, const float* sh, const int32_t* ids, void* ws,
+                               size_t ws_bytes, float* means_out, float* scales_out, float* quats_out,
+                               float* opac_out, float* sh_out, int32_t* ids_out, int64_t* n_kept, void* stream) {
+    if (N < 0 || N >= (int64_t(1) << 31)) return fail(POTR_EINVAL, "N = %lld", (long long)N);
+    if (!ws || !n_kept) return fail(POTR_EINVAL, "NULL buffer");
+    if (N > 0 && (!remove || !means || !scales || !quats || !opac || !sh || !means_out || !scales_out ||
+                  !quats_out || !opac_out || !sh_out || !ids_out))
+        return fail(POTR_EINVAL, "NULL buffer");
+    if (!aligned16(quats) || !aligned16(sh) || !aligned16(quats_out) || !aligned16(sh_out))
+        return fail(POTR_EINVAL, "quats and sh must be 16-byte aligned");
+    if (ws_bytes < prune_compact_scratch_bytes(N)) return fail(POTR_ECAPACITY, "prune workspace %zu bytes", ws_bytes);
+    const PruneArrays in{means, scales, quats, opac, sh, ids};
+    const PruneOut out{means_out, scales_out, quats_out, opac_out, sh_out, ids_out};
+    return launch_prune_compact(N, remove, in, out, ws, n_kept, (hipStream_t)stream);
 }
 
 }  // extern "C"
