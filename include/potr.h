@@ -387,6 +387,24 @@ POTR_API potr_status potr_prune_compact(int64_t N, const uint8_t* remove, const 
                                         float* quats_out, float* opac_out, float* sh_out, int32_t* ids_out,
                                         int64_t* n_kept, void* stream);
 
+/* ---------------------------------------------------------------------------
+ * potr_prune_select_noalloc -- for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): potr_prune_select without the workspace argument. Its scratch
+ * (4 KB: the select's state and histograms, whatever N) is a static device array
+ * of the library, one copy per GPU, which each GPU the library runs on keeps
+ * until the process ends; the call uses the copy of the current device, so
+ * `stream` must belong to the current device. The call clears the scratch
+ * itself (with a kernel) before using it. Calls that overlap on one GPU share
+ * that scratch and race: order them (one stream, or events between streams).
+ * Limits: N <= 2^31 - 1 (larger N is rejected with POTR_EINVAL); other
+ * arguments, outputs and errors as potr_prune_select. Allocates nothing and
+ * calls no allocating routine; only enqueues work.
+ * ------------------------------------------------------------------------- */
+POTR_API potr_status potr_prune_select_noalloc(int64_t N, const float* dmse, const float* importance,
+                                               double dmse_max, int32_t remaining, double a, uint8_t* remove,
+                                               int64_t* n_removed, void* stream);
+
 /* potr_autotune: times every tile shape (16x16, 8x8, 32x8) with every LDS batch
  * (64, 128, 320, 512) on the given jobs (`reps` timed runs each, after one
  * warm-up) and writes the fastest tile_w, tile_h, lds_batch into *inout. Uses

@@ -304,6 +304,19 @@ potr_status potr_prune_select(int64_t N, const float* dmse, const float* importa
                                (hipStream_t)stream);
 }
 
+potr_status potr_prune_select_noalloc(int64_t N, const float* dmse, const float* importance, double dmse_max,
+                                      int32_t remaining, double a, uint8_t* remove, int64_t* n_removed,
+                                      void* stream) {
+    if (N < 0 || N >= (int64_t(1) << 31))
+        return fail(POTR_EINVAL, "N = %lld: the no-allocation select takes at most 2^31 - 1 splats", (long long)N);
+    if (!(dmse_max > 0.0) || dmse_max > 1e300) return fail(POTR_EINVAL, "dmse_max = %g", dmse_max);
+    if (!(a > 0.0) || a > 1e300) return fail(POTR_EINVAL, "a = %g", a);
+    if (remaining < 1) return fail(POTR_EINVAL, "remaining = %d", remaining);
+    if (!n_removed || (N > 0 && (!dmse || !importance || !remove))) return fail(POTR_EINVAL, "NULL buffer");
+    return launch_prune_select_noalloc(N, dmse, importance, dmse_max, remaining, a, remove, n_removed,
+                                       (hipStream_t)stream);
+}
+
 potr_status potr_prune_compact(int64_t N, const uint8_t* remove, const float* means, const float* scales,
                                const float* quats, const float* opac, const float* sh, const int32_t* ids, void* ws,
                                size_t ws_bytes, float* means_out, float* scales_out, float* quats_out,

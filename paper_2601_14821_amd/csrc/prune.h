@@ -39,6 +39,10 @@ struct PruneOut {
 size_t prune_select_scratch_bytes();
 potr_status launch_prune_select(int64_t N, const float* dmse, const float* imp, double dmax, int32_t remaining,
                                 double a, void* scratch, uint8_t* remove, int64_t* n_removed, hipStream_t s);
+// The same with the scratch in the library's static device array (no allocation).
+potr_status launch_prune_select_noalloc(int64_t N, const float* dmse, const float* imp, double dmax,
+                                        int32_t remaining, double a, uint8_t* remove, int64_t* n_removed,
+                                        hipStream_t s);
 size_t prune_compact_scratch_bytes(int64_t N);
 potr_status launch_prune_compact(int64_t N, const uint8_t* remove, const PruneArrays& in, const PruneOut& out,
                                  void* scratch, int64_t* n_kept, hipStream_t s);

@@ -19,6 +19,8 @@
 // splat is rounded to a multiple of 2^-52 (an integer), and the budget test
 // sum >= ceil(total / remaining) is on integers, so the cut cannot depend on the
 // order of any summation.
+#include <mutex>
+
 #include "common.h"
 #include "prune.h"
 
@@ -311,6 +313,43 @@ potr_status launch_prune_select(int64_t N, const float* dmse, const float* imp, 
     hipLaunchKernelGGL(k_prune_mark, dim3((unsigned)(mb < 4096 ? mb : 4096)), dim3(256), 0, s, N, dmse, imp, dmax,
                        a, S, remove, n_removed);
     return check_launch("k_prune_mark");
+}
+
+// ---------------------------------------------------------------- no-allocation form
+// The select's scratch (state and histograms) as a file-scope device array: one
+// copy per GPU, alive until the process ends. Host code never passes the array's
+// name to a kernel (in host code it is only a stand-in for the symbol): its device
+// address is looked up once per device with hipGetSymbolAddress and kept.
+constexpr size_t kNoAllocScratchBytes = 4096;
+static __device__ __align__(256) char scratch[kNoAllocScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+potr_status launch_prune_select_noalloc(int64_t N, const float* dmse, const float* imp, double dmax,
+                                        int32_t remaining, double a, uint8_t* remove, int64_t* n_removed,
+                                        hipStream_t s) {
+    static_assert(sizeof(PruneState) + 256 * 8 + 256 * 4 <= kNoAllocScratchBytes, "select scratch fits");
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return fail(POTR_EHIP, "hipGetDevice: %s", hipGetErrorString(e));
+    if (dev < 0 || dev >= kMaxDevices) return fail(POTR_EUNSUPPORTED, "device %d beyond %d", dev, kMaxDevices);
+    void* ptr = nullptr;
+    {
+        std::lock_guard<std::mutex> lock(g_scratch_mu);
+        if (!g_scratch_ptr[dev]) {
+            e = hipGetSymbolAddress(&g_scratch_ptr[dev], HIP_SYMBOL(scratch));
+            if (e != hipSuccess) {
+                g_scratch_ptr[dev] = nullptr;
+                return fail(POTR_EHIP, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+            }
+        }
+        ptr = g_scratch_ptr[dev];
+    }
+    return launch_prune_select(N, dmse, imp, dmax, remaining, a, ptr, remove, n_removed, s);
 }
 
 size_t prune_compact_scratch_bytes(int64_t N) {
