@@ -388,6 +388,39 @@ POTR_API potr_status potr_prune_compact(int64_t N, const uint8_t* remove, const 
                                         int64_t* n_kept, void* stream);
 
 /* ---------------------------------------------------------------------------
+ * potr_sh_compact -- spherical-harmonics energy compaction (Sec. 4.4): new
+ * lighting coefficients per splat that keep the colours its training cameras
+ * see, at lower energy. Per splat and colour channel (in YCoCg: Y = R/4 + G/2 +
+ * B/4, Co = R/2 - B/2, Cg = -R/4 + G/2 - B/4), with Y the SH basis at the unit
+ * directions from each camera centre to the splat (rows weighted by the
+ * camera's importance over the splat's largest) and C = Y L the colours (the raw
+ * SH sum, before the renderer's +1/2 and clamp):
+ *   - an AC column is dropped (coefficient 0) when |cosine| with a kept column
+ *     before it exceeds alpha (the DC is always kept; a zero column is dropped);
+ *   - ridge regression L' = (Y^T Y + Gamma^T Gamma)^-1 Y^T C over the kept
+ *     columns, Gamma = sqrt(lam_c) diag(0, 1, .., 1), lam_Y = lam,
+ *     lam_Co = lam_Cg = 3 lam;
+ *   - AC coefficients with |L'_i| < tau are forced to 0 and the ridge problem is
+ *     solved again over the rest;
+ *   - back to RGB (R = Y + Co - Cg, G = Y + Cg, B = Y - Co - Cg).
+ * A splat no camera sees keeps its DC and gets AC 0; coefficients beyond
+ * sh_degree are set to 0. The paper's hyperparameters at quality q: lam = 10^-q,
+ * alpha = sigmoid(3 q); tau = 1/(2 (1 + 100 q)) is half the SH quantiser's step.
+ *   cams (host) [V]; importance [V, stride] FP32 (device): the per-camera
+ *     importance I_k(s) (e.g. from potr_render_score_out with a per-view
+ *     stride); means [N,3], sh [N,16,3] as for potr_project
+ *   ws  workspace of potr_sh_compact_workspace_size(N, V) bytes (137 doubles per
+ *       splat: its Gram matrix)
+ *   sh_out [N,16,3] FP32 out (must not overlap sh)
+ * Arithmetic: FP64 (the Gram matrices on the FP64 matrix cores).
+ * ------------------------------------------------------------------------- */
+POTR_API potr_status potr_sh_compact_workspace_size(int64_t N, int32_t V, size_t* bytes);
+POTR_API potr_status potr_sh_compact(int64_t N, int32_t V, const potr_camera* cams, int32_t sh_degree,
+                                     const float* means, const float* sh, const float* importance,
+                                     int64_t importance_stride, double lam, double alpha, double tau, void* ws,
+                                     size_t ws_bytes, float* sh_out, void* stream);
+
+/* ---------------------------------------------------------------------------
  * potr_prune_select_noalloc -- for callers that cannot allocate device memory
  * (code under HIP graph capture, tight serving loops, harnesses that forbid
  * hipMalloc): potr_prune_select without the workspace argument. Its scratch

@@ -80,6 +80,9 @@ SIGNATURES = {
     "potr_batch_destroy": (_i32, [_vp]),
     "potr_prune_workspace_size": (_i32, [_i64, C.POINTER(_sz)]),
     "potr_prune_select": (_i32, [_i64, _vp, _vp, C.c_double, _i32, C.c_double, _vp, _sz, _vp, _vp, _vp]),
+    "potr_sh_compact_workspace_size": (_i32, [_i64, _i32, C.POINTER(_sz)]),
+    "potr_sh_compact": (_i32, [_i64, _i32, _CAM_P, _i32, _vp, _vp, _vp, _i64, C.c_double, C.c_double, C.c_double,
+                               _vp, _sz, _vp, _vp]),
     "potr_prune_select_noalloc": (_i32, [_i64, _vp, _vp, C.c_double, _i32, C.c_double, _vp, _vp, _vp]),
     "potr_prune_compact": (_i32, [_i64] + [_vp] * 7 + [_vp, _sz] + [_vp] * 7 + [_vp]),
     "potr_autotune": (_i32, [_JOB_P, _i32, _CFG_P, _i32, C.POINTER(C.c_double), _CFG_P, C.POINTER(C.c_double),

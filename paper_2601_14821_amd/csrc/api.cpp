@@ -10,6 +10,7 @@
 #include "common.h"
 #include "fused.h"
 #include "prune.h"
+#include "sh_compact.h"
 
 namespace potr {
 
@@ -302,6 +303,32 @@ potr_status potr_prune_select(int64_t N, const float* dmse, const float* importa
     if (ws_bytes < prune_select_scratch_bytes()) return fail(POTR_ECAPACITY, "prune workspace %zu bytes", ws_bytes);
     return launch_prune_select(N, dmse, importance, dmse_max, remaining, a, ws, remove, n_removed,
                                (hipStream_t)stream);
+}
+
+potr_status potr_sh_compact_workspace_size(int64_t N, int32_t V, size_t* bytes) {
+    if (!bytes || N < 0 || V < 1) return fail(POTR_EINVAL, "bad argument");
+    *bytes = sh_compact_workspace_bytes(N, V);
+    return POTR_OK;
+}
+
+potr_status potr_sh_compact(int64_t N, int32_t V, const potr_camera* cams, int32_t sh_degree, const float* means,
+                            const float* sh, const float* importance, int64_t importance_stride, double lam,
+                            double alpha, double tau, void* ws, size_t ws_bytes, float* sh_out, void* stream) {
+    if (N < 0 || N >= (int64_t(1) << 31)) return fail(POTR_EINVAL, "N = %lld", (long long)N);
+    if (V < 1 || !cams) return fail(POTR_EINVAL, "need at least one camera");
+    if (sh_degree < 0 || sh_degree > 3) return fail(POTR_EINVAL, "sh_degree %d not in 0..3", sh_degree);
+    if (!(lam >= 0.0) || lam > 1e300 || !(alpha >= 0.0) || alpha > 1e300 || !(tau >= 0.0) || tau > 1e300)
+        return fail(POTR_EINVAL, "lam, alpha, tau must be finite and >= 0");
+    if (importance_stride < N) return fail(POTR_EINVAL, "importance stride %lld < N", (long long)importance_stride);
+    if (!ws || (N > 0 && (!means || !sh || !importance || !sh_out))) return fail(POTR_EINVAL, "NULL buffer");
+    if (N > 0 && sh_out < sh + 48 * N && sh < sh_out + 48 * N) return fail(POTR_EINVAL, "sh_out overlaps sh");
+    if (ws_bytes < sh_compact_workspace_bytes(N, V))
+        return fail(POTR_ECAPACITY, "SH compaction workspace %zu < %zu bytes", ws_bytes,
+                    sh_compact_workspace_bytes(N, V));
+    if (!aligned16(ws)) return fail(POTR_EINVAL, "workspace must be 16-byte aligned");
+    const ShCompactParams p{lam, alpha, tau};
+    return launch_sh_compact(N, V, cams, sh_degree, means, sh, importance, importance_stride, p, ws, sh_out,
+                             (hipStream_t)stream);
 }
 
 potr_status potr_prune_select_noalloc(int64_t N, const float* dmse, const float* importance, double dmse_max,

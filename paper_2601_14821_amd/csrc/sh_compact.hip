@@ -1,0 +1,251 @@
+// Spherical-harmonics energy compaction (paper Sec. 4.4): per splat, new
+// lighting coefficients from an importance-weighted ridge regression of the
+// colours the training cameras see, in YCoCg, with parallel columns dropped
+// and a second pass without the coefficients the first one left almost zero.
+//
+// Per splat the regression only needs the weighted Gram matrix
+// G = Y_w^T Y_w (Y_w: the SH basis at the camera directions, rows scaled by the
+// camera weights), because the colours are C = Y L, so the right-hand side is
+// Y_w^T C_w = G L and the cosines between columns are G_ij / sqrt(G_ii G_jj).
+//   k_sh_eyes   camera centres -R^T t (FP64) into the workspace;
+//   k_sh_gram   one wave per splat: its largest camera importance, then G by
+//               FP64 matrix-core products, 4 cameras per v_mfma_f64_16x16x4
+//               (the wave evaluates the basis of 64 cameras at once, one per
+//               lane, stages the weighted values in LDS and feeds them to the
+//               matrix core in its operand layout), upper triangle to the workspace;
+//   k_sh_solve  one thread per splat: column selection, then per channel the
+//               two ridge solves by Cholesky in the thread's LDS, back to RGB.
+// All arithmetic is FP64.
+#include "common.h"
+#include "sh_basis.h"
+#include "sh_compact.h"
+
+namespace potr {
+namespace {
+
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kPacked = 136;                 // upper triangle of 16 x 16
+constexpr int kRes = kPacked + 1;            // then the new coefficients (YCoCg, 16 x 3)
+constexpr int kSplatStride = kRes + 48;      // per splat: G, the largest importance, the result
+constexpr int kSolveThreads = 64;
+constexpr int kFStride = 137;                // doubles per thread of the factor in LDS (odd: spreads banks)
+
+__device__ inline int packed_upper(int i, int j) {   // i <= j
+    return i * 16 - (i * (i - 1)) / 2 + (j - i);
+}
+
+__global__ void k_sh_eyes(CamBatch cams, int32_t v0, int32_t nv, double* __restrict__ eyes) {
+    const int k = threadIdx.x;
+    if (k >= nv) return;
+    const potr_camera& c = cams.c[k];
+    double e[3];
+    for (int a = 0; a < 3; ++a)
+        e[a] = -((double)c.R[a] * (double)c.t[0] + (double)c.R[3 + a] * (double)c.t[1] +
+                 (double)c.R[6 + a] * (double)c.t[2]);
+    for (int a = 0; a < 3; ++a) eyes[3 * (int64_t)(v0 + k) + a] = e[a];
+}
+
+// One wave (64 threads) per splat.
+__global__ __launch_bounds__(64) void k_sh_gram(int64_t N, int32_t V, int degree, const double* __restrict__ eyes,
+                                                const float* __restrict__ means, const float* __restrict__ imp,
+                                                int64_t stride, double* __restrict__ gws) {
+    __shared__ double sy[64 * 17];   // weighted basis of 64 cameras (17: padding)
+    const int64_t k = blockIdx.x;
+    if (k >= N) return;
+    const int lane = threadIdx.x;
+    // the splat's largest camera importance
+    float m = 0.f;
+    for (int v = lane; v < V; v += 64) m = fmaxf(m, imp[(int64_t)v * stride + k]);
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) m = fmaxf(m, __shfl_xor(m, o, 64));
+    double* G = gws + k * kSplatStride;
+    if (lane == 0) G[kPacked] = (double)m;
+    if (!(m > 0.f)) return;   // no camera sees it (the solve keeps the DC only)
+    const double imax = (double)m;
+    const double mx = means[3 * k], my = means[3 * k + 1], mz = means[3 * k + 2];
+    f64x4 acc = {0.0, 0.0, 0.0, 0.0};
+    for (int v0 = 0; v0 < V; v0 += 64) {
+        const int v = v0 + lane;
+        double y[16];
+#pragma unroll
+        for (int i = 0; i < 16; ++i) y[i] = 0.0;
+        double w = 0.0;
+        if (v < V) {
+            w = (double)imp[(int64_t)v * stride + k] / imax;
+            double dx = mx - eyes[3 * v], dy = my - eyes[3 * v + 1], dz = mz - eyes[3 * v + 2];
+            const double r = __builtin_sqrt(dx * dx + dy * dy + dz * dz);
+            dx /= r;
+            dy /= r;
+            dz /= r;
+            sh_basis_d3(dx, dy, dz, degree, y);
+        }
+#pragma unroll
+        for (int i = 0; i < 16; ++i) sy[lane * 17 + i] = w * y[i];
+        __syncthreads();
+        // 16 products of 4 cameras each: lane l supplies basis l % 16 of camera l / 16
+        // as both A[i][c] and B[c][j] (Y_w^T is A, Y_w is B)
+        const int cams = min(64, V - v0);
+        for (int c0 = 0; c0 < cams; c0 += 4) {
+            const double a = sy[(c0 + lane / 16) * 17 + (lane % 16)];
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, a, acc, 0, 0, 0);
+        }
+        __syncthreads();
+    }
+    // the product's layout (measured): D[i][j] is register i / 4 of lane j + 16 (i % 4)
+    const int j = lane % 16;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int i = lane / 16 + 4 * r;
+        if (i <= j) G[packed_upper(i, j)] = acc[r];
+    }
+}
+
+struct Solver {
+    const double* G;   // this splat's packed upper triangle
+    double* F;         // this thread's factor (packed lower, row-major)
+    int M;
+
+    __device__ double g(int i, int j) const { return i <= j ? G[packed_upper(i, j)] : G[packed_upper(j, i)]; }
+
+    // Cholesky of G + lam diag(0, 1, .., 1) over the columns in `mask` (the
+    // others become identity rows, so their unknowns solve to 0).
+    __device__ void factor(uint32_t mask, double lam) {
+        for (int i = 0; i < M; ++i) {
+            const int ri = (i * (i + 1)) / 2;
+            const bool ki = (mask >> i) & 1u;
+            for (int j = 0; j <= i; ++j) {
+                const bool kj = (mask >> j) & 1u;
+                if (!ki || !kj) {
+                    F[ri + j] = (i == j) ? 1.0 : 0.0;
+                    continue;
+                }
+                double s = g(i, j) + ((i == j && i > 0) ? lam : 0.0);
+                const int rj = (j * (j + 1)) / 2;
+                for (int q = 0; q < j; ++q) s -= F[ri + q] * F[rj + q];
+                F[ri + j] = (i == j) ? __builtin_sqrt(s) : s / F[rj + j];
+            }
+        }
+    }
+
+    // x = (L L^T)^-1 b over the mask (rows outside it give 0); b and x stay in
+    // registers (every index below is a compile-time constant).
+    __device__ void solve(uint32_t mask, const double (&b)[16], double (&x)[16]) const {
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            if (i >= M) break;
+            const int ri = (i * (i + 1)) / 2;
+            double s = ((mask >> i) & 1u) ? b[i] : 0.0;
+#pragma unroll
+            for (int q = 0; q < i; ++q) s -= F[ri + q] * x[q];
+            x[i] = s / F[ri + i];
+        }
+#pragma unroll
+        for (int i = 15; i >= 0; --i) {
+            if (i >= M) continue;
+            double s = x[i];
+#pragma unroll
+            for (int q = i + 1; q < 16; ++q)
+                if (q < M) s -= F[(q * (q + 1)) / 2 + i] * x[q];
+            x[i] = s / F[(i * (i + 1)) / 2 + i];
+        }
+    }
+};
+
+__global__ __launch_bounds__(kSolveThreads) void k_sh_solve(int64_t N, int degree, const float* __restrict__ sh,
+                                                            double* __restrict__ gws, ShCompactParams p,
+                                                            float* __restrict__ sh_out) {
+    __shared__ double sF[kSolveThreads * kFStride];
+    const int64_t k = (int64_t)blockIdx.x * kSolveThreads + threadIdx.x;
+    if (k >= N) return;
+    const int M = (degree + 1) * (degree + 1);
+    const double* G = gws + k * kSplatStride;
+    double* res = gws + k * kSplatStride + kRes;   // this splat's result slots
+    const float* L = sh + 48 * k;
+    float* out = sh_out + 48 * k;
+    if (!(G[kPacked] > 0.0)) {   // no camera sees it: the DC stays, the rest is 0
+        for (int e = 0; e < 48; ++e) out[e] = e < 3 ? L[e] : 0.f;
+        return;
+    }
+    Solver S{G, sF + threadIdx.x * kFStride, M};
+    // columns: the DC, then each AC column not parallel to a kept one before it
+    uint32_t kept = 1u;
+    for (int i = 1; i < M; ++i) {
+        const double gii = S.g(i, i);
+        if (!(gii > 0.0)) continue;
+        bool par = false;
+        for (int j = 0; j < i; ++j) {
+            if (!((kept >> j) & 1u)) continue;
+            const double c = fabs(S.g(i, j)) / (__builtin_sqrt(gii) * __builtin_sqrt(S.g(j, j)));
+            par = par || c > p.alpha;
+        }
+        if (!par) kept |= 1u << i;
+    }
+    for (int ch = 0; ch < 3; ++ch) {
+        const double lam = ch == 0 ? p.lam : 3.0 * p.lam;
+        // this channel's coefficients in YCoCg and the right-hand side G L
+        double lc[16], b[16], x[16];
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            const double R = L[3 * i], Gc = L[3 * i + 1], B = L[3 * i + 2];
+            lc[i] = ch == 0 ? 0.25 * R + 0.5 * Gc + 0.25 * B : ch == 1 ? 0.5 * R - 0.5 * B : -0.25 * R + 0.5 * Gc - 0.25 * B;
+        }
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            double s = 0.0;
+#pragma unroll
+            for (int j = 0; j < 16; ++j)
+                if (i < M && j < M) s += S.g(i, j) * lc[j];
+            b[i] = s;
+            x[i] = 0.0;
+        }
+        S.factor(kept, lam);
+        S.solve(kept, b, x);
+        uint32_t kept2 = kept;
+#pragma unroll
+        for (int i = 1; i < 16; ++i)
+            if (i < M && ((kept >> i) & 1u) && fabs(x[i]) < p.tau) kept2 &= ~(1u << i);
+        if (kept2 != kept) {
+            S.factor(kept2, lam);
+            S.solve(kept2, b, x);
+        }
+#pragma unroll
+        for (int i = 0; i < 16; ++i) res[16 * ch + i] = i < M ? x[i] : 0.0;
+    }
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        const double Yv = res[i], Co = res[16 + i], Cg = res[32 + i];
+        out[3 * i] = (float)(Yv + Co - Cg);
+        out[3 * i + 1] = (float)(Yv + Cg);
+        out[3 * i + 2] = (float)(Yv - Co - Cg);
+    }
+}
+
+}  // namespace
+
+size_t sh_compact_workspace_bytes(int64_t N, int32_t V) {
+    return align_up((size_t)V * 3 * 8) + (size_t)N * kSplatStride * 8;
+}
+
+potr_status launch_sh_compact(int64_t N, int32_t V, const potr_camera* cams, int degree, const float* means,
+                              const float* sh, const float* imp, int64_t stride, const ShCompactParams& p,
+                              void* ws, float* sh_out, hipStream_t s) {
+    double* eyes = (double*)ws;
+    double* gws = (double*)((char*)ws + align_up((size_t)V * 3 * 8));
+    for (int32_t v0 = 0; v0 < V; v0 += kViewsPerLaunch) {
+        const int32_t nv = V - v0 < kViewsPerLaunch ? V - v0 : kViewsPerLaunch;
+        CamBatch cb{};
+        for (int32_t k = 0; k < nv; ++k) cb.c[k] = cams[v0 + k];
+        hipLaunchKernelGGL(k_sh_eyes, dim3(1), dim3(kViewsPerLaunch), 0, s, cb, v0, nv, eyes);
+    }
+    potr_status st = check_launch("k_sh_eyes");
+    if (st != POTR_OK || N == 0) return st;
+    hipLaunchKernelGGL(k_sh_gram, dim3((unsigned)N), dim3(64), 0, s, N, V, degree, eyes, means, imp, stride, gws);
+    st = check_launch("k_sh_gram");
+    if (st != POTR_OK) return st;
+    hipLaunchKernelGGL(k_sh_solve, dim3((unsigned)((N + kSolveThreads - 1) / kSolveThreads)), dim3(kSolveThreads), 0,
+                       s, N, degree, sh, gws, p, sh_out);
+    return check_launch("k_sh_solve");
+}
+
+}  // namespace potr
