@@ -134,7 +134,7 @@ POTR_API potr_status potr_project(int64_t N, int32_t V, const potr_camera* cams,
  *          later stages treat as "no pairs").
  * Cost: the workspace holds 32 bytes per (view, splat) (depth sort keys and
  * values, rects by id and in depth order), 8 bytes per (view, group of 4096
- * ranks, tile) and 4 bytes per (view, group, tile row).
+ * ranks, tile) and 8 bytes per (view, group, tile row).
  * ------------------------------------------------------------------------- */
 POTR_API potr_status potr_bin_workspace_size(int64_t N, int32_t V, const potr_camera* cams, const potr_config* cfg,
                                     size_t* bytes);
@@ -147,20 +147,22 @@ POTR_API potr_status potr_bin(int64_t N, int32_t V, const potr_camera* cams, con
  * all tiles of all views back to back in (view, tile) order: the order a sort
  * of (view, tile, depth, id) keys gives, obtained by placing every pair
  * directly from the counts potr_bin left in its workspace (no per-pair sort):
- * per (group of 4096 depth ranks, tile row), the group's pairs in the row are
- * laid out on chip and stored at their tiles' offsets.
+ * first every group's list of the splats covering each tile row, in rank
+ * order (into sort_ws), then per (group of 4096 ranks, tile row) the list's
+ * pairs at their tiles' offsets.
  * N, V, cams, cfg, proj, order and ws are those of the potr_bin call before
- * (ws is read, not changed).
+ * (ws is read, not changed, so potr_sort may be called again, e.g. with a
+ * larger capacity).
  *   n_pairs  (device) from potr_bin
  *   capacity (host) number of slots in sorted_ids; with more pairs than that
  *            nothing is placed and every range is empty (grow and call again)
- *   sort_ws  workspace of potr_sort_workspace_size(capacity) bytes (a 256-byte
- *            placeholder: nothing per pair is staged in global memory)
+ *   sort_ws  workspace of potr_sort_workspace_size(capacity) bytes: the row
+ *            lists, 8 bytes per (splat, covered tile row), at most one per pair
  *   sorted_ids [capacity] uint32 out: splat id (0..N-1) of every pair
  *   tile_ranges [V*tiles*2] int32 out: half-open [start, end) into sorted_ids;
  *            [0, 0) for a tile without pairs
  * Limits: every image the camera checks accept (at most 16384 px a side, so
- * up to 2048 tile columns of 8 px) fits the per-workgroup LDS (61 KB at 2048
+ * up to 2048 tile columns of 8 px) fits the per-workgroup LDS (104 KB at 2048
  * columns).
  * ------------------------------------------------------------------------- */
 POTR_API potr_status potr_sort_workspace_size(int64_t capacity, size_t* bytes);

@@ -31,8 +31,6 @@
 namespace potr {
 namespace {
 
-constexpr int kThreads = 256;
-constexpr int kWaves = kThreads / 64;
 constexpr int kSwThreads = 1024;              // depth radix pass: 16 waves x 4 keys per lane
 constexpr int kSwItems = 4;
 constexpr int kSwWaves = kSwThreads / 64;
@@ -392,10 +390,6 @@ struct Bins {
 };
 constexpr int kGroupRanks = 4096;             // depth ranks per group
 constexpr int kMaxSegs = 32;                  // at most this many segments per column scan
-constexpr int kColItems = 8;                  // placement: pairs per thread (2048 per block pass)
-// A pair in LDS is one word: tile x << kRankBits | rank of the splat within its group.
-constexpr int kRankBits = 12;
-static_assert(kGroupRanks == 1 << kRankBits, "a group's ranks fill the rank field");
 
 // The group counts' column scan goes by segments of seg_g groups: the count
 // kernel adds each segment's sums (segt[v][seg][t]), the tile kernel turns them
@@ -447,7 +441,9 @@ __global__ __launch_bounds__(256) void k_tile_bases(uint32_t* __restrict__ segt,
                                                     uint32_t* __restrict__ trel, uint32_t* __restrict__ rtot,
                                                     uint32_t* __restrict__ rows_done,
                                                     const uint32_t* __restrict__ fault,
-                                                    int64_t* __restrict__ rbase, int64_t* __restrict__ n_pairs) {
+                                                    int64_t* __restrict__ rbase, int64_t* __restrict__ n_pairs,
+                                                    uint32_t* __restrict__ rcov, uint32_t* __restrict__ rltot,
+                                                    int64_t* __restrict__ rlbase) {
     __shared__ uint32_t wsum[4];
     __shared__ int64_t wsum64[4];
     __shared__ bool s_last;
@@ -471,8 +467,29 @@ __global__ __launch_bounds__(256) void k_tile_bases(uint32_t* __restrict__ segt,
         run += all;
         __syncthreads();
     }
+    // the row's list of covering splats: every group's first entry in it (an
+    // exclusive scan of the cover counts over the groups, in place) and its length
+    uint32_t lrun = 0;
+    uint32_t* rc = rcov + ((int64_t)v * B.tiles_y + y) * B.G;
+    for (int g0 = 0; g0 < B.G; g0 += 256) {
+        const int g = g0 + threadIdx.x;
+        const uint32_t c = g < B.G ? rc[g] : 0u;
+        const uint32_t inc = wave_incl_scan(c);
+        if (lane == 63) wsum[w] = inc;
+        __syncthreads();
+        uint32_t pre = lrun, all = 0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            if (k < w) pre += wsum[k];
+            all += wsum[k];
+        }
+        if (g < B.G) rc[g] = pre + inc - c;
+        lrun += all;
+        __syncthreads();
+    }
     if (threadIdx.x == 0) {
         rtot[(int64_t)v * B.tiles_y + y] = run;
+        rltot[(int64_t)v * B.tiles_y + y] = lrun;
         __threadfence();
         s_last = atomicAdd(rows_done, 1u) == gridDim.x * gridDim.y - 1;
     }
@@ -503,6 +520,29 @@ __global__ __launch_bounds__(256) void k_tile_bases(uint32_t* __restrict__ segt,
         __syncthreads();
     }
     if (threadIdx.x == 0) *n_pairs = *fault ? (int64_t)-1 : carry;
+    // the same over the row lists' lengths: where each row's list starts
+    int64_t lcarry = 0;
+    for (int64_t b0 = 0; b0 < nr; b0 += 256) {
+        const int64_t i = b0 + threadIdx.x;
+        const int64_t tot = i < nr ? (int64_t)rltot[i] : 0;
+        int64_t inc = tot;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const int64_t u = __shfl_up(inc, d, 64);
+            if (lane >= d) inc += u;
+        }
+        if (lane == 63) wsum64[w] = inc;
+        __syncthreads();
+        int64_t pre = lcarry, all = 0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            if (k < w) pre += wsum64[k];
+            all += wsum64[k];
+        }
+        if (i < nr) rlbase[i] = pre + inc - tot;
+        lcarry += all;
+        __syncthreads();
+    }
 }
 
 // The counts of one group (a block per (group, view)), band by band of tile
@@ -520,8 +560,9 @@ constexpr size_t kGcLds = 48 * 1024;              // LDS budget of the differenc
 __global__ __launch_bounds__(kGcThreads) void k_count(const uint32_t* __restrict__ order,
                                                      const uint2* __restrict__ crect, Bins B, int band,
                                                      uint2* __restrict__ srect, uint32_t* __restrict__ gsum,
-                                                     uint32_t* __restrict__ tc, uint32_t* __restrict__ segt) {
-    extern __shared__ uint32_t d[];   // [band + 1][tiles_x + 1]
+                                                     uint32_t* __restrict__ tc, uint32_t* __restrict__ segt,
+                                                     uint32_t* __restrict__ rcov) {
+    extern __shared__ uint32_t d[];   // [band + 1][tiles_x + 1], then [tiles_y + 1] for the row covers
     const int g = blockIdx.x, v = blockIdx.y;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     constexpr int NW = kGcThreads / 64;
@@ -537,6 +578,20 @@ __global__ __launch_bounds__(kGcThreads) void k_count(const uint32_t* __restrict
             const int64_t r = (int64_t)v * B.N + r0 + idx;
             rr[k] = crect[(int64_t)v * B.N + order[r]];
             srect[r] = rr[k];
+        }
+    }
+    // how many of the group's splats cover each tile row: +1 at y0, -1 at y1,
+    // summed down the rows at the end
+    uint32_t* rd = d + (size_t)(band + 1) * W1;
+    for (int i = threadIdx.x; i <= B.tiles_y; i += kGcThreads) rd[i] = 0u;
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kGcItems; ++k) {
+        const int x0 = (int)(rr[k].x & 0xffffu), x1 = (int)(rr[k].x >> 16);
+        const int y0 = (int)(rr[k].y & 0xffffu), y1 = (int)(rr[k].y >> 16);
+        if (x0 < x1 && y0 < y1) {
+            atomicAdd(&rd[y0], 1u);
+            atomicSub(&rd[y1], 1u);
         }
     }
     uint32_t* out = tc + ((int64_t)v * B.G + g) * B.T;
@@ -586,50 +641,134 @@ __global__ __launch_bounds__(kGcThreads) void k_count(const uint32_t* __restrict
         }
         __syncthreads();
     }
+    // the row covers: a running sum down the rows (one wave)
+    if (w == 0) {
+        uint32_t carry = 0;
+        for (int y0 = 0; y0 < B.tiles_y; y0 += 64) {
+            const int y = y0 + lane;
+            const uint32_t inc = wave_incl_scan(y < B.tiles_y ? rd[y] : 0u);
+            if (y < B.tiles_y) rcov[((int64_t)v * B.tiles_y + y) * B.G + g] = carry + inc;
+            carry += (uint32_t)__builtin_amdgcn_readlane((int)inc, 63);
+        }
+    }
 }
 
-// Pair placement, a block per (view, group, row). The group's splats that cover
-// the row, in rank order, each make a run of pairs over the tiles x0..x1-1 of
-// their rect; laid back to back these runs are the group's pairs of the row in
-// (rank, x) order. Per round of 2048 ranks the covering ranks' runs go to LDS
-// as a compact list (a scan of the run widths gives their starts, ballots of
-// the cover flags their places in the list);
-// per pass of up to 2048 pairs every thread fills eight consecutive slots of
-// the pass buffer (one binary search for the run holding its first pair, then a
-// walk over the runs; two 16-byte LDS stores) with words (tile x, rank within
-// the group), the block ranks them
-// stably by tile x (ballots over the x bits, per-wave counters), maps each rank
-// to its splat id, sorts in LDS and stores each tile's run at the tile's cursor
-// (the group's first position in the tile, advanced per pass).
+// Row lists, a block per (group, view): for every tile row, the group's
+// splats that cover it, in depth-rank order, each as (splat id, its rect's
+// columns x0 | x1 << 16), written at the row list's place for the group (the
+// bin's cover counts, scanned). Within a band of 64 rows, every (row, rank
+// slot, wave) gets the ballot of its covering lanes; a scan of their counts
+// per row gives each wave's first place, a popcount below the lane its place.
+constexpr int kRwThreads = 1024;
+constexpr int kRwItems = kGroupRanks / kRwThreads;   // ranks per thread (rank = slot * 1024 + thread)
+constexpr int kRwSlots = kRwItems * (kRwThreads / 64);   // (slot, wave) pairs, in rank order
+constexpr int kRwBand = 64;
+static_assert(kRwSlots == 64, "one lane per (slot, wave) in the per-row scan");
+
+__device__ inline uint64_t lanes_below() {
+    const int lane = (int)(threadIdx.x & 63u);
+    return lane == 0 ? 0ull : (~0ull >> (64 - lane));
+}
+
+__global__ __launch_bounds__(kRwThreads) void k_rows(const uint2* __restrict__ srect, const uint32_t* __restrict__ order,
+                                                    const uint32_t* __restrict__ rcov,
+                                                    const int64_t* __restrict__ rlbase, Bins B,
+                                                    const int64_t* __restrict__ n_pairs, int64_t capacity,
+                                                    uint2* __restrict__ rows) {
+    __shared__ uint64_t mask[kRwBand][kRwSlots];
+    __shared__ uint32_t wb[kRwBand][kRwSlots];
+    __shared__ int64_t rbeg[kRwBand];
+    const int g = blockIdx.x, v = blockIdx.y;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int64_t n = *n_pairs;
+    if (!(n >= 0 && n <= capacity)) return;   // nothing is placed: the lists are not needed
+    const int64_t r0 = (int64_t)g * kGroupRanks;
+    const int ns = (int)min((int64_t)kGroupRanks, B.N - r0);
+    uint2 rr[kRwItems];
+    uint32_t id[kRwItems];
+#pragma unroll
+    for (int k = 0; k < kRwItems; ++k) {
+        const int idx = k * kRwThreads + (int)threadIdx.x;
+        rr[k] = make_uint2(0u, 0u);
+        id[k] = 0u;
+        if (idx < ns) {
+            const int64_t r = (int64_t)v * B.N + r0 + idx;
+            rr[k] = srect[r];
+            id[k] = order[r];
+        }
+    }
+    const uint64_t below = lanes_below();
+    for (int yb0 = 0; yb0 < B.tiles_y; yb0 += kRwBand) {
+        const int nb = min(kRwBand, B.tiles_y - yb0);
+        for (int yy = 0; yy < nb; ++yy) {
+            const uint32_t y = (uint32_t)(yb0 + yy);
+#pragma unroll
+            for (int k = 0; k < kRwItems; ++k) {
+                const uint32_t x0 = rr[k].x & 0xffffu, x1 = rr[k].x >> 16;
+                const uint32_t y0 = rr[k].y & 0xffffu, y1 = rr[k].y >> 16;
+                const uint64_t m = __ballot(x0 < x1 && y0 <= y && y < y1);
+                if (lane == 0) mask[yy][k * 16 + w] = m;
+            }
+        }
+        if ((int)threadIdx.x < nb) {
+            const int64_t vy = (int64_t)v * B.tiles_y + yb0 + threadIdx.x;
+            rbeg[threadIdx.x] = rlbase[vy] + rcov[vy * B.G + g];
+        }
+        __syncthreads();
+        for (int yy = w; yy < nb; yy += kRwThreads / 64) {
+            const uint32_t c = (uint32_t)__popcll(mask[yy][lane]);
+            wb[yy][lane] = wave_incl_scan(c) - c;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < kRwItems; ++k) {
+            const int x0 = (int)(rr[k].x & 0xffffu), x1 = (int)(rr[k].x >> 16);
+            const int y0 = max((int)(rr[k].y & 0xffffu), yb0), y1 = min((int)(rr[k].y >> 16), yb0 + nb);
+            if (x0 >= x1) continue;
+            for (int y = y0; y < y1; ++y) {
+                const int yy = y - yb0, sl = k * 16 + w;
+                const int64_t pos = rbeg[yy] + wb[yy][sl] + __popcll(mask[yy][sl] & below);
+                rows[pos] = make_uint2(id[k], rr[k].x);
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// Pair placement, a block per (view, group, row): the group's row list (its
+// splats covering the row, in rank order) goes out as pairs, each splat to
+// every tile x0..x1-1 of its run, at the tile's cursor (the group's first
+// position in the tile, from the bin's counts). Per chunk of 256 list entries
+// every wave marks, per tile column, which of its lanes cover the column (LDS
+// atomic ORs of the lane's bit: 64-bit masks, one per (wave, column)); a
+// column pass turns the masks into each wave's first place in the column
+// and advances the cursors; then every lane puts its splat id at its place in
+// each of its columns (the wave's first place plus the lanes below it in the
+// mask). Lanes are in rank order within a wave, waves within the chunk and
+// chunks within the list, so every tile's run of the group stays in rank order.
 // Blocks of group 0 also write the row's tile ranges, [0, 0) when empty and all
 // empty when the pairs exceed the capacity.
-constexpr int kPlRound = 2048;                       // ranks per round
-constexpr int kPlSlots = kPlRound / kThreads;        // ranks per lane per round
-constexpr int kPlPer = kThreads * kColItems / kThreads;   // pairs each thread expands per pass
-static_assert(kPlPer == 8, "the expansion stores a thread's slots as two 16-byte words");
+constexpr int kPcThreads = 256;
+constexpr int kPcWaves = kPcThreads / 64;
 
-template <int XBITS>
-__global__ __launch_bounds__(256) void k_place(const uint2* __restrict__ srect, const uint32_t* __restrict__ gsum,
-                                               const uint32_t* __restrict__ off, const int64_t* __restrict__ rbase,
-                                               const uint32_t* __restrict__ trel, const uint32_t* __restrict__ rtot,
-                                               Bins B, const int64_t* __restrict__ n_pairs, int64_t capacity,
-                                               const uint32_t* __restrict__ order, uint32_t* __restrict__ ids,
-                                               int32_t* __restrict__ ranges) {
-    extern __shared__ __align__(16) uint32_t lds[];
+__global__ __launch_bounds__(kPcThreads) void k_place(const uint2* __restrict__ rows,
+                                                     const uint32_t* __restrict__ rcov,
+                                                     const uint32_t* __restrict__ rltot,
+                                                     const int64_t* __restrict__ rlbase,
+                                                     const uint32_t* __restrict__ off,
+                                                     const int64_t* __restrict__ rbase,
+                                                     const uint32_t* __restrict__ trel,
+                                                     const uint32_t* __restrict__ rtot, Bins B,
+                                                     const int64_t* __restrict__ n_pairs, int64_t capacity,
+                                                     uint32_t* __restrict__ ids, int32_t* __restrict__ ranges) {
+    extern __shared__ __align__(16) uint64_t lds64[];
     const int TX = B.tiles_x;
-    uint32_t* s_id = lds;                              // [2048]: a pass's pair words, then its ids (16-byte aligned)
-    uint32_t* cur = s_id + kThreads * kColItems;       // [TX]
-    uint32_t* boff = cur + TX;                         // [TX]
-    uint32_t* s_off = boff + TX;                       // [kPlRound]: start of each covering rank's run
-    uint16_t* wcnt = reinterpret_cast<uint16_t*>(s_off + kPlRound);   // [kWaves][TX] (a pass has <= 2048 pairs)
-    uint16_t* s_x = wcnt + kWaves * TX;                // [2048]
-    uint16_t* s_x0 = s_x + kThreads * kColItems;       // [kPlRound]: its first tile
-    uint16_t* s_rk = s_x0 + kPlRound;                  // [kPlRound]: its rank within the round
-    __shared__ uint32_t wsum[kWaves];
-    __shared__ uint32_t wcov[kWaves];
+    uint64_t* mask = lds64;                                         // [kPcWaves][TX]
+    uint32_t* cur = reinterpret_cast<uint32_t*>(mask + kPcWaves * TX);   // [TX]
+    uint32_t* wbase = cur + TX;                                     // [kPcWaves][TX]
     // workgroups go to the 8 XCDs round-robin by linear id: block b runs on XCD
     // b % 8, and XCD x takes the groups x, x + 8, ... with all their rows, so a
-    // group's rects, ids and offsets are read through one XCD's L2
+    // group's offsets are read through one XCD's L2
     const int xcd = (int)(blockIdx.x & 7u), m = (int)(blockIdx.x >> 3), v = blockIdx.y;
     const int j = m / B.tiles_y, y = m - j * B.tiles_y, g = xcd + 8 * j;
     if (g >= B.G) return;
@@ -639,7 +778,7 @@ __global__ __launch_bounds__(256) void k_place(const uint2* __restrict__ srect, 
     const int64_t vy = (int64_t)v * B.tiles_y + y;
     if (g == 0) {
         const int64_t rb = rbase[vy];
-        for (int x = threadIdx.x; x < TX; x += kThreads) {
+        for (int x = threadIdx.x; x < TX; x += kPcThreads) {
             const int64_t i = (int64_t)v * B.T + (int64_t)y * TX + x;
             const int64_t b = rb + trel[i], e = rb + (x + 1 < TX ? trel[i + 1] : rtot[vy]);
             const bool any = fits && e > b;
@@ -648,200 +787,36 @@ __global__ __launch_bounds__(256) void k_place(const uint2* __restrict__ srect, 
         }
     }
     if (!fits) return;
-    const uint32_t len = gsum[vy * B.G + g];   // the group's pairs in the row
-    if (len == 0) return;
+    const int64_t lb = rlbase[vy];
+    const int64_t beg = lb + rcov[vy * B.G + g];
+    const int64_t end = lb + (g + 1 < B.G ? rcov[vy * B.G + g + 1] : rltot[vy]);
+    if (end <= beg) return;
+    const int cnt = (int)(end - beg);
     const uint32_t* orow = off + ((int64_t)v * B.G + g) * B.T + (int64_t)y * TX;
-    const uint32_t* gorder = order + (int64_t)v * B.N + (int64_t)g * kGroupRanks;
-    const uint2* grect = srect + (int64_t)v * B.N + (int64_t)g * kGroupRanks;
-    for (int x = threadIdx.x; x < TX; x += kThreads) cur[x] = orow[x];
-    const int ns = (int)min((int64_t)kGroupRanks, B.N - (int64_t)g * kGroupRanks);
-    const int per = (TX + kThreads - 1) / kThreads;   // counters per thread in the block scan
-    uint32_t placed = 0, expanded = 0, fill = 0;
-    // one pass over the pair words s_id[0, cntb): rank by tile x, sort in LDS,
-    // store each tile's run at its cursor and advance the cursors
-    auto place_pass = [&](const uint32_t cntb) {
-        for (int t = threadIdx.x; t < kWaves * TX; t += kThreads) wcnt[t] = 0;
+    for (int x = threadIdx.x; x < TX; x += kPcThreads) cur[x] = orow[x];
+    const uint64_t below = lanes_below(), bit = 1ull << lane;
+    for (int c0 = 0; c0 < cnt; c0 += kPcThreads) {
+        __syncthreads();   // the cursors are set, and the last chunk is done with the masks
+        for (int i = threadIdx.x; i < kPcWaves * TX; i += kPcThreads) mask[i] = 0ull;
+        const bool valid = c0 + (int)threadIdx.x < cnt;
+        const uint2 e = valid ? rows[beg + c0 + threadIdx.x] : make_uint2(0u, 0u);
+        const int x0 = (int)(e.y & 0xffffu), x1 = (int)(e.y >> 16);
         __syncthreads();
-        uint32_t key[kColItems], val[kColItems], rnk[kColItems];
+        uint64_t* mw = mask + w * TX;
+        for (int x = x0; x < x1; ++x) atomicOr((unsigned long long*)&mw[x], (unsigned long long)bit);
+        __syncthreads();
+        for (int x = threadIdx.x; x < TX; x += kPcThreads) {
+            uint32_t c = cur[x];
 #pragma unroll
-        for (int k = 0; k < kColItems; ++k) {
-            const uint32_t e = (uint32_t)(w * 64 * kColItems + k * 64 + lane);
-            key[k] = s_id[min(e, cntb - 1)];
-        }
-        // all id gathers first, without branches, so that they stay in flight together
-#pragma unroll
-        for (int k = 0; k < kColItems; ++k) {
-            val[k] = gorder[key[k] & (kGroupRanks - 1)];   // the splat id
-            key[k] >>= kRankBits;
-        }
-        // slots of this wave that hold pairs of the pass (the rest are skipped)
-        const uint32_t wb0 = (uint32_t)(w * 64 * kColItems);
-        const int kn = cntb > wb0 ? (int)min((uint32_t)kColItems, (cntb - wb0 + 63) / 64) : 0;
-#pragma unroll
-        for (int k = 0; k < kColItems; ++k) {
-            if (k >= kn) {
-                rnk[k] = 0xffffffffu;
-                continue;
+            for (int ww = 0; ww < kPcWaves; ++ww) {
+                wbase[ww * TX + x] = c;
+                c += (uint32_t)__popcll(mask[ww * TX + x]);
             }
-            const uint32_t e = (uint32_t)(w * 64 * kColItems + k * 64 + lane);
-            const bool ok = e < cntb;
-            const uint32_t d = ok ? key[k] : 0u;
-            key[k] = d;
-            uint32_t below, c;
-            match_rank<XBITS>(d, ok, below, c);
-            uint32_t r = 0;
-            if (ok) r = wcnt[w * TX + d];
-            __builtin_amdgcn_wave_barrier();
-            if (ok && below == 0) wcnt[w * TX + d] = (uint16_t)(r + c);
-            __builtin_amdgcn_wave_barrier();
-            rnk[k] = ok ? r + below : 0xffffffffu;
+            cur[x] = c;
         }
         __syncthreads();
-        // per x: exclusive prefix over waves, block count; then the block scan of the counts
-        uint32_t local[8];
-        uint32_t mine = 0;
-        for (int j = 0; j < per; ++j) {
-            const int x = threadIdx.x * per + j;
-            uint32_t run = 0;
-            if (x < TX)
-                for (int ww = 0; ww < kWaves; ++ww) {
-                    const uint32_t c = wcnt[ww * TX + x];
-                    wcnt[ww * TX + x] = (uint16_t)run;
-                    run += c;
-                }
-            local[j] = run;
-            mine += run;
-        }
-        uint32_t pre = block_excl_scan<kThreads>(mine, wsum);
-        for (int j = 0; j < per; ++j) {
-            const int x = threadIdx.x * per + j;
-            if (x < TX) boff[x] = pre;
-            pre += local[j];
-        }
-        __syncthreads();
-#pragma unroll
-        for (int k = 0; k < kColItems; ++k) {
-            if (rnk[k] == 0xffffffffu) continue;
-            const uint32_t p = boff[key[k]] + wcnt[w * TX + key[k]] + rnk[k];
-            s_id[p] = val[k];
-            s_x[p] = (uint16_t)key[k];
-        }
-        __syncthreads();
-        for (uint32_t i = threadIdx.x; i < cntb; i += kThreads) {
-            const uint32_t x = s_x[i];
-            ids[cur[x] + (i - boff[x])] = s_id[i];
-        }
-        __syncthreads();
-        // advance the cursors past this pass's runs
-        for (int x = threadIdx.x; x < TX; x += kThreads) {
-            const uint32_t end = (x + 1 < TX) ? boff[x + 1] : cntb;
-            cur[x] += end - boff[x];
-        }
-        __syncthreads();
-    };
-    for (int h0 = 0; h0 < ns; h0 += kPlRound) {
-        const int nh = min(kPlRound, ns - h0);
-        // lane l of wave w holds the round's ranks 512 w + 64 k + l (k < kPlSlots)
-        uint32_t wd[kPlSlots], x0v[kPlSlots];
-#pragma unroll
-        for (int k = 0; k < kPlSlots; ++k) {
-            const int rk = w * 64 * kPlSlots + k * 64 + lane;
-            const uint2 rr = grect[h0 + min(rk, nh - 1)];
-            const uint32_t x0 = rr.x & 0xffffu, x1 = rr.x >> 16;
-            const int y0 = (int)(rr.y & 0xffffu), y1 = (int)(rr.y >> 16);
-            wd[k] = (rk < nh && y0 <= y && y < y1 && x0 < x1) ? x1 - x0 : 0u;
-            x0v[k] = x0;
-        }
-        // exclusive scans in rank order (slot-major in a wave, then waves): of
-        // the widths (run starts) and of the cover flags (places in the list)
-        uint32_t carry = 0, ccnt = 0, ofs[kPlSlots], pos[kPlSlots];
-#pragma unroll
-        for (int k = 0; k < kPlSlots; ++k) {
-            const uint32_t inc = wave_incl_scan(wd[k]);
-            ofs[k] = carry + inc - wd[k];
-            carry += (uint32_t)__builtin_amdgcn_readlane((int32_t)inc, 63);
-            const uint64_t cb = __ballot(wd[k] != 0u);
-            pos[k] = ccnt + __builtin_amdgcn_mbcnt_hi((uint32_t)(cb >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)cb, 0u));
-            ccnt += (uint32_t)__popcll(cb);
-        }
-        if (lane == 0) {
-            wsum[w] = carry;
-            wcov[w] = ccnt;
-        }
-        __syncthreads();
-        uint32_t wb = 0, tot = 0, cb0 = 0, call = 0;
-#pragma unroll
-        for (int k = 0; k < kWaves; ++k) {
-            if (k < w) {
-                wb += wsum[k];
-                cb0 += wcov[k];
-            }
-            tot += wsum[k];
-            call += wcov[k];
-        }
-        const int ncov = (int)call;   // covering ranks of the round; tot: their pairs
-#pragma unroll
-        for (int k = 0; k < kPlSlots; ++k) {
-            if (wd[k] != 0u) {
-                const uint32_t idx = cb0 + pos[k];
-                s_off[idx] = wb + ofs[k];
-                s_x0[idx] = (uint16_t)x0v[k];
-                s_rk[idx] = (uint16_t)(w * 64 * kPlSlots + k * 64 + lane);
-            }
-        }
-        __syncthreads();
-        if (placed + tot > len) return;   // cannot happen: the counts come from the same rects
-        placed += tot;
-        // expand the round's pairs into the pass buffer behind those already there
-        for (uint32_t q0 = 0; q0 < tot;) {
-            const uint32_t take = min(tot - q0, (uint32_t)(kThreads * kColItems) - fill);
-            // this thread fills the buffer slots b0 .. b0 + kPlPer - 1 that this expansion reaches
-            const uint32_t b0 = threadIdx.x * kPlPer;
-            const uint32_t blo = max(b0, fill), bhi = min(b0 + kPlPer, fill + take);
-            if (blo < bhi) {
-                const uint32_t qa = q0 + (blo - fill);
-                int lo = 0, hi = ncov - 1;   // last run starting at or before qa
-                while (lo < hi) {
-                    const int mid = (lo + hi + 1) >> 1;
-                    if (s_off[mid] <= qa) lo = mid;
-                    else hi = mid - 1;
-                }
-                int r = lo;
-                uint32_t o = s_off[r], end = r + 1 < ncov ? s_off[r + 1] : tot;
-                uint32_t wv[kPlPer];
-#pragma unroll
-                for (int i = 0; i < kPlPer; ++i) {
-                    const uint32_t b = b0 + i;
-                    wv[i] = 0u;
-                    if (b >= blo && b < bhi) {
-                        const uint32_t q = q0 + (b - fill);
-                        if (q >= end) {   // runs are never empty: q is in the next one
-                            ++r;
-                            o = end;
-                            end = r + 1 < ncov ? s_off[r + 1] : tot;
-                        }
-                        wv[i] = (((uint32_t)s_x0[r] + (q - o)) << kRankBits) | (uint32_t)(h0 + s_rk[r]);
-                    }
-                }
-                if (blo == b0 && bhi == b0 + kPlPer) {   // whole slot block: two 16-byte stores
-                    uint4* dst = reinterpret_cast<uint4*>(s_id + b0);
-                    dst[0] = make_uint4(wv[0], wv[1], wv[2], wv[3]);
-                    dst[1] = make_uint4(wv[4], wv[5], wv[6], wv[7]);
-                } else {
-#pragma unroll
-                    for (int i = 0; i < kPlPer; ++i)
-                        if (b0 + i >= blo && b0 + i < bhi) s_id[b0 + i] = wv[i];
-                }
-            }
-            fill += take;
-            q0 += take;
-            expanded += take;
-            if (fill == (uint32_t)(kThreads * kColItems) || expanded == len) {
-                place_pass(fill);
-                fill = 0;
-            }
-        }
-        __syncthreads();   // the next round rewrites wsum and the run offsets
+        const uint32_t* bw = wbase + w * TX;
+        for (int x = x0; x < x1; ++x) ids[bw[x] + (uint32_t)__popcll(mw[x] & below)] = e.x;
     }
 }
 
@@ -881,6 +856,8 @@ struct BinWs {
     uint32_t *gsum, *rtot;
     int64_t* rbase;
     uint32_t *tc, *toff, *segt, *trel;
+    uint32_t *rcov, *rltot;   // per (view, row, group): covering splats (then first list entry); per row: list length
+    int64_t* rlbase;          // per (view, row): the row list's start
     size_t bytes;
 };
 
@@ -913,6 +890,9 @@ BinWs bin_layout(int64_t N, int32_t V, int32_t tiles_x, int32_t tiles_y, char* b
     w.tc = (uint32_t*)take(4 * (size_t)V * B.G * T);
     w.toff = (uint32_t*)take(4 * (size_t)V * B.G * T);
     w.trel = (uint32_t*)take(4 * (size_t)V * T);
+    w.rcov = (uint32_t*)take(4 * (size_t)V * ty * B.G);
+    w.rltot = (uint32_t*)take(4 * (size_t)V * ty);
+    w.rlbase = (int64_t*)take(8 * (size_t)V * ty);
     w.bytes = o;
     return w;
 }
@@ -930,15 +910,13 @@ int gc_band(int tiles_x) {
     const int rows = (int)(kGcLds / (4 * (size_t)(tiles_x + 1))) - 1;
     return std::max(1, std::min(kGcBand, rows));
 }
-size_t gc_lds(int band, int tiles_x) { return (size_t)(band + 1) * (tiles_x + 1) * 4; }
-
-// LDS of the placement: cursors and bases per tile, a pass of pair words / ids,
-// a round's run starts, 16-bit per-wave counters per tile, a pass's tile x, and
-// a round's first tiles and ranks (54 KB at 1600 tile columns)
-size_t place_lds(const Bins& B) {
-    return ((size_t)2 * B.tiles_x + (size_t)kThreads * kColItems + kPlRound) * 4 +
-           ((size_t)kWaves * B.tiles_x + (size_t)kThreads * kColItems + 2 * kPlRound) * 2;
+size_t gc_lds(int band, int tiles_x, int tiles_y) {
+    return (size_t)(band + 1) * (tiles_x + 1) * 4 + (size_t)(tiles_y + 1) * 4;
 }
+
+// LDS of the placement: per wave and tile column a 64-bit mask and a first
+// place, and a cursor per column (5.2 KB at 100 columns, 104 KB at 2048)
+size_t place_lds(const Bins& B) { return (size_t)B.tiles_x * (kPcWaves * 8 + kPcWaves * 4 + 4); }
 
 
 }  // namespace
@@ -947,9 +925,9 @@ size_t bin_workspace_bytes(int64_t N, int32_t V, int32_t tiles_x, int32_t tiles_
     return bin_layout(N, V, tiles_x, tiles_y, nullptr).bytes;
 }
 
-// The placement stages nothing in global memory; the workspace stays in the ABI
-// as a placeholder of one aligned block.
-size_t sort_workspace_bytes(int64_t) { return align_up(256); }
+// The row lists: one 8-byte entry per (splat, covered tile row), at most one
+// per pair, so `capacity` entries always suffice.
+size_t sort_workspace_bytes(int64_t capacity) { return align_up((size_t)(capacity > 0 ? capacity : 1) * 8); }
 
 potr_status launch_bin(int64_t N, int32_t V, const potr_camera& cam0, const potr_config& cfg,
                        const potr_proj* proj, void* ws, uint32_t* order, int64_t* n_pairs, hipStream_t s) {
@@ -986,15 +964,15 @@ potr_status launch_bin(int64_t N, int32_t V, const potr_camera& cam0, const potr
             kout = t;
         }
         const int band = gc_band(txs);
-        hipLaunchKernelGGL(k_count, dim3(B.G, V), dim3(kGcThreads), gc_lds(band, txs), s, (const uint32_t*)order,
-                           (const uint2*)w.crect, B, band, w.srect, w.gsum, w.tc, w.segt);
+        hipLaunchKernelGGL(k_count, dim3(B.G, V), dim3(kGcThreads), gc_lds(band, txs, tys), s, (const uint32_t*)order,
+                           (const uint2*)w.crect, B, band, w.srect, w.gsum, w.tc, w.segt, w.rcov);
         st = check_launch("k_count");
         if (st != POTR_OK) return st;
     }
     // tile starts within their rows and row totals, then row bases over
     // (view, row), the pair count, and every group's first position per tile
     hipLaunchKernelGGL(k_tile_bases, dim3(tys, V), dim3(256), 0, s, w.segt, B, w.trel, w.rtot, w.ctl.ticket + kMaxPasses,
-                       (const uint32_t*)w.ctl.fault, w.rbase, n_pairs);
+                       (const uint32_t*)w.ctl.fault, w.rbase, n_pairs, w.rcov, w.rltot, w.rlbase);
     st = check_launch("k_tile_bases");
     if (st != POTR_OK || N == 0) return st;
     hipLaunchKernelGGL(k_tile_offsets, dim3((unsigned)ceil_div(B.T, 256), B.nseg_g, V), dim3(256), 0, s,
@@ -1010,7 +988,6 @@ potr_status launch_sort(int64_t N, int32_t V, const potr_camera& cam0, const pot
     const int txs = tiles_x(cam0, cfg), tys = tiles_y(cam0, cfg);
     BinWs w = bin_layout(N, V, txs, tys, (char*)ws);
     const Bins B = bins_of(N, V, txs, tys);
-    (void)sort_ws;   // nothing is staged in global memory
     if (N == 0) {
         // no pairs: every tile range is [0, 0)
         const int64_t words = (int64_t)V * B.T;
@@ -1018,45 +995,17 @@ potr_status launch_sort(int64_t N, int32_t V, const potr_camera& cam0, const pot
                            dim3(256), 0, s, (uint64_t*)tile_ranges, words);
         return check_launch("k_clear");
     }
-    // every (group, row) segment to its tiles (and the tile ranges)
+    // the row lists, then every (group, row) list to its tiles (and the tile ranges)
+    uint2* rows = (uint2*)sort_ws;
+    hipLaunchKernelGGL(k_rows, dim3(B.G, V), dim3(kRwThreads), 0, s, (const uint2*)w.srect, order,
+                       (const uint32_t*)w.rcov, (const int64_t*)w.rlbase, B, n_pairs, capacity, rows);
+    potr_status st = check_launch("k_rows");
+    if (st != POTR_OK) return st;
     const dim3 gp((unsigned)(8 * ceil_div(B.G, 8) * tys), V);   // see the XCD mapping in k_place
-    const size_t lds = place_lds(B);
-    const uint2* sr = w.srect;
-    const uint32_t* gs = w.gsum;
-    const uint32_t* to = w.toff;
-    const int64_t* rb = w.rbase;
-    const uint32_t* tr = w.trel;
-    const uint32_t* rt = w.rtot;
-    switch (B.xbits) {
-        case 1: case 2: case 3: case 4: case 5:
-            hipLaunchKernelGGL(k_place<5>, gp, dim3(kThreads), lds, s, sr, gs, to, rb, tr, rt, B, n_pairs, capacity, order,
-                               sorted_ids, tile_ranges);
-            break;
-        case 6:
-            hipLaunchKernelGGL(k_place<6>, gp, dim3(kThreads), lds, s, sr, gs, to, rb, tr, rt, B, n_pairs, capacity, order,
-                               sorted_ids, tile_ranges);
-            break;
-        case 7:
-            hipLaunchKernelGGL(k_place<7>, gp, dim3(kThreads), lds, s, sr, gs, to, rb, tr, rt, B, n_pairs, capacity, order,
-                               sorted_ids, tile_ranges);
-            break;
-        case 8:
-            hipLaunchKernelGGL(k_place<8>, gp, dim3(kThreads), lds, s, sr, gs, to, rb, tr, rt, B, n_pairs, capacity, order,
-                               sorted_ids, tile_ranges);
-            break;
-        case 9:
-            hipLaunchKernelGGL(k_place<9>, gp, dim3(kThreads), lds, s, sr, gs, to, rb, tr, rt, B, n_pairs, capacity, order,
-                               sorted_ids, tile_ranges);
-            break;
-        case 10:
-            hipLaunchKernelGGL(k_place<10>, gp, dim3(kThreads), lds, s, sr, gs, to, rb, tr, rt, B, n_pairs, capacity, order,
-                               sorted_ids, tile_ranges);
-            break;
-        default:
-            hipLaunchKernelGGL(k_place<11>, gp, dim3(kThreads), lds, s, sr, gs, to, rb, tr, rt, B, n_pairs, capacity, order,
-                               sorted_ids, tile_ranges);
-            break;
-    }
+    hipLaunchKernelGGL(k_place, gp, dim3(kPcThreads), place_lds(B), s, (const uint2*)rows, (const uint32_t*)w.rcov,
+                       (const uint32_t*)w.rltot, (const int64_t*)w.rlbase, (const uint32_t*)w.toff,
+                       (const int64_t*)w.rbase, (const uint32_t*)w.trel, (const uint32_t*)w.rtot, B, n_pairs,
+                       capacity, sorted_ids, tile_ranges);
     return check_launch("k_place");
 }
 

@@ -104,7 +104,7 @@ def test_workspace_too_small_is_capacity_error(lib):
     st = _status("potr_bin", 1000, 2, _cams(2), C.byref(cfg), 16, 16, need - 1, 16, 16, None)
     assert st == L.POTR_ECAPACITY
     sneed = L.sort_workspace_size(5000)
-    assert sneed > 0   # a placeholder: the placement stages nothing per pair
+    assert sneed >= 8 * 5000   # the row lists: at most one 8-byte entry per pair
     st = _status("potr_sort", 1000, 2, _cams(2), C.byref(cfg), 16, 16, 16, need - 1, 16, 5000, 16, sneed, 16, 16,
                  None)
     assert st == L.POTR_ECAPACITY
