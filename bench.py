@@ -34,7 +34,11 @@ chip's issue limit of one wave64 instruction per CU per cycle, for the live
 kernel time) come from the committed counter record of that kernel on this
 workload, null once the kernel's sources differ.
 The CPU baseline is the FP64 oracle on view 0 of the same scene, timed on the
-host with all its cores and with one.
+host with all its cores, and with one on a 64-row strip of that view (scaled to
+the full height).
+
+    --profile-section multi_scene   runs only that extra section (for a
+                                    kernel-trace profile of it alone)
 """
 from __future__ import annotations
 
@@ -95,10 +99,12 @@ def host_cpu():
     return {"model": model, "nproc": os.cpu_count(), "usable": usable}
 
 
-def cpu_baseline(scene, cams, s):
+def cpu_baseline(scene, cams, s, strip_rows: int = 64):
     """The FP64 oracle on view 0: projection and tile lists (single-threaded in the
     oracle), then compositing and removal scores with all usable cores (at most
-    16, the host share of one GPU) and again with one core."""
+    16, the host share of one GPU); the one-core figure composites a strip of
+    `strip_rows` rows through the middle of the same view (the same camera with
+    its principal point moved) on one thread and scales it to the full height."""
     import oracle
     threads = oracle.default_threads()
     cam = cams[0]
@@ -109,15 +115,24 @@ def cpu_baseline(scene, cams, s):
     t2 = time.perf_counter()
     oracle.render(scene, cam, s, proj=proj, bins=bins, threads=threads, want=("image", "score_l1"))
     t3 = time.perf_counter()
-    oracle.render(scene, cam, s, proj=proj, bins=bins, threads=1, want=("image", "score_l1"))
+    y0 = (cam.height - strip_rows) // 2
+    strip = type(cam)(cam.R, cam.t, cam.fx, cam.fy, cam.cx, cam.cy - y0, cam.width, strip_rows)
+    sp = oracle.project(scene, strip, s)
+    sb = oracle.bin_sort(sp["rect"], sp["depth_key"], *s.tiles(strip))
     t4 = time.perf_counter()
+    oracle.render(scene, strip, s, proj=sp, bins=sb, threads=1, want=("image", "score_l1"))
+    t5 = time.perf_counter()
     prep = t2 - t0
-    all_s, one_s = prep + (t3 - t2), prep + (t4 - t3)
+    one_comp = (t5 - t4) * cam.height / strip_rows
+    all_s, one_s = prep + (t3 - t2), prep + one_comp
     return {"value": scene.n / all_s / 1e9, "unit": "Gsplat·views/s", "cores": threads, "kind": "oracle",
             "sample": (f"view 0 of the {len(cams)} ({scene.n} splats, {cam.width}x{cam.height}): FP64 projection "
                        f"and tile lists (1 thread, {prep:.2f} s), compositing and removal scores with {threads} "
-                       f"threads ({t3 - t2:.2f} s) and with 1 ({t4 - t3:.2f} s)"),
-            "seconds": round(all_s, 3), "one_core": {"value": scene.n / one_s / 1e9, "seconds": round(one_s, 3)},
+                       f"threads ({t3 - t2:.2f} s); one core: a {cam.width}x{strip_rows} strip through the middle "
+                       f"of the view composited on 1 thread ({t5 - t4:.2f} s), scaled by {cam.height}/{strip_rows}"),
+            "seconds": round(all_s, 3),
+            "one_core": {"value": scene.n / one_s / 1e9, "seconds": round(one_s, 3),
+                         "composite_seconds_scaled": round(one_comp, 3)},
             "pairs": int(len(bins[1])), "host": host_cpu()}
 
 
@@ -142,7 +157,7 @@ def main_line(args, torch, raster, synth, batch):
     ds = raster.to_device(scene)
     N, V = scene.n, len(cams)
     scores = torch.zeros(N, dtype=torch.float32, device="cuda")
-    bs = batch.BatchScorer([(ds, cams, scores)], s, views_per_job=VIEWS_PER_JOB)
+    bs = batch.BatchScorer([(ds, cams, scores)], s, views_per_job=args.views_per_job)
     bs.capture()
 
     def step():
@@ -212,7 +227,7 @@ def main_line(args, torch, raster, synth, batch):
                                 f"{cams[0].width}x{cams[0].height}, scores accumulated over all views"),
                    "splats": N, "views": V, "width": cams[0].width, "height": cams[0].height,
                    "tile": f"{s.tile_w}x{s.tile_h}", "lds_batch": s.lds_batch, "t_min": s.t_min,
-                   "path": (f"batched: project, bin and sort per job of {VIEWS_PER_JOB} views, then one persistent "
+                   "path": (f"batched: project, bin and sort per job of {args.views_per_job} views, then one persistent "
                             f"fused composite + removal launch over every (view, tile), replayed as one HIP graph")},
         "roofline": roofline,
         "plain": {"path": "plain per-view launches: project, bin, sort, fused composite + removal",
@@ -363,9 +378,13 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--views-per-job", type=int, default=VIEWS_PER_JOB,
+                    help="views per batch job on the main line (project, bin and sort run per job)")
     ap.add_argument("--main-only", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 256 MiB device copy (reference for hardware byte counters)")
+    ap.add_argument("--profile-section", choices=("single_view", "multi_scene", "fwd_bwd"), default=None,
+                    help="run only this extra section and print its result (no main line)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); multi-GPU scoring shards by view "
@@ -376,6 +395,13 @@ def main():
 
     from paper_2601_14821_amd import autograd, batch, raster, synth
 
+    if args.profile_section:
+        fn = {"single_view": lambda: single_view_section(args, torch, raster, synth),
+              "multi_scene": lambda: multi_scene_section(torch, raster, synth, batch),
+              "fwd_bwd": lambda: fwd_bwd_section(torch, raster, synth, autograd)}[args.profile_section]
+        log(args.profile_section)
+        print(json.dumps({args.profile_section: fn()}), flush=True)
+        return
     log("main line: full scene, batched graph and plain per-view launches")
     main_out, (scene, cams, s) = main_line(args, torch, raster, synth, batch)
     if args.copy_probe:

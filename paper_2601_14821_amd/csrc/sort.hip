@@ -277,8 +277,11 @@ __global__ __launch_bounds__(kSwThreads) void k_sweep(const uint32_t* __restrict
     if (threadIdx.x == 0) s_ticket = atomicAdd(P.ticket, 1u);
     for (int t = threadIdx.x; t < kSwWaves * 256; t += kSwThreads) (&wcnt[0][0])[t] = 0;
     __syncthreads();
-    const int seg = (int)(s_ticket / (uint32_t)g.bps);
-    const int64_t b = (int64_t)(s_ticket - (uint32_t)seg * (uint32_t)g.bps);
+    // tickets go round the views (segments) first, so the views' look-back chains
+    // advance side by side; a block still only waits on smaller tickets
+    const uint32_t segs = gridDim.x / (uint32_t)g.bps;
+    const int seg = (int)(s_ticket % segs);
+    const int64_t b = (int64_t)(s_ticket / segs);
     uint32_t kmin;
     const int np = passes_of(krange, seg, kmin);
     if (P.pass >= np) return;   // every block of this view returns: nobody waits on them
@@ -656,14 +659,16 @@ __global__ __launch_bounds__(kGcThreads) void k_count(const uint32_t* __restrict
 // Row lists, a block per (group, view): for every tile row, the group's
 // splats that cover it, in depth-rank order, each as (splat id, its rect's
 // columns x0 | x1 << 16), written at the row list's place for the group (the
-// bin's cover counts, scanned). Within a band of 64 rows, every (row, rank
-// slot, wave) gets the ballot of its covering lanes; a scan of their counts
-// per row gives each wave's first place, a popcount below the lane its place.
+// bin's cover counts, scanned). Within a band of rows, every (row, rank slot,
+// wave) gets the 64-bit mask of its covering lanes (each lane ORs its bit into
+// the masks of its rows); a scan of their counts per row gives each wave's
+// first place, a popcount below the lane its place.
 constexpr int kRwThreads = 1024;
 constexpr int kRwItems = kGroupRanks / kRwThreads;   // ranks per thread (rank = slot * 1024 + thread)
 constexpr int kRwSlots = kRwItems * (kRwThreads / 64);   // (slot, wave) pairs, in rank order
-constexpr int kRwBand = 64;
-static_assert(kRwSlots == 64, "one lane per (slot, wave) in the per-row scan");
+constexpr int kRwPer = kRwSlots / 64;                      // of them per lane in the per-row scan
+constexpr int kRwBand = 4096 / kRwSlots;                  // rows per band (48 KB of masks and places)
+static_assert(kRwSlots % 64 == 0, "the per-row scan gives each lane whole (slot, wave) pairs");
 
 __device__ inline uint64_t lanes_below() {
     const int lane = (int)(threadIdx.x & 63u);
@@ -697,18 +702,19 @@ __global__ __launch_bounds__(kRwThreads) void k_rows(const uint2* __restrict__ s
             id[k] = order[r];
         }
     }
-    const uint64_t below = lanes_below();
+    const uint64_t below = lanes_below(), bit = 1ull << lane;
     for (int yb0 = 0; yb0 < B.tiles_y; yb0 += kRwBand) {
         const int nb = min(kRwBand, B.tiles_y - yb0);
-        for (int yy = 0; yy < nb; ++yy) {
-            const uint32_t y = (uint32_t)(yb0 + yy);
+        for (int i = threadIdx.x; i < kRwBand * kRwSlots; i += kRwThreads) (&mask[0][0])[i] = 0ull;
+        __syncthreads();
+        // every lane sets its bit in the masks of the rows it covers
 #pragma unroll
-            for (int k = 0; k < kRwItems; ++k) {
-                const uint32_t x0 = rr[k].x & 0xffffu, x1 = rr[k].x >> 16;
-                const uint32_t y0 = rr[k].y & 0xffffu, y1 = rr[k].y >> 16;
-                const uint64_t m = __ballot(x0 < x1 && y0 <= y && y < y1);
-                if (lane == 0) mask[yy][k * 16 + w] = m;
-            }
+        for (int k = 0; k < kRwItems; ++k) {
+            const int x0 = (int)(rr[k].x & 0xffffu), x1 = (int)(rr[k].x >> 16);
+            const int y0 = max((int)(rr[k].y & 0xffffu), yb0), y1 = min((int)(rr[k].y >> 16), yb0 + nb);
+            if (x0 >= x1) continue;
+            for (int y = y0; y < y1; ++y)
+                atomicOr((unsigned long long*)&mask[y - yb0][k * (kRwThreads / 64) + w], (unsigned long long)bit);
         }
         if ((int)threadIdx.x < nb) {
             const int64_t vy = (int64_t)v * B.tiles_y + yb0 + threadIdx.x;
@@ -716,8 +722,18 @@ __global__ __launch_bounds__(kRwThreads) void k_rows(const uint2* __restrict__ s
         }
         __syncthreads();
         for (int yy = w; yy < nb; yy += kRwThreads / 64) {
-            const uint32_t c = (uint32_t)__popcll(mask[yy][lane]);
-            wb[yy][lane] = wave_incl_scan(c) - c;
+            uint32_t c[kRwPer], t = 0;
+#pragma unroll
+            for (int q = 0; q < kRwPer; ++q) {
+                c[q] = (uint32_t)__popcll(mask[yy][kRwPer * lane + q]);
+                t += c[q];
+            }
+            uint32_t pre = wave_incl_scan(t) - t;
+#pragma unroll
+            for (int q = 0; q < kRwPer; ++q) {
+                wb[yy][kRwPer * lane + q] = pre;
+                pre += c[q];
+            }
         }
         __syncthreads();
 #pragma unroll
@@ -726,7 +742,7 @@ __global__ __launch_bounds__(kRwThreads) void k_rows(const uint2* __restrict__ s
             const int y0 = max((int)(rr[k].y & 0xffffu), yb0), y1 = min((int)(rr[k].y >> 16), yb0 + nb);
             if (x0 >= x1) continue;
             for (int y = y0; y < y1; ++y) {
-                const int yy = y - yb0, sl = k * 16 + w;
+                const int yy = y - yb0, sl = k * (kRwThreads / 64) + w;
                 const int64_t pos = rbeg[yy] + wb[yy][sl] + __popcll(mask[yy][sl] & below);
                 rows[pos] = make_uint2(id[k], rr[k].x);
             }
