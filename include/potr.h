@@ -314,7 +314,10 @@ POTR_API potr_status potr_render_score_out(int64_t N, int32_t V, const potr_came
  *   capture. Jobs run in up to four lanes (own scratch in the workspace, own
  *   default-priority stream created with the batch), forked from `stream` after
  *   the work already on it and joined back before the render launch. Scores
- *   accumulate (+=) into each job's buffers.
+ *   accumulate (+=) into each job's buffers; a job with a fine-tuning step runs
+ *   it in its lane right after its tile lists (forward composite, loss gradient,
+ *   blend and projection backward), so the step's gradients are in the same
+ *   run (and the same graph) as the scores.
  * potr_batch_render: enqueues only the persistent render + removal launch over
  *   the tile lists the last run (or replay) left in the workspace; scores
  *   accumulate (+=) again. With the lists unchanged it adds the same sums (up to
@@ -332,8 +335,19 @@ typedef struct potr_job {
     int32_t V;
     const potr_camera* cams;                          /* host [V], copied at create */
     potr_outputs out;                                 /* device outputs of this job's views, as for
-                                                         potr_render_score_out (at least one) */
+                                                         potr_render_score_out */
     const float* target;                              /* device [V,H,W,3], needed with out.scores_se */
+    /* Optional fine-tuning step (Sec. 4.6): with grad_target [V,H,W,3] (device)
+       the batch also composites the job's views, forms the gradient of the
+       loss grad_weight * sum over pixels and channels of |image - grad_target|
+       (sign(0) = 0) and runs the backward, ADDING the gradients into d_means
+       [N,3], d_scales [N,3], d_quats [N,4], d_opac [N] and d_sh [N,16,3]
+       (device, all five needed). Jobs that add into the same gradient arrays
+       run in one lane, one after another. A job needs score outputs, a
+       fine-tuning step, or both. */
+    const float* grad_target;
+    float grad_weight;
+    float *d_means, *d_scales, *d_quats, *d_opac, *d_sh;
 } potr_job;
 
 typedef struct potr_batch_s* potr_batch;
@@ -443,7 +457,8 @@ POTR_API potr_status potr_prune_select_noalloc(int64_t N, const float* dmse, con
 /* potr_autotune: times every tile shape (16x16, 8x8, 32x8) with every LDS batch
  * (64, 128, 320, 512) on the given jobs (`reps` timed runs each, after one
  * warm-up) and writes the fastest tile_w, tile_h, lds_batch into *inout. Uses
- * temporary device memory and scratch scores (the jobs' outputs are untouched);
+ * temporary device memory and scratch scores, and leaves fine-tuning steps out
+ * (the jobs' outputs and gradients are untouched);
  * synchronises. A shape at which some job's pairs exceed one call's limit
  * (2^31 - 1) is skipped; POTR_EINVAL when no candidate fits. Optional:
  * best_ms, and the tried configs with their times (arrays of at least 12) and

@@ -46,7 +46,9 @@ class potr_outputs(C.Structure):
 class potr_job(C.Structure):
     _fields_ = [("N", C.c_int64), ("means", C.c_void_p), ("scales", C.c_void_p), ("quats", C.c_void_p),
                 ("opac", C.c_void_p), ("sh", C.c_void_p), ("V", C.c_int32), ("cams", C.POINTER(potr_camera)),
-                ("out", potr_outputs), ("target", C.c_void_p)]
+                ("out", potr_outputs), ("target", C.c_void_p), ("grad_target", C.c_void_p),
+                ("grad_weight", C.c_float), ("d_means", C.c_void_p), ("d_scales", C.c_void_p),
+                ("d_quats", C.c_void_p), ("d_opac", C.c_void_p), ("d_sh", C.c_void_p)]
 
 
 _CAM_P, _CFG_P, _JOB_P = C.POINTER(potr_camera), C.POINTER(potr_config), C.POINTER(potr_job)

@@ -5,8 +5,9 @@
     assert bs.overflowed() == 0
 
 An item is (scene, cameras, scores[, importance]) with [N] tensors, or
-(scene, cameras, raster.Outputs[, targets]) for per-view arrays, weights and
-dSE sums against target images [V,H,W,3].
+(scene, cameras, raster.Outputs[, targets[, FineTune]]) for per-view arrays,
+weights and dSE sums against target images [V,H,W,3] (outputs may be an empty
+Outputs() when the item only runs a fine-tuning step).
 
 Scenes are split into jobs of at most `views_per_job` views (one image size per
 job). The library plans pair capacities by counting once at construction, runs
@@ -22,8 +23,21 @@ import os
 
 import torch
 
+import dataclasses
+
 from . import _lib as L
-from .raster import Outputs
+from .raster import DeviceScene, Outputs
+
+
+@dataclasses.dataclass
+class FineTune:
+    """The fine-tuning step of an item (Sec. 4.6): the gradients of
+    weight * sum |image - target| over the item's views are ADDED into the
+    grads (d_means, d_scales, d_quats, d_opac, d_sh: tensors shaped like the
+    scene's parameters). weight = 1 / (V H W 3) makes it the mean L1 loss."""
+    target: torch.Tensor          # [V, H, W, 3]
+    grads: DeviceScene
+    weight: float = 1.0
 
 
 class BatchScorer:
@@ -35,14 +49,18 @@ class BatchScorer:
         jobs = []
         for item in scenes:
             ds, cams, out = item[0], item[1], item[2]
-            targets = None
+            targets, step = None, None
             if isinstance(out, Outputs):
                 targets = item[3] if len(item) > 3 else None
+                step = item[4] if len(item) > 4 else None
             else:
                 out = Outputs(scores=out, importance=item[3] if len(item) > 3 else None)
             if targets is not None:
                 targets = targets.contiguous()
                 self._keep.append(targets)
+            if step is not None:
+                step = FineTune(step.target.contiguous(), step.grads, step.weight)
+                self._keep.append(step)
             for v0 in range(0, len(cams), views_per_job):
                 cb = cams[v0:v0 + views_per_job]
                 arr = L.make_cameras(cb)
@@ -55,6 +73,12 @@ class BatchScorer:
                 j.cams = C.cast(arr, C.POINTER(L.potr_camera))
                 j.out = L.make_outputs(out, v0)
                 j.target = None if targets is None else targets[v0].data_ptr()
+                if step is not None:
+                    g = step.grads
+                    j.grad_target = step.target[v0].data_ptr()
+                    j.grad_weight = float(step.weight)
+                    j.d_means, j.d_scales, j.d_quats = L.ptr(g.means), L.ptr(g.scales), L.ptr(g.quats)
+                    j.d_opac, j.d_sh = L.ptr(g.opacities), L.ptr(g.sh)
                 jobs.append(j)
         self.n_jobs = len(jobs)
         self.jobs = (L.potr_job * self.n_jobs)(*jobs)

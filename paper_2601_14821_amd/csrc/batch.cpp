@@ -18,6 +18,7 @@ potr_status launch_count_pairs(int64_t N, int32_t V, const potr_camera* cams, co
                                const float* sh, potr_proj* proj, int32_t* tt, int64_t* counts, hipStream_t s);
 potr_status launch_check_overflow(const int64_t* n_pairs, const int64_t* caps, int32_t n, int32_t* flag,
                                   hipStream_t s);
+potr_status launch_l1_grad(const float* image, const float* target, int64_t n, float w, float* dl, hipStream_t s);
 }  // namespace potr
 
 using namespace potr;
@@ -34,8 +35,9 @@ struct potr_batch_s {
     // jobs run in lanes (job j in lane j % lanes): each lane has its own scratch
     // (tiles_touched, depth order, bin and sort workspaces) and, with more than
     // one lane, its own stream, forked from and joined back into the caller's
-    struct LaneOff { size_t tt, order, bin, stage; };
+    struct LaneOff { size_t tt, order, bin, stage, pix, g2d; };   // pix, g2d: fine-tuning scratch
     std::vector<LaneOff> lane_off;
+    std::vector<size_t> lane_of;       // the lane of each job
     std::vector<hipStream_t> lane_s;
     std::vector<hipEvent_t> lane_ev;   // [0]: fork; [1 + l]: lane l done
     size_t off_table = 0, off_prefix = 0, off_counter = 0, off_npairs = 0, off_caps = 0, off_flag = 0;
@@ -62,7 +64,7 @@ potr_status hip_ok(hipError_t e, const char* what) {
 void plan_layout(potr_batch_s* b) {
     size_t o = 0;
     auto take = [&](size_t n) { size_t r = o; o += align_up(n > 0 ? n : 1); return r; };
-    size_t max_tt = 0, max_bin = 0, max_stage = 0;
+    size_t max_tt = 0, max_bin = 0, max_stage = 0, max_pix = 0, max_g2d = 0;
     b->off.resize(b->jobs.size());
     b->n_view_jobs = 0;
     for (size_t j = 0; j < b->jobs.size(); ++j) {
@@ -75,14 +77,39 @@ void plan_layout(potr_batch_s* b) {
         max_bin = std::max(max_bin, bin_workspace_bytes(J.N, J.V, tiles_x(b->cams[j][0], b->cfg),
                                                          tiles_y(b->cams[j][0], b->cfg)));
         max_stage = std::max(max_stage, sort_workspace_bytes(b->capacity[j]));
+        if (J.grad_target) {
+            // image (then dL/dimage), P_K, T_final, stop position: 8 words per pixel;
+            // the screen-space gradients: 9 per (view, splat)
+            const size_t P = (size_t)b->cams[j][0].width * b->cams[j][0].height;
+            max_pix = std::max(max_pix, (size_t)J.V * P * 8 * 4);
+            max_g2d = std::max(max_g2d, (size_t)J.V * J.N * 9 * 4);
+        }
         b->n_view_jobs += J.V;
     }
     b->lane_off.resize(std::min(kLanes, b->jobs.size()));
+    // jobs go round the lanes, except that jobs adding into the same gradient
+    // arrays (views of one scene with a fine-tuning step) share a lane: the
+    // projection backward adds without atomics, so they must not overlap
+    const size_t L = b->lane_off.size();
+    std::vector<const float*> scenes;
+    b->lane_of.resize(b->jobs.size());
+    for (size_t j = 0; j < b->jobs.size(); ++j) {
+        const potr_job& J = b->jobs[j];
+        if (J.grad_target) {
+            size_t k = std::find(scenes.begin(), scenes.end(), J.d_means) - scenes.begin();
+            if (k == scenes.size()) scenes.push_back(J.d_means);
+            b->lane_of[j] = k % L;
+        } else {
+            b->lane_of[j] = j % L;
+        }
+    }
     for (auto& L : b->lane_off) {
         L.tt = take(max_tt);
         L.order = take(max_tt);
         L.bin = take(max_bin);
         L.stage = take(max_stage);
+        L.pix = take(max_pix);
+        L.g2d = take(max_g2d);
     }
     b->off_table = take((size_t)b->n_view_jobs * sizeof(ViewJob));
     b->off_prefix = take((size_t)(b->n_view_jobs + 1) * 8);
@@ -94,6 +121,7 @@ void plan_layout(potr_batch_s* b) {
 }
 
 bool has_output(const potr_job& J) { return J.out.scores || J.out.scores_se || J.out.importance; }
+bool has_step(const potr_job& J) { return J.grad_target != nullptr; }
 
 potr_status validate_jobs(const potr_job* jobs, int32_t n_jobs, bool need_output = true) {
     if (!jobs || n_jobs < 1) return fail(POTR_EINVAL, "need at least one job");
@@ -101,8 +129,13 @@ potr_status validate_jobs(const potr_job* jobs, int32_t n_jobs, bool need_output
         const potr_job& J = jobs[j];
         if (J.N < 0 || J.V < 1 || J.N * (int64_t)J.V >= (int64_t(1) << 31) || !J.cams)
             return fail(POTR_EINVAL, "job %d: bad N/V/cams", j);
-        if (J.N > 0 && (!J.means || !J.scales || !J.quats || !J.opac || !J.sh || (need_output && !has_output(J))))
+        if (J.N > 0 && (!J.means || !J.scales || !J.quats || !J.opac || !J.sh ||
+                        (need_output && !has_output(J) && !has_step(J))))
             return fail(POTR_EINVAL, "job %d: NULL buffer", j);
+        if (has_step(J) && J.N > 0 && (!J.d_means || !J.d_scales || !J.d_quats || !J.d_opac || !J.d_sh))
+            return fail(POTR_EINVAL, "job %d: the fine-tuning step needs all five gradient arrays", j);
+        if (has_step(J) && !(std::fabs(J.grad_weight) <= 3.0e38f))
+            return fail(POTR_EINVAL, "job %d: grad_weight %g", j, (double)J.grad_weight);
         if (check_outputs(J.out, J.N, J.V, J.target) != POTR_OK) {
             const std::string why = potr_last_error();
             return fail(POTR_EINVAL, "job %d: %s", j, why.c_str());
@@ -245,7 +278,7 @@ potr_status potr_batch_bind(potr_batch b, void* ws, size_t ws_bytes, void* strea
             vj.target = J.target ? J.target + (int64_t)v * c0.width * c0.height * 3 : nullptr;
             set_outputs(vj, J.out, J.N, v);
             table.push_back(vj);
-            prefix.push_back(prefix.back() + (J.N > 0 ? T : 0));
+            prefix.push_back(prefix.back() + (J.N > 0 && has_output(J) ? T : 0));   // no items without outputs
         }
     }
     if (prefix.back() >= (int64_t(1) << 40))
@@ -279,7 +312,7 @@ potr_status potr_batch_run(potr_batch b, void* stream) {
         const potr_job& J = b->jobs[j];
         const potr_camera* cams = b->cams[j].data();
         potr_proj* proj = (potr_proj*)(ws + b->off[j].proj);
-        const size_t lane = j % b->lane_off.size();
+        const size_t lane = b->lane_of[j];
         const auto& L = b->lane_off[lane];
         const hipStream_t ls = b->lane_s.empty() ? s : b->lane_s[lane];
         int32_t* tt = (int32_t*)(ws + L.tt);
@@ -292,6 +325,24 @@ potr_status potr_batch_run(potr_batch b, void* stream) {
         if (st == POTR_OK)
             st = launch_sort(J.N, J.V, cams[0], b->cfg, proj, order, ws + L.bin, npairs + j, b->capacity[j],
                              ws + L.stage, ids, ranges, ls);
+        if (st == POTR_OK && has_step(J) && J.N > 0) {
+            // the fine-tuning step: composite, L1 loss gradient (in place of the
+            // image), screen-space then parameter gradients
+            const int64_t P = (int64_t)cams[0].width * cams[0].height, VP = (int64_t)J.V * P;
+            float* img = (float*)(ws + L.pix);
+            float* pf = img + 3 * VP;
+            float* tf = pf + 3 * VP;
+            int32_t* nw = (int32_t*)(tf + VP);
+            float* g2d = (float*)(ws + L.g2d);
+            st = launch_blend(J.N, J.V, cams[0], b->cfg, proj, ids, ranges, img, pf, tf, nw, nullptr, ls);
+            if (st == POTR_OK) st = launch_l1_grad(img, J.grad_target, 3 * VP, J.grad_weight, img, ls);
+            if (st == POTR_OK) st = launch_zero(g2d, (int64_t)J.V * J.N * 9, ls);
+            if (st == POTR_OK)
+                st = launch_blend_backward(J.N, J.V, cams[0], b->cfg, proj, ids, ranges, pf, tf, nw, img, g2d, ls);
+            if (st == POTR_OK)
+                st = launch_project_backward(J.N, J.V, cams, b->cfg, J.means, J.scales, J.quats, J.opac, J.sh, g2d,
+                                             J.d_means, J.d_scales, J.d_quats, J.d_opac, J.d_sh, ls);
+        }
         if (st != POTR_OK) return st;
     }
     // join: the render waits for every lane
@@ -369,7 +420,8 @@ potr_status potr_batch_destroy(potr_batch b) {
 // Times every built tile shape with every LDS batch size on the given jobs and
 // writes the fastest into *inout. Each candidate plans its own batch (pair
 // counts depend on the tile shape) in temporary device memory; scores go to
-// scratch buffers, so the caller's outputs are untouched.
+// scratch buffers and fine-tuning steps are left out, so the caller's outputs
+// are untouched.
 extern "C" potr_status potr_autotune(const potr_job* jobs, int32_t n_jobs, potr_config* inout, int32_t reps,
                                      double* best_ms, potr_config* tried, double* tried_ms, int32_t* n_tried,
                                      void* stream) {
@@ -382,6 +434,7 @@ extern "C" potr_status potr_autotune(const potr_job* jobs, int32_t n_jobs, potr_
     std::vector<potr_job> scratch(jobs, jobs + n_jobs);
     std::vector<float*> bufs;
     for (auto& J : scratch) {
+        J.grad_target = nullptr;   // the tuner times the scoring only; caller gradients stay untouched
         if (!has_output(J)) {
             J.out.scores = reinterpret_cast<float*>(1);
             J.out.scores_stride = 0;

@@ -1,5 +1,5 @@
-// Small kernels of the batch runtime: pair counting for planning and the
-// capacity check after a run.
+// Small kernels of the batch runtime: pair counting for planning, the L1 loss
+// gradient of the fine-tuning step and the capacity check after a run.
 #include "common.h"
 
 namespace potr {
@@ -36,7 +36,23 @@ __global__ void k_check_overflow(const int64_t* __restrict__ n_pairs, const int6
     *flag = bad;
 }
 
+// dL/dimage of L = w * sum |image - target|: w * sign(image - target), sign(0) = 0.
+__global__ __launch_bounds__(256) void k_l1_grad(const float* __restrict__ image, const float* __restrict__ target,
+                                                 int64_t n, float w, float* __restrict__ dl) {
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+        const float d = image[i] - target[i];
+        dl[i] = d > 0.f ? w : (d < 0.f ? -w : 0.f);
+    }
+}
+
 }  // namespace
+
+potr_status launch_l1_grad(const float* image, const float* target, int64_t n, float w, float* dl, hipStream_t s) {
+    if (n <= 0) return POTR_OK;
+    const int64_t b = ceil_div(n, 256);
+    hipLaunchKernelGGL(k_l1_grad, dim3((unsigned)(b < 8192 ? b : 8192)), dim3(256), 0, s, image, target, n, w, dl);
+    return check_launch("k_l1_grad");
+}
 
 potr_status launch_count_pairs(int64_t N, int32_t V, const potr_camera* cams, const potr_config& cfg,
                                const float* means, const float* scales, const float* quats, const float* opac,
