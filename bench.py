@@ -30,7 +30,7 @@ Algorithmic work per launch:
   (blend sweep 13 + 12, removal sweep 13 + 30), visited and blended counted
   over all 200 views outside the timed region.
 `traffic` (HBM bytes per launch) and `valu_issue` (VALU instructions over the
-chip's issue limit of one wave64 instruction per CU per cycle, for the live
+chip's FP32 issue rate, 2 wave64 instructions per CU per cycle, for the live
 kernel time) come from the committed counter record of that kernel on this
 workload, null once the kernel's sources differ.
 The CPU baseline is the FP64 oracle on view 0 of the same scene, timed on the
@@ -55,7 +55,9 @@ if ROOT not in sys.path:
 METRIC = "splat-view removal scores/s (Gsplat·views/s) + fwd+bwd ms/view, % HBM peak"
 HBM_PEAK_GBS = 8000.0
 FP32_VECTOR_PEAK_TFLOPS = 157.3
-VALU_ISSUE_PER_S = 256 * 2.4e9   # wave64 VALU instructions per second, one per CU per cycle
+# wave64 FP32 VALU instructions per second at the published FP32 vector peak:
+# 157.3 TFLOP/s over 64 lanes x 2 flops per FMA (two per CU per cycle at 2.4 GHz)
+VALU_ISSUE_PER_S = FP32_VECTOR_PEAK_TFLOPS * 1e12 / 128.0
 FUSED_FLOPS_VISIT, FUSED_FLOPS_BLEND = 26.0, 42.0
 VIEWS_PER_JOB = 8
 COUNTER_RECORD = "render_score_persistent_full_scene_counters.json"

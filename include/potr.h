@@ -129,9 +129,7 @@ POTR_API potr_status potr_project(int64_t N, int32_t V, const potr_camera* cams,
  *   ws     workspace of potr_bin_workspace_size bytes; potr_sort reads it, so
  *          it must stay untouched between the two calls
  *   order  [V*N] uint32 out: order[v*N + r] = id of the splat with depth rank r in view v
- *   n_pairs (device) int64 out: total number of pairs over all views; -1 if a
- *          device-side wait of the ordering gave up (an internal error, which
- *          later stages treat as "no pairs").
+ *   n_pairs (device) int64 out: total number of pairs over all views
  * Cost: the workspace holds 32 bytes per (view, splat) (depth sort keys and
  * values, rects by id and in depth order), 8 bytes per (view, group of 4096
  * ranks, tile) and 8 bytes per (view, group, tile row).

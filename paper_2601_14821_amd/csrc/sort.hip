@@ -10,19 +10,15 @@
 // the order a sort of (tile, depth, id) keys would give, without sorting per
 // pair.
 //
-// Depth radix passes are one kernel each: a block of 1024 threads x 4 items
-// ranks its keys per digit with 64-lane ballots (stable order: wave, item,
-// lane), publishes its digit counts, and finds the counts of all blocks before
-// it by decoupled look-back over their published words. The passes sort by
-// key - min over the view's keys: a view whose keys span fewer than 2^24 (2^16,
-// 2^8) values needs three (two, one) passes, and the rest return at once. The
-// key range, then the digit totals of the passes needed, come from two reads
-// up front. Blocks take their place in
-// the chain from an atomic ticket, so a block only ever waits on blocks that
-// are already running. Each block sorts its keys in LDS and writes every
-// digit's run to consecutive addresses. Every wait is bounded: after
-// kSpinLimit polls the block records a fault and goes on (the bin then reports
-// n_pairs = -1), so no input can leave a kernel spinning.
+// Every depth radix pass is three wait-free kernels: per block of 4096 keys
+// its digit counts; per (view, digit) a scan of those over the blocks (the
+// blocks' first places); per block a stable rank of its keys by digit (ballots
+// per wave), an LDS sort and coalesced runs out. The passes sort by key - min
+// over the view's keys: a view whose keys span fewer than 2^24 (2^16, 2^8)
+// values needs three (two, one) passes, and the rest return at once. The key
+// range, then the digit totals of the passes needed, come from two reads up
+// front. No kernel waits on another block, so the passes share the chip with
+// kernels on other streams without spinning.
 #include <algorithm>
 
 #include "common.h"
@@ -36,74 +32,6 @@ constexpr int kSwItems = 4;
 constexpr int kSwWaves = kSwThreads / 64;
 constexpr int kTile = kSwThreads * kSwItems;  // keys per block
 constexpr int kMaxPasses = 4;
-constexpr uint32_t kSpinLimit = 1u << 20;
-
-// ---------------------------------------------------------------- look-back words
-// [63:60] pass tag, [59:58] state (1: block aggregate, 2: inclusive prefix), [57:0] count.
-// Status arrays are cleared once per call; the tag tells this pass's words from
-// those the previous pass left in the same array.
-constexpr uint64_t kStAgg = 1, kStInc = 2;
-constexpr uint64_t kValMask = (1ull << 58) - 1;
-
-__device__ inline uint64_t st_word(uint32_t tag, uint64_t state, uint64_t v) {
-    return ((uint64_t)tag << 60) | (state << 58) | v;
-}
-__device__ inline void st_put(uint64_t* p, uint64_t w) {
-    __hip_atomic_store(p, w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ inline uint64_t st_get(uint64_t* p) {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ inline uint32_t st_state(uint64_t w, uint32_t tag) {
-    return (uint32_t)(w >> 60) == tag ? (uint32_t)((w >> 58) & 3u) : 0u;
-}
-
-// Exclusive prefix of one counter over blocks 0..b-1 (words at st[p * stride]):
-// adds aggregates walking back until an inclusive prefix is found, reading W
-// predecessors per round (their loads are independent, so a round costs one
-// memory latency). Aggregates before a not yet published word are taken
-// before waiting on it.
-template <int W>
-__device__ uint64_t look_back(uint64_t* st, int64_t b, int stride, uint32_t tag, uint32_t* fault) {
-    uint64_t excl = 0;
-    uint32_t spins = 0;
-    int64_t hi = b - 1;
-    while (hi >= 0) {
-        uint64_t wv[W];
-#pragma unroll
-        for (int k = 0; k < W; ++k) wv[k] = hi - k >= 0 ? st_get(st + (hi - k) * stride) : 0ull;
-        int k = 0;
-        bool found = false, gap = false;
-        for (; k < W; ++k) {
-            if (hi - k < 0) {          // before block 0: an inclusive zero
-                found = true;
-                break;
-            }
-            const uint32_t s = st_state(wv[k], tag);
-            if (s == 0) {
-                gap = true;
-                break;
-            }
-            excl += wv[k] & kValMask;
-            if (s == kStInc) {
-                found = true;
-                break;
-            }
-        }
-        if (found) break;
-        if (gap) {
-            hi -= k;
-            if (++spins > kSpinLimit) {
-                atomicOr(fault, 1u);
-                break;
-            }
-            __builtin_amdgcn_s_sleep(1);
-            continue;
-        }
-        hi -= W;
-    }
-    return excl;
-}
 
 // Lanes of the wave (among those with ok set) whose BITS-bit key d equals this
 // lane's: how many there are (cnt) and how many sit below this lane (below).
@@ -160,11 +88,8 @@ __device__ inline int64_t seg_n(const Seg& g) {
 
 struct Pass {
     int32_t pass, shift, bits;
-    uint32_t tag;             // 1 + pass index
     const uint32_t* ghist;    // this pass's digit totals at ghist[seg * kMaxPasses * 256 + digit]
-    uint64_t* status;         // [seg][bps][1 << bits]
-    uint32_t* ticket;
-    uint32_t* fault;
+    uint32_t* offs;           // [seg][digit][block]: the block's count, then its first place for the digit
 };
 
 // Depth keys, rects and the range of the keys, per view, in one read of the
@@ -257,43 +182,102 @@ __global__ __launch_bounds__(kHistThreads) void k_digits(const uint32_t* __restr
 }
 
 // One stable radix pass over the depth keys of every view, by the digits of
-// key - min (the view's passes_of decides how many passes it needs; the later
-// ones return at once). Values come from vin, or are the element's index when
-// vin == nullptr. A view's last pass writes only the values, to vfinal; the
-// others write keys to kout and values to vout.
-__global__ __launch_bounds__(kSwThreads) void k_sweep(const uint32_t* __restrict__ kin, uint32_t* __restrict__ kout,
-                                                    const uint32_t* __restrict__ vin, uint32_t* __restrict__ vout,
-                                                    uint32_t* __restrict__ vfinal, Seg g, Pass P,
-                                                    const uint32_t* __restrict__ krange) {
+// key - min, in three wait-free kernels (the view's passes_of decides how many
+// passes it needs; the later ones return at once):
+//   k_pass_count   per block of kTile keys, its count of every digit;
+//   k_pass_scan    per (view, digit), the blocks' first places for the digit
+//                  (the digit's base over the view, plus the counts of the
+//                  blocks before), in place of the counts;
+//   k_pass_scatter per block, each key's rank among the block's keys of its
+//                  digit (ballots per wave, in (wave, item, lane) order, which
+//                  is the keys' order), an LDS sort of the block, and every
+//                  digit's run written to consecutive addresses.
+// Values come from vin, or are the element's index when vin == nullptr. A view's
+// last pass writes only the values, to vfinal; the others write keys to kout and
+// values to vout.
+constexpr int kPcItems = 16;   // keys per thread of the count kernel (256 threads: one tile)
+static_assert(256 * kPcItems == kTile, "the count kernel covers one scatter block");
+
+__global__ __launch_bounds__(256) void k_pass_count(const uint32_t* __restrict__ kin, Seg g, Pass P,
+                                                   const uint32_t* __restrict__ krange) {
+    __shared__ uint32_t h[256];
+    const int b = blockIdx.x, seg = blockIdx.y;
+    uint32_t kmin;
+    if (P.pass >= passes_of(krange, seg, kmin)) return;
+    h[threadIdx.x] = 0u;
+    __syncthreads();
+    const int64_t n = seg_n(g), seg0 = (int64_t)seg * g.len, blk0 = (int64_t)b * kTile;
+    const uint32_t mask = (1u << P.bits) - 1u;
+    uint32_t key[kPcItems];
+#pragma unroll
+    for (int k = 0; k < kPcItems; ++k) {
+        const int64_t e = blk0 + k * 256 + threadIdx.x;
+        key[k] = e < n ? kin[seg0 + e] : 0u;
+    }
+#pragma unroll
+    for (int k = 0; k < kPcItems; ++k)
+        if (blk0 + k * 256 + threadIdx.x < n) atomicAdd(&h[digit_of(key[k] - kmin, P.shift, mask)], 1u);
+    __syncthreads();
+    P.offs[((int64_t)seg * 256 + threadIdx.x) * g.bps + b] = h[threadIdx.x];
+}
+
+__global__ __launch_bounds__(256) void k_pass_scan(Seg g, Pass P, const uint32_t* __restrict__ krange) {
+    __shared__ uint32_t wsum[4];
+    __shared__ uint32_t s_base;
+    const int d = blockIdx.x, seg = blockIdx.y, lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    uint32_t kmin;
+    if (P.pass >= passes_of(krange, seg, kmin)) return;
+    // the digit's base: the view's keys of the digits below it
+    const uint32_t gh = P.ghist[(int64_t)seg * kMaxPasses * 256 + threadIdx.x];
+    const uint32_t base = block_excl_scan<256>(gh, wsum);
+    if ((int)threadIdx.x == d) s_base = base;
+    __syncthreads();
+    uint32_t carry = s_base;
+    uint32_t* row = P.offs + ((int64_t)seg * 256 + d) * g.bps;
+    for (int b0 = 0; b0 < g.bps; b0 += 256) {
+        const int b = b0 + (int)threadIdx.x;
+        const uint32_t c = b < g.bps ? row[b] : 0u;
+        const uint32_t inc = wave_incl_scan(c);
+        if (lane == 63) wsum[w] = inc;
+        __syncthreads();
+        uint32_t pre = carry, all = 0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            if (k < w) pre += wsum[k];
+            all += wsum[k];
+        }
+        if (b < g.bps) row[b] = pre + inc - c;
+        carry += all;
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(kSwThreads) void k_pass_scatter(const uint32_t* __restrict__ kin,
+                                                            uint32_t* __restrict__ kout,
+                                                            const uint32_t* __restrict__ vin,
+                                                            uint32_t* __restrict__ vout,
+                                                            uint32_t* __restrict__ vfinal, Seg g, Pass P,
+                                                            const uint32_t* __restrict__ krange) {
     __shared__ uint32_t wcnt[kSwWaves][256];
     __shared__ uint32_t goff[256];
     __shared__ uint32_t boff[256];
     __shared__ uint32_t wsum[kSwWaves];
-    __shared__ uint32_t s_ticket;
     __shared__ uint32_t s_key[kTile];
     __shared__ uint32_t s_val[kTile];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int b = blockIdx.x, seg = blockIdx.y;
     const uint32_t radix = 1u << P.bits, mask = radix - 1;
-    if (threadIdx.x == 0) s_ticket = atomicAdd(P.ticket, 1u);
-    for (int t = threadIdx.x; t < kSwWaves * 256; t += kSwThreads) (&wcnt[0][0])[t] = 0;
-    __syncthreads();
-    // tickets go round the views (segments) first, so the views' look-back chains
-    // advance side by side; a block still only waits on smaller tickets
-    const uint32_t segs = gridDim.x / (uint32_t)g.bps;
-    const int seg = (int)(s_ticket % segs);
-    const int64_t b = (int64_t)(s_ticket / segs);
     uint32_t kmin;
     const int np = passes_of(krange, seg, kmin);
-    if (P.pass >= np) return;   // every block of this view returns: nobody waits on them
+    if (P.pass >= np) return;   // every block of this view returns
+    for (int t = threadIdx.x; t < kSwWaves * 256; t += kSwThreads) (&wcnt[0][0])[t] = 0;
+    if (threadIdx.x < radix) goff[threadIdx.x] = P.offs[((int64_t)seg * 256 + threadIdx.x) * g.bps + b];
+    __syncthreads();
     const bool last = P.pass == np - 1;
     const int64_t n = seg_n(g);
     const int64_t seg0 = (int64_t)seg * g.len;
-    const int64_t blk0 = b * kTile;
+    const int64_t blk0 = (int64_t)b * kTile;
     const int64_t wbase = blk0 + (int64_t)w * (64 * kSwItems);
-
-    // this segment's digit bases: exclusive scan of the pass's digit totals
-    const uint32_t gh = threadIdx.x < radix ? P.ghist[(int64_t)seg * kMaxPasses * 256 + threadIdx.x] : 0u;
-    const uint32_t dbase = block_excl_scan<kSwThreads>(gh, wsum);
 
     uint32_t key[kSwItems];
     uint32_t val[kSwItems];
@@ -331,17 +315,6 @@ __global__ __launch_bounds__(kSwThreads) void k_sweep(const uint32_t* __restrict
             wcnt[ww][d] = run;
             run += c;
         }
-        // publish this block's count, then find the counts before it
-        uint64_t* st = P.status + ((int64_t)seg * g.bps) * radix + d;
-        uint64_t excl = 0;
-        if (b == 0) {
-            st_put(st, st_word(P.tag, kStInc, run));
-        } else {
-            st_put(st + b * radix, st_word(P.tag, kStAgg, run));
-            excl = look_back<4>(st, b, (int)radix, P.tag, P.fault);
-            st_put(st + b * radix, st_word(P.tag, kStInc, excl + run));
-        }
-        goff[d] = dbase + (uint32_t)excl;
     }
     // exclusive scan of the block's digit counts: LDS position of each digit's run
     const uint32_t bo = block_excl_scan<kSwThreads>(run, wsum);
@@ -373,7 +346,7 @@ __global__ __launch_bounds__(kSwThreads) void k_sweep(const uint32_t* __restrict
     }
 }
 
-// Clears 64-bit words (look-back status, digit totals, key range, tickets).
+// Clears 64-bit words (digit totals, key range, tickets).
 __global__ void k_clear(uint64_t* __restrict__ p, int64_t n) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
         p[i] = 0;
@@ -439,11 +412,10 @@ __device__ inline uint32_t seg_prefix(uint32_t* __restrict__ p, int64_t stride, 
 // totals (the tile's start relative to the row's), rtot = the row's total. The
 // block that finishes last (a counter, cleared with the control words) then
 // forms the row bases, an exclusive scan of the row totals over (view, row),
-// and the number of pairs (-1 if a depth pass gave up a wait).
+// and the number of pairs.
 __global__ __launch_bounds__(256) void k_tile_bases(uint32_t* __restrict__ segt, Bins B,
                                                     uint32_t* __restrict__ trel, uint32_t* __restrict__ rtot,
                                                     uint32_t* __restrict__ rows_done,
-                                                    const uint32_t* __restrict__ fault,
                                                     int64_t* __restrict__ rbase, int64_t* __restrict__ n_pairs,
                                                     uint32_t* __restrict__ rcov, uint32_t* __restrict__ rltot,
                                                     int64_t* __restrict__ rlbase) {
@@ -522,7 +494,7 @@ __global__ __launch_bounds__(256) void k_tile_bases(uint32_t* __restrict__ segt,
         carry += all;
         __syncthreads();
     }
-    if (threadIdx.x == 0) *n_pairs = *fault ? (int64_t)-1 : carry;
+    if (threadIdx.x == 0) *n_pairs = carry;
     // the same over the row lists' lengths: where each row's list starts
     int64_t lcarry = 0;
     for (int64_t b0 = 0; b0 < nr; b0 += 256) {
@@ -838,14 +810,13 @@ __global__ __launch_bounds__(kPcThreads) void k_place(const uint2* __restrict__ 
 
 // ---------------------------------------------------------------- host side
 // Region at the front of the workspace, cleared at the start of every bin:
-// tickets (one per depth pass), the fault word, digit totals, the key range and
-// the look-back status words.
+// counter words (the last one counts finished tile rows), digit totals and the
+// key range.
 struct Ctl {
     uint32_t* ticket;
-    uint32_t* fault;
     uint32_t* ghist;
     uint32_t* krange;   // per view: largest key, largest complemented key
-    uint64_t* status;
+    uint32_t* offs;   // per (view, digit, block) counts, then places (not cleared: written before read)
     int64_t clear_words;
 };
 
@@ -884,16 +855,15 @@ BinWs bin_layout(int64_t N, int32_t V, int32_t tiles_x, int32_t tiles_y, char* b
     BinWs w;
     size_t o = 0;
     auto take = [&](size_t b) { char* p = base ? base + o : nullptr; o += align_up(b > 0 ? b : 1); return p; };
-    // a ticket per depth pass, the tile-row counter of k_tile_bases, the fault word
+    // counter words (the tile-row counter of k_tile_bases among them)
     w.ctl.ticket = (uint32_t*)take(4 * (kMaxPasses + 2));
-    w.ctl.fault = w.ctl.ticket + kMaxPasses + 1;
     w.ctl.ghist = (uint32_t*)take(4 * (size_t)V * kMaxPasses * 256);
     w.ctl.krange = (uint32_t*)take(4 * 2 * (size_t)V);
-    w.ctl.status = (uint64_t*)take(8 * (size_t)V * bps * 256);
     const size_t ty = (size_t)tiles_y, T = (size_t)B.T;
     // cleared with the control words: the sums the group counts add into
     w.segt = (uint32_t*)take(4 * (size_t)V * B.nseg_g * T);
     w.ctl.clear_words = (int64_t)(o / 8);
+    w.ctl.offs = (uint32_t*)take(4 * (size_t)V * bps * 256);
     w.ka = (uint32_t*)take(4 * VN);
     w.kb = (uint32_t*)take(4 * VN);
     w.va = (uint32_t*)take(4 * VN);
@@ -914,11 +884,13 @@ BinWs bin_layout(int64_t N, int32_t V, int32_t tiles_x, int32_t tiles_y, char* b
 }
 
 
-potr_status sweep(const uint32_t* kin, uint32_t* kout, const uint32_t* vin, uint32_t* vout, uint32_t* vfinal,
-                  const Seg& g, int segs, const Pass& P, const uint32_t* krange, hipStream_t s) {
-    hipLaunchKernelGGL(k_sweep, dim3((unsigned)((int64_t)g.bps * segs)), dim3(kSwThreads), 0, s, kin, kout, vin, vout,
-                       vfinal, g, P, krange);
-    return check_launch("k_sweep");
+potr_status radix_pass(const uint32_t* kin, uint32_t* kout, const uint32_t* vin, uint32_t* vout, uint32_t* vfinal,
+                       const Seg& g, int segs, const Pass& P, const uint32_t* krange, hipStream_t s) {
+    const dim3 grid((unsigned)g.bps, (unsigned)segs);
+    hipLaunchKernelGGL(k_pass_count, grid, dim3(256), 0, s, kin, g, P, krange);
+    hipLaunchKernelGGL(k_pass_scan, dim3(256, (unsigned)segs), dim3(256), 0, s, g, P, krange);
+    hipLaunchKernelGGL(k_pass_scatter, grid, dim3(kSwThreads), 0, s, kin, kout, vin, vout, vfinal, g, P, krange);
+    return check_launch("k_pass_count / k_pass_scan / k_pass_scatter");
 }
 
 // rows per band of the group counts' difference array, and its LDS bytes
@@ -970,9 +942,8 @@ potr_status launch_bin(int64_t N, int32_t V, const potr_camera& cam0, const potr
         const uint32_t* vin = nullptr;
         uint32_t* vbuf[2] = {w.va, w.vb};   // never the output: a view's last pass may be any of them
         for (int pass = 0; pass < kMaxPasses; ++pass) {
-            Pass P{pass, 8 * pass, 8, (uint32_t)(1 + pass), w.ctl.ghist + pass * 256, w.ctl.status,
-                   w.ctl.ticket + pass, w.ctl.fault};
-            st = sweep(kin, kout, vin, vbuf[pass & 1], order, g, V, P, w.ctl.krange, s);
+            Pass P{pass, 8 * pass, 8, w.ctl.ghist + pass * 256, w.ctl.offs};
+            st = radix_pass(kin, kout, vin, vbuf[pass & 1], order, g, V, P, w.ctl.krange, s);
             if (st != POTR_OK) return st;
             vin = vbuf[pass & 1];
             uint32_t* t = kin;
@@ -988,7 +959,7 @@ potr_status launch_bin(int64_t N, int32_t V, const potr_camera& cam0, const potr
     // tile starts within their rows and row totals, then row bases over
     // (view, row), the pair count, and every group's first position per tile
     hipLaunchKernelGGL(k_tile_bases, dim3(tys, V), dim3(256), 0, s, w.segt, B, w.trel, w.rtot, w.ctl.ticket + kMaxPasses,
-                       (const uint32_t*)w.ctl.fault, w.rbase, n_pairs, w.rcov, w.rltot, w.rlbase);
+                       w.rbase, n_pairs, w.rcov, w.rltot, w.rlbase);
     st = check_launch("k_tile_bases");
     if (st != POTR_OK || N == 0) return st;
     hipLaunchKernelGGL(k_tile_offsets, dim3((unsigned)ceil_div(B.T, 256), B.nseg_g, V), dim3(256), 0, s,

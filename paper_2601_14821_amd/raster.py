@@ -125,8 +125,6 @@ class Rasterizer:
         n = None
         if read_count:
             n = int(n_pairs.item())
-            if n < 0:
-                raise L.PotrError("potr_bin", L.POTR_EHIP, "device-side ordering did not complete")
         vb.order, vb.n_pairs = order, n
         vb._bin_ws = ws
         vb._n_pairs_dev = n_pairs
