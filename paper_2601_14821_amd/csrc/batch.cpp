@@ -45,6 +45,7 @@ struct potr_batch_s {
     int32_t n_view_jobs = 0;
     int32_t grid = 0;
     bool with_se = false;   // some job asks for dSE sums
+    int n_out = 1;          // the most per-splat outputs of any job
     char* ws = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -218,8 +219,13 @@ potr_status potr_batch_create(const potr_job* jobs, int32_t n_jobs, const potr_c
     }
     plan_layout(b);
     b->with_se = false;
-    for (auto& J : b->jobs) b->with_se = b->with_se || (J.N > 0 && J.out.scores_se != nullptr);
-    b->grid = persistent_grid(b->cfg, b->with_se);
+    b->n_out = 1;
+    for (auto& J : b->jobs) {
+        b->with_se = b->with_se || (J.N > 0 && J.out.scores_se != nullptr);
+        const int n = (J.out.scores ? 1 : 0) + (J.out.importance ? 1 : 0) + (J.out.scores_se ? 1 : 0);
+        b->n_out = std::max(b->n_out, n);
+    }
+    b->grid = persistent_grid(b->cfg, b->n_out);
     if (b->lane_off.size() > 1) {
         st = POTR_OK;
         for (size_t l = 0; l < b->lane_off.size() && st == POTR_OK; ++l) {
@@ -354,7 +360,7 @@ potr_status potr_batch_run(potr_batch b, void* stream) {
     potr_status st = launch_render_score_persistent((const ViewJob*)(ws + b->off_table), b->n_view_jobs,
                                                     (const int64_t*)(ws + b->off_prefix),
                                                     (int64_t*)(ws + b->off_counter), b->grid, b->cfg,
-                                                    b->with_se, s);
+                                                    b->with_se, b->n_out, s);
     if (st != POTR_OK) return st;
     return launch_check_overflow(npairs, (const int64_t*)(ws + b->off_caps), (int32_t)b->jobs.size(),
                                  (int32_t*)(ws + b->off_flag), s);
@@ -365,7 +371,7 @@ potr_status potr_batch_render(potr_batch b, void* stream) {
     char* ws = b->ws;
     return launch_render_score_persistent((const ViewJob*)(ws + b->off_table), b->n_view_jobs,
                                           (const int64_t*)(ws + b->off_prefix), (int64_t*)(ws + b->off_counter),
-                                          b->grid, b->cfg, b->with_se, (hipStream_t)stream);
+                                          b->grid, b->cfg, b->with_se, b->n_out, (hipStream_t)stream);
 }
 
 potr_status potr_batch_capture(potr_batch b, void* stream) {

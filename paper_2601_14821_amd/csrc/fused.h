@@ -50,13 +50,16 @@ inline void set_outputs(ViewJob& j, const potr_outputs& o, int64_t N, int64_t v)
 
 // dynamic LDS bytes of the fused pass with n_out per-splat outputs
 size_t fused_smem_bytes(const potr_config& cfg, int n_out);
-int persistent_grid(const potr_config& cfg, bool with_se);
+// workgroups of the persistent launch: as many as fit on every CU at once with
+// n_out per-splat outputs staged per entry
+int persistent_grid(const potr_config& cfg, int n_out);
 potr_status launch_render_score(const ViewJobs& jobs, int32_t n_views, int32_t tiles_per_view,
                                 const potr_config& cfg, hipStream_t s);
 // with_se: some job of the table has scores_se (the kernel then also keeps the
-// per-entry dSE sums; jobs without it skip them)
+// per-entry dSE sums; jobs without it skip them); n_out: the most per-splat
+// outputs (1..3) any job of the table has, which sizes the LDS
 potr_status launch_render_score_persistent(const ViewJob* jobs_dev, int32_t n_jobs, const int64_t* item_prefix_dev,
                                            int64_t* counter_dev, int32_t grid, const potr_config& cfg,
-                                           bool with_se, hipStream_t s);
+                                           bool with_se, int n_out, hipStream_t s);
 
 }  // namespace potr

@@ -304,8 +304,11 @@ __global__ __launch_bounds__(TW * TH) __attribute__((amdgpu_waves_per_eu(7))) vo
 
 // Persistent form: items are (view job, tile) pairs numbered job-major;
 // item_prefix[j] is the first item of job j (item_prefix[n_jobs] = total).
+// waves per SIMD the persistent form is compiled for (its register budget)
+constexpr int kPersistentWaves = 7;
+
 template <int TW, int TH, bool SE>
-__global__ __launch_bounds__(TW * TH) void k_render_score_persistent(const ViewJob* __restrict__ jobs, int32_t n_jobs,
+__global__ __launch_bounds__(TW * TH) __attribute__((amdgpu_waves_per_eu(kPersistentWaves))) void k_render_score_persistent(const ViewJob* __restrict__ jobs, int32_t n_jobs,
                                                                      const int64_t* __restrict__ item_prefix,
                                                                      int64_t* __restrict__ counter, potr_config cfg) {
     extern __shared__ __align__(16) char smem[];
@@ -368,12 +371,12 @@ potr_status launch_render_score(const ViewJobs& jobs_dev, int32_t n_views, int32
     return check_launch("k_render_score");
 }
 
-int persistent_grid(const potr_config& cfg, bool with_se) {
+int persistent_grid(const potr_config& cfg, int n_out) {
     int dev = 0, cus = 256;
     if (hipGetDevice(&dev) == hipSuccess) hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     const int threads = cfg.tile_w * cfg.tile_h;
-    const size_t sm = fused_smem_bytes(cfg, with_se ? 3 : 2);
-    int by_waves = 32 / ((threads + 63) / 64);              // 32 waves per CU
+    const size_t sm = fused_smem_bytes(cfg, n_out);
+    int by_waves = 4 * kPersistentWaves / ((threads + 63) / 64);   // 4 SIMDs per CU
     int by_lds = (int)((160 * 1024) / (sm + 256));
     int per_cu = by_waves < by_lds ? by_waves : by_lds;
     if (per_cu < 1) per_cu = 1;
@@ -382,8 +385,9 @@ int persistent_grid(const potr_config& cfg, bool with_se) {
 
 template <bool SE>
 potr_status launch_persistent(const ViewJob* jobs_dev, int32_t n_jobs, const int64_t* item_prefix_dev,
-                              int64_t* counter_dev, int32_t grid_size, const potr_config& cfg, hipStream_t s) {
-    const size_t sm = fused_smem_bytes(cfg, SE ? 3 : 2);   // scores, importance (and dSE)
+                              int64_t* counter_dev, int32_t grid_size, const potr_config& cfg, int n_out,
+                              hipStream_t s) {
+    const size_t sm = fused_smem_bytes(cfg, n_out);
     const dim3 grid(grid_size);
     if (cfg.tile_w == 16 && cfg.tile_h == 16)
         hipLaunchKernelGGL((k_render_score_persistent<16, 16, SE>), grid, dim3(256), sm, s, jobs_dev, n_jobs,
@@ -401,12 +405,13 @@ potr_status launch_persistent(const ViewJob* jobs_dev, int32_t n_jobs, const int
 
 potr_status launch_render_score_persistent(const ViewJob* jobs_dev, int32_t n_jobs, const int64_t* item_prefix_dev,
                                            int64_t* counter_dev, int32_t grid_size, const potr_config& cfg,
-                                           bool with_se, hipStream_t s) {
+                                           bool with_se, int n_out, hipStream_t s) {
     hipLaunchKernelGGL(k_zero_i64, dim3(1), dim3(1), 0, s, counter_dev);
     potr_status st = check_launch("k_zero_i64");
     if (st != POTR_OK) return st;
-    return with_se ? launch_persistent<true>(jobs_dev, n_jobs, item_prefix_dev, counter_dev, grid_size, cfg, s)
-                   : launch_persistent<false>(jobs_dev, n_jobs, item_prefix_dev, counter_dev, grid_size, cfg, s);
+    return with_se
+               ? launch_persistent<true>(jobs_dev, n_jobs, item_prefix_dev, counter_dev, grid_size, cfg, n_out, s)
+               : launch_persistent<false>(jobs_dev, n_jobs, item_prefix_dev, counter_dev, grid_size, cfg, n_out, s);
 }
 
 }  // namespace potr
