@@ -631,9 +631,10 @@ __global__ __launch_bounds__(kGcThreads) void k_count(const uint32_t* __restrict
 // Row lists, a block per (group, view): for every tile row, the group's
 // splats that cover it, in depth-rank order, each as (splat id, its rect's
 // columns x0 | x1 << 16), written at the row list's place for the group (the
-// bin's cover counts, scanned). Within a band of rows, every (row, rank slot,
-// wave) gets the 64-bit mask of its covering lanes (each lane ORs its bit into
-// the masks of its rows); a scan of their counts per row gives each wave's
+// bin's cover counts, scanned). Within a band of up to 64 rows, every (row,
+// rank slot, wave) gets the 64-bit mask of its covering lanes (each lane marks
+// its rows in a word, and a bit transpose over the wave turns the 64 words
+// into the 64 rows' masks); a scan of their counts per row gives each wave's
 // first place, a popcount below the lane its place.
 constexpr int kRwThreads = 1024;
 constexpr int kRwItems = kGroupRanks / kRwThreads;   // ranks per thread (rank = slot * 1024 + thread)
@@ -641,6 +642,23 @@ constexpr int kRwSlots = kRwItems * (kRwThreads / 64);   // (slot, wave) pairs, 
 constexpr int kRwPer = kRwSlots / 64;                      // of them per lane in the per-row scan
 constexpr int kRwBand = 4096 / kRwSlots;                  // rows per band (48 KB of masks and places)
 static_assert(kRwSlots % 64 == 0, "the per-row scan gives each lane whole (slot, wave) pairs");
+
+// 64x64 bit-matrix transpose over a wave: lane i's word is row i; on return
+// lane j's word holds column j (bit i = bit j of lane i's word). Each stage
+// swaps the off-diagonal blocks of one bit of the row and column indices.
+__device__ inline uint64_t wave_transpose64(uint64_t r) {
+    const int lane = (int)(threadIdx.x & 63u);
+    constexpr uint64_t keep[6] = {0x00000000ffffffffull, 0x0000ffff0000ffffull, 0x00ff00ff00ff00ffull,
+                                  0x0f0f0f0f0f0f0f0full, 0x3333333333333333ull, 0x5555555555555555ull};
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        const int s = 32 >> k;
+        const uint64_t m = keep[k];
+        const uint64_t p = __shfl_xor(r, s, 64);
+        r = (lane & s) ? ((r & ~m) | ((p >> s) & m)) : ((r & m) | ((p & m) << s));
+    }
+    return r;
+}
 
 __device__ inline uint64_t lanes_below() {
     const int lane = (int)(threadIdx.x & 63u);
@@ -674,19 +692,22 @@ __global__ __launch_bounds__(kRwThreads) void k_rows(const uint2* __restrict__ s
             id[k] = order[r];
         }
     }
-    const uint64_t below = lanes_below(), bit = 1ull << lane;
+    const uint64_t below = lanes_below();
     for (int yb0 = 0; yb0 < B.tiles_y; yb0 += kRwBand) {
         const int nb = min(kRwBand, B.tiles_y - yb0);
-        for (int i = threadIdx.x; i < kRwBand * kRwSlots; i += kRwThreads) (&mask[0][0])[i] = 0ull;
-        __syncthreads();
-        // every lane sets its bit in the masks of the rows it covers
+        // every lane marks the band's rows it covers in one 64-bit word; the
+        // wave's words, transposed, give every row the mask of its covering lanes
 #pragma unroll
         for (int k = 0; k < kRwItems; ++k) {
             const int x0 = (int)(rr[k].x & 0xffffu), x1 = (int)(rr[k].x >> 16);
-            const int y0 = max((int)(rr[k].y & 0xffffu), yb0), y1 = min((int)(rr[k].y >> 16), yb0 + nb);
-            if (x0 >= x1) continue;
-            for (int y = y0; y < y1; ++y)
-                atomicOr((unsigned long long*)&mask[y - yb0][k * (kRwThreads / 64) + w], (unsigned long long)bit);
+            const int y0 = max((int)(rr[k].y & 0xffffu), yb0) - yb0, y1 = min((int)(rr[k].y >> 16), yb0 + nb) - yb0;
+            // rows [y0, y1) of the band, 0 <= y0 and y1 <= nb <= 64 (none when y0 >= y1)
+            const bool any = x0 < x1 && y0 < y1;
+            const uint64_t hi = y1 >= 64 ? ~0ull : (1ull << (any ? y1 : 0)) - 1ull;
+            const uint64_t lo = (1ull << (any ? y0 : 0)) - 1ull;
+            const uint64_t rowbits = any ? (hi & ~lo) : 0ull;
+            const uint64_t cov = wave_transpose64(rowbits);
+            if (lane < nb) mask[lane][k * (kRwThreads / 64) + w] = cov;
         }
         if ((int)threadIdx.x < nb) {
             const int64_t vy = (int64_t)v * B.tiles_y + yb0 + threadIdx.x;
@@ -723,21 +744,48 @@ __global__ __launch_bounds__(kRwThreads) void k_rows(const uint2* __restrict__ s
     }
 }
 
-// Pair placement, a block per (view, group, row): the group's row list (its
+// Pair placement, a block per (view, tile row, group): the group's row list (its
 // splats covering the row, in rank order) goes out as pairs, each splat to
 // every tile x0..x1-1 of its run, at the tile's cursor (the group's first
-// position in the tile, from the bin's counts). Per chunk of 256 list entries
-// every wave marks, per tile column, which of its lanes cover the column (LDS
-// atomic ORs of the lane's bit: 64-bit masks, one per (wave, column)); a
-// column pass turns the masks into each wave's first place in the column
-// and advances the cursors; then every lane puts its splat id at its place in
-// each of its columns (the wave's first place plus the lanes below it in the
-// mask). Lanes are in rank order within a wave, waves within the chunk and
-// chunks within the list, so every tile's run of the group stays in rank order.
-// Blocks of group 0 also write the row's tile ranges, [0, 0) when empty and all
-// empty when the pairs exceed the capacity.
+// position in the tile, from the bin's counts). The list goes by chunks of 256
+// entries. A chunk's pairs, numbered entry by entry (a block scan of the run
+// widths), are cut into equal consecutive shares, one per thread, so that wide
+// and narrow runs cost every thread alike; each thread walks its share twice.
+// The first walk sets, per pair, the entry's bit in the 64-bit mask of (the
+// entry's wave, the pair's column) (LDS atomic ORs). A column pass turns the
+// masks into each (wave, column)'s first place and advances the cursors. The
+// second walk puts each entry's splat id at its place in each of its columns:
+// the first place of its (wave, column) plus its wave's entries below it in
+// the mask. Entries are in rank order within a mask, masks within the chunk
+// and chunks within the list, so every tile's run of the group stays in rank
+// order. Blocks of group 0 also write the row's tile ranges, [0, 0) when empty
+// and all empty when the pairs exceed the capacity.
 constexpr int kPcThreads = 256;
 constexpr int kPcWaves = kPcThreads / 64;
+constexpr int kPcStage = 2048;   // pairs of a chunk staged for the coalesced write-out
+
+// The entry of a chunk whose pairs hold pair q: the largest i with pst[i] <= q
+// (pst: the entries' first pairs, nondecreasing from pst[0] = 0).
+__device__ inline int entry_of(const uint32_t* pst, uint32_t q) {
+    int lo = 0, hi = kPcThreads - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (pst[mid] <= q) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// The next entry after i with a nonempty run (one exists when a pair is left).
+__device__ inline int next_run(const uint32_t* ecol, int i, uint32_t& x, uint32_t& xe) {
+    uint32_t c;
+    do {
+        c = ecol[++i];
+    } while ((c >> 16) <= (c & 0xffffu));
+    x = c & 0xffffu;
+    xe = c >> 16;
+    return i;
+}
 
 __global__ __launch_bounds__(kPcThreads) void k_place(const uint2* __restrict__ rows,
                                                      const uint32_t* __restrict__ rcov,
@@ -751,22 +799,30 @@ __global__ __launch_bounds__(kPcThreads) void k_place(const uint2* __restrict__ 
                                                      uint32_t* __restrict__ ids, int32_t* __restrict__ ranges) {
     extern __shared__ __align__(16) uint64_t lds64[];
     const int TX = B.tiles_x;
-    uint64_t* mask = lds64;                                         // [kPcWaves][TX]
+    uint64_t* mask = lds64;                                              // [kPcWaves][TX]
     uint32_t* cur = reinterpret_cast<uint32_t*>(mask + kPcWaves * TX);   // [TX]
-    uint32_t* wbase = cur + TX;                                     // [kPcWaves][TX]
+    uint32_t* wbase = cur + TX;                                          // [kPcWaves][TX]
+    uint32_t* eid = wbase + kPcWaves * TX;                               // [kPcThreads] the chunk's splat ids
+    uint32_t* ecol = eid + kPcThreads;                                   // [kPcThreads] their runs x0 | x1 << 16
+    uint32_t* pst = ecol + kPcThreads;                                   // [kPcThreads] their first pairs
+    uint32_t* wsum = pst + kPcThreads;                                   // [kPcWaves]
+    uint32_t* cst = wsum + kPcWaves;                                     // [TX] the columns' first staged slots
+    uint32_t* sid = cst + TX;                                            // [kPcStage] staged splat ids
+    uint32_t* sdst = sid + kPcStage;                                     // [kPcStage] and their places
     // workgroups go to the 8 XCDs round-robin by linear id: block b runs on XCD
-    // b % 8, and XCD x takes the groups x, x + 8, ... with all their rows, so a
-    // group's offsets are read through one XCD's L2
+    // b % 8, and XCD x takes the tile rows x, x + 8, ... with all their groups in
+    // rank order, so every tile's list (the runs of all the groups, one after
+    // another) is written through one XCD's L2
     const int xcd = (int)(blockIdx.x & 7u), m = (int)(blockIdx.x >> 3), v = blockIdx.y;
-    const int j = m / B.tiles_y, y = m - j * B.tiles_y, g = xcd + 8 * j;
-    if (g >= B.G) return;
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int j = m / B.G, g = m - j * B.G, y = xcd + 8 * j;
+    if (y >= B.tiles_y) return;
+    const int t = (int)threadIdx.x, lane = t & 63, w = t >> 6;
     const int64_t n = *n_pairs;
     const bool fits = n >= 0 && n <= capacity;
     const int64_t vy = (int64_t)v * B.tiles_y + y;
     if (g == 0) {
         const int64_t rb = rbase[vy];
-        for (int x = threadIdx.x; x < TX; x += kPcThreads) {
+        for (int x = t; x < TX; x += kPcThreads) {
             const int64_t i = (int64_t)v * B.T + (int64_t)y * TX + x;
             const int64_t b = rb + trel[i], e = rb + (x + 1 < TX ? trel[i + 1] : rtot[vy]);
             const bool any = fits && e > b;
@@ -781,30 +837,102 @@ __global__ __launch_bounds__(kPcThreads) void k_place(const uint2* __restrict__ 
     if (end <= beg) return;
     const int cnt = (int)(end - beg);
     const uint32_t* orow = off + ((int64_t)v * B.G + g) * B.T + (int64_t)y * TX;
-    for (int x = threadIdx.x; x < TX; x += kPcThreads) cur[x] = orow[x];
-    const uint64_t below = lanes_below(), bit = 1ull << lane;
+    for (int x = t; x < TX; x += kPcThreads) cur[x] = orow[x];
     for (int c0 = 0; c0 < cnt; c0 += kPcThreads) {
-        __syncthreads();   // the cursors are set, and the last chunk is done with the masks
-        for (int i = threadIdx.x; i < kPcWaves * TX; i += kPcThreads) mask[i] = 0ull;
-        const bool valid = c0 + (int)threadIdx.x < cnt;
-        const uint2 e = valid ? rows[beg + c0 + threadIdx.x] : make_uint2(0u, 0u);
-        const int x0 = (int)(e.y & 0xffffu), x1 = (int)(e.y >> 16);
+        __syncthreads();   // the cursors are set, and the last chunk is done with every array
+        for (int i = t; i < kPcWaves * TX; i += kPcThreads) mask[i] = 0ull;
+        const bool valid = c0 + t < cnt;
+        const uint2 e = valid ? rows[beg + c0 + t] : make_uint2(0u, 0u);
+        const uint32_t ex0 = e.y & 0xffffu, ex1 = e.y >> 16;
+        const uint32_t wd = ex1 > ex0 ? ex1 - ex0 : 0u;
+        eid[t] = e.x;
+        ecol[t] = e.y;
+        const uint32_t inc = wave_incl_scan(wd);
+        if (lane == 63) wsum[w] = inc;
         __syncthreads();
-        uint64_t* mw = mask + w * TX;
-        for (int x = x0; x < x1; ++x) atomicOr((unsigned long long*)&mw[x], (unsigned long long)bit);
-        __syncthreads();
-        for (int x = threadIdx.x; x < TX; x += kPcThreads) {
-            uint32_t c = cur[x];
+        uint32_t pre = 0, np = 0;
 #pragma unroll
-            for (int ww = 0; ww < kPcWaves; ++ww) {
-                wbase[ww * TX + x] = c;
-                c += (uint32_t)__popcll(mask[ww * TX + x]);
+        for (int k = 0; k < kPcWaves; ++k) {
+            if (k < w) pre += wsum[k];
+            np += wsum[k];
+        }
+        pst[t] = pre + inc - wd;
+        __syncthreads();
+        // this thread's share [q0, q1) of the chunk's np pairs; its first pair's entry and column
+        const uint32_t share = (np + kPcThreads - 1) / kPcThreads;
+        const uint32_t q0 = min(np, (uint32_t)t * share), q1 = min(np, q0 + share);
+        int i0 = 0;
+        uint32_t x0 = 0, xe0 = 0;
+        if (q0 < q1) {
+            i0 = entry_of(pst, q0);
+            const uint32_t c = ecol[i0];
+            x0 = (c & 0xffffu) + (q0 - pst[i0]);
+            xe0 = c >> 16;
+        }
+        {
+            int i = i0;
+            uint32_t x = x0, xe = xe0;
+            for (uint32_t q = q0; q < q1; ++q) {
+                atomicOr((unsigned long long*)&mask[(i >> 6) * TX + (int)x], (unsigned long long)(1ull << (i & 63)));
+                if (++x == xe && q + 1 < q1) i = next_run(ecol, i, x, xe);
             }
-            cur[x] = c;
         }
         __syncthreads();
-        const uint32_t* bw = wbase + w * TX;
-        for (int x = x0; x < x1; ++x) ids[bw[x] + (uint32_t)__popcll(mw[x] & below)] = e.x;
+        // per column: each wave's first place, the cursor advanced past the
+        // chunk, and the column's first slot in the chunk's staging order
+        uint32_t carry = 0;
+        for (int x0c = 0; x0c < TX; x0c += kPcThreads) {
+            const int x = x0c + t;
+            uint32_t c0 = 0, c = 0;
+            if (x < TX) {
+                c0 = c = cur[x];
+#pragma unroll
+                for (int ww = 0; ww < kPcWaves; ++ww) {
+                    wbase[ww * TX + x] = c;
+                    c += (uint32_t)__popcll(mask[ww * TX + x]);
+                }
+                cur[x] = c;
+            }
+            const uint32_t cn = c - c0;
+            const uint32_t inc = wave_incl_scan(cn);
+            __syncthreads();   // wsum is free (read above, or by the last pass of this loop)
+            if (lane == 63) wsum[w] = inc;
+            __syncthreads();
+            uint32_t pre = carry, all = 0;
+#pragma unroll
+            for (int k = 0; k < kPcWaves; ++k) {
+                if (k < w) pre += wsum[k];
+                all += wsum[k];
+            }
+            if (x < TX) cst[x] = pre + inc - cn;
+            carry += all;
+        }
+        __syncthreads();
+        // the chunk's ids go out in place order: staged in LDS by (column, place),
+        // then copied to consecutive addresses per column; a chunk of more pairs
+        // than the staging holds writes every id at its place directly
+        const bool staged = np <= (uint32_t)kPcStage;
+        {
+            int i = i0;
+            uint32_t x = x0, xe = xe0;
+            for (uint32_t q = q0; q < q1; ++q) {
+                const int s = (i >> 6) * TX + (int)x;
+                const uint64_t below = (1ull << (i & 63)) - 1ull;
+                const uint32_t dst = wbase[s] + (uint32_t)__popcll(mask[s] & below);
+                if (staged) {
+                    const uint32_t slot = cst[x] + (dst - wbase[x]);
+                    sid[slot] = eid[i];
+                    sdst[slot] = dst;
+                } else {
+                    ids[dst] = eid[i];
+                }
+                if (++x == xe && q + 1 < q1) i = next_run(ecol, i, x, xe);
+            }
+        }
+        if (staged) {
+            __syncthreads();
+            for (uint32_t o = (uint32_t)t; o < np; o += kPcThreads) ids[sdst[o]] = sid[o];
+        }
     }
 }
 
@@ -903,8 +1031,13 @@ size_t gc_lds(int band, int tiles_x, int tiles_y) {
 }
 
 // LDS of the placement: per wave and tile column a 64-bit mask and a first
-// place, and a cursor per column (5.2 KB at 100 columns, 104 KB at 2048)
-size_t place_lds(const Bins& B) { return (size_t)B.tiles_x * (kPcWaves * 8 + kPcWaves * 4 + 4); }
+// place, a cursor and a first staging slot per column, per chunk entry its id,
+// run and first pair, and the staged ids and places (24.5 KB at 100 columns,
+// 131 KB at 2048)
+size_t place_lds(const Bins& B) {
+    return (size_t)B.tiles_x * (kPcWaves * 8 + kPcWaves * 4 + 4 + 4) + 3 * kPcThreads * 4 + kPcWaves * 4 +
+           2 * (size_t)kPcStage * 4;
+}
 
 
 }  // namespace
@@ -988,7 +1121,7 @@ potr_status launch_sort(int64_t N, int32_t V, const potr_camera& cam0, const pot
                        (const uint32_t*)w.rcov, (const int64_t*)w.rlbase, B, n_pairs, capacity, rows);
     potr_status st = check_launch("k_rows");
     if (st != POTR_OK) return st;
-    const dim3 gp((unsigned)(8 * ceil_div(B.G, 8) * tys), V);   // see the XCD mapping in k_place
+    const dim3 gp((unsigned)(8 * ceil_div(tys, 8) * B.G), V);   // see the XCD mapping in k_place
     hipLaunchKernelGGL(k_place, gp, dim3(kPcThreads), place_lds(B), s, (const uint2*)rows, (const uint32_t*)w.rcov,
                        (const uint32_t*)w.rltot, (const int64_t*)w.rlbase, (const uint32_t*)w.toff,
                        (const int64_t*)w.rbase, (const uint32_t*)w.trel, (const uint32_t*)w.rtot, B, n_pairs,
