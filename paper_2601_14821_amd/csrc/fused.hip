@@ -79,7 +79,9 @@ __device__ void render_score_tile(const ViewJob& J, int tile, const potr_config&
     const float fx = (float)px + 0.5f, fy = (float)py + 0.5f;
     const int beg = J.ranges[2 * tile], end = J.ranges[2 * tile + 1];
     const int B = cfg.lds_batch;
-    const float qmax = cfg.q_max, amin = cfg.alpha_min, amax = cfg.alpha_max, tmin = cfg.t_min;
+    const float qmax = cfg.q_max, amin = cfg.alpha_min, tmin = cfg.t_min;
+    // a min's result is canonical, so the per-entry min against it needs no canonicalisation
+    const float amax = fminf(cfg.alpha_max, 1.f);
     const float emin = exp_floor(qmax);
     // SE instantiations serve jobs with and without dSE output
     const bool se = SE && J.scores_se != nullptr;
@@ -100,10 +102,12 @@ __device__ void render_score_tile(const ViewJob& J, int tile, const potr_config&
     for (int base = beg; base < end; base += B) {
         if (__syncthreads_count(!done) == 0) break;
         const int cnt = min(B, end - base);
+        const int wofs = __builtin_amdgcn_readfirstlane(base - beg);   // list offset of the batch
         stage<NT, TH>(J.proj, J.ids, base, cnt, sm, qmax, tile_y0);
         staged = base;
         __syncthreads();
-        nl = wave_list<kRecWords>(reinterpret_cast<const uint32_t*>(sm.rec) + kRowsWord, cnt, row_lo, row_hi, L);
+        nl = __builtin_amdgcn_readfirstlane(
+            wave_list<kRecWords>(reinterpret_cast<const uint32_t*>(sm.rec) + kRowsWord, cnt, row_lo, row_hi, L));
         nh = 0;
         if (__ballot(!done) == 0) continue;
         for (int i = 0; i < nl; i += 4) {
@@ -135,9 +139,9 @@ __device__ void render_score_tile(const ViewJob& J, int tile, const potr_config&
                 cg = add_weighted(cg, w, b.w);
                 cb = add_weighted(cb, w, rc[u]);
                 T = stop ? T : Tn;
-                walk = stop ? base - beg + j : walk;
+                walk = stop ? wofs + j : walk;
                 done = done || stop;
-                if (__ballot(al != 0.f && !stop) != 0) {
+                if ((__ballot(al != 0.f) & ~__ballot(stop)) != 0) {
                     if (lane == 0) Hl[nh] = (uint16_t)j;
                     ++nh;
                 }
@@ -193,18 +197,22 @@ __device__ void render_score_tile(const ViewJob& J, int tile, const potr_config&
         // one the blend sweep left in LDS, else those reaching the wave's rows
         const uint16_t* LL = Hl;
         int nv = nh;
+        bool hits = true;
         if (staged != beg + base) {
             __syncthreads();
             stage<NT, TH>(J.proj, J.ids, beg + base, cnt, sm, qmax, tile_y0);
             staged = beg + base;
             __syncthreads();
-            nl = wave_list<kRecWords>(reinterpret_cast<const uint32_t*>(sm.rec) + kRowsWord, cnt, row_lo, row_hi, L);
+            nl = __builtin_amdgcn_readfirstlane(
+                wave_list<kRecWords>(reinterpret_cast<const uint32_t*>(sm.rec) + kRowsWord, cnt, row_lo, row_hi, L));
             nh = 0;
             LL = L;
             nv = nl;
+            hits = false;
         }
         // entries of this wave's list from jlim on lie past every lane's walk
-        const int jlim = min(cnt, wave_walk - base);
+        const int jlim = __builtin_amdgcn_readfirstlane(min(cnt, wave_walk - base));
+        nv = __builtin_amdgcn_readfirstlane(nv);
         for (int i = 0; i < nv; i += 4) {
             int js[4];
             list4(LL, i, js);
@@ -246,8 +254,9 @@ __device__ void render_score_tile(const ViewJob& J, int tile, const potr_config&
                 imv[u] = w;
                 T = next_T(T, al);
             }
-            const bool any = __ballot(imv[0] != 0.f || imv[1] != 0.f || imv[2] != 0.f || imv[3] != 0.f) != 0;
-            if (!any) continue;
+            // an entry of the blended list was blended by some lane, so only a
+            // group of the full list can contribute nothing
+            if (!hits && __ballot(imv[0] != 0.f || imv[1] != 0.f || imv[2] != 0.f || imv[3] != 0.f) == 0) continue;
             // lane u < 4 writes entry js[u] (only entries that are in the list)
             const int jw = lane == 0 ? js[0] : lane == 1 ? js[1] : lane == 2 ? js[2] : js[3];
             const bool writer = lane < ng;

@@ -747,7 +747,7 @@ __global__ __launch_bounds__(kRwThreads) void k_rows(const uint2* __restrict__ s
 // Pair placement, a block per (view, tile row, group): the group's row list (its
 // splats covering the row, in rank order) goes out as pairs, each splat to
 // every tile x0..x1-1 of its run, at the tile's cursor (the group's first
-// position in the tile, from the bin's counts). The list goes by chunks of 256
+// position in the tile, from the bin's counts). The list goes by chunks of 128
 // entries. A chunk's pairs, numbered entry by entry (a block scan of the run
 // widths), are cut into equal consecutive shares, one per thread, so that wide
 // and narrow runs cost every thread alike; each thread walks its share twice.
@@ -760,9 +760,9 @@ __global__ __launch_bounds__(kRwThreads) void k_rows(const uint2* __restrict__ s
 // and chunks within the list, so every tile's run of the group stays in rank
 // order. Blocks of group 0 also write the row's tile ranges, [0, 0) when empty
 // and all empty when the pairs exceed the capacity.
-constexpr int kPcThreads = 256;
+constexpr int kPcThreads = 128;
 constexpr int kPcWaves = kPcThreads / 64;
-constexpr int kPcStage = 2048;   // pairs of a chunk staged for the coalesced write-out
+constexpr int kPcStage = 1024;   // pairs of a chunk staged for the coalesced write-out
 
 // The entry of a chunk whose pairs hold pair q: the largest i with pst[i] <= q
 // (pst: the entries' first pairs, nondecreasing from pst[0] = 0).
@@ -1032,8 +1032,8 @@ size_t gc_lds(int band, int tiles_x, int tiles_y) {
 
 // LDS of the placement: per wave and tile column a 64-bit mask and a first
 // place, a cursor and a first staging slot per column, per chunk entry its id,
-// run and first pair, and the staged ids and places (24.5 KB at 100 columns,
-// 131 KB at 2048)
+// run and first pair, and the staged ids and places (12.6 KB at 100 columns,
+// 73.5 KB at 2048)
 size_t place_lds(const Bins& B) {
     return (size_t)B.tiles_x * (kPcWaves * 8 + kPcWaves * 4 + 4 + 4) + 3 * kPcThreads * 4 + kPcWaves * 4 +
            2 * (size_t)kPcStage * 4;
