@@ -808,7 +808,7 @@ __global__ __launch_bounds__(kPcThreads) void k_place(const uint2* __restrict__ 
     uint32_t* wsum = pst + kPcThreads;                                   // [kPcWaves]
     uint32_t* cst = wsum + kPcWaves;                                     // [TX] the columns' first staged slots
     uint32_t* sid = cst + TX;                                            // [kPcStage] staged splat ids
-    uint32_t* sdst = sid + kPcStage;                                     // [kPcStage] and their places
+    uint16_t* scol = reinterpret_cast<uint16_t*>(sid + kPcStage);       // [kPcStage] and their columns
     // workgroups go to the 8 XCDs round-robin by linear id: block b runs on XCD
     // b % 8, and XCD x takes the tile rows x, x + 8, ... with all their groups in
     // rank order, so every tile's list (the runs of all the groups, one after
@@ -908,9 +908,10 @@ __global__ __launch_bounds__(kPcThreads) void k_place(const uint2* __restrict__ 
             carry += all;
         }
         __syncthreads();
-        // the chunk's ids go out in place order: staged in LDS by (column, place),
-        // then copied to consecutive addresses per column; a chunk of more pairs
-        // than the staging holds writes every id at its place directly
+        // the chunk's ids go out in place order: staged in LDS by (column, place)
+        // with their columns, then copied to consecutive addresses per column; a
+        // chunk of more pairs than the staging holds writes every id at its place
+        // directly
         const bool staged = np <= (uint32_t)kPcStage;
         {
             int i = i0;
@@ -922,7 +923,7 @@ __global__ __launch_bounds__(kPcThreads) void k_place(const uint2* __restrict__ 
                 if (staged) {
                     const uint32_t slot = cst[x] + (dst - wbase[x]);
                     sid[slot] = eid[i];
-                    sdst[slot] = dst;
+                    scol[slot] = (uint16_t)x;
                 } else {
                     ids[dst] = eid[i];
                 }
@@ -931,7 +932,10 @@ __global__ __launch_bounds__(kPcThreads) void k_place(const uint2* __restrict__ 
         }
         if (staged) {
             __syncthreads();
-            for (uint32_t o = (uint32_t)t; o < np; o += kPcThreads) ids[sdst[o]] = sid[o];
+            for (uint32_t o = (uint32_t)t; o < np; o += kPcThreads) {
+                const int x = scol[o];
+                ids[wbase[x] + (o - cst[x])] = sid[o];
+            }
         }
     }
 }
@@ -1032,11 +1036,11 @@ size_t gc_lds(int band, int tiles_x, int tiles_y) {
 
 // LDS of the placement: per wave and tile column a 64-bit mask and a first
 // place, a cursor and a first staging slot per column, per chunk entry its id,
-// run and first pair, and the staged ids and places (12.6 KB at 100 columns,
-// 73.5 KB at 2048)
+// run and first pair, and the staged ids and their columns (10.6 KB at 100
+// columns, 71.5 KB at 2048)
 size_t place_lds(const Bins& B) {
     return (size_t)B.tiles_x * (kPcWaves * 8 + kPcWaves * 4 + 4 + 4) + 3 * kPcThreads * 4 + kPcWaves * 4 +
-           2 * (size_t)kPcStage * 4;
+           (size_t)kPcStage * 6;
 }
 
 
