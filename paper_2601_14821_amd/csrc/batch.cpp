@@ -325,9 +325,12 @@ potr_status potr_batch_run(potr_batch b, void* stream) {
         uint32_t* order = (uint32_t*)(ws + L.order);
         uint32_t* ids = (uint32_t*)(ws + b->off[j].ids);
         int32_t* ranges = (int32_t*)(ws + b->off[j].ranges);
+        // the projection also writes the bin's depth keys and rects
+        const BinKeys bk = bin_keys(J.N, J.V, cams[0], b->cfg, ws + L.bin);
         potr_status st =
-            launch_project(J.N, J.V, cams, b->cfg, J.means, J.scales, J.quats, J.opac, J.sh, proj, tt, ls);
-        if (st == POTR_OK) st = launch_bin(J.N, J.V, cams[0], b->cfg, proj, ws + L.bin, order, npairs + j, ls);
+            launch_project(J.N, J.V, cams, b->cfg, J.means, J.scales, J.quats, J.opac, J.sh, proj, tt, ls, &bk);
+        if (st == POTR_OK)
+            st = launch_bin(J.N, J.V, cams[0], b->cfg, proj, ws + L.bin, order, npairs + j, ls, true);
         if (st == POTR_OK)
             st = launch_sort(J.N, J.V, cams[0], b->cfg, proj, order, ws + L.bin, npairs + j, b->capacity[j],
                              ws + L.stage, ids, ranges, ls);

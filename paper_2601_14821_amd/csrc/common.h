@@ -28,13 +28,29 @@ potr_status fail(potr_status st, const char* fmt, ...);
 potr_status check_launch(const char* what);
 
 // ---- launchers (defined in the .hip files) ----
+struct BinKeys;
+// keys (optional): also write the bin's keys, rects and key-range partials there
 potr_status launch_project(int64_t N, int32_t V, const potr_camera* cams, const potr_config& cfg,
                            const float* means, const float* scales, const float* quats, const float* opac,
-                           const float* sh, potr_proj* proj, int32_t* tiles_touched, hipStream_t s);
+                           const float* sh, potr_proj* proj, int32_t* tiles_touched, hipStream_t s,
+                           const BinKeys* keys = nullptr);
 
 size_t bin_workspace_bytes(int64_t N, int32_t V, int32_t tiles_x, int32_t tiles_y);
+// Where a projection launch can write, in a bin workspace, what the bin's first
+// kernel would otherwise take from the records: per (view, splat) the depth key
+// (its FP32 bits) and the packed rect (x0 | x1 << 16, y0 | y1 << 16), and per
+// (view, wave of 64 splats) the wave's largest key and largest complemented key.
+struct BinKeys {
+    uint32_t* keys;
+    uint2* rects;
+    uint2* part;
+    int64_t per_view;   // partials per view: ceil(N / 64)
+};
+BinKeys bin_keys(int64_t N, int32_t V, const potr_camera& cam0, const potr_config& cfg, void* ws);
+// keys_ready: the launch_project before this call wrote bin_keys(...) of this workspace
 potr_status launch_bin(int64_t N, int32_t V, const potr_camera& cam0, const potr_config& cfg,
-                       const potr_proj* proj, void* ws, uint32_t* order, int64_t* n_pairs, hipStream_t s);
+                       const potr_proj* proj, void* ws, uint32_t* order, int64_t* n_pairs, hipStream_t s,
+                       bool keys_ready = false);
 size_t sort_workspace_bytes(int64_t capacity);
 potr_status launch_sort(int64_t N, int32_t V, const potr_camera& cam0, const potr_config& cfg,
                         const potr_proj* proj, const uint32_t* order, void* ws, const int64_t* n_pairs,

@@ -32,14 +32,19 @@ constexpr int kShStride = 13;   // float4 per splat in LDS (12 used)
 // DEG: the SH degree in use (0..3), a template argument so that the colour sum
 // is fully unrolled with every coefficient and basis value in a register.
 // STAGED: SH coefficients staged in LDS (launches of several views).
-template <int DEG, bool STAGED>
+// KEYS: also write the bin's depth keys, packed rects and per-wave key-range
+// partials (BinKeys); every lane of a wave then stays to the end (a lane past
+// the last splat repeats the last one and stores nothing), for the wave's max.
+template <int DEG, bool STAGED, bool KEYS>
 __global__ __launch_bounds__(kProjThreads) void k_project(int64_t N, int32_t v0, int32_t nv, CamBatch cams, Lims lims,
                                                  potr_config cfg, const float* __restrict__ means,
                                                  const float* __restrict__ scales, const float* __restrict__ quats,
                                                  const float* __restrict__ opac, const float* __restrict__ sh,
-                                                 potr_proj* __restrict__ proj, int32_t* __restrict__ tiles_touched) {
+                                                 potr_proj* __restrict__ proj, int32_t* __restrict__ tiles_touched,
+                                                 BinKeys bk) {
     const int64_t i0 = (int64_t)blockIdx.x * kProjThreads;
-    const int64_t i = i0 + threadIdx.x;
+    const bool live = i0 + threadIdx.x < N;
+    const int64_t i = live ? i0 + threadIdx.x : N - 1;
     const float4* sh4;   // this splat's coefficients, 16 bytes at a time
     if constexpr (STAGED) {
         __shared__ float4 s_sh[kProjThreads * kShStride];
@@ -52,11 +57,11 @@ __global__ __launch_bounds__(kProjThreads) void k_project(int64_t N, int32_t v0,
             s_sh[t * kShStride + m] = g4[t * 12 + m];
         }
         __syncthreads();
-        sh4 = s_sh + threadIdx.x * kShStride;
+        sh4 = s_sh + (live ? threadIdx.x : i - i0) * kShStride;
     } else {
         sh4 = reinterpret_cast<const float4*>(sh) + 12 * i;
     }
-    if (i >= N) return;
+    if (!KEYS && !live) return;
 
     const float mx = means[3 * i], my = means[3 * i + 1], mz = means[3 * i + 2];
     const double o = opac[i];
@@ -186,8 +191,27 @@ __global__ __launch_bounds__(kProjThreads) void k_project(int64_t N, int32_t v0,
                 }
             }
         }
-        proj[out] = rec;
-        tiles_touched[out] = ntiles;
+        if (live) {
+            proj[out] = rec;
+            tiles_touched[out] = ntiles;
+        }
+        if constexpr (KEYS) {
+            const uint32_t key = __float_as_uint(rec.depth);
+            if (live) {
+                bk.keys[out] = key;
+                bk.rects[out] = make_uint2((uint32_t)(uint16_t)rec.rect[0] | ((uint32_t)(uint16_t)rec.rect[2] << 16),
+                                           (uint32_t)(uint16_t)rec.rect[1] | ((uint32_t)(uint16_t)rec.rect[3] << 16));
+            }
+            uint32_t hi = key, lo = ~key;   // a repeated last splat leaves the maxima unchanged
+#pragma unroll
+            for (int m = 32; m >= 1; m >>= 1) {
+                hi = max(hi, (uint32_t)__shfl_xor((int)hi, m, 64));
+                lo = max(lo, (uint32_t)__shfl_xor((int)lo, m, 64));
+            }
+            // lane 0 of every wave that holds a splat (a wave wholly past N has none)
+            if ((threadIdx.x & 63) == 0 && i0 + threadIdx.x < N)
+                bk.part[(int64_t)(v0 + vv) * bk.per_view + (i0 + threadIdx.x) / 64] = make_uint2(hi, lo);
+        }
     }
 }
 
@@ -195,7 +219,8 @@ __global__ __launch_bounds__(kProjThreads) void k_project(int64_t N, int32_t v0,
 
 potr_status launch_project(int64_t N, int32_t V, const potr_camera* cams, const potr_config& cfg,
                            const float* means, const float* scales, const float* quats, const float* opac,
-                           const float* sh, potr_proj* proj, int32_t* tiles_touched, hipStream_t s) {
+                           const float* sh, potr_proj* proj, int32_t* tiles_touched, hipStream_t s,
+                           const BinKeys* keys) {
     if (N == 0) return POTR_OK;
     const dim3 grid((unsigned)ceil_div(N, kProjThreads));
     for (int32_t v0 = 0; v0 < V; v0 += kViewsPerLaunch) {
@@ -209,15 +234,20 @@ potr_status launch_project(int64_t N, int32_t V, const potr_camera* cams, const 
             lm.y[k] = (double)cfg.jclamp * 0.5 * cb.c[k].height / (double)cb.c[k].fy;
         }
         const bool staged = nv > 1;
+        const BinKeys bk = keys ? *keys : BinKeys{nullptr, nullptr, nullptr, 0};
         auto go = [&](auto kern) {
             hipLaunchKernelGGL(kern, grid, dim3(kProjThreads), 0, s, N, v0, nv, cb, lm, cfg, means, scales, quats, opac,
-                               sh, proj, tiles_touched);
+                               sh, proj, tiles_touched, bk);
+        };
+        auto pick = [&](auto k_st_keys, auto k_st, auto k_keys, auto k_plain) {
+            if (keys) staged ? go(k_st_keys) : go(k_keys);
+            else staged ? go(k_st) : go(k_plain);
         };
         switch (cfg.sh_degree) {
-            case 0: staged ? go(k_project<0, true>) : go(k_project<0, false>); break;
-            case 1: staged ? go(k_project<1, true>) : go(k_project<1, false>); break;
-            case 2: staged ? go(k_project<2, true>) : go(k_project<2, false>); break;
-            default: staged ? go(k_project<3, true>) : go(k_project<3, false>); break;
+            case 0: pick(k_project<0, true, true>, k_project<0, true, false>, k_project<0, false, true>, k_project<0, false, false>); break;
+            case 1: pick(k_project<1, true, true>, k_project<1, true, false>, k_project<1, false, true>, k_project<1, false, false>); break;
+            case 2: pick(k_project<2, true, true>, k_project<2, true, false>, k_project<2, false, true>, k_project<2, false, false>); break;
+            default: pick(k_project<3, true, true>, k_project<3, true, false>, k_project<3, false, true>, k_project<3, false, false>); break;
         }
         potr_status st = check_launch("k_project");
         if (st != POTR_OK) return st;

@@ -145,6 +145,38 @@ __global__ __launch_bounds__(kHistThreads) void k_keys(const potr_proj* __restri
     }
 }
 
+// The key range of every view from the per-wave partials a projection launch
+// left (largest key, largest complemented key per wave of 64 splats; see
+// BinKeys): a grid of (blocks, view), each folding a stride of the partials.
+__global__ __launch_bounds__(kHistThreads) void k_krange(const uint2* __restrict__ part, int64_t per_view,
+                                                        uint32_t* __restrict__ krange) {
+    __shared__ uint32_t s_hi, s_lo;
+    if (threadIdx.x == 0) s_hi = s_lo = 0u;
+    __syncthreads();
+    const int v = blockIdx.y;
+    uint32_t hi = 0u, lo = 0u;
+    for (int64_t k = (int64_t)blockIdx.x * kHistThreads + threadIdx.x; k < per_view;
+         k += (int64_t)gridDim.x * kHistThreads) {
+        const uint2 q = part[(int64_t)v * per_view + k];
+        hi = max(hi, q.x);
+        lo = max(lo, q.y);
+    }
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) {
+        hi = max(hi, (uint32_t)__shfl_xor((int)hi, m, 64));
+        lo = max(lo, (uint32_t)__shfl_xor((int)lo, m, 64));
+    }
+    if ((threadIdx.x & 63) == 0) {
+        atomicMax(&s_hi, hi);
+        atomicMax(&s_lo, lo);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        atomicMax(krange + 2 * v, s_hi);
+        atomicMax(krange + 2 * v + 1, s_lo);
+    }
+}
+
 // Radix passes needed for the offsets key - min of one view: 8 bits each, at
 // least one (which then also writes the identity order of equal keys).
 __device__ inline int passes_of(const uint32_t* krange, int v, uint32_t& kmin) {
@@ -972,6 +1004,7 @@ struct BinWs {
     Ctl ctl;
     uint32_t *ka, *kb, *va, *vb;
     uint2 *crect, *srect;   // rects by splat id, and in depth order
+    uint2* kpart;           // per (view, wave of 64 splats) key-range partials of a fused projection
     uint32_t *gsum, *rtot;
     int64_t* rbase;
     uint32_t *tc, *toff, *segt, *trel;
@@ -996,6 +1029,7 @@ BinWs bin_layout(int64_t N, int32_t V, int32_t tiles_x, int32_t tiles_y, char* b
     w.segt = (uint32_t*)take(4 * (size_t)V * B.nseg_g * T);
     w.ctl.clear_words = (int64_t)(o / 8);
     w.ctl.offs = (uint32_t*)take(4 * (size_t)V * bps * 256);
+    w.kpart = (uint2*)take(8 * (size_t)V * (size_t)ceil_div(N > 0 ? N : 1, 64));
     w.ka = (uint32_t*)take(4 * VN);
     w.kb = (uint32_t*)take(4 * VN);
     w.va = (uint32_t*)take(4 * VN);
@@ -1054,8 +1088,14 @@ size_t bin_workspace_bytes(int64_t N, int32_t V, int32_t tiles_x, int32_t tiles_
 // per pair, so `capacity` entries always suffice.
 size_t sort_workspace_bytes(int64_t capacity) { return align_up((size_t)(capacity > 0 ? capacity : 1) * 8); }
 
+BinKeys bin_keys(int64_t N, int32_t V, const potr_camera& cam0, const potr_config& cfg, void* ws) {
+    const BinWs w = bin_layout(N, V, tiles_x(cam0, cfg), tiles_y(cam0, cfg), (char*)ws);
+    return BinKeys{w.ka, w.crect, w.kpart, ceil_div(N > 0 ? N : 1, 64)};
+}
+
 potr_status launch_bin(int64_t N, int32_t V, const potr_camera& cam0, const potr_config& cfg,
-                       const potr_proj* proj, void* ws, uint32_t* order, int64_t* n_pairs, hipStream_t s) {
+                       const potr_proj* proj, void* ws, uint32_t* order, int64_t* n_pairs, hipStream_t s,
+                       bool keys_ready) {
     const int txs = tiles_x(cam0, cfg), tys = tiles_y(cam0, cfg);
     BinWs w = bin_layout(N, V, txs, tys, (char*)ws);
     const Bins B = bins_of(N, V, txs, tys);
@@ -1068,8 +1108,16 @@ potr_status launch_bin(int64_t N, int32_t V, const potr_camera& cam0, const potr
         // 8-bit passes as the view's span of keys needs (the rest return at once)
         Seg g{N, nullptr, 0, (int32_t)ceil_div(N, kTile)};
         const dim3 kg((unsigned)ceil_div(N, kHistThreads * kHistItems), V);
-        hipLaunchKernelGGL(k_keys, kg, dim3(kHistThreads), 0, s, proj, N, w.ka, w.crect, w.ctl.krange);
-        st = check_launch("k_keys");
+        if (keys_ready) {
+            // keys and rects written by the projection: only the key range is left
+            const int64_t pv = ceil_div(N, 64);
+            const dim3 kr((unsigned)std::min<int64_t>(64, ceil_div(pv, kHistThreads)), V);
+            hipLaunchKernelGGL(k_krange, kr, dim3(kHistThreads), 0, s, (const uint2*)w.kpart, pv, w.ctl.krange);
+            st = check_launch("k_krange");
+        } else {
+            hipLaunchKernelGGL(k_keys, kg, dim3(kHistThreads), 0, s, proj, N, w.ka, w.crect, w.ctl.krange);
+            st = check_launch("k_keys");
+        }
         if (st != POTR_OK) return st;
         hipLaunchKernelGGL(k_digits, kg, dim3(kHistThreads), 0, s, (const uint32_t*)w.ka, N,
                            (const uint32_t*)w.ctl.krange, w.ctl.ghist);
