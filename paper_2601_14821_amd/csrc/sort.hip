@@ -870,11 +870,13 @@ __global__ __launch_bounds__(kPcThreads) void k_place(const uint2* __restrict__ 
     const int cnt = (int)(end - beg);
     const uint32_t* orow = off + ((int64_t)v * B.G + g) * B.T + (int64_t)y * TX;
     for (int x = t; x < TX; x += kPcThreads) cur[x] = orow[x];
+    uint2 en = t < cnt ? rows[beg + t] : make_uint2(0u, 0u);   // this thread's entry of the first chunk
     for (int c0 = 0; c0 < cnt; c0 += kPcThreads) {
         __syncthreads();   // the cursors are set, and the last chunk is done with every array
         for (int i = t; i < kPcWaves * TX; i += kPcThreads) mask[i] = 0ull;
-        const bool valid = c0 + t < cnt;
-        const uint2 e = valid ? rows[beg + c0 + t] : make_uint2(0u, 0u);
+        const uint2 e = en;
+        // the next chunk's entry, in flight while this chunk is placed
+        if (c0 + kPcThreads < cnt) en = c0 + kPcThreads + t < cnt ? rows[beg + c0 + kPcThreads + t] : make_uint2(0u, 0u);
         const uint32_t ex0 = e.y & 0xffffu, ex1 = e.y >> 16;
         const uint32_t wd = ex1 > ex0 ? ex1 - ex0 : 0u;
         eid[t] = e.x;
