@@ -313,7 +313,7 @@ def timed(torch, fn, reps, warm=1):
     return (time.perf_counter() - t0) * 1000.0 / reps
 
 
-def multi_scene_section(torch, raster, synth, batch):
+def multi_scene_section(torch, raster, synth, batch, views_per_job=8):
     """16 scenes of uneven size (50 k..2 M splats, 8..32 views, three image sizes) scored
     in one batch: the autotuner picks tile shape and LDS batch on the whole batch, then
     per-job project/bin/sort and one persistent render + removal launch are replayed as
@@ -323,9 +323,9 @@ def multi_scene_section(torch, raster, synth, batch):
     for scene, cams in work:
         ds = raster.to_device(scene)
         items.append((ds, cams, torch.zeros(scene.n, device="cuda")))
-    s, tune = batch.autotune(items, synth.RenderSettings(), reps=1)
+    s, tune = batch.autotune(items, synth.RenderSettings(), reps=1, views_per_job=views_per_job)
     torch.cuda.empty_cache()
-    bs = batch.BatchScorer(items, s, views_per_job=8)
+    bs = batch.BatchScorer(items, s, views_per_job=views_per_job)
     bs.capture()
 
     def replay():
@@ -344,7 +344,7 @@ def multi_scene_section(torch, raster, synth, batch):
     torch.cuda.empty_cache()
     return {"workload": f"{len(work)} clustered scenes, {ns} splats in all (50k..2M log-uniform), {nv} views "
                         f"(8..32 per scene) at 640x480, 1280x720 and 1600x1064",
-            "autotuned": f"{s.tile_w}x{s.tile_h} tiles, LDS batch {s.lds_batch}",
+            "autotuned": f"{s.tile_w}x{s.tile_h} tiles, LDS batch {s.lds_batch}", "views_per_job": views_per_job,
             "autotune_ms": {f"{c['tile']}/{c['lds_batch']}": round(c["ms"], 2) for c in tune["tried"]},
             "ms_per_batch": round(ms, 3), "ms_per_view": round(ms / nv, 4),
             "gsplat_views_per_s": round(sv / (ms / 1000.0) / 1e9, 4),
@@ -403,6 +403,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--views-per-job", type=int, default=VIEWS_PER_JOB,
                     help="views per batch job on the main line (project, bin and sort run per job)")
+    ap.add_argument("--multi-views-per-job", type=int, default=8,
+                    help="views per batch job in the uneven multi-scene section")
     ap.add_argument("--main-only", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 256 MiB device copy (reference for hardware byte counters)")
@@ -420,7 +422,7 @@ def main():
 
     if args.profile_section:
         fn = {"single_view": lambda: single_view_section(args, torch, raster, synth),
-              "multi_scene": lambda: multi_scene_section(torch, raster, synth, batch),
+              "multi_scene": lambda: multi_scene_section(torch, raster, synth, batch, args.multi_views_per_job),
               "fwd_bwd": lambda: fwd_bwd_section(torch, raster, synth, autograd, batch)}[args.profile_section]
         log(args.profile_section)
         print(json.dumps({args.profile_section: fn()}), flush=True)
@@ -457,7 +459,7 @@ def main():
         log("single view")
         out["single_view"] = single_view_section(args, torch, raster, synth)
         log("multi scene")
-        out["multi_scene"] = multi_scene_section(torch, raster, synth, batch)
+        out["multi_scene"] = multi_scene_section(torch, raster, synth, batch, args.multi_views_per_job)
         log("forward + backward")
         out["fwd_bwd"] = fwd_bwd_section(torch, raster, synth, autograd, batch)
     if not args.no_cpu_baseline:

@@ -43,6 +43,7 @@ struct potr_batch_s {
     size_t off_table = 0, off_prefix = 0, off_counter = 0, off_npairs = 0, off_caps = 0, off_flag = 0;
     size_t bytes = 0;
     int32_t n_view_jobs = 0;
+    int64_t n_items = 0;    // (view, tile) items of the render launch (none: no job asks for outputs)
     int32_t grid = 0;
     bool with_se = false;   // some job asks for dSE sums
     int n_out = 1;          // the most per-splat outputs of any job
@@ -289,6 +290,7 @@ potr_status potr_batch_bind(potr_batch b, void* ws, size_t ws_bytes, void* strea
     }
     if (prefix.back() >= (int64_t(1) << 40))
         return fail(POTR_EINVAL, "%lld (view, tile) items in one batch", (long long)prefix.back());
+    b->n_items = prefix.back();
     hipStream_t s = (hipStream_t)stream;
     potr_status st = hip_ok(hipMemcpyAsync(b->ws + b->off_table, table.data(), table.size() * sizeof(ViewJob),
                                            hipMemcpyHostToDevice, s), "upload job table");
@@ -360,11 +362,13 @@ potr_status potr_batch_run(potr_batch b, void* stream) {
         if (st == POTR_OK) st = hip_ok(hipStreamWaitEvent(s, b->lane_ev[1 + l], 0), "join wait");
         if (st != POTR_OK) return st;
     }
-    potr_status st = launch_render_score_persistent((const ViewJob*)(ws + b->off_table), b->n_view_jobs,
-                                                    (const int64_t*)(ws + b->off_prefix),
-                                                    (int64_t*)(ws + b->off_counter), b->grid, b->cfg,
-                                                    b->with_se, b->n_out, s);
-    if (st != POTR_OK) return st;
+    if (b->n_items > 0) {
+        potr_status st = launch_render_score_persistent((const ViewJob*)(ws + b->off_table), b->n_view_jobs,
+                                                        (const int64_t*)(ws + b->off_prefix),
+                                                        (int64_t*)(ws + b->off_counter), b->grid, b->cfg,
+                                                        b->with_se, b->n_out, s);
+        if (st != POTR_OK) return st;
+    }
     return launch_check_overflow(npairs, (const int64_t*)(ws + b->off_caps), (int32_t)b->jobs.size(),
                                  (int32_t*)(ws + b->off_flag), s);
 }
@@ -372,6 +376,7 @@ potr_status potr_batch_run(potr_batch b, void* stream) {
 potr_status potr_batch_render(potr_batch b, void* stream) {
     if (!b || !b->ws) return fail(POTR_EINVAL, "batch not bound to a workspace");
     char* ws = b->ws;
+    if (b->n_items == 0) return POTR_OK;   // no job asks for outputs
     return launch_render_score_persistent((const ViewJob*)(ws + b->off_table), b->n_view_jobs,
                                           (const int64_t*)(ws + b->off_prefix), (int64_t*)(ws + b->off_counter),
                                           b->grid, b->cfg, b->with_se, b->n_out, (hipStream_t)stream);
