@@ -941,34 +941,55 @@ __global__ __launch_bounds__(kPcThreads) void k_place(const uint2* __restrict__ 
             if (x < TX) cst[x] = pre + inc - cn;
             carry += all;
         }
-        __syncthreads();
         // the chunk's ids go out in place order: staged in LDS by (column, place)
         // with their columns, then copied to consecutive addresses per column; a
         // chunk of more pairs than the staging holds writes every id at its place
-        // directly
-        const bool staged = np <= (uint32_t)kPcStage;
+        // directly. Staged: each (wave, column) base becomes its first staging slot,
+        // and each column's first slot the difference place - slot of its pairs, so
+        // that a pair needs one LDS round trip and a copy one more
+        const bool staged = carry <= (uint32_t)kPcStage;
+        if (staged) {
+            for (int x = t; x < TX; x += kPcThreads) {
+                const uint32_t c0 = wbase[x], s0 = cst[x];
+#pragma unroll
+                for (int ww = 0; ww < kPcWaves; ++ww) wbase[ww * TX + x] = s0 + (wbase[ww * TX + x] - c0);
+                cst[x] = c0 - s0;
+            }
+        }
+        __syncthreads();
         {
             int i = i0;
             uint32_t x = x0, xe = xe0;
             for (uint32_t q = q0; q < q1; ++q) {
                 const int s = (i >> 6) * TX + (int)x;
                 const uint64_t below = (1ull << (i & 63)) - 1ull;
-                const uint32_t dst = wbase[s] + (uint32_t)__popcll(mask[s] & below);
+                const uint32_t at = wbase[s] + (uint32_t)__popcll(mask[s] & below);   // staging slot, or place
                 if (staged) {
-                    const uint32_t slot = cst[x] + (dst - wbase[x]);
-                    sid[slot] = eid[i];
-                    scol[slot] = (uint16_t)x;
+                    sid[at] = eid[i];
+                    scol[at] = (uint16_t)x;
                 } else {
-                    ids[dst] = eid[i];
+                    ids[at] = eid[i];
                 }
                 if (++x == xe && q + 1 < q1) i = next_run(ecol, i, x, xe);
             }
         }
         if (staged) {
             __syncthreads();
-            for (uint32_t o = (uint32_t)t; o < np; o += kPcThreads) {
-                const int x = scol[o];
-                ids[wbase[x] + (o - cst[x])] = sid[o];
+            // four copies in flight per thread
+            for (uint32_t o0 = (uint32_t)t; o0 < np; o0 += 4 * kPcThreads) {
+                uint32_t xs[4], vs[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const uint32_t o = o0 + u * kPcThreads;
+                    xs[u] = o < np ? scol[o] : 0u;
+                    vs[u] = o < np ? sid[o] : 0u;
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const uint32_t o = o0 + u * kPcThreads;
+                    const uint32_t d = cst[xs[u]];
+                    if (o < np) ids[o + d] = vs[u];
+                }
             }
         }
     }
