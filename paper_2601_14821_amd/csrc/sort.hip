@@ -672,7 +672,7 @@ constexpr int kRwThreads = 1024;
 constexpr int kRwItems = kGroupRanks / kRwThreads;   // ranks per thread (rank = slot * 1024 + thread)
 constexpr int kRwSlots = kRwItems * (kRwThreads / 64);   // (slot, wave) pairs, in rank order
 constexpr int kRwPer = kRwSlots / 64;                      // of them per lane in the per-row scan
-constexpr int kRwBand = 4096 / kRwSlots;                  // rows per band (48 KB of masks and places)
+constexpr int kRwBand = 4096 / kRwSlots;                  // rows per band (~49 KB of masks and places)
 static_assert(kRwSlots % 64 == 0, "the per-row scan gives each lane whole (slot, wave) pairs");
 
 // 64x64 bit-matrix transpose over a wave: lane i's word is row i; on return
@@ -702,8 +702,10 @@ __global__ __launch_bounds__(kRwThreads) void k_rows(const uint2* __restrict__ s
                                                     const int64_t* __restrict__ rlbase, Bins B,
                                                     const int64_t* __restrict__ n_pairs, int64_t capacity,
                                                     uint2* __restrict__ rows) {
-    __shared__ uint64_t mask[kRwBand][kRwSlots];
-    __shared__ uint32_t wb[kRwBand][kRwSlots];
+    // rows padded by one word: the lanes of a wave index rows with a common slot,
+    // so an unpadded power-of-two row stride would put them all in one LDS bank
+    __shared__ uint64_t mask[kRwBand][kRwSlots + 1];
+    __shared__ uint32_t wb[kRwBand][kRwSlots + 1];
     __shared__ int64_t rbeg[kRwBand];
     const int g = blockIdx.x, v = blockIdx.y;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
