@@ -35,7 +35,7 @@ struct potr_batch_s {
     // jobs run in lanes (job j in lane j % lanes): each lane has its own scratch
     // (tiles_touched, depth order, bin and sort workspaces) and, with more than
     // one lane, its own stream, forked from and joined back into the caller's
-    struct LaneOff { size_t tt, order, bin, stage, pix, g2d; };   // pix, g2d: fine-tuning scratch
+    struct LaneOff { size_t order, bin, stage, pix, g2d; };   // pix, g2d: fine-tuning scratch
     std::vector<LaneOff> lane_off;
     std::vector<size_t> lane_of;       // the lane of each job
     std::vector<hipStream_t> lane_s;
@@ -66,7 +66,7 @@ potr_status hip_ok(hipError_t e, const char* what) {
 void plan_layout(potr_batch_s* b) {
     size_t o = 0;
     auto take = [&](size_t n) { size_t r = o; o += align_up(n > 0 ? n : 1); return r; };
-    size_t max_tt = 0, max_bin = 0, max_stage = 0, max_pix = 0, max_g2d = 0;
+    size_t max_vn = 0, max_bin = 0, max_stage = 0, max_pix = 0, max_g2d = 0;
     b->off.resize(b->jobs.size());
     b->n_view_jobs = 0;
     for (size_t j = 0; j < b->jobs.size(); ++j) {
@@ -75,7 +75,7 @@ void plan_layout(potr_batch_s* b) {
         b->off[j].proj = take((size_t)J.V * J.N * sizeof(potr_proj));
         b->off[j].ids = take((size_t)b->capacity[j] * 4);
         b->off[j].ranges = take((size_t)J.V * T * 2 * 4);
-        max_tt = std::max(max_tt, (size_t)J.V * J.N * 4);
+        max_vn = std::max(max_vn, (size_t)J.V * J.N * 4);
         max_bin = std::max(max_bin, bin_workspace_bytes(J.N, J.V, tiles_x(b->cams[j][0], b->cfg),
                                                          tiles_y(b->cams[j][0], b->cfg)));
         max_stage = std::max(max_stage, sort_workspace_bytes(b->capacity[j]));
@@ -106,8 +106,7 @@ void plan_layout(potr_batch_s* b) {
         }
     }
     for (auto& L : b->lane_off) {
-        L.tt = take(max_tt);
-        L.order = take(max_tt);
+        L.order = take(max_vn);
         L.bin = take(max_bin);
         L.stage = take(max_stage);
         L.pix = take(max_pix);
@@ -323,14 +322,13 @@ potr_status potr_batch_run(potr_batch b, void* stream) {
         const size_t lane = b->lane_of[j];
         const auto& L = b->lane_off[lane];
         const hipStream_t ls = b->lane_s.empty() ? s : b->lane_s[lane];
-        int32_t* tt = (int32_t*)(ws + L.tt);
         uint32_t* order = (uint32_t*)(ws + L.order);
         uint32_t* ids = (uint32_t*)(ws + b->off[j].ids);
         int32_t* ranges = (int32_t*)(ws + b->off[j].ranges);
         // the projection also writes the bin's depth keys and rects
         const BinKeys bk = bin_keys(J.N, J.V, cams[0], b->cfg, ws + L.bin);
         potr_status st =
-            launch_project(J.N, J.V, cams, b->cfg, J.means, J.scales, J.quats, J.opac, J.sh, proj, tt, ls, &bk);
+            launch_project(J.N, J.V, cams, b->cfg, J.means, J.scales, J.quats, J.opac, J.sh, proj, nullptr, ls, &bk);
         if (st == POTR_OK)
             st = launch_bin(J.N, J.V, cams[0], b->cfg, proj, ws + L.bin, order, npairs + j, ls, true);
         if (st == POTR_OK)

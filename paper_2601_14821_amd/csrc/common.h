@@ -29,7 +29,8 @@ potr_status check_launch(const char* what);
 
 // ---- launchers (defined in the .hip files) ----
 struct BinKeys;
-// keys (optional): also write the bin's keys, rects and key-range partials there
+// keys (optional): also write the bin's keys, rects and key-range partials there;
+// tiles_touched may be NULL (not written)
 potr_status launch_project(int64_t N, int32_t V, const potr_camera* cams, const potr_config& cfg,
                            const float* means, const float* scales, const float* quats, const float* opac,
                            const float* sh, potr_proj* proj, int32_t* tiles_touched, hipStream_t s,

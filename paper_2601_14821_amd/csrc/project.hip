@@ -193,7 +193,7 @@ __global__ __launch_bounds__(kProjThreads) void k_project(int64_t N, int32_t v0,
         }
         if (live) {
             proj[out] = rec;
-            tiles_touched[out] = ntiles;
+            if (tiles_touched) tiles_touched[out] = ntiles;
         }
         if constexpr (KEYS) {
             const uint32_t key = __float_as_uint(rec.depth);

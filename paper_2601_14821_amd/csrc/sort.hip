@@ -11,14 +11,15 @@
 // pair.
 //
 // Every depth radix pass is three wait-free kernels: per block of 4096 keys
-// its digit counts; per (view, digit) a scan of those over the blocks (the
-// blocks' first places); per block a stable rank of its keys by digit (ballots
-// per wave), an LDS sort and coalesced runs out. The passes sort by key - min
-// over the view's keys: a view whose keys span fewer than 2^24 (2^16, 2^8)
-// values needs three (two, one) passes, and the rest return at once. The key
-// range, then the digit totals of the passes needed, come from two reads up
-// front. No kernel waits on another block, so the passes share the chip with
-// kernels on other streams without spinning.
+// its digit counts (also summed into the view's digit totals); per (view,
+// digit) a scan of those over the blocks (the blocks' first places); per block
+// a stable rank of its keys by digit (ballots per wave), an LDS sort and
+// coalesced runs out. The passes sort by key - min over the view's keys: a
+// view whose keys span fewer than 2^24 (2^16, 2^8) values needs three (two,
+// one) passes, and the rest return at once. The key range comes from one read
+// up front (or from the projection that wrote the keys). No kernel waits on
+// another block, so the passes share the chip with kernels on other streams
+// without spinning.
 #include <algorithm>
 
 #include "common.h"
@@ -88,7 +89,7 @@ __device__ inline int64_t seg_n(const Seg& g) {
 
 struct Pass {
     int32_t pass, shift, bits;
-    const uint32_t* ghist;    // this pass's digit totals at ghist[seg * kMaxPasses * 256 + digit]
+    uint32_t* ghist;          // this pass's digit totals at ghist[seg * kMaxPasses * 256 + digit] (cleared, then summed by k_pass_count)
     uint32_t* offs;           // [seg][digit][block]: the block's count, then its first place for the digit
 };
 
@@ -187,36 +188,11 @@ __device__ inline int passes_of(const uint32_t* krange, int v, uint32_t& kmin) {
     return max(1, (bits + 7) / 8);
 }
 
-// Digit totals of the passes a view needs, over the offsets key - min.
-__global__ __launch_bounds__(kHistThreads) void k_digits(const uint32_t* __restrict__ keys, int64_t N,
-                                                        const uint32_t* __restrict__ krange,
-                                                        uint32_t* __restrict__ ghist) {
-    __shared__ uint32_t h[kMaxPasses][256];
-    for (int t = threadIdx.x; t < kMaxPasses * 256; t += kHistThreads) (&h[0][0])[t] = 0;
-    __syncthreads();
-    const int v = blockIdx.y;
-    uint32_t kmin;
-    const int np = passes_of(krange, v, kmin);
-    const int64_t base = (int64_t)v * N;
-    const int64_t e0 = (int64_t)blockIdx.x * (kHistThreads * kHistItems) + threadIdx.x;
-    uint32_t d[kHistItems];
-#pragma unroll
-    for (int k = 0; k < kHistItems; ++k) d[k] = keys[base + min(e0 + (int64_t)k * kHistThreads, N - 1)] - kmin;
-#pragma unroll
-    for (int k = 0; k < kHistItems; ++k)
-        if (e0 + (int64_t)k * kHistThreads < N)
-            for (int p = 0; p < np; ++p) atomicAdd(&h[p][(d[k] >> (8 * p)) & 255u], 1u);
-    __syncthreads();
-    for (int t = threadIdx.x; t < np * 256; t += kHistThreads) {
-        const uint32_t c = (&h[0][0])[t];
-        if (c) atomicAdd(ghist + (int64_t)v * kMaxPasses * 256 + t, c);
-    }
-}
-
 // One stable radix pass over the depth keys of every view, by the digits of
 // key - min, in three wait-free kernels (the view's passes_of decides how many
 // passes it needs; the later ones return at once):
-//   k_pass_count   per block of kTile keys, its count of every digit;
+//   k_pass_count   per block of kTile keys, its count of every digit, also
+//                  added into the view's totals of the digit;
 //   k_pass_scan    per (view, digit), the blocks' first places for the digit
 //                  (the digit's base over the view, plus the counts of the
 //                  blocks before), in place of the counts;
@@ -250,7 +226,9 @@ __global__ __launch_bounds__(256) void k_pass_count(const uint32_t* __restrict__
     for (int k = 0; k < kPcItems; ++k)
         if (blk0 + k * 256 + threadIdx.x < n) atomicAdd(&h[digit_of(key[k] - kmin, P.shift, mask)], 1u);
     __syncthreads();
-    P.offs[((int64_t)seg * 256 + threadIdx.x) * g.bps + b] = h[threadIdx.x];
+    const uint32_t c = h[threadIdx.x];
+    P.offs[((int64_t)seg * 256 + threadIdx.x) * g.bps + b] = c;
+    if (c) atomicAdd(P.ghist + (int64_t)seg * kMaxPasses * 256 + threadIdx.x, c);   // the view's digit totals
 }
 
 __global__ __launch_bounds__(256) void k_pass_scan(Seg g, Pass P, const uint32_t* __restrict__ krange) {
@@ -1143,10 +1121,6 @@ potr_status launch_bin(int64_t N, int32_t V, const potr_camera& cam0, const potr
             hipLaunchKernelGGL(k_keys, kg, dim3(kHistThreads), 0, s, proj, N, w.ka, w.crect, w.ctl.krange);
             st = check_launch("k_keys");
         }
-        if (st != POTR_OK) return st;
-        hipLaunchKernelGGL(k_digits, kg, dim3(kHistThreads), 0, s, (const uint32_t*)w.ka, N,
-                           (const uint32_t*)w.ctl.krange, w.ctl.ghist);
-        st = check_launch("k_digits");
         if (st != POTR_OK) return st;
         uint32_t *kin = w.ka, *kout = w.kb;
         const uint32_t* vin = nullptr;
