@@ -24,8 +24,9 @@ namespace {
 constexpr int kBwdChunk = 128;   // entries staged per round
 constexpr int kG = 9;            // gradient components per (view, splat)
 
+// Compiled for seven waves per SIMD (71 registers, no spills).
 template <int TW, int TH>
-__global__ __launch_bounds__(TW * TH) void k_blend_bwd(int64_t N, int32_t W, int32_t H, int32_t tiles_x,
+__global__ __launch_bounds__(TW * TH) __attribute__((amdgpu_waves_per_eu(7))) void k_blend_bwd(int64_t N, int32_t W, int32_t H, int32_t tiles_x,
                                                        int32_t tiles_per_view, potr_config cfg,
                                                        const potr_proj* __restrict__ proj,
                                                        const uint32_t* __restrict__ ids,
@@ -43,7 +44,7 @@ __global__ __launch_bounds__(TW * TH) void k_blend_bwd(int64_t N, int32_t W, int
     __shared__ float s_c[kBwdChunk];    // b
     __shared__ uint32_t s_id[kBwdChunk];
     __shared__ uint32_t s_rows[kBwdChunk];
-    __shared__ float s_part[kG][NW][kBwdChunk];
+    __shared__ float s_part[kG][kBwdChunk];   // per-entry sums over the waves (LDS float adds)
     __shared__ __align__(8) uint16_t s_list[NW][kBwdChunk];
     __shared__ int s_wmax;
     const int tile = blockIdx.x, v = blockIdx.y;
@@ -108,20 +109,21 @@ __global__ __launch_bounds__(TW * TH) void k_blend_bwd(int64_t N, int32_t W, int
         uint16_t* const L = s_list[wid];
         const int nl = wave_list(s_rows, cnt, row_lo, row_hi, L);
         const int jlim = min(cnt, wave_walk - base);
-        for (int j = lane; j < cnt; j += 64)
+        for (int j = threadIdx.x; j < cnt; j += NT)
 #pragma unroll
-            for (int c = 0; c < kG; ++c) s_part[c][wid][j] = 0.f;
+            for (int c = 0; c < kG; ++c) s_part[c][j] = 0.f;
+        __syncthreads();   // cleared before any wave adds into them
         // groups of four entries: per-lane gradients, then one reduce-scatter per component
         for (int i = 0; i < nl; i += 4) {
             const uint2 q = *reinterpret_cast<const uint2*>(L + i);
             const uint32_t qx = __builtin_amdgcn_readfirstlane(q.x), qy = __builtin_amdgcn_readfirstlane(q.y);
             const int js[4] = {(int)(qx & 0xffffu), (int)(qx >> 16), (int)(qy & 0xffffu), (int)(qy >> 16)};
             if (js[0] >= jlim) break;
-            float g[4][kG];
+            // per entry and lane, five values from which the nine gradient terms follow
+            // at the reduction: w = T alpha, dL/dalpha G, dL/dq (0 where alpha is clamped), dx, dy
+            float gw[4], go[4], gq[4], gx[4], gy[4];
 #pragma unroll
-            for (int u = 0; u < 4; ++u)
-#pragma unroll
-                for (int c = 0; c < kG; ++c) g[u][c] = 0.f;
+            for (int u = 0; u < 4; ++u) gw[u] = go[u] = gq[u] = gx[u] = gy[u] = 0.f;
             bool any = false;
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
@@ -133,7 +135,7 @@ __global__ __launch_bounds__(TW * TH) void k_blend_bwd(int64_t N, int32_t W, int
                 const Gauss e = eval_gauss(a, b, fx, fy);
                 const float al = alpha_of(e, emin, amin, amax);
                 if (al != 0.f) {
-                    const float dx = e.dx, dy = e.dy, al0 = e.al0;
+                    const float al0 = e.al0;
                     const float w = __fmul_rn(T, al);
                     const float cr = b.z, cg = b.w, cb = s_c[j];
                     Pr = add_weighted(Pr, w, cr);
@@ -142,18 +144,12 @@ __global__ __launch_bounds__(TW * TH) void k_blend_bwd(int64_t N, int32_t W, int
                     const float inv = __builtin_amdgcn_rcpf(1.f - al);
                     const float dLda = gr * (T * cr - (PKr - Pr + Br) * inv) + gg * (T * cg - (PKg - Pg + Bg) * inv) +
                                        gb * (T * cb - (PKb - Pb + Bb) * inv);
-                    g[u][6] = gr * w;
-                    g[u][7] = gg * w;
-                    g[u][8] = gb * w;
+                    gw[u] = w;
                     if (al0 < amax) {
-                        g[u][5] = dLda * e.G;                      // dalpha/do = G
-                        const float dLdq = -0.5f * al0 * dLda;
-                        const float4 cn = s_u[j];       // conic a, b, c
-                        g[u][0] = dLdq * 2.f * (cn.x * dx + cn.y * dy);
-                        g[u][1] = dLdq * 2.f * (cn.y * dx + cn.z * dy);
-                        g[u][2] = dLdq * dx * dx;
-                        g[u][3] = dLdq * 2.f * dx * dy;
-                        g[u][4] = dLdq * dy * dy;
+                        go[u] = dLda * e.G;                      // dalpha/do = G
+                        gq[u] = -0.5f * al0 * dLda;              // dL/dq
+                        gx[u] = e.dx;
+                        gy[u] = e.dy;
                     }
                     any = true;
                     T = next_T(T, al);
@@ -162,18 +158,51 @@ __global__ __launch_bounds__(TW * TH) void k_blend_bwd(int64_t N, int32_t W, int
             if (__ballot(any) == 0) continue;
             const int jw = lane == 0 ? js[0] : lane == 1 ? js[1] : lane == 2 ? js[2] : js[3];
             const bool writer = lane < 4 && i + lane < nl && jw < jlim;
+            // the mean2d terms 2 dL/dq (a dx + b dy), 2 dL/dq (b dx + c dy) are formed from
+            // the sums of dL/dq dx and dL/dq dy with the entry's conic (a, b, c)
+            float sq[9];
+            {
+                float t0[4], t1[4], t2[4], t3[4];
 #pragma unroll
-            for (int c = 0; c < kG; ++c) {
-                const float s = wave_sum4(g[0][c], g[1][c], g[2][c], g[3][c]);
-                if (writer) s_part[c][wid][jw] = s;
+                for (int u = 0; u < 4; ++u) {
+                    t0[u] = gq[u] * gx[u];
+                    t1[u] = gq[u] * gy[u];
+                }
+                sq[0] = wave_sum4(t0[0], t0[1], t0[2], t0[3]);
+                sq[1] = wave_sum4(t1[0], t1[1], t1[2], t1[3]);
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    t2[u] = t0[u] * gx[u];
+                    t3[u] = t0[u] * gy[u];
+                    t0[u] = t1[u] * gy[u];
+                }
+                sq[2] = wave_sum4(t2[0], t2[1], t2[2], t2[3]);
+                sq[3] = wave_sum4(t3[0], t3[1], t3[2], t3[3]);
+                sq[4] = wave_sum4(t0[0], t0[1], t0[2], t0[3]);
+                sq[5] = wave_sum4(go[0], go[1], go[2], go[3]);
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    t0[u] = gr * gw[u];
+                    t1[u] = gg * gw[u];
+                    t2[u] = gb * gw[u];
+                }
+                sq[6] = wave_sum4(t0[0], t0[1], t0[2], t0[3]);
+                sq[7] = wave_sum4(t1[0], t1[1], t1[2], t1[3]);
+                sq[8] = wave_sum4(t2[0], t2[1], t2[2], t2[3]);
+            }
+            if (writer) {
+                const float4 cn = s_u[jw];   // conic a, b, c of the lane's entry
+                const float gs[kG] = {2.f * (cn.x * sq[0] + cn.y * sq[1]), 2.f * (cn.y * sq[0] + cn.z * sq[1]),
+                                      sq[2], 2.f * sq[3], sq[4], sq[5], sq[6], sq[7], sq[8]};
+#pragma unroll
+                for (int c = 0; c < kG; ++c)
+                    if (gs[c] != 0.f) atomicAdd(&s_part[c][jw], gs[c]);
             }
         }
         __syncthreads();
         for (int e = threadIdx.x; e < cnt * kG; e += NT) {
             const int j = e / kG, c = e - j * kG;
-            float t = 0.f;
-#pragma unroll
-            for (int w = 0; w < NW; ++w) t += s_part[c][w][j];
+            const float t = s_part[c][j];
             if (t != 0.f) unsafeAtomicAdd(grad2d + ((int64_t)v * N + s_id[j]) * kG + c, t);
         }
         __syncthreads();
