@@ -306,7 +306,9 @@ POTR_API potr_status potr_render_score_out(int64_t N, int32_t V, const potr_came
  *   `stream` and uses temporary device memory. Pair capacity per job =
  *   count * (1 + margin) + 1024.
  * potr_batch_workspace_size / potr_batch_bind: the caller supplies one device
- *   workspace; bind uploads the job table into it (synchronises).
+ *   workspace; bind uploads the job table into it (synchronises). The render's
+ *   queue holds the jobs' items by decreasing mean counted pairs per tile, so
+ *   the cheapest tiles are the last ones drawn.
  * potr_batch_pairs: counted pairs and capacities per job (host arrays [n_jobs]).
  * potr_batch_run: enqueues the whole batch; no allocation, no host sync, safe to
  *   capture. Jobs run in up to four lanes (own scratch in the workspace, own

@@ -268,7 +268,19 @@ potr_status potr_batch_bind(potr_batch b, void* ws, size_t ws_bytes, void* strea
     b->ws = (char*)ws;
     std::vector<ViewJob> table;
     std::vector<int64_t> prefix(1, 0);
+    // The render pulls items in table order, so the jobs go in by decreasing
+    // mean pairs per tile (the counts of the plan): the costliest tiles are
+    // taken first and the last items drawn, which set the launch's tail, are
+    // the cheapest ones (longest processing time first, per job).
+    std::vector<size_t> order(b->jobs.size());
+    std::vector<double> cost(b->jobs.size());
     for (size_t j = 0; j < b->jobs.size(); ++j) {
+        order[j] = j;
+        const double items = (double)b->jobs[j].V * (double)tiles_of(b->cams[j][0], b->cfg);
+        cost[j] = items > 0.0 ? (double)b->counted[j] / items : 0.0;
+    }
+    std::stable_sort(order.begin(), order.end(), [&](size_t x, size_t y) { return cost[x] > cost[y]; });
+    for (size_t j : order) {
         const potr_job& J = b->jobs[j];
         const potr_camera& c0 = b->cams[j][0];
         const int T = tiles_of(c0, b->cfg);
