@@ -160,7 +160,7 @@ POTR_API potr_status potr_bin(int64_t N, int32_t V, const potr_camera* cams, con
  *   tile_ranges [V*tiles*2] int32 out: half-open [start, end) into sorted_ids;
  *            [0, 0) for a tile without pairs
  * Limits: every image the camera checks accept (at most 16384 px a side, so
- * up to 2048 tile columns of 8 px) fits the per-workgroup LDS (71.5 KB at 2048
+ * up to 2048 tile columns of 8 px) fits the per-workgroup LDS (72.0 KB at 2048
  * columns).
  * ------------------------------------------------------------------------- */
 POTR_API potr_status potr_sort_workspace_size(int64_t capacity, size_t* bytes);

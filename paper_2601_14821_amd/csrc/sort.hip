@@ -762,7 +762,8 @@ __global__ __launch_bounds__(kRwThreads) void k_rows(const uint2* __restrict__ s
 // position in the tile, from the bin's counts). The list goes by chunks of 128
 // entries. A chunk's pairs, numbered entry by entry (a block scan of the run
 // widths), are cut into equal consecutive shares, one per thread, so that wide
-// and narrow runs cost every thread alike; each thread walks its share twice.
+// and narrow runs cost every thread alike (the entry whose run holds a share's
+// first pair marks itself as the share's first); each thread walks its share twice.
 // The first walk sets, per pair, the entry's bit in the 64-bit mask of (the
 // entry's wave, the pair's column) (LDS atomic ORs). A column pass turns the
 // masks into each (wave, column)'s first place and advances the cursors. The
@@ -775,18 +776,6 @@ __global__ __launch_bounds__(kRwThreads) void k_rows(const uint2* __restrict__ s
 constexpr int kPcThreads = 128;
 constexpr int kPcWaves = kPcThreads / 64;
 constexpr int kPcStage = 1024;   // pairs of a chunk staged for the coalesced write-out
-
-// The entry of a chunk whose pairs hold pair q: the largest i with pst[i] <= q
-// (pst: the entries' first pairs, nondecreasing from pst[0] = 0).
-__device__ inline int entry_of(const uint32_t* pst, uint32_t q) {
-    int lo = 0, hi = kPcThreads - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (pst[mid] <= q) lo = mid;
-        else hi = mid - 1;
-    }
-    return lo;
-}
 
 // The next entry after i with a nonempty run (one exists when a pair is left).
 __device__ inline int next_run(const uint32_t* ecol, int i, uint32_t& x, uint32_t& xe) {
@@ -817,7 +806,8 @@ __global__ __launch_bounds__(kPcThreads) void k_place(const uint2* __restrict__ 
     uint32_t* eid = wbase + kPcWaves * TX;                               // [kPcThreads] the chunk's splat ids
     uint32_t* ecol = eid + kPcThreads;                                   // [kPcThreads] their runs x0 | x1 << 16
     uint32_t* pst = ecol + kPcThreads;                                   // [kPcThreads] their first pairs
-    uint32_t* wsum = pst + kPcThreads;                                   // [kPcWaves]
+    uint32_t* fe = pst + kPcThreads;                                     // [kPcThreads] each share's first entry
+    uint32_t* wsum = fe + kPcThreads;                                    // [kPcWaves]
     uint32_t* cst = wsum + kPcWaves;                                     // [TX] the columns' first staged slots
     uint32_t* sid = cst + TX;                                            // [kPcStage] staged splat ids
     uint16_t* scol = reinterpret_cast<uint16_t*>(sid + kPcStage);       // [kPcStage] and their columns
@@ -870,15 +860,20 @@ __global__ __launch_bounds__(kPcThreads) void k_place(const uint2* __restrict__ 
             if (k < w) pre += wsum[k];
             np += wsum[k];
         }
-        pst[t] = pre + inc - wd;
-        __syncthreads();
-        // this thread's share [q0, q1) of the chunk's np pairs; its first pair's entry and column
+        const uint32_t p0 = pre + inc - wd;
+        pst[t] = p0;
+        // thread s's share is pairs [s * share, (s + 1) * share) of the chunk's np;
+        // the entry whose run holds a share's first pair marks itself as its first
         const uint32_t share = (np + kPcThreads - 1) / kPcThreads;
+        if (wd > 0)
+            for (uint32_t sh = (p0 + share - 1) / share; sh * share < p0 + wd; ++sh) fe[sh] = (uint32_t)t;
+        __syncthreads();
+        // this thread's share [q0, q1); its first pair's entry and column
         const uint32_t q0 = min(np, (uint32_t)t * share), q1 = min(np, q0 + share);
         int i0 = 0;
         uint32_t x0 = 0, xe0 = 0;
         if (q0 < q1) {
-            i0 = entry_of(pst, q0);
+            i0 = (int)fe[t];
             const uint32_t c = ecol[i0];
             x0 = (c & 0xffffu) + (q0 - pst[i0]);
             xe0 = c >> 16;
@@ -1073,10 +1068,10 @@ size_t gc_lds(int band, int tiles_x, int tiles_y) {
 
 // LDS of the placement: per wave and tile column a 64-bit mask and a first
 // place, a cursor and a first staging slot per column, per chunk entry its id,
-// run and first pair, and the staged ids and their columns (10.6 KB at 100
-// columns, 71.5 KB at 2048)
+// run and first pair, per thread its share's first entry, and the staged ids
+// and their columns (11.1 KB at 100 columns, 72.0 KB at 2048)
 size_t place_lds(const Bins& B) {
-    return (size_t)B.tiles_x * (kPcWaves * 8 + kPcWaves * 4 + 4 + 4) + 3 * kPcThreads * 4 + kPcWaves * 4 +
+    return (size_t)B.tiles_x * (kPcWaves * 8 + kPcWaves * 4 + 4 + 4) + 4 * kPcThreads * 4 + kPcWaves * 4 +
            (size_t)kPcStage * 6;
 }
 
