@@ -807,8 +807,8 @@ __global__ __launch_bounds__(kPcThreads) void k_place(const uint2* __restrict__ 
     uint32_t* ecol = eid + kPcThreads;                                   // [kPcThreads] their runs x0 | x1 << 16
     uint32_t* pst = ecol + kPcThreads;                                   // [kPcThreads] their first pairs
     uint32_t* fe = pst + kPcThreads;                                     // [kPcThreads] each share's first entry
-    uint32_t* wsum = fe + kPcThreads;                                    // [kPcWaves]
-    uint32_t* cst = wsum + kPcWaves;                                     // [TX] the columns' first staged slots
+    uint32_t* wsum = fe + kPcThreads;                                    // [2][kPcWaves]
+    uint32_t* cst = wsum + 2 * kPcWaves;                                 // [TX] place - staging slot per column
     uint32_t* sid = cst + TX;                                            // [kPcStage] staged splat ids
     uint16_t* scol = reinterpret_cast<uint16_t*>(sid + kPcStage);       // [kPcStage] and their columns
     // workgroups go to the 8 XCDs round-robin by linear id: block b runs on XCD
@@ -887,49 +887,47 @@ __global__ __launch_bounds__(kPcThreads) void k_place(const uint2* __restrict__ 
             }
         }
         __syncthreads();
-        // per column: each wave's first place, the cursor advanced past the
-        // chunk, and the column's first slot in the chunk's staging order
+        // the chunk's ids go out in place order: staged in LDS by (column, place)
+        // with their columns, then copied to consecutive addresses per column; a
+        // chunk of more pairs than the staging holds writes every id at its place
+        // directly. Per column: each wave's first place, the cursor advanced past
+        // the chunk, and the column's first slot in the staging order; staged,
+        // each (wave, column) base is kept as its first staging slot and the
+        // column's first slot as the difference place - slot of its pairs, so that
+        // a pair needs one LDS round trip and a copy one more
+        const bool staged = np <= (uint32_t)kPcStage;
         uint32_t carry = 0;
-        for (int x0c = 0; x0c < TX; x0c += kPcThreads) {
+        for (int x0c = 0, par = 0; x0c < TX; x0c += kPcThreads, par ^= kPcWaves) {
             const int x = x0c + t;
-            uint32_t c0 = 0, c = 0;
+            uint32_t c0 = 0, c = 0, cw[kPcWaves];
             if (x < TX) {
                 c0 = c = cur[x];
 #pragma unroll
                 for (int ww = 0; ww < kPcWaves; ++ww) {
-                    wbase[ww * TX + x] = c;
+                    cw[ww] = c;
                     c += (uint32_t)__popcll(mask[ww * TX + x]);
                 }
                 cur[x] = c;
             }
             const uint32_t cn = c - c0;
             const uint32_t inc = wave_incl_scan(cn);
-            __syncthreads();   // wsum is free (read above, or by the last pass of this loop)
-            if (lane == 63) wsum[w] = inc;
+            // the passes alternate between two halves of wsum, so one barrier
+            // separates a pass's reads from the next writes of the same half
+            if (lane == 63) wsum[par + w] = inc;
             __syncthreads();
             uint32_t pre = carry, all = 0;
 #pragma unroll
             for (int k = 0; k < kPcWaves; ++k) {
-                if (k < w) pre += wsum[k];
-                all += wsum[k];
+                if (k < w) pre += wsum[par + k];
+                all += wsum[par + k];
             }
-            if (x < TX) cst[x] = pre + inc - cn;
-            carry += all;
-        }
-        // the chunk's ids go out in place order: staged in LDS by (column, place)
-        // with their columns, then copied to consecutive addresses per column; a
-        // chunk of more pairs than the staging holds writes every id at its place
-        // directly. Staged: each (wave, column) base becomes its first staging slot,
-        // and each column's first slot the difference place - slot of its pairs, so
-        // that a pair needs one LDS round trip and a copy one more
-        const bool staged = carry <= (uint32_t)kPcStage;
-        if (staged) {
-            for (int x = t; x < TX; x += kPcThreads) {
-                const uint32_t c0 = wbase[x], s0 = cst[x];
+            if (x < TX) {
+                const uint32_t s0 = pre + inc - cn;
 #pragma unroll
-                for (int ww = 0; ww < kPcWaves; ++ww) wbase[ww * TX + x] = s0 + (wbase[ww * TX + x] - c0);
+                for (int ww = 0; ww < kPcWaves; ++ww) wbase[ww * TX + x] = staged ? s0 + (cw[ww] - c0) : cw[ww];
                 cst[x] = c0 - s0;
             }
+            carry += all;
         }
         __syncthreads();
         {
@@ -1071,7 +1069,7 @@ size_t gc_lds(int band, int tiles_x, int tiles_y) {
 // run and first pair, per thread its share's first entry, and the staged ids
 // and their columns (11.1 KB at 100 columns, 72.0 KB at 2048)
 size_t place_lds(const Bins& B) {
-    return (size_t)B.tiles_x * (kPcWaves * 8 + kPcWaves * 4 + 4 + 4) + 4 * kPcThreads * 4 + kPcWaves * 4 +
+    return (size_t)B.tiles_x * (kPcWaves * 8 + kPcWaves * 4 + 4 + 4) + 4 * kPcThreads * 4 + 2 * kPcWaves * 4 +
            (size_t)kPcStage * 6;
 }
 
