@@ -842,7 +842,8 @@ __global__ __launch_bounds__(kPcThreads) void k_place(const uint2* __restrict__ 
     for (int x = t; x < TX; x += kPcThreads) cur[x] = orow[x];
     uint2 en = t < cnt ? rows[beg + t] : make_uint2(0u, 0u);   // this thread's entry of the first chunk
     for (int c0 = 0; c0 < cnt; c0 += kPcThreads) {
-        __syncthreads();   // the cursors are set, and the last chunk is done with every array
+        // (each thread's cursors are its own; the barrier before the last chunk's
+        // copy-out ended every other use of the arrays written from here on)
         for (int i = t; i < kPcWaves * TX; i += kPcThreads) mask[i] = 0ull;
         const uint2 e = en;
         // the next chunk's entry, in flight while this chunk is placed
@@ -946,8 +947,8 @@ __global__ __launch_bounds__(kPcThreads) void k_place(const uint2* __restrict__ 
                 if (++x == xe && q + 1 < q1) i = next_run(ecol, i, x, xe);
             }
         }
+        __syncthreads();
         if (staged) {
-            __syncthreads();
             // four copies in flight per thread
             for (uint32_t o0 = (uint32_t)t; o0 < np; o0 += 4 * kPcThreads) {
                 uint32_t xs[4], vs[4];
