@@ -454,6 +454,70 @@ POTR_API potr_status potr_prune_select_noalloc(int64_t N, const float* dmse, con
                                                double dmse_max, int32_t remaining, double a, uint8_t* remove,
                                                int64_t* n_removed, void* stream);
 
+/* ---------------------------------------------------------------------------
+ * Codec (paper Sec. 4.5; hyperparameters of the Sec. 5.1 table). Encoder: the
+ * attributes are quantised uniformly, x_hat = floor(1/2 + x SF) with one scale
+ * factor per attribute (activated scale, unit quaternion x, y, z with w >= 0,
+ * activated opacity, every SH coefficient; DC coefficients as differences to
+ * the previous splat); positions go to the centre of an octree leaf, a node
+ * being split while it holds more than one splat or its one splat misses
+ * |mu - centre| < max(gamma, beta * distance to the nearest training camera
+ * eye); the octree is written depth first, one occupancy byte per node (bit
+ * c = x | y << 1 | z << 2 for each child octant, 0 for a leaf), then the
+ * attributes in that leaf order, one property after another; zstd last.
+ * Decoder: the reverse, opacity dequantised a quarter step up, (x_hat + 1/4) / SF.
+ *
+ * Where the paper leaves the format open: the root is the cube at the per-axis
+ * minimum of the positions with side (largest extent) * (1 + 2^-20); positions
+ * are placed on a 2^max_depth grid per axis and nodes at max_depth are leaves
+ * whatever they hold (their splat counts are stored, u32 each); the precision
+ * test compares squares in FP64. Layout, little-endian: a 104-byte header
+ * (magic "POTR", version 1, N, max_depth, sh_degree, lo[3], size, the four
+ * scale factors, node and cap-leaf counts), the node bytes, the cap-leaf
+ * counts, then 7 + 3 (sh_degree + 1)^2 int32 streams of N values: opacity,
+ * scale x y z, rotation x y z, SH coefficient j channel r g b.
+ *
+ * potr_codec_encode (device inputs as for potr_project: means [N,3], scales
+ *   [N,3], quats [N,4] (w,x,y,z), opacities [N], sh [N,16,3] of which the first
+ *   (sh_degree+1)^2 coefficients are coded; cams: host array of the training
+ *   cameras, whose eyes set the precision bound): writes the uncompressed
+ *   bitstream into the host buffer raw (raw_cap bytes, at most
+ *   potr_codec_max_bytes) and its size into *raw_bytes (also when the buffer is
+ *   too small: POTR_ECAPACITY). leaf_order (device [N], optional): the input
+ *   index of each coded splat. ws: potr_codec_workspace_size bytes of device
+ *   memory. Synchronises `stream`; the octree bytes are written on the host.
+ *   POTR_EINVAL for non-finite positions or a quantised value outside int32.
+ * potr_codec_compress / potr_codec_decompress: zstd at `level` through the
+ *   system's libzstd.so.1 (POTR_EUNSUPPORTED when it cannot be loaded).
+ * potr_codec_info / potr_codec_decode: N and sh_degree of a bitstream, and the
+ *   decoded model into host arrays (layouts as above; the splats in leaf
+ *   order, SH coefficients past sh_degree zero). POTR_EINVAL for a stream that
+ *   does not parse.
+ * ------------------------------------------------------------------------- */
+typedef struct potr_codec_params {
+    double beta, gamma;                          /* precision test */
+    double sf_scale, sf_rot, sf_opac, sf_sh;     /* quantisation scale factors */
+    int32_t max_depth;                           /* octree depth cap, 1..21 */
+    int32_t reserved;
+} potr_codec_params;
+
+POTR_API potr_status potr_codec_workspace_size(int64_t N, int32_t sh_degree, int32_t n_cams, size_t* bytes);
+POTR_API potr_status potr_codec_max_bytes(int64_t N, int32_t sh_degree, int32_t max_depth, size_t* bytes);
+POTR_API potr_status potr_codec_encode(int64_t N, const float* means, const float* scales, const float* quats,
+                                       const float* opacities, const float* sh, int32_t sh_degree,
+                                       const potr_camera* cams, int32_t n_cams, const potr_codec_params* prm,
+                                       void* ws, size_t ws_bytes, uint8_t* raw, size_t raw_cap, size_t* raw_bytes,
+                                       uint32_t* leaf_order, void* stream);
+POTR_API potr_status potr_codec_compress_bound(size_t raw_bytes, size_t* bytes);
+POTR_API potr_status potr_codec_compress(const uint8_t* raw, size_t raw_bytes, int32_t level, uint8_t* out,
+                                         size_t out_cap, size_t* out_bytes);
+POTR_API potr_status potr_codec_decompressed_size(const uint8_t* comp, size_t comp_bytes, size_t* raw_bytes);
+POTR_API potr_status potr_codec_decompress(const uint8_t* comp, size_t comp_bytes, uint8_t* raw, size_t raw_cap,
+                                           size_t* raw_bytes);
+POTR_API potr_status potr_codec_info(const uint8_t* raw, size_t raw_bytes, int64_t* N, int32_t* sh_degree);
+POTR_API potr_status potr_codec_decode(const uint8_t* raw, size_t raw_bytes, float* means, float* scales,
+                                       float* quats, float* opacities, float* sh);
+
 /* potr_autotune: times every tile shape (16x16, 8x8, 32x8) with every LDS batch
  * (64, 128, 320, 512) on the given jobs (`reps` timed runs each, after one
  * warm-up) and writes the fastest tile_w, tile_h, lds_batch into *inout. Uses

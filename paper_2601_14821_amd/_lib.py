@@ -85,6 +85,16 @@ SIGNATURES = {
     "potr_sh_compact_workspace_size": (_i32, [_i64, _i32, C.POINTER(_sz)]),
     "potr_sh_compact": (_i32, [_i64, _i32, _CAM_P, _i32, _vp, _vp, _vp, _i64, C.c_double, C.c_double, C.c_double,
                                _vp, _sz, _vp, _vp]),
+    "potr_codec_workspace_size": (_i32, [_i64, _i32, _i32, C.POINTER(_sz)]),
+    "potr_codec_max_bytes": (_i32, [_i64, _i32, _i32, C.POINTER(_sz)]),
+    "potr_codec_encode": (_i32, [_i64, _vp, _vp, _vp, _vp, _vp, _i32, _CAM_P, _i32, _vp, _vp, _sz, _vp, _sz,
+                                 C.POINTER(_sz), _vp, _vp]),
+    "potr_codec_compress_bound": (_i32, [_sz, C.POINTER(_sz)]),
+    "potr_codec_compress": (_i32, [_vp, _sz, _i32, _vp, _sz, C.POINTER(_sz)]),
+    "potr_codec_decompressed_size": (_i32, [_vp, _sz, C.POINTER(_sz)]),
+    "potr_codec_decompress": (_i32, [_vp, _sz, _vp, _sz, C.POINTER(_sz)]),
+    "potr_codec_info": (_i32, [_vp, _sz, C.POINTER(_i64), C.POINTER(_i32)]),
+    "potr_codec_decode": (_i32, [_vp, _sz, _vp, _vp, _vp, _vp, _vp]),
     "potr_prune_select_noalloc": (_i32, [_i64, _vp, _vp, C.c_double, _i32, C.c_double, _vp, _vp, _vp]),
     "potr_prune_compact": (_i32, [_i64] + [_vp] * 7 + [_vp, _sz] + [_vp] * 7 + [_vp]),
     "potr_autotune": (_i32, [_JOB_P, _i32, _CFG_P, _i32, C.POINTER(C.c_double), _CFG_P, C.POINTER(C.c_double),

@@ -21,7 +21,7 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("POTR_ARCH", "gfx950")
 
 SOURCES = ["api.cpp", "batch.cpp", "project.hip", "sort.hip", "blend.hip", "backward.hip", "fused.hip",
-           "batch_kernels.hip", "prune.hip", "sh_compact.hip"]
+           "batch_kernels.hip", "prune.hip", "sh_compact.hip", "codec.hip"]
 
 FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-fPIC", "-std=c++17", "-Wall", "-fvisibility=hidden",
