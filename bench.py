@@ -395,6 +395,45 @@ def fwd_bwd_section(torch, raster, synth, autograd, batch):
                                       "as one job of the batch runtime, replayed as one HIP graph"}}
 
 
+def codec_section(torch, raster, synth):
+    """The codec (Sec. 4.5) on the full scene (3M splats, its 200 training
+    cameras for the precision bound) at q = 0.5: the encoder (device per-splat
+    work, host octree bytes and copies), zstd, and the decoder, wall-clock."""
+    import time
+
+    from paper_2601_14821_amd import codec
+
+    scene, cams = synth.workload_full_scene()
+    ds = raster.to_device(scene)
+    prm = codec.params(0.5)
+
+    def wall(fn, reps=3):
+        ts = []
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            r = fn()
+            ts.append(time.perf_counter() - t0)
+        ts.sort()
+        return r, ts[len(ts) // 2] * 1e3
+
+    raw = codec.encode(ds, cams, prm)      # warm-up (library load, kernels)
+    raw, enc_ms = wall(lambda: codec.encode(ds, cams, prm))
+    comp, zstd_ms = wall(lambda: codec.compress(raw, 3), reps=1)
+    back, unzstd_ms = wall(lambda: codec.decompress(comp), reps=1)
+    _, dec_ms = wall(lambda: codec.decode(back), reps=1)
+    n = scene.n
+    del ds
+    torch.cuda.empty_cache()
+    return {"workload": f"{n} clustered splats, precision bound from {len(cams)} training cameras, q = 0.5",
+            "encode_ms": round(enc_ms, 1), "encode_msplats_per_s": round(n / enc_ms / 1e3, 2),
+            "zstd_ms": round(zstd_ms, 1), "unzstd_ms": round(unzstd_ms, 1), "decode_ms": round(dec_ms, 1),
+            "raw_bytes": len(raw), "zstd_bytes": len(comp), "bytes_per_splat": round(len(comp) / n, 2),
+            "ratio_vs_236B": round(236.0 * n / len(comp), 2),
+            "note": "synthetic SH values are noise, so the SH streams barely compress; energy compaction "
+                    "(Sec. 4.4) is not applied here"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -408,7 +447,7 @@ def main():
     ap.add_argument("--main-only", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 256 MiB device copy (reference for hardware byte counters)")
-    ap.add_argument("--profile-section", choices=("single_view", "multi_scene", "fwd_bwd"), default=None,
+    ap.add_argument("--profile-section", choices=("single_view", "multi_scene", "fwd_bwd", "codec"), default=None,
                     help="run only this extra section and print its result (no main line)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -423,7 +462,8 @@ def main():
     if args.profile_section:
         fn = {"single_view": lambda: single_view_section(args, torch, raster, synth),
               "multi_scene": lambda: multi_scene_section(torch, raster, synth, batch, args.multi_views_per_job),
-              "fwd_bwd": lambda: fwd_bwd_section(torch, raster, synth, autograd, batch)}[args.profile_section]
+              "fwd_bwd": lambda: fwd_bwd_section(torch, raster, synth, autograd, batch),
+              "codec": lambda: codec_section(torch, raster, synth)}[args.profile_section]
         log(args.profile_section)
         print(json.dumps({args.profile_section: fn()}), flush=True)
         return
@@ -462,6 +502,8 @@ def main():
         out["multi_scene"] = multi_scene_section(torch, raster, synth, batch, args.multi_views_per_job)
         log("forward + backward")
         out["fwd_bwd"] = fwd_bwd_section(torch, raster, synth, autograd, batch)
+        log("codec")
+        out["codec"] = codec_section(torch, raster, synth)
     if not args.no_cpu_baseline:
         log("cpu baseline")
         out["cpu_baseline"] = cpu_baseline(scene, cams, s)

@@ -48,13 +48,14 @@ def encode(ds, cams, prm: potr_codec_params, sh_degree: int = 3, want_order: boo
     if ws is None or ws.numel() < b.value:
         ws = torch.empty(max(b.value, 256), dtype=torch.uint8, device=dev)
     L.call("potr_codec_max_bytes", N, sh_degree, prm.max_depth, C.byref(b))
-    raw = (C.c_uint8 * b.value)()
+    # pinned host memory: the attribute streams leave the device in one DMA
+    raw = torch.empty(b.value, dtype=torch.uint8, pin_memory=True)
     n = C.c_size_t(0)
     order = torch.empty(max(N, 1), dtype=torch.int32, device=dev)[:N] if want_order else None
     L.call("potr_codec_encode", N, L.ptr(ds.means), L.ptr(ds.scales), L.ptr(ds.quats), L.ptr(ds.opacities),
-           L.ptr(ds.sh), sh_degree, cam, len(cams), C.byref(prm), L.ptr(ws), ws.numel(), _u8(raw), b.value,
+           L.ptr(ds.sh), sh_degree, cam, len(cams), C.byref(prm), L.ptr(ws), ws.numel(), raw.data_ptr(), b.value,
            C.byref(n), L.ptr(order) if order is not None else None, L.stream_handle())
-    out = bytes(memoryview(raw)[: n.value])
+    out = raw[: n.value].numpy().tobytes()
     if want_order:
         return out, order.long()
     return out
