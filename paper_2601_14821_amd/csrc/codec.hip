@@ -588,7 +588,12 @@ potr_status potr_codec_decode(const uint8_t* raw, size_t raw_bytes, float* means
     const int D = (int)h.depth;
     const uint8_t* nodes = raw + sizeof(Header);
     const uint8_t* capsb = nodes + h.n_nodes;
-    const int32_t* st = reinterpret_cast<const int32_t*>(capsb + 4 * h.n_caps);
+    const uint8_t* stb = capsb + 4 * h.n_caps;   // int32 streams (not necessarily 4-byte aligned)
+    auto st_at = [&](int64_t idx) {
+        int32_t v;
+        std::memcpy(&v, stb + 4 * idx, 4);
+        return v;
+    };
     // depth-first walk of the bytes: the leaves' centres in order
     struct Frame {
         int depth;
@@ -659,10 +664,10 @@ potr_status potr_codec_decode(const uint8_t* raw, size_t raw_bytes, float* means
     const int nsh = ((int)h.sh_degree + 1) * ((int)h.sh_degree + 1);
     int64_t dc[3] = {0, 0, 0};
     for (int64_t k = 0; k < N; ++k) {
-        opacities[k] = (float)(((double)st[k] + 0.25) / sf_opac);
-        for (int a = 0; a < 3; ++a) scales[3 * k + a] = (float)((double)st[(1 + a) * N + k] / sf_scale);
+        opacities[k] = (float)(((double)st_at(k) + 0.25) / sf_opac);
+        for (int a = 0; a < 3; ++a) scales[3 * k + a] = (float)((double)st_at((1 + a) * N + k) / sf_scale);
         double x[3];
-        for (int a = 0; a < 3; ++a) x[a] = (double)st[(4 + a) * N + k] / sf_rot;
+        for (int a = 0; a < 3; ++a) x[a] = (double)st_at((4 + a) * N + k) / sf_rot;
         const double n2 = (x[0] * x[0] + x[1] * x[1]) + x[2] * x[2];
         const double r = 1.0 - n2;
         quats[4 * k] = (float)std::sqrt(r > 0.0 ? r : 0.0);
@@ -672,7 +677,7 @@ potr_status potr_codec_decode(const uint8_t* raw, size_t raw_bytes, float* means
             for (int ch = 0; ch < 3; ++ch) {
                 float v = 0.f;
                 if (j < nsh) {
-                    int64_t q = st[(int64_t)(7 + 3 * j + ch) * N + k];
+                    int64_t q = st_at((int64_t)(7 + 3 * j + ch) * N + k);
                     if (j == 0) {
                         dc[ch] += q;
                         q = dc[ch];
