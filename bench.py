@@ -434,7 +434,7 @@ def codec_section(torch, raster, synth):
     return {"workload": f"{n} clustered splats, precision bound from {len(cams)} training cameras, q = 0.5",
             "encode_ms": round(enc_ms, 1), "encode_msplats_per_s": round(n / enc_ms / 1e3, 2),
             "zstd_ms": round(zstd_ms, 1), "unzstd_ms": round(unzstd_ms, 1), "decode_ms": round(dec_ms, 1),
-            "raw_bytes": len(raw), "zstd_bytes": len(comp), "bytes_per_splat": round(len(comp) / n, 2),
+            "raw_bytes": int(raw.nbytes), "zstd_bytes": len(comp), "bytes_per_splat": round(len(comp) / n, 2),
             "ratio_vs_236B": round(236.0 * n / len(comp), 2),
             "note": "synthetic SH values are noise, so the SH streams barely compress; energy compaction "
                     "(Sec. 4.4) is not applied here"}

@@ -37,9 +37,18 @@ def _u8(buf) -> C.c_void_p:
     return C.cast(buf, C.c_void_p)
 
 
+def _src(data):
+    """(pointer, length) of a bytes object or a uint8 numpy array."""
+    if isinstance(data, np.ndarray):
+        data = np.ascontiguousarray(data, np.uint8)
+        return C.c_void_p(data.ctypes.data), data.nbytes, data
+    return data, len(data), data
+
+
 def encode(ds, cams, prm: potr_codec_params, sh_degree: int = 3, want_order: bool = False, ws=None):
-    """potr_codec_encode: the uncompressed bitstream (bytes) and, if asked, the
-    input index of each coded splat (device int64 tensor)."""
+    """potr_codec_encode: the uncompressed bitstream (a uint8 numpy array over
+    pinned host memory) and, if asked, the input index of each coded splat
+    (device int64 tensor)."""
     N = ds.n
     dev = ds.means.device
     cam = L.make_cameras(cams)
@@ -55,40 +64,44 @@ def encode(ds, cams, prm: potr_codec_params, sh_degree: int = 3, want_order: boo
     L.call("potr_codec_encode", N, L.ptr(ds.means), L.ptr(ds.scales), L.ptr(ds.quats), L.ptr(ds.opacities),
            L.ptr(ds.sh), sh_degree, cam, len(cams), C.byref(prm), L.ptr(ws), ws.numel(), raw.data_ptr(), b.value,
            C.byref(n), L.ptr(order) if order is not None else None, L.stream_handle())
-    out = raw[: n.value].numpy().tobytes()
+    out = raw[: n.value].numpy()
     if want_order:
         return out, order.long()
     return out
 
 
-def compress(raw: bytes, level: int = 3) -> bytes:
+def compress(raw, level: int = 3) -> bytes:
+    """zstd of a bitstream (bytes or uint8 array)."""
+    p, size, _keep = _src(raw)
     b = C.c_size_t(0)
-    L.call("potr_codec_compress_bound", len(raw), C.byref(b))
+    L.call("potr_codec_compress_bound", size, C.byref(b))
     out = (C.c_uint8 * b.value)()
     n = C.c_size_t(0)
-    L.call("potr_codec_compress", raw, len(raw), level, _u8(out), b.value, C.byref(n))
+    L.call("potr_codec_compress", p, size, level, _u8(out), b.value, C.byref(n))
     return bytes(memoryview(out)[: n.value])
 
 
-def decompress(comp: bytes) -> bytes:
+def decompress(comp) -> bytes:
+    p, size, _keep = _src(comp)
     b = C.c_size_t(0)
-    L.call("potr_codec_decompressed_size", comp, len(comp), C.byref(b))
+    L.call("potr_codec_decompressed_size", p, size, C.byref(b))
     out = (C.c_uint8 * max(b.value, 1))()
     n = C.c_size_t(0)
-    L.call("potr_codec_decompress", comp, len(comp), _u8(out), b.value, C.byref(n))
+    L.call("potr_codec_decompress", p, size, _u8(out), b.value, C.byref(n))
     return bytes(memoryview(out)[: n.value])
 
 
-def decode(raw: bytes) -> dict:
+def decode(raw) -> dict:
     """potr_codec_decode: the model as host arrays, splats in leaf order."""
+    p, size, _keep = _src(raw)
     n = C.c_int64(0)
     deg = C.c_int32(0)
-    L.call("potr_codec_info", raw, len(raw), C.byref(n), C.byref(deg))
+    L.call("potr_codec_info", p, size, C.byref(n), C.byref(deg))
     N = n.value
     out = dict(means=np.zeros((N, 3), np.float32), scales=np.zeros((N, 3), np.float32),
                quats=np.zeros((N, 4), np.float32), opacities=np.zeros(N, np.float32),
                sh=np.zeros((N, 16, 3), np.float32))
-    L.call("potr_codec_decode", raw, len(raw), out["means"].ctypes.data, out["scales"].ctypes.data,
+    L.call("potr_codec_decode", p, size, out["means"].ctypes.data, out["scales"].ctypes.data,
            out["quats"].ctypes.data, out["opacities"].ctypes.data, out["sh"].ctypes.data)
     out["sh_degree"] = deg.value
     return out

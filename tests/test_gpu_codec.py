@@ -49,6 +49,7 @@ def test_bitstream_matches_oracle(n, seed, q, D, dup, nc, extra):
     po, pg = _prm(q, D, **extra)
     want, info = oc.encode_raw(s, cams, po)
     got, order = codec.encode(raster.to_device(s), cams, pg, want_order=True)
+    got = got.tobytes()
     torch.cuda.synchronize()
     assert np.array_equal(order.cpu().numpy(), info["order"])
     assert len(got) == len(want)
@@ -68,7 +69,7 @@ def test_empty_model():
     ds = raster.to_device(s)
     empty = raster.DeviceScene(ds.means[:0], ds.scales[:0], ds.quats[:0], ds.opacities[:0], ds.sh[:0])
     raw = codec.encode(empty, cams, codec.params(0.5))
-    assert len(raw) == oc.HEADER.size
+    assert raw.nbytes == oc.HEADER.size
     dec = codec.decode(raw)
     assert dec["means"].shape == (0, 3)
 
@@ -98,7 +99,7 @@ def test_full_scene_sampled():
     assert np.array_equal(np.sort(order), np.arange(scene.n))
     comp = codec.compress(raw)
     dec = codec.decode(codec.decompress(comp))
-    head = oc.HEADER.unpack_from(raw, 0)
+    head = oc.HEADER.unpack_from(raw[: oc.HEADER.size].tobytes(), 0)
     lo, size = np.array(head[5:8]), head[8]
     _, size_o, _ = oc.grid(scene.means, 21)
     assert size == size_o and np.array_equal(lo, scene.means.min(0).astype(np.float64))
@@ -120,4 +121,4 @@ def test_full_scene_sampled():
     u = oc.unit_quat(scene.quats[i])
     np.testing.assert_array_equal(dec["quats"][k, 1:], oc.dequantise(np.floor(0.5 + u[:, 1:] * po["sf_rot"]),
                                                                      po["sf_rot"]).astype(np.float32))
-    print(f"codec full scene: raw {len(raw)} B, zstd {len(comp)} B, {scene.n * 236 / len(comp):.1f}x vs 236 B/splat")
+    print(f"codec full scene: raw {raw.nbytes} B, zstd {len(comp)} B, {scene.n * 236 / len(comp):.1f}x vs 236 B/splat")
