@@ -216,7 +216,7 @@ def main_line(args, torch, raster, synth, batch):
     del rz
     torch.cuda.empty_cache()
     achieved = FLOPS_PER_WALKED * visited / 1e12 / (kernel_ms / 1000.0)
-    counted = (FUSED_FLOPS_VISIT * visited + FUSED_FLOPS_BLEND * blended) / 1e12 / (kernel_ms / 1000.0)
+    achieved_counted = (FUSED_FLOPS_VISIT * visited + FUSED_FLOPS_BLEND * blended) / 1e12 / (kernel_ms / 1000.0)
     kernel = "k_render_score_persistent"
     ctr = measured_counters(kernel, COUNTER_RECORD)
     valu = ctr.get("valu_insts_per_launch") if ctr else None
@@ -224,7 +224,8 @@ def main_line(args, torch, raster, synth, batch):
                 "frac": round(achieved / FP32_VECTOR_PEAK_TFLOPS, 4),
                 "traffic": None if ctr is None else int(ctr["bytes_per_launch"]), "kernel": kernel,
                 "kernel_ms": round(kernel_ms, 4), "flops_per_walked_pair": FLOPS_PER_WALKED, "walked_pairs": int(visited),
-                "achieved_counted": round(counted, 3), "frac_counted": round(counted / FP32_VECTOR_PEAK_TFLOPS, 4),
+                "achieved_counted": round(achieved_counted, 3),
+                "frac_counted": round(achieved_counted / FP32_VECTOR_PEAK_TFLOPS, 4),
                 "valu_issue": None if valu is None else round(valu / (VALU_ISSUE_PER_S * kernel_ms / 1000.0), 4)}
     gs = lambda t: round(N * V / (t / 1000.0) / 1e9, 4)
     out = {
