@@ -488,9 +488,7 @@ POTR_API potr_status potr_prune_select_noalloc(int64_t N, const float* dmse, con
  *   memory. Synchronises `stream`; the octree bytes are written on the host.
  *   POTR_EINVAL for non-finite positions or a quantised value outside int32.
  * potr_codec_compress / potr_codec_decompress: zstd at `level` through the
- *   system's libzstd.so.1 (POTR_EUNSUPPORTED when it cannot be loaded); one
- *   standard frame, compressed by up to 16 worker threads where the library
- *   has them.
+ *   system's libzstd.so.1 (POTR_EUNSUPPORTED when it cannot be loaded).
  * potr_codec_info / potr_codec_decode: N and sh_degree of a bitstream, and the
  *   decoded model into host arrays (layouts as above; the splats in leaf
  *   order, SH coefficients past sh_degree zero). POTR_EINVAL for a stream that

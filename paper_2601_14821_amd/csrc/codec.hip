@@ -27,7 +27,6 @@
 #include <cmath>
 #include <cstring>
 #include <mutex>
-#include <thread>
 #include <vector>
 
 #include <hipcub/hipcub.hpp>
@@ -342,11 +341,6 @@ void emit_nodes(int64_t N, int D, const std::vector<uint64_t>& code, const std::
 struct Zstd {
     size_t (*bound)(size_t) = nullptr;
     size_t (*compress)(void*, size_t, const void*, size_t, int) = nullptr;
-    // the advanced interface, for compression over several threads
-    void* (*cctx_new)() = nullptr;
-    size_t (*cctx_free)(void*) = nullptr;
-    size_t (*cctx_set)(void*, int, int) = nullptr;
-    size_t (*compress2)(void*, void*, size_t, const void*, size_t) = nullptr;
     size_t (*decompress)(void*, size_t, const void*, size_t) = nullptr;
     unsigned (*is_error)(size_t) = nullptr;
     unsigned long long (*content_size)(const void*, size_t) = nullptr;
@@ -364,10 +358,6 @@ const Zstd& zstd() {
         z.decompress = (size_t(*)(void*, size_t, const void*, size_t))dlsym(h, "ZSTD_decompress");
         z.is_error = (unsigned (*)(size_t))dlsym(h, "ZSTD_isError");
         z.content_size = (unsigned long long (*)(const void*, size_t))dlsym(h, "ZSTD_getFrameContentSize");
-        z.cctx_new = (void* (*)())dlsym(h, "ZSTD_createCCtx");
-        z.cctx_free = (size_t(*)(void*))dlsym(h, "ZSTD_freeCCtx");
-        z.cctx_set = (size_t(*)(void*, int, int))dlsym(h, "ZSTD_CCtx_setParameter");
-        z.compress2 = (size_t(*)(void*, void*, size_t, const void*, size_t))dlsym(h, "ZSTD_compress2");
         z.ok = z.bound && z.compress && z.decompress && z.is_error && z.content_size;
     });
     return z;
@@ -550,25 +540,7 @@ potr_status potr_codec_compress(const uint8_t* raw, size_t raw_bytes, int32_t le
     const Zstd& z = zstd();
     if (!z.ok) return fail(POTR_EUNSUPPORTED, "libzstd.so.1 not found");
     if (!raw || !out || !out_bytes) return fail(POTR_EINVAL, "NULL argument");
-    size_t n = 0;
-    bool done = false;
-    if (z.cctx_new && z.cctx_free && z.cctx_set && z.compress2) {
-        // one frame compressed by several worker threads (the frame format is
-        // the same; a library built without threads rejects the worker count)
-        constexpr int kLevel = 100, kWorkers = 400;   // ZSTD_c_compressionLevel, ZSTD_c_nbWorkers
-        const unsigned hw = std::thread::hardware_concurrency();
-        const int workers = (int)std::min(16u, hw > 0 ? hw : 1u);
-        void* cx = z.cctx_new();
-        if (cx) {
-            if (!z.is_error(z.cctx_set(cx, kLevel, level))) {
-                if (workers > 1) (void)z.cctx_set(cx, kWorkers, workers);
-                n = z.compress2(cx, out, out_cap, raw, raw_bytes);
-                done = true;
-            }
-            z.cctx_free(cx);
-        }
-    }
-    if (!done) n = z.compress(out, out_cap, raw, raw_bytes, level);
+    const size_t n = z.compress(out, out_cap, raw, raw_bytes, level);
     if (z.is_error(n)) return fail(POTR_ECAPACITY, "zstd compression failed (buffer of %zu bytes)", out_cap);
     *out_bytes = n;
     return POTR_OK;
