@@ -292,9 +292,11 @@ def single_view_section(args, torch, raster, synth):
     t1 = time.perf_counter()
     if not rz.pairs_fit(runs[-1][1]):
         raise RuntimeError("the timed steps ran out of pair slots")
-    for ev, _ in runs:
-        for i, k in enumerate(stages):
-            stage_ms[k] += ev[i].elapsed_time(ev[i + 1]) / args.steps
+    # per stage the median over the steps (a host stall while a stage is being
+    # launched would otherwise show up as that stage's time)
+    for i, k in enumerate(stages):
+        ts = sorted(ev[i].elapsed_time(ev[i + 1]) for ev, _ in runs)
+        stage_ms[k] = ts[len(ts) // 2]
     ms = (t1 - t0) * 1000.0 / args.steps
     pairs, visited, blended = view_work(torch, rz, ds, cams)
     flops = FUSED_FLOPS_VISIT * visited + FUSED_FLOPS_BLEND * blended
