@@ -485,7 +485,8 @@ POTR_API potr_status potr_prune_select_noalloc(int64_t N, const float* dmse, con
  *   potr_codec_max_bytes) and its size into *raw_bytes (also when the buffer is
  *   too small: POTR_ECAPACITY). leaf_order (device [N], optional): the input
  *   index of each coded splat. ws: potr_codec_workspace_size bytes of device
- *   memory. Synchronises `stream`; the octree bytes are written on the host.
+ *   memory. Synchronises `stream` (to size the octree bytes, then to copy
+ *   the bitstream out).
  *   POTR_EINVAL for non-finite positions or a quantised value outside int32.
  * potr_codec_compress / potr_codec_decompress: zstd at `level` through the
  *   system's libzstd.so.1 (POTR_EUNSUPPORTED when it cannot be loaded).

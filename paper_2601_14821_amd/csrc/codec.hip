@@ -10,11 +10,13 @@
 // every node down to one level below the longer common prefix with either
 // neighbour holds another splat and splits; from there its node holds it alone
 // and splits until the precision test passes (or the depth cap is reached).
-// The attributes are quantised straight into leaf order. On the host, one pass
-// over the sorted splats writes the occupancy bytes: splat k enters the tree
-// one level below its common prefix with splat k-1, sets its octant bit in the
-// byte of the node where it branches off, and appends the bytes of its new
-// nodes (one child each, as far as it knows) and of its leaf.
+// The attributes are quantised straight into leaf order. The occupancy bytes
+// follow from the same order: splat k enters the tree one level below its
+// common prefix with splat k-1, appends the bytes of its new nodes (one child
+// each, as far as it knows) and of its leaf at a scanned offset, and sets its
+// octant bit in the byte of the node where it branches off (found, per depth,
+// by a running maximum over the splats that entered at or above it). zstd runs
+// on the host.
 //
 // Decoder, on the host: zstd, then a depth-first walk of the bytes that gives
 // the leaf centres in the same order as the attribute streams, which are
@@ -254,6 +256,77 @@ __global__ __launch_bounds__(kThreads) void k_codec_attr(int64_t N, const uint32
     if (bad) atomicOr(flag, 1);
 }
 
+// The octree bytes, depth first (as the recursion would write them). A sorted
+// splat appends the bytes of its new nodes, from the depth where it enters the
+// tree to its leaf (none when it shares the previous splat's cap leaf): each of
+// its internal nodes starts with the bit of its own child, its leaf is 0. The
+// node where splat k branches off (at depth enter[k] - 1) was appended by the
+// last splat before k that entered the tree at or above that depth; k sets its
+// octant bit there.
+__device__ inline uint32_t digit_at(uint64_t c, int level, int D) {   // level 1..D
+    return (uint32_t)(c >> (3 * (D - level))) & 7u;
+}
+
+__global__ __launch_bounds__(kThreads) void k_codec_count(int64_t N, const uint8_t* __restrict__ enter,
+                                                         const uint8_t* __restrict__ leaf, int D,
+                                                         uint64_t* __restrict__ nb, uint32_t* __restrict__ capf) {
+    const int64_t k = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (k >= N) return;
+    const int e = enter[k], d = leaf[k];
+    nb[k] = e <= D ? (uint64_t)(d - e + 1) : 0ull;
+    capf[k] = (e <= D && d == D) ? 1u : 0u;
+}
+
+__global__ __launch_bounds__(kThreads) void k_codec_own(int64_t N, const uint64_t* __restrict__ code,
+                                                       const uint8_t* __restrict__ enter,
+                                                       const uint8_t* __restrict__ leaf,
+                                                       const uint64_t* __restrict__ off, int D,
+                                                       uint8_t* __restrict__ nodes) {
+    const int64_t k = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (k >= N) return;
+    const int e = enter[k], d = leaf[k];
+    if (e > D) return;
+    const uint64_t c = code[k], p = off[k];
+    for (int L = e; L < d; ++L) nodes[p + (uint64_t)(L - e)] = (uint8_t)(1u << digit_at(c, L + 1, D));
+    nodes[p + (uint64_t)(d - e)] = 0;
+}
+
+// f[k] = k where splat k entered the tree at depth <= l, else -1 (the running
+// maximum of f is then the last such splat at or before each position)
+__global__ __launch_bounds__(kThreads) void k_codec_flag(int64_t N, const uint8_t* __restrict__ enter, int l,
+                                                        int32_t* __restrict__ f) {
+    const int64_t k = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (k >= N) return;
+    f[k] = (int)enter[k] <= l ? (int32_t)k : -1;
+}
+
+__global__ __launch_bounds__(kThreads) void k_codec_branch(int64_t N, const uint64_t* __restrict__ code,
+                                                          const uint8_t* __restrict__ enter,
+                                                          const uint64_t* __restrict__ off,
+                                                          const int32_t* __restrict__ last, int l, int D,
+                                                          uint32_t* __restrict__ words) {
+    const int64_t k = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (k >= N) return;
+    const int e = enter[k];
+    if (e != l + 1 || e > D) return;   // branches off at depth l (k > 0 here: splat 0 enters at 0)
+    const int32_t a = last[k - 1];      // >= 0: splat 0 entered at depth 0
+    const uint64_t pos = off[a] + (uint64_t)(l - (int)enter[a]);
+    atomicOr(words + (pos >> 2), (1u << digit_at(code[k], l + 1, D)) << (8 * (uint32_t)(pos & 3)));
+}
+
+// The splat count of each leaf at the depth cap: the splat that opens it and
+// the duplicates right behind it.
+__global__ __launch_bounds__(kThreads) void k_codec_caps(int64_t N, const uint8_t* __restrict__ enter,
+                                                        const uint32_t* __restrict__ capf,
+                                                        const uint32_t* __restrict__ capoff, int D,
+                                                        uint32_t* __restrict__ caps) {
+    const int64_t k = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (k >= N || !capf[k]) return;
+    int64_t j = k + 1;
+    while (j < N && (int)enter[j] > D) ++j;
+    caps[capoff[k]] = (uint32_t)(j - k);
+}
+
 // ---------------------------------------------------------------- host
 
 struct EncWs {
@@ -268,18 +341,31 @@ struct EncWs {
     uint8_t* leaf;
     int32_t* streams;
     int* flag;
+    uint64_t* nb;       // bytes per sorted splat (in the codes' first buffer, free after the sort)
+    uint64_t* off;      // their exclusive scan (in the precision bounds' buffer, free after the leaves)
+    uint32_t* capf;
+    uint32_t* capoff;
+    int32_t* f;
+    int32_t* last;
+    uint8_t* nodes;     // N * (21 + 1) bytes at most, rounded to words
+    uint32_t* caps;
+    uint64_t* totals;   // n_nodes, n_caps
     void* sort_tmp;
     size_t sort_bytes;
     size_t bytes;
 };
 
+// scratch of the library's radix sort and scans (size queries only: they read
+// no memory and cannot fail for valid sizes)
 size_t sort_tmp_bytes(int64_t N) {
-    size_t b = 0;
-    // a size query only: it reads no memory and cannot fail for valid sizes
-    (void)hipcub::DeviceRadixSort::SortPairs(nullptr, b, (const uint64_t*)nullptr, (uint64_t*)nullptr,
-                                       (const uint32_t*)nullptr, (uint32_t*)nullptr, (int)std::max<int64_t>(N, 1), 0,
-                                       64);
-    return b;
+    const int n = (int)std::max<int64_t>(N, 1);
+    size_t a = 0, b = 0, c = 0, d = 0;
+    (void)hipcub::DeviceRadixSort::SortPairs(nullptr, a, (const uint64_t*)nullptr, (uint64_t*)nullptr,
+                                             (const uint32_t*)nullptr, (uint32_t*)nullptr, n, 0, 64);
+    (void)hipcub::DeviceScan::ExclusiveSum(nullptr, b, (const uint64_t*)nullptr, (uint64_t*)nullptr, n);
+    (void)hipcub::DeviceScan::ExclusiveSum(nullptr, c, (const uint32_t*)nullptr, (uint32_t*)nullptr, n);
+    (void)hipcub::DeviceScan::InclusiveScan(nullptr, d, (const int32_t*)nullptr, (int32_t*)nullptr, hipcub::Max(), n);
+    return std::max(std::max(a, b), std::max(c, d));
 }
 
 EncWs enc_layout(int64_t N, int deg, int n_cams, char* base) {
@@ -302,6 +388,15 @@ EncWs enc_layout(int64_t N, int deg, int n_cams, char* base) {
     w.leaf = (uint8_t*)take(n);
     w.streams = (int32_t*)take(n * (size_t)n_streams(deg) * 4);
     w.flag = (int*)take(4);
+    w.nb = w.code_in;
+    w.off = (uint64_t*)w.thr2;
+    w.capf = (uint32_t*)take(n * 4);
+    w.capoff = (uint32_t*)take(n * 4);
+    w.f = (int32_t*)take(n * 4);
+    w.last = (int32_t*)take(n * 4);
+    w.nodes = (uint8_t*)take(align_up(n * 22, 4));
+    w.caps = (uint32_t*)take(n * 4);
+    w.totals = (uint64_t*)take(16);
     w.sort_bytes = sort_tmp_bytes(N);
     w.sort_tmp = take(w.sort_bytes);
     w.bytes = off;
@@ -314,28 +409,6 @@ potr_status hip_ok(hipError_t e, const char* what) {
 }
 
 bool finite_pos(double x) { return x > 0.0 && x < 1e300; }
-
-// The octree bytes from the sorted codes, entry depths and leaf depths.
-void emit_nodes(int64_t N, int D, const std::vector<uint64_t>& code, const std::vector<uint8_t>& enter,
-                const std::vector<uint8_t>& leaf, std::vector<uint8_t>& nodes, std::vector<uint32_t>& caps) {
-    int64_t at[32];   // byte of the node at each depth on the current path
-    for (int64_t k = 0; k < N; ++k) {
-        const int e = enter[k], d = leaf[k];
-        if (e > D) {   // the previous splat's cap leaf
-            caps.back() += 1;
-            continue;
-        }
-        const uint64_t c = code[k];
-        auto digit = [&](int level) { return (int)((c >> (3 * (D - level))) & 7u); };   // level 1..D
-        if (e > 0) nodes[at[e - 1]] |= (uint8_t)(1u << digit(e));
-        for (int L = e; L < d; ++L) {
-            at[L] = (int64_t)nodes.size();
-            nodes.push_back((uint8_t)(1u << digit(L + 1)));
-        }
-        nodes.push_back(0);
-        if (d == D) caps.push_back(1);
-    }
-}
 
 // ---- zstd (the system's libzstd, loaded on first use)
 struct Zstd {
@@ -425,8 +498,7 @@ potr_status potr_codec_encode(int64_t N, const float* means, const float* scales
     h.sf[1] = prm->sf_rot;
     h.sf[2] = prm->sf_opac;
     h.sf[3] = prm->sf_sh;
-    std::vector<uint8_t> nodes;
-    std::vector<uint32_t> caps;
+    uint64_t n_nodes = 0, n_caps = 0;
     potr_status st = POTR_OK;
     if (N > 0) {
         // root cube
@@ -494,31 +566,66 @@ potr_status potr_codec_encode(int64_t N, const float* means, const float* scales
         if (leaf_order &&
             (st = hip_ok(hipMemcpyAsync(leaf_order, w.idx, (size_t)N * 4, hipMemcpyDeviceToDevice, s), "leaf order")))
             return st;
-        std::vector<uint64_t> code((size_t)N);
-        std::vector<uint8_t> enter((size_t)N), leaf((size_t)N);
+        // the octree bytes and the cap-leaf counts, on the device
+        hipLaunchKernelGGL(k_codec_count, grid, dim3(kThreads), 0, s, N, (const uint8_t*)w.enter,
+                           (const uint8_t*)w.leaf, D, w.nb, w.capf);
+        if ((st = check_launch("k_codec_count")) != POTR_OK) return st;
+        tb = w.sort_bytes;
+        if ((st = hip_ok(hipcub::DeviceScan::ExclusiveSum(w.sort_tmp, tb, (const uint64_t*)w.nb, w.off, (int)N, s),
+                         "scan of the node bytes")))
+            return st;
+        tb = w.sort_bytes;
+        if ((st = hip_ok(hipcub::DeviceScan::ExclusiveSum(w.sort_tmp, tb, (const uint32_t*)w.capf, w.capoff, (int)N, s),
+                         "scan of the cap leaves")))
+            return st;
+        hipLaunchKernelGGL(k_codec_own, grid, dim3(kThreads), 0, s, N, (const uint64_t*)w.code,
+                           (const uint8_t*)w.enter, (const uint8_t*)w.leaf, (const uint64_t*)w.off, D, w.nodes);
+        if ((st = check_launch("k_codec_own")) != POTR_OK) return st;
+        for (int l = 0; l < D; ++l) {
+            hipLaunchKernelGGL(k_codec_flag, grid, dim3(kThreads), 0, s, N, (const uint8_t*)w.enter, l, w.f);
+            if ((st = check_launch("k_codec_flag")) != POTR_OK) return st;
+            tb = w.sort_bytes;
+            if ((st = hip_ok(hipcub::DeviceScan::InclusiveScan(w.sort_tmp, tb, (const int32_t*)w.f, w.last,
+                                                                hipcub::Max(), (int)N, s),
+                             "running last entry")))
+                return st;
+            hipLaunchKernelGGL(k_codec_branch, grid, dim3(kThreads), 0, s, N, (const uint64_t*)w.code,
+                               (const uint8_t*)w.enter, (const uint64_t*)w.off, (const int32_t*)w.last, l, D,
+                               (uint32_t*)w.nodes);
+            if ((st = check_launch("k_codec_branch")) != POTR_OK) return st;
+        }
+        hipLaunchKernelGGL(k_codec_caps, grid, dim3(kThreads), 0, s, N, (const uint8_t*)w.enter,
+                           (const uint32_t*)w.capf, (const uint32_t*)w.capoff, D, w.caps);
+        if ((st = check_launch("k_codec_caps")) != POTR_OK) return st;
+        uint64_t last_off = 0, last_nb = 0;
+        uint32_t last_capoff = 0, last_capf = 0;
         int flag = 0;
-        if ((st = hip_ok(hipMemcpyAsync(code.data(), w.code, (size_t)N * 8, hipMemcpyDeviceToHost, s), "codes")) ||
-            (st = hip_ok(hipMemcpyAsync(enter.data(), w.enter, (size_t)N, hipMemcpyDeviceToHost, s), "depths")) ||
-            (st = hip_ok(hipMemcpyAsync(leaf.data(), w.leaf, (size_t)N, hipMemcpyDeviceToHost, s), "depths")) ||
+        if ((st = hip_ok(hipMemcpyAsync(&last_off, w.off + (N - 1), 8, hipMemcpyDeviceToHost, s), "totals")) ||
+            (st = hip_ok(hipMemcpyAsync(&last_nb, w.nb + (N - 1), 8, hipMemcpyDeviceToHost, s), "totals")) ||
+            (st = hip_ok(hipMemcpyAsync(&last_capoff, w.capoff + (N - 1), 4, hipMemcpyDeviceToHost, s), "totals")) ||
+            (st = hip_ok(hipMemcpyAsync(&last_capf, w.capf + (N - 1), 4, hipMemcpyDeviceToHost, s), "totals")) ||
             (st = hip_ok(hipMemcpyAsync(&flag, w.flag, 4, hipMemcpyDeviceToHost, s), "flag")) ||
             (st = hip_ok(hipStreamSynchronize(s), "codec")))
             return st;
         if (flag) return fail(POTR_EINVAL, "a quantised value leaves the int32 range");
-        nodes.reserve((size_t)N * 2);
-        emit_nodes(N, D, code, enter, leaf, nodes, caps);
+        n_nodes = last_off + last_nb;
+        n_caps = (uint64_t)last_capoff + last_capf;
     }
-    h.n_nodes = nodes.size();
-    h.n_caps = caps.size();
-    const size_t total = sizeof(Header) + nodes.size() + 4 * caps.size() + 4 * (size_t)N * S;
+    h.n_nodes = n_nodes;
+    h.n_caps = n_caps;
+    const size_t total = sizeof(Header) + (size_t)n_nodes + 4 * (size_t)n_caps + 4 * (size_t)N * S;
     *raw_bytes = total;
     if (total > raw_cap) return fail(POTR_ECAPACITY, "bitstream of %zu bytes, buffer of %zu", total, raw_cap);
     uint8_t* p = raw;
     std::memcpy(p, &h, sizeof(Header));
     p += sizeof(Header);
-    if (!nodes.empty()) std::memcpy(p, nodes.data(), nodes.size());
-    p += nodes.size();
-    if (!caps.empty()) std::memcpy(p, caps.data(), 4 * caps.size());
-    p += 4 * caps.size();
+    if (n_nodes > 0 &&
+        (st = hip_ok(hipMemcpyAsync(p, w.nodes, (size_t)n_nodes, hipMemcpyDeviceToHost, s), "node bytes")))
+        return st;
+    p += n_nodes;
+    if (n_caps > 0 && (st = hip_ok(hipMemcpyAsync(p, w.caps, 4 * (size_t)n_caps, hipMemcpyDeviceToHost, s), "caps")))
+        return st;
+    p += 4 * n_caps;
     if (N > 0) {
         if ((st = hip_ok(hipMemcpyAsync(p, w.streams, 4 * (size_t)N * S, hipMemcpyDeviceToHost, s), "streams")))
             return st;
