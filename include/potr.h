@@ -281,7 +281,19 @@ typedef struct potr_outputs {
     float* importance;
     int64_t importance_stride;
     float importance_weight;
+    int32_t fixed_point;   /* 1: the three arrays are int64 fixed-point sums (below) */
 } potr_outputs;
+
+/* potr_fixed_to_float -- out[i] = acc[i] * 2^-32 for n elements (device arrays).
+ * For callers that need run-to-run reproducible sums: with
+ * potr_outputs.fixed_point = 1, scores, scores_se and importance point to int64
+ * arrays in units of 2^-32 (strides in elements). Each wave's sum of a (tile,
+ * splat) is rounded to that grid, and the sums over waves, tiles and views are
+ * integer adds, which commute: the result does not depend on the order the
+ * hardware takes them in, so repeated runs give the same bits. The rounding
+ * costs at most 2^-33 per wave sum; totals must stay below 2^31 in magnitude.
+ * The fused pass in this mode keeps 8-byte per-entry sums in LDS. */
+POTR_API potr_status potr_fixed_to_float(const int64_t* acc, int64_t n, float* out, void* stream);
 
 /* potr_render_score_out -- potr_render_score with its reductions described by
  * `out` (host struct): per-view arrays and weights as above. image may be NULL;

@@ -40,7 +40,8 @@ class potr_config(C.Structure):
 class potr_outputs(C.Structure):
     _fields_ = [("scores", C.c_void_p), ("scores_stride", C.c_int64), ("scores_weight", C.c_float),
                 ("scores_se", C.c_void_p), ("se_stride", C.c_int64), ("se_weight", C.c_float),
-                ("importance", C.c_void_p), ("importance_stride", C.c_int64), ("importance_weight", C.c_float)]
+                ("importance", C.c_void_p), ("importance_stride", C.c_int64), ("importance_weight", C.c_float),
+                ("fixed_point", C.c_int32)]
 
 
 class potr_job(C.Structure):
@@ -95,6 +96,7 @@ SIGNATURES = {
     "potr_codec_decompress": (_i32, [_vp, _sz, _vp, _sz, C.POINTER(_sz)]),
     "potr_codec_info": (_i32, [_vp, _sz, C.POINTER(_i64), C.POINTER(_i32)]),
     "potr_codec_decode": (_i32, [_vp, _sz, _vp, _vp, _vp, _vp, _vp]),
+    "potr_fixed_to_float": (_i32, [_vp, _i64, _vp, _vp]),
     "potr_prune_select_noalloc": (_i32, [_i64, _vp, _vp, C.c_double, _i32, C.c_double, _vp, _vp, _vp]),
     "potr_prune_compact": (_i32, [_i64] + [_vp] * 7 + [_vp, _sz] + [_vp] * 7 + [_vp]),
     "potr_autotune": (_i32, [_JOB_P, _i32, _CFG_P, _i32, C.POINTER(C.c_double), _CFG_P, C.POINTER(C.c_double),
@@ -166,13 +168,18 @@ def make_outputs(o, v0: int = 0) -> potr_outputs:
     """potr_outputs for an `Outputs` description (raster.py), its arrays
     starting at view v0 of theirs."""
     c = potr_outputs()
+    fixed = bool(getattr(o, "fixed_point", False))
+    elem = 8 if fixed else 4
     for name, stride, weight in (("scores", "scores_stride", "scores_weight"), ("scores_se", "se_stride", "se_weight"),
                                  ("importance", "importance_stride", "importance_weight")):
         t = getattr(o, name)
         st = int(getattr(o, stride))
-        setattr(c, name, None if t is None else t.data_ptr() + 4 * v0 * st)
+        if t is not None and t.element_size() != elem:
+            raise ValueError(f"{name}: {'int64' if fixed else 'float32'} elements expected")
+        setattr(c, name, None if t is None else t.data_ptr() + elem * v0 * st)
         setattr(c, stride, st)
         setattr(c, weight, float(getattr(o, weight)))
+    c.fixed_point = 1 if fixed else 0
     return c
 
 

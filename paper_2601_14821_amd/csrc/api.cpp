@@ -267,10 +267,15 @@ potr_status potr_render_score_out(int64_t N, int32_t V, const potr_camera* cams,
             j.target = target ? target + v * P * 3 : nullptr;
             set_outputs(j, *out, N, v);
         }
-        st = launch_render_score(jobs, nv, T, *cfg, (hipStream_t)stream);
+        st = launch_render_score(jobs, nv, T, *cfg, out->fixed_point != 0, (hipStream_t)stream);
         if (st != POTR_OK) return st;
     }
     return POTR_OK;
+}
+
+potr_status potr_fixed_to_float(const int64_t* acc, int64_t n, float* out, void* stream) {
+    if (n < 0 || (n > 0 && (!acc || !out))) return fail(POTR_EINVAL, "bad argument");
+    return launch_fixed_to_float(n, acc, out, (hipStream_t)stream);
 }
 
 potr_status potr_render_score(int64_t N, int32_t V, const potr_camera* cams, const potr_config* cfg,

@@ -46,6 +46,7 @@ struct potr_batch_s {
     int64_t n_items = 0;    // (view, tile) items of the render launch (none: no job asks for outputs)
     int32_t grid = 0;
     bool with_se = false;   // some job asks for dSE sums
+    bool fixed = false;     // the jobs' outputs are fixed-point sums
     int n_out = 1;          // the most per-splat outputs of any job
     char* ws = nullptr;
     hipGraph_t graph = nullptr;
@@ -126,6 +127,7 @@ bool has_step(const potr_job& J) { return J.grad_target != nullptr; }
 
 potr_status validate_jobs(const potr_job* jobs, int32_t n_jobs, bool need_output = true) {
     if (!jobs || n_jobs < 1) return fail(POTR_EINVAL, "need at least one job");
+    int fixed_mode = -1;   // the fixed_point of the first job with outputs
     for (int32_t j = 0; j < n_jobs; ++j) {
         const potr_job& J = jobs[j];
         if (J.N < 0 || J.V < 1 || J.N * (int64_t)J.V >= (int64_t(1) << 31) || !J.cams)
@@ -143,6 +145,11 @@ potr_status validate_jobs(const potr_job* jobs, int32_t n_jobs, bool need_output
         }
         if (J.N > 0 && (reinterpret_cast<uintptr_t>(J.sh) & 15u) != 0)
             return fail(POTR_EINVAL, "job %d: sh must be 16-byte aligned", j);
+        if (has_output(J)) {
+            if (fixed_mode < 0) fixed_mode = J.out.fixed_point;
+            if (J.out.fixed_point != fixed_mode)
+                return fail(POTR_EINVAL, "job %d: all jobs' outputs must be fixed point or none", j);
+        }
     }
     return POTR_OK;
 }
@@ -220,12 +227,14 @@ potr_status potr_batch_create(const potr_job* jobs, int32_t n_jobs, const potr_c
     plan_layout(b);
     b->with_se = false;
     b->n_out = 1;
+    b->fixed = false;
     for (auto& J : b->jobs) {
         b->with_se = b->with_se || (J.N > 0 && J.out.scores_se != nullptr);
         const int n = (J.out.scores ? 1 : 0) + (J.out.importance ? 1 : 0) + (J.out.scores_se ? 1 : 0);
         b->n_out = std::max(b->n_out, n);
+        b->fixed = b->fixed || (has_output(J) && J.out.fixed_point != 0);
     }
-    b->grid = persistent_grid(b->cfg, b->n_out);
+    b->grid = persistent_grid(b->cfg, b->n_out, b->fixed);
     if (b->lane_off.size() > 1) {
         st = POTR_OK;
         for (size_t l = 0; l < b->lane_off.size() && st == POTR_OK; ++l) {
@@ -376,7 +385,7 @@ potr_status potr_batch_run(potr_batch b, void* stream) {
         potr_status st = launch_render_score_persistent((const ViewJob*)(ws + b->off_table), b->n_view_jobs,
                                                         (const int64_t*)(ws + b->off_prefix),
                                                         (int64_t*)(ws + b->off_counter), b->grid, b->cfg,
-                                                        b->with_se, b->n_out, s);
+                                                        b->with_se, b->n_out, b->fixed, s);
         if (st != POTR_OK) return st;
     }
     return launch_check_overflow(npairs, (const int64_t*)(ws + b->off_caps), (int32_t)b->jobs.size(),
@@ -389,7 +398,7 @@ potr_status potr_batch_render(potr_batch b, void* stream) {
     if (b->n_items == 0) return POTR_OK;   // no job asks for outputs
     return launch_render_score_persistent((const ViewJob*)(ws + b->off_table), b->n_view_jobs,
                                           (const int64_t*)(ws + b->off_prefix), (int64_t*)(ws + b->off_counter),
-                                          b->grid, b->cfg, b->with_se, b->n_out, (hipStream_t)stream);
+                                          b->grid, b->cfg, b->with_se, b->n_out, b->fixed, (hipStream_t)stream);
 }
 
 potr_status potr_batch_capture(potr_batch b, void* stream) {
@@ -470,7 +479,8 @@ extern "C" potr_status potr_autotune(const potr_job* jobs, int32_t n_jobs, potr_
             if (!*outs[o]) continue;
             const int64_t n = strides[o] > 0 ? (int64_t)(J.V - 1) * strides[o] + J.N : J.N;
             float* p = nullptr;
-            st = hip_ok(hipMalloc(&p, (size_t)(n > 0 ? n : 1) * 4), "hipMalloc (scratch outputs)");
+            // 8 bytes per element: room for fixed-point outputs too
+            st = hip_ok(hipMalloc(&p, (size_t)(n > 0 ? n : 1) * 8), "hipMalloc (scratch outputs)");
             if (st != POTR_OK) break;
             bufs.push_back(p);
             *outs[o] = p;

@@ -11,6 +11,8 @@
 // gather. The arithmetic per (pixel, splat) is that of potr_blend / potr_score
 // (raster_eval.h): the images are the same bit for bit, the per-splat sums up to
 // the order of their float additions.
+#include <algorithm>
+
 #include "common.h"
 #include "dpp.h"
 #include "fused.h"
@@ -64,7 +66,13 @@ __device__ inline void list4(const uint16_t* L, int i, int (&j)[4]) {
     j[3] = (int)(y >> 16);
 }
 
-template <int TW, int TH, bool SE>
+// Fixed point (FX): per-splat sums in int64 units of 2^-32, added in integers
+// (which commute), so that every run gives the same bits whatever the order of
+// the waves' and tiles' additions.
+constexpr double kFixedOne = 4294967296.0;   // 2^32
+__device__ inline unsigned long long to_fixed(double x) { return (unsigned long long)__double2ll_rn(x * kFixedOne); }
+
+template <int TW, int TH, bool SE, bool FX>
 __device__ void render_score_tile(const ViewJob& J, int tile, const potr_config& cfg, const Smem& sm) {
     constexpr int NT = TW * TH;
     constexpr int NW = (NT + 63) / 64;
@@ -179,7 +187,11 @@ __device__ void render_score_tile(const ViewJob& J, int tile, const potr_config&
     // ---- removal sweep over the walked prefix
     if (threadIdx.x == 0) sm.misc[0] = 0;
     // per-entry sums start at zero (the flush clears what it reads)
-    for (int j = threadIdx.x; j < n_out * B; j += NT) sm.part[j] = 0.f;
+    long long* const part64 = reinterpret_cast<long long*>(sm.part);   // FX: the sums as fixed point
+    for (int j = threadIdx.x; j < n_out * B; j += NT) {
+        if constexpr (FX) part64[j] = 0;
+        else sm.part[j] = 0.f;
+    }
     __syncthreads();
     if (walk > 0) atomicMax(&sm.misc[0], walk);
     __syncthreads();
@@ -262,30 +274,57 @@ __device__ void render_score_tile(const ViewJob& J, int tile, const potr_config&
             const bool writer = lane < ng;
             if (J.scores) {
                 const float s = wave_sum4(l1v[0], l1v[1], l1v[2], l1v[3]);
-                if (writer) atomicAdd(&sm.part[o_l1 * B + jw], s);
+                if (writer) {
+                    if constexpr (FX) atomicAdd((unsigned long long*)&part64[o_l1 * B + jw], to_fixed(s));
+                    else atomicAdd(&sm.part[o_l1 * B + jw], s);
+                }
             }
             if (J.importance) {
                 const float s = wave_sum4(imv[0], imv[1], imv[2], imv[3]);
-                if (writer) atomicAdd(&sm.part[o_im * B + jw], s);
+                if (writer) {
+                    if constexpr (FX) atomicAdd((unsigned long long*)&part64[o_im * B + jw], to_fixed(s));
+                    else atomicAdd(&sm.part[o_im * B + jw], s);
+                }
             }
             if (se) {
                 const float s = wave_sum4(sev[0], sev[1], sev[2], sev[3]);
-                if (writer) atomicAdd(&sm.part[o_se * B + jw], s);
+                if (writer) {
+                    if constexpr (FX) atomicAdd((unsigned long long*)&part64[o_se * B + jw], to_fixed(s));
+                    else atomicAdd(&sm.part[o_se * B + jw], s);
+                }
             }
         }
         __syncthreads();
         for (int j = threadIdx.x; j < cnt; j += NT) {
             const uint32_t id = __float_as_uint(sm.rec[j].c.y);
-            float t[3] = {0.f, 0.f, 0.f};
+            if constexpr (FX) {
+                // the weight scales the exact sum (an int64 below 2^53 converts exactly), one rounding
+                long long t[3] = {0, 0, 0};
 #pragma unroll
-            for (int o = 0; o < 3; ++o)
-                if (o < n_out) {
-                    t[o] = sm.part[o * B + j];
-                    sm.part[o * B + j] = 0.f;
-                }
-            if (J.scores && t[o_l1] != 0.f) unsafeAtomicAdd(J.scores + id, t[o_l1] * J.w_l1);
-            if (J.importance && t[o_im] != 0.f) unsafeAtomicAdd(J.importance + id, t[o_im] * J.w_im);
-            if (se && t[o_se] != 0.f) unsafeAtomicAdd(J.scores_se + id, t[o_se] * J.w_se);
+                for (int o = 0; o < 3; ++o)
+                    if (o < n_out) {
+                        t[o] = part64[o * B + j];
+                        part64[o * B + j] = 0;
+                    }
+                auto add = [&](float* out, long long v, float w) {
+                    atomicAdd(reinterpret_cast<unsigned long long*>(out) + id,
+                              (unsigned long long)__double2ll_rn((double)v * (double)w));
+                };
+                if (J.scores && t[o_l1] != 0) add(J.scores, t[o_l1], J.w_l1);
+                if (J.importance && t[o_im] != 0) add(J.importance, t[o_im], J.w_im);
+                if (se && t[o_se] != 0) add(J.scores_se, t[o_se], J.w_se);
+            } else {
+                float t[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+                for (int o = 0; o < 3; ++o)
+                    if (o < n_out) {
+                        t[o] = sm.part[o * B + j];
+                        sm.part[o * B + j] = 0.f;
+                    }
+                if (J.scores && t[o_l1] != 0.f) unsafeAtomicAdd(J.scores + id, t[o_l1] * J.w_l1);
+                if (J.importance && t[o_im] != 0.f) unsafeAtomicAdd(J.importance + id, t[o_im] * J.w_im);
+                if (se && t[o_se] != 0.f) unsafeAtomicAdd(J.scores_se + id, t[o_se] * J.w_se);
+            }
         }
     }
     __syncthreads();
@@ -303,12 +342,12 @@ __device__ inline Smem carve(char* base, int B) {
     return s;
 }
 
-template <int TW, int TH, bool SE>
+template <int TW, int TH, bool SE, bool FX>
 __global__ __launch_bounds__(TW * TH) __attribute__((amdgpu_waves_per_eu(7))) void k_render_score(ViewJobs jobs, potr_config cfg) {
     extern __shared__ __align__(16) char smem[];
     const Smem sm = carve<TW, TH>(smem, cfg.lds_batch);
     const ViewJob J = jobs.j[blockIdx.y];
-    render_score_tile<TW, TH, SE>(J, blockIdx.x, cfg, sm);
+    render_score_tile<TW, TH, SE, FX>(J, blockIdx.x, cfg, sm);
 }
 
 // Persistent form: items are (view job, tile) pairs numbered job-major;
@@ -316,7 +355,7 @@ __global__ __launch_bounds__(TW * TH) __attribute__((amdgpu_waves_per_eu(7))) vo
 // waves per SIMD the persistent form is compiled for (its register budget)
 constexpr int kPersistentWaves = 7;
 
-template <int TW, int TH, bool SE>
+template <int TW, int TH, bool SE, bool FX>
 __global__ __launch_bounds__(TW * TH) __attribute__((amdgpu_waves_per_eu(kPersistentWaves))) void k_render_score_persistent(const ViewJob* __restrict__ jobs, int32_t n_jobs,
                                                                      const int64_t* __restrict__ item_prefix,
                                                                      int64_t* __restrict__ counter, potr_config cfg) {
@@ -337,54 +376,77 @@ __global__ __launch_bounds__(TW * TH) __attribute__((amdgpu_waves_per_eu(kPersis
             else hi = mid - 1;
         }
         const ViewJob J = jobs[lo];
-        render_score_tile<TW, TH, SE>(J, (int)(item - item_prefix[lo]), cfg, sm);
+        render_score_tile<TW, TH, SE, FX>(J, (int)(item - item_prefix[lo]), cfg, sm);
     }
 }
 
 __global__ void k_zero_i64(int64_t* p) { *p = 0; }
 
+__global__ void k_fixed_to_float(int64_t n, const long long* __restrict__ acc, float* __restrict__ out) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        out[i] = (float)((double)acc[i] * (1.0 / kFixedOne));
+}
+
+// per-entry sums: 4 bytes each, 8 in fixed point
 template <int TW, int TH>
-size_t smem_bytes(int B, int n_out) {
+size_t smem_bytes(int B, int n_out, bool fx) {
     constexpr int NW = (TW * TH + 63) / 64;
-    return (size_t)B * sizeof(Rec) + (size_t)NW * B * 4 + 16 + (size_t)n_out * B * 4;
+    return (size_t)B * sizeof(Rec) + (size_t)NW * B * 4 + 16 + (size_t)n_out * B * (fx ? 8 : 4);
+}
+
+template <int TW, int TH, bool SE>
+void launch_plain(const ViewJobs& jobs_dev, dim3 grid, size_t sm, const potr_config& cfg, bool fx, hipStream_t s) {
+    if (fx) hipLaunchKernelGGL((k_render_score<TW, TH, SE, true>), grid, dim3(TW * TH), sm, s, jobs_dev, cfg);
+    else hipLaunchKernelGGL((k_render_score<TW, TH, SE, false>), grid, dim3(TW * TH), sm, s, jobs_dev, cfg);
+}
+
+template <int TW, int TH, bool SE>
+void launch_pers(const ViewJob* jobs_dev, int32_t n_jobs, const int64_t* item_prefix_dev, int64_t* counter_dev,
+                 dim3 grid, size_t sm, const potr_config& cfg, bool fx, hipStream_t s) {
+    if (fx)
+        hipLaunchKernelGGL((k_render_score_persistent<TW, TH, SE, true>), grid, dim3(TW * TH), sm, s, jobs_dev,
+                           n_jobs, item_prefix_dev, counter_dev, cfg);
+    else
+        hipLaunchKernelGGL((k_render_score_persistent<TW, TH, SE, false>), grid, dim3(TW * TH), sm, s, jobs_dev,
+                           n_jobs, item_prefix_dev, counter_dev, cfg);
 }
 
 }  // namespace
 
-size_t fused_smem_bytes(const potr_config& cfg, int n_out) {
-    if (cfg.tile_w == 8) return smem_bytes<8, 8>(cfg.lds_batch, n_out);
-    if (cfg.tile_w == 32) return smem_bytes<32, 8>(cfg.lds_batch, n_out);
-    return smem_bytes<16, 16>(cfg.lds_batch, n_out);
+size_t fused_smem_bytes(const potr_config& cfg, int n_out, bool fx) {
+    if (cfg.tile_w == 8) return smem_bytes<8, 8>(cfg.lds_batch, n_out, fx);
+    if (cfg.tile_w == 32) return smem_bytes<32, 8>(cfg.lds_batch, n_out, fx);
+    return smem_bytes<16, 16>(cfg.lds_batch, n_out, fx);
 }
 
 potr_status launch_render_score(const ViewJobs& jobs_dev, int32_t n_views, int32_t tiles_per_view,
-                                const potr_config& cfg, hipStream_t s) {
+                                const potr_config& cfg, bool fx, hipStream_t s) {
     // the views of one call share their set of outputs
     const ViewJob& j0 = jobs_dev.j[0];
     const int n_out = (j0.scores ? 1 : 0) + (j0.importance ? 1 : 0) + (j0.scores_se ? 1 : 0);
-    const size_t sm = fused_smem_bytes(cfg, n_out);
+    const size_t sm = fused_smem_bytes(cfg, n_out, fx);
     const dim3 grid(tiles_per_view, n_views);
     const bool se = jobs_dev.j[0].scores_se != nullptr;
     if (cfg.tile_w == 16 && cfg.tile_h == 16) {
-        if (se) hipLaunchKernelGGL((k_render_score<16, 16, true>), grid, dim3(256), sm, s, jobs_dev, cfg);
-        else hipLaunchKernelGGL((k_render_score<16, 16, false>), grid, dim3(256), sm, s, jobs_dev, cfg);
+        if (se) launch_plain<16, 16, true>(jobs_dev, grid, sm, cfg, fx, s);
+        else launch_plain<16, 16, false>(jobs_dev, grid, sm, cfg, fx, s);
     } else if (cfg.tile_w == 8 && cfg.tile_h == 8) {
-        if (se) hipLaunchKernelGGL((k_render_score<8, 8, true>), grid, dim3(64), sm, s, jobs_dev, cfg);
-        else hipLaunchKernelGGL((k_render_score<8, 8, false>), grid, dim3(64), sm, s, jobs_dev, cfg);
+        if (se) launch_plain<8, 8, true>(jobs_dev, grid, sm, cfg, fx, s);
+        else launch_plain<8, 8, false>(jobs_dev, grid, sm, cfg, fx, s);
     } else if (cfg.tile_w == 32 && cfg.tile_h == 8) {
-        if (se) hipLaunchKernelGGL((k_render_score<32, 8, true>), grid, dim3(256), sm, s, jobs_dev, cfg);
-        else hipLaunchKernelGGL((k_render_score<32, 8, false>), grid, dim3(256), sm, s, jobs_dev, cfg);
+        if (se) launch_plain<32, 8, true>(jobs_dev, grid, sm, cfg, fx, s);
+        else launch_plain<32, 8, false>(jobs_dev, grid, sm, cfg, fx, s);
     } else {
         return fail(POTR_EUNSUPPORTED, "tile %dx%d not built", cfg.tile_w, cfg.tile_h);
     }
     return check_launch("k_render_score");
 }
 
-int persistent_grid(const potr_config& cfg, int n_out) {
+int persistent_grid(const potr_config& cfg, int n_out, bool fx) {
     int dev = 0, cus = 256;
     if (hipGetDevice(&dev) == hipSuccess) hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     const int threads = cfg.tile_w * cfg.tile_h;
-    const size_t sm = fused_smem_bytes(cfg, n_out);
+    const size_t sm = fused_smem_bytes(cfg, n_out, fx);
     int by_waves = 4 * kPersistentWaves / ((threads + 63) / 64);   // 4 SIMDs per CU
     int by_lds = (int)((160 * 1024) / (sm + 256));
     int per_cu = by_waves < by_lds ? by_waves : by_lds;
@@ -394,19 +456,16 @@ int persistent_grid(const potr_config& cfg, int n_out) {
 
 template <bool SE>
 potr_status launch_persistent(const ViewJob* jobs_dev, int32_t n_jobs, const int64_t* item_prefix_dev,
-                              int64_t* counter_dev, int32_t grid_size, const potr_config& cfg, int n_out,
+                              int64_t* counter_dev, int32_t grid_size, const potr_config& cfg, int n_out, bool fx,
                               hipStream_t s) {
-    const size_t sm = fused_smem_bytes(cfg, n_out);
+    const size_t sm = fused_smem_bytes(cfg, n_out, fx);
     const dim3 grid(grid_size);
     if (cfg.tile_w == 16 && cfg.tile_h == 16)
-        hipLaunchKernelGGL((k_render_score_persistent<16, 16, SE>), grid, dim3(256), sm, s, jobs_dev, n_jobs,
-                           item_prefix_dev, counter_dev, cfg);
+        launch_pers<16, 16, SE>(jobs_dev, n_jobs, item_prefix_dev, counter_dev, grid, sm, cfg, fx, s);
     else if (cfg.tile_w == 8 && cfg.tile_h == 8)
-        hipLaunchKernelGGL((k_render_score_persistent<8, 8, SE>), grid, dim3(64), sm, s, jobs_dev, n_jobs,
-                           item_prefix_dev, counter_dev, cfg);
+        launch_pers<8, 8, SE>(jobs_dev, n_jobs, item_prefix_dev, counter_dev, grid, sm, cfg, fx, s);
     else if (cfg.tile_w == 32 && cfg.tile_h == 8)
-        hipLaunchKernelGGL((k_render_score_persistent<32, 8, SE>), grid, dim3(256), sm, s, jobs_dev, n_jobs,
-                           item_prefix_dev, counter_dev, cfg);
+        launch_pers<32, 8, SE>(jobs_dev, n_jobs, item_prefix_dev, counter_dev, grid, sm, cfg, fx, s);
     else
         return fail(POTR_EUNSUPPORTED, "tile %dx%d not built", cfg.tile_w, cfg.tile_h);
     return check_launch("k_render_score_persistent");
@@ -414,13 +473,21 @@ potr_status launch_persistent(const ViewJob* jobs_dev, int32_t n_jobs, const int
 
 potr_status launch_render_score_persistent(const ViewJob* jobs_dev, int32_t n_jobs, const int64_t* item_prefix_dev,
                                            int64_t* counter_dev, int32_t grid_size, const potr_config& cfg,
-                                           bool with_se, int n_out, hipStream_t s) {
+                                           bool with_se, int n_out, bool fx, hipStream_t s) {
     hipLaunchKernelGGL(k_zero_i64, dim3(1), dim3(1), 0, s, counter_dev);
     potr_status st = check_launch("k_zero_i64");
     if (st != POTR_OK) return st;
-    return with_se
-               ? launch_persistent<true>(jobs_dev, n_jobs, item_prefix_dev, counter_dev, grid_size, cfg, n_out, s)
-               : launch_persistent<false>(jobs_dev, n_jobs, item_prefix_dev, counter_dev, grid_size, cfg, n_out, s);
+    return with_se ? launch_persistent<true>(jobs_dev, n_jobs, item_prefix_dev, counter_dev, grid_size, cfg, n_out,
+                                             fx, s)
+                   : launch_persistent<false>(jobs_dev, n_jobs, item_prefix_dev, counter_dev, grid_size, cfg, n_out,
+                                              fx, s);
+}
+
+potr_status launch_fixed_to_float(int64_t n, const int64_t* acc, float* out, hipStream_t s) {
+    if (n <= 0) return POTR_OK;
+    const int blocks = (int)std::min<int64_t>(4096, (n + 255) / 256);
+    hipLaunchKernelGGL(k_fixed_to_float, dim3(blocks), dim3(256), 0, s, n, (const long long*)acc, out);
+    return check_launch("k_fixed_to_float");
 }
 
 }  // namespace potr

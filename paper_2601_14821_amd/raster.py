@@ -66,9 +66,19 @@ class Outputs:
     importance: torch.Tensor | None = None
     importance_stride: int = 0
     importance_weight: float = 1.0
+    # int64 tensors of fixed-point sums (units of 2^-32; fixed_to_float converts):
+    # the same bits on every run
+    fixed_point: bool = False
 
     def any(self) -> bool:
         return self.scores is not None or self.scores_se is not None or self.importance is not None
+
+
+def fixed_to_float(acc: torch.Tensor) -> torch.Tensor:
+    """potr_fixed_to_float: FP32 values of fixed-point sums (int64, units of 2^-32)."""
+    out = torch.empty(acc.shape, dtype=torch.float32, device=acc.device)
+    L.call("potr_fixed_to_float", L.ptr(acc), acc.numel(), L.ptr(out), L.stream_handle())
+    return out
 
 
 class Rasterizer:

@@ -54,6 +54,7 @@ def test_struct_layouts():
     # three (pointer, int64 stride, float weight) triples, each padded to 24 bytes
     assert C.sizeof(L.potr_outputs) == 72
     assert L.potr_outputs.importance_weight.offset == 64
+    assert L.potr_outputs.fixed_point.offset == 68
     assert C.sizeof(L.potr_job) == 8 * 6 + 8 + 8 + 72 + 8 + 8 + 8 + 5 * 8
 
 
