@@ -190,3 +190,28 @@ def test_outputs_se_needs_target_and_some_output(lib):
     arr = (L.potr_job * 1)(j)
     assert _status("potr_batch_create", arr, 1, C.byref(_cfg()), 0.05, C.byref(out), None) == L.POTR_EINVAL
     assert "job 0" in lib.potr_last_error().decode() and "stride" in lib.potr_last_error().decode()
+
+
+def test_fixed_point_mode_is_validated(lib):
+    o = L.potr_outputs()
+    o.scores, o.scores_weight = 16, 1.0
+    o.fixed_point = 2
+    assert _render_score_out(o) == L.POTR_EINVAL
+    assert "fixed_point" in lib.potr_last_error().decode()
+    # the jobs of one batch are all fixed point or none
+    cams = _cams(1)
+    jobs = []
+    for k in range(3):
+        j = L.potr_job()
+        j.N, j.V = 100, 1
+        j.cams = C.cast(cams, C.POINTER(L.potr_camera))
+        j.means = j.scales = j.quats = j.opac = j.sh = 16
+        j.out.scores, j.out.scores_weight = 16, 1.0
+        j.out.fixed_point = 1 if k == 2 else 0
+        jobs.append(j)
+    arr = (L.potr_job * 3)(*jobs)
+    out = C.c_void_p()
+    assert _status("potr_batch_create", arr, 3, C.byref(_cfg()), 0.05, C.byref(out), None) == L.POTR_EINVAL
+    assert "job 2" in lib.potr_last_error().decode() and "fixed point" in lib.potr_last_error().decode()
+    assert _status("potr_fixed_to_float", None, 5, None, None) == L.POTR_EINVAL
+    assert _status("potr_fixed_to_float", None, 0, None, None) == L.POTR_OK
