@@ -24,9 +24,10 @@ namespace {
 constexpr int kBwdChunk = 128;   // entries staged per round
 constexpr int kG = 9;            // gradient components per (view, splat)
 
-// Compiled for seven waves per SIMD (71 registers, no spills).
+// Compiled for seven waves per SIMD (71 registers, no spills); 8x8 tiles (one
+// wave per workgroup, its LDS arrays sized for the tile) take what fits.
 template <int TW, int TH>
-__global__ __launch_bounds__(TW * TH) __attribute__((amdgpu_waves_per_eu(7))) void k_blend_bwd(int64_t N, int32_t W, int32_t H, int32_t tiles_x,
+__global__ __launch_bounds__(TW * TH) __attribute__((amdgpu_waves_per_eu(TW * TH >= 256 ? 7 : 1))) void k_blend_bwd(int64_t N, int32_t W, int32_t H, int32_t tiles_x,
                                                        int32_t tiles_per_view, potr_config cfg,
                                                        const potr_proj* __restrict__ proj,
                                                        const uint32_t* __restrict__ ids,

@@ -182,7 +182,7 @@ potr_status count_jobs(const std::vector<potr_job>& jobs, const std::vector<std:
             for (int32_t k = 0; k < nv; ++k) out[j] += counts[k];
         }
     }
-    hipFree(tmp);
+    (void)hipFree(tmp);
     return st;
 }
 
@@ -405,15 +405,15 @@ potr_status potr_batch_capture(potr_batch b, void* stream) {
     if (!b || !b->ws) return fail(POTR_EINVAL, "batch not bound to a workspace");
     if (!stream) return fail(POTR_EINVAL, "capture needs a stream other than the null stream");
     hipStream_t s = (hipStream_t)stream;
-    if (b->exec) { hipGraphExecDestroy(b->exec); b->exec = nullptr; }
-    if (b->graph) { hipGraphDestroy(b->graph); b->graph = nullptr; }
+    if (b->exec) { (void)hipGraphExecDestroy(b->exec); b->exec = nullptr; }
+    if (b->graph) { (void)hipGraphDestroy(b->graph); b->graph = nullptr; }
     potr_status st = hip_ok(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal), "begin capture");
     if (st != POTR_OK) return st;
     const potr_status run = potr_batch_run(b, stream);
     hipGraph_t g = nullptr;
     st = hip_ok(hipStreamEndCapture(s, &g), "end capture");
     if (run != POTR_OK) {
-        if (g) hipGraphDestroy(g);
+        if (g) (void)hipGraphDestroy(g);
         return run;
     }
     if (st != POTR_OK) return st;
@@ -436,13 +436,14 @@ potr_status potr_batch_overflow(potr_batch b, int32_t* n_overflowed, void* strea
 
 potr_status potr_batch_destroy(potr_batch b) {
     if (!b) return POTR_OK;
-    if (b->exec) hipGraphExecDestroy(b->exec);
-    if (b->graph) hipGraphDestroy(b->graph);
+    // teardown: nothing to report on failure
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
     for (hipStream_t ls : b->lane_s) {
-        hipStreamSynchronize(ls);
-        hipStreamDestroy(ls);
+        (void)hipStreamSynchronize(ls);
+        (void)hipStreamDestroy(ls);
     }
-    for (hipEvent_t ev : b->lane_ev) hipEventDestroy(ev);
+    for (hipEvent_t ev : b->lane_ev) (void)hipEventDestroy(ev);
     delete b;
     return POTR_OK;
 }
@@ -518,7 +519,7 @@ extern "C" potr_status potr_autotune(const potr_job* jobs, int32_t n_jobs, potr_
             if (st == POTR_OK) st = hip_ok(hipEventRecord(e1, s), "event record");
             if (st == POTR_OK) st = hip_ok(hipEventSynchronize(e1), "event sync");
             if (st == POTR_OK) st = hip_ok(hipEventElapsedTime(&ms, e0, e1), "elapsed");
-            if (ws) hipFree(ws);
+            if (ws) (void)hipFree(ws);
             potr_batch_destroy(b);
             if (st != POTR_OK) break;
             const double per = ms / reps;
@@ -531,9 +532,9 @@ extern "C" potr_status potr_autotune(const potr_job* jobs, int32_t n_jobs, potr_
             }
         }
     }
-    if (e0) hipEventDestroy(e0);
-    if (e1) hipEventDestroy(e1);
-    for (float* p : bufs) hipFree(p);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    for (float* p : bufs) (void)hipFree(p);
     if (n_tried) *n_tried = k;
     if (st != POTR_OK) return st;
     if (k == 0) return fail(POTR_EINVAL, "no candidate fits: a job's pairs exceed one call's limit at every shape");

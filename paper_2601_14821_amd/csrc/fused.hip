@@ -75,7 +75,6 @@ __device__ inline unsigned long long to_fixed(double x) { return (unsigned long 
 template <int TW, int TH, bool SE, bool FX>
 __device__ void render_score_tile(const ViewJob& J, int tile, const potr_config& cfg, const Smem& sm) {
     constexpr int NT = TW * TH;
-    constexpr int NW = (NT + 63) / 64;
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     const int tile_y0 = (tile / J.tiles_x) * TH;
     const int px = (tile % J.tiles_x) * TW + (int)(threadIdx.x % TW);
@@ -444,7 +443,9 @@ potr_status launch_render_score(const ViewJobs& jobs_dev, int32_t n_views, int32
 
 int persistent_grid(const potr_config& cfg, int n_out, bool fx) {
     int dev = 0, cus = 256;
-    if (hipGetDevice(&dev) == hipSuccess) hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        cus = 256;
     const int threads = cfg.tile_w * cfg.tile_h;
     const size_t sm = fused_smem_bytes(cfg, n_out, fx);
     int by_waves = 4 * kPersistentWaves / ((threads + 63) / 64);   // 4 SIMDs per CU
