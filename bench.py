@@ -226,7 +226,10 @@ def main_line(args, torch, raster, synth, batch):
                 "kernel_ms": round(kernel_ms, 4), "flops_per_walked_pair": FLOPS_PER_WALKED, "walked_pairs": int(visited),
                 "achieved_counted": round(achieved_counted, 3),
                 "frac_counted": round(achieved_counted / FP32_VECTOR_PEAK_TFLOPS, 4),
-                "valu_issue": None if valu is None else round(valu / (VALU_ISSUE_PER_S * kernel_ms / 1000.0), 4)}
+                "valu_issue": None if valu is None else round(valu / (VALU_ISSUE_PER_S * kernel_ms / 1000.0), 4),
+                "traffic_gbs": None if ctr is None else round(ctr["bytes_per_launch"] / 1e9 / (kernel_ms / 1000.0), 1),
+                "hbm_frac": None if ctr is None else round(ctr["bytes_per_launch"] / 1e9 / (kernel_ms / 1000.0)
+                                                           / HBM_PEAK_GBS, 4)}
     gs = lambda t: round(N * V / (t / 1000.0) / 1e9, 4)
     out = {
         "value": gs(ms),
