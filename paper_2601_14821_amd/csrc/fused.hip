@@ -139,15 +139,21 @@ __device__ void render_score_tile(const ViewJob& J, int tile, const potr_config&
                 const float4 b = rb[u];
                 const float a0 = alpha_of(eval_gauss(ra[u], b, fx, fy), emin, amin, amax);
                 const float al = done ? 0.f : a0;
-                const float Tn = next_T(T, al);
+                float Tn = next_T(T, al);
                 const bool stop = Tn < tmin;       // T >= tmin before, so only when al > 0
-                const float w = stop ? 0.f : __fmul_rn(T, al);
+                float w = __fmul_rn(T, al);
+                // a lane stops once per tile: only entries where some lane of the
+                // wave stops take the selects (the lane keeps T and adds nothing)
+                if (__ballot(stop) != 0) {
+                    w = stop ? 0.f : w;
+                    Tn = stop ? T : Tn;
+                    walk = stop ? wofs + j : walk;
+                    done = done || stop;
+                }
                 cr = add_weighted(cr, w, b.z);
                 cg = add_weighted(cg, w, b.w);
                 cb = add_weighted(cb, w, rc[u]);
-                T = stop ? T : Tn;
-                walk = stop ? wofs + j : walk;
-                done = done || stop;
+                T = Tn;
                 if ((__ballot(al != 0.f) & ~__ballot(stop)) != 0) {
                     if (lane == 0) Hl[nh] = (uint16_t)j;
                     ++nh;
