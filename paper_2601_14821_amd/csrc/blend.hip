@@ -98,16 +98,22 @@ __global__ __launch_bounds__(TW * TH) void k_blend(int64_t N, int32_t W, int32_t
                 const float4 b = s_b[j];
                 const float a0 = alpha_of(eval_gauss(s_a[j], b, fx, fy), emin, amin, amax);
                 const float al = done ? 0.f : a0;
-                const float Tn = next_T(T, al);
+                float Tn = next_T(T, al);
                 const bool stop = Tn < tmin;       // T >= tmin before, so only when al > 0
-                const float w = stop ? 0.f : __fmul_rn(T, al);
+                float w = __fmul_rn(T, al);
+                // a lane stops once per tile: only entries where some lane of the
+                // wave stops take the selects (the lane keeps T and adds nothing)
+                if (__ballot(stop) != 0) {
+                    w = stop ? 0.f : w;
+                    Tn = stop ? T : Tn;
+                    walk = stop ? base - beg + j : walk;
+                    done = done || stop;
+                }
                 cr = add_weighted(cr, w, b.z);
                 cg = add_weighted(cg, w, b.w);
                 cb = add_weighted(cb, w, s_c[j]);
-                T = stop ? T : Tn;
-                walk = stop ? base - beg + j : walk;
+                T = Tn;
                 blended += (al != 0.f && !stop) ? 1 : 0;
-                done = done || stop;
             }
             if (__ballot(!done) == 0) break;
         }
