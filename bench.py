@@ -20,7 +20,11 @@ Also reported (extra fields):
            batch picked by the autotuner on the whole batch, then one HIP-graph
            replay of the batched persistent scorer;
   fwd_bwd: 1M splats x 4 views at 1280x720, forward + L1 loss gradient +
-           hand-written backward, ms per view.
+           hand-written backward, ms per view;
+  codec:   the compressed format of the full scene (encode, zstd, decode);
+  prune_sh: on the full scene, one pruning select and the survivor
+           compaction (statistics over 8 views), and SH energy compaction
+           over all 200 cameras.
 
 Roofline: the persistent render + removal kernel, which takes most of the main
 line's time, timed with HIP events on the stream it runs on around
@@ -448,6 +452,70 @@ def codec_section(torch, raster, synth):
                     "(Sec. 4.4) is not applied here"}
 
 
+def prune_sh_section(torch, raster, synth):
+    """The pruning controller's device steps (Sec. 4.3) and SH energy compaction
+    (Sec. 4.4) on the full scene (3M splats). Select and compaction take dMSE_k
+    and I_k from the fused render over the first 8 views against their own
+    unpruned images; compaction fits every splat over all 200 training cameras,
+    with I_k(s) [200, N] from the same kernel. GPU times by HIP events, medians."""
+    from paper_2601_14821_amd import prune, sh_compact
+
+    scene, cams = synth.workload_full_scene()
+    s = synth.RenderSettings()
+    ds = raster.to_device(scene)
+    rz = raster.Rasterizer(s)
+    N, V = scene.n, len(cams)
+    P = cams[0].width * cams[0].height
+    c8 = cams[:8]
+    targets = rz.render_views(ds, c8).image.clone()
+    dmse, imp, _ = rz.removal_statistics(ds, c8, targets)
+    del targets
+    per_view = torch.zeros(V, N, dtype=torch.float32, device="cuda")
+    rz.score_views_fused(ds, cams, 8, out=raster.Outputs(importance=per_view, importance_stride=N,
+                                                         importance_weight=1.0 / P))
+    rz.release()
+    hp = prune.hyperparameters()
+    ws = prune._workspace(N, ds.means.device)
+    stream = torch.cuda.current_stream()
+
+    def gpu_ms(fn, reps=5):
+        fn()
+        ts = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            r = fn()
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        ts.sort()
+        return r, ts[len(ts) // 2]
+
+    (remove, n_rm), sel_ms = gpu_ms(lambda: prune.select(dmse, imp, hp["dmse_max"], hp["n_iter"], hp["a"], ws=ws))
+    removed = int(n_rm.item())
+    (_, _, kept), comp_ms = gpu_ms(lambda: prune.compact(ds, remove, ws=ws))
+    out_sh = torch.empty_like(ds.sh)
+    _, sh_ms = gpu_ms(lambda: sh_compact.compact(ds, cams, per_view, out=out_sh), reps=3)
+    seen = int((per_view.max(dim=0).values > 0).sum().item())
+    sel_bytes = N * (13 * 8 + 1)                 # 12 histogram passes + the marking pass over (dMSE, I), the mask
+    comp_bytes = N * (1 + 236 + 4) + kept * (236 + 4)
+    gram_flops = 2.0 * 16 * 16 * V * seen        # Y_w^T Y_w on the FP64 matrix cores
+    del per_view, ds, ws, remove, out_sh
+    torch.cuda.empty_cache()
+    return {"workload": f"{N} clustered splats; statistics over {len(c8)} views at {c8[0].width}x{c8[0].height}; "
+                        f"SH compaction over {V} cameras",
+            "select_ms": round(sel_ms, 3), "select_gbs": round(sel_bytes / sel_ms / 1e6, 1),
+            "select_hbm_frac": round(sel_bytes / sel_ms / 1e6 / 8000.0, 3), "removed": removed,
+            "compact_ms": round(comp_ms, 3), "compact_gbs": round(comp_bytes / comp_ms / 1e6, 1), "kept": kept,
+            "sh_compact_ms": round(sh_ms, 2), "sh_msplats_per_s": round(N / sh_ms / 1e3, 2),
+            "sh_splats_seen": seen, "sh_gram_tflops": round(gram_flops / sh_ms / 1e9, 2),
+            "sh_gram_fp64_frac": round(gram_flops / sh_ms / 1e9 / 78.6, 3),
+            "note": "select: 105 B per splat (12 histogram passes and the marking pass read dMSE and I, "
+                    "the mask is written); compaction: the mask, 236 B of attributes and the id read per "
+                    "splat, 240 B written per survivor; SH Gram: 2*16*16*V flops per splat any camera sees, "
+                    "priced on the whole compaction (Gram, eyes and the ridge solves)"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -461,7 +529,8 @@ def main():
     ap.add_argument("--main-only", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 256 MiB device copy (reference for hardware byte counters)")
-    ap.add_argument("--profile-section", choices=("single_view", "multi_scene", "fwd_bwd", "codec"), default=None,
+    ap.add_argument("--profile-section", choices=("single_view", "multi_scene", "fwd_bwd", "codec", "prune_sh"),
+                    default=None,
                     help="run only this extra section and print its result (no main line)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -477,7 +546,8 @@ def main():
         fn = {"single_view": lambda: single_view_section(args, torch, raster, synth),
               "multi_scene": lambda: multi_scene_section(torch, raster, synth, batch, args.multi_views_per_job),
               "fwd_bwd": lambda: fwd_bwd_section(torch, raster, synth, autograd, batch),
-              "codec": lambda: codec_section(torch, raster, synth)}[args.profile_section]
+              "codec": lambda: codec_section(torch, raster, synth),
+              "prune_sh": lambda: prune_sh_section(torch, raster, synth)}[args.profile_section]
         log(args.profile_section)
         print(json.dumps({args.profile_section: fn()}), flush=True)
         return
@@ -518,6 +588,8 @@ def main():
         out["fwd_bwd"] = fwd_bwd_section(torch, raster, synth, autograd, batch)
         log("codec")
         out["codec"] = codec_section(torch, raster, synth)
+        log("pruning select and SH compaction")
+        out["prune_sh"] = prune_sh_section(torch, raster, synth)
     if not args.no_cpu_baseline:
         log("cpu baseline")
         out["cpu_baseline"] = cpu_baseline(scene, cams, s)

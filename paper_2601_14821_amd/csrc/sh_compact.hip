@@ -8,14 +8,20 @@
 // camera weights), because the colours are C = Y L, so the right-hand side is
 // Y_w^T C_w = G L and the cosines between columns are G_ij / sqrt(G_ii G_jj).
 //   k_sh_eyes   camera centres -R^T t (FP64) into the workspace;
-//   k_sh_gram   one wave per splat: its largest camera importance, then G by
-//               FP64 matrix-core products, 4 cameras per v_mfma_f64_16x16x4
-//               (the wave evaluates the basis of 64 cameras at once, one per
-//               lane, stages the weighted values in LDS and feeds them to the
-//               matrix core in its operand layout), upper triangle to the workspace;
-//   k_sh_solve  one thread per splat: column selection, then per channel the
-//               two ridge solves by Cholesky in the thread's LDS, back to RGB.
-// All arithmetic is FP64.
+//   k_sh_seen   one thread per splat, coalesced over the importance rows: its
+//               largest camera importance; a splat no camera sees gets its
+//               output (the DC, AC 0) here, the others go to a list (one
+//               atomic per wave), so the two kernels below run full waves of
+//               seen splats however sparse they are;
+//   k_sh_gram   one wave per listed splat: G by FP64 matrix-core products,
+//               4 cameras per v_mfma_f64_16x16x4 (the wave evaluates the basis
+//               of 64 cameras at once, one per lane, stages the weighted values
+//               in LDS and feeds them to the matrix core in its operand layout),
+//               upper triangle to the workspace;
+//   k_sh_solve  one thread per listed splat: column selection, then per channel
+//               the two ridge solves by Cholesky in the thread's LDS, back to RGB.
+// A splat's result depends only on its own data, so the list's order (set by
+// the atomics) does not change any output. All arithmetic is FP64.
 #include "common.h"
 #include "sh_basis.h"
 #include "sh_compact.h"
@@ -30,6 +36,7 @@ constexpr int kRes = kPacked + 1;            // then the new coefficients (YCoCg
 constexpr int kSplatStride = kRes + 48;      // per splat: G, the largest importance, the result
 constexpr int kSolveThreads = 64;
 constexpr int kFStride = 137;                // doubles per thread of the factor in LDS (odd: spreads banks)
+constexpr int64_t kListBlocks = 8192;        // grid of the list kernels (they stride over the seen count)
 
 __device__ inline int packed_upper(int i, int j) {   // i <= j
     return i * 16 - (i * (i - 1)) / 2 + (j - i);
@@ -46,58 +53,85 @@ __global__ void k_sh_eyes(CamBatch cams, int32_t v0, int32_t nv, double* __restr
     for (int a = 0; a < 3; ++a) eyes[3 * (int64_t)(v0 + k) + a] = e[a];
 }
 
-// One wave (64 threads) per splat.
-__global__ __launch_bounds__(64) void k_sh_gram(int64_t N, int32_t V, int degree, const double* __restrict__ eyes,
-                                                const float* __restrict__ means, const float* __restrict__ imp,
-                                                int64_t stride, double* __restrict__ gws) {
-    __shared__ double sy[64 * 17];   // weighted basis of 64 cameras (17: padding)
-    const int64_t k = blockIdx.x;
-    if (k >= N) return;
-    const int lane = threadIdx.x;
-    // the splat's largest camera importance
+__global__ void k_sh_clear(uint32_t* n_seen) { *n_seen = 0u; }
+
+__global__ __launch_bounds__(256) void k_sh_seen(int64_t N, int32_t V, const float* __restrict__ sh,
+                                                 const float* __restrict__ imp, int64_t stride,
+                                                 double* __restrict__ gws, uint32_t* __restrict__ n_seen,
+                                                 int32_t* __restrict__ list, float* __restrict__ sh_out) {
+    const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
     float m = 0.f;
-    for (int v = lane; v < V; v += 64) m = fmaxf(m, imp[(int64_t)v * stride + k]);
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) m = fmaxf(m, __shfl_xor(m, o, 64));
-    double* G = gws + k * kSplatStride;
-    if (lane == 0) G[kPacked] = (double)m;
-    if (!(m > 0.f)) return;   // no camera sees it (the solve keeps the DC only)
-    const double imax = (double)m;
-    const double mx = means[3 * k], my = means[3 * k + 1], mz = means[3 * k + 2];
-    f64x4 acc = {0.0, 0.0, 0.0, 0.0};
-    for (int v0 = 0; v0 < V; v0 += 64) {
-        const int v = v0 + lane;
-        double y[16];
-#pragma unroll
-        for (int i = 0; i < 16; ++i) y[i] = 0.0;
-        double w = 0.0;
-        if (v < V) {
-            w = (double)imp[(int64_t)v * stride + k] / imax;
-            double dx = mx - eyes[3 * v], dy = my - eyes[3 * v + 1], dz = mz - eyes[3 * v + 2];
-            const double r = __builtin_sqrt(dx * dx + dy * dy + dz * dz);
-            dx /= r;
-            dy /= r;
-            dz /= r;
-            sh_basis_d3(dx, dy, dz, degree, y);
-        }
-#pragma unroll
-        for (int i = 0; i < 16; ++i) sy[lane * 17 + i] = w * y[i];
-        __syncthreads();
-        // 16 products of 4 cameras each: lane l supplies basis l % 16 of camera l / 16
-        // as both A[i][c] and B[c][j] (Y_w^T is A, Y_w is B)
-        const int cams = min(64, V - v0);
-        for (int c0 = 0; c0 < cams; c0 += 4) {
-            const double a = sy[(c0 + lane / 16) * 17 + (lane % 16)];
-            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, a, acc, 0, 0, 0);
-        }
-        __syncthreads();
+    if (k < N)
+        for (int32_t v = 0; v < V; ++v) m = fmaxf(m, imp[(int64_t)v * stride + k]);
+    const bool seen = k < N && m > 0.f;
+    const uint64_t bal = __ballot(seen);
+    if (bal != 0) {
+        const int lane = threadIdx.x & 63;
+        const int lead = __ffsll((long long)bal) - 1;
+        uint32_t base = 0;
+        if (lane == lead) base = atomicAdd(n_seen, (uint32_t)__popcll(bal));
+        base = __shfl(base, lead, 64);
+        if (seen) list[base + __popcll(bal & ((uint64_t(1) << lane) - 1))] = (int32_t)k;
     }
-    // the product's layout (measured): D[i][j] is register i / 4 of lane j + 16 (i % 4)
-    const int j = lane % 16;
+    if (k >= N) return;
+    if (seen) {
+        gws[k * kSplatStride + kPacked] = (double)m;
+    } else {   // no camera sees it: the DC stays, the rest is 0
+        const float* L = sh + 48 * k;
+        float* out = sh_out + 48 * k;
+        for (int e = 0; e < 48; ++e) out[e] = e < 3 ? L[e] : 0.f;
+    }
+}
+
+// One wave (64 threads) per listed splat.
+__global__ __launch_bounds__(64) void k_sh_gram(int32_t V, int degree, const double* __restrict__ eyes,
+                                                const float* __restrict__ means, const float* __restrict__ imp,
+                                                int64_t stride, double* __restrict__ gws,
+                                                const uint32_t* __restrict__ n_seen,
+                                                const int32_t* __restrict__ list) {
+    __shared__ double sy[64 * 17];   // weighted basis of 64 cameras (17: padding)
+    const uint32_t n = *n_seen;
+    const int lane = threadIdx.x;
+    for (uint32_t it = blockIdx.x; it < n; it += gridDim.x) {
+        const int64_t k = list[it];
+        double* G = gws + k * kSplatStride;
+        const double imax = G[kPacked];   // the splat's largest camera importance (> 0)
+        const double mx = means[3 * k], my = means[3 * k + 1], mz = means[3 * k + 2];
+        f64x4 acc = {0.0, 0.0, 0.0, 0.0};
+        for (int v0 = 0; v0 < V; v0 += 64) {
+            const int v = v0 + lane;
+            double y[16];
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        const int i = lane / 16 + 4 * r;
-        if (i <= j) G[packed_upper(i, j)] = acc[r];
+            for (int i = 0; i < 16; ++i) y[i] = 0.0;
+            double w = 0.0;
+            if (v < V) {
+                w = (double)imp[(int64_t)v * stride + k] / imax;
+                double dx = mx - eyes[3 * v], dy = my - eyes[3 * v + 1], dz = mz - eyes[3 * v + 2];
+                const double r = __builtin_sqrt(dx * dx + dy * dy + dz * dz);
+                dx /= r;
+                dy /= r;
+                dz /= r;
+                sh_basis_d3(dx, dy, dz, degree, y);
+            }
+#pragma unroll
+            for (int i = 0; i < 16; ++i) sy[lane * 17 + i] = w * y[i];
+            __syncthreads();
+            // 16 products of 4 cameras each: lane l supplies basis l % 16 of camera l / 16
+            // as both A[i][c] and B[c][j] (Y_w^T is A, Y_w is B)
+            const int cams = min(64, V - v0);
+            for (int c0 = 0; c0 < cams; c0 += 4) {
+                const double a = sy[(c0 + lane / 16) * 17 + (lane % 16)];
+                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, a, acc, 0, 0, 0);
+            }
+            __syncthreads();
+        }
+        // the product's layout (measured): D[i][j] is register i / 4 of lane j + 16 (i % 4)
+        const int j = lane % 16;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int i = lane / 16 + 4 * r;
+            if (i <= j) G[packed_upper(i, j)] = acc[r];
+        }
     }
 }
 
@@ -152,86 +186,95 @@ struct Solver {
     }
 };
 
-__global__ __launch_bounds__(kSolveThreads) void k_sh_solve(int64_t N, int degree, const float* __restrict__ sh,
+__global__ __launch_bounds__(kSolveThreads) void k_sh_solve(int degree, const float* __restrict__ sh,
                                                             double* __restrict__ gws, ShCompactParams p,
+                                                            const uint32_t* __restrict__ n_seen,
+                                                            const int32_t* __restrict__ list,
                                                             float* __restrict__ sh_out) {
     __shared__ double sF[kSolveThreads * kFStride];
-    const int64_t k = (int64_t)blockIdx.x * kSolveThreads + threadIdx.x;
-    if (k >= N) return;
+    const uint32_t n = *n_seen;
     const int M = (degree + 1) * (degree + 1);
-    const double* G = gws + k * kSplatStride;
-    double* res = gws + k * kSplatStride + kRes;   // this splat's result slots
-    const float* L = sh + 48 * k;
-    float* out = sh_out + 48 * k;
-    if (!(G[kPacked] > 0.0)) {   // no camera sees it: the DC stays, the rest is 0
-        for (int e = 0; e < 48; ++e) out[e] = e < 3 ? L[e] : 0.f;
-        return;
-    }
-    Solver S{G, sF + threadIdx.x * kFStride, M};
-    // columns: the DC, then each AC column not parallel to a kept one before it
-    uint32_t kept = 1u;
-    for (int i = 1; i < M; ++i) {
-        const double gii = S.g(i, i);
-        if (!(gii > 0.0)) continue;
-        bool par = false;
-        for (int j = 0; j < i; ++j) {
-            if (!((kept >> j) & 1u)) continue;
-            const double c = fabs(S.g(i, j)) / (__builtin_sqrt(gii) * __builtin_sqrt(S.g(j, j)));
-            par = par || c > p.alpha;
+    for (uint32_t it = blockIdx.x * kSolveThreads + threadIdx.x; it < n; it += gridDim.x * kSolveThreads) {
+        const int64_t k = list[it];
+        const double* G = gws + k * kSplatStride;
+        double* res = gws + k * kSplatStride + kRes;   // this splat's result slots
+        const float* L = sh + 48 * k;
+        float* out = sh_out + 48 * k;
+        Solver S{G, sF + threadIdx.x * kFStride, M};
+        // columns: the DC, then each AC column not parallel to a kept one before it
+        uint32_t kept = 1u;
+        for (int i = 1; i < M; ++i) {
+            const double gii = S.g(i, i);
+            if (!(gii > 0.0)) continue;
+            bool par = false;
+            for (int j = 0; j < i; ++j) {
+                if (!((kept >> j) & 1u)) continue;
+                const double c = fabs(S.g(i, j)) / (__builtin_sqrt(gii) * __builtin_sqrt(S.g(j, j)));
+                par = par || c > p.alpha;
+            }
+            if (!par) kept |= 1u << i;
         }
-        if (!par) kept |= 1u << i;
-    }
-    for (int ch = 0; ch < 3; ++ch) {
-        const double lam = ch == 0 ? p.lam : 3.0 * p.lam;
-        // this channel's coefficients in YCoCg and the right-hand side G L
-        double lc[16], b[16], x[16];
+        for (int ch = 0; ch < 3; ++ch) {
+            const double lam = ch == 0 ? p.lam : 3.0 * p.lam;
+            // this channel's coefficients in YCoCg and the right-hand side G L
+            double lc[16], b[16], x[16];
+#pragma unroll
+            for (int i = 0; i < 16; ++i) {
+                const double R = L[3 * i], Gc = L[3 * i + 1], B = L[3 * i + 2];
+                lc[i] = ch == 0 ? 0.25 * R + 0.5 * Gc + 0.25 * B : ch == 1 ? 0.5 * R - 0.5 * B : -0.25 * R + 0.5 * Gc - 0.25 * B;
+            }
+#pragma unroll
+            for (int i = 0; i < 16; ++i) {
+                double s = 0.0;
+#pragma unroll
+                for (int j = 0; j < 16; ++j)
+                    if (i < M && j < M) s += S.g(i, j) * lc[j];
+                b[i] = s;
+                x[i] = 0.0;
+            }
+            S.factor(kept, lam);
+            S.solve(kept, b, x);
+            uint32_t kept2 = kept;
+#pragma unroll
+            for (int i = 1; i < 16; ++i)
+                if (i < M && ((kept >> i) & 1u) && fabs(x[i]) < p.tau) kept2 &= ~(1u << i);
+            if (kept2 != kept) {
+                S.factor(kept2, lam);
+                S.solve(kept2, b, x);
+            }
+#pragma unroll
+            for (int i = 0; i < 16; ++i) res[16 * ch + i] = i < M ? x[i] : 0.0;
+        }
 #pragma unroll
         for (int i = 0; i < 16; ++i) {
-            const double R = L[3 * i], Gc = L[3 * i + 1], B = L[3 * i + 2];
-            lc[i] = ch == 0 ? 0.25 * R + 0.5 * Gc + 0.25 * B : ch == 1 ? 0.5 * R - 0.5 * B : -0.25 * R + 0.5 * Gc - 0.25 * B;
+            const double Yv = res[i], Co = res[16 + i], Cg = res[32 + i];
+            out[3 * i] = (float)(Yv + Co - Cg);
+            out[3 * i + 1] = (float)(Yv + Cg);
+            out[3 * i + 2] = (float)(Yv - Co - Cg);
         }
-#pragma unroll
-        for (int i = 0; i < 16; ++i) {
-            double s = 0.0;
-#pragma unroll
-            for (int j = 0; j < 16; ++j)
-                if (i < M && j < M) s += S.g(i, j) * lc[j];
-            b[i] = s;
-            x[i] = 0.0;
-        }
-        S.factor(kept, lam);
-        S.solve(kept, b, x);
-        uint32_t kept2 = kept;
-#pragma unroll
-        for (int i = 1; i < 16; ++i)
-            if (i < M && ((kept >> i) & 1u) && fabs(x[i]) < p.tau) kept2 &= ~(1u << i);
-        if (kept2 != kept) {
-            S.factor(kept2, lam);
-            S.solve(kept2, b, x);
-        }
-#pragma unroll
-        for (int i = 0; i < 16; ++i) res[16 * ch + i] = i < M ? x[i] : 0.0;
-    }
-#pragma unroll
-    for (int i = 0; i < 16; ++i) {
-        const double Yv = res[i], Co = res[16 + i], Cg = res[32 + i];
-        out[3 * i] = (float)(Yv + Co - Cg);
-        out[3 * i + 1] = (float)(Yv + Cg);
-        out[3 * i + 2] = (float)(Yv - Co - Cg);
     }
 }
 
 }  // namespace
 
+// Workspace: camera centres [V,3] | seen count | seen list [N] | per splat
+// kSplatStride doubles (G, the largest importance, the result).
 size_t sh_compact_workspace_bytes(int64_t N, int32_t V) {
-    return align_up((size_t)V * 3 * 8) + (size_t)N * kSplatStride * 8;
+    return align_up((size_t)V * 3 * 8) + align_up(sizeof(uint32_t)) + align_up((size_t)N * 4) +
+           (size_t)N * kSplatStride * 8;
 }
 
 potr_status launch_sh_compact(int64_t N, int32_t V, const potr_camera* cams, int degree, const float* means,
                               const float* sh, const float* imp, int64_t stride, const ShCompactParams& p,
                               void* ws, float* sh_out, hipStream_t s) {
-    double* eyes = (double*)ws;
-    double* gws = (double*)((char*)ws + align_up((size_t)V * 3 * 8));
+    char* w = (char*)ws;
+    double* eyes = (double*)w;
+    w += align_up((size_t)V * 3 * 8);
+    uint32_t* n_seen = (uint32_t*)w;
+    w += align_up(sizeof(uint32_t));
+    int32_t* list = (int32_t*)w;
+    w += align_up((size_t)N * 4);
+    double* gws = (double*)w;
     for (int32_t v0 = 0; v0 < V; v0 += kViewsPerLaunch) {
         const int32_t nv = V - v0 < kViewsPerLaunch ? V - v0 : kViewsPerLaunch;
         CamBatch cb{};
@@ -240,11 +283,20 @@ potr_status launch_sh_compact(int64_t N, int32_t V, const potr_camera* cams, int
     }
     potr_status st = check_launch("k_sh_eyes");
     if (st != POTR_OK || N == 0) return st;
-    hipLaunchKernelGGL(k_sh_gram, dim3((unsigned)N), dim3(64), 0, s, N, V, degree, eyes, means, imp, stride, gws);
+    // the seen count stays on the device: the two list kernels stride over it
+    hipLaunchKernelGGL(k_sh_clear, dim3(1), dim3(1), 0, s, n_seen);
+    hipLaunchKernelGGL(k_sh_seen, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, N, V, sh, imp, stride, gws,
+                       n_seen, list, sh_out);
+    st = check_launch("k_sh_seen");
+    if (st != POTR_OK) return st;
+    const int64_t gram_blocks = N < kListBlocks ? N : kListBlocks;
+    hipLaunchKernelGGL(k_sh_gram, dim3((unsigned)gram_blocks), dim3(64), 0, s, V, degree, eyes, means, imp, stride,
+                       gws, n_seen, list);
     st = check_launch("k_sh_gram");
     if (st != POTR_OK) return st;
-    hipLaunchKernelGGL(k_sh_solve, dim3((unsigned)((N + kSolveThreads - 1) / kSolveThreads)), dim3(kSolveThreads), 0,
-                       s, N, degree, sh, gws, p, sh_out);
+    const int64_t sb = (N + kSolveThreads - 1) / kSolveThreads;
+    hipLaunchKernelGGL(k_sh_solve, dim3((unsigned)(sb < kListBlocks ? sb : kListBlocks)), dim3(kSolveThreads), 0, s,
+                       degree, sh, gws, p, n_seen, list, sh_out);
     return check_launch("k_sh_solve");
 }
 

@@ -88,3 +88,25 @@ def test_unseen_splats_keep_only_their_dc():
     np.testing.assert_array_equal(got[:100, 0], scene.sh[:100, 0])
     assert not got[:100, 1:].any()
     _check(got, ref, margin)
+
+
+def test_every_splat_seen_list_longer_than_one_grid():
+    """600k splats that all four cameras see (importances drawn directly, not
+    rendered): the seen list is longer than one pass of the Gram grid (8192
+    waves) and of the solve grid (8192 x 64 threads), so both stride over it;
+    sampled splats against the oracle, then a second, smaller call whose result
+    must not depend on the first one's list."""
+    _need_gpu()
+    rng = np.random.default_rng(517)
+    for n, V in ((600_000, 4), (5_000, 9)):
+        scene = synth.random_scene(n, 518 + V, clustered=False)
+        cams = synth.hemisphere_cameras(V, 96, 64, seed=520 + V)
+        imp = rng.uniform(0.01, 1.0, size=(V, n)).astype(np.float32)
+        ds = raster.to_device(scene)
+        got = sh_compact.compact(ds, cams, torch.from_numpy(imp).cuda(), **sh_compact.hyperparameters(0.5))
+        torch.cuda.synchronize()
+        idx = np.unique(np.concatenate([rng.choice(n, 300, replace=False), [0, n - 1]]))
+        ref, margin = oshc.compact(scene, cams, imp, degree=3, idx=idx, with_margins=True,
+                                   **sh_compact.hyperparameters(0.5))
+        err = _check(got.cpu().numpy()[idx], ref, margin)
+        print(f"N={n} V={V}: max rel err {err:.2e}", flush=True)
