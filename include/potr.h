@@ -437,9 +437,9 @@ POTR_API potr_status potr_prune_compact(int64_t N, const uint8_t* remove, const 
  *   cams (host) [V]; importance [V, stride] FP32 (device): the per-camera
  *     importance I_k(s) (e.g. from potr_render_score_out with a per-view
  *     stride); means [N,3], sh [N,16,3] as for potr_project
- *   ws  workspace of potr_sh_compact_workspace_size(N, V) bytes (per splat 185
- *       doubles, its Gram matrix, largest importance and result, and a 4-byte
- *       slot of the list of splats some camera sees)
+ *   ws  workspace of potr_sh_compact_workspace_size(N, V) bytes (per splat 137
+ *       doubles, its Gram matrix and largest importance, and a 4-byte slot of
+ *       the list of splats some camera sees)
  *   sh_out [N,16,3] FP32 out (must not overlap sh)
  * Arithmetic: FP64 (the Gram matrices on the FP64 matrix cores).
  * ------------------------------------------------------------------------- */

@@ -32,8 +32,7 @@ namespace {
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kPacked = 136;                 // upper triangle of 16 x 16
-constexpr int kRes = kPacked + 1;            // then the new coefficients (YCoCg, 16 x 3)
-constexpr int kSplatStride = kRes + 48;      // per splat: G, the largest importance, the result
+constexpr int kSplatStride = kPacked + 1;    // per splat: G, then its largest camera importance
 constexpr int kSolveThreads = 64;
 constexpr int kFStride = 137;                // doubles per thread of the factor in LDS (odd: spreads banks)
 constexpr int64_t kListBlocks = 8192;        // grid of the list kernels (they stride over the seen count)
@@ -186,6 +185,20 @@ struct Solver {
     }
 };
 
+// The second ridge pass: AC coefficients below tau are forced to 0 and the
+// rest solved again (nothing to do when none is dropped). The factor holds
+// (kept, lam) on entry; it is replaced only when the pass runs.
+__device__ __forceinline__ void second_pass(Solver& S, uint32_t kept, double lam, double tau, const double (&b)[16],
+                            double (&x)[16]) {
+    uint32_t kept2 = kept;
+#pragma unroll
+    for (int i = 1; i < 16; ++i)
+        if (i < S.M && ((kept >> i) & 1u) && fabs(x[i]) < tau) kept2 &= ~(1u << i);
+    if (kept2 == kept) return;
+    S.factor(kept2, lam);
+    S.solve(kept2, b, x);
+}
+
 __global__ __launch_bounds__(kSolveThreads) void k_sh_solve(int degree, const float* __restrict__ sh,
                                                             double* __restrict__ gws, ShCompactParams p,
                                                             const uint32_t* __restrict__ n_seen,
@@ -197,7 +210,6 @@ __global__ __launch_bounds__(kSolveThreads) void k_sh_solve(int degree, const fl
     for (uint32_t it = blockIdx.x * kSolveThreads + threadIdx.x; it < n; it += gridDim.x * kSolveThreads) {
         const int64_t k = list[it];
         const double* G = gws + k * kSplatStride;
-        double* res = gws + k * kSplatStride + kRes;   // this splat's result slots
         const float* L = sh + 48 * k;
         float* out = sh_out + 48 * k;
         Solver S{G, sF + threadIdx.x * kFStride, M};
@@ -214,40 +226,48 @@ __global__ __launch_bounds__(kSolveThreads) void k_sh_solve(int degree, const fl
             }
             if (!par) kept |= 1u << i;
         }
-        for (int ch = 0; ch < 3; ++ch) {
-            const double lam = ch == 0 ? p.lam : 3.0 * p.lam;
-            // this channel's coefficients in YCoCg and the right-hand side G L
-            double lc[16], b[16], x[16];
-#pragma unroll
-            for (int i = 0; i < 16; ++i) {
-                const double R = L[3 * i], Gc = L[3 * i + 1], B = L[3 * i + 2];
-                lc[i] = ch == 0 ? 0.25 * R + 0.5 * Gc + 0.25 * B : ch == 1 ? 0.5 * R - 0.5 * B : -0.25 * R + 0.5 * Gc - 0.25 * B;
-            }
-#pragma unroll
-            for (int i = 0; i < 16; ++i) {
-                double s = 0.0;
-#pragma unroll
-                for (int j = 0; j < 16; ++j)
-                    if (i < M && j < M) s += S.g(i, j) * lc[j];
-                b[i] = s;
-                x[i] = 0.0;
-            }
-            S.factor(kept, lam);
-            S.solve(kept, b, x);
-            uint32_t kept2 = kept;
-#pragma unroll
-            for (int i = 1; i < 16; ++i)
-                if (i < M && ((kept >> i) & 1u) && fabs(x[i]) < p.tau) kept2 &= ~(1u << i);
-            if (kept2 != kept) {
-                S.factor(kept2, lam);
-                S.solve(kept2, b, x);
-            }
-#pragma unroll
-            for (int i = 0; i < 16; ++i) res[16 * ch + i] = i < M ? x[i] : 0.0;
-        }
+        // the coefficients in YCoCg and the right-hand sides G L of the three
+        // channels, in one pass over the packed upper triangle
+        double l0[16], l1[16], l2[16], b0[16], b1[16], b2[16];
 #pragma unroll
         for (int i = 0; i < 16; ++i) {
-            const double Yv = res[i], Co = res[16 + i], Cg = res[32 + i];
+            const double R = L[3 * i], Gc = L[3 * i + 1], B = L[3 * i + 2];
+            l0[i] = 0.25 * R + 0.5 * Gc + 0.25 * B;
+            l1[i] = 0.5 * R - 0.5 * B;
+            l2[i] = -0.25 * R + 0.5 * Gc - 0.25 * B;
+            b0[i] = b1[i] = b2[i] = 0.0;
+        }
+#pragma unroll
+        for (int i = 0; i < 16; ++i)
+#pragma unroll
+            for (int j = 0; j < 16; ++j) {
+                if (j < i || j >= M) continue;
+                const double g = G[packed_upper(i, j)];
+                b0[i] += g * l0[j];
+                b1[i] += g * l1[j];
+                b2[i] += g * l2[j];
+                if (j != i) {
+                    b0[j] += g * l0[i];
+                    b1[j] += g * l1[i];
+                    b2[j] += g * l2[i];
+                }
+            }
+        // Y with lam; Co and Cg share 3 lam, so their first solves share one
+        // factorization (both are taken before either second pass refactors)
+        double x0[16], x1[16], x2[16];
+#pragma unroll
+        for (int i = 0; i < 16; ++i) x0[i] = x1[i] = x2[i] = 0.0;
+        S.factor(kept, p.lam);
+        S.solve(kept, b0, x0);
+        second_pass(S, kept, p.lam, p.tau, b0, x0);
+        S.factor(kept, 3.0 * p.lam);
+        S.solve(kept, b1, x1);
+        S.solve(kept, b2, x2);
+        second_pass(S, kept, 3.0 * p.lam, p.tau, b1, x1);
+        second_pass(S, kept, 3.0 * p.lam, p.tau, b2, x2);
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            const double Yv = i < M ? x0[i] : 0.0, Co = i < M ? x1[i] : 0.0, Cg = i < M ? x2[i] : 0.0;
             out[3 * i] = (float)(Yv + Co - Cg);
             out[3 * i + 1] = (float)(Yv + Cg);
             out[3 * i + 2] = (float)(Yv - Co - Cg);
@@ -258,7 +278,7 @@ __global__ __launch_bounds__(kSolveThreads) void k_sh_solve(int degree, const fl
 }  // namespace
 
 // Workspace: camera centres [V,3] | seen count | seen list [N] | per splat
-// kSplatStride doubles (G, the largest importance, the result).
+// kSplatStride doubles (G, then the largest importance).
 size_t sh_compact_workspace_bytes(int64_t N, int32_t V) {
     return align_up((size_t)V * 3 * 8) + align_up(sizeof(uint32_t)) + align_up((size_t)N * 4) +
            (size_t)N * kSplatStride * 8;
