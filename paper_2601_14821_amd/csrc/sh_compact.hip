@@ -58,10 +58,23 @@ __global__ __launch_bounds__(256) void k_sh_seen(int64_t N, int32_t V, const flo
                                                  const float* __restrict__ imp, int64_t stride,
                                                  double* __restrict__ gws, uint32_t* __restrict__ n_seen,
                                                  int32_t* __restrict__ list, float* __restrict__ sh_out) {
-    const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    __shared__ uint8_t s_seen[256];
+    const int64_t k0 = (int64_t)blockIdx.x * 256;
+    const int64_t k = k0 + threadIdx.x;
     float m = 0.f;
-    if (k < N)
-        for (int32_t v = 0; v < V; ++v) m = fmaxf(m, imp[(int64_t)v * stride + k]);
+    if (k < N) {   // four running maxima keep four loads in flight
+        float m1 = 0.f, m2 = 0.f, m3 = 0.f;
+        const float* col = imp + k;
+        int32_t v = 0;
+        for (; v + 4 <= V; v += 4) {
+            m = fmaxf(m, col[(int64_t)v * stride]);
+            m1 = fmaxf(m1, col[(int64_t)(v + 1) * stride]);
+            m2 = fmaxf(m2, col[(int64_t)(v + 2) * stride]);
+            m3 = fmaxf(m3, col[(int64_t)(v + 3) * stride]);
+        }
+        for (; v < V; ++v) m = fmaxf(m, col[(int64_t)v * stride]);
+        m = fmaxf(fmaxf(m, m1), fmaxf(m2, m3));
+    }
     const bool seen = k < N && m > 0.f;
     const uint64_t bal = __ballot(seen);
     if (bal != 0) {
@@ -72,13 +85,17 @@ __global__ __launch_bounds__(256) void k_sh_seen(int64_t N, int32_t V, const flo
         base = __shfl(base, lead, 64);
         if (seen) list[base + __popcll(bal & ((uint64_t(1) << lane) - 1))] = (int32_t)k;
     }
-    if (k >= N) return;
-    if (seen) {
-        gws[k * kSplatStride + kPacked] = (double)m;
-    } else {   // no camera sees it: the DC stays, the rest is 0
-        const float* L = sh + 48 * k;
-        float* out = sh_out + 48 * k;
-        for (int e = 0; e < 48; ++e) out[e] = e < 3 ? L[e] : 0.f;
+    if (seen) gws[k * kSplatStride + kPacked] = (double)m;
+    s_seen[threadIdx.x] = seen ? 1 : 0;
+    __syncthreads();
+    // a splat no camera sees keeps its DC, the rest 0: the block writes the
+    // outputs of its unseen splats together, consecutive threads on
+    // consecutive floats
+    const int64_t nk = N - k0 < 256 ? N - k0 : 256;
+    for (int e = threadIdx.x; e < nk * 48; e += 256) {
+        const int j = e / 48, c = e - 48 * j;
+        if (s_seen[j]) continue;
+        sh_out[48 * k0 + e] = c < 3 ? sh[48 * k0 + e] : 0.f;
     }
 }
 
