@@ -110,3 +110,35 @@ def test_every_splat_seen_list_longer_than_one_grid():
                                    **sh_compact.hyperparameters(0.5))
         err = _check(got.cpu().numpy()[idx], ref, margin)
         print(f"N={n} V={V}: max rel err {err:.2e}", flush=True)
+
+
+def test_full_scene_sampled_splats():
+    """The full scene as the benchmark runs it: 3M clustered splats, I_k(s) over
+    all 200 views at 1600x1064 from the fused kernel, one compaction call; 200
+    seen and 50 unseen splats, drawn at random, against the oracle."""
+    _need_gpu()
+    scene, cams = synth.workload_full_scene()
+    ds = raster.to_device(scene)
+    rz = raster.Rasterizer(synth.RenderSettings())
+    N, V, P = scene.n, len(cams), cams[0].width * cams[0].height
+    print("per-view importance", flush=True)
+    per_view = torch.zeros(V, N, device="cuda")
+    rz.score_views_fused(ds, cams, 8, out=raster.Outputs(importance=per_view, importance_stride=N,
+                                                         importance_weight=1.0 / P))
+    rz.release()
+    hp = sh_compact.hyperparameters(0.5)
+    print("compaction", flush=True)
+    got = sh_compact.compact(ds, cams, per_view, **hp).cpu().numpy()
+    imp = per_view.cpu().numpy()
+    del per_view
+    seen = imp.max(axis=0) > 0
+    rng = np.random.default_rng(521)
+    idx = np.sort(np.concatenate([rng.choice(np.flatnonzero(seen), 200, replace=False),
+                                  rng.choice(np.flatnonzero(~seen), 50, replace=False)]))
+    print(f"{int(seen.sum())} splats seen; oracle on {len(idx)}", flush=True)
+    ref, margin = oshc.compact(scene, cams, imp, degree=3, idx=idx, with_margins=True, **hp)
+    err = _check(got[idx], ref, margin)
+    print(f"max rel err {err:.2e}", flush=True)
+    unseen = idx[~seen[idx]]
+    np.testing.assert_array_equal(got[unseen, 0], scene.sh[unseen, 0])
+    assert not got[unseen, 1:].any()
