@@ -180,7 +180,7 @@ struct Solver {
 
     // x = (L L^T)^-1 b over the mask (rows outside it give 0); b and x stay in
     // registers (every index below is a compile-time constant).
-    __device__ void solve(uint32_t mask, const double (&b)[16], double (&x)[16]) const {
+    __device__ __forceinline__ void solve(uint32_t mask, const double (&b)[16], double (&x)[16]) const {
 #pragma unroll
         for (int i = 0; i < 16; ++i) {
             if (i >= M) break;
