@@ -18,8 +18,11 @@
 //               of 64 cameras at once, one per lane, stages the weighted values
 //               in LDS and feeds them to the matrix core in its operand layout),
 //               upper triangle to the workspace;
-//   k_sh_solve  one thread per listed splat: column selection, then per channel
-//               the two ridge solves by Cholesky in the thread's LDS, back to RGB.
+//   k_sh_solve  one thread per listed splat: column selection, the right-hand
+//               sides of the three channels in one pass over G, then per channel
+//               the two ridge solves by Cholesky in the thread's LDS (Co and Cg
+//               have the same weight, so their first solves share a factor),
+//               back to RGB.
 // A splat's result depends only on its own data, so the list's order (set by
 // the atomics) does not change any output. All arithmetic is FP64.
 #include "common.h"
