@@ -44,7 +44,7 @@ def _check(got, ref, margin, tol=2e-6):
     return float(err[~near].max())
 
 
-@pytest.mark.parametrize("degree", [3, 1])
+@pytest.mark.parametrize("degree", [3, 2, 1, 0])
 def test_small_scene_paper_hyperparameters(degree):
     _need_gpu()
     scene, cams = synth.workload_small()
